@@ -1,0 +1,180 @@
+"""Seeded synthetic initial conditions shared by the HIP path's tests and the oracle.
+
+This module holds input recipes only: it draws seeded states and converts pointwise
+initial data into cell averages.  It contains none of the method's arithmetic (no GP
+weights, no fluxes, no detection), so both sides can use it without sharing any code
+of the scheme itself.
+
+Every array returned is float64, conservative variables, structure-of-arrays with
+shape (nvar, ny, nx) in 2D (nvar = 4: rho, rho*u, rho*v, E) and (5, nz, ny, nx) in
+3D, row-major with x fastest.
+
+Recipes (paper: Sec. "Grid convergence -- the isentropic vortex test" for the vortex
+and its Gauss-Legendre cell averaging; the four-quadrant and blast problems are
+synthetic stand-ins shaped like the paper's shock problems):
+  * isentropic vortex, strength beta, mean flow (1, 1), cell averages by the
+    5-point Gauss-Legendre rule per axis (25 nodes per cell),
+  * four-quadrant Riemann problem, states drawn from numpy's PCG64 with the given
+    seed: rho in [0.1, 2], |u|, |v| <= 1.5, p in [0.02, 2]; exact cell averages by
+    area fractions,
+  * smooth density wave advected at constant velocity and pressure (exact solution
+    is a translation), used for convergence checks,
+  * 3D blast: ambient rho = 1 with seeded +-1% noise, p = 1e-5, and p = 1e4 in the
+    cells whose centres lie within r = 3 dx of the cube centre.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+GAMMA = 1.4
+
+
+def _gl5():
+    x, w = np.polynomial.legendre.leggauss(5)
+    # map [-1, 1] -> [-1/2, 1/2]; weights sum to 1
+    return 0.5 * x, 0.5 * w
+
+
+def prim_to_cons(rho, u, v, p, gamma=GAMMA):
+    """Pointwise primitive -> conservative (2D ideal gas)."""
+    return np.stack([rho, rho * u, rho * v,
+                     p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
+
+
+def cell_centres(n, lo, hi):
+    d = (hi - lo) / n
+    return lo + (np.arange(n) + 0.5) * d, d
+
+
+# --------------------------------------------------------------------------
+# isentropic vortex (paper: isentropic vortex test, pointwise IC formulas)
+# --------------------------------------------------------------------------
+def vortex_point(x, y, xc, yc, beta=5.0, mean=(1.0, 1.0), gamma=GAMMA):
+    """Pointwise conservative state of the isentropic vortex centred at (xc, yc)."""
+    dx = x - xc
+    dy = y - yc
+    r2 = dx * dx + dy * dy
+    e = np.exp(1.0 - r2)
+    rho = (1.0 - (gamma - 1.0) * beta * beta / (8.0 * gamma * math.pi ** 2) * e) ** (1.0 / (gamma - 1.0))
+    s = beta / (2.0 * math.pi) * np.exp(0.5 * (1.0 - r2))
+    u = mean[0] - s * dy
+    v = mean[1] + s * dx
+    p = rho ** gamma
+    return prim_to_cons(rho, u, v, p, gamma)
+
+
+def vortex(nx, ny, lo=(0.0, 0.0), hi=(10.0, 10.0), centre=None, beta=5.0,
+           mean=(1.0, 1.0), t=0.0, gamma=GAMMA):
+    """Cell-averaged vortex at time t (exact solution: translation by mean*t, periodic).
+
+    The vortex centre is moved by mean*t and wrapped into the box; each quadrature
+    node uses the nearest periodic image of the centre.
+    """
+    Lx, Ly = hi[0] - lo[0], hi[1] - lo[1]
+    if centre is None:
+        centre = (lo[0] + 0.5 * Lx, lo[1] + 0.5 * Ly)
+    xc = lo[0] + ((centre[0] + mean[0] * t - lo[0]) % Lx)
+    yc = lo[1] + ((centre[1] + mean[1] * t - lo[1]) % Ly)
+    xcen, dx = cell_centres(nx, lo[0], hi[0])
+    ycen, dy = cell_centres(ny, lo[1], hi[1])
+    g, w = _gl5()
+    out = np.zeros((4, ny, nx))
+    for a in range(5):
+        yy = (ycen + g[a] * dy)[:, None]
+        for b in range(5):
+            xx = (xcen + g[b] * dx)[None, :]
+            ddx = xx - xc
+            ddy = yy - yc
+            ddx = ddx - Lx * np.round(ddx / Lx)
+            ddy = ddy - Ly * np.round(ddy / Ly)
+            out += w[a] * w[b] * vortex_point(ddx, ddy, 0.0, 0.0, beta, mean, gamma)
+    return out
+
+
+# --------------------------------------------------------------------------
+# four-quadrant Riemann problem (seeded)
+# --------------------------------------------------------------------------
+def quadrant_states(seed):
+    """Four primitive states (rho, u, v, p), quadrants ordered NE, NW, SW, SE."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    st = []
+    for _ in range(4):
+        rho = rng.uniform(0.1, 2.0)
+        u = rng.uniform(-1.5, 1.5)
+        v = rng.uniform(-1.5, 1.5)
+        p = rng.uniform(0.02, 2.0)
+        st.append((rho, u, v, p))
+    return st
+
+
+def quadrants(nx, ny, seed=1, lo=(0.0, 0.0), hi=(1.0, 1.0), split=(0.5, 0.5), gamma=GAMMA):
+    """Exact cell averages of the piecewise-constant four-quadrant state."""
+    st = quadrant_states(seed)
+    cons = [prim_to_cons(*[np.float64(c) for c in s], gamma=gamma) for s in st]
+    xe = np.linspace(lo[0], hi[0], nx + 1)
+    ye = np.linspace(lo[1], hi[1], ny + 1)
+    # fraction of each cell on the east (x > split) / north (y > split) side
+    fe = np.clip((xe[1:] - np.maximum(xe[:-1], split[0])) / (xe[1:] - xe[:-1]), 0.0, 1.0)
+    fn = np.clip((ye[1:] - np.maximum(ye[:-1], split[1])) / (ye[1:] - ye[:-1]), 0.0, 1.0)
+    fw, fs = 1.0 - fe, 1.0 - fn
+    out = np.zeros((4, ny, nx))
+    for q, (ax, ay) in enumerate([(fe, fn), (fw, fn), (fw, fs), (fe, fs)]):
+        area = ay[:, None] * ax[None, :]
+        out += cons[q][:, None, None] * area[None]
+    return out
+
+
+# --------------------------------------------------------------------------
+# smooth density wave (constant u, v, p; exact solution is a translation)
+# --------------------------------------------------------------------------
+def density_wave(nx, ny, L=1.0, amp=0.2, u=1.0, v=1.0, p=1.0, t=0.0, gamma=GAMMA):
+    """Cell averages of rho = 1 + amp*sin(2 pi (x + y - (u+v) t)/L), exact by integration."""
+    dx = L / nx
+    dy = L / ny
+    k = 2.0 * math.pi / L
+    xe = np.arange(nx + 1) * dx
+    ye = np.arange(ny + 1) * dy
+    sh = (u + v) * t
+    # average of sin(k(x + y - sh)) over a cell = -(1/(k^2 dx dy)) * second difference of sin
+    X0, X1 = xe[None, :-1], xe[None, 1:]
+    Y0, Y1 = ye[:-1, None], ye[1:, None]
+    def S(X, Y):
+        return np.sin(k * (X + Y - sh))
+    avg = -(S(X1, Y1) - S(X0, Y1) - S(X1, Y0) + S(X0, Y0)) / (k * k * dx * dy)
+    rho = 1.0 + amp * avg
+    out = np.zeros((4, ny, nx))
+    out[0] = rho
+    out[1] = rho * u
+    out[2] = rho * v
+    out[3] = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+    return out
+
+
+# --------------------------------------------------------------------------
+# 1D shock tube laid out along x in an nx-by-ny strip
+# --------------------------------------------------------------------------
+def shock_tube(nx, ny, left, right, x0=0.5, gamma=GAMMA):
+    """Primitive (rho, u, p) left/right states split at x0 on [0,1]; v = 0."""
+    xe = np.linspace(0.0, 1.0, nx + 1)
+    fr = np.clip((xe[1:] - np.maximum(xe[:-1], x0)) / (xe[1:] - xe[:-1]), 0.0, 1.0)
+    cl = prim_to_cons(np.float64(left[0]), np.float64(left[1]), 0.0, np.float64(left[2]), gamma)
+    cr = prim_to_cons(np.float64(right[0]), np.float64(right[1]), 0.0, np.float64(right[2]), gamma)
+    row = cl[:, None] * (1.0 - fr)[None] + cr[:, None] * fr[None]
+    return np.repeat(row[:, None, :], ny, axis=1).copy()
+
+
+# --------------------------------------------------------------------------
+# 3D blast (seeded density noise)
+# --------------------------------------------------------------------------
+def blast3d(n, seed=3, r_cells=3.0, p_in=1e4, p_out=1e-5, noise=0.01, gamma=GAMMA):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rho = 1.0 + noise * rng.uniform(-1.0, 1.0, size=(n, n, n))
+    c = (np.arange(n) + 0.5) - 0.5 * n  # cell-centre offsets in cell units
+    d2 = c[:, None, None] ** 2 + c[None, :, None] ** 2 + c[None, None, :] ** 2
+    p = np.where(d2 <= r_cells * r_cells, p_in, p_out)
+    out = np.zeros((5, n, n, n))
+    out[0] = rho
+    out[4] = p / (gamma - 1.0)
+    return out

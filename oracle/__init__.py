@@ -1,0 +1,232 @@
+"""GP-MOOD oracle: plain FP64 CPU reference.  TEST INFRASTRUCTURE ONLY.
+
+Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may import
+this package.  The product library (paper_2110_08683_amd) never imports it and
+shares no code with it; the two meet only through the seeded inputs of
+gpmood_inputs and the values they return.
+
+Parts:
+  weights_mp.py     GP prediction vectors and u2 curvature weights in mpmath
+                    (80 digits, rounded to double), eqs. (SE-pred), (SE-cov),
+                    (gp_reconstructor), (normalized_z), App. B.
+  gpmood_oracle.c   the stage: GP reconstruction, HLLC, candidate, MOOD loop
+                    (Steps 3-10), SSP-RK3, dt, totals; plain loops in FP64.
+  exact_riemann.py  Toro's exact Riemann solver for the 1D shock-tube pins.
+
+Pins: see tests/test_oracle_*.py.  Every function here is pinned by at least
+one test against something the paper or the mathematics fixes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+from . import weights_mp
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gpmood_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+ORC_CSD, ORC_PLATEAU, ORC_U2, ORC_RSCAD = 1, 2, 4, 8
+ORC_ALL = ORC_CSD | ORC_PLATEAU | ORC_U2 | ORC_RSCAD
+
+
+def build(force=True):
+    """Compile the oracle with gcc (plain -O2, no FP contraction, no fast-math)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        cp = ctypes.POINTER(_Cfg)
+        L.orc_stage.argtypes = [cp, ctypes.c_int, dp, dp, ctypes.c_double, dp, ip,
+                                ctypes.POINTER(ctypes.c_longlong)]
+        L.orc_stage.restype = ctypes.c_int
+        L.orc_stage_forced.argtypes = [cp, ctypes.c_int, dp, dp, ctypes.c_double, ip, dp]
+        L.orc_candidate.argtypes = [cp, dp, ctypes.c_double, ip, dp, ip]
+        L.orc_criteria.argtypes = [cp, dp, dp, ip, ip, ctypes.POINTER(ctypes.c_uint), ip]
+        L.orc_relax.argtypes = [cp, dp, dp]
+        L.orc_dt.argtypes = [cp, dp, ctypes.c_double]
+        L.orc_dt.restype = ctypes.c_double
+        L.orc_run.argtypes = [cp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp,
+                              ctypes.POINTER(ctypes.c_longlong), ip]
+        L.orc_totals.argtypes = [cp, dp, dp]
+        L.orc_hllc.argtypes = [ctypes.c_double, dp, dp, ctypes.c_int, dp]
+        L.orc_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+        ("bcx", ctypes.c_int), ("bcy", ctypes.c_int),
+        ("gamma", ctypes.c_double),
+        ("nlev", ctypes.c_int),
+        ("rad", ctypes.c_int * 4),
+        ("nst", ctypes.c_int * 4),
+        ("off", ctypes.POINTER(ctypes.c_int) * 4),
+        ("nq", ctypes.c_int * 4),
+        ("qw", ctypes.POINTER(ctypes.c_double) * 4),
+        ("z", ctypes.POINTER(ctypes.c_double) * 4),
+        ("w2", ctypes.POINTER(ctypes.c_double)),
+        ("off1", ctypes.POINTER(ctypes.c_int)),
+        ("sigma_v", ctypes.c_double), ("sigma_p", ctypes.c_double),
+        ("flags", ctypes.c_uint),
+    ]
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+class Oracle:
+    """2D GP-MOOD oracle on a uniform grid [lo, hi] with nx-by-ny cells.
+
+    bc: (bcx, bcy), 0 periodic / 1 outflow.  cascade: radii, strictly decreasing,
+    ending in 0 (FOG).  ell: physical GP length scale.
+    """
+
+    def __init__(self, nx, ny, lo=(0.0, 0.0), hi=(1.0, 1.0), bc=(0, 0), cascade=(3, 2, 1, 0),
+                 ell=None, gamma=1.4, sigma_v=5.0, sigma_p=5.0, flags=ORC_ALL, shape="diamond"):
+        self.nx, self.ny = int(nx), int(ny)
+        self.dx = (hi[0] - lo[0]) / nx
+        self.dy = (hi[1] - lo[1]) / ny
+        if ell is None:
+            ell = 12.0 * min(self.dx, self.dy)
+        self.ell = ell
+        self.cascade = tuple(cascade)
+        ax, ay = ell / self.dx, ell / self.dy
+        self._keep = []
+        c = _Cfg()
+        c.nx, c.ny, c.dx, c.dy = self.nx, self.ny, self.dx, self.dy
+        c.bcx, c.bcy = int(bc[0]), int(bc[1])
+        c.gamma = gamma
+        c.nlev = len(cascade)
+        for l, R in enumerate(cascade):
+            st = np.array(weights_mp.stencil(R, shape), dtype=np.int32).reshape(-1)
+            z = np.array(weights_mp.weights(R, ax, ay, shape), dtype=np.float64).reshape(-1)
+            q = weights_mp.nq(R)
+            _, qw = weights_mp.gauss_rule_float(q)
+            qw = np.array(qw, dtype=np.float64)
+            self._keep += [st, z, qw]
+            c.rad[l] = R
+            c.nst[l] = len(st) // 2
+            c.off[l] = _ip(st)
+            c.nq[l] = q
+            c.qw[l] = _dp(qw)
+            c.z[l] = _dp(z)
+        w2 = np.array(weights_mp.d2_weights(ax, ay, ell), dtype=np.float64).reshape(-1)
+        off1 = np.array(weights_mp.stencil(1), dtype=np.int32).reshape(-1)
+        self._keep += [w2, off1]
+        c.w2 = _dp(w2)
+        c.off1 = _ip(off1)
+        c.sigma_v, c.sigma_p = sigma_v, sigma_p
+        c.flags = flags
+        self.cfg = c
+        self.gamma = gamma
+
+    # -- helpers
+    def _arr(self, U):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        assert U.shape == (4, self.ny, self.nx), U.shape
+        return U
+
+    def stage(self, s, Un, Us, dt):
+        """One stage with the full MOOD loop.  Returns (Uout, order, counts, iters)."""
+        Un, Us = self._arr(Un), self._arr(Us)
+        out = np.empty_like(Us)
+        order = np.empty((self.ny, self.nx), dtype=np.int32)
+        counts = np.zeros(len(self.cascade), dtype=np.int64)
+        it = lib().orc_stage(ctypes.byref(self.cfg), int(s), _dp(Un), _dp(Us), float(dt), _dp(out),
+                             _ip(order), counts.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)))
+        return out, order, counts, it
+
+    def stage_forced(self, s, Un, Us, dt, order):
+        Un, Us = self._arr(Un), self._arr(Us)
+        order = np.ascontiguousarray(order, dtype=np.int32)
+        out = np.empty_like(Us)
+        lib().orc_stage_forced(ctypes.byref(self.cfg), int(s), _dp(Un), _dp(Us), float(dt),
+                               _ip(order), _dp(out))
+        return out
+
+    def candidate(self, Us, dt, order):
+        Us = self._arr(Us)
+        order = np.ascontiguousarray(order, dtype=np.int32)
+        out = np.empty_like(Us)
+        rs = np.empty((self.ny, self.nx), dtype=np.int32)
+        lib().orc_candidate(ctypes.byref(self.cfg), _dp(Us), float(dt), _ip(order), _dp(out), _ip(rs))
+        return out, rs
+
+    def criteria(self, Us, Ustar, order, rsbad=None):
+        Us, Ustar = self._arr(Us), self._arr(Ustar)
+        order = np.ascontiguousarray(order, dtype=np.int32)
+        bits = np.empty((self.ny, self.nx), dtype=np.uint32)
+        tr = np.empty((self.ny, self.nx), dtype=np.int32)
+        rsp = _ip(np.ascontiguousarray(rsbad, dtype=np.int32)) if rsbad is not None else None
+        if rsbad is not None:
+            rsbad = np.ascontiguousarray(rsbad, dtype=np.int32)
+            rsp = _ip(rsbad)
+        lib().orc_criteria(ctypes.byref(self.cfg), _dp(Us), _dp(Ustar), _ip(order), rsp,
+                           bits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint)), _ip(tr))
+        return bits, tr
+
+    def relax(self, Us):
+        Us = self._arr(Us)
+        out = np.empty((self.ny, self.nx, 5))
+        lib().orc_relax(ctypes.byref(self.cfg), _dp(Us), _dp(out))
+        return out
+
+    def dt(self, U, cfl):
+        return lib().orc_dt(ctypes.byref(self.cfg), _dp(self._arr(U)), float(cfl))
+
+    def run(self, U, cfl=0.8, nsteps=1, fixed_dt=0.0):
+        """nsteps SSP-RK3 steps.  Returns (U, dts, counts[nsteps,3,nlev], iters[nsteps,3])."""
+        U = self._arr(U).copy()
+        dts = np.zeros(nsteps)
+        counts = np.zeros((nsteps, 3, len(self.cascade)), dtype=np.int64)
+        iters = np.zeros((nsteps, 3), dtype=np.int32)
+        lib().orc_run(ctypes.byref(self.cfg), _dp(U), float(cfl), float(fixed_dt), int(nsteps),
+                      _dp(dts), counts.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), _ip(iters))
+        return U, dts, counts, iters
+
+    def totals(self, U):
+        t = np.zeros(4)
+        lib().orc_totals(ctypes.byref(self.cfg), _dp(self._arr(U)), _dp(t))
+        return t
+
+
+def hllc(UL, UR, direction=0, gamma=1.4):
+    UL = np.ascontiguousarray(UL, dtype=np.float64)
+    UR = np.ascontiguousarray(UR, dtype=np.float64)
+    F = np.zeros(4)
+    lib().orc_hllc(float(gamma), _dp(UL), _dp(UR), int(direction), _dp(F))
+    return F
+
+
+def num_threads():
+    return lib().orc_num_threads()

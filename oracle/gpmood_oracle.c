@@ -1,0 +1,511 @@
+/*
+ * GP-MOOD oracle: a plain, slow FP64 reference of one SSP-RK3 stage in 2D.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, the smoke check and the benchmark's
+ * CPU-baseline leg may load this library.  It shares no code, header or table
+ * with the product library; its GP weights come from oracle/weights_mp.py.
+ *
+ * Source: Bourgeois & Lee, "GP-MOOD: a positive-preserving high-order finite
+ * volume method for hyperbolic conservation laws".
+ *   - Euler equations and ideal-gas EoS: Sec. "Governing equations", eq. (euler_eqn)
+ *   - FV update with q-point face quadrature: eq. (fvm_discrete), eq. (fvm_F)
+ *   - GP reconstruction z^T q: eq. (gp_reconstructor) (weights are inputs here)
+ *   - FOG (R = 0): Sec. "The full set of spatial reconstruction methods"
+ *   - PAD eq. (PAD), CAD eq. (CAD) and CAD on Riemann states (Sec. CAD),
+ *     DMP eq. (DMP_RK), plateau eq. (plateau), u2 eqs. (u2_curvature, u2_a, u2_b),
+ *     CSD eqs. (divV, gradP)
+ *   - EDP_1 face order: Sec. "The scheme cascade with GP"
+ *   - MOOD loop: Sec. "Stepwise implementation", Steps 3-10
+ *   - SSP-RK3: eq. (rk3)
+ *   - HLLC: the paper only cites Toro et al. 1994; the textbook form is used
+ *     (Davis wave-speed estimates, Toro's star states).
+ *
+ * Every loop below is the plain definition: each MOOD iteration recomputes every
+ * face flux and every candidate from scratch and re-detects every cell.
+ * Build with -O2 -ffp-contract=off, no fast-math (NaN/Inf are legitimate values
+ * that CAD must see).  OpenMP only splits independent per-face and per-cell loops.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NV 4
+#define GH 4 /* ghost depth: R_max + 1 = 4 for R = 3; u2 needs 2 */
+
+enum { ORC_CSD = 1u, ORC_PLATEAU = 2u, ORC_U2 = 4u, ORC_RSCAD = 8u };
+
+typedef struct {
+    int nx, ny;
+    double dx, dy;
+    int bcx, bcy; /* 0 periodic, 1 outflow (zero gradient) */
+    double gamma;
+    int nlev;
+    int rad[4];         /* cascade radii, strictly decreasing, last one 0 (FOG) */
+    int nst[4];         /* stencil size per level */
+    const int *off[4];  /* per level: [nst][2] offsets (di, dj) */
+    int nq[4];          /* quadrature points per face per level */
+    const double *qw[4];/* per level: quadrature weights [nq] */
+    const double *z[4]; /* per level: weights [4 faces: x-, x+, y-, y+][nq][nst] */
+    const double *w2;   /* [2][5] u2 curvature weights on the R = 1 stencil */
+    const int *off1;    /* [5][2] R = 1 stencil offsets matching w2 */
+    double sigma_v, sigma_p;
+    unsigned flags;
+} orc_cfg;
+
+/* ---------------------------------------------------------------- helpers */
+static double dmin(double a, double b) { return a < b ? a : b; }
+static double dmax(double a, double b) { return a > b ? a : b; }
+
+static int src_index(int i, int n, int bc)
+{
+    if (bc == 0) { int r = i % n; return r < 0 ? r + n : r; }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+typedef struct { int NX, NY; double *u; } ghosted;
+
+static size_t gidx(const ghosted *g, int v, int i, int j)
+{
+    return ((size_t)v * g->NY + (size_t)(j + GH)) * g->NX + (size_t)(i + GH);
+}
+
+static void fill_ghosted(const orc_cfg *c, const double *U, ghosted *g)
+{
+    g->NX = c->nx + 2 * GH;
+    g->NY = c->ny + 2 * GH;
+    g->u = (double *)malloc(sizeof(double) * NV * g->NX * g->NY);
+    for (int v = 0; v < NV; ++v)
+        for (int j = -GH; j < c->ny + GH; ++j)
+            for (int i = -GH; i < c->nx + GH; ++i) {
+                int si = src_index(i, c->nx, c->bcx), sj = src_index(j, c->ny, c->bcy);
+                g->u[gidx(g, v, i, j)] = U[((size_t)v * c->ny + sj) * c->nx + si];
+            }
+}
+
+static double pressure(double g, const double *q) /* ideal-gas EoS on conservative variables */
+{
+    return (g - 1.0) * (q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) / q[0]);
+}
+
+static int level_of(const orc_cfg *c, int r)
+{
+    for (int l = 0; l < c->nlev; ++l)
+        if (c->rad[l] == r) return l;
+    return -1;
+}
+
+/* ------------------------------------------------------------------ HLLC */
+/* Flux through a face with unit normal along axis `dir` (0: x, 1: y). */
+static void hllc(double g, const double *UL, const double *UR, int dir, double *F)
+{
+    int n = 1 + dir, t = 2 - dir;
+    double rl = UL[0], ul = UL[n] / rl, vl = UL[t] / rl, El = UL[3];
+    double rr = UR[0], ur = UR[n] / rr, vr = UR[t] / rr, Er = UR[3];
+    double pl = (g - 1.0) * (El - 0.5 * rl * (ul * ul + vl * vl));
+    double pr = (g - 1.0) * (Er - 0.5 * rr * (ur * ur + vr * vr));
+    double cl = sqrt(g * pl / rl), cr = sqrt(g * pr / rr);
+    double SL = dmin(ul - cl, ur - cr);
+    double SR = dmax(ul + cl, ur + cr);
+    double Ss = (pr - pl + rl * ul * (SL - ul) - rr * ur * (SR - ur)) /
+                (rl * (SL - ul) - rr * (SR - ur));
+    double f[4];
+    if (SL >= 0.0) {
+        f[0] = rl * ul; f[1] = rl * ul * ul + pl; f[2] = rl * ul * vl; f[3] = ul * (El + pl);
+    } else if (Ss >= 0.0) {
+        double fac = rl * (SL - ul) / (SL - Ss);
+        double us[4] = {fac, fac * Ss, fac * vl,
+                        fac * (El / rl + (Ss - ul) * (Ss + pl / (rl * (SL - ul))))};
+        double uk[4] = {rl, rl * ul, rl * vl, El};
+        double fk[4] = {rl * ul, rl * ul * ul + pl, rl * ul * vl, ul * (El + pl)};
+        for (int k = 0; k < 4; ++k) f[k] = fk[k] + SL * (us[k] - uk[k]);
+    } else if (SR > 0.0) {
+        double fac = rr * (SR - ur) / (SR - Ss);
+        double us[4] = {fac, fac * Ss, fac * vr,
+                        fac * (Er / rr + (Ss - ur) * (Ss + pr / (rr * (SR - ur))))};
+        double uk[4] = {rr, rr * ur, rr * vr, Er};
+        double fk[4] = {rr * ur, rr * ur * ur + pr, rr * ur * vr, ur * (Er + pr)};
+        for (int k = 0; k < 4; ++k) f[k] = fk[k] + SR * (us[k] - uk[k]);
+    } else {
+        f[0] = rr * ur; f[1] = rr * ur * ur + pr; f[2] = rr * ur * vr; f[3] = ur * (Er + pr);
+    }
+    /* back from (normal, tangential) to (x, y) momentum components */
+    F[0] = f[0]; F[n] = f[1]; F[t] = f[2]; F[3] = f[3];
+}
+
+void orc_hllc(double g, const double *UL, const double *UR, int dir, double *F)
+{
+    hllc(g, UL, UR, dir, F);
+}
+
+/* --------------------------------------------------- GP reconstruction */
+/* State of cell (i, j) (ghosted indices allowed) at face f, point k, level l. */
+static void recon(const orc_cfg *c, const ghosted *g, int l, int f, int k, int i, int j, double *q)
+{
+    int ns = c->nst[l];
+    const double *z = c->z[l] + ((size_t)f * c->nq[l] + k) * ns;
+    for (int v = 0; v < NV; ++v) {
+        double s = 0.0;
+        for (int m = 0; m < ns; ++m)
+            s += z[m] * g->u[gidx(g, v, i + c->off[l][2 * m], j + c->off[l][2 * m + 1])];
+        q[v] = s;
+    }
+}
+
+static int state_nonfinite(double gam, const double *q)
+{
+    return !isfinite(q[0]) || !isfinite(pressure(gam, q));
+}
+
+/* --------------------------------------------- per-stage relaxation data */
+typedef struct { double rmin, rmax; int plat, csd, u2; } relax_t;
+
+static double rho_at(const ghosted *g, int i, int j) { return g->u[gidx(g, 0, i, j)]; }
+
+static void cell_relax(const orc_cfg *c, const ghosted *g, int i, int j, relax_t *r)
+{
+    double gam = c->gamma;
+    /* DMP bounds over N(ij) U {ij}: the four face neighbours and the cell, eq. (DMP_RK) */
+    const int nb[5][2] = {{0, 0}, {-1, 0}, {1, 0}, {0, -1}, {0, 1}};
+    double lo = rho_at(g, i, j), hi = lo;
+    for (int k = 1; k < 5; ++k) {
+        double v = rho_at(g, i + nb[k][0], j + nb[k][1]);
+        lo = dmin(lo, v);
+        hi = dmax(hi, v);
+    }
+    r->rmin = lo;
+    r->rmax = hi;
+    /* plateau, eq. (plateau) */
+    r->plat = (hi - lo) < dmin(c->dx * c->dx * c->dx, c->dy * c->dy * c->dy);
+    /* CSD, eqs. (divV) and (gradP), on the stage's cell averages */
+    double qE[4], qW[4], qN[4], qS[4];
+    for (int v = 0; v < NV; ++v) {
+        qE[v] = g->u[gidx(g, v, i + 1, j)];
+        qW[v] = g->u[gidx(g, v, i - 1, j)];
+        qN[v] = g->u[gidx(g, v, i, j + 1)];
+        qS[v] = g->u[gidx(g, v, i, j - 1)];
+    }
+    double divV = (qE[1] / qE[0] - qW[1] / qW[0]) / (2.0 * c->dx) +
+                  (qN[2] / qN[0] - qS[2] / qS[0]) / (2.0 * c->dy);
+    double pE = pressure(gam, qE), pW = pressure(gam, qW);
+    double pN = pressure(gam, qN), pS = pressure(gam, qS);
+    double gradp = fabs(pE - pW) / (2.0 * c->dx * dmin(pE, pW)) +
+                   fabs(pN - pS) / (2.0 * c->dy * dmin(pN, pS));
+    r->csd = (divV >= -c->sigma_v) && (gradp <= c->sigma_p);
+    /* u2, eqs. (u2_curvature), (u2_a), (u2_b): GP-R1 second derivatives of rho
+       at the cell and its face neighbours, per direction */
+    double delta = dmin(c->dx, c->dy);
+    int ok = 1;
+    for (int d = 0; d < 2; ++d) {
+        double cmin = 0.0, cmax = 0.0;
+        for (int k = 0; k < 5; ++k) {
+            int mi = i + nb[k][0], mj = j + nb[k][1];
+            double kap = 0.0;
+            for (int m = 0; m < 5; ++m)
+                kap += c->w2[d * 5 + m] * rho_at(g, mi + c->off1[2 * m], mj + c->off1[2 * m + 1]);
+            if (k == 0) { cmin = kap; cmax = kap; }
+            else { cmin = dmin(cmin, kap); cmax = dmax(cmax, kap); }
+        }
+        int a = (cmin * cmax > -delta) && (dmax(fabs(cmax), fabs(cmin)) < delta);
+        int b = (cmin * cmax > -delta) && (fabs(cmin) / fabs(cmax) >= 0.5);
+        ok = ok && (a || b);
+    }
+    r->u2 = ok;
+}
+
+/* Criteria bits of one cell: bit0 CAD(candidate), bit1 RS-CAD ok, bit2 PAD,
+   bit3 CSD, bit4 plateau, bit5 DMP, bit6 u2. */
+static unsigned criteria(const orc_cfg *c, const relax_t *r, const double *us, int rs_bad)
+{
+    double rho = us[0], p = pressure(c->gamma, us);
+    unsigned b = 0;
+    if (isfinite(rho) && isfinite(p)) b |= 1u;
+    if (!rs_bad) b |= 2u;
+    if (rho > 0.0 && p > 0.0) b |= 4u;
+    if (r->csd) b |= 8u;
+    if (r->plat) b |= 16u;
+    if (r->rmin <= rho && rho <= r->rmax) b |= 32u;
+    if (r->u2) b |= 64u;
+    return b;
+}
+
+/* Steps 4-10 of the stepwise algorithm for one cell; returns 1 if troubled. */
+static int detect(const orc_cfg *c, int order, unsigned b)
+{
+    if (order == 0) return 0;                                   /* Step 10: FOG accepted */
+    if (!(b & 1u)) return 1;                                    /* Step 4: CAD */
+    if ((c->flags & ORC_RSCAD) && !(b & 2u)) return 1;          /*         CAD on Riemann states */
+    if (!(b & 4u)) return 1;                                    /* Step 5: PAD */
+    if ((c->flags & ORC_CSD) && (b & 8u)) return 0;             /* Step 6: CSD early accept */
+    if ((c->flags & ORC_PLATEAU) && (b & 16u)) return 0;        /* Step 7: plateau */
+    if (b & 32u) return 0;                                      /* Step 8: DMP */
+    if ((c->flags & ORC_U2) && (b & 64u)) return 0;             /* Step 9: u2 */
+    return 1;
+}
+
+/* ------------------------------------------------------ candidate update */
+/* One evaluation of U* = U_s - dt F_nabla(U_s) with per-cell orders (EDP_1 faces).
+   rsbad[cell] receives the Riemann-state CAD flags of each cell's own states. */
+static void candidate(const orc_cfg *c, const ghosted *g, const int *order, double dt,
+                      double *Ustar, int *rsbad)
+{
+    int nx = c->nx, ny = c->ny;
+    size_t ncell = (size_t)nx * ny;
+    double *Fx = (double *)calloc((size_t)NV * (nx + 1) * ny, sizeof(double));
+    double *Gy = (double *)calloc((size_t)NV * nx * (ny + 1), sizeof(double));
+    unsigned char *rsx = (unsigned char *)calloc((size_t)(nx + 1) * ny, 1);
+    unsigned char *rsy = (unsigned char *)calloc((size_t)nx * (ny + 1), 1);
+    double gam = c->gamma;
+
+    /* x faces: face i sits between cells (i-1, j) [left] and (i, j) [right] */
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i <= nx; ++i) {
+            int oL = order[(size_t)j * nx + src_index(i - 1, nx, c->bcx)];
+            int oR = order[(size_t)j * nx + src_index(i, nx, c->bcx)];
+            int l = level_of(c, oL < oR ? oL : oR); /* EDP_1: min of the two orders */
+            double F[4] = {0, 0, 0, 0};
+            unsigned char bad = 0;
+            for (int k = 0; k < c->nq[l]; ++k) {
+                double qL[4], qR[4], f[4];
+                recon(c, g, l, 1, k, i - 1, j, qL); /* x+ face of the left cell */
+                recon(c, g, l, 0, k, i, j, qR);     /* x- face of the right cell */
+                if (state_nonfinite(gam, qL)) bad |= 1;
+                if (state_nonfinite(gam, qR)) bad |= 2;
+                hllc(gam, qL, qR, 0, f);
+                for (int v = 0; v < NV; ++v) F[v] += c->qw[l][k] * f[v];
+            }
+            for (int v = 0; v < NV; ++v) Fx[((size_t)v * ny + j) * (nx + 1) + i] = F[v];
+            rsx[(size_t)j * (nx + 1) + i] = bad;
+        }
+    /* y faces: face j sits between cells (i, j-1) [bottom/left] and (i, j) [top/right] */
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j <= ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            int oL = order[(size_t)src_index(j - 1, ny, c->bcy) * nx + i];
+            int oR = order[(size_t)src_index(j, ny, c->bcy) * nx + i];
+            int l = level_of(c, oL < oR ? oL : oR);
+            double G[4] = {0, 0, 0, 0};
+            unsigned char bad = 0;
+            for (int k = 0; k < c->nq[l]; ++k) {
+                double qL[4], qR[4], f[4];
+                recon(c, g, l, 3, k, i, j - 1, qL); /* y+ face of the lower cell */
+                recon(c, g, l, 2, k, i, j, qR);     /* y- face of the upper cell */
+                if (state_nonfinite(gam, qL)) bad |= 1;
+                if (state_nonfinite(gam, qR)) bad |= 2;
+                hllc(gam, qL, qR, 1, f);
+                for (int v = 0; v < NV; ++v) G[v] += c->qw[l][k] * f[v];
+            }
+            for (int v = 0; v < NV; ++v) Gy[((size_t)v * (ny + 1) + j) * nx + i] = G[v];
+            rsy[(size_t)j * nx + i] = bad;
+        }
+    /* candidate, eq. (fvm_discrete) with eq. (fvm_F) */
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            size_t cidx = (size_t)j * nx + i;
+            for (int v = 0; v < NV; ++v) {
+                double us = g->u[gidx(g, v, i, j)];
+                double dF = Fx[((size_t)v * ny + j) * (nx + 1) + i + 1] - Fx[((size_t)v * ny + j) * (nx + 1) + i];
+                double dG = Gy[((size_t)v * (ny + 1) + j + 1) * nx + i] - Gy[((size_t)v * (ny + 1) + j) * nx + i];
+                Ustar[(size_t)v * ncell + cidx] = us - dt * (dF / c->dx + dG / c->dy);
+            }
+            /* the cell owns the right state of its left faces and the left state of its right faces */
+            rsbad[cidx] = ((rsx[(size_t)j * (nx + 1) + i] & 2) != 0) ||
+                          ((rsx[(size_t)j * (nx + 1) + i + 1] & 1) != 0) ||
+                          ((rsy[(size_t)j * nx + i] & 2) != 0) ||
+                          ((rsy[(size_t)(j + 1) * nx + i] & 1) != 0);
+        }
+    free(Fx); free(Gy); free(rsx); free(rsy);
+}
+
+static void combine(const orc_cfg *c, int s, const double *Un, const double *Ustar, double *Uout)
+{
+    size_t n = (size_t)NV * c->nx * c->ny;
+    for (size_t k = 0; k < n; ++k) {
+        if (s == 0) Uout[k] = Ustar[k];                                  /* U^(1) */
+        else if (s == 1) Uout[k] = 0.25 * (3.0 * Un[k] + Ustar[k]);      /* hat U^(2) */
+        else Uout[k] = (Un[k] + 2.0 * Ustar[k]) / 3.0;                   /* U^(n+1) */
+    }
+}
+
+/* --------------------------------------------------------------- stage */
+/* One SSP-RK3 stage with the full MOOD loop.
+   order_out: final radius per cell; counts[l]: cells ending at level l;
+   returns the number of MOOD iterations (candidate evaluations). */
+int orc_stage(const orc_cfg *c, int s, const double *Un, const double *Us, double dt,
+              double *Uout, int *order_out, long long *counts)
+{
+    int nx = c->nx, ny = c->ny;
+    size_t ncell = (size_t)nx * ny;
+    ghosted g;
+    fill_ghosted(c, Us, &g);
+    relax_t *rx = (relax_t *)malloc(sizeof(relax_t) * ncell);
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) cell_relax(c, &g, i, j, &rx[(size_t)j * nx + i]);
+
+    int *order = (int *)malloc(sizeof(int) * ncell);
+    for (size_t k = 0; k < ncell; ++k) order[k] = c->rad[0]; /* every stage starts at the top order */
+    double *Ustar = (double *)malloc(sizeof(double) * NV * ncell);
+    int *rsbad = (int *)malloc(sizeof(int) * ncell);
+    int *trouble = (int *)malloc(sizeof(int) * ncell);
+    int iters = 0;
+    for (;;) {
+        ++iters;
+        candidate(c, &g, order, dt, Ustar, rsbad);
+        long long ntr = 0;
+#pragma omp parallel for schedule(static) reduction(+ : ntr)
+        for (long long k = 0; k < (long long)ncell; ++k) {
+            double us[4];
+            for (int v = 0; v < NV; ++v) us[v] = Ustar[(size_t)v * ncell + k];
+            trouble[k] = detect(c, order[k], criteria(c, &rx[k], us, rsbad[k]));
+            ntr += trouble[k];
+        }
+        if (ntr == 0) break;
+        for (size_t k = 0; k < ncell; ++k)
+            if (trouble[k]) order[k] = c->rad[level_of(c, order[k]) + 1]; /* next scheme in the cascade */
+    }
+    combine(c, s, Un, Ustar, Uout);
+    if (counts)
+        for (int l = 0; l < c->nlev; ++l) counts[l] = 0;
+    for (size_t k = 0; k < ncell; ++k) {
+        if (order_out) order_out[k] = order[k];
+        if (counts) counts[level_of(c, order[k])]++;
+    }
+    free(order); free(Ustar); free(rsbad); free(trouble); free(rx); free(g.u);
+    return iters;
+}
+
+/* Stage with prescribed per-cell orders (no detection): "forced-mask" replay. */
+void orc_stage_forced(const orc_cfg *c, int s, const double *Un, const double *Us, double dt,
+                      const int *order, double *Uout)
+{
+    size_t ncell = (size_t)c->nx * c->ny;
+    ghosted g;
+    fill_ghosted(c, Us, &g);
+    double *Ustar = (double *)malloc(sizeof(double) * NV * ncell);
+    int *rsbad = (int *)malloc(sizeof(int) * ncell);
+    candidate(c, &g, order, dt, Ustar, rsbad);
+    combine(c, s, Un, Ustar, Uout);
+    free(Ustar); free(rsbad); free(g.u);
+}
+
+/* Candidate only (U* and the per-cell Riemann-state CAD flags) for given orders. */
+void orc_candidate(const orc_cfg *c, const double *Us, double dt, const int *order,
+                   double *Ustar, int *rsbad)
+{
+    ghosted g;
+    fill_ghosted(c, Us, &g);
+    candidate(c, &g, order, dt, Ustar, rsbad);
+    free(g.u);
+}
+
+/* Criteria bits (see criteria()) and the verdict for every cell, for a given
+   stage input, candidate, orders and Riemann-state flags. */
+void orc_criteria(const orc_cfg *c, const double *Us, const double *Ustar, const int *order,
+                  const int *rsbad, unsigned *bits, int *troubled)
+{
+    int nx = c->nx, ny = c->ny;
+    size_t ncell = (size_t)nx * ny;
+    ghosted g;
+    fill_ghosted(c, Us, &g);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            size_t k = (size_t)j * nx + i;
+            relax_t r;
+            cell_relax(c, &g, i, j, &r);
+            double us[4];
+            for (int v = 0; v < NV; ++v) us[v] = Ustar[(size_t)v * ncell + k];
+            unsigned b = criteria(c, &r, us, rsbad ? rsbad[k] : 0);
+            if (bits) bits[k] = b;
+            if (troubled) troubled[k] = detect(c, order[k], b);
+        }
+    free(g.u);
+}
+
+/* Relaxation data of every cell: rmin, rmax and (plateau, csd, u2) as 0/1 doubles. */
+void orc_relax(const orc_cfg *c, const double *Us, double *out /* [ncell][5] */)
+{
+    int nx = c->nx, ny = c->ny;
+    ghosted g;
+    fill_ghosted(c, Us, &g);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            relax_t r;
+            cell_relax(c, &g, i, j, &r);
+            double *o = out + 5 * ((size_t)j * nx + i);
+            o[0] = r.rmin; o[1] = r.rmax; o[2] = r.plat; o[3] = r.csd; o[4] = r.u2;
+        }
+    free(g.u);
+}
+
+/* ----------------------------------------------------------------- dt */
+/* dt = CFL * min over cells and directions of Delta_d / (|u_d| + c), from U^n.
+   Cells without a sound speed (rho or p not positive and finite) are skipped. */
+double orc_dt(const orc_cfg *c, const double *U, double cfl)
+{
+    size_t ncell = (size_t)c->nx * c->ny;
+    double lam = 0.0;
+    for (size_t k = 0; k < ncell; ++k) {
+        double q[4];
+        for (int v = 0; v < NV; ++v) q[v] = U[(size_t)v * ncell + k];
+        double p = pressure(c->gamma, q);
+        if (!(q[0] > 0.0 && p > 0.0 && isfinite(q[0]) && isfinite(p))) continue;
+        double cs = sqrt(c->gamma * p / q[0]);
+        double lx = (fabs(q[1] / q[0]) + cs) / c->dx;
+        double ly = (fabs(q[2] / q[0]) + cs) / c->dy;
+        lam = dmax(lam, dmax(lx, ly));
+    }
+    return cfl / lam;
+}
+
+/* --------------------------------------------------------------- step */
+/* nsteps SSP-RK3 steps in place.  dts (nullable) receives each step's dt;
+   counts (nullable) [nsteps*3][nlev] final-order counts; iters (nullable) [nsteps*3]. */
+void orc_run(const orc_cfg *c, double *U, double cfl, double fixed_dt, int nsteps,
+             double *dts, long long *counts, int *iters)
+{
+    size_t n = (size_t)NV * c->nx * c->ny;
+    double *U1 = (double *)malloc(sizeof(double) * n);
+    double *U2 = (double *)malloc(sizeof(double) * n);
+    for (int st = 0; st < nsteps; ++st) {
+        double dt = fixed_dt > 0.0 ? fixed_dt : orc_dt(c, U, cfl);
+        if (dts) dts[st] = dt;
+        long long *cn = counts ? counts + (size_t)st * 3 * c->nlev : 0;
+        int a = orc_stage(c, 0, U, U, dt, U1, 0, cn);
+        int b = orc_stage(c, 1, U, U1, dt, U2, 0, cn ? cn + c->nlev : 0);
+        int d = orc_stage(c, 2, U, U2, dt, U1, 0, cn ? cn + 2 * c->nlev : 0);
+        if (iters) { iters[3 * st] = a; iters[3 * st + 1] = b; iters[3 * st + 2] = d; }
+        memcpy(U, U1, sizeof(double) * n);
+    }
+    free(U1); free(U2);
+}
+
+/* -------------------------------------------------------------- totals */
+/* Neumaier-compensated sum of each conserved variable times the cell area. */
+void orc_totals(const orc_cfg *c, const double *U, double *tot)
+{
+    size_t ncell = (size_t)c->nx * c->ny;
+    for (int v = 0; v < NV; ++v) {
+        double s = 0.0, comp = 0.0;
+        for (size_t k = 0; k < ncell; ++k) {
+            double x = U[(size_t)v * ncell + k];
+            double t = s + x;
+            if (fabs(s) >= fabs(x)) comp += (s - t) + x;
+            else comp += (x - t) + s;
+            s = t;
+        }
+        tot[v] = (s + comp) * c->dx * c->dy;
+    }
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
