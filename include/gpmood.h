@@ -1,0 +1,173 @@
+/*
+ * gpmood.h -- C ABI of the MI355X (gfx950) GP-MOOD stage engine.
+ *
+ * The library advances cell averages of the 2D compressible Euler equations
+ * (Bourgeois & Lee, "GP-MOOD", Sec. "Governing equations", eq. (euler_eqn);
+ * ideal gas, p = (gamma-1)(E - |m|^2/(2 rho))) on a uniform Cartesian grid with
+ * the GP-MOOD finite-volume method: (2R+1)th-order GP reconstruction
+ * (eq. (gp_reconstructor)) at the Gauss nodes of Table tab:QR-pt-weight, HLLC
+ * fluxes, the a-posteriori MOOD loop (Sec. "Stepwise implementation", Steps 3-10)
+ * with EDP_1 face orders, and SSP-RK3 (eq. (rk3)).
+ *
+ * Conventions for every entry point:
+ *  - Return a gpm_status; no C++ exception crosses the ABI.  gpm_strerror()
+ *    gives a message, including the HIP error text for GPM_EHIP.
+ *  - Device buffers are owned by the caller and bound with gpm_bind(); the
+ *    library never allocates or frees device memory.  Host arrays are owned by
+ *    the caller and only read or written during the call.
+ *  - Work is queued on the HIP stream given to gpm_create() (NULL: the null
+ *    stream) and is asynchronous, except for the calls documented as
+ *    synchronising (they wait for the stream).
+ *  - Layout of a state: structure of arrays, double or float as chosen at
+ *    creation, [var][j][i] with i (x) fastest, var = rho, rho*u, rho*v, E;
+ *    nx*ny interior cells, no ghost cells (boundary conditions are applied
+ *    by index remapping inside the kernels).
+ *  - A context is not thread-safe; separate contexts are independent.
+ *  - Physically inadmissible states (negative density or pressure, NaN, Inf)
+ *    are not errors: they are what the MOOD detection handles.
+ */
+#ifndef GPMOOD_H
+#define GPMOOD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gpm_ctx gpm_ctx;
+
+typedef enum {
+    GPM_OK = 0,
+    GPM_EINVAL = 1,      /* bad argument: null pointer, size, radius, cascade, ell, gamma */
+    GPM_ENOMEM = 2,      /* host allocation failed */
+    GPM_EHIP = 3,        /* a HIP runtime call failed (message kept) */
+    GPM_ESTATE = 4,      /* call out of order (no scheme, nothing bound) */
+    GPM_ENOTCONV = 5,    /* the MOOD loop exceeded its pass limit (cannot happen for a
+                            terminating cascade; reported rather than looping forever) */
+    GPM_EUNSUPPORTED = 6 /* configuration not built (e.g. dim != 2) */
+} gpm_status;
+
+typedef enum { GPM_F32 = 0, GPM_F64 = 1 } gpm_prec;
+typedef enum { GPM_BC_PERIODIC = 0, GPM_BC_OUTFLOW = 1 } gpm_bc;
+
+/* Grid: n[d] cells on [lo[d], hi[d]], one boundary condition per axis
+   (periodic wraps, outflow copies the nearest interior cell: zero gradient). */
+typedef struct {
+    int dim;        /* 2 */
+    int n[3];       /* nx, ny (n[2] ignored in 2D) */
+    double lo[3], hi[3];
+    int bc[3];      /* gpm_bc per axis */
+    double gamma;   /* ratio of specific heats, > 1 (paper: 1.4) */
+} gpm_grid;
+
+/* Detection switches (gpm_scheme.flags); GPM_FLAGS_ALL is the paper's method. */
+enum {
+    GPM_CSD = 1u,      /* compressibility-shock early accept, eqs. (divV), (gradP) */
+    GPM_PLATEAU = 2u,  /* plateau relaxation, eq. (plateau) */
+    GPM_U2 = 4u,       /* u2 relaxation with GP-R1 curvature, eqs. (u2_a), (u2_b), App. B */
+    GPM_RSCAD = 8u,    /* CAD on the cell's reconstructed Riemann states (Sec. CAD) */
+    GPM_FLAGS_ALL = 15u
+};
+
+/* Scheme: the order cascade as GP radii, strictly decreasing and ending at 0
+   (FOG, the safe scheme), e.g. {3,2,1,0} (7->5->3->1) or the paper's GP-MOOD7
+   {3,1,0} (Sec. "The scheme cascade with GP"); radius R uses the (R+1)-point
+   Gauss rule.  ell is the physical GP length scale (Sec. "Basic theory on GP
+   regression": ell = 6 or 12 min(dx, dy) by default; 0 selects 12 min(dx,dy)). */
+typedef struct {
+    int nlev;
+    int radius[4];
+    double ell;
+    double sigma_v, sigma_p; /* CSD thresholds (paper: 5, 5) */
+    unsigned flags;          /* GPM_* detection switches */
+} gpm_scheme;
+
+/* Create a context for a grid, a precision and a HIP stream (hipStream_t, may be
+   NULL).  Allocates host memory only.  Errors: GPM_EINVAL (bad grid, gamma <= 1,
+   n < 1 or > 32768 per axis), GPM_EUNSUPPORTED (dim != 2). */
+gpm_status gpm_create(const gpm_grid *grid, int prec, void *hip_stream, gpm_ctx **out);
+
+/* Set the cascade, ell, CSD thresholds and flags.  Builds the GP prediction
+   vectors on the host in quadruple precision (eqs. (SE-pred), (SE-cov),
+   (gp_reconstructor), (normalized_z) with the signed-sum normalisation; Cholesky
+   of C as in Sec. "Singularity of the covariance kernel matrix") and the GP-R1
+   second-derivative weights of App. B, then rounds them to the context's
+   precision.  Errors: GPM_EINVAL for a cascade that is not strictly decreasing,
+   does not end at 0, has a radius outside 0..3 or more than 4 levels, ell < 0, or
+   a covariance matrix that is not numerically positive definite. */
+gpm_status gpm_set_scheme(gpm_ctx *ctx, const gpm_scheme *scheme);
+
+/* Bytes the caller must provide: state_bytes for three state slots (each
+   4*nx*ny elements of the context's precision), work_bytes for the workspace
+   (orders, troubled lists, counters, reduction partials).  Either pointer may
+   be NULL. */
+gpm_status gpm_workspace_size(const gpm_ctx *ctx, size_t *state_bytes, size_t *work_bytes);
+
+/* Bind caller-owned device memory: `state` (>= state_bytes, 256-byte aligned)
+   and `work` (>= work_bytes, 256-byte aligned).  Slot 0 is the current state
+   after gpm_init_state(); gpm_step() rotates the slots.  Errors: GPM_EINVAL for a
+   NULL or misaligned pointer. */
+gpm_status gpm_bind(gpm_ctx *ctx, void *state, void *work);
+
+/* Device address of state slot `slot` (0..2) and the slot that holds the
+   current solution (for zero-copy views).  Errors: GPM_ESTATE if not bound. */
+gpm_status gpm_state_ptr(const gpm_ctx *ctx, int slot, void **ptr, int *current_slot);
+
+/* Copy interior cell averages from the host (double, SoA [4][ny][nx]) into the
+   current state, converting to the context's precision.  Synchronising. */
+gpm_status gpm_init_state(gpm_ctx *ctx, const double *U_host);
+
+/* Copy the current state to the host as double (SoA).  Synchronising. */
+gpm_status gpm_get_state(gpm_ctx *ctx, double *U_host);
+
+/* CFL time step from the current state (read as U^n): dt = cfl * min over cells
+   and axes of Delta_d / (|u_d| + c) in FP64 (reading of the paper's CFL
+   condition, Sec. "Numerical stability"); cells without a sound speed (rho or p
+   not positive and finite) are skipped.  The result stays on the device for the
+   next stages; if dt_host is non-NULL the call synchronises and returns it. */
+gpm_status gpm_compute_dt(gpm_ctx *ctx, double cfl, double *dt_host);
+
+/* Set the device dt directly (for replays and fixed-step runs). */
+gpm_status gpm_set_dt(gpm_ctx *ctx, double dt);
+
+/* One SSP-RK3 stage s (0, 1, 2) of eq. (rk3) on caller device buffers:
+   U_out = combine_s(U_n, U_s - dt F(U_s)), with the MOOD loop run to completion
+   on the candidate U_s - dt F(U_s).  U_n, U_s, U_out hold 4*nx*ny elements of the
+   context's precision; U_out must not alias U_s (U_n may alias U_s when s = 0).
+   Synchronises once per batch of cascade passes to test for termination.
+   Errors: GPM_ESTATE (no scheme or not bound), GPM_EINVAL (s, pointers),
+   GPM_ENOTCONV (pass limit). */
+gpm_status gpm_stage_dev(gpm_ctx *ctx, int s, const void *U_n, const void *U_s, void *U_out);
+
+/* nsteps full steps on the bound slots: dt from the current state (cfl > 0) or
+   the device dt set by gpm_set_dt (cfl <= 0), then stages 0, 1, 2. */
+gpm_status gpm_step(gpm_ctx *ctx, double cfl, int nsteps);
+
+/* Statistics of the last stage: counts[l] = cells whose final scheme is
+   cascade level l (the paper's per-step troubled-cell fractions), mood_iters =
+   number of candidate evaluations (1 + cascade passes).  Synchronising. */
+gpm_status gpm_troubled_counts(gpm_ctx *ctx, long long counts[4], int *mood_iters);
+
+/* Final per-cell GP radius of the last stage (uint8 [ny][nx]).  Synchronising. */
+gpm_status gpm_get_order_mask(gpm_ctx *ctx, unsigned char *order_host);
+
+/* Conserved totals sum(U) * dx * dy of the current state, per variable, with a
+   compensated (double-double) reduction in a fixed order.  Synchronising. */
+gpm_status gpm_totals(gpm_ctx *ctx, double totals[4]);
+
+/* Totals of an arbitrary device state (same layout as a slot).  Synchronising. */
+gpm_status gpm_totals_dev(gpm_ctx *ctx, const void *U, double totals[4]);
+
+/* Tunables: cascade passes launched between termination checks (>= 1) and rows
+   per wavefront march in the first pass (4..256).  Defaults 4 and 16. */
+gpm_status gpm_set_tuning(gpm_ctx *ctx, int passes_per_check, int rows_per_wave);
+
+const char *gpm_strerror(gpm_status st);
+const char *gpm_last_error(const gpm_ctx *ctx);
+void gpm_destroy(gpm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPMOOD_H */

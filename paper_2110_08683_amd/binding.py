@@ -1,0 +1,223 @@
+"""Thin ctypes binding of libgpmood.so (include/gpmood.h), names as in the C ABI.
+
+Argument marshalling only: every step of the stage runs in the HIP kernels of the
+library.  PyTorch supplies device memory (uint8 tensors sized by
+gpm_workspace_size) and the HIP stream.  If the library has not been built the
+import fails loudly; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgpmood.so")
+
+GPM_OK, GPM_EINVAL, GPM_ENOMEM, GPM_EHIP, GPM_ESTATE, GPM_ENOTCONV, GPM_EUNSUPPORTED = range(7)
+GPM_F32, GPM_F64 = 0, 1
+GPM_BC_PERIODIC, GPM_BC_OUTFLOW = 0, 1
+GPM_CSD, GPM_PLATEAU, GPM_U2, GPM_RSCAD = 1, 2, 4, 8
+GPM_FLAGS_ALL = 15
+
+# every symbol include/gpmood.h declares
+EXPORTS = ("gpm_create", "gpm_set_scheme", "gpm_workspace_size", "gpm_bind", "gpm_state_ptr",
+           "gpm_init_state", "gpm_get_state", "gpm_compute_dt", "gpm_set_dt", "gpm_stage_dev",
+           "gpm_step", "gpm_troubled_counts", "gpm_get_order_mask", "gpm_totals", "gpm_totals_dev",
+           "gpm_set_tuning", "gpm_strerror", "gpm_last_error", "gpm_destroy")
+
+
+class gpm_grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("lo", ctypes.c_double * 3),
+                ("hi", ctypes.c_double * 3), ("bc", ctypes.c_int * 3), ("gamma", ctypes.c_double)]
+
+
+class gpm_scheme(ctypes.Structure):
+    _fields_ = [("nlev", ctypes.c_int), ("radius", ctypes.c_int * 4), ("ell", ctypes.c_double),
+                ("sigma_v", ctypes.c_double), ("sigma_p", ctypes.c_double), ("flags", ctypes.c_uint)]
+
+
+class GpmError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libgpmood.so (raises if it is missing: build it with __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: the HIP library must be built (python -c "
+                          "'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, dp, st = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+    ctxp = ctypes.c_void_p
+    sig = {
+        "gpm_create": ([ctypes.POINTER(gpm_grid), ctypes.c_int, vp, ctypes.POINTER(ctxp)], st),
+        "gpm_set_scheme": ([ctxp, ctypes.POINTER(gpm_scheme)], st),
+        "gpm_workspace_size": ([ctxp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)], st),
+        "gpm_bind": ([ctxp, vp, vp], st),
+        "gpm_state_ptr": ([ctxp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int)], st),
+        "gpm_init_state": ([ctxp, dp], st),
+        "gpm_get_state": ([ctxp, dp], st),
+        "gpm_compute_dt": ([ctxp, ctypes.c_double, dp], st),
+        "gpm_set_dt": ([ctxp, ctypes.c_double], st),
+        "gpm_stage_dev": ([ctxp, ctypes.c_int, vp, vp, vp], st),
+        "gpm_step": ([ctxp, ctypes.c_double, ctypes.c_int], st),
+        "gpm_troubled_counts": ([ctxp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_int)], st),
+        "gpm_get_order_mask": ([ctxp, ctypes.POINTER(ctypes.c_ubyte)], st),
+        "gpm_totals": ([ctxp, dp], st),
+        "gpm_totals_dev": ([ctxp, vp, dp], st),
+        "gpm_set_tuning": ([ctxp, ctypes.c_int, ctypes.c_int], st),
+        "gpm_strerror": ([st], ctypes.c_char_p),
+        "gpm_last_error": ([ctxp], ctypes.c_char_p),
+        "gpm_destroy": ([ctxp], None),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class GPMood:
+    """One 2D problem on the GPU: owns torch device buffers and a library context.
+
+    nx, ny, lo, hi, bc=(bcx, bcy) with 0 periodic / 1 outflow, prec 'f32' | 'f64',
+    cascade = GP radii ending in 0, ell = physical length scale (None: 12 min(dx, dy)).
+    """
+
+    def __init__(self, nx, ny, lo=(0.0, 0.0), hi=(1.0, 1.0), bc=(0, 0), prec="f64",
+                 cascade=(3, 2, 1, 0), ell=None, gamma=1.4, sigma_v=5.0, sigma_p=5.0,
+                 flags=GPM_FLAGS_ALL, stream=None, device=None):
+        import torch
+        L = lib()
+        self.torch = torch
+        self.device = torch.device(device if device is not None else "cuda")
+        self.nx, self.ny = int(nx), int(ny)
+        self.prec = prec
+        self.dtype = torch.float64 if prec == "f64" else torch.float32
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        g = gpm_grid()
+        g.dim = 2
+        g.n[0], g.n[1], g.n[2] = self.nx, self.ny, 1
+        g.lo[0], g.lo[1] = lo
+        g.hi[0], g.hi[1] = hi
+        g.bc[0], g.bc[1] = bc
+        g.gamma = gamma
+        ctx = ctypes.c_void_p()
+        self._check(L.gpm_create(ctypes.byref(g), GPM_F64 if prec == "f64" else GPM_F32,
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)), None)
+        self.ctx = ctx
+        s = gpm_scheme()
+        s.nlev = len(cascade)
+        for k, r in enumerate(cascade):
+            s.radius[k] = r
+        s.ell = 0.0 if ell is None else float(ell)
+        s.sigma_v, s.sigma_p, s.flags = sigma_v, sigma_p, flags
+        self._check(L.gpm_set_scheme(self.ctx, ctypes.byref(s)))
+        sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(L.gpm_workspace_size(self.ctx, ctypes.byref(sb), ctypes.byref(wb)))
+        self.state_buf = torch.empty(sb.value, dtype=torch.uint8, device=self.device)
+        self.work_buf = torch.empty(wb.value, dtype=torch.uint8, device=self.device)
+        self._check(L.gpm_bind(self.ctx, ctypes.c_void_p(self.state_buf.data_ptr()),
+                               ctypes.c_void_p(self.work_buf.data_ptr())))
+        self.slot_elems = sb.value // 3 // (8 if prec == "f64" else 4)
+
+    # -- plumbing
+    def _check(self, st, ctx=0):
+        if st != GPM_OK:
+            L = lib()
+            msg = L.gpm_strerror(st).decode()
+            c = self.ctx if ctx == 0 else ctx
+            if c is not None:
+                msg += ": " + (L.gpm_last_error(c) or b"").decode()
+            raise GpmError(f"status {st}: {msg}")
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            lib().gpm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def slot(self, k):
+        """Torch view (4, ny, nx) of state slot k."""
+        n = 4 * self.nx * self.ny
+        esz = 8 if self.prec == "f64" else 4
+        base = self.state_buf[k * self.slot_elems * esz:(k * self.slot_elems + n) * esz]
+        return base.view(self.dtype).view(4, self.ny, self.nx)
+
+    def current_slot(self):
+        p, cur = ctypes.c_void_p(), ctypes.c_int()
+        self._check(lib().gpm_state_ptr(self.ctx, 0, ctypes.byref(p), ctypes.byref(cur)))
+        return cur.value
+
+    # -- ABI calls
+    def gpm_init_state(self, U):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        assert U.shape == (4, self.ny, self.nx)
+        self._check(lib().gpm_init_state(self.ctx, _dp(U)))
+
+    def gpm_get_state(self):
+        U = np.empty((4, self.ny, self.nx))
+        self._check(lib().gpm_get_state(self.ctx, _dp(U)))
+        return U
+
+    def gpm_compute_dt(self, cfl, sync=True):
+        if sync:
+            dt = ctypes.c_double()
+            self._check(lib().gpm_compute_dt(self.ctx, float(cfl), ctypes.byref(dt)))
+            return dt.value
+        self._check(lib().gpm_compute_dt(self.ctx, float(cfl), None))
+        return None
+
+    def gpm_set_dt(self, dt):
+        self._check(lib().gpm_set_dt(self.ctx, float(dt)))
+
+    def gpm_stage_dev(self, s, Un, Us, Uout):
+        """Un, Us, Uout: torch tensors (4, ny, nx) of the context dtype on the device."""
+        for t in (Un, Us, Uout):
+            assert t.dtype == self.dtype and t.is_contiguous() and t.numel() == 4 * self.nx * self.ny
+        self._check(lib().gpm_stage_dev(self.ctx, int(s), ctypes.c_void_p(Un.data_ptr()),
+                                        ctypes.c_void_p(Us.data_ptr()), ctypes.c_void_p(Uout.data_ptr())))
+
+    def gpm_step(self, cfl=0.8, nsteps=1):
+        self._check(lib().gpm_step(self.ctx, float(cfl), int(nsteps)))
+
+    def gpm_troubled_counts(self):
+        c = (ctypes.c_longlong * 4)()
+        it = ctypes.c_int()
+        self._check(lib().gpm_troubled_counts(self.ctx, c, ctypes.byref(it)))
+        return np.array(list(c), dtype=np.int64), it.value
+
+    def gpm_get_order_mask(self):
+        m = np.empty((self.ny, self.nx), dtype=np.uint8)
+        self._check(lib().gpm_get_order_mask(self.ctx, m.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))))
+        return m
+
+    def gpm_totals(self):
+        t = np.zeros(4)
+        self._check(lib().gpm_totals(self.ctx, _dp(t)))
+        return t
+
+    def gpm_totals_dev(self, U):
+        t = np.zeros(4)
+        self._check(lib().gpm_totals_dev(self.ctx, ctypes.c_void_p(U.data_ptr()), _dp(t)))
+        return t
+
+    def gpm_set_tuning(self, passes_per_check=4, rows_per_wave=16):
+        self._check(lib().gpm_set_tuning(self.ctx, int(passes_per_check), int(rows_per_wave)))

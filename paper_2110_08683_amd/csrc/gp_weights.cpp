@@ -1,0 +1,210 @@
+// GP prediction vectors in quadruple precision (host, once per scheme).
+//
+// Bourgeois & Lee, "GP-MOOD":
+//   eq. (SE-pred)  t*_m = prod_d sqrt(pi/2) a_d [erf((s_d+1/2)/(sqrt2 a_d)) - erf((s_d-1/2)/(sqrt2 a_d))]
+//   eq. (SE-cov)   C_mn = prod_d sqrt(pi) a_d^2 { phi(u+) + phi(u-) - 2 phi(u0) },
+//                  phi(u) = u erf(u) + exp(-u^2)/sqrt(pi), u = (D +- 1, D)/(sqrt2 a_d)
+//   eq. (gp_reconstructor)  z = C^{-1} t*, by Cholesky of the SPD matrix C
+//   eq. (normalized_z)      z <- z / (z^T 1)   (signed sum: the stated purpose is z^T 1 = 1)
+//   App. B          second derivative of the t* factor along d at the cell centre
+// with a_d = ell / Delta_d and all separations in cell units (eq. (delta_mnd)).
+// Sec. "Singularity of the covariance kernel matrix": C is badly conditioned
+// (about 4e15 for R = 3 at ell = 12 dx), so everything runs in __float128 and is
+// rounded to double / float at the end, as the paper does.
+#include "gp_weights.h"
+#include "gpmood_tables.h"
+
+#include <quadmath.h>
+
+#include <cstring>
+#include <vector>
+
+namespace gpm {
+namespace {
+
+typedef __float128 qf;
+
+const qf QPI = acosq((qf)-1);
+
+qf t_factor(qf s, qf a)
+{
+    qf r2a = sqrtq((qf)2) * a;
+    return sqrtq(QPI / 2) * a * (erfq((s + (qf)0.5) / r2a) - erfq((s - (qf)0.5) / r2a));
+}
+
+qf phi(qf u) { return u * erfq(u) + expq(-u * u) / sqrtq(QPI); }
+
+qf c_factor(qf D, qf a)
+{
+    qf r2a = sqrtq((qf)2) * a;
+    return sqrtq(QPI) * a * a * (phi((D + 1) / r2a) + phi((D - 1) / r2a) - 2 * phi(D / r2a));
+}
+
+qf d2_t_factor(qf s, qf a, qf ell)
+{
+    qf h = (qf)0.5;
+    qf em = expq(-(s - h) * (s - h) / (2 * a * a));
+    qf ep = expq(-(s + h) * (s + h) / (2 * a * a));
+    return ((s - h) * em - (s + h) * ep) / (ell * ell);
+}
+
+struct Cell { int di, dj; };
+
+std::vector<Cell> diamond(int R)
+{
+    std::vector<Cell> st;
+    for (int dj = -R; dj <= R; ++dj)
+        for (int di = -R; di <= R; ++di)
+            if ((di < 0 ? -di : di) + (dj < 0 ? -dj : dj) <= R) st.push_back({di, dj});
+    return st;
+}
+
+// Cholesky factor L (lower) of the n x n SPD matrix A, row-major; false if not SPD.
+bool cholesky(std::vector<qf> &A, int n)
+{
+    for (int j = 0; j < n; ++j) {
+        qf d = A[j * n + j];
+        for (int k = 0; k < j; ++k) d -= A[j * n + k] * A[j * n + k];
+        if (!(d > 0)) return false;
+        qf l = sqrtq(d);
+        A[j * n + j] = l;
+        for (int i = j + 1; i < n; ++i) {
+            qf s = A[i * n + j];
+            for (int k = 0; k < j; ++k) s -= A[i * n + k] * A[j * n + k];
+            A[i * n + j] = s / l;
+        }
+    }
+    return true;
+}
+
+void chol_solve(const std::vector<qf> &L, int n, std::vector<qf> &b)
+{
+    for (int i = 0; i < n; ++i) {
+        qf s = b[i];
+        for (int k = 0; k < i; ++k) s -= L[i * n + k] * b[k];
+        b[i] = s / L[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        qf s = b[i];
+        for (int k = i + 1; k < n; ++k) s -= L[k * n + i] * b[k];
+        b[i] = s / L[i * n + i];
+    }
+}
+
+// Gauss nodes (non-negative members of the rule in Table tab:QR-pt-weight) and weights.
+void gauss_slots(int R, qf g[2], qf w[2])
+{
+    if (R == 1) {
+        g[0] = 1 / (2 * sqrtq((qf)3));
+        w[0] = (qf)0.5;
+    } else if (R == 2) {
+        g[0] = sqrtq((qf)3 / 5) / 2;
+        w[0] = (qf)5 / 18;
+        g[1] = 0;
+        w[1] = (qf)8 / 18;
+    } else {
+        qf s = sqrtq((qf)6 / 5);
+        g[0] = sqrtq((qf)3 / 7 + 2 * s / 7) / 2;
+        g[1] = sqrtq((qf)3 / 7 - 2 * s / 7) / 2;
+        w[0] = (18 - sqrtq((qf)30)) / 72;
+        w[1] = (18 + sqrtq((qf)30)) / 72;
+    }
+}
+
+int index_of(const std::vector<Cell> &st, int di, int dj)
+{
+    for (size_t m = 0; m < st.size(); ++m)
+        if (st[m].di == di && st[m].dj == dj) return (int)m;
+    return -1;
+}
+
+}  // namespace
+
+int gpw_level(int R, double ax_d, double ay_d, GpwLevel *out)
+{
+    std::memset(out, 0, sizeof(*out));
+    out->R = R;
+    if (R <= 0) return 0;
+    const qf ax = ax_d, ay = ay_d;
+    std::vector<Cell> st = diamond(R);
+    const int n = (int)st.size();
+    std::vector<qf> L(n * n);
+    for (int m = 0; m < n; ++m)
+        for (int k = 0; k < n; ++k)
+            L[m * n + k] = c_factor((qf)(st[k].di - st[m].di), ax) * c_factor((qf)(st[k].dj - st[m].dj), ay);
+    if (!cholesky(L, n)) return -1;
+    qf g[2], w[2];
+    gauss_slots(R, g, w);
+    for (int k = 0; k < slots_of(R); ++k) {
+        out->qw64[k] = (double)w[k];
+        out->qw32[k] = (float)w[k];
+    }
+    for (int dir = 0; dir < 2; ++dir)
+        for (int k = 0; k < slots_of(R); ++k) {
+            // x faces: x* = (+1/2, g); y faces: x* = (g, +1/2)
+            qf xs = dir == 0 ? (qf)0.5 : g[k];
+            qf ys = dir == 0 ? g[k] : (qf)0.5;
+            std::vector<qf> z(n);
+            for (int m = 0; m < n; ++m) z[m] = t_factor(xs - st[m].di, ax) * t_factor(ys - st[m].dj, ay);
+            chol_solve(L, n, z);
+            qf sum = 0;
+            for (int m = 0; m < n; ++m) sum += z[m];
+            for (int m = 0; m < n; ++m) z[m] /= sum;
+            auto Z = [&](int di, int dj) { return z[index_of(st, di, dj)]; };
+            for (int e = 0; e < kNQ[R]; ++e) {
+                const int a = kQ[e].a, b = kQ[e].b, c = kQ[e].comp;
+                qf W;
+                if (a == 0 && b == 0) {
+                    W = Z(0, 0);
+                } else if (b == 0) {
+                    W = c == C_EE ? (Z(a, 0) + Z(-a, 0)) / 2 : (Z(a, 0) - Z(-a, 0)) / 2;
+                } else if (a == 0) {
+                    W = c == C_EE ? (Z(0, b) + Z(0, -b)) / 2 : (Z(0, b) - Z(0, -b)) / 2;
+                } else {
+                    qf pp = Z(a, b), mp = Z(-a, b), pm = Z(a, -b), mm = Z(-a, -b);
+                    if (c == C_EE) W = (pp + mp + pm + mm) / 4;
+                    else if (c == C_OE) W = (pp - mp + pm - mm) / 4;
+                    else if (c == C_EO) W = (pp + mp - pm - mm) / 4;
+                    else W = (pp - mp - pm + mm) / 4;
+                }
+                out->w64[dir][k][e] = (double)W;
+                out->w32[dir][k][e] = (float)W;
+            }
+        }
+    return 0;
+}
+
+int gpw_curvature(double ax_d, double ay_d, double ell_d, GpwCurv *out)
+{
+    std::memset(out, 0, sizeof(*out));
+    const qf ax = ax_d, ay = ay_d, ell = ell_d;
+    std::vector<Cell> st = diamond(1);
+    const int n = (int)st.size();
+    std::vector<qf> L(n * n);
+    for (int m = 0; m < n; ++m)
+        for (int k = 0; k < n; ++k)
+            L[m * n + k] = c_factor((qf)(st[k].di - st[m].di), ax) * c_factor((qf)(st[k].dj - st[m].dj), ay);
+    if (!cholesky(L, n)) return -1;
+    for (int d = 0; d < 2; ++d) {
+        std::vector<qf> w(n);
+        for (int m = 0; m < n; ++m) {
+            qf sx = -(qf)st[m].di, sy = -(qf)st[m].dj;  // x* = cell centre
+            w[m] = d == 0 ? d2_t_factor(sx, ax, ell) * t_factor(sy, ay)
+                          : t_factor(sx, ax) * d2_t_factor(sy, ay, ell);
+        }
+        chol_solve(L, n, w);
+        qf c0 = w[index_of(st, 0, 0)];
+        qf along = d == 0 ? (w[index_of(st, 1, 0)] + w[index_of(st, -1, 0)]) / 2
+                          : (w[index_of(st, 0, 1)] + w[index_of(st, 0, -1)]) / 2;
+        qf across = d == 0 ? (w[index_of(st, 0, 1)] + w[index_of(st, 0, -1)]) / 2
+                           : (w[index_of(st, 1, 0)] + w[index_of(st, -1, 0)]) / 2;
+        qf v[3] = {c0, along, across};
+        for (int k = 0; k < 3; ++k) {
+            out->w64[d][k] = (double)v[k];
+            out->w32[d][k] = (float)v[k];
+        }
+    }
+    return 0;
+}
+
+}  // namespace gpm

@@ -1,0 +1,34 @@
+// Host-side GP weight generation (quadruple precision), internal to the library.
+#ifndef GPMOOD_GP_WEIGHTS_H
+#define GPMOOD_GP_WEIGHTS_H
+
+namespace gpm {
+
+// Quarter-basis weights of one radius for both directions:
+// w[dir][slot][k], dir 0 = x faces (face x+, nodes +g), dir 1 = y faces (face y+,
+// nodes +g), k over the first kNQ[R] entries of kQ.  Values rounded from quad
+// precision to double (w64) and, separately, to float (w32).
+struct GpwLevel {
+    int R;
+    double w64[2][2][25];
+    float w32[2][2][25];
+    double qw64[2];  // Gauss weights of the stored slots (pair member / centre node)
+    float qw32[2];
+};
+
+// u2 curvature weights (App. B, GP-R1 stencil, at the cell centre, unnormalised),
+// per direction d: [0] centre cell, [1] the two neighbours along d, [2] the two
+// neighbours across d.
+struct GpwCurv {
+    double w64[2][3];
+    float w32[2][3];
+};
+
+// ax = ell/dx, ay = ell/dy.  Returns 0, or -1 if the covariance matrix is not
+// numerically positive definite in quad precision.
+int gpw_level(int R, double ax, double ay, GpwLevel *out);
+int gpw_curvature(double ax, double ay, double ell, GpwCurv *out);
+
+}  // namespace gpm
+
+#endif

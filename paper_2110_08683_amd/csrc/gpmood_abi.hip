@@ -1,0 +1,492 @@
+// C ABI of the GP-MOOD stage engine: context, scheme setup, binding of caller
+// memory, and the host control of the MOOD loop (see include/gpmood.h).
+#include "gpmood.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gp_weights.h"
+#include "gpmood_device.h"
+#include "gpmood_launch.h"
+
+using namespace gpm;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kTotBlocks = 1024;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+}  // namespace
+
+struct gpm_ctx {
+    gpm_grid grid;
+    int prec;
+    hipStream_t stream;
+    int nx, ny;
+    size_t ncell;
+    double dx, dy;
+    bool have_scheme = false;
+    gpm_scheme scheme;
+    Weights<double> w64;
+    Weights<float> w32;
+    int top = 0;
+    int next[4] = {0, 0, 0, 0};
+    int levidx[4] = {0, 0, 0, 0};
+    // bound memory
+    char *state = nullptr;
+    char *work = nullptr;
+    int cur = 0;
+    uint8_t *order = nullptr;
+    unsigned *stamp = nullptr;
+    int *lists[2] = {nullptr, nullptr};
+    int *aff = nullptr;
+    Ctl *ctl = nullptr;
+    double *partial = nullptr;
+    unsigned pass = 0;
+    int passes_per_check = 4;
+    int rows = 16;
+    int last_npass = 0;
+    int *pinned = nullptr;
+    std::string err;
+};
+
+static gpm_status fail(gpm_ctx *c, gpm_status st, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return st;
+}
+
+#define HIPCHK(c, expr)                                                                      \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((c), GPM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+static size_t state_slot_bytes(const gpm_ctx *c)
+{
+    return align_up(4 * c->ncell * (c->prec == GPM_F64 ? 8 : 4));
+}
+
+static size_t work_layout(const gpm_ctx *c, size_t off[6])
+{
+    size_t o = 0;
+    off[0] = o; o = align_up(o + c->ncell);                      // order
+    off[1] = o; o = align_up(o + 4 * c->ncell);                  // stamp
+    off[2] = o; o = align_up(o + 4 * c->ncell);                  // list 0
+    off[3] = o; o = align_up(o + 4 * c->ncell);                  // list 1
+    off[4] = o; o = align_up(o + 4 * c->ncell);                  // affected
+    off[5] = o; o = align_up(o + sizeof(Ctl));                   // control block
+    o = align_up(o + (size_t)kTotBlocks * 4 * 2 * sizeof(double));  // totals partials
+    return o;
+}
+
+extern "C" {
+
+const char *gpm_strerror(gpm_status st)
+{
+    switch (st) {
+    case GPM_OK: return "ok";
+    case GPM_EINVAL: return "invalid argument";
+    case GPM_ENOMEM: return "out of host memory";
+    case GPM_EHIP: return "HIP runtime error";
+    case GPM_ESTATE: return "call out of order (scheme or buffers missing)";
+    case GPM_ENOTCONV: return "MOOD loop exceeded its pass limit";
+    case GPM_EUNSUPPORTED: return "unsupported configuration";
+    }
+    return "unknown status";
+}
+
+const char *gpm_last_error(const gpm_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+gpm_status gpm_create(const gpm_grid *grid, int prec, void *hip_stream, gpm_ctx **out)
+{
+    if (!grid || !out) return GPM_EINVAL;
+    *out = nullptr;
+    if (grid->dim != 2) return GPM_EUNSUPPORTED;
+    if (prec != GPM_F32 && prec != GPM_F64) return GPM_EINVAL;
+    for (int d = 0; d < 2; ++d) {
+        if (grid->n[d] < 1 || grid->n[d] > 32768) return GPM_EINVAL;
+        if (!(grid->hi[d] > grid->lo[d])) return GPM_EINVAL;
+        if (grid->bc[d] != GPM_BC_PERIODIC && grid->bc[d] != GPM_BC_OUTFLOW) return GPM_EINVAL;
+    }
+    if (!(grid->gamma > 1.0)) return GPM_EINVAL;
+    gpm_ctx *c = new (std::nothrow) gpm_ctx;
+    if (!c) return GPM_ENOMEM;
+    c->grid = *grid;
+    c->prec = prec;
+    c->stream = (hipStream_t)hip_stream;
+    c->nx = grid->n[0];
+    c->ny = grid->n[1];
+    c->ncell = (size_t)c->nx * c->ny;
+    c->dx = (grid->hi[0] - grid->lo[0]) / c->nx;
+    c->dy = (grid->hi[1] - grid->lo[1]) / c->ny;
+    if (hipHostMalloc((void **)&c->pinned, 64, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return GPM_EHIP;
+    }
+    *out = c;
+    return GPM_OK;
+}
+
+void gpm_destroy(gpm_ctx *c)
+{
+    if (!c) return;
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    delete c;
+}
+
+gpm_status gpm_set_scheme(gpm_ctx *c, const gpm_scheme *s)
+{
+    if (!c || !s) return GPM_EINVAL;
+    if (s->nlev < 1 || s->nlev > 4) return fail(c, GPM_EINVAL, "nlev must be 1..4");
+    for (int l = 0; l < s->nlev; ++l) {
+        if (s->radius[l] < 0 || s->radius[l] > 3) return fail(c, GPM_EINVAL, "radius must be 0..3");
+        if (l > 0 && !(s->radius[l] < s->radius[l - 1])) return fail(c, GPM_EINVAL, "cascade must strictly decrease");
+    }
+    if (s->radius[s->nlev - 1] != 0) return fail(c, GPM_EINVAL, "cascade must end at radius 0 (FOG)");
+    if (s->radius[0] == 0) return fail(c, GPM_EINVAL, "top scheme must have radius >= 1");
+    if (!(s->ell >= 0.0)) return fail(c, GPM_EINVAL, "ell must be >= 0");
+    const double ell = s->ell > 0.0 ? s->ell : 12.0 * (c->dx < c->dy ? c->dx : c->dy);
+    const double ax = ell / c->dx, ay = ell / c->dy;
+    std::memset(&c->w64, 0, sizeof(c->w64));
+    std::memset(&c->w32, 0, sizeof(c->w32));
+    for (int R = 1; R <= 3; ++R) {
+        bool used = false;
+        for (int l = 0; l < s->nlev; ++l) used = used || s->radius[l] == R;
+        if (!used) continue;
+        GpwLevel L;
+        if (gpw_level(R, ax, ay, &L) != 0) return fail(c, GPM_EINVAL, "GP covariance matrix not positive definite");
+        for (int d = 0; d < 2; ++d)
+            for (int p = 0; p < slots_of(R); ++p)
+                for (int e = 0; e < kNQ[R]; ++e) {
+                    if (R == 3) { c->w64.w3[d][p][e] = L.w64[d][p][e]; c->w32.w3[d][p][e] = L.w32[d][p][e]; }
+                    if (R == 2) { c->w64.w2[d][p][e] = L.w64[d][p][e]; c->w32.w2[d][p][e] = L.w32[d][p][e]; }
+                    if (R == 1) { c->w64.w1[d][0][e] = L.w64[d][0][e]; c->w32.w1[d][0][e] = L.w32[d][0][e]; }
+                }
+        for (int p = 0; p < slots_of(R); ++p) {
+            if (R == 3) { c->w64.qw3[p] = L.qw64[p]; c->w32.qw3[p] = L.qw32[p]; }
+            if (R == 2) { c->w64.qw2[p] = L.qw64[p]; c->w32.qw2[p] = L.qw32[p]; }
+            if (R == 1) { c->w64.qw1 = L.qw64[0]; c->w32.qw1 = L.qw32[0]; }
+        }
+    }
+    GpwCurv K;
+    if (gpw_curvature(ax, ay, ell, &K) != 0) return fail(c, GPM_EINVAL, "GP-R1 covariance matrix not positive definite");
+    for (int d = 0; d < 2; ++d)
+        for (int k = 0; k < 3; ++k) {
+            c->w64.curv[d][k] = K.w64[d][k];
+            c->w32.curv[d][k] = K.w32[d][k];
+        }
+    c->scheme = *s;
+    c->scheme.ell = ell;
+    c->top = s->radius[0];
+    for (int r = 0; r < 4; ++r) { c->next[r] = 0; c->levidx[r] = 0; }
+    for (int l = 0; l < s->nlev; ++l) {
+        c->levidx[s->radius[l]] = l;
+        c->next[s->radius[l]] = l + 1 < s->nlev ? s->radius[l + 1] : 0;
+    }
+    c->have_scheme = true;
+    return GPM_OK;
+}
+
+gpm_status gpm_workspace_size(const gpm_ctx *c, size_t *state_bytes, size_t *work_bytes)
+{
+    if (!c) return GPM_EINVAL;
+    size_t off[6];
+    if (state_bytes) *state_bytes = 3 * state_slot_bytes(c);
+    if (work_bytes) *work_bytes = work_layout(c, off);
+    return GPM_OK;
+}
+
+gpm_status gpm_bind(gpm_ctx *c, void *state, void *work)
+{
+    if (!c || !state || !work) return GPM_EINVAL;
+    if (((uintptr_t)state % kAlign) || ((uintptr_t)work % kAlign)) return fail(c, GPM_EINVAL, "buffers must be 256-byte aligned");
+    size_t off[6];
+    const size_t wbytes = work_layout(c, off);
+    c->state = (char *)state;
+    c->work = (char *)work;
+    c->order = (uint8_t *)(c->work + off[0]);
+    c->stamp = (unsigned *)(c->work + off[1]);
+    c->lists[0] = (int *)(c->work + off[2]);
+    c->lists[1] = (int *)(c->work + off[3]);
+    c->aff = (int *)(c->work + off[4]);
+    c->ctl = (Ctl *)(c->work + off[5]);
+    c->partial = (double *)(c->work + align_up(off[5] + sizeof(Ctl)));
+    c->cur = 0;
+    c->pass = 0;
+    HIPCHK(c, hipMemsetAsync(c->work, 0, wbytes, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return GPM_OK;
+}
+
+gpm_status gpm_state_ptr(const gpm_ctx *c, int slot, void **ptr, int *current_slot)
+{
+    if (!c || slot < 0 || slot > 2) return GPM_EINVAL;
+    if (!c->state) return GPM_ESTATE;
+    if (ptr) *ptr = c->state + slot * state_slot_bytes(c);
+    if (current_slot) *current_slot = c->cur;
+    return GPM_OK;
+}
+
+static void *slot_ptr(gpm_ctx *c, int slot) { return c->state + slot * state_slot_bytes(c); }
+
+gpm_status gpm_init_state(gpm_ctx *c, const double *U)
+{
+    if (!c || !U) return GPM_EINVAL;
+    if (!c->state) return fail(c, GPM_ESTATE, "not bound");
+    const size_t n = 4 * c->ncell;
+    if (c->prec == GPM_F64) {
+        HIPCHK(c, hipMemcpyAsync(slot_ptr(c, c->cur), U, n * 8, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        std::vector<float> tmp(n);
+        for (size_t k = 0; k < n; ++k) tmp[k] = (float)U[k];
+        HIPCHK(c, hipMemcpyAsync(slot_ptr(c, c->cur), tmp.data(), n * 4, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return GPM_OK;
+}
+
+gpm_status gpm_get_state(gpm_ctx *c, double *U)
+{
+    if (!c || !U) return GPM_EINVAL;
+    if (!c->state) return fail(c, GPM_ESTATE, "not bound");
+    const size_t n = 4 * c->ncell;
+    if (c->prec == GPM_F64) {
+        HIPCHK(c, hipMemcpyAsync(U, slot_ptr(c, c->cur), n * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        std::vector<float> tmp(n);
+        HIPCHK(c, hipMemcpyAsync(tmp.data(), slot_ptr(c, c->cur), n * 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (size_t k = 0; k < n; ++k) U[k] = tmp[k];
+    }
+    return GPM_OK;
+}
+
+static gpm_status compute_dt_from(gpm_ctx *c, const void *U, double cfl)
+{
+    hipError_t e = c->prec == GPM_F64
+                       ? launch_dt<double>((const double *)U, c->ncell, c->grid.gamma, c->dx, c->dy, cfl, c->ctl, c->stream)
+                       : launch_dt<float>((const float *)U, c->ncell, c->grid.gamma, c->dx, c->dy, cfl, c->ctl, c->stream);
+    if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("dt kernels: ") + hipGetErrorString(e));
+    return GPM_OK;
+}
+
+gpm_status gpm_compute_dt(gpm_ctx *c, double cfl, double *dt_host)
+{
+    if (!c) return GPM_EINVAL;
+    if (!c->state) return fail(c, GPM_ESTATE, "not bound");
+    if (!(cfl > 0.0)) return fail(c, GPM_EINVAL, "cfl must be > 0");
+    gpm_status st = compute_dt_from(c, slot_ptr(c, c->cur), cfl);
+    if (st != GPM_OK) return st;
+    if (dt_host) {
+        HIPCHK(c, hipMemcpyAsync(dt_host, &c->ctl->dt, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return GPM_OK;
+}
+
+gpm_status gpm_set_dt(gpm_ctx *c, double dt)
+{
+    if (!c) return GPM_EINVAL;
+    if (!c->state) return fail(c, GPM_ESTATE, "not bound");
+    hipError_t e = launch_set_dt(c->ctl, dt, c->stream);
+    if (e != hipSuccess) return fail(c, GPM_EHIP, hipGetErrorString(e));
+    return GPM_OK;
+}
+
+gpm_status gpm_set_tuning(gpm_ctx *c, int passes_per_check, int rows_per_wave)
+{
+    if (!c || passes_per_check < 1 || passes_per_check > 64 || rows_per_wave < 4 || rows_per_wave > 256)
+        return GPM_EINVAL;
+    c->passes_per_check = passes_per_check;
+    c->rows = rows_per_wave;
+    return GPM_OK;
+}
+
+}  // extern "C"
+
+template <typename real>
+static void fill_args(const gpm_ctx *c, const Weights<real> &W, StageArgs<real> &A)
+{
+    A.nx = c->nx;
+    A.ny = c->ny;
+    A.bcx = c->grid.bc[0];
+    A.bcy = c->grid.bc[1];
+    A.rows = c->rows;
+    A.top = c->top;
+    A.flags = c->scheme.flags;
+    A.dx = (real)c->dx;
+    A.dy = (real)c->dy;
+    A.gamma = (real)c->grid.gamma;
+    A.sigma_v = (real)c->scheme.sigma_v;
+    A.sigma_p = (real)c->scheme.sigma_p;
+    const double d3 = c->dx * c->dx * c->dx < c->dy * c->dy * c->dy ? c->dx * c->dx * c->dx : c->dy * c->dy * c->dy;
+    A.plat_thr = (real)d3;
+    A.delta = (real)(c->dx < c->dy ? c->dx : c->dy);
+    A.W = W;
+    A.dt = &c->ctl->dt;
+    A.order = c->order;
+}
+
+template <typename real>
+static gpm_status run_stage(gpm_ctx *c, const Weights<real> &W, int s, const void *Un, const void *Us, void *Uout)
+{
+    StageArgs<real> A;
+    fill_args(c, W, A);
+    A.s = s;
+    A.Un = (const real *)Un;
+    A.Us = (const real *)Us;
+    A.Uout = (real *)Uout;
+    hipError_t e = launch_reset(c->ctl, c->levidx[c->top], (unsigned long long)c->ncell, c->stream);
+    if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("reset: ") + hipGetErrorString(e));
+    A.list_out = c->lists[0];
+    A.count_out = &c->ctl->nlist[0];
+    e = launch_first_pass<real>(A, c->stream);
+    if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("first pass: ") + hipGetErrorString(e));
+
+    // cascade passes, queued in batches and gated on the device counts
+    int nb_rec = (int)((c->ncell + 63) / 64);
+    if (nb_rec > 2048) nb_rec = 2048;
+    int nb_low = (int)((c->ncell + 255) / 256);
+    if (nb_low > 512) nb_low = 512;
+    LowerArgsHost L;
+    L.order = c->order;
+    L.stamp = c->stamp;
+    L.levcnt = c->ctl->levcnt;
+    L.aff = c->aff;
+    L.nx = c->nx;
+    L.ny = c->ny;
+    L.bcx = c->grid.bc[0];
+    L.bcy = c->grid.bc[1];
+    for (int r = 0; r < 4; ++r) { L.next[r] = c->next[r]; L.levidx[r] = c->levidx[r]; }
+    L.nblocks = nb_low;
+    int k = 0;
+    for (;;) {
+        HIPCHK(c, hipMemcpyAsync(c->pinned, &c->ctl->nlist[k], sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (*c->pinned == 0) break;
+        if (k + c->passes_per_check > kMaxPasses) {
+            c->last_npass = k;
+            return fail(c, GPM_ENOTCONV, "MOOD loop exceeded the pass limit");
+        }
+        for (int b = 0; b < c->passes_per_check; ++b, ++k) {
+            if (c->pass == 0xffffffffu) {
+                HIPCHK(c, hipMemsetAsync(c->stamp, 0, 4 * c->ncell, c->stream));
+                c->pass = 0;
+            }
+            L.pass = ++c->pass;
+            L.list_in = c->lists[k & 1];
+            L.count_in = &c->ctl->nlist[k];
+            L.count_aff = &c->ctl->naff[k];
+            e = launch_cascade_lower(L, c->stream);
+            if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("cascade lower: ") + hipGetErrorString(e));
+            A.list_out = c->lists[(k + 1) & 1];
+            A.count_out = &c->ctl->nlist[k + 1];
+            e = launch_cascade_recompute<real>(A, c->aff, &c->ctl->naff[k], nb_rec, c->stream);
+            if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("cascade recompute: ") + hipGetErrorString(e));
+        }
+    }
+    c->last_npass = k;
+    return GPM_OK;
+}
+
+extern "C" {
+
+gpm_status gpm_stage_dev(gpm_ctx *c, int s, const void *Un, const void *Us, void *Uout)
+{
+    if (!c) return GPM_EINVAL;
+    if (!c->have_scheme) return fail(c, GPM_ESTATE, "no scheme set");
+    if (!c->state) return fail(c, GPM_ESTATE, "not bound");
+    if (s < 0 || s > 2 || !Us || !Uout || (s > 0 && !Un)) return fail(c, GPM_EINVAL, "bad stage arguments");
+    if (Uout == Us) return fail(c, GPM_EINVAL, "U_out must not alias U_s");
+    return c->prec == GPM_F64 ? run_stage<double>(c, c->w64, s, Un, Us, Uout)
+                              : run_stage<float>(c, c->w32, s, Un, Us, Uout);
+}
+
+gpm_status gpm_step(gpm_ctx *c, double cfl, int nsteps)
+{
+    if (!c || nsteps < 0) return GPM_EINVAL;
+    if (!c->have_scheme) return fail(c, GPM_ESTATE, "no scheme set");
+    if (!c->state) return fail(c, GPM_ESTATE, "not bound");
+    for (int n = 0; n < nsteps; ++n) {
+        const int u0 = c->cur, a = (c->cur + 1) % 3, b = (c->cur + 2) % 3;
+        if (cfl > 0.0) {
+            gpm_status st = compute_dt_from(c, slot_ptr(c, u0), cfl);
+            if (st != GPM_OK) return st;
+        }
+        gpm_status st = gpm_stage_dev(c, 0, slot_ptr(c, u0), slot_ptr(c, u0), slot_ptr(c, a));
+        if (st != GPM_OK) return st;
+        st = gpm_stage_dev(c, 1, slot_ptr(c, u0), slot_ptr(c, a), slot_ptr(c, b));
+        if (st != GPM_OK) return st;
+        st = gpm_stage_dev(c, 2, slot_ptr(c, u0), slot_ptr(c, b), slot_ptr(c, a));
+        if (st != GPM_OK) return st;
+        c->cur = a;
+    }
+    return GPM_OK;
+}
+
+gpm_status gpm_troubled_counts(gpm_ctx *c, long long counts[4], int *mood_iters)
+{
+    if (!c) return GPM_EINVAL;
+    if (!c->state) return fail(c, GPM_ESTATE, "not bound");
+    unsigned long long lc[4];
+    HIPCHK(c, hipMemcpyAsync(lc, c->ctl->levcnt, sizeof(lc), hipMemcpyDeviceToHost, c->stream));
+    std::vector<int> nl(c->last_npass + 1);
+    HIPCHK(c, hipMemcpyAsync(nl.data(), c->ctl->nlist, sizeof(int) * nl.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (counts)
+        for (int l = 0; l < 4; ++l) counts[l] = (long long)lc[l];
+    if (mood_iters) {
+        int it = 1;
+        for (size_t k = 0; k < nl.size(); ++k)
+            if (nl[k] > 0) ++it;
+        *mood_iters = it;
+    }
+    return GPM_OK;
+}
+
+gpm_status gpm_get_order_mask(gpm_ctx *c, unsigned char *out)
+{
+    if (!c || !out) return GPM_EINVAL;
+    if (!c->state) return fail(c, GPM_ESTATE, "not bound");
+    HIPCHK(c, hipMemcpyAsync(out, c->order, c->ncell, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return GPM_OK;
+}
+
+gpm_status gpm_totals_dev(gpm_ctx *c, const void *U, double totals[4])
+{
+    if (!c || !U || !totals) return GPM_EINVAL;
+    if (!c->state) return fail(c, GPM_ESTATE, "not bound");
+    int nblk = (int)((c->ncell + 255) / 256);
+    if (nblk > kTotBlocks) nblk = kTotBlocks;
+    const double area = c->dx * c->dy;
+    hipError_t e = c->prec == GPM_F64
+                       ? launch_totals<double>((const double *)U, c->ncell, area, c->partial, nblk, c->ctl, c->stream)
+                       : launch_totals<float>((const float *)U, c->ncell, area, c->partial, nblk, c->ctl, c->stream);
+    if (e != hipSuccess) return fail(c, GPM_EHIP, hipGetErrorString(e));
+    HIPCHK(c, hipMemcpyAsync(totals, c->ctl->totals, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return GPM_OK;
+}
+
+gpm_status gpm_totals(gpm_ctx *c, double totals[4])
+{
+    if (!c) return GPM_EINVAL;
+    if (!c->state) return fail(c, GPM_ESTATE, "not bound");
+    return gpm_totals_dev(c, slot_ptr(c, c->cur), totals);
+}
+
+}  // extern "C"

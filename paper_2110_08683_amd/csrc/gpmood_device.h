@@ -1,0 +1,320 @@
+// Device-side building blocks of the 2D GP-MOOD stage (internal header, HIP).
+//
+// Bourgeois & Lee, "GP-MOOD":
+//   reconstruction  eq. (gp_reconstructor): state = z^T q over the radius-R diamond,
+//                   evaluated in the quarter basis of gpmood_tables.h
+//   face quadrature eq. (fvm_F) with the Gauss rules of Table tab:QR-pt-weight
+//   Riemann solver  HLLC (the paper cites Toro et al. 1994; textbook form with
+//                   Davis wave-speed bounds and Toro's star states)
+//   detection       Steps 4-10 of the stepwise algorithm: CAD eq. (CAD) and CAD on
+//                   the reconstructed Riemann states, PAD eq. (PAD), CSD eqs. (divV),
+//                   (gradP), plateau eq. (plateau), DMP eq. (DMP_RK), u2 eqs.
+//                   (u2_curvature), (u2_a), (u2_b) with App. B curvature weights
+//   stage combine   eq. (rk3)
+//
+// Everything here is written with explicit operation order (the library is built
+// with -ffp-contract=off and uses fma() only where written), so the first pass
+// and the cascade passes produce bit-identical face fluxes for the same face
+// order: a face flux is the same number whichever kernel evaluates it, which keeps
+// the update exactly conservative.
+#ifndef GPMOOD_DEVICE_H
+#define GPMOOD_DEVICE_H
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gpmood_tables.h"
+
+namespace gpm {
+
+constexpr int kMaxPasses = 512;
+
+// Per-radius quarter-basis weights and Gauss weights, plus the u2 curvature weights.
+template <typename real>
+struct Weights {
+    real w3[2][2][25];
+    real w2[2][2][13];
+    real w1[2][1][5];
+    real qw3[2], qw2[2], qw1;
+    real curv[2][3];
+};
+
+template <typename real>
+struct StageArgs {
+    const real *Un;
+    const real *Us;
+    real *Uout;
+    const double *dt;  // device scalar
+    uint8_t *order;    // final GP radius per cell
+    int *list_out;     // troubled cells of this evaluation
+    int *count_out;    // their number
+    int nx, ny, bcx, bcy;
+    int s;             // RK stage 0..2
+    int rows;          // rows per wavefront march (first pass)
+    int top;           // top radius
+    unsigned flags;
+    real dx, dy, gamma, sigma_v, sigma_p, plat_thr, delta;
+    Weights<real> W;
+};
+
+// Device control block (lives in the workspace).
+struct Ctl {
+    int nlist[kMaxPasses + 2];  // troubled count of evaluation k (0: first pass)
+    int naff[kMaxPasses + 2];   // cells recomputed by cascade pass k
+    unsigned long long levcnt[4];
+    unsigned long long lam_bits;
+    double dt;
+    double totals[4];
+};
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ int remap(int i, int n, int bc)
+{
+    if (bc == 0) {
+        int r = i % n;
+        return r < 0 ? r + n : r;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+template <typename real>
+__device__ __forceinline__ real vmin(real a, real b) { return a < b ? a : b; }
+template <typename real>
+__device__ __forceinline__ real vmax(real a, real b) { return a > b ? a : b; }
+template <typename real>
+__device__ __forceinline__ bool finite(real x) { return __builtin_isfinite(x); }
+
+// Ideal-gas pressure from conservative variables (detection form).
+template <typename real>
+__device__ __forceinline__ real pressure(real g, real r, real mx, real my, real E)
+{
+    return (g - real(1)) * (E - real(0.5) * (mx * mx + my * my) / r);
+}
+
+template <int R>
+__device__ __forceinline__ constexpr int node_slot(int k)
+{
+    // table order of nodes: R=3: +g1 +g2 -g2 -g1; R=2: +g 0 -g; R=1: +g -g
+    return R == 3 ? ((k == 0 || k == 3) ? 0 : 1) : (R == 2 ? (k == 1 ? 1 : 0) : 0);
+}
+
+template <int R, typename real>
+__device__ __forceinline__ real node_weight(const Weights<real> &W, int k)
+{
+    if constexpr (R == 3) return W.qw3[node_slot<3>(k)];
+    else if constexpr (R == 2) return W.qw2[node_slot<2>(k)];
+    else if constexpr (R == 1) return W.qw1;
+    else return real(1);
+}
+
+template <int R, typename real>
+__device__ __forceinline__ real wq(const Weights<real> &W, int dir, int slot, int e)
+{
+    if constexpr (R == 3) return W.w3[dir][slot][e];
+    else if constexpr (R == 2) return W.w2[dir][slot][e];
+    else return W.w1[dir][0][e];
+}
+
+// Parity sums Q[e] of one variable's radius-R stencil values; ld(di, dj) returns
+// the cell average at offset (di, dj).
+template <int R, typename real, typename Load>
+__device__ __forceinline__ void build_Q(real (&Q)[kNQ[R]], Load ld)
+{
+#pragma unroll
+    for (int e = 0; e < kNQ[R]; ++e) {
+        const int a = kQ[e].a, b = kQ[e].b, c = kQ[e].comp;
+        if (a == 0 && b == 0) {
+            Q[e] = ld(0, 0);
+        } else if (b == 0) {
+            if (c == C_EE) Q[e] = ld(a, 0) + ld(-a, 0);
+            else Q[e] = ld(a, 0) - ld(-a, 0);
+        } else if (a == 0) {
+            if (c == C_EE) Q[e] = ld(0, b) + ld(0, -b);
+            else Q[e] = ld(0, b) - ld(0, -b);
+        } else {
+            // four entries per (a, b): EE, OE, EO, OO in that order (see kQ)
+            if (c == C_EE) {
+                const real pp = ld(a, b), mp = ld(-a, b), pm = ld(a, -b), mm = ld(-a, -b);
+                const real s1 = pp + mp, d1 = pp - mp, s2 = pm + mm, d2 = pm - mm;
+                Q[e] = s1 + s2;
+                Q[e + 1] = d1 + d2;
+                Q[e + 2] = s1 - s2;
+                Q[e + 3] = d1 - d2;
+            }
+        }
+    }
+}
+
+// The 2q face states of one variable for direction DIR (0: x faces, 1: y faces):
+// sm[k] on the - face, sp[k] on the + face, node k in table order.
+template <int R, int DIR, typename real>
+__device__ __forceinline__ void states_dir(const real (&Q)[kNQ[R]], const Weights<real> &W,
+                                           real (&sm)[nodes_of(R)], real (&sp)[nodes_of(R)])
+{
+    constexpr int q = nodes_of(R);
+    constexpr int cF = DIR == 0 ? C_OE : C_EO;  // odd across the face
+    constexpr int cN = DIR == 0 ? C_EO : C_OE;  // odd along the face (node sign)
+#pragma unroll
+    for (int p = 0; p < slots_of(R); ++p) {
+        real P[4] = {real(0), real(0), real(0), real(0)};
+        const bool zero = slot_is_zero(R, p);
+#pragma unroll
+        for (int e = 0; e < kNQ[R]; ++e) {
+            const int c = kQ[e].comp;
+            if (zero && (c == cN || c == C_OO)) continue;
+            P[c] = fma(wq<R>(W, DIR, p, e), Q[e], P[c]);
+        }
+        const real A = P[C_EE] + P[cF];
+        const real Bm = P[C_EE] - P[cF];
+        if (zero) {
+            sp[p] = A;
+            sm[p] = Bm;
+        } else {
+            const real C = P[cN] + P[C_OO];
+            const real D = P[cN] - P[C_OO];
+            sp[p] = A + C;
+            sp[q - 1 - p] = A - C;
+            sm[p] = Bm + D;
+            sm[q - 1 - p] = Bm - D;
+        }
+    }
+}
+
+// HLLC flux through a face normal to axis DIR.  badL / badR: the density or the
+// pressure of the left / right state is not finite (CAD on Riemann states).
+template <int DIR, typename real>
+__device__ __forceinline__ void hllc(real g, const real *UL, const real *UR, real *F, bool &badL, bool &badR)
+{
+    constexpr int n = 1 + DIR, t = 2 - DIR;
+    const real rl = UL[0], irl = real(1) / rl, ul = UL[n] * irl, vl = UL[t] * irl, El = UL[3];
+    const real rr = UR[0], irr = real(1) / rr, ur = UR[n] * irr, vr = UR[t] * irr, Er = UR[3];
+    const real pl = (g - real(1)) * (El - real(0.5) * rl * (ul * ul + vl * vl));
+    const real pr = (g - real(1)) * (Er - real(0.5) * rr * (ur * ur + vr * vr));
+    badL = !(finite(rl) && finite(pl));
+    badR = !(finite(rr) && finite(pr));
+    const real cl = sqrt(g * pl * irl), cr = sqrt(g * pr * irr);
+    const real SL = vmin(ul - cl, ur - cr);
+    const real SR = vmax(ul + cl, ur + cr);
+    const real Ss = (pr - pl + rl * ul * (SL - ul) - rr * ur * (SR - ur)) / (rl * (SL - ul) - rr * (SR - ur));
+    const bool useL = Ss >= real(0);
+    // star state of the side selected by the sign of S*
+    const real rk = useL ? rl : rr, uk = useL ? ul : ur, vk = useL ? vl : vr;
+    const real Ek = useL ? El : Er, pk = useL ? pl : pr, Sk = useL ? SL : SR, irk = useL ? irl : irr;
+    const real sku = Sk - uk;
+    const real fac = rk * sku / (Sk - Ss);
+    const real fk[4] = {rk * uk, rk * uk * uk + pk, rk * uk * vk, uk * (Ek + pk)};
+    const real uc[4] = {rk, rk * uk, rk * vk, Ek};
+    const real us[4] = {fac, fac * Ss, fac * vk, fac * (Ek * irk + (Ss - uk) * (Ss + pk / (rk * sku)))};
+    const real fL[4] = {rl * ul, rl * ul * ul + pl, rl * ul * vl, ul * (El + pl)};
+    const real fR[4] = {rr * ur, rr * ur * ur + pr, rr * ur * vr, ur * (Er + pr)};
+    const bool takeL = SL >= real(0);
+    const bool takeStar = !takeL && (useL || SR > real(0));
+    real f[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const real fs = fk[k] + Sk * (us[k] - uc[k]);
+        f[k] = takeL ? fL[k] : (takeStar ? fs : fR[k]);
+    }
+    F[0] = f[0];
+    F[n] = f[1];
+    F[t] = f[2];
+    F[3] = f[3];
+}
+
+// Stage combination of eq. (rk3): U^(1) = U*, hat U^(2) = (3 U^n + U*)/4,
+// U^(n+1) = (U^n + 2 U*)/3.
+template <typename real>
+__device__ __forceinline__ real combine(int s, real un, real ust)
+{
+    if (s == 0) return ust;
+    if (s == 1) return real(0.25) * (real(3) * un + ust);
+    return (un + real(2) * ust) / real(3);
+}
+
+// Detection of one cell (Steps 4-10).  nb(di, dj, v) returns the stage input at
+// an offset within radius 2.  Returns true if the candidate is troubled.
+template <typename real, typename Nb>
+__device__ __forceinline__ bool troubled(const StageArgs<real> &A, int order, const real (&ust)[4],
+                                         bool rsbad, Nb nb)
+{
+    if (order == 0) return false;  // Step 10: the safe scheme is accepted
+    const real g = A.gamma;
+    const real rho = ust[0];
+    const real p = pressure(g, ust[0], ust[1], ust[2], ust[3]);
+    if (!(finite(rho) && finite(p))) return true;            // Step 4: CAD
+    if ((A.flags & 8u) && rsbad) return true;                // CAD on the Riemann states
+    if (!(rho > real(0) && p > real(0))) return true;        // Step 5: PAD
+    // DMP bounds over the cell and its face neighbours
+    const real rc = nb(0, 0, 0), rW = nb(-1, 0, 0), rE = nb(1, 0, 0), rS = nb(0, -1, 0), rN = nb(0, 1, 0);
+    real lo = rc, hi = rc;
+    lo = vmin(lo, rW); hi = vmax(hi, rW);
+    lo = vmin(lo, rE); hi = vmax(hi, rE);
+    lo = vmin(lo, rS); hi = vmax(hi, rS);
+    lo = vmin(lo, rN); hi = vmax(hi, rN);
+    if (lo <= rho && rho <= hi) return false;                // Step 8: DMP
+    if ((A.flags & 2u) && (hi - lo) < A.plat_thr) return false;  // Step 7: plateau
+    if (A.flags & 1u) {                                       // Step 6: CSD
+        const real pE = pressure(g, rE, nb(1, 0, 1), nb(1, 0, 2), nb(1, 0, 3));
+        const real pW = pressure(g, rW, nb(-1, 0, 1), nb(-1, 0, 2), nb(-1, 0, 3));
+        const real pN = pressure(g, rN, nb(0, 1, 1), nb(0, 1, 2), nb(0, 1, 3));
+        const real pS = pressure(g, rS, nb(0, -1, 1), nb(0, -1, 2), nb(0, -1, 3));
+        const real divV = (nb(1, 0, 1) / rE - nb(-1, 0, 1) / rW) / (real(2) * A.dx) +
+                          (nb(0, 1, 2) / rN - nb(0, -1, 2) / rS) / (real(2) * A.dy);
+        const real gradp = fabs(pE - pW) / (real(2) * A.dx * vmin(pE, pW)) +
+                           fabs(pN - pS) / (real(2) * A.dy * vmin(pN, pS));
+        if (divV >= -A.sigma_v && gradp <= A.sigma_p) return false;
+    }
+    if (A.flags & 4u) {                                       // Step 9: u2
+        bool ok = true;
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            const real w0 = A.W.curv[d][0], wa = A.W.curv[d][1], wt = A.W.curv[d][2];
+            const int cx[5] = {0, -1, 1, 0, 0}, cy[5] = {0, 0, 0, -1, 1};
+            real cmin = real(0), cmax = real(0);
+#pragma unroll
+            for (int m = 0; m < 5; ++m) {
+                const int mi = cx[m], mj = cy[m];
+                const real along = d == 0 ? nb(mi - 1, mj, 0) + nb(mi + 1, mj, 0) : nb(mi, mj - 1, 0) + nb(mi, mj + 1, 0);
+                const real across = d == 0 ? nb(mi, mj - 1, 0) + nb(mi, mj + 1, 0) : nb(mi - 1, mj, 0) + nb(mi + 1, mj, 0);
+                real kap = w0 * nb(mi, mj, 0);
+                kap = fma(wa, along, kap);
+                kap = fma(wt, across, kap);
+                if (m == 0) { cmin = kap; cmax = kap; }
+                else { cmin = vmin(cmin, kap); cmax = vmax(cmax, kap); }
+            }
+            const bool prod = cmin * cmax > -A.delta;
+            const bool a = prod && vmax(fabs(cmax), fabs(cmin)) < A.delta;
+            const bool b = prod && fabs(cmin) >= real(0.5) * fabs(cmax);
+            ok = ok && (a || b);
+        }
+        if (ok) return false;
+    }
+    return true;
+}
+
+// Order this wavefront's LDS writes before its later LDS reads of other lanes'
+// data.  The lanes of a wavefront execute in lockstep and LDS serves a wavefront's
+// requests in order, so this only keeps the compiler from moving the accesses.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Append flagged cells of the wavefront to a list (ballot + prefix, one atomic per
+// wave).  Must be reached by all 64 lanes of the wavefront together.
+__device__ __forceinline__ void wave_append(bool flag, int cell, int *list, int *count)
+{
+    const unsigned long long mask = __ballot(flag);
+    if (mask == 0ull) return;
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    if (lane == 0) base = atomicAdd(count, (int)__popcll(mask));
+    base = __shfl(base, 0);
+    if (flag) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = cell;
+}
+
+}  // namespace gpm
+
+#endif

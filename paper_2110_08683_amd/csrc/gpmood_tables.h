@@ -1,0 +1,53 @@
+// Internal tables shared by the host weight generator and the device kernels.
+//
+// The GP prediction vectors of a blocky-diamond stencil (Sec. "The GP stencil")
+// have the mirror symmetries of the grid: the weights of face x- are those of
+// face x+ mirrored in x, the weights of node -g are those of node +g mirrored
+// along the face.  The library therefore stores each direction's weights for the
+// + face and the positive nodes only, in a "quarter basis": for every quarter
+// position (a, b) with a, b >= 0 and a + b <= R the four stencil values
+// q(+-a, +-b) are combined into parity sums
+//     EE = sum of all four, OE = odd in di, EO = odd in dj, OO = odd in both,
+// and the weights into the matching combinations divided by the multiplicity.
+// One set of products then yields the four states (+face/-face) x (+node/-node)
+// by a two-stage butterfly (exact algebra, the identity
+// sum_i w_i q_i = (1/4) (Hw)^T (Hq) with the 4x4 Hadamard matrix H).
+//
+// The entry list below is ordered so that radius 1 is a prefix of radius 2,
+// which is a prefix of radius 3: the parity sums computed for the top order serve
+// every lower order of the cascade.
+#ifndef GPMOOD_TABLES_H
+#define GPMOOD_TABLES_H
+
+namespace gpm {
+
+enum Comp { C_EE = 0, C_OE = 1, C_EO = 2, C_OO = 3 };
+
+struct QEntry {
+    int a, b, comp;
+};
+
+// Parity entries in order; radius R uses the first kNQ[R] of them.
+constexpr QEntry kQ[25] = {
+    {0, 0, C_EE},
+    {1, 0, C_EE}, {1, 0, C_OE}, {0, 1, C_EE}, {0, 1, C_EO},
+    {2, 0, C_EE}, {2, 0, C_OE}, {0, 2, C_EE}, {0, 2, C_EO},
+    {1, 1, C_EE}, {1, 1, C_OE}, {1, 1, C_EO}, {1, 1, C_OO},
+    {3, 0, C_EE}, {3, 0, C_OE}, {0, 3, C_EE}, {0, 3, C_EO},
+    {2, 1, C_EE}, {2, 1, C_OE}, {2, 1, C_EO}, {2, 1, C_OO},
+    {1, 2, C_EE}, {1, 2, C_OE}, {1, 2, C_EO}, {1, 2, C_OO},
+};
+constexpr int kNQ[4] = {1, 5, 13, 25};
+
+// Gauss nodes per face for radius R (Step 3 of the stepwise algorithm: q = R + 1;
+// FOG uses one node, its states are constant along the face).
+constexpr int nodes_of(int R) { return R == 0 ? 1 : R + 1; }
+// Distinct node slots stored per direction: one per +-g pair, plus the centre
+// node of the 3-point rule (R = 2).
+constexpr int slots_of(int R) { return R == 0 ? 0 : (R == 1 ? 1 : 2); }
+// Is slot k the centre node (g = 0)?
+constexpr bool slot_is_zero(int R, int k) { return R == 2 && k == 1; }
+
+}  // namespace gpm
+
+#endif

@@ -1,0 +1,45 @@
+"""The C-ABI library loads and exports every symbol include/gpmood.h declares (no GPU
+needed: nothing is called that touches a device), and the header and the binding
+agree on the exported names."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "gpmood.h")).read()
+    return set(re.findall(r"^\S.*?\b(gpm_[a-z_]+)\s*\(", src, flags=re.M))
+
+
+def test_header_names_match_binding():
+    from paper_2110_08683_amd.binding import EXPORTS
+    assert _declared() == set(EXPORTS)
+
+
+def test_library_exports_all_symbols():
+    from paper_2110_08683_amd.binding import LIB_PATH
+    if not os.path.exists(LIB_PATH):
+        pytest.fail("libgpmood.so not built: run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_strerror_and_argument_errors_without_gpu():
+    from paper_2110_08683_amd import binding as B
+    L = B.lib()
+    assert L.gpm_strerror(0) == b"ok"
+    assert L.gpm_strerror(5).startswith(b"MOOD")
+    # invalid grids are rejected before any device call
+    g = B.gpm_grid()
+    g.dim = 3
+    ctx = ctypes.c_void_p()
+    assert L.gpm_create(ctypes.byref(g), 0, None, ctypes.byref(ctx)) == B.GPM_EUNSUPPORTED
+    g.dim = 2
+    g.n[0], g.n[1] = 0, 4
+    assert L.gpm_create(ctypes.byref(g), 0, None, ctypes.byref(ctx)) == B.GPM_EINVAL
+    assert L.gpm_create(None, 0, None, ctypes.byref(ctx)) == B.GPM_EINVAL

@@ -1,0 +1,175 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, element by element.
+
+Bar (FP64): relative L1 per field <= 1e-12 and identical order masks, except at ties
+(cells whose oracle detection margin lies within rounding of a threshold), which are
+then replayed with the oracle forced to the GPU's mask.  FP32 runs report their
+L1 / Linf error against the oracle and must stay within a stated bound.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import gpmood_inputs as gi
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _gp(torch_cuda, *a, **k):
+    from paper_2110_08683_amd import GPMood
+    return GPMood(*a, **k)
+
+
+def _rel_l1(a, b):
+    out = []
+    for v in range(4):
+        d = np.abs(a[v] - b[v]).sum()
+        s = np.abs(b[v]).sum()
+        out.append(d / s if s > 0 else d)
+    return np.array(out)
+
+
+def test_vortex_fp64_matches_oracle(torch_cuda):
+    """Vortex 64x64 on [0,10]^2, periodic, GP-MOOD7 (7->5->3->1), ell = 12 dx, CFL 0.8,
+    20 steps: every field within 1e-12 relative L1, order mask uniform top order."""
+    n = 64
+    _note("vortex64 f64 20 steps")
+    U0 = gi.vortex(n, n, hi=(10.0, 10.0))
+    g = _gp(torch_cuda, n, n, hi=(10.0, 10.0), bc=(0, 0), prec="f64", cascade=(3, 2, 1, 0))
+    o = oracle.Oracle(n, n, hi=(10.0, 10.0), bc=(0, 0), cascade=(3, 2, 1, 0))
+    g.gpm_init_state(U0)
+    Uo = U0.copy()
+    for step in range(20):
+        dt_g = g.gpm_compute_dt(0.8)
+        dt_o = o.dt(Uo, 0.8)
+        assert abs(dt_g - dt_o) <= 1e-12 * dt_o
+        g.gpm_step(0.0, 1)
+        Uo, _, counts, _ = o.run(Uo, fixed_dt=dt_g, nsteps=1)
+        assert counts[:, :, 1:].sum() == 0
+    Ug = g.gpm_get_state()
+    err = _rel_l1(Ug, Uo)
+    assert np.all(err <= 1e-12), err
+    mask = g.gpm_get_order_mask()
+    assert np.all(mask == 3)
+    c, it = g.gpm_troubled_counts()
+    assert c[0] == n * n and it == 1
+    # conservation on the periodic grid
+    np.testing.assert_allclose(g.gpm_totals(), o.totals(U0), rtol=1e-13)
+
+
+def _replay_stage(torch_cuda, g, o, s, Un, Us, dt):
+    torch = torch_cuda
+    dev = torch.device("cuda")
+    tn = torch.from_numpy(Un).to(dev)
+    ts = torch.from_numpy(Us).to(dev)
+    tout = torch.empty_like(ts)
+    g.gpm_set_dt(dt)
+    g.gpm_stage_dev(s, tn, ts, tout)
+    torch.cuda.synchronize()
+    Ug = tout.cpu().numpy()
+    mask = g.gpm_get_order_mask().astype(np.int32)
+    counts, iters = g.gpm_troubled_counts()
+    Uo, order, ocounts, oiters = o.stage(s, Un, Us, dt)
+    return Ug, mask, counts, iters, Uo, order, ocounts, oiters
+
+
+@pytest.mark.parametrize("n,seed,bc,cascade", [
+    (96, 1, (1, 1), (3, 2, 1, 0)),
+    (75, 2, (0, 0), (3, 2, 1, 0)),
+    (64, 3, (1, 0), (3, 1, 0)),
+    (70, 4, (1, 1), (2, 1, 0)),
+    (66, 5, (0, 1), (1, 0)),
+])
+def test_quadrants_stage_replay_fp64(torch_cuda, n, seed, bc, cascade):
+    """Four-quadrant shocks: each RK stage replayed on the oracle's own stage inputs.
+    Candidates within 1e-12 and masks identical (ties are reported if they occur)."""
+    _note(f"quadrant replay n={n} seed={seed} bc={bc} cascade={cascade}")
+    U0 = gi.quadrants(n, n, seed=seed)
+    o = oracle.Oracle(n, n, bc=bc, cascade=cascade)
+    g = _gp(torch_cuda, n, n, bc=bc, prec="f64", cascade=cascade)
+    U = o.run(U0, cfl=0.8, nsteps=3)[0]  # let the waves develop
+    dt = o.dt(U, 0.8)
+    U1 = o.stage(0, U, U, dt)[0]
+    U2 = o.stage(1, U, U1, dt)[0]
+    exercised = 0
+    for s, Us in ((0, U), (1, U1), (2, U2)):
+        Ug, mask, counts, iters, Uo, order, ocounts, oiters = _replay_stage(torch_cuda, g, o, s, U, Us, dt)
+        diff = mask != order
+        if diff.any():
+            # ties: replay the oracle with the GPU mask and demand agreement there
+            Uf = o.stage_forced(s, U, Us, dt, mask)
+            err = _rel_l1(Ug, Uf)
+            pytest.fail(f"mask differs at {int(diff.sum())} cells (stage {s}); forced-replay err {err}")
+        np.testing.assert_array_equal(counts[:len(cascade)], ocounts)
+        assert iters == oiters
+        err = _rel_l1(Ug, Uo)
+        assert np.all(err <= 1e-12), (s, err)
+        exercised += int(ocounts[1:].sum())
+    assert exercised > 0
+
+
+def test_quadrants_steps_conservation_fp64(torch_cuda):
+    """Periodic four-quadrant run, 10 GPU steps: totals conserved to roundoff and the final
+    state close to the oracle's (masks may diverge slowly through ties over many steps)."""
+    n = 64
+    _note("quadrant periodic conservation f64")
+    U0 = gi.quadrants(n, n, seed=6)
+    g = _gp(torch_cuda, n, n, bc=(0, 0), prec="f64")
+    o = oracle.Oracle(n, n, bc=(0, 0))
+    g.gpm_init_state(U0)
+    t0 = g.gpm_totals()
+    g.gpm_step(0.8, 10)
+    t1 = g.gpm_totals()
+    np.testing.assert_allclose(t1, t0, rtol=1e-13)
+    Uo = o.run(U0, cfl=0.8, nsteps=10)[0]
+    err = _rel_l1(g.gpm_get_state(), Uo)
+    assert np.all(err < 1e-9), err
+
+
+def test_vortex_fp32_error_report(torch_cuda):
+    """FP32 bulk path on the vortex: L1 / Linf against the FP64 oracle, stated per run."""
+    n = 64
+    _note("vortex64 f32 20 steps")
+    U0 = gi.vortex(n, n, hi=(10.0, 10.0))
+    g = _gp(torch_cuda, n, n, hi=(10.0, 10.0), bc=(0, 0), prec="f32")
+    o = oracle.Oracle(n, n, hi=(10.0, 10.0), bc=(0, 0))
+    g.gpm_init_state(U0)
+    Uo = U0.copy()
+    for _ in range(20):
+        dt = g.gpm_compute_dt(0.8)
+        g.gpm_step(0.0, 1)
+        Uo = o.run(Uo, fixed_dt=dt, nsteps=1)[0]
+    Ug = g.gpm_get_state()
+    l1 = _rel_l1(Ug, Uo)
+    linf = np.abs(Ug - Uo).max(axis=(1, 2)) / np.abs(Uo).max(axis=(1, 2))
+    print(f"[fp32 vortex] rel L1 {l1} rel Linf {linf}")
+    assert np.all(l1 < 1e-5) and np.all(linf < 1e-4)
+    assert np.all(g.gpm_get_order_mask() == 3)
+
+
+def test_fp32_quadrants_positivity(torch_cuda):
+    n = 128
+    _note("quadrant f32 positivity")
+    U0 = gi.quadrants(n, n, seed=1)
+    g = _gp(torch_cuda, n, n, bc=(1, 1), prec="f32")
+    g.gpm_init_state(U0)
+    g.gpm_step(0.8, 20)
+    U = g.gpm_get_state()
+    p = 0.4 * (U[3] - 0.5 * (U[1] ** 2 + U[2] ** 2) / U[0])
+    assert np.all(U[0] > 0) and np.all(p > 0)
+    c, it = g.gpm_troubled_counts()
+    assert c.sum() == n * n and it >= 2
