@@ -1,0 +1,186 @@
+"""Throughput of the GP-MOOD stage engine on one MI355X.
+
+Workload (the headline configuration): 2D four-quadrant Riemann problem on
+[0,1]^2 with 2048 x 2048 cells, outflow boundaries, quadrant states drawn from
+PCG64 seed 1 (rho in [0.1, 2], |u|,|v| <= 1.5, p in [0.02, 2]), GP-MOOD7 with the
+7->5->3->1 cascade, ell = 12 dx, HLLC, SSP-RK3, CFL 0.8.  Synthetic input.
+
+A step is one full SSP-RK3 step: the FP64 dt max-reduction and three stages, each
+with its complete MOOD cascade.  The metric is cell-updates per second per RK
+stage: cells * 3 * steps / elapsed, where elapsed is wall time between two
+torch.cuda.synchronize() calls around exactly `steps` steps.  The FP32 bulk path
+is the headline value; the FP64 path is reported beside it.
+
+The roofline object is for the dominant kernel (the first pass at the top order),
+whose launches are bracketed by HIP events on the library's stream during the
+timed region.  The kernel is bound by vector ALU work, so `achieved` is its
+algorithmic flop count per launch divided by its mean launch time.
+cpu_baseline times the plain FP64 oracle on one stage of the same 2048^2 problem.
+
+Usage: python bench.py [--gpus 1] [--steps 500] [--warmup 20] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N = 2048
+SEED = 1
+CASCADE = (3, 2, 1, 0)
+CFL = 0.8
+METRIC = "cell-updates/s per RK stage (GP-MOOD7 2D, incl. cascade), % HBM peak; FP32 vs FP64"
+
+# Algorithmic work of one cell in the first pass at radius 3, as formulated here
+# (quarter-basis reconstruction; FMA = 2 flops, a division or square root = 1):
+#   reconstruction, per variable: 36 adds (parity sums) + 4 x (25 FMA + 8 adds)
+#     = 268 flops; x 4 variables                                     = 1072
+#   HLLC, 8 solves per cell (2 owned faces x 4 Gauss nodes), 98 each  =  784
+#   Gauss quadrature sums, 8 x 4 FMA                                   =   64
+#   flux differences, candidate update                                 =   28
+#   RK combination (average over the three stages)                     =    8
+FLOPS_PER_CELL = {3: 1956}
+# HBM bytes per cell per stage that the first pass must move (FP32 / FP64):
+# read U_s (4 values), write U_out (4 values) and the order byte, plus U^n
+# (4 values) in stages 1 and 2: averaged over the three stages.
+def bytes_per_cell(esz):
+    return (4 * esz + 4 * esz + 1) + (2.0 / 3.0) * 4 * esz
+
+
+PEAK = {"f32": 157.3e12, "f64": 78.6e12}   # published vector peaks (FP32 with packed math)
+PEAK_UNPACKED = 78.6e12                     # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+HBM_PEAK = 8.0e12
+
+
+def run_gpu(prec, steps, warmup, U0):
+    import torch
+
+    from paper_2110_08683_amd import GPMood
+    g = GPMood(N, N, bc=(1, 1), prec=prec, cascade=CASCADE, device="cuda:0")
+    g.gpm_init_state(U0)
+    g.gpm_step(CFL, warmup)
+    torch.cuda.synchronize()
+    g.gpm_instrument(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.gpm_step(CFL, steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ins = g.gpm_instrument_read()
+    g.gpm_instrument(False)
+    elapsed = t1 - t0
+    ncell = N * N
+    value = ncell * 3 * steps / elapsed
+    fp_ms = ins["first_pass_ms"] / max(1, ins["first_pass_launches"])
+    lev = ins["level_cells"]
+    stages = max(1, ins["stages"])
+    out = {
+        "value": value,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "first_pass_ms_mean": fp_ms,
+        "cascade_ms_mean": ins["cascade_ms"] / stages,
+        "mood_iters_mean": ins["mood_iters"] / stages,
+        "final_order_fraction": [l / (ncell * stages) for l in lev[:len(CASCADE)]],
+    }
+    U = g.gpm_get_state()
+    out["finite"] = bool((U == U).all())
+    g.close()
+    return out
+
+
+def roofline(prec, res):
+    esz = 4 if prec == "f32" else 8
+    cells = N * N
+    t = res["first_pass_ms_mean"] * 1e-3
+    flops = FLOPS_PER_CELL[CASCADE[0]] * cells
+    achieved = flops / t
+    hbm = bytes_per_cell(esz) * cells / t
+    return {
+        "bound": "alu",
+        "kernel": "k_first_pass<%s,R=3>" % ("float" if prec == "f32" else "double"),
+        "achieved": achieved / 1e12,
+        "peak": PEAK[prec] / 1e12,
+        "unit": "TFLOP/s",
+        "frac": achieved / PEAK[prec],
+        "frac_of_unpacked_peak": achieved / PEAK_UNPACKED,
+        "flops_per_cell": FLOPS_PER_CELL[CASCADE[0]],
+        "cells_per_launch": cells,
+        "mean_launch_ms": res["first_pass_ms_mean"],
+        "hbm_algorithmic_GBps": hbm / 1e9,
+        "hbm_frac": hbm / HBM_PEAK,
+        "traffic": None,
+    }
+
+
+def cpu_baseline(U0):
+    import gpmood_inputs  # noqa: F401
+    import oracle
+    o = oracle.Oracle(N, N, bc=(1, 1), cascade=CASCADE)
+    dt = o.dt(U0, CFL)
+    t0 = time.perf_counter()
+    _, _, counts, iters = o.stage(0, U0, U0, dt)
+    el = time.perf_counter() - t0
+    return {"value": N * N / el, "unit": "cell-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "one SSP-RK3 stage (stage 0, full MOOD loop, %d evaluations) of the 2048^2 four-quadrant "
+                      "problem from its initial state, FP64, %.1f s" % (iters, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {a.gpus})", file=sys.stderr)
+        sys.exit(2)
+    import gpmood_inputs as gi
+    U0 = gi.quadrants(N, N, seed=SEED)
+    print(f"[bench] fp32 {a.steps} steps after {a.warmup} warmup", file=sys.stderr, flush=True)
+    r32 = run_gpu("f32", a.steps, a.warmup, U0)
+    print(f"[bench] fp32 done: {r32['value']:.3e} cell-updates/s", file=sys.stderr, flush=True)
+    r64 = None
+    if not a.no_fp64:
+        r64 = run_gpu("f64", a.steps, a.warmup, U0)
+        print(f"[bench] fp64 done: {r64['value']:.3e} cell-updates/s", file=sys.stderr, flush=True)
+    line = {
+        "metric": METRIC,
+        "value": r32["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2D four-quadrant Riemann problem, 2048x2048 on [0,1]^2, outflow, PCG64 seed 1, "
+                               "GP-MOOD7 cascade 7-5-3-1, ell=12dx, HLLC, SSP-RK3, CFL 0.8",
+                   "cells": N * N, "precision_bulk": "f32", "dt_reduction": "f64"},
+        "roofline": roofline("f32", r32),
+        "mood": {"iters_per_stage": r32["mood_iters_mean"], "final_order_fraction": r32["final_order_fraction"],
+                 "cascade_ms_per_stage": r32["cascade_ms_mean"], "first_pass_ms": r32["first_pass_ms_mean"]},
+    }
+    if r64 is not None:
+        line["fp64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"], "roofline": roofline("f64", r64),
+                        "mood_iters_per_stage": r64["mood_iters_mean"],
+                        "final_order_fraction": r64["final_order_fraction"]}
+        line["fp32_over_fp64"] = r32["value"] / r64["value"]
+    if not a.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(U0)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -163,6 +163,20 @@ gpm_status gpm_totals_dev(gpm_ctx *ctx, const void *U, double totals[4]);
    per wavefront march in the first pass (4..256).  Defaults 4 and 16. */
 gpm_status gpm_set_tuning(gpm_ctx *ctx, int passes_per_check, int rows_per_wave);
 
+/* Instrumentation for measurement (not part of the method).  When enabled,
+   every first-pass launch and every stage's cascade are bracketed by HIP events
+   recorded on the context stream, and per-stage statistics (final-order counts
+   per cascade level, MOOD iterations) are accumulated on the device.  Enabling
+   resets the accumulators. */
+gpm_status gpm_instrument(gpm_ctx *ctx, int enable);
+
+/* Read the accumulators (synchronising): first-pass time and launches, cascade
+   time (from the end of the first pass to the end of the stage) and stages,
+   summed final-order counts per level and summed MOOD iterations. */
+gpm_status gpm_instrument_read(gpm_ctx *ctx, double *first_pass_ms, long long *first_pass_launches,
+                               double *cascade_ms, long long *stages, long long level_cells[4],
+                               long long *mood_iters);
+
 const char *gpm_strerror(gpm_status st);
 const char *gpm_last_error(const gpm_ctx *ctx);
 void gpm_destroy(gpm_ctx *ctx);

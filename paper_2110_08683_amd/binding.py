@@ -25,7 +25,8 @@ GPM_FLAGS_ALL = 15
 EXPORTS = ("gpm_create", "gpm_set_scheme", "gpm_workspace_size", "gpm_bind", "gpm_state_ptr",
            "gpm_init_state", "gpm_get_state", "gpm_compute_dt", "gpm_set_dt", "gpm_stage_dev",
            "gpm_step", "gpm_troubled_counts", "gpm_get_order_mask", "gpm_totals", "gpm_totals_dev",
-           "gpm_set_tuning", "gpm_strerror", "gpm_last_error", "gpm_destroy")
+           "gpm_set_tuning", "gpm_instrument", "gpm_instrument_read", "gpm_strerror", "gpm_last_error",
+           "gpm_destroy")
 
 
 class gpm_grid(ctypes.Structure):
@@ -73,6 +74,9 @@ def lib():
         "gpm_totals": ([ctxp, dp], st),
         "gpm_totals_dev": ([ctxp, vp, dp], st),
         "gpm_set_tuning": ([ctxp, ctypes.c_int, ctypes.c_int], st),
+        "gpm_instrument": ([ctxp, ctypes.c_int], st),
+        "gpm_instrument_read": ([ctxp, dp, ctypes.POINTER(ctypes.c_longlong), dp, ctypes.POINTER(ctypes.c_longlong),
+                                 ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)], st),
         "gpm_strerror": ([st], ctypes.c_char_p),
         "gpm_last_error": ([ctxp], ctypes.c_char_p),
         "gpm_destroy": ([ctxp], None),
@@ -221,3 +225,15 @@ class GPMood:
 
     def gpm_set_tuning(self, passes_per_check=4, rows_per_wave=16):
         self._check(lib().gpm_set_tuning(self.ctx, int(passes_per_check), int(rows_per_wave)))
+
+    def gpm_instrument(self, enable=True):
+        self._check(lib().gpm_instrument(self.ctx, int(bool(enable))))
+
+    def gpm_instrument_read(self):
+        fp, cm = ctypes.c_double(), ctypes.c_double()
+        nfp, nst, it = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong()
+        lev = (ctypes.c_longlong * 4)()
+        self._check(lib().gpm_instrument_read(self.ctx, ctypes.byref(fp), ctypes.byref(nfp), ctypes.byref(cm),
+                                              ctypes.byref(nst), lev, ctypes.byref(it)))
+        return {"first_pass_ms": fp.value, "first_pass_launches": nfp.value, "cascade_ms": cm.value,
+                "stages": nst.value, "level_cells": list(lev), "mood_iters": it.value}

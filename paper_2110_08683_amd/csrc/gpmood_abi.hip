@@ -46,16 +46,27 @@ struct gpm_ctx {
     char *work = nullptr;
     int cur = 0;
     uint8_t *order = nullptr;
-    unsigned *stamp = nullptr;
-    int *lists[2] = {nullptr, nullptr};
-    int *aff = nullptr;
+    unsigned *cstamp = nullptr;
+    unsigned *fstamp = nullptr;
+    int *flist[2] = {nullptr, nullptr};
+    int *clist[2] = {nullptr, nullptr};
+    void *FX = nullptr;
+    void *GY = nullptr;
+    uint8_t *FXf = nullptr;
+    uint8_t *GYf = nullptr;
     Ctl *ctl = nullptr;
     double *partial = nullptr;
     unsigned pass = 0;
     int passes_per_check = 4;
+    int tail_threshold = 48;  // troubled cells below which the cascade finishes in one workgroup
     int rows = 16;
     int last_npass = 0;
+    bool fresh_ctl = true;
     int *pinned = nullptr;
+    // instrumentation
+    bool instrument = false;
+    std::vector<hipEvent_t> evs;  // 3 per instrumented stage: first pass start/end, stage end
+    size_t nev_used = 0;
     std::string err;
 };
 
@@ -77,16 +88,24 @@ static size_t state_slot_bytes(const gpm_ctx *c)
     return align_up(4 * c->ncell * (c->prec == GPM_F64 ? 8 : 4));
 }
 
-static size_t work_layout(const gpm_ctx *c, size_t off[6])
+static size_t nfaces_x(const gpm_ctx *c) { return (size_t)(c->nx + 1) * c->ny; }
+static size_t nfaces_y(const gpm_ctx *c) { return (size_t)c->nx * (c->ny + 1); }
+
+// Workspace partition (each part 256-byte aligned).
+enum { W_ORDER, W_CSTAMP, W_FSTAMP, W_FL0, W_FL1, W_CL0, W_CL1, W_FX, W_GY, W_FXF, W_GYF, W_CTL, W_PART, W_N };
+
+static size_t work_layout(const gpm_ctx *c, size_t off[W_N])
 {
+    const size_t nf = nfaces_x(c) + nfaces_y(c);
+    const size_t esz = c->prec == GPM_F64 ? 8 : 4;
+    const size_t sz[W_N] = {c->ncell, 4 * c->ncell, 4 * nf, 4 * nf, 4 * nf, 4 * c->ncell, 4 * c->ncell,
+                            4 * esz * nfaces_x(c), 4 * esz * nfaces_y(c), nfaces_x(c), nfaces_y(c), sizeof(Ctl),
+                            (size_t)kTotBlocks * 4 * 2 * sizeof(double)};
     size_t o = 0;
-    off[0] = o; o = align_up(o + c->ncell);                      // order
-    off[1] = o; o = align_up(o + 4 * c->ncell);                  // stamp
-    off[2] = o; o = align_up(o + 4 * c->ncell);                  // list 0
-    off[3] = o; o = align_up(o + 4 * c->ncell);                  // list 1
-    off[4] = o; o = align_up(o + 4 * c->ncell);                  // affected
-    off[5] = o; o = align_up(o + sizeof(Ctl));                   // control block
-    o = align_up(o + (size_t)kTotBlocks * 4 * 2 * sizeof(double));  // totals partials
+    for (int k = 0; k < W_N; ++k) {
+        off[k] = o;
+        o = align_up(o + sz[k]);
+    }
     return o;
 }
 
@@ -142,6 +161,7 @@ void gpm_destroy(gpm_ctx *c)
 {
     if (!c) return;
     if (c->pinned) (void)hipHostFree(c->pinned);
+    for (hipEvent_t e : c->evs) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -201,7 +221,7 @@ gpm_status gpm_set_scheme(gpm_ctx *c, const gpm_scheme *s)
 gpm_status gpm_workspace_size(const gpm_ctx *c, size_t *state_bytes, size_t *work_bytes)
 {
     if (!c) return GPM_EINVAL;
-    size_t off[6];
+    size_t off[W_N];
     if (state_bytes) *state_bytes = 3 * state_slot_bytes(c);
     if (work_bytes) *work_bytes = work_layout(c, off);
     return GPM_OK;
@@ -211,19 +231,26 @@ gpm_status gpm_bind(gpm_ctx *c, void *state, void *work)
 {
     if (!c || !state || !work) return GPM_EINVAL;
     if (((uintptr_t)state % kAlign) || ((uintptr_t)work % kAlign)) return fail(c, GPM_EINVAL, "buffers must be 256-byte aligned");
-    size_t off[6];
+    size_t off[W_N];
     const size_t wbytes = work_layout(c, off);
     c->state = (char *)state;
     c->work = (char *)work;
-    c->order = (uint8_t *)(c->work + off[0]);
-    c->stamp = (unsigned *)(c->work + off[1]);
-    c->lists[0] = (int *)(c->work + off[2]);
-    c->lists[1] = (int *)(c->work + off[3]);
-    c->aff = (int *)(c->work + off[4]);
-    c->ctl = (Ctl *)(c->work + off[5]);
-    c->partial = (double *)(c->work + align_up(off[5] + sizeof(Ctl)));
+    c->order = (uint8_t *)(c->work + off[W_ORDER]);
+    c->cstamp = (unsigned *)(c->work + off[W_CSTAMP]);
+    c->fstamp = (unsigned *)(c->work + off[W_FSTAMP]);
+    c->flist[0] = (int *)(c->work + off[W_FL0]);
+    c->flist[1] = (int *)(c->work + off[W_FL1]);
+    c->clist[0] = (int *)(c->work + off[W_CL0]);
+    c->clist[1] = (int *)(c->work + off[W_CL1]);
+    c->FX = c->work + off[W_FX];
+    c->GY = c->work + off[W_GY];
+    c->FXf = (uint8_t *)(c->work + off[W_FXF]);
+    c->GYf = (uint8_t *)(c->work + off[W_GYF]);
+    c->ctl = (Ctl *)(c->work + off[W_CTL]);
+    c->partial = (double *)(c->work + off[W_PART]);
     c->cur = 0;
     c->pass = 0;
+    c->fresh_ctl = true;
     HIPCHK(c, hipMemsetAsync(c->work, 0, wbytes, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return GPM_OK;
@@ -338,6 +365,40 @@ static void fill_args(const gpm_ctx *c, const Weights<real> &W, StageArgs<real> 
     A.W = W;
     A.dt = &c->ctl->dt;
     A.order = c->order;
+    A.FX = (real *)c->FX;
+    A.GY = (real *)c->GY;
+    A.FXf = c->FXf;
+    A.GYf = c->GYf;
+    A.cstamp = c->cstamp;
+    A.fstamp = c->fstamp;
+    for (int r = 0; r < 4; ++r) A.next[r] = c->next[r];
+}
+
+// Claim stamps grow monotonically; the stamp arrays are cleared at the start of a
+// stage when fewer than a stage's worth of stamps is left before the wrap.
+static gpm_status stamps_for_stage(gpm_ctx *c)
+{
+    if (c->pass >= 0xffffffffu - (unsigned)(2 * kMaxPasses + 8)) {
+        HIPCHK(c, hipMemsetAsync(c->cstamp, 0, 4 * c->ncell, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->fstamp, 0, 4 * (nfaces_x(c) + nfaces_y(c)), c->stream));
+        c->pass = 0;
+    }
+    return GPM_OK;
+}
+
+static gpm_status next_stamp(gpm_ctx *c, unsigned *out)
+{
+    *out = ++c->pass;
+    return GPM_OK;
+}
+
+static gpm_status level_counts(gpm_ctx *c)
+{
+    LevIdx li;
+    for (int r = 0; r < 4; ++r) li.v[r] = c->levidx[r];
+    hipError_t e = launch_level_hist(c->order, c->ncell, li, c->ctl, c->stream);
+    if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("level histogram: ") + hipGetErrorString(e));
+    return GPM_OK;
 }
 
 template <typename real>
@@ -349,56 +410,89 @@ static gpm_status run_stage(gpm_ctx *c, const Weights<real> &W, int s, const voi
     A.Un = (const real *)Un;
     A.Us = (const real *)Us;
     A.Uout = (real *)Uout;
-    hipError_t e = launch_reset(c->ctl, c->levidx[c->top], (unsigned long long)c->ncell, c->stream);
+    const int nzero = c->fresh_ctl ? kMaxPasses + 2 : (c->last_npass + 3 < kMaxPasses + 2 ? c->last_npass + 3 : kMaxPasses + 2);
+    hipError_t e = launch_reset(c->ctl, nzero, c->stream);
     if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("reset: ") + hipGetErrorString(e));
-    A.list_out = c->lists[0];
-    A.count_out = &c->ctl->nlist[0];
-    e = launch_first_pass<real>(A, c->stream);
+    c->fresh_ctl = false;
+
+    // evaluation 0 (first pass) claims the faces and cells of cascade pass 1
+    gpm_status st = stamps_for_stage(c);
+    if (st != GPM_OK) return st;
+    PassOut P;
+    st = next_stamp(c, &P.stamp);
+    if (st != GPM_OK) return st;
+    P.flist = c->flist[1];
+    P.clist = c->clist[1];
+    P.fcount = &c->ctl->nface[1];
+    P.ccount = &c->ctl->ncell[1];
+    P.tcount = &c->ctl->ntroub[0];
+    hipEvent_t *ev = nullptr;
+    if (c->instrument) {
+        while (c->evs.size() < 3 * (c->nev_used + 1)) {
+            hipEvent_t x;
+            HIPCHK(c, hipEventCreate(&x));
+            c->evs.push_back(x);
+        }
+        ev = &c->evs[3 * c->nev_used];
+        ++c->nev_used;
+        HIPCHK(c, hipEventRecord(ev[0], c->stream));
+    }
+    e = launch_first_pass<real>(A, P, c->stream);
     if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("first pass: ") + hipGetErrorString(e));
+    if (ev) HIPCHK(c, hipEventRecord(ev[1], c->stream));
 
     // cascade passes, queued in batches and gated on the device counts
-    int nb_rec = (int)((c->ncell + 63) / 64);
-    if (nb_rec > 2048) nb_rec = 2048;
-    int nb_low = (int)((c->ncell + 255) / 256);
-    if (nb_low > 512) nb_low = 512;
-    LowerArgsHost L;
-    L.order = c->order;
-    L.stamp = c->stamp;
-    L.levcnt = c->ctl->levcnt;
-    L.aff = c->aff;
-    L.nx = c->nx;
-    L.ny = c->ny;
-    L.bcx = c->grid.bc[0];
-    L.bcy = c->grid.bc[1];
-    for (int r = 0; r < 4; ++r) { L.next[r] = c->next[r]; L.levidx[r] = c->levidx[r]; }
-    L.nblocks = nb_low;
-    int k = 0;
+    int nb = (int)((c->ncell + 63) / 64);
+    if (nb > 512) nb = 512;
+    int k = 1;  // next cascade pass
+    int batch = c->passes_per_check;
     for (;;) {
-        HIPCHK(c, hipMemcpyAsync(c->pinned, &c->ctl->nlist[k], sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->pinned, &c->ctl->ntroub[k - 1], sizeof(int), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         if (*c->pinned == 0) break;
-        if (k + c->passes_per_check > kMaxPasses) {
-            c->last_npass = k;
+        if (*c->pinned <= c->tail_threshold) {
+            // few troubled cells: finish in one workgroup without host round trips
+            const int kend = kMaxPasses;
+            const unsigned stamp0 = c->pass + 1;
+            c->pass += (unsigned)(kend - k) + 1;
+            e = launch_cascade_tail<real>(A, c->flist, c->clist, c->ctl, k, kend, stamp0, c->stream);
+            if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("cascade tail: ") + hipGetErrorString(e));
+            HIPCHK(c, hipMemcpyAsync(c->pinned, &c->ctl->tail_end, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            k = *c->pinned;
+            if (k >= kend) {
+                c->last_npass = kend - 1;
+                return fail(c, GPM_ENOTCONV, "MOOD loop exceeded the pass limit");
+            }
+            break;
+        }
+        if (k + batch > kMaxPasses) {
+            c->last_npass = k - 1;
             return fail(c, GPM_ENOTCONV, "MOOD loop exceeded the pass limit");
         }
-        for (int b = 0; b < c->passes_per_check; ++b, ++k) {
-            if (c->pass == 0xffffffffu) {
-                HIPCHK(c, hipMemsetAsync(c->stamp, 0, 4 * c->ncell, c->stream));
-                c->pass = 0;
-            }
-            L.pass = ++c->pass;
-            L.list_in = c->lists[k & 1];
-            L.count_in = &c->ctl->nlist[k];
-            L.count_aff = &c->ctl->naff[k];
-            e = launch_cascade_lower(L, c->stream);
-            if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("cascade lower: ") + hipGetErrorString(e));
-            A.list_out = c->lists[(k + 1) & 1];
-            A.count_out = &c->ctl->nlist[k + 1];
-            e = launch_cascade_recompute<real>(A, c->aff, &c->ctl->naff[k], nb_rec, c->stream);
-            if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("cascade recompute: ") + hipGetErrorString(e));
+        const int nbatch = batch;
+        if (k > 4 * c->passes_per_check && batch < 64) batch *= 2;  // long cascades: fewer host checks
+        for (int b = 0; b < nbatch; ++b, ++k) {
+            st = next_stamp(c, &P.stamp);
+            if (st != GPM_OK) return st;
+            P.flist = c->flist[(k + 1) & 1];
+            P.clist = c->clist[(k + 1) & 1];
+            P.fcount = &c->ctl->nface[k + 1];
+            P.ccount = &c->ctl->ncell[k + 1];
+            P.tcount = &c->ctl->ntroub[k];
+            e = launch_cascade_pass<real>(A, c->flist[k & 1], &c->ctl->nface[k], c->clist[k & 1], &c->ctl->ncell[k],
+                                          P, nb, c->stream);
+            if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("cascade pass: ") + hipGetErrorString(e));
         }
     }
-    c->last_npass = k;
+    c->last_npass = k - 1;
+    if (ev) {
+        st = level_counts(c);
+        if (st != GPM_OK) return st;
+        e = launch_stats(c->ctl, c->last_npass, 0, c->stream);
+        if (e != hipSuccess) return fail(c, GPM_EHIP, hipGetErrorString(e));
+        HIPCHK(c, hipEventRecord(ev[2], c->stream));
+    }
     return GPM_OK;
 }
 
@@ -441,17 +535,19 @@ gpm_status gpm_troubled_counts(gpm_ctx *c, long long counts[4], int *mood_iters)
 {
     if (!c) return GPM_EINVAL;
     if (!c->state) return fail(c, GPM_ESTATE, "not bound");
+    gpm_status st = level_counts(c);
+    if (st != GPM_OK) return st;
     unsigned long long lc[4];
     HIPCHK(c, hipMemcpyAsync(lc, c->ctl->levcnt, sizeof(lc), hipMemcpyDeviceToHost, c->stream));
-    std::vector<int> nl(c->last_npass + 1);
-    HIPCHK(c, hipMemcpyAsync(nl.data(), c->ctl->nlist, sizeof(int) * nl.size(), hipMemcpyDeviceToHost, c->stream));
+    std::vector<int> nc(c->last_npass + 2);
+    HIPCHK(c, hipMemcpyAsync(nc.data(), c->ctl->ncell, sizeof(int) * nc.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (counts)
         for (int l = 0; l < 4; ++l) counts[l] = (long long)lc[l];
     if (mood_iters) {
         int it = 1;
-        for (size_t k = 0; k < nl.size(); ++k)
-            if (nl[k] > 0) ++it;
+        for (size_t k = 1; k < nc.size(); ++k)
+            if (nc[k] > 0) ++it;
         *mood_iters = it;
     }
     return GPM_OK;
@@ -487,6 +583,47 @@ gpm_status gpm_totals(gpm_ctx *c, double totals[4])
     if (!c) return GPM_EINVAL;
     if (!c->state) return fail(c, GPM_ESTATE, "not bound");
     return gpm_totals_dev(c, slot_ptr(c, c->cur), totals);
+}
+
+gpm_status gpm_instrument(gpm_ctx *c, int enable)
+{
+    if (!c) return GPM_EINVAL;
+    if (!c->state) return fail(c, GPM_ESTATE, "not bound");
+    if (enable) {
+        hipError_t e = launch_stats(c->ctl, 0, 1, c->stream);
+        if (e != hipSuccess) return fail(c, GPM_EHIP, hipGetErrorString(e));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->nev_used = 0;
+    }
+    c->instrument = enable != 0;
+    return GPM_OK;
+}
+
+gpm_status gpm_instrument_read(gpm_ctx *c, double *first_pass_ms, long long *first_pass_launches,
+                               double *cascade_ms, long long *stages, long long level_cells[4],
+                               long long *mood_iters)
+{
+    if (!c) return GPM_EINVAL;
+    if (!c->state) return fail(c, GPM_ESTATE, "not bound");
+    unsigned long long acc[6];
+    HIPCHK(c, hipMemcpyAsync(acc, c->ctl->acc_lev, sizeof(acc), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double fp = 0.0, cm = 0.0;
+    for (size_t k = 0; k < c->nev_used; ++k) {
+        float a = 0.f, b = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&a, c->evs[3 * k], c->evs[3 * k + 1]));
+        HIPCHK(c, hipEventElapsedTime(&b, c->evs[3 * k + 1], c->evs[3 * k + 2]));
+        fp += a;
+        cm += b;
+    }
+    if (first_pass_ms) *first_pass_ms = fp;
+    if (first_pass_launches) *first_pass_launches = (long long)c->nev_used;
+    if (cascade_ms) *cascade_ms = cm;
+    if (stages) *stages = (long long)c->nev_used;
+    if (level_cells)
+        for (int l = 0; l < 4; ++l) level_cells[l] = (long long)acc[l];
+    if (mood_iters) *mood_iters = (long long)acc[4];
+    return GPM_OK;
 }
 
 }  // extern "C"

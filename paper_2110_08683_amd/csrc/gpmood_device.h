@@ -27,7 +27,7 @@
 
 namespace gpm {
 
-constexpr int kMaxPasses = 512;
+constexpr int kMaxPasses = 16384;
 
 // Per-radius quarter-basis weights and Gauss weights, plus the u2 curvature weights.
 template <typename real>
@@ -44,27 +44,51 @@ struct StageArgs {
     const real *Un;
     const real *Us;
     real *Uout;
-    const double *dt;  // device scalar
-    uint8_t *order;    // final GP radius per cell
-    int *list_out;     // troubled cells of this evaluation
-    int *count_out;    // their number
+    const double *dt;     // device scalar
+    uint8_t *order;       // GP radius per cell (final after the stage)
+    // face fluxes of this stage: x faces [4][ny][nx+1] (face i between cells i-1
+    // and i), y faces [4][ny+1][nx]; per face, bit 0 / bit 1: the left (lower) /
+    // right (upper) reconstructed state has a non-finite density or pressure
+    real *FX;
+    real *GY;
+    uint8_t *FXf;
+    uint8_t *GYf;
+    unsigned *cstamp;     // claim stamps of cells [nx*ny] and faces [NFX + NFY]
+    unsigned *fstamp;
     int nx, ny, bcx, bcy;
-    int s;             // RK stage 0..2
-    int rows;          // rows per wavefront march (first pass)
-    int top;           // top radius
+    int s;                // RK stage 0..2
+    int rows;             // rows per wavefront march (first pass)
+    int top;              // top radius
     unsigned flags;
+    int next[4];          // next radius of the cascade after radius r
     real dx, dy, gamma, sigma_v, sigma_p, plat_thr, delta;
     Weights<real> W;
 };
 
+// Outputs of one evaluation: the troubled count, and the faces and cells that the
+// next cascade pass recomputes (claimed with `stamp`, unique per evaluation).
+struct PassOut {
+    int *flist;
+    int *fcount;
+    int *clist;
+    int *ccount;
+    int *tcount;
+    unsigned stamp;
+};
+
 // Device control block (lives in the workspace).
 struct Ctl {
-    int nlist[kMaxPasses + 2];  // troubled count of evaluation k (0: first pass)
-    int naff[kMaxPasses + 2];   // cells recomputed by cascade pass k
+    int nface[kMaxPasses + 2];   // faces recomputed by cascade pass k (k >= 1)
+    int ncell[kMaxPasses + 2];   // cells re-evaluated by cascade pass k (k >= 1)
+    int ntroub[kMaxPasses + 2];  // troubled cells of evaluation k (0: first pass)
     unsigned long long levcnt[4];
     unsigned long long lam_bits;
     double dt;
     double totals[4];
+    unsigned long long acc_lev[4];  // instrumentation: summed final-order counts
+    unsigned long long acc_iters;   // summed MOOD iterations
+    unsigned long long acc_stages;
+    int tail_end;                   // first pass index the single-block tail did not need
 };
 
 // ------------------------------------------------------------------ helpers
@@ -301,6 +325,43 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+// Add the number of flagged lanes of the wavefront to *count (one atomic per
+// wavefront).  Must be reached by all 64 lanes of the wavefront together.
+__device__ __forceinline__ void wave_count(bool flag, int *count)
+{
+    const unsigned long long mask = __ballot(flag);
+    if (mask != 0ull && (threadIdx.x & 63) == 0) atomicAdd(count, (int)__popcll(mask));
+}
+
+// Append up to K flagged values per lane to a list with one atomic per wavefront.
+// Must be reached by all 64 lanes of the wavefront together.
+template <int K>
+__device__ __forceinline__ void wave_append_multi(const bool (&flag)[K], const int (&val)[K], int *list, int *count)
+{
+    unsigned long long m[K];
+    int tot = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        m[k] = __ballot(flag[k]);
+        tot += (int)__popcll(m[k]);
+    }
+    if (tot == 0) return;
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    if (lane == 0) base = atomicAdd(count, tot);
+    base = __shfl(base, 0);
+    const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (flag[k]) list[base + __popcll(m[k] & below)] = val[k];
+        base += (int)__popcll(m[k]);
+    }
+}
+
+struct LevIdx {
+    int v[4];  // cascade level of radius r
+};
 
 // Append flagged cells of the wavefront to a list (ballot + prefix, one atomic per
 // wave).  Must be reached by all 64 lanes of the wavefront together.

@@ -10,14 +10,18 @@
 // exchanges x-face states with its right neighbour by a lane shuffle, evaluates
 // HLLC on its own x face, and evaluates the y face below it against the y+ states
 // it kept from row j-1.  Cell (i, j-1) is then complete: candidate, detection,
-// RK combine and the wavefront-ballot append of troubled cells.  No block
-// barrier is needed anywhere: each wavefront only reads LDS it wrote itself.
+// RK combine.  Every face flux (and its Riemann-state CAD flags) is stored for the
+// cascade.  A troubled cell takes the next scheme of the cascade at once and claims
+// its four faces and the five cells whose candidates they change.  No block
+// barrier is needed: each wavefront only reads LDS it wrote itself.
 //
-// Cascade (k_cascade_lower, k_cascade_recompute): troubled cells move to the next
-// scheme of the cascade; the troubled cells and their face neighbours are
-// recomputed with EDP_1 face orders and re-detected; the new troubled cells are
-// appended to the next list.  Both kernels read their item count from device
-// memory and return at once when it is zero, so several passes can be queued
+// Cascade pass k (k_faces, then k_cells): recompute the claimed faces at their new
+// EDP_1 order (min of the two cells' radii), then re-evaluate the claimed cells
+// from the stored fluxes, re-detect, lower the troubled ones and claim the faces
+// and cells of pass k+1.  Each face flux is computed once and read by both of its
+// cells, so the update stays exactly conservative.  Every list holds each face or
+// cell at most once (claim stamps), and both kernels read their item count from
+// device memory and return at once when it is zero, so passes can be queued
 // without a host round trip.
 #include "gpmood_device.h"
 #include "gpmood_launch.h"
@@ -35,8 +39,48 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
     return (b & 7) * per + (b >> 3);
 }
 
+// Claims after lowering cell (i, j) (act = this lane lowered it): its four faces
+// (and, on periodic axes, the duplicate copy of a boundary face) are listed for
+// recomputation in the next pass, and the cell with its four face neighbours for
+// re-evaluation.  A stamp per face and per cell keeps each list duplicate-free.
+// Must be reached by all 64 lanes of the wavefront together.
+template <typename real>
+__device__ __forceinline__ void claim_after_lowering(const StageArgs<real> &A, const PassOut &P, int i, int j,
+                                                     bool act)
+{
+    const int nx = A.nx, ny = A.ny;
+    const int nfx = (nx + 1) * ny;
+    // faces: x faces i, i+1 of row j; y faces j, j+1 of column i; periodic duplicates
+    int fid[6];
+    bool fok[6];
+    fid[0] = j * (nx + 1) + i;
+    fid[1] = j * (nx + 1) + i + 1;
+    fid[2] = nfx + j * nx + i;
+    fid[3] = nfx + (j + 1) * nx + i;
+    fok[0] = fok[1] = fok[2] = fok[3] = act;
+    fid[4] = i == 0 ? j * (nx + 1) + nx : j * (nx + 1);          // copy of face 0 / face nx
+    fok[4] = act && A.bcx == 0 && (i == 0 || i == nx - 1);
+    fid[5] = j == 0 ? nfx + ny * nx + i : nfx + i;                // copy of face 0 / face ny
+    fok[5] = act && A.bcy == 0 && (j == 0 || j == ny - 1);
+    bool fmine[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) fmine[k] = fok[k] && atomicMax(&A.fstamp[fid[k]], P.stamp) < P.stamp;
+    const int di[5] = {0, -1, 1, 0, 0}, dj[5] = {0, 0, 0, -1, 1};
+    int cid[5];
+    bool cmine[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int ii = i + di[k], jj = j + dj[k];
+        const bool inside = (A.bcx == 0 || (ii >= 0 && ii < nx)) && (A.bcy == 0 || (jj >= 0 && jj < ny));
+        cid[k] = (act && inside) ? remap(jj, ny, A.bcy) * nx + remap(ii, nx, A.bcx) : 0;
+        cmine[k] = act && inside && atomicMax(&A.cstamp[cid[k]], P.stamp) < P.stamp;
+    }
+    wave_append_multi(fmine, fid, P.flist, P.fcount);
+    wave_append_multi(cmine, cid, P.clist, P.ccount);
+}
+
 template <typename real, int RT, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_first_pass(const StageArgs<real> A)
+__global__ __launch_bounds__(64 * WPB) void k_first_pass(const StageArgs<real> A, const PassOut P)
 {
     constexpr int q = nodes_of(RT);
     constexpr int NQ = kNQ[RT];
@@ -53,8 +97,10 @@ __global__ __launch_bounds__(64 * WPB) void k_first_pass(const StageArgs<real> A
     const int x0 = sx * 62, y0 = sy * T;
     const int yend = min(y0 + T, ny);
     const int i = x0 - 1 + lane;
-    const bool own = lane >= 1 && lane <= 62 && i < nx;
+    const bool own_col = lane >= 1 && lane <= 62 && i < nx;
+    const bool own = own_col;
     const size_t plane = (size_t)nx * ny;
+    const size_t nfx = (size_t)(nx + 1) * ny, nfy = (size_t)nx * (ny + 1);
 
     const int sc0 = remap(x0 - 4 + lane, nx, A.bcx);
     const bool has1 = lane < LW - 64;
@@ -133,6 +179,13 @@ __global__ __launch_bounds__(64 * WPB) void k_first_pass(const StageArgs<real> A
 #pragma unroll
                 for (int v = 0; v < 4; ++v) F[v] = fma(w, f[v], F[v]);
             }
+            // store face i+1/2: lanes of the strip's own cells, plus the domain's left face
+            if ((own || (lane == 0 && x0 == 0)) && j < ny) {
+                const size_t fi = (size_t)j * (nx + 1) + (i + 1);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) A.FX[v * nfx + fi] = F[v];
+                A.FXf[fi] = (uint8_t)((rsx ? 1 : 0) | (badNb ? 2 : 0));
+            }
             const int badm = __shfl_up((int)badNb, 1);
             rsx = rsx || (badm != 0);
 #pragma unroll
@@ -152,6 +205,14 @@ __global__ __launch_bounds__(64 * WPB) void k_first_pass(const StageArgs<real> A
                 const real w = node_weight<RT>(A.W, k);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) G[v] = fma(w, f[v], G[v]);
+            }
+            // store face j-1/2 (y index j): the segment's faces above its first row,
+            // plus the domain's bottom face
+            if (own_col && (j > y0 || y0 == 0)) {
+                const size_t gi = (size_t)j * nx + i;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) A.GY[v * nfy + gi] = G[v];
+                A.GYf[gi] = (uint8_t)((badLy ? 1 : 0) | (badRy ? 2 : 0));
             }
             if (j - 1 >= y0) {
                 // cell (i, j-1) is complete
@@ -173,9 +234,10 @@ __global__ __launch_bounds__(64 * WPB) void k_first_pass(const StageArgs<real> A
                         const real un = A.s == 0 ? real(0) : A.Un[v * plane + c];
                         A.Uout[v * plane + c] = combine(A.s, un, ust[v]);
                     }
-                    A.order[c] = (uint8_t)RT;
+                    A.order[c] = (uint8_t)(tr ? A.next[RT] : RT);
                 }
-                wave_append(tr, jr * nx + i, A.list_out, A.count_out);
+                wave_count(tr, P.tcount);
+                claim_after_lowering(A, P, i, jr, tr);
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) Gprev[v] = G[v];
@@ -194,64 +256,6 @@ __global__ __launch_bounds__(64 * WPB) void k_first_pass(const StageArgs<real> A
 }
 
 // ------------------------------------------------------------- cascade pass
-struct LowerArgs {
-    const int *list_in;
-    const int *count_in;
-    int *aff;
-    int *count_aff;
-    uint8_t *order;
-    unsigned *stamp;
-    unsigned long long *levcnt;
-    int nx, ny, bcx, bcy;
-    unsigned pass;
-    int ncap;       // number of cells: upper bound of every list
-    int next[4];    // next radius after r
-    int levidx[4];  // cascade level of radius r
-};
-
-__device__ __forceinline__ void claim(const LowerArgs &A, int c, bool valid)
-{
-    bool mine = false;
-    if (valid) mine = atomicMax(&A.stamp[c], A.pass) < A.pass;
-    wave_append(mine, c, A.aff, A.count_aff);
-}
-
-__global__ __launch_bounds__(256) void k_cascade_lower(const LowerArgs A)
-{
-    int n = *A.count_in;
-    n = n < A.ncap ? n : A.ncap;  // a list never holds more than one entry per cell
-    if (n <= 0) return;
-    const int stride = gridDim.x * blockDim.x;
-    const int nround = (n + stride - 1) / stride;
-    for (int r = 0; r < nround; ++r) {
-        const int idx = r * stride + blockIdx.x * blockDim.x + threadIdx.x;
-        const bool valid = idx < n;
-        int c = 0, i = 0, j = 0;
-        if (valid) {
-            c = A.list_in[idx];
-            const int o = A.order[c];
-            const int o2 = A.next[o];
-            A.order[c] = (uint8_t)o2;
-            atomicAdd(&A.levcnt[A.levidx[o]], (unsigned long long)-1ll);
-            atomicAdd(&A.levcnt[A.levidx[o2]], 1ull);
-            i = c % A.nx;
-            j = c / A.nx;
-        }
-        // the cell and its four face neighbours (boundary ghosts map back into the grid)
-        claim(A, c, valid);
-        const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int ii = i + di[k], jj = j + dj[k];
-            const bool inside_x = A.bcx == 0 || (ii >= 0 && ii < A.nx);
-            const bool inside_y = A.bcy == 0 || (jj >= 0 && jj < A.ny);
-            const bool ok = valid && inside_x && inside_y;
-            const int cc = ok ? remap(jj, A.ny, A.bcy) * A.nx + remap(ii, A.nx, A.bcx) : 0;
-            claim(A, cc, ok);
-        }
-    }
-}
-
 // Face states of the cell centred at (ci, cj) (ghost positions allowed) for
 // direction DIR at radius R, read from global memory with boundary remaps.
 template <typename real, int R, int DIR>
@@ -279,8 +283,8 @@ __device__ __forceinline__ void cell_states(const StageArgs<real> &A, int ci, in
     }
 }
 
-// Flux through the face between cell L = (iL, jL) and cell R (its + neighbour
-// along DIR) at radius Rf; same node order and sums as the first pass.
+// Flux through the face between cell L = (iL, jL) and its + neighbour along DIR at
+// radius Rf, summed over the face's Gauss nodes (eq. (fvm_F)).
 template <typename real, int Rf, int DIR>
 __device__ __forceinline__ void face_flux_t(const StageArgs<real> &A, int iL, int jL, real (&F)[4],
                                             bool &badL, bool &badR)
@@ -306,72 +310,86 @@ __device__ __forceinline__ void face_flux_t(const StageArgs<real> &A, int iL, in
     }
 }
 
-// Face flux at a runtime radius.  Everything is inlined into the kernel: device
-// function calls are avoided on purpose (a call to a large function also needs
-// the scratch stack, and long branches inside such a callee can clobber its return
-// address register).
+// Everything is inlined into the kernels: device-function calls are avoided on
+// purpose (a large callee needs a scratch stack, and long branches inside such a
+// callee have been seen to reuse its return-address register).
 template <typename real, int DIR>
 __device__ __forceinline__ void face_flux(const StageArgs<real> &A, int Rf, int iL, int jL, real (&F)[4],
                                           bool &badL, bool &badR)
 {
+    // faces recomputed by the cascade are never at the top order of GP-MOOD7/5,
+    // but a top order of 1..3 is allowed in general
     if (Rf == 3) face_flux_t<real, 3, DIR>(A, iL, jL, F, badL, badR);
     else if (Rf == 2) face_flux_t<real, 2, DIR>(A, iL, jL, F, badL, badR);
     else if (Rf == 1) face_flux_t<real, 1, DIR>(A, iL, jL, F, badL, badR);
     else face_flux_t<real, 0, DIR>(A, iL, jL, F, badL, badR);
 }
 
+// Cascade pass, part 1: recompute the listed faces at their EDP_1 order (the
+// smaller radius of the two cells), one thread per face.
 template <typename real>
-__global__ __launch_bounds__(64) void k_cascade_recompute(const StageArgs<real> A, const int *aff,
-                                                          const int *count_aff, int ncap)
+__device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const int *flist, int n, int t0, int stride)
 {
-    int n = *count_aff;
-    n = n < ncap ? n : ncap;  // a list never holds more than one entry per cell
-    if (n <= 0) return;
-    const int stride = gridDim.x * blockDim.x;
-    const int nround = (n + stride - 1) / stride;
+    const int nx = A.nx, ny = A.ny;
+    const int nfx = (nx + 1) * ny, nfy = nx * (ny + 1);
+    for (int idx = t0; idx < n; idx += stride) {
+        const int f = flist[idx];
+        real F[4];
+        bool bl = false, br = false;
+        if (f < nfx) {
+            const int j = f / (nx + 1), i = f - j * (nx + 1);  // between cells i-1 and i
+            const int oL = A.order[(size_t)j * nx + remap(i - 1, nx, A.bcx)];
+            const int oR = A.order[(size_t)j * nx + remap(i, nx, A.bcx)];
+            face_flux<real, 0>(A, min(oL, oR), i - 1, j, F, bl, br);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) A.FX[(size_t)v * nfx + f] = F[v];
+            A.FXf[f] = (uint8_t)((bl ? 1 : 0) | (br ? 2 : 0));
+        } else {
+            const int g = f - nfx;
+            const int j = g / nx, i = g - j * nx;  // between cells (i, j-1) and (i, j)
+            const int oL = A.order[(size_t)remap(j - 1, ny, A.bcy) * nx + i];
+            const int oR = A.order[(size_t)remap(j, ny, A.bcy) * nx + i];
+            face_flux<real, 1>(A, min(oL, oR), i, j - 1, F, bl, br);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) A.GY[(size_t)v * nfy + g] = F[v];
+            A.GYf[g] = (uint8_t)((bl ? 1 : 0) | (br ? 2 : 0));
+        }
+    }
+}
+
+// Cascade pass, part 2: re-evaluate the listed cells from the stored fluxes,
+// re-detect, lower the troubled ones and claim the faces and cells of the next
+// pass.  Detection reads no other cell's order, so lowering in place is safe.
+// The number of rounds is the same for all lanes (wavefront-wide list appends).
+template <typename real>
+__device__ __forceinline__ void cells_phase(const StageArgs<real> &A, const int *clist, int n, int t0, int stride,
+                                            const PassOut &P)
+{
     const int nx = A.nx, ny = A.ny;
     const size_t plane = (size_t)nx * ny;
+    const size_t nfx = (size_t)(nx + 1) * ny, nfy = (size_t)nx * (ny + 1);
+    const int nround = (n + stride - 1) / stride;
     const real dt = (real)(*A.dt);
     for (int r = 0; r < nround; ++r) {
-        const int idx = r * stride + blockIdx.x * blockDim.x + threadIdx.x;
+        const int idx = r * stride + t0;
         const bool valid = idx < n;
         bool tr = false;
-        int c = 0;
+        int i = 0, j = 0;
         if (valid) {
-            c = aff[idx];
-            const int i = c % nx, j = c / nx;
+            const int c = clist[idx];
+            i = c % nx;
+            j = c / nx;
             const int o = A.order[c];
-            const int oW = A.order[(size_t)j * nx + remap(i - 1, nx, A.bcx)];
-            const int oE = A.order[(size_t)j * nx + remap(i + 1, nx, A.bcx)];
-            const int oS = A.order[(size_t)remap(j - 1, ny, A.bcy) * nx + i];
-            const int oN = A.order[(size_t)remap(j + 1, ny, A.bcy) * nx + i];
-            real Fm[4], Fp[4], Gm[4], Gp[4];
-            bool rs = false;
-#pragma unroll 1
-            for (int f = 0; f < 4; ++f) {
-                real F[4];
-                bool bl = false, br = false;
-                if (f == 0) face_flux<real, 0>(A, min(o, oW), i - 1, j, F, bl, br);
-                else if (f == 1) face_flux<real, 0>(A, min(o, oE), i, j, F, bl, br);
-                else if (f == 2) face_flux<real, 1>(A, min(o, oS), i, j - 1, F, bl, br);
-                else face_flux<real, 1>(A, min(o, oN), i, j, F, bl, br);
-                // the cell owns the right state of its - faces and the left state of its + faces
-                rs = rs || ((f & 1) ? bl : br);
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    if (f == 0) Fm[v] = F[v];
-                    else if (f == 1) Fp[v] = F[v];
-                    else if (f == 2) Gm[v] = F[v];
-                    else Gp[v] = F[v];
-                }
-            }
+            const size_t fxm = (size_t)j * (nx + 1) + i, gym = (size_t)j * nx + i;
             real ust[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const real us = A.Us[v * plane + c];
-                const real dFx = Fp[v] - Fm[v];
-                ust[v] = us - dt * (dFx / A.dx + (Gp[v] - Gm[v]) / A.dy);
+                const real dFx = A.FX[v * nfx + fxm + 1] - A.FX[v * nfx + fxm];
+                ust[v] = us - dt * (dFx / A.dx + (A.GY[v * nfy + gym + nx] - A.GY[v * nfy + gym]) / A.dy);
             }
+            // the cell's own states: right state of its - faces, left state of its + faces
+            const bool rs = (A.FXf[fxm] & 2) || (A.FXf[fxm + 1] & 1) || (A.GYf[gym] & 2) || (A.GYf[gym + nx] & 1);
             auto nb = [&](int di, int dj, int v) {
                 return A.Us[v * plane + (size_t)remap(j + dj, ny, A.bcy) * nx + remap(i + di, nx, A.bcx)];
             };
@@ -381,20 +399,131 @@ __global__ __launch_bounds__(64) void k_cascade_recompute(const StageArgs<real> 
                 const real un = A.s == 0 ? real(0) : A.Un[v * plane + c];
                 A.Uout[v * plane + c] = combine(A.s, un, ust[v]);
             }
+            if (tr) A.order[c] = (uint8_t)A.next[o];
         }
-        wave_append(tr, c, A.list_out, A.count_out);
+        wave_count(tr, P.tcount);
+        claim_after_lowering(A, P, i, j, tr);
     }
 }
 
-// -------------------------------------------------------- small kernels
-__global__ void k_reset(Ctl *ctl, int top_level, unsigned long long ncell)
+template <typename real>
+__global__ __launch_bounds__(64) void k_faces(const StageArgs<real> A, const int *flist, const int *fcount)
 {
-    const int t = threadIdx.x;
-    for (int k = t; k < kMaxPasses + 2; k += blockDim.x) {
-        ctl->nlist[k] = 0;
-        ctl->naff[k] = 0;
+    const int cap = (A.nx + 1) * A.ny + A.nx * (A.ny + 1);
+    int n = *fcount;
+    n = n < cap ? n : cap;  // a list holds each face at most once
+    faces_phase(A, flist, n, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+template <typename real>
+__global__ __launch_bounds__(64) void k_cells(const StageArgs<real> A, const int *clist, const int *ccount,
+                                              const PassOut P)
+{
+    int n = *ccount;
+    n = n < A.nx * A.ny ? n : A.nx * A.ny;  // a list holds each cell at most once
+    if (n <= 0) return;
+    cells_phase(A, clist, n, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, P);
+}
+
+// The tail of a long cascade (few troubled cells per pass) in one workgroup:
+// passes k0, k0+1, ... run back to back with block barriers, until a pass has no
+// cell to re-evaluate (recorded in ctl->tail_end) or kend is reached.  Pass k's
+// claims use stamp0 + (k - k0).
+struct TailArgs {
+    int *flist[2];
+    int *clist[2];
+    Ctl *ctl;
+    int k0, kend;
+    unsigned stamp0;
+};
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_tail(const StageArgs<real> A, const TailArgs T)
+{
+    const int capf = (A.nx + 1) * A.ny + A.nx * (A.ny + 1), capc = A.nx * A.ny;
+    Ctl *ctl = T.ctl;
+    int k = T.k0;
+    for (; k < T.kend; ++k) {
+        __syncthreads();  // the previous pass's lists, counts and fluxes are complete
+        int nc = __hip_atomic_load(&ctl->ncell[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int nf = __hip_atomic_load(&ctl->nface[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        nc = nc < capc ? nc : capc;
+        nf = nf < capf ? nf : capf;
+        if (nc <= 0) break;  // same value in every thread: the block leaves together
+        faces_phase(A, T.flist[k & 1], nf, threadIdx.x, blockDim.x);
+        __syncthreads();
+        PassOut P;
+        P.flist = T.flist[(k + 1) & 1];
+        P.fcount = &ctl->nface[k + 1];
+        P.clist = T.clist[(k + 1) & 1];
+        P.ccount = &ctl->ncell[k + 1];
+        P.tcount = &ctl->ntroub[k];
+        P.stamp = T.stamp0 + (unsigned)(k - T.k0);
+        cells_phase(A, T.clist[k & 1], nc, threadIdx.x, blockDim.x, P);
     }
-    if (t < 4) ctl->levcnt[t] = t == top_level ? ncell : 0ull;
+    if (threadIdx.x == 0) ctl->tail_end = k;
+}
+
+// -------------------------------------------------------- small kernels
+__global__ void k_reset(Ctl *ctl, int nzero)
+{
+    for (int k = threadIdx.x; k < nzero && k < kMaxPasses + 2; k += blockDim.x) {
+        ctl->nface[k] = 0;
+        ctl->ncell[k] = 0;
+        ctl->ntroub[k] = 0;
+    }
+}
+
+// Histogram of the final cascade level of every cell (for statistics only).
+__global__ __launch_bounds__(256) void k_level_hist(const uint8_t *order, size_t ncell, const LevIdx levidx,
+                                                    unsigned long long *levcnt)
+{
+    __shared__ unsigned int h[4];
+    if (threadIdx.x < 4) h[threadIdx.x] = 0;
+    __syncthreads();
+    unsigned int loc[4] = {0, 0, 0, 0};
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < ncell; k += (size_t)gridDim.x * blockDim.x) {
+        const int r = order[k] & 3;
+        loc[0] += r == 0;
+        loc[1] += r == 1;
+        loc[2] += r == 2;
+        loc[3] += r == 3;
+    }
+    for (int r = 0; r < 4; ++r)
+        if (loc[r]) atomicAdd(&h[r], loc[r]);
+    __syncthreads();
+    if (threadIdx.x < 4 && h[threadIdx.x]) atomicAdd(&levcnt[levidx.v[threadIdx.x]], (unsigned long long)h[threadIdx.x]);
+}
+
+__global__ void k_zero_levcnt(Ctl *ctl)
+{
+    if (threadIdx.x < 4) ctl->levcnt[threadIdx.x] = 0ull;
+}
+
+// Instrumentation: add this stage's final-order counts and MOOD iterations
+// (1 + cascade passes that re-evaluated cells) to the accumulators.
+__global__ void k_stats_accum(Ctl *ctl, int npass, int reset)
+{
+    __shared__ unsigned long long cnt;
+    if (threadIdx.x == 0) cnt = 0ull;
+    __syncthreads();
+    if (reset) {
+        if (threadIdx.x < 4) ctl->acc_lev[threadIdx.x] = 0ull;
+        if (threadIdx.x == 0) {
+            ctl->acc_iters = 0ull;
+            ctl->acc_stages = 0ull;
+        }
+        return;
+    }
+    unsigned long long loc = 0;
+    for (int k = 1 + threadIdx.x; k <= npass && k < kMaxPasses + 2; k += blockDim.x) loc += ctl->ncell[k] > 0;
+    if (loc) atomicAdd(&cnt, loc);
+    __syncthreads();
+    if (threadIdx.x < 4) ctl->acc_lev[threadIdx.x] += ctl->levcnt[threadIdx.x];
+    if (threadIdx.x == 0) {
+        ctl->acc_iters += 1ull + cnt;
+        ctl->acc_stages += 1ull;
+    }
 }
 
 // max over cells of (|u_d| + c) / Delta_d in FP64, as the bit pattern of a
@@ -493,62 +622,65 @@ __global__ void k_totals_final(const double *partial, int nblk, double area, Ctl
 
 // ------------------------------------------------------------- launchers
 template <typename real, int RT>
-static hipError_t launch_first_pass_rt(const StageArgs<real> &A, hipStream_t st)
+static hipError_t launch_first_pass_rt(const StageArgs<real> &A, const PassOut &P, hipStream_t st)
 {
     constexpr int WPB = sizeof(real) == 8 ? 2 : 4;
     const int nstrip = (A.nx + 61) / 62, nseg = (A.ny + A.rows - 1) / A.rows;
     const int nwave = nstrip * nseg;
     const int nblk = (nwave + WPB - 1) / WPB;
-    hipLaunchKernelGGL((k_first_pass<real, RT, WPB>), dim3(nblk), dim3(64 * WPB), 0, st, A);
+    hipLaunchKernelGGL((k_first_pass<real, RT, WPB>), dim3(nblk), dim3(64 * WPB), 0, st, A, P);
     return hipGetLastError();
 }
 
 template <typename real>
-hipError_t launch_first_pass(const StageArgs<real> &A, hipStream_t st)
+hipError_t launch_first_pass(const StageArgs<real> &A, const PassOut &P, hipStream_t st)
 {
     switch (A.top) {
-    case 3: return launch_first_pass_rt<real, 3>(A, st);
-    case 2: return launch_first_pass_rt<real, 2>(A, st);
-    case 1: return launch_first_pass_rt<real, 1>(A, st);
+    case 3: return launch_first_pass_rt<real, 3>(A, P, st);
+    case 2: return launch_first_pass_rt<real, 2>(A, P, st);
+    case 1: return launch_first_pass_rt<real, 1>(A, P, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_cascade_lower(const LowerArgsHost &h, hipStream_t st)
+template <typename real>
+hipError_t launch_cascade_pass(const StageArgs<real> &A, const int *flist, const int *fcount, const int *clist,
+                               const int *ccount, const PassOut &P, int nblocks, hipStream_t st)
 {
-    LowerArgs A;
-    A.list_in = h.list_in;
-    A.count_in = h.count_in;
-    A.aff = h.aff;
-    A.count_aff = h.count_aff;
-    A.order = h.order;
-    A.stamp = h.stamp;
-    A.levcnt = h.levcnt;
-    A.nx = h.nx;
-    A.ny = h.ny;
-    A.bcx = h.bcx;
-    A.bcy = h.bcy;
-    A.pass = h.pass;
-    A.ncap = h.nx * h.ny;
-    for (int k = 0; k < 4; ++k) {
-        A.next[k] = h.next[k];
-        A.levidx[k] = h.levidx[k];
-    }
-    hipLaunchKernelGGL(k_cascade_lower, dim3(h.nblocks), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_faces<real>, dim3(nblocks), dim3(64), 0, st, A, flist, fcount);
+    hipLaunchKernelGGL(k_cells<real>, dim3(nblocks), dim3(64), 0, st, A, clist, ccount, P);
     return hipGetLastError();
 }
 
 template <typename real>
-hipError_t launch_cascade_recompute(const StageArgs<real> &A, const int *aff, const int *count_aff, int nblocks,
-                                    hipStream_t st)
+hipError_t launch_cascade_tail(const StageArgs<real> &A, int *const flist[2], int *const clist[2], Ctl *ctl, int k0,
+                               int kend, unsigned stamp0, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cascade_recompute<real>, dim3(nblocks), dim3(64), 0, st, A, aff, count_aff, A.nx * A.ny);
+    TailArgs T;
+    T.flist[0] = flist[0];
+    T.flist[1] = flist[1];
+    T.clist[0] = clist[0];
+    T.clist[1] = clist[1];
+    T.ctl = ctl;
+    T.k0 = k0;
+    T.kend = kend;
+    T.stamp0 = stamp0;
+    hipLaunchKernelGGL(k_tail<real>, dim3(1), dim3(256), 0, st, A, T);
     return hipGetLastError();
 }
 
-hipError_t launch_reset(Ctl *ctl, int top_level, unsigned long long ncell, hipStream_t st)
+hipError_t launch_reset(Ctl *ctl, int nzero, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, st, ctl, top_level, ncell);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, st, ctl, nzero);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_hist(const uint8_t *order, size_t ncell, const LevIdx &levidx, Ctl *ctl, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero_levcnt, dim3(1), dim3(64), 0, st, ctl);
+    size_t nblk = (ncell + 255) / 256;
+    if (nblk > 1024) nblk = 1024;
+    hipLaunchKernelGGL(k_level_hist, dim3((unsigned)nblk), dim3(256), 0, st, order, ncell, levidx, ctl->levcnt);
     return hipGetLastError();
 }
 
@@ -562,6 +694,12 @@ hipError_t launch_dt(const real *U, size_t ncell, double gamma, double dx, doubl
     hipLaunchKernelGGL(k_dt_reduce<real>, dim3((unsigned)nblk), dim3(256), 0, st, U, ncell, gamma, dx, dy,
                        &ctl->lam_bits);
     hipLaunchKernelGGL(k_dt_finalize, dim3(1), dim3(1), 0, st, ctl, cfl);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats(Ctl *ctl, int npass, int reset, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_stats_accum, dim3(1), dim3(256), 0, st, ctl, npass, reset);
     return hipGetLastError();
 }
 
@@ -580,10 +718,16 @@ hipError_t launch_totals(const real *U, size_t ncell, double area, double *parti
     return hipGetLastError();
 }
 
-template hipError_t launch_first_pass<float>(const StageArgs<float> &, hipStream_t);
-template hipError_t launch_first_pass<double>(const StageArgs<double> &, hipStream_t);
-template hipError_t launch_cascade_recompute<float>(const StageArgs<float> &, const int *, const int *, int, hipStream_t);
-template hipError_t launch_cascade_recompute<double>(const StageArgs<double> &, const int *, const int *, int, hipStream_t);
+template hipError_t launch_first_pass<float>(const StageArgs<float> &, const PassOut &, hipStream_t);
+template hipError_t launch_first_pass<double>(const StageArgs<double> &, const PassOut &, hipStream_t);
+template hipError_t launch_cascade_pass<float>(const StageArgs<float> &, const int *, const int *, const int *,
+                                               const int *, const PassOut &, int, hipStream_t);
+template hipError_t launch_cascade_pass<double>(const StageArgs<double> &, const int *, const int *, const int *,
+                                                const int *, const PassOut &, int, hipStream_t);
+template hipError_t launch_cascade_tail<float>(const StageArgs<float> &, int *const[2], int *const[2], Ctl *, int, int,
+                                               unsigned, hipStream_t);
+template hipError_t launch_cascade_tail<double>(const StageArgs<double> &, int *const[2], int *const[2], Ctl *, int,
+                                                int, unsigned, hipStream_t);
 template hipError_t launch_dt<float>(const float *, size_t, double, double, double, double, Ctl *, hipStream_t);
 template hipError_t launch_dt<double>(const double *, size_t, double, double, double, double, Ctl *, hipStream_t);
 template hipError_t launch_totals<float>(const float *, size_t, double, double *, int, Ctl *, hipStream_t);
