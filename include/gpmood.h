@@ -85,7 +85,8 @@ typedef struct {
 
 /* Create a context for a grid, a precision and a HIP stream (hipStream_t, may be
    NULL).  Allocates host memory only.  Errors: GPM_EINVAL (bad grid, gamma <= 1,
-   n < 1 or > 32768 per axis), GPM_EUNSUPPORTED (dim != 2). */
+   n < 1 or > 32768 per axis), GPM_EUNSUPPORTED (dim != 2, or a periodic axis
+   with fewer than 4 cells: the radius-3 stencil reaches 4 cells past a face). */
 gpm_status gpm_create(const gpm_grid *grid, int prec, void *hip_stream, gpm_ctx **out);
 
 /* Set the cascade, ell, CSD thresholds and flags.  Builds the GP prediction
@@ -93,21 +94,24 @@ gpm_status gpm_create(const gpm_grid *grid, int prec, void *hip_stream, gpm_ctx 
    (gp_reconstructor), (normalized_z) with the signed-sum normalisation; Cholesky
    of C as in Sec. "Singularity of the covariance kernel matrix") and the GP-R1
    second-derivative weights of App. B, then rounds them to the context's
-   precision.  Errors: GPM_EINVAL for a cascade that is not strictly decreasing,
+   precision.  When memory is bound the call copies the cascade's weight table
+   into the workspace and synchronises the stream.  Errors: GPM_EINVAL for a
+   cascade that is not strictly decreasing,
    does not end at 0, has a radius outside 0..3 or more than 4 levels, ell < 0, or
    a covariance matrix that is not numerically positive definite. */
 gpm_status gpm_set_scheme(gpm_ctx *ctx, const gpm_scheme *scheme);
 
 /* Bytes the caller must provide: state_bytes for three state slots (each
    4*nx*ny elements of the context's precision), work_bytes for the workspace
-   (orders, troubled lists, counters, reduction partials).  Either pointer may
-   be NULL. */
+   (orders, face fluxes, troubled lists, counters, reduction partials, the
+   cascade's weight table).  Either pointer may be NULL. */
 gpm_status gpm_workspace_size(const gpm_ctx *ctx, size_t *state_bytes, size_t *work_bytes);
 
 /* Bind caller-owned device memory: `state` (>= state_bytes, 256-byte aligned)
    and `work` (>= work_bytes, 256-byte aligned).  Slot 0 is the current state
-   after gpm_init_state(); gpm_step() rotates the slots.  Errors: GPM_EINVAL for a
-   NULL or misaligned pointer. */
+   after gpm_init_state(); gpm_step() rotates the slots.  Clears the workspace
+   (and, with a scheme set, writes its weight table); synchronising.  Errors:
+   GPM_EINVAL for a NULL or misaligned pointer. */
 gpm_status gpm_bind(gpm_ctx *ctx, void *state, void *work);
 
 /* Device address of state slot `slot` (0..2) and the slot that holds the

@@ -38,6 +38,8 @@ struct gpm_ctx {
     gpm_scheme scheme;
     Weights<double> w64;
     Weights<float> w32;
+    std::vector<double> gtab64;  // compact cascade weights (kGtabSize), both precisions
+    std::vector<float> gtab32;
     int top = 0;
     int next[4] = {0, 0, 0, 0};
     int levidx[4] = {0, 0, 0, 0};
@@ -56,6 +58,7 @@ struct gpm_ctx {
     uint8_t *GYf = nullptr;
     Ctl *ctl = nullptr;
     double *partial = nullptr;
+    void *gtab = nullptr;
     unsigned pass = 0;
     int passes_per_check = 4;
     int tail_threshold = 48;  // troubled cells below which the cascade finishes in one workgroup
@@ -76,6 +79,18 @@ static gpm_status fail(gpm_ctx *c, gpm_status st, const std::string &msg)
     return st;
 }
 
+// Copy the compact cascade weights into the workspace (synchronous: a setup step).
+static gpm_status upload_gtab(gpm_ctx *c)
+{
+    if (!c->gtab || !c->have_scheme) return GPM_OK;
+    const void *src = c->prec == GPM_F64 ? (const void *)c->gtab64.data() : (const void *)c->gtab32.data();
+    const size_t bytes = (size_t)kGtabSize * (c->prec == GPM_F64 ? 8 : 4);
+    hipError_t e = hipMemcpyAsync(c->gtab, src, bytes, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("weight upload: ") + hipGetErrorString(e));
+    return GPM_OK;
+}
+
 #define HIPCHK(c, expr)                                                                      \
     do {                                                                                     \
         hipError_t e_ = (expr);                                                              \
@@ -92,7 +107,7 @@ static size_t nfaces_x(const gpm_ctx *c) { return (size_t)(c->nx + 1) * c->ny; }
 static size_t nfaces_y(const gpm_ctx *c) { return (size_t)c->nx * (c->ny + 1); }
 
 // Workspace partition (each part 256-byte aligned).
-enum { W_ORDER, W_CSTAMP, W_FSTAMP, W_FL0, W_FL1, W_CL0, W_CL1, W_FX, W_GY, W_FXF, W_GYF, W_CTL, W_PART, W_N };
+enum { W_ORDER, W_CSTAMP, W_FSTAMP, W_FL0, W_FL1, W_CL0, W_CL1, W_FX, W_GY, W_FXF, W_GYF, W_CTL, W_PART, W_GTAB, W_N };
 
 static size_t work_layout(const gpm_ctx *c, size_t off[W_N])
 {
@@ -100,7 +115,7 @@ static size_t work_layout(const gpm_ctx *c, size_t off[W_N])
     const size_t esz = c->prec == GPM_F64 ? 8 : 4;
     const size_t sz[W_N] = {c->ncell, 4 * c->ncell, 4 * nf, 4 * nf, 4 * nf, 4 * c->ncell, 4 * c->ncell,
                             4 * esz * nfaces_x(c), 4 * esz * nfaces_y(c), nfaces_x(c), nfaces_y(c), sizeof(Ctl),
-                            (size_t)kTotBlocks * 4 * 2 * sizeof(double)};
+                            (size_t)kTotBlocks * 4 * 2 * sizeof(double), (size_t)kGtabSize * esz};
     size_t o = 0;
     for (int k = 0; k < W_N; ++k) {
         off[k] = o;
@@ -137,6 +152,8 @@ gpm_status gpm_create(const gpm_grid *grid, int prec, void *hip_stream, gpm_ctx 
         if (grid->n[d] < 1 || grid->n[d] > 32768) return GPM_EINVAL;
         if (!(grid->hi[d] > grid->lo[d])) return GPM_EINVAL;
         if (grid->bc[d] != GPM_BC_PERIODIC && grid->bc[d] != GPM_BC_OUTFLOW) return GPM_EINVAL;
+        // the widest stencil reaches 4 cells past an edge; a periodic axis must hold it
+        if (grid->bc[d] == GPM_BC_PERIODIC && grid->n[d] < 4) return GPM_EUNSUPPORTED;
     }
     if (!(grid->gamma > 1.0)) return GPM_EINVAL;
     gpm_ctx *c = new (std::nothrow) gpm_ctx;
@@ -180,6 +197,15 @@ gpm_status gpm_set_scheme(gpm_ctx *c, const gpm_scheme *s)
     const double ax = ell / c->dx, ay = ell / c->dy;
     std::memset(&c->w64, 0, sizeof(c->w64));
     std::memset(&c->w32, 0, sizeof(c->w32));
+    std::vector<double> g64(kGtabSize, 0.0);
+    std::vector<float> g32(kGtabSize, 0.0f);
+    // FOG: the cell value itself (gathered 4x at the centre), one node of weight 1
+    for (int d = 0; d < 2; ++d) {
+        g64[(0 * 2 + d) * kGtabPerDir + C_EE] = 0.25;
+        g32[(0 * 2 + d) * kGtabPerDir + C_EE] = 0.25f;
+    }
+    g64[kGtabNodeOff + 0] = 1.0;
+    g32[kGtabNodeOff + 0] = 1.0f;
     for (int R = 1; R <= 3; ++R) {
         bool used = false;
         for (int l = 0; l < s->nlev; ++l) used = used || s->radius[l] == R;
@@ -193,6 +219,21 @@ gpm_status gpm_set_scheme(gpm_ctx *c, const gpm_scheme *s)
                     if (R == 2) { c->w64.w2[d][p][e] = L.w64[d][p][e]; c->w32.w2[d][p][e] = L.w32[d][p][e]; }
                     if (R == 1) { c->w64.w1[d][0][e] = L.w64[d][0][e]; c->w32.w1[d][0][e] = L.w32[d][0][e]; }
                 }
+        for (int d = 0; d < 2; ++d)
+            for (int p = 0; p < slots_of(R); ++p)
+                for (int e = 0; e < kNQ[R]; ++e) {
+                    const int a = kQ[e].a, b = kQ[e].b;
+                    int pos = 0;
+                    while (!((int)((kPosA >> (4 * pos)) & 15u) == a && (int)((kPosB >> (4 * pos)) & 15u) == b)) ++pos;
+                    const double f = (a == 0 && b == 0) ? 0.25 : ((a == 0 || b == 0) ? 0.5 : 1.0);
+                    const int k = (R * 2 + d) * kGtabPerDir + p * (kNPos * 4) + pos * 4 + kQ[e].comp;
+                    g64[k] = L.w64[d][p][e] * f;
+                    g32[k] = L.w32[d][p][e] * (float)f;
+                }
+        for (int p = 0; p < slots_of(R); ++p) {
+            g64[kGtabNodeOff + R * 2 + p] = L.qw64[p];
+            g32[kGtabNodeOff + R * 2 + p] = L.qw32[p];
+        }
         for (int p = 0; p < slots_of(R); ++p) {
             if (R == 3) { c->w64.qw3[p] = L.qw64[p]; c->w32.qw3[p] = L.qw32[p]; }
             if (R == 2) { c->w64.qw2[p] = L.qw64[p]; c->w32.qw2[p] = L.qw32[p]; }
@@ -206,6 +247,8 @@ gpm_status gpm_set_scheme(gpm_ctx *c, const gpm_scheme *s)
             c->w64.curv[d][k] = K.w64[d][k];
             c->w32.curv[d][k] = K.w32[d][k];
         }
+    c->gtab64.swap(g64);
+    c->gtab32.swap(g32);
     c->scheme = *s;
     c->scheme.ell = ell;
     c->top = s->radius[0];
@@ -215,7 +258,7 @@ gpm_status gpm_set_scheme(gpm_ctx *c, const gpm_scheme *s)
         c->next[s->radius[l]] = l + 1 < s->nlev ? s->radius[l + 1] : 0;
     }
     c->have_scheme = true;
-    return GPM_OK;
+    return upload_gtab(c);
 }
 
 gpm_status gpm_workspace_size(const gpm_ctx *c, size_t *state_bytes, size_t *work_bytes)
@@ -248,12 +291,13 @@ gpm_status gpm_bind(gpm_ctx *c, void *state, void *work)
     c->GYf = (uint8_t *)(c->work + off[W_GYF]);
     c->ctl = (Ctl *)(c->work + off[W_CTL]);
     c->partial = (double *)(c->work + off[W_PART]);
+    c->gtab = c->work + off[W_GTAB];
     c->cur = 0;
     c->pass = 0;
     c->fresh_ctl = true;
     HIPCHK(c, hipMemsetAsync(c->work, 0, wbytes, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    return GPM_OK;
+    return upload_gtab(c);
 }
 
 gpm_status gpm_state_ptr(const gpm_ctx *c, int slot, void **ptr, int *current_slot)
@@ -369,6 +413,7 @@ static void fill_args(const gpm_ctx *c, const Weights<real> &W, StageArgs<real> 
     A.GY = (real *)c->GY;
     A.FXf = c->FXf;
     A.GYf = c->GYf;
+    A.gtab = (const real *)c->gtab;
     A.cstamp = c->cstamp;
     A.fstamp = c->fstamp;
     for (int r = 0; r < 4; ++r) A.next[r] = c->next[r];

@@ -63,6 +63,7 @@ struct StageArgs {
     int next[4];          // next radius of the cascade after radius r
     real dx, dy, gamma, sigma_v, sigma_p, plat_thr, delta;
     Weights<real> W;
+    const real *gtab;     // compact cascade weights, kGtabSize values (device)
 };
 
 // Outputs of one evaluation: the troubled count, and the faces and cells that the
@@ -98,6 +99,15 @@ __device__ __forceinline__ int remap(int i, int n, int bc)
         int r = i % n;
         return r < 0 ? r + n : r;
     }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// remap() for an index at most one period outside the axis (-n <= i < 2n): the
+// cascade reaches at most 4 cells beyond the domain, and periodic axes have at
+// least 4 cells.
+__device__ __forceinline__ int wrap(int i, int n, int bc)
+{
+    if (bc == 0) return i < 0 ? i + n : (i >= n ? i - n : i);
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
@@ -334,47 +344,35 @@ __device__ __forceinline__ void wave_count(bool flag, int *count)
     if (mask != 0ull && (threadIdx.x & 63) == 0) atomicAdd(count, (int)__popcll(mask));
 }
 
-// Append up to K flagged values per lane to a list with one atomic per wavefront.
-// Must be reached by all 64 lanes of the wavefront together.
-template <int K>
-__device__ __forceinline__ void wave_append_multi(const bool (&flag)[K], const int (&val)[K], int *list, int *count)
+// Reserve n slots per lane in two lists at once (n = count0 + 65536 * count1,
+// each count below 1024) with one atomic per list and wavefront; returns the
+// lane's first slot of each list.  Must be reached by all 64 lanes of the
+// wavefront together.
+__device__ __forceinline__ void wave_reserve2(int n, int *count0, int *count1, int &base0, int &base1)
 {
-    unsigned long long m[K];
-    int tot = 0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        m[k] = __ballot(flag[k]);
-        tot += (int)__popcll(m[k]);
-    }
-    if (tot == 0) return;
     const int lane = threadIdx.x & 63;
-    int base = 0;
-    if (lane == 0) base = atomicAdd(count, tot);
-    base = __shfl(base, 0);
-    const unsigned long long below = (1ull << lane) - 1ull;
+    int incl = n;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        if (flag[k]) list[base + __popcll(m[k] & below)] = val[k];
-        base += (int)__popcll(m[k]);
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(incl, d);
+        if (lane >= d) incl += t;
     }
+    const int tot = __shfl(incl, 63);
+    int b0 = 0, b1 = 0;
+    if (lane == 63) {
+        if (tot & 0xffff) b0 = atomicAdd(count0, tot & 0xffff);
+        if (tot >> 16) b1 = atomicAdd(count1, tot >> 16);
+    }
+    b0 = __shfl(b0, 63);
+    b1 = __shfl(b1, 63);
+    const int excl = incl - n;
+    base0 = b0 + (excl & 0xffff);
+    base1 = b1 + (excl >> 16);
 }
 
 struct LevIdx {
     int v[4];  // cascade level of radius r
 };
-
-// Append flagged cells of the wavefront to a list (ballot + prefix, one atomic per
-// wave).  Must be reached by all 64 lanes of the wavefront together.
-__device__ __forceinline__ void wave_append(bool flag, int cell, int *list, int *count)
-{
-    const unsigned long long mask = __ballot(flag);
-    if (mask == 0ull) return;
-    const int lane = threadIdx.x & 63;
-    int base = 0;
-    if (lane == 0) base = atomicAdd(count, (int)__popcll(mask));
-    base = __shfl(base, 0);
-    if (flag) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = cell;
-}
 
 }  // namespace gpm
 

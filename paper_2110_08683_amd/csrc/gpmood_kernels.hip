@@ -63,8 +63,12 @@ __device__ __forceinline__ void claim_after_lowering(const StageArgs<real> &A, c
     fid[5] = j == 0 ? nfx + ny * nx + i : nfx + i;                // copy of face 0 / face ny
     fok[5] = act && A.bcy == 0 && (j == 0 || j == ny - 1);
     bool fmine[6];
+    int nmine = 0;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) fmine[k] = fok[k] && atomicMax(&A.fstamp[fid[k]], P.stamp) < P.stamp;
+    for (int k = 0; k < 6; ++k) {
+        fmine[k] = fok[k] && atomicMax(&A.fstamp[fid[k]], P.stamp) < P.stamp;
+        nmine += fmine[k] ? 1 : 0;
+    }
     const int di[5] = {0, -1, 1, 0, 0}, dj[5] = {0, 0, 0, -1, 1};
     int cid[5];
     bool cmine[5];
@@ -72,11 +76,20 @@ __device__ __forceinline__ void claim_after_lowering(const StageArgs<real> &A, c
     for (int k = 0; k < 5; ++k) {
         const int ii = i + di[k], jj = j + dj[k];
         const bool inside = (A.bcx == 0 || (ii >= 0 && ii < nx)) && (A.bcy == 0 || (jj >= 0 && jj < ny));
-        cid[k] = (act && inside) ? remap(jj, ny, A.bcy) * nx + remap(ii, nx, A.bcx) : 0;
+        cid[k] = (act && inside) ? wrap(jj, ny, A.bcy) * nx + wrap(ii, nx, A.bcx) : 0;
         cmine[k] = act && inside && atomicMax(&A.cstamp[cid[k]], P.stamp) < P.stamp;
+        nmine += cmine[k] ? 65536 : 0;
     }
-    wave_append_multi(fmine, fid, P.flist, P.fcount);
-    wave_append_multi(cmine, cid, P.clist, P.ccount);
+    int fb, cb;
+    wave_reserve2(nmine, P.fcount, P.ccount, fb, cb);
+    if (nmine != 0) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            if (fmine[k]) P.flist[fb++] = fid[k];
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+            if (cmine[k]) P.clist[cb++] = cid[k];
+    }
 }
 
 template <typename real, int RT, int WPB>
@@ -256,111 +269,220 @@ __global__ __launch_bounds__(64 * WPB) void k_first_pass(const StageArgs<real> A
 }
 
 // ------------------------------------------------------------- cascade pass
-// Face states of the cell centred at (ci, cj) (ghost positions allowed) for
-// direction DIR at radius R, read from global memory with boundary remaps.
-template <typename real, int R, int DIR>
-__device__ __forceinline__ void cell_states(const StageArgs<real> &A, int ci, int cj,
-                                            real (&sm)[nodes_of(R)][4], real (&sp)[nodes_of(R)][4])
+// HLLC through a face normal to axis dir (runtime): the momenta are swapped into
+// the x-face form and back, so the arithmetic is that of hllc<dir>.
+template <typename real>
+__device__ __forceinline__ void hllc_rt(real g, int dir, const real (&UL)[4], const real (&UR)[4], real (&F)[4],
+                                        bool &badL, bool &badR)
 {
-    const size_t plane = (size_t)A.nx * A.ny;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const real *U = A.Us + v * plane;
-        if constexpr (R == 0) {
-            const real x = U[(size_t)remap(cj, A.ny, A.bcy) * A.nx + remap(ci, A.nx, A.bcx)];
-            sm[0][v] = x;
-            sp[0][v] = x;
-        } else {
-            real Q[kNQ[R]];
-            build_Q<R>(Q, [&](int di, int dj) {
-                return U[(size_t)remap(cj + dj, A.ny, A.bcy) * A.nx + remap(ci + di, A.nx, A.bcx)];
-            });
-            real m_[nodes_of(R)], p_[nodes_of(R)];
-            states_dir<R, DIR>(Q, A.W, m_, p_);
-#pragma unroll
-            for (int k = 0; k < nodes_of(R); ++k) { sm[k][v] = m_[k]; sp[k][v] = p_[k]; }
-        }
-    }
+    const real L[4] = {UL[0], dir ? UL[2] : UL[1], dir ? UL[1] : UL[2], UL[3]};
+    const real Rr[4] = {UR[0], dir ? UR[2] : UR[1], dir ? UR[1] : UR[2], UR[3]};
+    real f[4];
+    hllc<0>(g, L, Rr, f, badL, badR);
+    F[0] = f[0];
+    F[1] = dir ? f[2] : f[1];
+    F[2] = dir ? f[1] : f[2];
+    F[3] = f[3];
 }
 
-// Flux through the face between cell L = (iL, jL) and its + neighbour along DIR at
-// radius Rf, summed over the face's Gauss nodes (eq. (fvm_F)).
-template <typename real, int Rf, int DIR>
-__device__ __forceinline__ void face_flux_t(const StageArgs<real> &A, int iL, int jL, real (&F)[4],
-                                            bool &badL, bool &badR)
+// Per-wavefront LDS of the cascade's face work: 16 faces x 4 lanes, each lane with
+// the 4 left and 4 right node states of its variable (later: one node's flux),
+// and one flag word per lane.
+template <typename real>
+struct FaceXchg {
+    real s[64][8];
+    int fl[64];
+};
+
+// Copy the compact weight table into LDS (all threads of the block; a block
+// barrier must follow before it is read).
+template <typename real>
+__device__ __forceinline__ void load_gtab(const real *gtab, real *wl)
 {
-    constexpr int q = nodes_of(Rf);
-    real lm[q][4], lp[q][4], rm[q][4], rp[q][4];
-    cell_states<real, Rf, DIR>(A, iL, jL, lm, lp);
-    cell_states<real, Rf, DIR>(A, iL + (DIR == 0), jL + (DIR == 1), rm, rp);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) F[v] = real(0);
-    badL = false;
-    badR = false;
-#pragma unroll
-    for (int k = 0; k < q; ++k) {
-        real f[4];
-        bool bl, br;
-        hllc<DIR>(A.gamma, lp[k], rm[k], f, bl, br);
-        badL = badL || bl;
-        badR = badR || br;
-        const real w = node_weight<Rf>(A.W, k);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) F[v] = fma(w, f[v], F[v]);
-    }
+    for (int k = threadIdx.x; k < kGtabSize; k += blockDim.x) wl[k] = gtab[k];
 }
 
-// Everything is inlined into the kernels: device-function calls are avoided on
-// purpose (a large callee needs a scratch stack, and long branches inside such a
-// callee have been seen to reuse its return-address register).
-template <typename real, int DIR>
-__device__ __forceinline__ void face_flux(const StageArgs<real> &A, int Rf, int iL, int jL, real (&F)[4],
-                                          bool &badL, bool &badR)
+// Parity sums of the four mirror cells (+-a, +-b) of one variable, as in build_Q.
+template <typename real>
+__device__ __forceinline__ void parity4(real pp, real mp, real pm, real mm, real (&Q)[4])
 {
-    // faces recomputed by the cascade are never at the top order of GP-MOOD7/5,
-    // but a top order of 1..3 is allowed in general
-    if (Rf == 3) face_flux_t<real, 3, DIR>(A, iL, jL, F, badL, badR);
-    else if (Rf == 2) face_flux_t<real, 2, DIR>(A, iL, jL, F, badL, badR);
-    else if (Rf == 1) face_flux_t<real, 1, DIR>(A, iL, jL, F, badL, badR);
-    else face_flux_t<real, 0, DIR>(A, iL, jL, F, badL, badR);
+    const real s1 = pp + mp, d1 = pp - mp, s2 = pm + mm, d2 = pm - mm;
+    Q[C_EE] = s1 + s2;
+    Q[C_OE] = d1 + d2;
+    Q[C_EO] = s1 - s2;
+    Q[C_OO] = d1 - d2;
 }
 
 // Cascade pass, part 1: recompute the listed faces at their EDP_1 order (the
-// smaller radius of the two cells), one thread per face.
+// smaller radius of the two cells), four lanes per face.  Lane v of a quad
+// gathers variable v of both cells' quarter positions (all loads issued at once),
+// forms that variable's states at every Gauss node, and after an LDS transpose
+// lane k solves the HLLC problem of node k; lane v then sums variable v of the
+// node fluxes with the Gauss weights (eq. (fvm_F)).  The products and sums are
+// those of the first pass (build_Q, states_dir, hllc), in the same order, with
+// the multiplicity of on-axis positions folded into the table weights.
+//
+// A listed face borders a cell lowered in the previous evaluation, so its radius
+// is below the top radius: at most 2 for GP-MOOD7.  Radius 3 (positions 6..9) is
+// still handled, by a rolled loop.  The number of rounds is uniform across the
+// wavefront (LDS exchange); wl is the LDS copy of the compact weight table.
 template <typename real>
-__device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const int *flist, int n, int t0, int stride)
+__device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real *wl, FaceXchg<real> &X,
+                                            const int *flist, int n, int t0, int stride)
 {
     const int nx = A.nx, ny = A.ny;
     const int nfx = (nx + 1) * ny, nfy = nx * (ny + 1);
-    for (int idx = t0; idx < n; idx += stride) {
-        const int f = flist[idx];
-        real F[4];
-        bool bl = false, br = false;
-        if (f < nfx) {
-            const int j = f / (nx + 1), i = f - j * (nx + 1);  // between cells i-1 and i
-            const int oL = A.order[(size_t)j * nx + remap(i - 1, nx, A.bcx)];
-            const int oR = A.order[(size_t)j * nx + remap(i, nx, A.bcx)];
-            face_flux<real, 0>(A, min(oL, oR), i - 1, j, F, bl, br);
+    const size_t plane = (size_t)nx * ny;
+    const int lane = threadIdx.x & 63, v = lane & 3, q0 = lane & ~3;
+    const int nround = (4 * n + stride - 1) / stride;
+    for (int r = 0; r < nround; ++r) {
+        const int idx = (r * stride + t0) >> 2;
+        const bool valid = idx < n;
+        int dir = 0, R = 0, fo = 0;
+        real PL[2][4], PR[2][4];  // [slot][component] of variable v, left and right cell
 #pragma unroll
-            for (int v = 0; v < 4; ++v) A.FX[(size_t)v * nfx + f] = F[v];
-            A.FXf[f] = (uint8_t)((bl ? 1 : 0) | (br ? 2 : 0));
-        } else {
-            const int g = f - nfx;
-            const int j = g / nx, i = g - j * nx;  // between cells (i, j-1) and (i, j)
-            const int oL = A.order[(size_t)remap(j - 1, ny, A.bcy) * nx + i];
-            const int oR = A.order[(size_t)remap(j, ny, A.bcy) * nx + i];
-            face_flux<real, 1>(A, min(oL, oR), i, j - 1, F, bl, br);
+        for (int p = 0; p < 2; ++p)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) A.GY[(size_t)v * nfy + g] = F[v];
-            A.GYf[g] = (uint8_t)((bl ? 1 : 0) | (br ? 2 : 0));
+            for (int c = 0; c < 4; ++c) PL[p][c] = PR[p][c] = real(0);
+        if (valid) {
+            const int f = flist[idx];
+            int iL, jL, cL, cR;
+            if (f < nfx) {
+                const int j = f / (nx + 1), i = f - j * (nx + 1);  // between cells i-1 and i
+                dir = 0;
+                fo = f;
+                iL = i - 1;
+                jL = j;
+                cL = j * nx + wrap(i - 1, nx, A.bcx);
+                cR = j * nx + wrap(i, nx, A.bcx);
+            } else {
+                const int g = f - nfx;
+                const int j = g / nx, i = g - j * nx;  // between cells (i, j-1) and (i, j)
+                dir = 1;
+                fo = g;
+                iL = i;
+                jL = j - 1;
+                cL = wrap(j - 1, ny, A.bcy) * nx + i;
+                cR = wrap(j, ny, A.bcy) * nx + i;
+            }
+            const int iR = iL + (dir == 0), jR = jL + (dir == 1);
+            const real *U = A.Us + v * plane;
+            // quarter positions 0..5 (radius <= 2) of both cells: 48 independent loads
+            constexpr int pa[6] = {0, 1, 0, 2, 0, 1}, pb[6] = {0, 0, 1, 0, 2, 1};
+            real QL[6][4], QR[6][4];
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                const int xLp = wrap(iL + pa[e], nx, A.bcx), xLm = wrap(iL - pa[e], nx, A.bcx);
+                const int xRp = wrap(iR + pa[e], nx, A.bcx), xRm = wrap(iR - pa[e], nx, A.bcx);
+                const size_t yLp = (size_t)wrap(jL + pb[e], ny, A.bcy) * nx;
+                const size_t yLm = (size_t)wrap(jL - pb[e], ny, A.bcy) * nx;
+                const size_t yRp = (size_t)wrap(jR + pb[e], ny, A.bcy) * nx;
+                const size_t yRm = (size_t)wrap(jR - pb[e], ny, A.bcy) * nx;
+                parity4(U[yLp + xLp], U[yLp + xLm], U[yLm + xLp], U[yLm + xLm], QL[e]);
+                parity4(U[yRp + xRp], U[yRp + xRm], U[yRm + xRp], U[yRm + xRm], QR[e]);
+            }
+            R = min((int)A.order[cL], (int)A.order[cR]);
+            const real *wt = wl + (R * 2 + dir) * kGtabPerDir;
+            const int np = R <= 0 ? 1 : (R == 1 ? 3 : (R == 2 ? 6 : 10));
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                if (e < np) {
+#pragma unroll
+                    for (int p = 0; p < 2; ++p)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            const real w = wt[p * (kNPos * 4) + e * 4 + c];
+                            PL[p][c] = fma(w, QL[e][c], PL[p][c]);
+                            PR[p][c] = fma(w, QR[e][c], PR[p][c]);
+                        }
+                }
+            }
+#pragma unroll 1
+            for (int e = 6; e < np; ++e) {
+                const int a = (int)((kPosA >> (4 * e)) & 15u), b = (int)((kPosB >> (4 * e)) & 15u);
+                const int xLp = wrap(iL + a, nx, A.bcx), xLm = wrap(iL - a, nx, A.bcx);
+                const int xRp = wrap(iR + a, nx, A.bcx), xRm = wrap(iR - a, nx, A.bcx);
+                const size_t yLp = (size_t)wrap(jL + b, ny, A.bcy) * nx, yLm = (size_t)wrap(jL - b, ny, A.bcy) * nx;
+                const size_t yRp = (size_t)wrap(jR + b, ny, A.bcy) * nx, yRm = (size_t)wrap(jR - b, ny, A.bcy) * nx;
+                real ql[4], qr[4];
+                parity4(U[yLp + xLp], U[yLp + xLm], U[yLm + xLp], U[yLm + xLm], ql);
+                parity4(U[yRp + xRp], U[yRp + xRm], U[yRm + xRp], U[yRm + xRm], qr);
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const real w = wt[p * (kNPos * 4) + e * 4 + c];
+                        PL[p][c] = fma(w, ql[c], PL[p][c]);
+                        PR[p][c] = fma(w, qr[c], PR[p][c]);
+                    }
+            }
         }
+        const int q = R <= 0 ? 1 : R + 1;
+        // states of variable v at node k (table order; slot 1 is the inner pair for
+        // R = 3 and the centre node for R = 2; a single node has no +- partner)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int slot = (R >= 2 && k >= 1 && k <= q - 2) ? 1 : 0;
+            const bool single = R <= 0 || (R == 2 && k == 1);
+            const bool plus = k < (q >> 1);
+            const real lee = slot ? PL[1][C_EE] : PL[0][C_EE], loe = slot ? PL[1][C_OE] : PL[0][C_OE];
+            const real leo = slot ? PL[1][C_EO] : PL[0][C_EO], loo = slot ? PL[1][C_OO] : PL[0][C_OO];
+            const real ree = slot ? PR[1][C_EE] : PR[0][C_EE], roe = slot ? PR[1][C_OE] : PR[0][C_OE];
+            const real reo = slot ? PR[1][C_EO] : PR[0][C_EO], roo = slot ? PR[1][C_OO] : PR[0][C_OO];
+            const real lF = dir ? leo : loe, lN = dir ? loe : leo;  // odd across / along the face
+            const real rF = dir ? reo : roe, rN = dir ? roe : reo;
+            const real Ap = lee + lF, Cp = lN + loo;  // + face of the left cell
+            const real Bm = ree - rF, Dm = rN - roo;  // - face of the right cell
+            X.s[lane][k] = single ? Ap : (plus ? Ap + Cp : Ap - Cp);
+            X.s[lane][4 + k] = single ? Bm : (plus ? Bm + Dm : Bm - Dm);
+        }
+        wave_lds_sync();
+        real fk[4] = {real(0), real(0), real(0), real(0)};
+        int flg = 0;
+        if (valid && v < q) {  // lane v solves node k = v
+            real UL[4], UR[4];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                UL[w] = X.s[q0 + w][v];
+                UR[w] = X.s[q0 + w][4 + v];
+            }
+            bool bl, br;
+            hllc_rt(A.gamma, dir, UL, UR, fk, bl, br);
+            flg = (bl ? 1 : 0) | (br ? 2 : 0);
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int w = 0; w < 4; ++w) X.s[lane][w] = fk[w];
+        X.fl[lane] = flg;
+        wave_lds_sync();
+        if (valid) {
+            real F = real(0);
+            int fl = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (k < q) {
+                    const int slot = (R >= 2 && k >= 1 && k <= q - 2) ? 1 : 0;
+                    F = fma(wl[kGtabNodeOff + R * 2 + slot], X.s[q0 + k][v], F);
+                    fl |= X.fl[q0 + k];
+                }
+            }
+            if (dir == 0) {
+                A.FX[(size_t)v * nfx + fo] = F;
+                if (v == 0) A.FXf[fo] = (uint8_t)fl;
+            } else {
+                A.GY[(size_t)v * nfy + fo] = F;
+                if (v == 0) A.GYf[fo] = (uint8_t)fl;
+            }
+        }
+        wave_lds_sync();  // the next round overwrites X
     }
 }
 
 // Cascade pass, part 2: re-evaluate the listed cells from the stored fluxes,
 // re-detect, lower the troubled ones and claim the faces and cells of the next
 // pass.  Detection reads no other cell's order, so lowering in place is safe.
-// The number of rounds is the same for all lanes (wavefront-wide list appends).
+// Everything a cell needs (fluxes, flags, its radius-2 neighbourhood) is loaded
+// at once, up front.  The number of rounds is uniform across the wavefront.
 template <typename real>
 __device__ __forceinline__ void cells_phase(const StageArgs<real> &A, const int *clist, int n, int t0, int stride,
                                             const PassOut &P)
@@ -377,28 +499,56 @@ __device__ __forceinline__ void cells_phase(const StageArgs<real> &A, const int 
         int i = 0, j = 0;
         if (valid) {
             const int c = clist[idx];
-            i = c % nx;
             j = c / nx;
-            const int o = A.order[c];
+            i = c - j * nx;
             const size_t fxm = (size_t)j * (nx + 1) + i, gym = (size_t)j * nx + i;
-            real ust[4];
+            size_t yr[5];
+            int xc[5];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const real us = A.Us[v * plane + c];
-                const real dFx = A.FX[v * nfx + fxm + 1] - A.FX[v * nfx + fxm];
-                ust[v] = us - dt * (dFx / A.dx + (A.GY[v * nfy + gym + nx] - A.GY[v * nfy + gym]) / A.dy);
+            for (int d = 0; d < 5; ++d) {
+                yr[d] = (size_t)wrap(j + d - 2, ny, A.bcy) * nx;
+                xc[d] = wrap(i + d - 2, nx, A.bcx);
             }
+            // radius-2 diamond of densities and the other variables of the cell and
+            // its face neighbours: every value detection may read
+            constexpr int di13[13] = {0, -1, 1, 0, 0, -2, 2, 0, 0, -1, 1, -1, 1};
+            constexpr int dj13[13] = {0, 0, 0, -1, 1, 0, 0, -2, 2, -1, -1, 1, 1};
+            real rho[13], mom[5][3];
+#pragma unroll
+            for (int m = 0; m < 13; ++m) rho[m] = A.Us[yr[dj13[m] + 2] + xc[di13[m] + 2]];
+#pragma unroll
+            for (int m = 0; m < 5; ++m)
+#pragma unroll
+                for (int w = 1; w < 4; ++w) mom[m][w - 1] = A.Us[w * plane + yr[dj13[m] + 2] + xc[di13[m] + 2]];
+            real fx[4][2], gy[4][2], un[4];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                fx[w][0] = A.FX[w * nfx + fxm];
+                fx[w][1] = A.FX[w * nfx + fxm + 1];
+                gy[w][0] = A.GY[w * nfy + gym];
+                gy[w][1] = A.GY[w * nfy + gym + nx];
+                un[w] = A.s == 0 ? real(0) : A.Un[w * plane + c];
+            }
+            const int o = A.order[c];
             // the cell's own states: right state of its - faces, left state of its + faces
             const bool rs = (A.FXf[fxm] & 2) || (A.FXf[fxm + 1] & 1) || (A.GYf[gym] & 2) || (A.GYf[gym + nx] & 1);
-            auto nb = [&](int di, int dj, int v) {
-                return A.Us[v * plane + (size_t)remap(j + dj, ny, A.bcy) * nx + remap(i + di, nx, A.bcx)];
+            real ust[4];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const real us = w == 0 ? rho[0] : mom[0][w - 1];
+                const real dFx = fx[w][1] - fx[w][0];
+                ust[w] = us - dt * (dFx / A.dx + (gy[w][1] - gy[w][0]) / A.dy);
+            }
+            auto nb = [&](int di, int dj, int w) -> real {
+                int m = 0;
+#pragma unroll
+                for (int t = 0; t < 13; ++t)
+                    if (di13[t] == di && dj13[t] == dj) m = t;
+                return w == 0 ? rho[m] : mom[m < 5 ? m : 0][w - 1];
             };
             tr = troubled(A, o, ust, rs, nb);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const real un = A.s == 0 ? real(0) : A.Un[v * plane + c];
-                A.Uout[v * plane + c] = combine(A.s, un, ust[v]);
-            }
+            for (int w = 0; w < 4; ++w) A.Uout[w * plane + c] = combine(A.s, un[w], ust[w]);
             if (tr) A.order[c] = (uint8_t)A.next[o];
         }
         wave_count(tr, P.tcount);
@@ -407,12 +557,18 @@ __device__ __forceinline__ void cells_phase(const StageArgs<real> &A, const int 
 }
 
 template <typename real>
-__global__ __launch_bounds__(64) void k_faces(const StageArgs<real> A, const int *flist, const int *fcount)
+__global__ __launch_bounds__(256) void k_faces(const StageArgs<real> A, const int *flist, const int *fcount)
 {
+    __shared__ real wl[kGtabSize];
+    __shared__ FaceXchg<real> xch[4];
     const int cap = (A.nx + 1) * A.ny + A.nx * (A.ny + 1);
     int n = *fcount;
     n = n < cap ? n : cap;  // a list holds each face at most once
-    faces_phase(A, flist, n, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+    if (4 * n <= (int)(blockIdx.x * blockDim.x)) return;  // no face for this block
+    load_gtab(A.gtab, wl);
+    __syncthreads();
+    faces_phase(A, wl, xch[threadIdx.x >> 6], flist, n, blockIdx.x * blockDim.x + threadIdx.x,
+                gridDim.x * blockDim.x);
 }
 
 template <typename real>
@@ -421,7 +577,7 @@ __global__ __launch_bounds__(64) void k_cells(const StageArgs<real> A, const int
 {
     int n = *ccount;
     n = n < A.nx * A.ny ? n : A.nx * A.ny;  // a list holds each cell at most once
-    if (n <= 0) return;
+    if (n <= (int)(blockIdx.x * blockDim.x)) return;
     cells_phase(A, clist, n, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, P);
 }
 
@@ -437,11 +593,16 @@ struct TailArgs {
     unsigned stamp0;
 };
 
+constexpr int kTailThreads = 512;
+
 template <typename real>
-__global__ __launch_bounds__(256) void k_tail(const StageArgs<real> A, const TailArgs T)
+__global__ __launch_bounds__(kTailThreads) void k_tail(const StageArgs<real> A, const TailArgs T)
 {
+    __shared__ real wl[kGtabSize];
+    __shared__ FaceXchg<real> xch[kTailThreads / 64];
     const int capf = (A.nx + 1) * A.ny + A.nx * (A.ny + 1), capc = A.nx * A.ny;
     Ctl *ctl = T.ctl;
+    load_gtab(A.gtab, wl);
     int k = T.k0;
     for (; k < T.kend; ++k) {
         __syncthreads();  // the previous pass's lists, counts and fluxes are complete
@@ -450,7 +611,7 @@ __global__ __launch_bounds__(256) void k_tail(const StageArgs<real> A, const Tai
         nc = nc < capc ? nc : capc;
         nf = nf < capf ? nf : capf;
         if (nc <= 0) break;  // same value in every thread: the block leaves together
-        faces_phase(A, T.flist[k & 1], nf, threadIdx.x, blockDim.x);
+        faces_phase(A, wl, xch[threadIdx.x >> 6], T.flist[k & 1], nf, threadIdx.x, blockDim.x);
         __syncthreads();
         PassOut P;
         P.flist = T.flist[(k + 1) & 1];
@@ -647,7 +808,7 @@ template <typename real>
 hipError_t launch_cascade_pass(const StageArgs<real> &A, const int *flist, const int *fcount, const int *clist,
                                const int *ccount, const PassOut &P, int nblocks, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_faces<real>, dim3(nblocks), dim3(64), 0, st, A, flist, fcount);
+    hipLaunchKernelGGL(k_faces<real>, dim3(nblocks), dim3(256), 0, st, A, flist, fcount);
     hipLaunchKernelGGL(k_cells<real>, dim3(nblocks), dim3(64), 0, st, A, clist, ccount, P);
     return hipGetLastError();
 }
@@ -665,7 +826,7 @@ hipError_t launch_cascade_tail(const StageArgs<real> &A, int *const flist[2], in
     T.k0 = k0;
     T.kend = kend;
     T.stamp0 = stamp0;
-    hipLaunchKernelGGL(k_tail<real>, dim3(1), dim3(256), 0, st, A, T);
+    hipLaunchKernelGGL(k_tail<real>, dim3(1), dim3(kTailThreads), 0, st, A, T);
     return hipGetLastError();
 }
 

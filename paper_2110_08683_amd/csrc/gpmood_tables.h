@@ -48,6 +48,23 @@ constexpr int slots_of(int R) { return R == 0 ? 0 : (R == 1 ? 1 : 2); }
 // Is slot k the centre node (g = 0)?
 constexpr bool slot_is_zero(int R, int k) { return R == 2 && k == 1; }
 
+// Compact form for the cascade, which runs few faces per pass and is bound by
+// latency and instruction fetch rather than arithmetic: the quarter positions
+// (a, b) in the same order as kQ, radius R using the first kNP[R].  Each position
+// is gathered as its four mirror cells (+-a, +-b); on an axis the mirror copies
+// coincide, so its parity sums come out 2x (4x at the centre) and the table
+// weights carry the matching factor 1/2 (1/4), which keeps every product exact.
+constexpr int kNP[4] = {1, 3, 6, 10};
+constexpr int kNPos = 10;
+// a and b of position e, 4 bits each: (0,0) (1,0) (0,1) (2,0) (0,2) (1,1) (3,0) (0,3) (2,1) (1,2)
+constexpr unsigned long long kPosA = 0x1203102010ull;
+constexpr unsigned long long kPosB = 0x2130120100ull;
+// Table layout [R 0..3][dir 0..1][slot 0..1][position 0..9][component 0..3],
+// followed by the Gauss weights [R][slot] (R = 0: the single node, weight 1).
+constexpr int kGtabPerDir = 2 * kNPos * 4;
+constexpr int kGtabNodeOff = 4 * 2 * kGtabPerDir;
+constexpr int kGtabSize = kGtabNodeOff + 4 * 2;
+
 }  // namespace gpm
 
 #endif

@@ -43,3 +43,9 @@ def test_strerror_and_argument_errors_without_gpu():
     g.n[0], g.n[1] = 0, 4
     assert L.gpm_create(ctypes.byref(g), 0, None, ctypes.byref(ctx)) == B.GPM_EINVAL
     assert L.gpm_create(None, 0, None, ctypes.byref(ctx)) == B.GPM_EINVAL
+    # a periodic axis must hold the 4-cell reach of the widest stencil
+    g.n[0], g.n[1] = 3, 8
+    g.lo[0], g.lo[1], g.hi[0], g.hi[1] = 0.0, 0.0, 1.0, 1.0
+    g.bc[0], g.bc[1] = 0, 1
+    g.gamma = 1.4
+    assert L.gpm_create(ctypes.byref(g), 0, None, ctypes.byref(ctx)) == B.GPM_EUNSUPPORTED
