@@ -163,20 +163,28 @@ gpm_status gpm_totals(gpm_ctx *ctx, double totals[4]);
 /* Totals of an arbitrary device state (same layout as a slot).  Synchronising. */
 gpm_status gpm_totals_dev(gpm_ctx *ctx, const void *U, double totals[4]);
 
-/* Tunables: cascade passes launched between termination checks (>= 1) and rows
-   per wavefront march in the first pass (4..256).  Defaults 4 and 16. */
-gpm_status gpm_set_tuning(gpm_ctx *ctx, int passes_per_check, int rows_per_wave);
+/* Tunables.  The cascade of a stage is queued as a batch of multi-block passes
+   followed by a single-workgroup kernel that finishes it once a pass leaves at
+   most tail_threshold troubled cells (0..4096; it hands back to a new batch if a
+   pass leaves more than 4 x tail_threshold), with one host check per batch.
+   passes_per_check (1..128) is the smallest batch; the batch otherwise follows
+   the previous stage's number of multi-block passes.  rows_per_wave (4..256):
+   rows per wavefront march in the first pass.  Defaults 4, 16 and 48. */
+gpm_status gpm_set_tuning(gpm_ctx *ctx, int passes_per_check, int rows_per_wave, int tail_threshold);
 
-/* Instrumentation for measurement (not part of the method).  When enabled,
-   every first-pass launch and every stage's cascade are bracketed by HIP events
-   recorded on the context stream, and per-stage statistics (final-order counts
-   per cascade level, MOOD iterations) are accumulated on the device.  Enabling
-   resets the accumulators. */
-gpm_status gpm_instrument(gpm_ctx *ctx, int enable);
+/* Instrumentation for measurement (not part of the method).  mode bit 0: every
+   first-pass launch and every stage's cascade are bracketed by HIP events on the
+   context stream and MOOD iterations are counted on the host (no extra kernels);
+   bit 1 (implies bit 0): the final-order counts per cascade level are also
+   accumulated on the device (two small kernels per stage).  0 disables; a
+   non-zero mode resets the accumulators.  Errors: GPM_EINVAL for a mode outside
+   0..3. */
+gpm_status gpm_instrument(gpm_ctx *ctx, int mode);
 
 /* Read the accumulators (synchronising): first-pass time and launches, cascade
    time (from the end of the first pass to the end of the stage) and stages,
-   summed final-order counts per level and summed MOOD iterations. */
+   summed final-order counts per level (mode bit 1 only, else zeros) and summed
+   MOOD iterations. */
 gpm_status gpm_instrument_read(gpm_ctx *ctx, double *first_pass_ms, long long *first_pass_launches,
                                double *cascade_ms, long long *stages, long long level_cells[4],
                                long long *mood_iters);

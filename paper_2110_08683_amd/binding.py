@@ -73,7 +73,7 @@ def lib():
         "gpm_get_order_mask": ([ctxp, ctypes.POINTER(ctypes.c_ubyte)], st),
         "gpm_totals": ([ctxp, dp], st),
         "gpm_totals_dev": ([ctxp, vp, dp], st),
-        "gpm_set_tuning": ([ctxp, ctypes.c_int, ctypes.c_int], st),
+        "gpm_set_tuning": ([ctxp, ctypes.c_int, ctypes.c_int, ctypes.c_int], st),
         "gpm_instrument": ([ctxp, ctypes.c_int], st),
         "gpm_instrument_read": ([ctxp, dp, ctypes.POINTER(ctypes.c_longlong), dp, ctypes.POINTER(ctypes.c_longlong),
                                  ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)], st),
@@ -223,11 +223,12 @@ class GPMood:
         self._check(lib().gpm_totals_dev(self.ctx, ctypes.c_void_p(U.data_ptr()), _dp(t)))
         return t
 
-    def gpm_set_tuning(self, passes_per_check=4, rows_per_wave=16):
-        self._check(lib().gpm_set_tuning(self.ctx, int(passes_per_check), int(rows_per_wave)))
+    def gpm_set_tuning(self, passes_per_check=4, rows_per_wave=16, tail_threshold=48):
+        self._check(lib().gpm_set_tuning(self.ctx, int(passes_per_check), int(rows_per_wave), int(tail_threshold)))
 
-    def gpm_instrument(self, enable=True):
-        self._check(lib().gpm_instrument(self.ctx, int(bool(enable))))
+    def gpm_instrument(self, mode=1):
+        """mode 0: off, 1: events and iteration counts, 3: also final-order counts (True means 1)."""
+        self._check(lib().gpm_instrument(self.ctx, int(mode)))
 
     def gpm_instrument_read(self):
         fp, cm = ctypes.c_double(), ctypes.c_double()

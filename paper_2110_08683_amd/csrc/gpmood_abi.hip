@@ -60,14 +60,16 @@ struct gpm_ctx {
     double *partial = nullptr;
     void *gtab = nullptr;
     unsigned pass = 0;
-    int passes_per_check = 4;
-    int tail_threshold = 48;  // troubled cells below which the cascade finishes in one workgroup
+    int passes_per_check = 4;  // smallest batch of multi-block cascade passes
+    int head_guess = 4;        // batch length: the previous stage's multi-block passes + 2
+    int tail_threshold = 48;   // troubled cells at or below which one workgroup finishes the cascade
     int rows = 16;
     int last_npass = 0;
     bool fresh_ctl = true;
     int *pinned = nullptr;
     // instrumentation
-    bool instrument = false;
+    int instrument = 0;           // bit 0: stage events and iteration counts, bit 1: level statistics
+    long long acc_iters = 0, acc_stages = 0;
     std::vector<hipEvent_t> evs;  // 3 per instrumented stage: first pass start/end, stage end
     size_t nev_used = 0;
     std::string err;
@@ -377,12 +379,15 @@ gpm_status gpm_set_dt(gpm_ctx *c, double dt)
     return GPM_OK;
 }
 
-gpm_status gpm_set_tuning(gpm_ctx *c, int passes_per_check, int rows_per_wave)
+gpm_status gpm_set_tuning(gpm_ctx *c, int passes_per_check, int rows_per_wave, int tail_threshold)
 {
-    if (!c || passes_per_check < 1 || passes_per_check > 64 || rows_per_wave < 4 || rows_per_wave > 256)
+    if (!c || passes_per_check < 1 || passes_per_check > 128 || rows_per_wave < 4 || rows_per_wave > 256 ||
+        tail_threshold < 0 || tail_threshold > 4096)
         return GPM_EINVAL;
     c->passes_per_check = passes_per_check;
+    c->head_guess = passes_per_check;
     c->rows = rows_per_wave;
+    c->tail_threshold = tail_threshold;
     return GPM_OK;
 }
 
@@ -419,8 +424,9 @@ static void fill_args(const gpm_ctx *c, const Weights<real> &W, StageArgs<real> 
     for (int r = 0; r < 4; ++r) A.next[r] = c->next[r];
 }
 
-// Claim stamps grow monotonically; the stamp arrays are cleared at the start of a
-// stage when fewer than a stage's worth of stamps is left before the wrap.
+// Claim stamps grow monotonically (kMaxPasses + 2 per stage); the stamp arrays
+// are cleared at the start of a stage when fewer than a stage's worth is left
+// before the wrap.
 static gpm_status stamps_for_stage(gpm_ctx *c)
 {
     if (c->pass >= 0xffffffffu - (unsigned)(2 * kMaxPasses + 8)) {
@@ -428,12 +434,6 @@ static gpm_status stamps_for_stage(gpm_ctx *c)
         HIPCHK(c, hipMemsetAsync(c->fstamp, 0, 4 * (nfaces_x(c) + nfaces_y(c)), c->stream));
         c->pass = 0;
     }
-    return GPM_OK;
-}
-
-static gpm_status next_stamp(gpm_ctx *c, unsigned *out)
-{
-    *out = ++c->pass;
     return GPM_OK;
 }
 
@@ -460,17 +460,27 @@ static gpm_status run_stage(gpm_ctx *c, const Weights<real> &W, int s, const voi
     if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("reset: ") + hipGetErrorString(e));
     c->fresh_ctl = false;
 
-    // evaluation 0 (first pass) claims the faces and cells of cascade pass 1
+    // evaluation 0 (first pass) claims the faces and cells of cascade pass 1;
+    // pass k claims with stamp0 + k
     gpm_status st = stamps_for_stage(c);
     if (st != GPM_OK) return st;
+    Cascade C;
+    C.flist[0] = c->flist[0];
+    C.flist[1] = c->flist[1];
+    C.clist[0] = c->clist[0];
+    C.clist[1] = c->clist[1];
+    C.ctl = c->ctl;
+    C.stamp0 = c->pass + 1;
+    C.tail_thr = c->tail_threshold;
+    C.back_thr = 4 * c->tail_threshold;
+    c->pass += (unsigned)kMaxPasses + 2;
     PassOut P;
-    st = next_stamp(c, &P.stamp);
-    if (st != GPM_OK) return st;
     P.flist = c->flist[1];
     P.clist = c->clist[1];
     P.fcount = &c->ctl->nface[1];
     P.ccount = &c->ctl->ncell[1];
     P.tcount = &c->ctl->ntroub[0];
+    P.stamp = C.stamp0;
     hipEvent_t *ev = nullptr;
     if (c->instrument) {
         while (c->evs.size() < 3 * (c->nev_used + 1)) {
@@ -486,56 +496,55 @@ static gpm_status run_stage(gpm_ctx *c, const Weights<real> &W, int s, const voi
     if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("first pass: ") + hipGetErrorString(e));
     if (ev) HIPCHK(c, hipEventRecord(ev[1], c->stream));
 
-    // cascade passes, queued in batches and gated on the device counts
+    // Cascade: a batch of multi-block passes (each returns at once when it has no
+    // work or when the tail takes over), then the single-workgroup tail, then one
+    // host check.  The tail hands back when a pass grows large again; the batch
+    // length follows the previous stage's number of multi-block passes.
     int nb = (int)((c->ncell + 63) / 64);
     if (nb > 512) nb = 512;
     int k = 1;  // next cascade pass
-    int batch = c->passes_per_check;
+    int batch = c->head_guess;
     for (;;) {
-        HIPCHK(c, hipMemcpyAsync(c->pinned, &c->ctl->ntroub[k - 1], sizeof(int), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        if (*c->pinned == 0) break;
-        if (*c->pinned <= c->tail_threshold) {
-            // few troubled cells: finish in one workgroup without host round trips
-            const int kend = kMaxPasses;
-            const unsigned stamp0 = c->pass + 1;
-            c->pass += (unsigned)(kend - k) + 1;
-            e = launch_cascade_tail<real>(A, c->flist, c->clist, c->ctl, k, kend, stamp0, c->stream);
-            if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("cascade tail: ") + hipGetErrorString(e));
-            HIPCHK(c, hipMemcpyAsync(c->pinned, &c->ctl->tail_end, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(c, hipStreamSynchronize(c->stream));
-            k = *c->pinned;
-            if (k >= kend) {
-                c->last_npass = kend - 1;
-                return fail(c, GPM_ENOTCONV, "MOOD loop exceeded the pass limit");
-            }
-            break;
-        }
-        if (k + batch > kMaxPasses) {
+        if (k + batch > kMaxPasses - 1) batch = kMaxPasses - 1 - k;
+        if (batch < 0) {
             c->last_npass = k - 1;
             return fail(c, GPM_ENOTCONV, "MOOD loop exceeded the pass limit");
         }
-        const int nbatch = batch;
-        if (k > 4 * c->passes_per_check && batch < 64) batch *= 2;  // long cascades: fewer host checks
-        for (int b = 0; b < nbatch; ++b, ++k) {
-            st = next_stamp(c, &P.stamp);
-            if (st != GPM_OK) return st;
-            P.flist = c->flist[(k + 1) & 1];
-            P.clist = c->clist[(k + 1) & 1];
-            P.fcount = &c->ctl->nface[k + 1];
-            P.ccount = &c->ctl->ncell[k + 1];
-            P.tcount = &c->ctl->ntroub[k];
-            e = launch_cascade_pass<real>(A, c->flist[k & 1], &c->ctl->nface[k], c->clist[k & 1], &c->ctl->ncell[k],
-                                          P, nb, c->stream);
+        for (int b = 0; b < batch; ++b) {
+            e = launch_cascade_pass<real>(A, C, k + b, nb, c->stream);
             if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("cascade pass: ") + hipGetErrorString(e));
         }
+        e = launch_cascade_tail<real>(A, C, k, k + batch, kMaxPasses, c->stream);
+        if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("cascade tail: ") + hipGetErrorString(e));
+        HIPCHK(c, hipMemcpyAsync(c->pinned, &c->ctl->tail_end, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        const int tail_end = c->pinned[0], tail_k0 = c->pinned[1], back = c->pinned[2];
+        if (tail_end >= kMaxPasses) {
+            c->last_npass = kMaxPasses - 1;
+            return fail(c, GPM_ENOTCONV, "MOOD loop exceeded the pass limit");
+        }
+        if (!back) {
+            // multi-block passes this stage needed before the tail (or the end)
+            const int head = (tail_k0 > 0 ? tail_k0 : tail_end) - 1;
+            int g = head + 2;
+            g = g < c->passes_per_check ? c->passes_per_check : (g > 128 ? 128 : g);
+            c->head_guess = g;
+            k = tail_end;
+            break;
+        }
+        k = tail_end;
+        batch = batch < 8 ? 8 : (batch > 64 ? 128 : 2 * batch);
     }
     c->last_npass = k - 1;
     if (ev) {
-        st = level_counts(c);
-        if (st != GPM_OK) return st;
-        e = launch_stats(c->ctl, c->last_npass, 0, c->stream);
-        if (e != hipSuccess) return fail(c, GPM_EHIP, hipGetErrorString(e));
+        c->acc_iters += c->last_npass + 1;
+        c->acc_stages += 1;
+        if (c->instrument & 2) {
+            st = level_counts(c);
+            if (st != GPM_OK) return st;
+            e = launch_stats(c->ctl, c->last_npass, 0, c->stream);
+            if (e != hipSuccess) return fail(c, GPM_EHIP, hipGetErrorString(e));
+        }
         HIPCHK(c, hipEventRecord(ev[2], c->stream));
     }
     return GPM_OK;
@@ -634,13 +643,16 @@ gpm_status gpm_instrument(gpm_ctx *c, int enable)
 {
     if (!c) return GPM_EINVAL;
     if (!c->state) return fail(c, GPM_ESTATE, "not bound");
+    if (enable < 0 || enable > 3) return fail(c, GPM_EINVAL, "instrument mode must be 0..3");
     if (enable) {
         hipError_t e = launch_stats(c->ctl, 0, 1, c->stream);
         if (e != hipSuccess) return fail(c, GPM_EHIP, hipGetErrorString(e));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         c->nev_used = 0;
+        c->acc_iters = 0;
+        c->acc_stages = 0;
     }
-    c->instrument = enable != 0;
+    c->instrument = enable == 2 ? 3 : enable;
     return GPM_OK;
 }
 
@@ -667,7 +679,7 @@ gpm_status gpm_instrument_read(gpm_ctx *c, double *first_pass_ms, long long *fir
     if (stages) *stages = (long long)c->nev_used;
     if (level_cells)
         for (int l = 0; l < 4; ++l) level_cells[l] = (long long)acc[l];
-    if (mood_iters) *mood_iters = (long long)acc[4];
+    if (mood_iters) *mood_iters = c->acc_iters;
     return GPM_OK;
 }
 

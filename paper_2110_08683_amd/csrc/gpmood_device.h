@@ -68,6 +68,7 @@ struct StageArgs {
 
 // Outputs of one evaluation: the troubled count, and the faces and cells that the
 // next cascade pass recomputes (claimed with `stamp`, unique per evaluation).
+// The counters are updated with generic-address atomics and may live in LDS.
 struct PassOut {
     int *flist;
     int *fcount;
@@ -89,7 +90,24 @@ struct Ctl {
     unsigned long long acc_lev[4];  // instrumentation: summed final-order counts
     unsigned long long acc_iters;   // summed MOOD iterations
     unsigned long long acc_stages;
-    int tail_end;                   // first pass index the single-block tail did not need
+    // cascade control, written by the pass kernels and the single-workgroup tail
+    int tail_end;     // first pass the tail did not run
+    int tail_k0;      // first pass left to the tail by the multi-block passes (0: none)
+    int tail_back;    // 1: the tail stopped at tail_end because the pass grew large
+};
+
+// Control of the cascade passes of one stage.  Pass k reads lists [k & 1] with
+// counts nface[k], ncell[k] and writes lists [(k + 1) & 1]; its claims carry the
+// stamp stamp0 + k (the first pass: stamp0).  A multi-block pass whose previous
+// evaluation left at most tail_thr troubled cells does nothing and records itself
+// in tail_k0: the single-workgroup tail runs from there.  The tail hands back
+// (tail_back) at a pass whose previous evaluation left more than back_thr.
+struct Cascade {
+    int *flist[2];
+    int *clist[2];
+    Ctl *ctl;
+    unsigned stamp0;
+    int tail_thr, back_thr;
 };
 
 // ------------------------------------------------------------------ helpers
@@ -359,9 +377,9 @@ __device__ __forceinline__ void wave_reserve2(int n, int *count0, int *count1, i
     }
     const int tot = __shfl(incl, 63);
     int b0 = 0, b1 = 0;
-    if (lane == 63) {
-        if (tot & 0xffff) b0 = atomicAdd(count0, tot & 0xffff);
-        if (tot >> 16) b1 = atomicAdd(count1, tot >> 16);
+    if (lane == 63 && tot != 0) {  // both issued before either result is used
+        b0 = atomicAdd(count0, tot & 0xffff);
+        b1 = atomicAdd(count1, tot >> 16);
     }
     b0 = __shfl(b0, 63);
     b1 = __shfl(b1, 63);

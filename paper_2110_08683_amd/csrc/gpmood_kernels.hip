@@ -57,28 +57,45 @@ __device__ __forceinline__ void claim_after_lowering(const StageArgs<real> &A, c
     fid[1] = j * (nx + 1) + i + 1;
     fid[2] = nfx + j * nx + i;
     fid[3] = nfx + (j + 1) * nx + i;
-    fok[0] = fok[1] = fok[2] = fok[3] = act;
-    fid[4] = i == 0 ? j * (nx + 1) + nx : j * (nx + 1);          // copy of face 0 / face nx
-    fok[4] = act && A.bcx == 0 && (i == 0 || i == nx - 1);
-    fid[5] = j == 0 ? nfx + ny * nx + i : nfx + i;                // copy of face 0 / face ny
-    fok[5] = act && A.bcy == 0 && (j == 0 || j == ny - 1);
-    bool fmine[6];
-    int nmine = 0;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        fmine[k] = fok[k] && atomicMax(&A.fstamp[fid[k]], P.stamp) < P.stamp;
-        nmine += fmine[k] ? 1 : 0;
-    }
+    fok[0] = fok[1] = fok[2] = fok[3] = true;
+    fok[4] = A.bcx == 0 && (i == 0 || i == nx - 1);
+    fid[4] = fok[4] ? (i == 0 ? j * (nx + 1) + nx : j * (nx + 1)) : fid[0];  // copy of face 0 / face nx
+    fok[5] = A.bcy == 0 && (j == 0 || j == ny - 1);
+    fid[5] = fok[5] ? (j == 0 ? nfx + ny * nx + i : nfx + i) : fid[2];      // copy of face 0 / face ny
     const int di[5] = {0, -1, 1, 0, 0}, dj[5] = {0, 0, 0, -1, 1};
     int cid[5];
-    bool cmine[5];
+    bool cok[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
         const int ii = i + di[k], jj = j + dj[k];
-        const bool inside = (A.bcx == 0 || (ii >= 0 && ii < nx)) && (A.bcy == 0 || (jj >= 0 && jj < ny));
-        cid[k] = (act && inside) ? wrap(jj, ny, A.bcy) * nx + wrap(ii, nx, A.bcx) : 0;
-        cmine[k] = act && inside && atomicMax(&A.cstamp[cid[k]], P.stamp) < P.stamp;
-        nmine += cmine[k] ? 65536 : 0;
+        cok[k] = (A.bcx == 0 || (ii >= 0 && ii < nx)) && (A.bcy == 0 || (jj >= 0 && jj < ny));
+        cid[k] = cok[k] ? wrap(jj, ny, A.bcy) * nx + wrap(ii, nx, A.bcx) : j * nx + i;
+    }
+    bool fmine[6], cmine[5];
+    int nmine = 0;
+    if (act) {
+        // all eleven stamp updates are issued back to back; an entry that does not
+        // apply updates its own cell or face with 0, which changes nothing
+        unsigned fo[6], co[5];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) fo[k] = atomicMax(&A.fstamp[fid[k]], fok[k] ? P.stamp : 0u);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) co[k] = atomicMax(&A.cstamp[cid[k]], cok[k] ? P.stamp : 0u);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            fmine[k] = fok[k] && fo[k] < P.stamp;
+            nmine += fmine[k] ? 1 : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            cmine[k] = cok[k] && co[k] < P.stamp;
+            nmine += cmine[k] ? 65536 : 0;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) fmine[k] = false;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) cmine[k] = false;
     }
     int fb, cb;
     wave_reserve2(nmine, P.fcount, P.ccount, fb, cb);
@@ -556,73 +573,132 @@ __device__ __forceinline__ void cells_phase(const StageArgs<real> &A, const int 
     }
 }
 
+// Outputs of cascade pass k.
+__device__ __forceinline__ PassOut pass_out(const Cascade &C, int k)
+{
+    PassOut P;
+    P.flist = C.flist[(k + 1) & 1];
+    P.fcount = &C.ctl->nface[k + 1];
+    P.clist = C.clist[(k + 1) & 1];
+    P.ccount = &C.ctl->ncell[k + 1];
+    P.tcount = &C.ctl->ntroub[k];
+    P.stamp = C.stamp0 + (unsigned)k;
+    return P;
+}
+
+// Does multi-block pass k run?  Not when it has nothing to do, nor when the
+// previous evaluation left few troubled cells (the tail takes over from k).
+__device__ __forceinline__ bool pass_runs(const Cascade &C, int k)
+{
+    return C.ctl->ncell[k] > 0 && C.ctl->ntroub[k - 1] > C.tail_thr;
+}
+
 template <typename real>
-__global__ __launch_bounds__(256) void k_faces(const StageArgs<real> A, const int *flist, const int *fcount)
+__global__ __launch_bounds__(256) void k_faces(const StageArgs<real> A, const Cascade C, int k)
 {
     __shared__ real wl[kGtabSize];
     __shared__ FaceXchg<real> xch[4];
+    if (!pass_runs(C, k)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0 && C.ctl->ncell[k] > 0) C.ctl->tail_k0 = k;
+        return;
+    }
     const int cap = (A.nx + 1) * A.ny + A.nx * (A.ny + 1);
-    int n = *fcount;
+    int n = C.ctl->nface[k];
     n = n < cap ? n : cap;  // a list holds each face at most once
     if (4 * n <= (int)(blockIdx.x * blockDim.x)) return;  // no face for this block
     load_gtab(A.gtab, wl);
     __syncthreads();
-    faces_phase(A, wl, xch[threadIdx.x >> 6], flist, n, blockIdx.x * blockDim.x + threadIdx.x,
+    faces_phase(A, wl, xch[threadIdx.x >> 6], C.flist[k & 1], n, blockIdx.x * blockDim.x + threadIdx.x,
                 gridDim.x * blockDim.x);
 }
 
 template <typename real>
-__global__ __launch_bounds__(64) void k_cells(const StageArgs<real> A, const int *clist, const int *ccount,
-                                              const PassOut P)
+__global__ __launch_bounds__(64) void k_cells(const StageArgs<real> A, const Cascade C, int k)
 {
-    int n = *ccount;
+    if (!pass_runs(C, k)) return;
+    int n = C.ctl->ncell[k];
     n = n < A.nx * A.ny ? n : A.nx * A.ny;  // a list holds each cell at most once
     if (n <= (int)(blockIdx.x * blockDim.x)) return;
-    cells_phase(A, clist, n, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, P);
+    cells_phase(A, C.clist[k & 1], n, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x,
+                pass_out(C, k));
 }
 
 // The tail of a long cascade (few troubled cells per pass) in one workgroup:
-// passes k0, k0+1, ... run back to back with block barriers, until a pass has no
-// cell to re-evaluate (recorded in ctl->tail_end) or kend is reached.  Pass k's
-// claims use stamp0 + (k - k0).
-struct TailArgs {
-    int *flist[2];
-    int *clist[2];
-    Ctl *ctl;
-    int k0, kend;
-    unsigned stamp0;
-};
-
+// passes run back to back with block barriers, from tail_k0 (or kdef when the
+// multi-block passes did not hand over), until a pass has no cell to re-evaluate,
+// kend is reached, or the previous evaluation left more than back_thr troubled
+// cells (hand back to the multi-block passes).  The counts of the running passes
+// stay in LDS and are copied to the control block as each pass completes.
 constexpr int kTailThreads = 512;
 
 template <typename real>
-__global__ __launch_bounds__(kTailThreads) void k_tail(const StageArgs<real> A, const TailArgs T)
+__global__ __launch_bounds__(kTailThreads) void k_tail(const StageArgs<real> A, const Cascade C, int kbeg, int kdef,
+                                                       int kend)
 {
     __shared__ real wl[kGtabSize];
     __shared__ FaceXchg<real> xch[kTailThreads / 64];
+    // [pass parity][faces, cells, troubled cells of the previous evaluation]
+    __shared__ int cnt[2][3];
     const int capf = (A.nx + 1) * A.ny + A.nx * (A.ny + 1), capc = A.nx * A.ny;
-    Ctl *ctl = T.ctl;
+    Ctl *ctl = C.ctl;
     load_gtab(A.gtab, wl);
-    int k = T.k0;
-    for (; k < T.kend; ++k) {
+    int k0 = ctl->tail_k0 > 0 ? ctl->tail_k0 : kdef;
+    if (ctl->tail_k0 <= 0) {
+        // no hand-over: the cascade either ended inside the batch kbeg..kdef-1 (at
+        // the first pass with no cell) or continues at kdef
+        __shared__ int kfirst;
+        if (threadIdx.x == 0) kfirst = kdef;
+        __syncthreads();
+        for (int kk = kbeg + (int)threadIdx.x; kk < kdef; kk += blockDim.x)
+            if (ctl->ncell[kk] <= 0) atomicMin(&kfirst, kk);
+        __syncthreads();
+        k0 = kfirst;
+    }
+    if (threadIdx.x == 0) {
+        cnt[k0 & 1][0] = ctl->nface[k0];
+        cnt[k0 & 1][1] = ctl->ncell[k0];
+        cnt[k0 & 1][2] = ctl->ntroub[k0 - 1];
+    }
+    int k = k0;
+    bool back = false;
+    for (; k < kend; ++k) {
         __syncthreads();  // the previous pass's lists, counts and fluxes are complete
-        int nc = __hip_atomic_load(&ctl->ncell[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        int nf = __hip_atomic_load(&ctl->nface[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int nf = cnt[k & 1][0], nc = cnt[k & 1][1];
+        const int nt = cnt[k & 1][2];
+        if (threadIdx.x == 0 && k > k0) {
+            ctl->nface[k] = nf;
+            ctl->ncell[k] = nc;
+            ctl->ntroub[k - 1] = nt;
+        }
         nc = nc < capc ? nc : capc;
         nf = nf < capf ? nf : capf;
-        if (nc <= 0) break;  // same value in every thread: the block leaves together
-        faces_phase(A, wl, xch[threadIdx.x >> 6], T.flist[k & 1], nf, threadIdx.x, blockDim.x);
+        if (nc <= 0) break;  // same values in every thread: the block leaves together
+        if (nt > C.back_thr) {
+            back = true;
+            break;
+        }
+        if (threadIdx.x == 0) cnt[(k + 1) & 1][0] = cnt[(k + 1) & 1][1] = cnt[(k + 1) & 1][2] = 0;
+        faces_phase(A, wl, xch[threadIdx.x >> 6], C.flist[k & 1], nf, threadIdx.x, blockDim.x);
         __syncthreads();
-        PassOut P;
-        P.flist = T.flist[(k + 1) & 1];
-        P.fcount = &ctl->nface[k + 1];
-        P.clist = T.clist[(k + 1) & 1];
-        P.ccount = &ctl->ncell[k + 1];
-        P.tcount = &ctl->ntroub[k];
-        P.stamp = T.stamp0 + (unsigned)(k - T.k0);
-        cells_phase(A, T.clist[k & 1], nc, threadIdx.x, blockDim.x, P);
+        PassOut P = pass_out(C, k);
+        P.fcount = &cnt[(k + 1) & 1][0];
+        P.ccount = &cnt[(k + 1) & 1][1];
+        P.tcount = &cnt[(k + 1) & 1][2];
+        cells_phase(A, C.clist[k & 1], nc, threadIdx.x, blockDim.x, P);
     }
-    if (threadIdx.x == 0) ctl->tail_end = k;
+    if (k >= kend) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            ctl->nface[k] = cnt[k & 1][0];
+            ctl->ncell[k] = cnt[k & 1][1];
+            ctl->ntroub[k - 1] = cnt[k & 1][2];
+        }
+    }
+    if (threadIdx.x == 0) {
+        ctl->tail_end = k;
+        ctl->tail_back = back ? 1 : 0;
+        if (back) ctl->tail_k0 = 0;  // the next multi-block batch starts afresh
+    }
 }
 
 // -------------------------------------------------------- small kernels
@@ -632,6 +708,11 @@ __global__ void k_reset(Ctl *ctl, int nzero)
         ctl->nface[k] = 0;
         ctl->ncell[k] = 0;
         ctl->ntroub[k] = 0;
+    }
+    if (threadIdx.x == 0) {
+        ctl->tail_end = 0;
+        ctl->tail_k0 = 0;
+        ctl->tail_back = 0;
     }
 }
 
@@ -805,28 +886,18 @@ hipError_t launch_first_pass(const StageArgs<real> &A, const PassOut &P, hipStre
 }
 
 template <typename real>
-hipError_t launch_cascade_pass(const StageArgs<real> &A, const int *flist, const int *fcount, const int *clist,
-                               const int *ccount, const PassOut &P, int nblocks, hipStream_t st)
+hipError_t launch_cascade_pass(const StageArgs<real> &A, const Cascade &C, int k, int nblocks, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_faces<real>, dim3(nblocks), dim3(256), 0, st, A, flist, fcount);
-    hipLaunchKernelGGL(k_cells<real>, dim3(nblocks), dim3(64), 0, st, A, clist, ccount, P);
+    hipLaunchKernelGGL(k_faces<real>, dim3(nblocks), dim3(256), 0, st, A, C, k);
+    hipLaunchKernelGGL(k_cells<real>, dim3(nblocks), dim3(64), 0, st, A, C, k);
     return hipGetLastError();
 }
 
 template <typename real>
-hipError_t launch_cascade_tail(const StageArgs<real> &A, int *const flist[2], int *const clist[2], Ctl *ctl, int k0,
-                               int kend, unsigned stamp0, hipStream_t st)
+hipError_t launch_cascade_tail(const StageArgs<real> &A, const Cascade &C, int kbeg, int kdef, int kend,
+                               hipStream_t st)
 {
-    TailArgs T;
-    T.flist[0] = flist[0];
-    T.flist[1] = flist[1];
-    T.clist[0] = clist[0];
-    T.clist[1] = clist[1];
-    T.ctl = ctl;
-    T.k0 = k0;
-    T.kend = kend;
-    T.stamp0 = stamp0;
-    hipLaunchKernelGGL(k_tail<real>, dim3(1), dim3(kTailThreads), 0, st, A, T);
+    hipLaunchKernelGGL(k_tail<real>, dim3(1), dim3(kTailThreads), 0, st, A, C, kbeg, kdef, kend);
     return hipGetLastError();
 }
 
@@ -881,14 +952,11 @@ hipError_t launch_totals(const real *U, size_t ncell, double area, double *parti
 
 template hipError_t launch_first_pass<float>(const StageArgs<float> &, const PassOut &, hipStream_t);
 template hipError_t launch_first_pass<double>(const StageArgs<double> &, const PassOut &, hipStream_t);
-template hipError_t launch_cascade_pass<float>(const StageArgs<float> &, const int *, const int *, const int *,
-                                               const int *, const PassOut &, int, hipStream_t);
-template hipError_t launch_cascade_pass<double>(const StageArgs<double> &, const int *, const int *, const int *,
-                                                const int *, const PassOut &, int, hipStream_t);
-template hipError_t launch_cascade_tail<float>(const StageArgs<float> &, int *const[2], int *const[2], Ctl *, int, int,
-                                               unsigned, hipStream_t);
-template hipError_t launch_cascade_tail<double>(const StageArgs<double> &, int *const[2], int *const[2], Ctl *, int,
-                                                int, unsigned, hipStream_t);
+template hipError_t launch_cascade_pass<float>(const StageArgs<float> &, const Cascade &, int, int, hipStream_t);
+template hipError_t launch_cascade_pass<double>(const StageArgs<double> &, const Cascade &, int, int, hipStream_t);
+template hipError_t launch_cascade_tail<float>(const StageArgs<float> &, const Cascade &, int, int, int, hipStream_t);
+template hipError_t launch_cascade_tail<double>(const StageArgs<double> &, const Cascade &, int, int, int,
+                                                hipStream_t);
 template hipError_t launch_dt<float>(const float *, size_t, double, double, double, double, Ctl *, hipStream_t);
 template hipError_t launch_dt<double>(const double *, size_t, double, double, double, double, Ctl *, hipStream_t);
 template hipError_t launch_totals<float>(const float *, size_t, double, double *, int, Ctl *, hipStream_t);

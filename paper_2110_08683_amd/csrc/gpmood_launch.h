@@ -11,11 +11,10 @@ namespace gpm {
 template <typename real>
 hipError_t launch_first_pass(const StageArgs<real> &A, const PassOut &P, hipStream_t st);
 template <typename real>
-hipError_t launch_cascade_pass(const StageArgs<real> &A, const int *flist, const int *fcount, const int *clist,
-                               const int *ccount, const PassOut &P, int nblocks, hipStream_t st);
+hipError_t launch_cascade_pass(const StageArgs<real> &A, const Cascade &C, int k, int nblocks, hipStream_t st);
 template <typename real>
-hipError_t launch_cascade_tail(const StageArgs<real> &A, int *const flist[2], int *const clist[2], Ctl *ctl, int k0,
-                               int kend, unsigned stamp0, hipStream_t st);
+hipError_t launch_cascade_tail(const StageArgs<real> &A, const Cascade &C, int kbeg, int kdef, int kend,
+                               hipStream_t st);
 hipError_t launch_reset(Ctl *ctl, int nzero, hipStream_t st);
 hipError_t launch_level_hist(const uint8_t *order, size_t ncell, const LevIdx &levidx, Ctl *ctl, hipStream_t st);
 template <typename real>
