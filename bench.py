@@ -14,7 +14,9 @@ is the headline value; the FP64 path is reported beside it.
 The roofline object is for the dominant kernel (the first pass at the top order),
 whose launches are bracketed by HIP events on the library's stream during the
 timed region.  The kernel is bound by vector ALU work, so `achieved` is its
-algorithmic flop count per launch divided by its mean launch time.
+algorithmic flop count per launch (4.4 kflop per cell x 2048^2 cells) divided by
+its mean launch time; `traffic` is the HBM bytes per launch measured with
+rocprofv3 counters for the current kernel sources (null if they changed).
 cpu_baseline times the plain FP64 oracle (OpenMP over rows, all host cores) on the
 first two steps of the same 2048^2 problem, about 15-20 s of CPU work.
 
@@ -38,27 +40,47 @@ CASCADE = (3, 2, 1, 0)
 CFL = 0.8
 ORDER_SAMPLE_STEPS = 5   # untimed steps after the timed region that sample the final-order fractions
 CPU_STEPS = 2            # full SSP-RK3 steps of the oracle for the CPU baseline
+COPY_PROBE_BYTES = 512 << 20
 METRIC = "cell-updates/s per RK stage (GP-MOOD7 2D, incl. cascade), % HBM peak; FP32 vs FP64"
 
-# Algorithmic work of one cell in the first pass at radius 3, as formulated here
-# (quarter-basis reconstruction; FMA = 2 flops, a division or square root = 1):
-#   reconstruction, per variable: 36 adds (parity sums) + 4 x (25 FMA + 8 adds)
-#     = 268 flops; x 4 variables                                     = 1072
-#   HLLC, 8 solves per cell (2 owned faces x 4 Gauss nodes), 98 each  =  784
-#   Gauss quadrature sums, 8 x 4 FMA                                   =   64
-#   flux differences, candidate update                                 =   28
-#   RK combination (average over the three stages)                     =    8
-FLOPS_PER_CELL = {3: 1956}
-# HBM bytes per cell per stage that the first pass must move (FP32 / FP64):
-# read U_s (4 values), write U_out (4 values) and the order byte, plus U^n
-# (4 values) in stages 1 and 2: averaged over the three stages.
+# Algorithmic work of one cell-stage of the first pass at radius 3 (GP-MOOD7 2D),
+# the method as stated: 4 faces x 4 Gauss nodes x 4 variables x 25-long dot
+# products = 1600 FMA = 3200 flop, 8 HLLC solves (~90 flop + 5 div + 2 sqrt
+# each), ~300 flop of Riemann-state checks, detection and update: ~4.4 kflop.
+ALGO_FLOPS_PER_CELL = 4400
+# What this build executes per cell with the quarter-basis form (FMA = 2 flop,
+# a division or square root = 1): reconstruction 4 x (36 adds + 4 x (25 FMA + 8
+# adds)) = 1072, HLLC 8 x 98 = 784, quadrature 8 x 4 FMA = 64, update 28,
+# RK combination (mean over stages) 8.
+EXEC_FLOPS_PER_CELL = 1956
+
+
 def bytes_per_cell(esz):
-    return (4 * esz + 4 * esz + 1) + (2.0 / 3.0) * 4 * esz
+    """Minimal HBM bytes per cell-stage of the first pass: read U_s (4 values),
+    U^n in stages 1 and 2 (4 values, 2/3 on average), write U_out (4 values) and
+    the order byte."""
+    return 4 * esz + (2.0 / 3.0) * 4 * esz + 4 * esz + 1
 
 
-PEAK = {"f32": 157.3e12, "f64": 78.6e12}   # published vector peaks (FP32 with packed math)
+PEAK = {"f32": 157.3e12, "f64": 78.6e12}   # published vector peaks (FP32: packed math)
 PEAK_UNPACKED = 78.6e12                     # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 HBM_PEAK = 8.0e12
+
+# HBM bytes per first-pass launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
+# (mean over the launches of 3 steps, so 1/3 stage-0 launches that read no U^n),
+# scaled by the counters' reading of a 512 MiB device copy (FETCH x 2.0, WRITE x
+# 1.0).  Valid for the kernel sources with this hash only; see profiles/.
+TRAFFIC = {"src": "58acef9f349e8ca8", "f32": 355.3e6, "f64": None}
+KERNEL_SOURCES = ["gpmood_kernels.hip", "gpmood_device.h", "gpmood_tables.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2110_08683_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def run_gpu(prec, steps, warmup, U0):
@@ -105,23 +127,25 @@ def roofline(prec, res):
     esz = 4 if prec == "f32" else 8
     cells = N * N
     t = res["first_pass_ms_mean"] * 1e-3
-    flops = FLOPS_PER_CELL[CASCADE[0]] * cells
-    achieved = flops / t
-    hbm = bytes_per_cell(esz) * cells / t
+    achieved = ALGO_FLOPS_PER_CELL * cells / t
+    traffic = TRAFFIC.get(prec) if TRAFFIC["src"] == kernel_source_hash() else None
     return {
         "bound": "alu",
-        "kernel": "k_first_pass<%s,R=3>" % ("float" if prec == "f32" else "double"),
         "achieved": achieved / 1e12,
         "peak": PEAK[prec] / 1e12,
         "unit": "TFLOP/s",
         "frac": achieved / PEAK[prec],
-        "frac_of_unpacked_peak": achieved / PEAK_UNPACKED,
-        "flops_per_cell": FLOPS_PER_CELL[CASCADE[0]],
+        "traffic": traffic,
+        "kernel": "k_first_pass<%s,R=3>" % ("float" if prec == "f32" else "double"),
+        "flops_per_cell": ALGO_FLOPS_PER_CELL,
         "cells_per_launch": cells,
         "mean_launch_ms": res["first_pass_ms_mean"],
-        "hbm_algorithmic_GBps": hbm / 1e9,
-        "hbm_frac": hbm / HBM_PEAK,
-        "traffic": None,
+        "executed_flops_per_cell": EXEC_FLOPS_PER_CELL,
+        "executed_TFLOPs": EXEC_FLOPS_PER_CELL * cells / t / 1e12,
+        "frac_of_unpacked_peak": achieved / (PEAK_UNPACKED if prec == "f32" else PEAK[prec]),
+        "hbm_algorithmic_GBps": bytes_per_cell(esz) * cells / t / 1e9,
+        "hbm_measured_GBps": None if traffic is None else traffic / t / 1e9,
+        "hbm_frac": bytes_per_cell(esz) * cells / t / HBM_PEAK,
     }
 
 
@@ -145,11 +169,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 512 MiB device copy (calibrates HBM byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {a.gpus})", file=sys.stderr)
         sys.exit(2)
     import gpmood_inputs as gi
+    if a.copy_probe:
+        import torch
+        src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy probe: 3 copies of {COPY_PROBE_BYTES} bytes", file=sys.stderr, flush=True)
+        del src, dst
     U0 = gi.quadrants(N, N, seed=SEED)
     print(f"[bench] fp32 {a.steps} steps after {a.warmup} warmup", file=sys.stderr, flush=True)
     r32 = run_gpu("f32", a.steps, a.warmup, U0)

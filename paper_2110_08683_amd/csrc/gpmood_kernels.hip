@@ -109,19 +109,18 @@ __device__ __forceinline__ void claim_after_lowering(const StageArgs<real> &A, c
     }
 }
 
-template <typename real, int RT, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_first_pass(const StageArgs<real> A, const PassOut P)
+// One wavefront's strip (tile wid of the problem) of the first pass; ring is the
+// wavefront's LDS ring.
+template <typename real, int RT>
+__device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const PassOut &P, int wid,
+                                                real (*ring)[4][LW])
 {
     constexpr int q = nodes_of(RT);
     constexpr int NQ = kNQ[RT];
-    __shared__ real ring_all[WPB][8][4][LW];
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    real(*ring)[4][LW] = ring_all[wv];
 
     const int nx = A.nx, ny = A.ny, T = A.rows;
     const int nstrip = (nx + 61) / 62, nseg = (ny + T - 1) / T;
-    const int wid = xcd_tile(blockIdx.x, gridDim.x) * WPB + wv;
     if (wid >= nstrip * nseg) return;  // whole wavefront leaves together
     const int sx = wid % nstrip, sy = wid / nstrip;
     const int x0 = sx * 62, y0 = sy * T;
@@ -283,6 +282,14 @@ __global__ __launch_bounds__(64 * WPB) void k_first_pass(const StageArgs<real> A
         store_row(j + 4, pf);
         wave_lds_sync();
     }
+}
+
+template <typename real, int RT, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_first_pass(const StageArgs<real> A, const PassOut P)
+{
+    __shared__ real ring_all[WPB][8][4][LW];
+    const int wv = threadIdx.x >> 6;
+    first_pass_wave<real, RT>(A, P, xcd_tile(blockIdx.x, gridDim.x) * WPB + wv, ring_all[wv]);
 }
 
 // ------------------------------------------------------------- cascade pass
@@ -631,40 +638,44 @@ __global__ __launch_bounds__(64) void k_cells(const StageArgs<real> A, const Cas
 // stay in LDS and are copied to the control block as each pass completes.
 constexpr int kTailThreads = 512;
 
+// LDS of the single-workgroup cascade.
 template <typename real>
-__global__ __launch_bounds__(kTailThreads) void k_tail(const StageArgs<real> A, const Cascade C, int kbeg, int kdef,
-                                                       int kend)
+struct TailShared {
+    real wl[kGtabSize];
+    FaceXchg<real> xch[kTailThreads / 64];
+    int cnt[2][3];  // [pass parity][faces, cells, troubled cells of the previous evaluation]
+    int kfirst;
+};
+
+template <typename real>
+__device__ __forceinline__ void tail_body(const StageArgs<real> &A, const Cascade &C, int kbeg, int kdef, int kend,
+                                          TailShared<real> &S)
 {
-    __shared__ real wl[kGtabSize];
-    __shared__ FaceXchg<real> xch[kTailThreads / 64];
-    // [pass parity][faces, cells, troubled cells of the previous evaluation]
-    __shared__ int cnt[2][3];
     const int capf = (A.nx + 1) * A.ny + A.nx * (A.ny + 1), capc = A.nx * A.ny;
     Ctl *ctl = C.ctl;
-    load_gtab(A.gtab, wl);
+    load_gtab(A.gtab, S.wl);
     int k0 = ctl->tail_k0 > 0 ? ctl->tail_k0 : kdef;
-    if (ctl->tail_k0 <= 0) {
+    if (ctl->tail_k0 <= 0 && kbeg < kdef) {
         // no hand-over: the cascade either ended inside the batch kbeg..kdef-1 (at
         // the first pass with no cell) or continues at kdef
-        __shared__ int kfirst;
-        if (threadIdx.x == 0) kfirst = kdef;
+        if (threadIdx.x == 0) S.kfirst = kdef;
         __syncthreads();
         for (int kk = kbeg + (int)threadIdx.x; kk < kdef; kk += blockDim.x)
-            if (ctl->ncell[kk] <= 0) atomicMin(&kfirst, kk);
+            if (ctl->ncell[kk] <= 0) atomicMin(&S.kfirst, kk);
         __syncthreads();
-        k0 = kfirst;
+        k0 = S.kfirst;
     }
     if (threadIdx.x == 0) {
-        cnt[k0 & 1][0] = ctl->nface[k0];
-        cnt[k0 & 1][1] = ctl->ncell[k0];
-        cnt[k0 & 1][2] = ctl->ntroub[k0 - 1];
+        S.cnt[k0 & 1][0] = ctl->nface[k0];
+        S.cnt[k0 & 1][1] = ctl->ncell[k0];
+        S.cnt[k0 & 1][2] = ctl->ntroub[k0 - 1];
     }
     int k = k0;
     bool back = false;
     for (; k < kend; ++k) {
         __syncthreads();  // the previous pass's lists, counts and fluxes are complete
-        int nf = cnt[k & 1][0], nc = cnt[k & 1][1];
-        const int nt = cnt[k & 1][2];
+        int nf = S.cnt[k & 1][0], nc = S.cnt[k & 1][1];
+        const int nt = S.cnt[k & 1][2];
         if (threadIdx.x == 0 && k > k0) {
             ctl->nface[k] = nf;
             ctl->ncell[k] = nc;
@@ -677,21 +688,21 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const StageArgs<real> A, 
             back = true;
             break;
         }
-        if (threadIdx.x == 0) cnt[(k + 1) & 1][0] = cnt[(k + 1) & 1][1] = cnt[(k + 1) & 1][2] = 0;
-        faces_phase(A, wl, xch[threadIdx.x >> 6], C.flist[k & 1], nf, threadIdx.x, blockDim.x);
+        if (threadIdx.x == 0) S.cnt[(k + 1) & 1][0] = S.cnt[(k + 1) & 1][1] = S.cnt[(k + 1) & 1][2] = 0;
+        faces_phase(A, S.wl, S.xch[threadIdx.x >> 6], C.flist[k & 1], nf, threadIdx.x, blockDim.x);
         __syncthreads();
         PassOut P = pass_out(C, k);
-        P.fcount = &cnt[(k + 1) & 1][0];
-        P.ccount = &cnt[(k + 1) & 1][1];
-        P.tcount = &cnt[(k + 1) & 1][2];
+        P.fcount = &S.cnt[(k + 1) & 1][0];
+        P.ccount = &S.cnt[(k + 1) & 1][1];
+        P.tcount = &S.cnt[(k + 1) & 1][2];
         cells_phase(A, C.clist[k & 1], nc, threadIdx.x, blockDim.x, P);
     }
     if (k >= kend) {
         __syncthreads();
         if (threadIdx.x == 0) {
-            ctl->nface[k] = cnt[k & 1][0];
-            ctl->ncell[k] = cnt[k & 1][1];
-            ctl->ntroub[k - 1] = cnt[k & 1][2];
+            ctl->nface[k] = S.cnt[k & 1][0];
+            ctl->ncell[k] = S.cnt[k & 1][1];
+            ctl->ntroub[k - 1] = S.cnt[k & 1][2];
         }
     }
     if (threadIdx.x == 0) {
@@ -699,6 +710,14 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const StageArgs<real> A, 
         ctl->tail_back = back ? 1 : 0;
         if (back) ctl->tail_k0 = 0;  // the next multi-block batch starts afresh
     }
+}
+
+template <typename real>
+__global__ __launch_bounds__(kTailThreads) void k_tail(const StageArgs<real> A, const Cascade C, int kbeg, int kdef,
+                                                       int kend)
+{
+    __shared__ TailShared<real> S;
+    tail_body(A, C, kbeg, kdef, kend, S);
 }
 
 // -------------------------------------------------------- small kernels
