@@ -189,6 +189,62 @@ gpm_status gpm_instrument_read(gpm_ctx *ctx, double *first_pass_ms, long long *f
                                double *cascade_ms, long long *stages, long long level_cells[4],
                                long long *mood_iters);
 
+/* ---------------------------------------------------------------------------
+   Batched ensemble: many independent problems of uneven size advanced
+   together.  Each problem is a 2D grid of its own size and boundary conditions;
+   all share one scheme and precision.  A step advances every problem by one
+   SSP-RK3 step with its own CFL time step (Sec. "Numerical stability and
+   performance comparison"), using for each kernel kind one launch for the whole
+   batch: the dt reduction, the first pass over all problems' strips, and one
+   workgroup per problem that runs that problem's complete MOOD cascade (Sec.
+   "Stepwise implementation", Steps 3-10).  Results per problem are those of a
+   single-problem context.  Not thread-safe per batch. */
+typedef struct gpm_batch gpm_batch;
+
+/* Create a batch of nprob problems (grids[p] as for gpm_create; same precision
+   and stream for all).  Allocates host memory only.  Errors as gpm_create, for
+   the first problem that fails. */
+gpm_status gpm_batch_create(int nprob, const gpm_grid *grids, int prec, void *hip_stream, gpm_batch **out);
+
+/* One scheme for every problem (as gpm_set_scheme; ell = 0 selects 12 min(dx,dy)
+   per problem).  Problems whose ell/dx and ell/dy agree share one weight build. */
+gpm_status gpm_batch_set_scheme(gpm_batch *b, const gpm_scheme *scheme);
+
+/* Bytes of the single device buffer the batch needs (all problems' state slots
+   and workspaces plus the batch tables). */
+gpm_status gpm_batch_workspace_size(const gpm_batch *b, size_t *bytes);
+
+/* Bind the caller's device buffer (>= the size above, 256-byte aligned);
+   clears it.  Synchronising.  Errors: GPM_EINVAL for NULL or misalignment. */
+gpm_status gpm_batch_bind(gpm_batch *b, void *mem);
+
+/* First-pass rows per wavefront for every problem (4..256, default 16). */
+gpm_status gpm_batch_set_tuning(gpm_batch *b, int rows_per_wave);
+
+/* Initial state / current state of problem p (host double SoA [4][ny_p][nx_p]).
+   Synchronising. */
+gpm_status gpm_batch_init_state(gpm_batch *b, int p, const double *U_host);
+gpm_status gpm_batch_get_state(gpm_batch *b, int p, double *U_host);
+
+/* Advance every problem by nsteps SSP-RK3 steps at the given CFL number.  With
+   use_graph != 0 each step is one replay of a captured HIP graph (captured on
+   first use and again when cfl changes).  Asynchronous; pass-limit overflows are
+   reported by gpm_batch_status.  Errors: GPM_EINVAL (cfl <= 0), GPM_ESTATE. */
+gpm_status gpm_batch_step(gpm_batch *b, double cfl, int nsteps, int use_graph);
+
+/* Per problem (arrays of nprob, either may be NULL): MOOD evaluations of the
+   last stage and the last dt.  Synchronising.  GPM_ENOTCONV if some problem's
+   cascade hit the pass limit (its entry in mood_iters is 0). */
+gpm_status gpm_batch_status(gpm_batch *b, int *mood_iters, double *dt);
+
+/* Final-order counts per cascade level and evaluations of problem p's last
+   stage, and its order mask (as gpm_troubled_counts, gpm_get_order_mask). */
+gpm_status gpm_batch_troubled_counts(gpm_batch *b, int p, long long counts[4], int *mood_iters);
+gpm_status gpm_batch_get_order_mask(gpm_batch *b, int p, unsigned char *mask_host);
+
+const char *gpm_batch_last_error(const gpm_batch *b);
+void gpm_batch_destroy(gpm_batch *b);
+
 const char *gpm_strerror(gpm_status st);
 const char *gpm_last_error(const gpm_ctx *ctx);
 void gpm_destroy(gpm_ctx *ctx);

@@ -25,8 +25,11 @@ GPM_FLAGS_ALL = 15
 EXPORTS = ("gpm_create", "gpm_set_scheme", "gpm_workspace_size", "gpm_bind", "gpm_state_ptr",
            "gpm_init_state", "gpm_get_state", "gpm_compute_dt", "gpm_set_dt", "gpm_stage_dev",
            "gpm_step", "gpm_troubled_counts", "gpm_get_order_mask", "gpm_totals", "gpm_totals_dev",
-           "gpm_set_tuning", "gpm_instrument", "gpm_instrument_read", "gpm_strerror", "gpm_last_error",
-           "gpm_destroy")
+           "gpm_set_tuning", "gpm_instrument", "gpm_instrument_read", "gpm_batch_create",
+           "gpm_batch_set_scheme", "gpm_batch_workspace_size", "gpm_batch_bind", "gpm_batch_set_tuning",
+           "gpm_batch_init_state", "gpm_batch_get_state", "gpm_batch_step", "gpm_batch_status",
+           "gpm_batch_troubled_counts", "gpm_batch_get_order_mask", "gpm_batch_last_error",
+           "gpm_batch_destroy", "gpm_strerror", "gpm_last_error", "gpm_destroy")
 
 
 class gpm_grid(ctypes.Structure):
@@ -77,6 +80,20 @@ def lib():
         "gpm_instrument": ([ctxp, ctypes.c_int], st),
         "gpm_instrument_read": ([ctxp, dp, ctypes.POINTER(ctypes.c_longlong), dp, ctypes.POINTER(ctypes.c_longlong),
                                  ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)], st),
+        "gpm_batch_create": ([ctypes.c_int, ctypes.POINTER(gpm_grid), ctypes.c_int, vp, ctypes.POINTER(ctxp)], st),
+        "gpm_batch_set_scheme": ([ctxp, ctypes.POINTER(gpm_scheme)], st),
+        "gpm_batch_workspace_size": ([ctxp, ctypes.POINTER(ctypes.c_size_t)], st),
+        "gpm_batch_bind": ([ctxp, vp], st),
+        "gpm_batch_set_tuning": ([ctxp, ctypes.c_int], st),
+        "gpm_batch_init_state": ([ctxp, ctypes.c_int, dp], st),
+        "gpm_batch_get_state": ([ctxp, ctypes.c_int, dp], st),
+        "gpm_batch_step": ([ctxp, ctypes.c_double, ctypes.c_int, ctypes.c_int], st),
+        "gpm_batch_status": ([ctxp, ctypes.POINTER(ctypes.c_int), dp], st),
+        "gpm_batch_troubled_counts": ([ctxp, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong),
+                                       ctypes.POINTER(ctypes.c_int)], st),
+        "gpm_batch_get_order_mask": ([ctxp, ctypes.c_int, ctypes.POINTER(ctypes.c_ubyte)], st),
+        "gpm_batch_last_error": ([ctxp], ctypes.c_char_p),
+        "gpm_batch_destroy": ([ctxp], None),
         "gpm_strerror": ([st], ctypes.c_char_p),
         "gpm_last_error": ([ctxp], ctypes.c_char_p),
         "gpm_destroy": ([ctxp], None),
@@ -238,3 +255,99 @@ class GPMood:
                                               ctypes.byref(nst), lev, ctypes.byref(it)))
         return {"first_pass_ms": fp.value, "first_pass_launches": nfp.value, "cascade_ms": cm.value,
                 "stages": nst.value, "level_cells": list(lev), "mood_iters": it.value}
+
+
+class GPMoodBatch:
+    """Many independent 2D problems advanced together (one launch per kernel kind).
+
+    sizes: list of (nx, ny); lo, hi, bc, prec, cascade, ell as for GPMood (shared).
+    """
+
+    def __init__(self, sizes, lo=(0.0, 0.0), hi=(1.0, 1.0), bc=(0, 0), prec="f32", cascade=(3, 2, 1, 0),
+                 ell=None, gamma=1.4, sigma_v=5.0, sigma_p=5.0, flags=GPM_FLAGS_ALL, stream=None, device=None):
+        import torch
+        L = lib()
+        self.device = torch.device(device if device is not None else "cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.sizes = [(int(a), int(b)) for a, b in sizes]
+        self.prec = prec
+        grids = (gpm_grid * len(self.sizes))()
+        for k, (nx, ny) in enumerate(self.sizes):
+            g = grids[k]
+            g.dim = 2
+            g.n[0], g.n[1], g.n[2] = nx, ny, 1
+            g.lo[0], g.lo[1] = lo
+            g.hi[0], g.hi[1] = hi
+            g.bc[0], g.bc[1] = bc
+            g.gamma = gamma
+        b = ctypes.c_void_p()
+        st = L.gpm_batch_create(len(self.sizes), grids, GPM_F64 if prec == "f64" else GPM_F32,
+                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(b))
+        if st != GPM_OK:
+            raise GpmError(f"status {st}: {L.gpm_strerror(st).decode()}")
+        self.b = b
+        s = gpm_scheme()
+        s.nlev = len(cascade)
+        for k, r in enumerate(cascade):
+            s.radius[k] = r
+        s.ell = 0.0 if ell is None else float(ell)
+        s.sigma_v, s.sigma_p, s.flags = sigma_v, sigma_p, flags
+        self._check(L.gpm_batch_set_scheme(self.b, ctypes.byref(s)))
+        nb = ctypes.c_size_t()
+        self._check(L.gpm_batch_workspace_size(self.b, ctypes.byref(nb)))
+        self.buf = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        self._check(L.gpm_batch_bind(self.b, ctypes.c_void_p(self.buf.data_ptr())))
+
+    def _check(self, st):
+        if st != GPM_OK:
+            L = lib()
+            raise GpmError(f"status {st}: {L.gpm_strerror(st).decode()}: "
+                           f"{(L.gpm_batch_last_error(self.b) or b'').decode()}")
+
+    def close(self):
+        if getattr(self, "b", None) is not None:
+            lib().gpm_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def gpm_batch_set_tuning(self, rows_per_wave=16):
+        self._check(lib().gpm_batch_set_tuning(self.b, int(rows_per_wave)))
+
+    def gpm_batch_init_state(self, p, U):
+        nx, ny = self.sizes[p]
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        assert U.shape == (4, ny, nx)
+        self._check(lib().gpm_batch_init_state(self.b, int(p), _dp(U)))
+
+    def gpm_batch_get_state(self, p):
+        nx, ny = self.sizes[p]
+        U = np.empty((4, ny, nx))
+        self._check(lib().gpm_batch_get_state(self.b, int(p), _dp(U)))
+        return U
+
+    def gpm_batch_step(self, cfl=0.8, nsteps=1, use_graph=True):
+        self._check(lib().gpm_batch_step(self.b, float(cfl), int(nsteps), 1 if use_graph else 0))
+
+    def gpm_batch_status(self):
+        n = len(self.sizes)
+        it = (ctypes.c_int * n)()
+        dt = np.zeros(n)
+        self._check(lib().gpm_batch_status(self.b, it, _dp(dt)))
+        return np.array(list(it), dtype=np.int64), dt
+
+    def gpm_batch_troubled_counts(self, p):
+        c = (ctypes.c_longlong * 4)()
+        it = ctypes.c_int()
+        self._check(lib().gpm_batch_troubled_counts(self.b, int(p), c, ctypes.byref(it)))
+        return np.array(list(c), dtype=np.int64), it.value
+
+    def gpm_batch_get_order_mask(self, p):
+        nx, ny = self.sizes[p]
+        m = np.empty((ny, nx), dtype=np.uint8)
+        self._check(lib().gpm_batch_get_order_mask(self.b, int(p), m.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))))
+        return m

@@ -18,113 +18,7 @@
 
 using namespace gpm;
 
-namespace {
-
-constexpr size_t kAlign = 256;
-constexpr int kTotBlocks = 1024;
-
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-}  // namespace
-
-struct gpm_ctx {
-    gpm_grid grid;
-    int prec;
-    hipStream_t stream;
-    int nx, ny;
-    size_t ncell;
-    double dx, dy;
-    bool have_scheme = false;
-    gpm_scheme scheme;
-    Weights<double> w64;
-    Weights<float> w32;
-    std::vector<double> gtab64;  // compact cascade weights (kGtabSize), both precisions
-    std::vector<float> gtab32;
-    int top = 0;
-    int next[4] = {0, 0, 0, 0};
-    int levidx[4] = {0, 0, 0, 0};
-    // bound memory
-    char *state = nullptr;
-    char *work = nullptr;
-    int cur = 0;
-    uint8_t *order = nullptr;
-    unsigned *cstamp = nullptr;
-    unsigned *fstamp = nullptr;
-    int *flist[2] = {nullptr, nullptr};
-    int *clist[2] = {nullptr, nullptr};
-    void *FX = nullptr;
-    void *GY = nullptr;
-    uint8_t *FXf = nullptr;
-    uint8_t *GYf = nullptr;
-    Ctl *ctl = nullptr;
-    double *partial = nullptr;
-    void *gtab = nullptr;
-    unsigned pass = 0;
-    int passes_per_check = 4;  // smallest batch of multi-block cascade passes
-    int head_guess = 4;        // batch length: the previous stage's multi-block passes + 2
-    int tail_threshold = 48;   // troubled cells at or below which one workgroup finishes the cascade
-    int rows = 16;
-    int last_npass = 0;
-    bool fresh_ctl = true;
-    int *pinned = nullptr;
-    // instrumentation
-    int instrument = 0;           // bit 0: stage events and iteration counts, bit 1: level statistics
-    long long acc_iters = 0, acc_stages = 0;
-    std::vector<hipEvent_t> evs;  // 3 per instrumented stage: first pass start/end, stage end
-    size_t nev_used = 0;
-    std::string err;
-};
-
-static gpm_status fail(gpm_ctx *c, gpm_status st, const std::string &msg)
-{
-    if (c) c->err = msg;
-    return st;
-}
-
-// Copy the compact cascade weights into the workspace (synchronous: a setup step).
-static gpm_status upload_gtab(gpm_ctx *c)
-{
-    if (!c->gtab || !c->have_scheme) return GPM_OK;
-    const void *src = c->prec == GPM_F64 ? (const void *)c->gtab64.data() : (const void *)c->gtab32.data();
-    const size_t bytes = (size_t)kGtabSize * (c->prec == GPM_F64 ? 8 : 4);
-    hipError_t e = hipMemcpyAsync(c->gtab, src, bytes, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("weight upload: ") + hipGetErrorString(e));
-    return GPM_OK;
-}
-
-#define HIPCHK(c, expr)                                                                      \
-    do {                                                                                     \
-        hipError_t e_ = (expr);                                                              \
-        if (e_ != hipSuccess)                                                                \
-            return fail((c), GPM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));   \
-    } while (0)
-
-static size_t state_slot_bytes(const gpm_ctx *c)
-{
-    return align_up(4 * c->ncell * (c->prec == GPM_F64 ? 8 : 4));
-}
-
-static size_t nfaces_x(const gpm_ctx *c) { return (size_t)(c->nx + 1) * c->ny; }
-static size_t nfaces_y(const gpm_ctx *c) { return (size_t)c->nx * (c->ny + 1); }
-
-// Workspace partition (each part 256-byte aligned).
-enum { W_ORDER, W_CSTAMP, W_FSTAMP, W_FL0, W_FL1, W_CL0, W_CL1, W_FX, W_GY, W_FXF, W_GYF, W_CTL, W_PART, W_GTAB, W_N };
-
-static size_t work_layout(const gpm_ctx *c, size_t off[W_N])
-{
-    const size_t nf = nfaces_x(c) + nfaces_y(c);
-    const size_t esz = c->prec == GPM_F64 ? 8 : 4;
-    const size_t sz[W_N] = {c->ncell, 4 * c->ncell, 4 * nf, 4 * nf, 4 * nf, 4 * c->ncell, 4 * c->ncell,
-                            4 * esz * nfaces_x(c), 4 * esz * nfaces_y(c), nfaces_x(c), nfaces_y(c), sizeof(Ctl),
-                            (size_t)kTotBlocks * 4 * 2 * sizeof(double), (size_t)kGtabSize * esz};
-    size_t o = 0;
-    for (int k = 0; k < W_N; ++k) {
-        off[k] = o;
-        o = align_up(o + sz[k]);
-    }
-    return o;
-}
+#include "gpmood_ctx.h"
 
 extern "C" {
 
@@ -311,7 +205,6 @@ gpm_status gpm_state_ptr(const gpm_ctx *c, int slot, void **ptr, int *current_sl
     return GPM_OK;
 }
 
-static void *slot_ptr(gpm_ctx *c, int slot) { return c->state + slot * state_slot_bytes(c); }
 
 gpm_status gpm_init_state(gpm_ctx *c, const double *U)
 {
@@ -394,59 +287,6 @@ gpm_status gpm_set_tuning(gpm_ctx *c, int passes_per_check, int rows_per_wave, i
 }  // extern "C"
 
 template <typename real>
-static void fill_args(const gpm_ctx *c, const Weights<real> &W, StageArgs<real> &A)
-{
-    A.nx = c->nx;
-    A.ny = c->ny;
-    A.bcx = c->grid.bc[0];
-    A.bcy = c->grid.bc[1];
-    A.rows = c->rows;
-    A.top = c->top;
-    A.flags = c->scheme.flags;
-    A.dx = (real)c->dx;
-    A.dy = (real)c->dy;
-    A.gamma = (real)c->grid.gamma;
-    A.sigma_v = (real)c->scheme.sigma_v;
-    A.sigma_p = (real)c->scheme.sigma_p;
-    const double d3 = c->dx * c->dx * c->dx < c->dy * c->dy * c->dy ? c->dx * c->dx * c->dx : c->dy * c->dy * c->dy;
-    A.plat_thr = (real)d3;
-    A.delta = (real)(c->dx < c->dy ? c->dx : c->dy);
-    A.W = W;
-    A.dt = &c->ctl->dt;
-    A.order = c->order;
-    A.FX = (real *)c->FX;
-    A.GY = (real *)c->GY;
-    A.FXf = c->FXf;
-    A.GYf = c->GYf;
-    A.gtab = (const real *)c->gtab;
-    A.cstamp = c->cstamp;
-    A.fstamp = c->fstamp;
-    for (int r = 0; r < 4; ++r) A.next[r] = c->next[r];
-}
-
-// Claim stamps grow monotonically (kMaxPasses + 2 per stage); the stamp arrays
-// are cleared at the start of a stage when fewer than a stage's worth is left
-// before the wrap.
-static gpm_status stamps_for_stage(gpm_ctx *c)
-{
-    if (c->pass >= 0xffffffffu - (unsigned)(2 * kMaxPasses + 8)) {
-        HIPCHK(c, hipMemsetAsync(c->cstamp, 0, 4 * c->ncell, c->stream));
-        HIPCHK(c, hipMemsetAsync(c->fstamp, 0, 4 * (nfaces_x(c) + nfaces_y(c)), c->stream));
-        c->pass = 0;
-    }
-    return GPM_OK;
-}
-
-static gpm_status level_counts(gpm_ctx *c)
-{
-    LevIdx li;
-    for (int r = 0; r < 4; ++r) li.v[r] = c->levidx[r];
-    hipError_t e = launch_level_hist(c->order, c->ncell, li, c->ctl, c->stream);
-    if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("level histogram: ") + hipGetErrorString(e));
-    return GPM_OK;
-}
-
-template <typename real>
 static gpm_status run_stage(gpm_ctx *c, const Weights<real> &W, int s, const void *Un, const void *Us, void *Uout)
 {
     StageArgs<real> A;
@@ -455,32 +295,31 @@ static gpm_status run_stage(gpm_ctx *c, const Weights<real> &W, int s, const voi
     A.Un = (const real *)Un;
     A.Us = (const real *)Us;
     A.Uout = (real *)Uout;
-    const int nzero = c->fresh_ctl ? kMaxPasses + 2 : (c->last_npass + 3 < kMaxPasses + 2 ? c->last_npass + 3 : kMaxPasses + 2);
-    hipError_t e = launch_reset(c->ctl, nzero, c->stream);
-    if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("reset: ") + hipGetErrorString(e));
-    c->fresh_ctl = false;
-
     // evaluation 0 (first pass) claims the faces and cells of cascade pass 1;
     // pass k claims with stamp0 + k
     gpm_status st = stamps_for_stage(c);
     if (st != GPM_OK) return st;
+    const unsigned stamp0 = c->pass + 1;
+    c->pass += (unsigned)kMaxPasses + 2;
+    const int nzero = c->fresh_ctl ? kMaxPasses + 2 : (c->last_npass + 3 < kMaxPasses + 2 ? c->last_npass + 3 : kMaxPasses + 2);
+    hipError_t e = launch_reset(c->ctl, nzero, stamp0, c->stream);
+    if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("reset: ") + hipGetErrorString(e));
+    c->fresh_ctl = false;
     Cascade C;
     C.flist[0] = c->flist[0];
     C.flist[1] = c->flist[1];
     C.clist[0] = c->clist[0];
     C.clist[1] = c->clist[1];
     C.ctl = c->ctl;
-    C.stamp0 = c->pass + 1;
     C.tail_thr = c->tail_threshold;
     C.back_thr = 4 * c->tail_threshold;
-    c->pass += (unsigned)kMaxPasses + 2;
     PassOut P;
     P.flist = c->flist[1];
     P.clist = c->clist[1];
     P.fcount = &c->ctl->nface[1];
     P.ccount = &c->ctl->ncell[1];
     P.tcount = &c->ctl->ntroub[0];
-    P.stamp = C.stamp0;
+    P.stamp = 0;  // set on the device from ctl->stamp0
     hipEvent_t *ev = nullptr;
     if (c->instrument) {
         while (c->evs.size() < 3 * (c->nev_used + 1)) {

@@ -1,0 +1,455 @@
+// C ABI of the batched ensemble: many independent 2D problems (uneven grid sizes,
+// one scheme) advanced together, one launch per kernel kind and stage for the
+// whole batch, optionally replayed as HIP graphs (see include/gpmood.h).
+//
+// Every problem keeps its own single-problem context (weights, workspace, state
+// slots, control block) inside one caller buffer.  Device tables hold, for each
+// of the three slot rotations of an SSP-RK3 step and each stage, every problem's
+// stage arguments, so a step's launches never change their arguments and a
+// captured step graph can be replayed: the claim stamps advance on the device.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gpmood.h"
+#include "gpmood_ctx.h"
+
+namespace {
+
+// First-pass block count of one problem (strips of 62 columns x `rows` rows,
+// WPB wavefronts per block) and dt blocks (256 threads, up to 16 cells each).
+int fp_blocks(const gpm_ctx *c, int rows)
+{
+    const int wpb = c->prec == GPM_F64 ? 2 : 4;
+    const int waves = ((c->nx + 61) / 62) * ((c->ny + rows - 1) / rows);
+    return (waves + wpb - 1) / wpb;
+}
+
+int dt_blocks(const gpm_ctx *c)
+{
+    const size_t b = (c->ncell + 4095) / 4096;
+    return (int)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+struct gpm_batch {
+    int nprob = 0;
+    int prec = GPM_F32;
+    hipStream_t stream = nullptr;
+    std::vector<gpm_ctx *> ctx;
+    bool have_scheme = false;
+    char *mem = nullptr;
+    int rows = 16;
+    int cur = 0;  // slot rotation of the next step (the same for every problem)
+    // device tables (inside the caller buffer)
+    void *args = nullptr;       // StageArgs<real>[3 rotations][3 stages][nprob]
+    PassOut *pout[3] = {};      // per stage: first-pass outputs [nprob]
+    Cascade *casc = nullptr;    // [nprob]
+    int *blk = nullptr;         // [nprob + 1]
+    int *dblk = nullptr;        // [nprob + 1]
+    int *st_iters = nullptr;    // [nprob]
+    double *st_dt = nullptr;    // [nprob]
+    int nfp = 0, ndt = 0;
+    // graphs: one captured SSP-RK3 step per rotation
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
+    double graph_cfl = -1.0;
+    unsigned long long stages_run = 0;  // since the stamps were last cleared
+    std::string err;
+};
+
+static gpm_status bfail(gpm_batch *b, gpm_status st, const std::string &msg)
+{
+    if (b) b->err = msg;
+    return st;
+}
+
+#define BHIPCHK(b, expr)                                                                     \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return bfail((b), GPM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+// Byte layout of the caller buffer: per problem its three state slots and its
+// workspace, then the tables.
+struct BatchLayout {
+    std::vector<size_t> state_off, work_off;
+    size_t args, pout, casc, blk, dblk, iters, dts, total;
+};
+
+static BatchLayout batch_layout(const gpm_batch *b)
+{
+    BatchLayout L;
+    size_t o = 0;
+    for (int p = 0; p < b->nprob; ++p) {
+        size_t woff[W_N];
+        L.state_off.push_back(o);
+        o = align_up(o + 3 * state_slot_bytes(b->ctx[p]));
+        L.work_off.push_back(o);
+        o = align_up(o + work_layout(b->ctx[p], woff));
+    }
+    const size_t asz = b->prec == GPM_F64 ? sizeof(StageArgs<double>) : sizeof(StageArgs<float>);
+    L.args = o;
+    o = align_up(o + 9 * (size_t)b->nprob * asz);
+    L.pout = o;
+    o = align_up(o + 3 * (size_t)b->nprob * sizeof(PassOut));
+    L.casc = o;
+    o = align_up(o + (size_t)b->nprob * sizeof(Cascade));
+    L.blk = o;
+    o = align_up(o + (size_t)(b->nprob + 1) * sizeof(int));
+    L.dblk = o;
+    o = align_up(o + (size_t)(b->nprob + 1) * sizeof(int));
+    L.iters = o;
+    o = align_up(o + (size_t)b->nprob * sizeof(int));
+    L.dts = o;
+    o = align_up(o + (size_t)b->nprob * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+static void drop_graphs(gpm_batch *b)
+{
+    for (int r = 0; r < 3; ++r)
+        if (b->graph[r]) {
+            (void)hipGraphExecDestroy(b->graph[r]);
+            b->graph[r] = nullptr;
+        }
+    b->graph_cfl = -1.0;
+}
+
+// Fill and upload the device tables (after bind and scheme, or a tuning change).
+template <typename real>
+static gpm_status build_tables(gpm_batch *b)
+{
+    const int P = b->nprob;
+    std::vector<StageArgs<real>> args(9 * (size_t)P);
+    std::vector<PassOut> pout(3 * (size_t)P);
+    std::vector<Cascade> casc(P);
+    std::vector<int> blk(P + 1), dblk(P + 1);
+    blk[0] = dblk[0] = 0;
+    for (int p = 0; p < P; ++p) {
+        gpm_ctx *c = b->ctx[p];
+        c->rows = b->rows;
+        const Weights<real> &W = *(const Weights<real> *)(sizeof(real) == 8 ? (const void *)&c->w64 : (const void *)&c->w32);
+        for (int r = 0; r < 3; ++r) {
+            const int u0 = r, a = (r + 1) % 3, bb = (r + 2) % 3;
+            const int un[3] = {u0, u0, u0}, us[3] = {u0, a, bb}, uo[3] = {a, bb, a};
+            for (int s = 0; s < 3; ++s) {
+                StageArgs<real> &A = args[((size_t)r * 3 + s) * P + p];
+                fill_args(c, W, A);
+                A.s = s;
+                A.Un = (const real *)slot_ptr(c, un[s]);
+                A.Us = (const real *)slot_ptr(c, us[s]);
+                A.Uout = (real *)slot_ptr(c, uo[s]);
+            }
+        }
+        for (int s = 0; s < 3; ++s) {
+            PassOut &Q = pout[(size_t)s * P + p];
+            Q.flist = c->flist[1];
+            Q.clist = c->clist[1];
+            Q.fcount = &c->ctl->nface[1];
+            Q.ccount = &c->ctl->ncell[1];
+            Q.tcount = &c->ctl->ntroub[0];
+            Q.stamp = 0;  // set on the device from ctl->stamp0
+        }
+        Cascade &C = casc[p];
+        C.flist[0] = c->flist[0];
+        C.flist[1] = c->flist[1];
+        C.clist[0] = c->clist[0];
+        C.clist[1] = c->clist[1];
+        C.ctl = c->ctl;
+        C.tail_thr = 0;
+        C.back_thr = 0x7fffffff;  // one workgroup per problem runs the whole cascade
+        blk[p + 1] = blk[p] + fp_blocks(c, b->rows);
+        dblk[p + 1] = dblk[p] + dt_blocks(c);
+    }
+    b->nfp = blk[P];
+    b->ndt = dblk[P];
+    const BatchLayout L = batch_layout(b);
+    BHIPCHK(b, hipMemcpyAsync(b->mem + L.args, args.data(), args.size() * sizeof(StageArgs<real>),
+                              hipMemcpyHostToDevice, b->stream));
+    BHIPCHK(b, hipMemcpyAsync(b->mem + L.pout, pout.data(), pout.size() * sizeof(PassOut), hipMemcpyHostToDevice,
+                              b->stream));
+    BHIPCHK(b, hipMemcpyAsync(b->mem + L.casc, casc.data(), casc.size() * sizeof(Cascade), hipMemcpyHostToDevice,
+                              b->stream));
+    BHIPCHK(b, hipMemcpyAsync(b->mem + L.blk, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    BHIPCHK(b, hipMemcpyAsync(b->mem + L.dblk, dblk.data(), dblk.size() * sizeof(int), hipMemcpyHostToDevice,
+                              b->stream));
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    drop_graphs(b);
+    return GPM_OK;
+}
+
+static gpm_status rebuild(gpm_batch *b)
+{
+    if (!b->mem || !b->have_scheme) return GPM_OK;
+    return b->prec == GPM_F64 ? build_tables<double>(b) : build_tables<float>(b);
+}
+
+template <typename real>
+static BatchTabs<real> tabs(const gpm_batch *b, int rot, int s)
+{
+    BatchTabs<real> B;
+    B.args = (const StageArgs<real> *)b->args + ((size_t)rot * 3 + s) * b->nprob;
+    B.pout = b->pout[s];
+    B.casc = b->casc;
+    B.blk = b->blk;
+    B.dblk = b->dblk;
+    B.nprob = b->nprob;
+    return B;
+}
+
+// Enqueue one SSP-RK3 step with slot rotation rot on stream st.
+template <typename real>
+static hipError_t enqueue_step(gpm_batch *b, int rot, double cfl, hipStream_t st)
+{
+    const int top = b->ctx[0]->top;
+    hipError_t e = launch_batch_dt<real>(tabs<real>(b, rot, 0), b->ndt, b->casc, cfl, st);
+    for (int s = 0; s < 3 && e == hipSuccess; ++s)
+        e = launch_batch_stage<real>(tabs<real>(b, rot, s), top, b->nfp, b->casc, st);
+    return e;
+}
+
+static hipError_t enqueue_step_any(gpm_batch *b, int rot, double cfl, hipStream_t st)
+{
+    return b->prec == GPM_F64 ? enqueue_step<double>(b, rot, cfl, st) : enqueue_step<float>(b, rot, cfl, st);
+}
+
+// The claim stamps advance by kMaxPasses + 2 per stage on the device; clear the
+// stamp arrays before they would wrap.
+static gpm_status stamps_guard(gpm_batch *b, int nsteps)
+{
+    const unsigned long long per = (unsigned long long)kMaxPasses + 2;
+    if ((b->stages_run + 3ull * nsteps + 3ull) * per < 0xffffffffull) return GPM_OK;
+    for (gpm_ctx *c : b->ctx) {
+        BHIPCHK(b, hipMemsetAsync(c->cstamp, 0, 4 * c->ncell, b->stream));
+        BHIPCHK(b, hipMemsetAsync(c->fstamp, 0, 4 * (nfaces_x(c) + nfaces_y(c)), b->stream));
+    }
+    BHIPCHK(b, launch_batch_stamp_restart(b->casc, b->nprob, b->stream));
+    b->stages_run = 0;
+    if ((3ull * nsteps + 3ull) * per >= 0xffffffffull) return bfail(b, GPM_EINVAL, "too many steps in one call");
+    return GPM_OK;
+}
+
+extern "C" {
+
+gpm_status gpm_batch_create(int nprob, const gpm_grid *grids, int prec, void *hip_stream, gpm_batch **out)
+{
+    if (!out || !grids || nprob < 1 || nprob > 65536) return GPM_EINVAL;
+    *out = nullptr;
+    gpm_batch *b = new (std::nothrow) gpm_batch;
+    if (!b) return GPM_ENOMEM;
+    b->nprob = nprob;
+    b->prec = prec;
+    b->stream = (hipStream_t)hip_stream;
+    for (int p = 0; p < nprob; ++p) {
+        gpm_ctx *c = nullptr;
+        const gpm_status st = gpm_create(&grids[p], prec, hip_stream, &c);
+        if (st != GPM_OK) {
+            for (gpm_ctx *x : b->ctx) gpm_destroy(x);
+            delete b;
+            return st;
+        }
+        b->ctx.push_back(c);
+    }
+    *out = b;
+    return GPM_OK;
+}
+
+void gpm_batch_destroy(gpm_batch *b)
+{
+    if (!b) return;
+    drop_graphs(b);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    for (gpm_ctx *c : b->ctx) gpm_destroy(c);
+    delete b;
+}
+
+const char *gpm_batch_last_error(const gpm_batch *b) { return b ? b->err.c_str() : ""; }
+
+gpm_status gpm_batch_set_scheme(gpm_batch *b, const gpm_scheme *s)
+{
+    if (!b || !s) return GPM_EINVAL;
+    for (int p = 0; p < b->nprob; ++p) {
+        gpm_ctx *c = b->ctx[p];
+        // problems with the same cell aspect share their weights (ell in cells)
+        const double ell = s->ell > 0.0 ? s->ell : 12.0 * (c->dx < c->dy ? c->dx : c->dy);
+        int q = -1;
+        for (int r = 0; r < p && q < 0; ++r) {
+            const gpm_ctx *d = b->ctx[r];
+            const double elld = s->ell > 0.0 ? s->ell : 12.0 * (d->dx < d->dy ? d->dx : d->dy);
+            if (ell / c->dx == elld / d->dx && ell / c->dy == elld / d->dy) q = r;
+        }
+        if (q < 0) {
+            const gpm_status st = gpm_set_scheme(c, s);
+            if (st != GPM_OK) return bfail(b, st, std::string("problem ") + std::to_string(p) + ": " + c->err);
+        } else {
+            const gpm_ctx *d = b->ctx[q];
+            c->w64 = d->w64;
+            c->w32 = d->w32;
+            c->gtab64 = d->gtab64;
+            c->gtab32 = d->gtab32;
+            c->scheme = d->scheme;
+            c->scheme.ell = ell;
+            c->top = d->top;
+            for (int r = 0; r < 4; ++r) {
+                c->next[r] = d->next[r];
+                c->levidx[r] = d->levidx[r];
+            }
+            c->have_scheme = true;
+            const gpm_status st = upload_gtab(c);
+            if (st != GPM_OK) return bfail(b, st, c->err);
+        }
+    }
+    b->have_scheme = true;
+    return rebuild(b);
+}
+
+gpm_status gpm_batch_workspace_size(const gpm_batch *b, size_t *bytes)
+{
+    if (!b || !bytes) return GPM_EINVAL;
+    *bytes = batch_layout(b).total;
+    return GPM_OK;
+}
+
+gpm_status gpm_batch_bind(gpm_batch *b, void *mem)
+{
+    if (!b || !mem) return GPM_EINVAL;
+    if ((uintptr_t)mem % kAlign) return bfail(b, GPM_EINVAL, "buffer must be 256-byte aligned");
+    const BatchLayout L = batch_layout(b);
+    b->mem = (char *)mem;
+    for (int p = 0; p < b->nprob; ++p) {
+        const gpm_status st = gpm_bind(b->ctx[p], b->mem + L.state_off[p], b->mem + L.work_off[p]);
+        if (st != GPM_OK) return bfail(b, st, b->ctx[p]->err);
+    }
+    b->args = b->mem + L.args;
+    const size_t psz = (size_t)b->nprob * sizeof(PassOut);
+    for (int s = 0; s < 3; ++s) b->pout[s] = (PassOut *)(b->mem + L.pout + s * psz);
+    b->casc = (Cascade *)(b->mem + L.casc);
+    b->blk = (int *)(b->mem + L.blk);
+    b->dblk = (int *)(b->mem + L.dblk);
+    b->st_iters = (int *)(b->mem + L.iters);
+    b->st_dt = (double *)(b->mem + L.dts);
+    b->cur = 0;
+    b->stages_run = 0;
+    return rebuild(b);
+}
+
+gpm_status gpm_batch_set_tuning(gpm_batch *b, int rows_per_wave)
+{
+    if (!b || rows_per_wave < 4 || rows_per_wave > 256) return GPM_EINVAL;
+    b->rows = rows_per_wave;
+    return rebuild(b);
+}
+
+gpm_status gpm_batch_init_state(gpm_batch *b, int p, const double *U)
+{
+    if (!b || p < 0 || p >= b->nprob) return GPM_EINVAL;
+    gpm_ctx *c = b->ctx[p];
+    c->cur = b->cur;
+    const gpm_status st = gpm_init_state(c, U);
+    return st == GPM_OK ? st : bfail(b, st, c->err);
+}
+
+gpm_status gpm_batch_get_state(gpm_batch *b, int p, double *U)
+{
+    if (!b || p < 0 || p >= b->nprob) return GPM_EINVAL;
+    gpm_ctx *c = b->ctx[p];
+    c->cur = b->cur;
+    const gpm_status st = gpm_get_state(c, U);
+    return st == GPM_OK ? st : bfail(b, st, c->err);
+}
+
+gpm_status gpm_batch_step(gpm_batch *b, double cfl, int nsteps, int use_graph)
+{
+    if (!b || nsteps < 0) return GPM_EINVAL;
+    if (!(cfl > 0.0)) return bfail(b, GPM_EINVAL, "cfl must be > 0");
+    if (!b->have_scheme) return bfail(b, GPM_ESTATE, "no scheme set");
+    if (!b->mem) return bfail(b, GPM_ESTATE, "not bound");
+    gpm_status st = stamps_guard(b, nsteps);
+    if (st != GPM_OK) return st;
+    if (use_graph) {
+        if (cfl != b->graph_cfl) {
+            drop_graphs(b);
+            if (!b->cap_stream) BHIPCHK(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+            for (int r = 0; r < 3; ++r) {
+                hipGraph_t g = nullptr;
+                BHIPCHK(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+                const hipError_t e = enqueue_step_any(b, r, cfl, b->cap_stream);
+                const hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
+                if (e != hipSuccess || e2 != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return bfail(b, GPM_EHIP, std::string("graph capture: ") +
+                                                  hipGetErrorString(e != hipSuccess ? e : e2));
+                }
+                const hipError_t e3 = hipGraphInstantiate(&b->graph[r], g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e3 != hipSuccess) return bfail(b, GPM_EHIP, std::string("graph: ") + hipGetErrorString(e3));
+            }
+            b->graph_cfl = cfl;
+        }
+        for (int n = 0; n < nsteps; ++n) {
+            BHIPCHK(b, hipGraphLaunch(b->graph[b->cur], b->stream));
+            b->cur = (b->cur + 1) % 3;
+            b->stages_run += 3;
+        }
+    } else {
+        for (int n = 0; n < nsteps; ++n) {
+            const hipError_t e = enqueue_step_any(b, b->cur, cfl, b->stream);
+            if (e != hipSuccess) return bfail(b, GPM_EHIP, std::string("batch step: ") + hipGetErrorString(e));
+            b->cur = (b->cur + 1) % 3;
+            b->stages_run += 3;
+        }
+    }
+    for (gpm_ctx *c : b->ctx) c->cur = b->cur;
+    return GPM_OK;
+}
+
+gpm_status gpm_batch_status(gpm_batch *b, int *mood_iters, double *dt)
+{
+    if (!b) return GPM_EINVAL;
+    if (!b->mem) return bfail(b, GPM_ESTATE, "not bound");
+    const hipError_t e = launch_batch_status(b->casc, b->nprob, b->st_iters, b->st_dt, b->stream);
+    if (e != hipSuccess) return bfail(b, GPM_EHIP, hipGetErrorString(e));
+    std::vector<int> it(b->nprob);
+    std::vector<double> d(b->nprob);
+    BHIPCHK(b, hipMemcpyAsync(it.data(), b->st_iters, sizeof(int) * b->nprob, hipMemcpyDeviceToHost, b->stream));
+    BHIPCHK(b, hipMemcpyAsync(d.data(), b->st_dt, sizeof(double) * b->nprob, hipMemcpyDeviceToHost, b->stream));
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    bool over = false;
+    for (int p = 0; p < b->nprob; ++p) {
+        if (mood_iters) mood_iters[p] = it[p];
+        if (dt) dt[p] = d[p];
+        over = over || it[p] == 0;
+        b->ctx[p]->last_npass = it[p] > 0 ? it[p] - 1 : kMaxPasses - 1;
+    }
+    return over ? bfail(b, GPM_ENOTCONV, "a problem's MOOD loop exceeded the pass limit") : GPM_OK;
+}
+
+gpm_status gpm_batch_troubled_counts(gpm_batch *b, int p, long long counts[4], int *mood_iters)
+{
+    if (!b || p < 0 || p >= b->nprob) return GPM_EINVAL;
+    std::vector<int> it(b->nprob);
+    const gpm_status s0 = gpm_batch_status(b, it.data(), nullptr);
+    if (s0 != GPM_OK && s0 != GPM_ENOTCONV) return s0;
+    gpm_ctx *c = b->ctx[p];
+    const gpm_status st = gpm_troubled_counts(c, counts, nullptr);
+    if (st != GPM_OK) return bfail(b, st, c->err);
+    if (mood_iters) *mood_iters = it[p];
+    return GPM_OK;
+}
+
+gpm_status gpm_batch_get_order_mask(gpm_batch *b, int p, unsigned char *mask)
+{
+    if (!b || p < 0 || p >= b->nprob) return GPM_EINVAL;
+    const gpm_status st = gpm_get_order_mask(b->ctx[p], mask);
+    return st == GPM_OK ? st : bfail(b, st, b->ctx[p]->err);
+}
+
+}  // extern "C"

@@ -45,6 +45,7 @@ struct StageArgs {
     const real *Us;
     real *Uout;
     const double *dt;     // device scalar
+    const unsigned *stamp0;  // device scalar: claim stamp of the first pass (pass k: + k)
     uint8_t *order;       // GP radius per cell (final after the stage)
     // face fluxes of this stage: x faces [4][ny][nx+1] (face i between cells i-1
     // and i), y faces [4][ny+1][nx]; per face, bit 0 / bit 1: the left (lower) /
@@ -62,13 +63,15 @@ struct StageArgs {
     unsigned flags;
     int next[4];          // next radius of the cascade after radius r
     real dx, dy, gamma, sigma_v, sigma_p, plat_thr, delta;
+    double dx64, dy64, gamma64;  // the same in FP64 (the dt reduction)
     Weights<real> W;
     const real *gtab;     // compact cascade weights, kGtabSize values (device)
 };
 
 // Outputs of one evaluation: the troubled count, and the faces and cells that the
-// next cascade pass recomputes (claimed with `stamp`, unique per evaluation).
-// The counters are updated with generic-address atomics and may live in LDS.
+// next cascade pass recomputes (claimed with `stamp`, unique per evaluation; the
+// kernels set it from the control block).  The counters are updated with
+// generic-address atomics and may live in LDS.
 struct PassOut {
     int *flist;
     int *fcount;
@@ -94,11 +97,12 @@ struct Ctl {
     int tail_end;     // first pass the tail did not run
     int tail_k0;      // first pass left to the tail by the multi-block passes (0: none)
     int tail_back;    // 1: the tail stopped at tail_end because the pass grew large
+    unsigned stamp0;  // claim stamp of this stage's first pass; pass k claims with stamp0 + k
 };
 
 // Control of the cascade passes of one stage.  Pass k reads lists [k & 1] with
 // counts nface[k], ncell[k] and writes lists [(k + 1) & 1]; its claims carry the
-// stamp stamp0 + k (the first pass: stamp0).  A multi-block pass whose previous
+// stamp ctl->stamp0 + k (the first pass: ctl->stamp0).  A multi-block pass whose previous
 // evaluation left at most tail_thr troubled cells does nothing and records itself
 // in tail_k0: the single-workgroup tail runs from there.  The tail hands back
 // (tail_back) at a pass whose previous evaluation left more than back_thr.
@@ -106,7 +110,6 @@ struct Cascade {
     int *flist[2];
     int *clist[2];
     Ctl *ctl;
-    unsigned stamp0;
     int tail_thr, back_thr;
 };
 
@@ -387,6 +390,19 @@ __device__ __forceinline__ void wave_reserve2(int n, int *count0, int *count1, i
     base0 = b0 + (excl & 0xffff);
     base1 = b1 + (excl >> 16);
 }
+
+// Device tables of a batch for one stage: per-problem stage arguments, first-pass
+// outputs and cascade control, and the block prefixes of the first pass and of
+// the dt reduction (problem p owns blocks prefix[p] .. prefix[p+1]-1).
+template <typename real>
+struct BatchTabs {
+    const StageArgs<real> *args;
+    const PassOut *pout;
+    const Cascade *casc;
+    const int *blk;
+    const int *dblk;
+    int nprob;
+};
 
 struct LevIdx {
     int v[4];  // cascade level of radius r

@@ -289,7 +289,9 @@ __global__ __launch_bounds__(64 * WPB) void k_first_pass(const StageArgs<real> A
 {
     __shared__ real ring_all[WPB][8][4][LW];
     const int wv = threadIdx.x >> 6;
-    first_pass_wave<real, RT>(A, P, xcd_tile(blockIdx.x, gridDim.x) * WPB + wv, ring_all[wv]);
+    PassOut Q = P;
+    Q.stamp = *A.stamp0;
+    first_pass_wave<real, RT>(A, Q, xcd_tile(blockIdx.x, gridDim.x) * WPB + wv, ring_all[wv]);
 }
 
 // ------------------------------------------------------------- cascade pass
@@ -581,7 +583,7 @@ __device__ __forceinline__ void cells_phase(const StageArgs<real> &A, const int 
 }
 
 // Outputs of cascade pass k.
-__device__ __forceinline__ PassOut pass_out(const Cascade &C, int k)
+__device__ __forceinline__ PassOut pass_out(const Cascade &C, int k, unsigned stamp0)
 {
     PassOut P;
     P.flist = C.flist[(k + 1) & 1];
@@ -589,7 +591,7 @@ __device__ __forceinline__ PassOut pass_out(const Cascade &C, int k)
     P.clist = C.clist[(k + 1) & 1];
     P.ccount = &C.ctl->ncell[k + 1];
     P.tcount = &C.ctl->ntroub[k];
-    P.stamp = C.stamp0 + (unsigned)k;
+    P.stamp = stamp0 + (unsigned)k;
     return P;
 }
 
@@ -627,7 +629,7 @@ __global__ __launch_bounds__(64) void k_cells(const StageArgs<real> A, const Cas
     n = n < A.nx * A.ny ? n : A.nx * A.ny;  // a list holds each cell at most once
     if (n <= (int)(blockIdx.x * blockDim.x)) return;
     cells_phase(A, C.clist[k & 1], n, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x,
-                pass_out(C, k));
+                pass_out(C, k, C.ctl->stamp0));
 }
 
 // The tail of a long cascade (few troubled cells per pass) in one workgroup:
@@ -653,6 +655,7 @@ __device__ __forceinline__ void tail_body(const StageArgs<real> &A, const Cascad
 {
     const int capf = (A.nx + 1) * A.ny + A.nx * (A.ny + 1), capc = A.nx * A.ny;
     Ctl *ctl = C.ctl;
+    const unsigned stamp0 = ctl->stamp0;
     load_gtab(A.gtab, S.wl);
     int k0 = ctl->tail_k0 > 0 ? ctl->tail_k0 : kdef;
     if (ctl->tail_k0 <= 0 && kbeg < kdef) {
@@ -691,7 +694,7 @@ __device__ __forceinline__ void tail_body(const StageArgs<real> &A, const Cascad
         if (threadIdx.x == 0) S.cnt[(k + 1) & 1][0] = S.cnt[(k + 1) & 1][1] = S.cnt[(k + 1) & 1][2] = 0;
         faces_phase(A, S.wl, S.xch[threadIdx.x >> 6], C.flist[k & 1], nf, threadIdx.x, blockDim.x);
         __syncthreads();
-        PassOut P = pass_out(C, k);
+        PassOut P = pass_out(C, k, stamp0);
         P.fcount = &S.cnt[(k + 1) & 1][0];
         P.ccount = &S.cnt[(k + 1) & 1][1];
         P.tcount = &S.cnt[(k + 1) & 1][2];
@@ -721,7 +724,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const StageArgs<real> A, 
 }
 
 // -------------------------------------------------------- small kernels
-__global__ void k_reset(Ctl *ctl, int nzero)
+__global__ void k_reset(Ctl *ctl, int nzero, unsigned stamp0)
 {
     for (int k = threadIdx.x; k < nzero && k < kMaxPasses + 2; k += blockDim.x) {
         ctl->nface[k] = 0;
@@ -732,6 +735,7 @@ __global__ void k_reset(Ctl *ctl, int nzero)
         ctl->tail_end = 0;
         ctl->tail_k0 = 0;
         ctl->tail_back = 0;
+        ctl->stamp0 = stamp0;
     }
 }
 
@@ -790,12 +794,12 @@ __global__ void k_stats_accum(Ctl *ctl, int npass, int reset)
 // max over cells of (|u_d| + c) / Delta_d in FP64, as the bit pattern of a
 // non-negative double (which orders like the integer).
 template <typename real>
-__global__ __launch_bounds__(256) void k_dt_reduce(const real *U, size_t ncell, double gamma, double dx,
-                                                   double dy, unsigned long long *lam_bits)
+__device__ __forceinline__ void dt_reduce_body(const real *U, size_t ncell, double gamma, double dx, double dy,
+                                               unsigned long long *lam_bits, size_t first, size_t stride,
+                                               double *red)
 {
-    __shared__ double red[256];
     double lam = 0.0;
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < ncell; k += (size_t)gridDim.x * blockDim.x) {
+    for (size_t k = first; k < ncell; k += stride) {
         const double r = U[k], mx = U[ncell + k], my = U[2 * ncell + k], E = U[3 * ncell + k];
         const double p = (gamma - 1.0) * (E - 0.5 * (mx * mx + my * my) / r);
         if (!(r > 0.0 && p > 0.0 && __builtin_isfinite(r) && __builtin_isfinite(p))) continue;
@@ -812,6 +816,15 @@ __global__ __launch_bounds__(256) void k_dt_reduce(const real *U, size_t ncell, 
         __syncthreads();
     }
     if (threadIdx.x == 0 && red[0] > 0.0) atomicMax(lam_bits, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_dt_reduce(const real *U, size_t ncell, double gamma, double dx,
+                                                   double dy, unsigned long long *lam_bits)
+{
+    __shared__ double red[256];
+    dt_reduce_body(U, ncell, gamma, dx, dy, lam_bits, (size_t)blockIdx.x * blockDim.x + threadIdx.x,
+                   (size_t)gridDim.x * blockDim.x, red);
 }
 
 __global__ void k_dt_finalize(Ctl *ctl, double cfl)
@@ -882,6 +895,160 @@ __global__ void k_totals_final(const double *partial, int nblk, double area, Ctl
 }
 
 // ------------------------------------------------------------- launchers
+// ------------------------------------------------------------ batched ensemble
+// Many independent problems advance together: one first-pass launch over all
+// their strips, one single-workgroup cascade per problem in one launch, and the
+// per-problem dt in three small launches.  The per-problem arguments live in
+// device tables written once; they are read through the constant address space
+// (scalar loads: the tables do not change while the kernels run).
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+
+// Generic reference to entry p of a device table, loaded as constant memory.
+template <typename T>
+__device__ __forceinline__ const T &table_entry(const T *tab, int p)
+{
+    return *(const T *)(((cptr<T>)tab) + p);
+}
+
+__device__ __forceinline__ int find_problem(cptr<int> prefix, int n, int b)
+{
+    int lo = 0, hi = n;  // prefix[lo] <= b < prefix[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <typename real, int RT, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_first_pass_batch(const BatchTabs<real> B)
+{
+    __shared__ real ring_all[WPB][8][4][LW];
+    cptr<int> blk = (cptr<int>)B.blk;
+    const int p = find_problem(blk, B.nprob, blockIdx.x);
+    const StageArgs<real> &A = table_entry(B.args, p);
+    PassOut Q = table_entry(B.pout, p);
+    Q.stamp = *A.stamp0;
+    const int wv = threadIdx.x >> 6;
+    first_pass_wave<real, RT>(A, Q, (blockIdx.x - blk[p]) * WPB + wv, ring_all[wv]);
+}
+
+// Problem p = blockIdx.x runs its whole cascade (no hand-back).
+template <typename real>
+__global__ __launch_bounds__(kTailThreads) void k_tail_batch(const BatchTabs<real> B)
+{
+    __shared__ TailShared<real> S;
+    const int p = blockIdx.x;
+    const StageArgs<real> &A = table_entry(B.args, p);
+    const Cascade &C = table_entry(B.casc, p);
+    tail_body(A, C, 1, 1, kMaxPasses, S);
+}
+
+// Stage start of every problem: counts of evaluation 0 and pass 1, tail state,
+// and a fresh claim stamp range (kMaxPasses + 2 stamps per stage).
+__global__ void k_reset_batch(const Cascade *casc, int nprob)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nprob) return;
+    Ctl *ctl = casc[p].ctl;
+    ctl->nface[1] = 0;
+    ctl->ncell[1] = 0;
+    ctl->ntroub[0] = 0;
+    ctl->tail_end = 0;
+    ctl->tail_k0 = 0;
+    ctl->tail_back = 0;
+    ctl->stamp0 += (unsigned)kMaxPasses + 2;
+}
+
+// The stamp range restarts after the stamp arrays were cleared.
+__global__ void k_stamp_restart_batch(const Cascade *casc, int nprob)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nprob) casc[p].ctl->stamp0 = 0u;
+}
+
+__global__ void k_dt_begin_batch(const Cascade *casc, int nprob)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nprob) casc[p].ctl->lam_bits = 0ull;
+}
+
+// Blocks dblk[p] .. dblk[p+1]-1 reduce problem p's U^n (the stage-0 input).
+template <typename real>
+__global__ __launch_bounds__(256) void k_dt_reduce_batch(const BatchTabs<real> B)
+{
+    __shared__ double red[256];
+    cptr<int> dblk = (cptr<int>)B.dblk;
+    const int p = find_problem(dblk, B.nprob, blockIdx.x);
+    const StageArgs<real> &A = table_entry(B.args, p);
+    const Cascade &C = table_entry(B.casc, p);
+    const int lb = blockIdx.x - dblk[p], nb = dblk[p + 1] - dblk[p];
+    dt_reduce_body(A.Us, (size_t)A.nx * A.ny, A.gamma64, A.dx64, A.dy64, &C.ctl->lam_bits,
+                   (size_t)lb * blockDim.x + threadIdx.x, (size_t)nb * blockDim.x, red);
+}
+
+__global__ void k_dt_end_batch(const Cascade *casc, int nprob, double cfl)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nprob) {
+        Ctl *ctl = casc[p].ctl;
+        ctl->dt = cfl / __longlong_as_double((long long)ctl->lam_bits);
+    }
+}
+
+// Per problem: evaluations of the last stage (0 if its cascade hit the pass
+// limit) and dt.
+__global__ void k_batch_status(const Cascade *casc, int nprob, int *iters, double *dts)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nprob) {
+        const Ctl *ctl = casc[p].ctl;
+        iters[p] = ctl->tail_end >= kMaxPasses ? 0 : ctl->tail_end;
+        dts[p] = ctl->dt;
+    }
+}
+
+template <typename real>
+hipError_t launch_batch_stage(const BatchTabs<real> &B, int top, int nfp_blocks, const Cascade *casc,
+                              hipStream_t st)
+{
+    constexpr int WPB = sizeof(real) == 8 ? 2 : 4;
+    const int nb = (B.nprob + 255) / 256;
+    hipLaunchKernelGGL(k_reset_batch, dim3(nb), dim3(256), 0, st, casc, B.nprob);
+    switch (top) {
+    case 3: hipLaunchKernelGGL((k_first_pass_batch<real, 3, WPB>), dim3(nfp_blocks), dim3(64 * WPB), 0, st, B); break;
+    case 2: hipLaunchKernelGGL((k_first_pass_batch<real, 2, WPB>), dim3(nfp_blocks), dim3(64 * WPB), 0, st, B); break;
+    case 1: hipLaunchKernelGGL((k_first_pass_batch<real, 1, WPB>), dim3(nfp_blocks), dim3(64 * WPB), 0, st, B); break;
+    default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_tail_batch<real>, dim3(B.nprob), dim3(kTailThreads), 0, st, B);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_batch_dt(const BatchTabs<real> &B, int ndt_blocks, const Cascade *casc, double cfl, hipStream_t st)
+{
+    const int nb = (B.nprob + 255) / 256;
+    hipLaunchKernelGGL(k_dt_begin_batch, dim3(nb), dim3(256), 0, st, casc, B.nprob);
+    hipLaunchKernelGGL(k_dt_reduce_batch<real>, dim3(ndt_blocks), dim3(256), 0, st, B);
+    hipLaunchKernelGGL(k_dt_end_batch, dim3(nb), dim3(256), 0, st, casc, B.nprob, cfl);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_status(const Cascade *casc, int nprob, int *iters, double *dts, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_batch_status, dim3((nprob + 255) / 256), dim3(256), 0, st, casc, nprob, iters, dts);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_stamp_restart(const Cascade *casc, int nprob, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_stamp_restart_batch, dim3((nprob + 255) / 256), dim3(256), 0, st, casc, nprob);
+    return hipGetLastError();
+}
+
 template <typename real, int RT>
 static hipError_t launch_first_pass_rt(const StageArgs<real> &A, const PassOut &P, hipStream_t st)
 {
@@ -920,9 +1087,9 @@ hipError_t launch_cascade_tail(const StageArgs<real> &A, const Cascade &C, int k
     return hipGetLastError();
 }
 
-hipError_t launch_reset(Ctl *ctl, int nzero, hipStream_t st)
+hipError_t launch_reset(Ctl *ctl, int nzero, unsigned stamp0, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, st, ctl, nzero);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, st, ctl, nzero, stamp0);
     return hipGetLastError();
 }
 
@@ -980,5 +1147,10 @@ template hipError_t launch_dt<float>(const float *, size_t, double, double, doub
 template hipError_t launch_dt<double>(const double *, size_t, double, double, double, double, Ctl *, hipStream_t);
 template hipError_t launch_totals<float>(const float *, size_t, double, double *, int, Ctl *, hipStream_t);
 template hipError_t launch_totals<double>(const double *, size_t, double, double *, int, Ctl *, hipStream_t);
+
+template hipError_t launch_batch_stage<float>(const BatchTabs<float> &, int, int, const Cascade *, hipStream_t);
+template hipError_t launch_batch_stage<double>(const BatchTabs<double> &, int, int, const Cascade *, hipStream_t);
+template hipError_t launch_batch_dt<float>(const BatchTabs<float> &, int, const Cascade *, double, hipStream_t);
+template hipError_t launch_batch_dt<double>(const BatchTabs<double> &, int, const Cascade *, double, hipStream_t);
 
 }  // namespace gpm

@@ -15,7 +15,7 @@ hipError_t launch_cascade_pass(const StageArgs<real> &A, const Cascade &C, int k
 template <typename real>
 hipError_t launch_cascade_tail(const StageArgs<real> &A, const Cascade &C, int kbeg, int kdef, int kend,
                                hipStream_t st);
-hipError_t launch_reset(Ctl *ctl, int nzero, hipStream_t st);
+hipError_t launch_reset(Ctl *ctl, int nzero, unsigned stamp0, hipStream_t st);
 hipError_t launch_level_hist(const uint8_t *order, size_t ncell, const LevIdx &levidx, Ctl *ctl, hipStream_t st);
 template <typename real>
 hipError_t launch_dt(const real *U, size_t ncell, double gamma, double dx, double dy, double cfl, Ctl *ctl,
@@ -25,6 +25,13 @@ hipError_t launch_stats(Ctl *ctl, int npass, int reset, hipStream_t st);
 template <typename real>
 hipError_t launch_totals(const real *U, size_t ncell, double area, double *partial, int nblk, Ctl *ctl,
                          hipStream_t st);
+
+template <typename real>
+hipError_t launch_batch_stage(const BatchTabs<real> &B, int top, int nfp_blocks, const Cascade *casc, hipStream_t st);
+template <typename real>
+hipError_t launch_batch_dt(const BatchTabs<real> &B, int ndt_blocks, const Cascade *casc, double cfl, hipStream_t st);
+hipError_t launch_batch_status(const Cascade *casc, int nprob, int *iters, double *dts, hipStream_t st);
+hipError_t launch_batch_stamp_restart(const Cascade *casc, int nprob, hipStream_t st);
 
 }  // namespace gpm
 
