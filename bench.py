@@ -20,7 +20,12 @@ rocprofv3 counters for the current kernel sources (null if they changed).
 cpu_baseline times the plain FP64 oracle (OpenMP over rows, all host cores) on the
 first two steps of the same 2048^2 problem, about 15-20 s of CPU work.
 
-Usage: python bench.py [--gpus 1] [--steps 500] [--warmup 20] [--no-cpu-baseline]
+A second leg times the batched ensemble (256 four-quadrant problems of sides 128
+to 1024, FP32, one HIP-graph replay per step) and the same work done one problem
+at a time; it is reported under "batched".  A third leg times a reverse-mode rollout
+(512^2 vortex + density bump, 200 steps, checkpoints every 20) under "adjoint".
+
+Usage: python bench.py [--gpus 1] [--steps 500] [--warmup 20] [--batch-steps 10] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -40,6 +45,7 @@ CASCADE = (3, 2, 1, 0)
 CFL = 0.8
 ORDER_SAMPLE_STEPS = 5   # untimed steps after the timed region that sample the final-order fractions
 CPU_STEPS = 2            # full SSP-RK3 steps of the oracle for the CPU baseline
+BATCH_N = 256            # problems of the batched ensemble
 COPY_PROBE_BYTES = 512 << 20
 METRIC = "cell-updates/s per RK stage (GP-MOOD7 2D, incl. cascade), % HBM peak; FP32 vs FP64"
 
@@ -149,6 +155,93 @@ def roofline(prec, res):
     }
 
 
+def batch_sizes():
+    """256 square problems, side uniform over {128, 192, ..., 1024} (numpy PCG64, seed 1000)."""
+    import numpy as np
+    rng = np.random.default_rng(1000)
+    return [int(x) for x in rng.choice(np.arange(128, 1025, 64), size=BATCH_N)]
+
+
+def run_batch(steps, warmup):
+    """The batched ensemble: every problem a four-quadrant problem with its own seed
+    (1000 + k), GP-MOOD7 FP32, one HIP-graph replay per SSP-RK3 step."""
+    import torch
+
+    import gpmood_inputs as gi
+    from paper_2110_08683_amd import GPMood, GPMoodBatch
+    sides = batch_sizes()
+    b = GPMoodBatch([(n, n) for n in sides], bc=(1, 1), prec="f32", cascade=CASCADE, device="cuda:0")
+    for k, n in enumerate(sides):
+        b.gpm_batch_init_state(k, gi.quadrants(n, n, seed=1000 + k))
+    b.gpm_batch_step(CFL, warmup, use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.gpm_batch_step(CFL, steps, use_graph=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    iters, _ = b.gpm_batch_status()
+    cells = sum(n * n for n in sides)
+    b.close()
+    # the same work one problem at a time: one single-problem context per distinct
+    # side (its first problem's initial state), weighted by the side's multiplicity
+    seq = 0.0
+    for n in sorted(set(sides)):
+        k = sides.index(n)
+        g = GPMood(n, n, bc=(1, 1), prec="f32", cascade=CASCADE, device="cuda:0")
+        g.gpm_init_state(gi.quadrants(n, n, seed=1000 + k))
+        g.gpm_step(CFL, warmup)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g.gpm_step(CFL, steps)
+        torch.cuda.synchronize()
+        seq += (time.perf_counter() - t1) * sides.count(n)
+        g.close()
+    return {"value": cells * 3 * steps / el, "unit": "cell-updates/s", "problems": BATCH_N, "cells": cells,
+            "steps": steps, "warmup": warmup, "ms_per_step": 1e3 * el / steps,
+            "mood_iters_last_stage_mean": float(iters.mean()),
+            "one_at_a_time_value": cells * 3 * steps / seq, "speedup_vs_one_at_a_time": seq / el,
+            "workload": "256 four-quadrant problems (seeds 1000+k), square sides uniform over "
+                        "{128,...,1024} step 64 (seed 1000), outflow, GP-MOOD7 7-5-3-1, FP32, CFL 0.8, "
+                        "one HIP-graph replay per step"}
+
+
+def run_adjoint(steps, every):
+    """Reverse-mode rollout: 512^2 vortex + Gaussian density bump on [0,10]^2,
+    periodic, GP-MOOD7 FP32, loss = sum over the middle quarter of rho^2 dx dy,
+    gradient with respect to the initial state and ell, checkpoint every `every`."""
+    import torch
+
+    import gpmood_inputs as gi
+    from paper_2110_08683_amd import GPMood
+    from paper_2110_08683_amd.adjoint import rollout
+    n = 512
+    g = GPMood(n, n, hi=(10.0, 10.0), bc=(0, 0), prec="f32", cascade=CASCADE, device="cuda:0")
+    U0 = torch.tensor(gi.vortex_bump(n, n, seed=5), dtype=torch.float32, device="cuda:0").requires_grad_(True)
+    ell = torch.tensor(g.ell, dtype=torch.float64, requires_grad=True)
+    a, b = n // 4, 3 * n // 4
+    # warm-up (library and allocator) on a short rollout
+    UT = rollout(g, U0, 2, cfl=CFL, checkpoint_every=every, ell=ell)
+    ((UT[0, a:b, a:b].double() ** 2).sum() * (10.0 / n) ** 2).backward()
+    U0.grad = None
+    ell.grad = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    UT = rollout(g, U0, steps, cfl=CFL, checkpoint_every=every, ell=ell)
+    loss = (UT[0, a:b, a:b].double() ** 2).sum() * (10.0 / n) ** 2
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    gn = float(U0.grad[0].double().norm())
+    g.close()
+    return {"workload": "512^2 isentropic vortex + Gaussian density bump (seed 5) on [0,10]^2, periodic, "
+                        "GP-MOOD7 FP32, CFL 0.8, loss = sum_box rho^2 dx dy", "steps": steps,
+            "checkpoint_every": every, "forward_ms_per_step": 1e3 * (t1 - t0) / steps,
+            "backward_ms_per_step": 1e3 * (t2 - t1) / steps, "backward_over_forward": (t2 - t1) / (t1 - t0),
+            "loss": float(loss), "grad_rho0_norm": gn, "dL_dell": float(ell.grad)}
+
+
 def cpu_baseline(U0):
     import oracle
     o = oracle.Oracle(N, N, bc=(1, 1), cascade=CASCADE)
@@ -169,6 +262,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=10,
+                    help="steps of the batched-ensemble leg (0 skips it)")
+    ap.add_argument("--adjoint-steps", type=int, default=200,
+                    help="steps of the reverse-mode leg (0 skips it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB device copy (calibrates HBM byte counters)")
     a = ap.parse_args()
@@ -218,6 +315,15 @@ def main():
                         "mood_iters_per_stage": r64["mood_iters_mean"],
                         "final_order_fraction": r64["final_order_fraction"]}
         line["fp32_over_fp64"] = r32["value"] / r64["value"]
+    if a.batch_steps > 0:
+        print(f"[bench] batched ensemble {a.batch_steps} steps", file=sys.stderr, flush=True)
+        line["batched"] = run_batch(a.batch_steps, 2)
+        print(f"[bench] batched done: {line['batched']['value']:.3e} cell-updates/s", file=sys.stderr, flush=True)
+    if a.adjoint_steps > 0:
+        print(f"[bench] adjoint rollout {a.adjoint_steps} steps", file=sys.stderr, flush=True)
+        line["adjoint"] = run_adjoint(a.adjoint_steps, 20)
+        print(f"[bench] adjoint done: backward/forward {line['adjoint']['backward_over_forward']:.2f}",
+              file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(U0)

@@ -93,6 +93,34 @@ def vortex(nx, ny, lo=(0.0, 0.0), hi=(10.0, 10.0), centre=None, beta=5.0,
     return out
 
 
+def vortex_bump(nx, ny, lo=(0.0, 0.0), hi=(10.0, 10.0), seed=5, amp=0.05, gamma=GAMMA):
+    """Centred vortex plus a Gaussian density bump (velocity and pressure unchanged),
+    cell-averaged with the 5x5 Gauss-Legendre rule.  The bump's centre is uniform in
+    the middle half of the box and its width in [0.05, 0.1] times the box side
+    (numpy PCG64, given seed)."""
+    rng = np.random.default_rng(seed)
+    Lx, Ly = hi[0] - lo[0], hi[1] - lo[1]
+    bx = lo[0] + Lx * (0.25 + 0.5 * rng.random())
+    by = lo[1] + Ly * (0.25 + 0.5 * rng.random())
+    wid = min(Lx, Ly) * (0.05 + 0.05 * rng.random())
+    xc, yc = lo[0] + 0.5 * Lx, lo[1] + 0.5 * Ly
+    xcen, dx = cell_centres(nx, lo[0], hi[0])
+    ycen, dy = cell_centres(ny, lo[1], hi[1])
+    g, w = _gl5()
+    out = np.zeros((4, ny, nx))
+    for a in range(5):
+        yy = (ycen + g[a] * dy)[:, None] + 0.0 * xcen[None, :]
+        for b in range(5):
+            xx = (xcen + g[b] * dx)[None, :] + 0.0 * ycen[:, None]
+            U = vortex_point(xx, yy, xc, yc, 5.0, (1.0, 1.0), gamma)
+            rho = U[0]
+            u, v = U[1] / rho, U[2] / rho
+            p = (gamma - 1.0) * (U[3] - 0.5 * rho * (u * u + v * v))
+            rho = rho + amp * np.exp(-((xx - bx) ** 2 + (yy - by) ** 2) / (2.0 * wid * wid))
+            out += w[a] * w[b] * prim_to_cons(rho, u, v, p, gamma)
+    return out
+
+
 # --------------------------------------------------------------------------
 # four-quadrant Riemann problem (seeded)
 # --------------------------------------------------------------------------
@@ -168,6 +196,23 @@ def shock_tube(nx, ny, left, right, x0=0.5, gamma=GAMMA):
 # --------------------------------------------------------------------------
 # 3D blast (seeded density noise)
 # --------------------------------------------------------------------------
+def density_wave3d(n, amp=0.2, u=1.0, v=1.0, w=1.0, p=1.0, t=0.0, gamma=GAMMA):
+    """Smooth 3D density wave on the periodic unit cube, rho = 1 + amp sin(2 pi (x+y+z -
+    (u+v+w) t)), constant velocity and pressure: exact cell averages of the translated
+    wave (5, n, n, n)."""
+    c, d = cell_centres(n, 0.0, 1.0)
+    ph = 2.0 * math.pi * (c[None, None, :] + c[None, :, None] + c[:, None, None] - (u + v + w) * t)
+    f = (math.sin(math.pi * d) / (math.pi * d)) ** 3
+    rho = 1.0 + amp * f * np.sin(ph)
+    out = np.zeros((5, n, n, n))
+    out[0] = rho
+    out[1] = rho * u
+    out[2] = rho * v
+    out[3] = rho * w
+    out[4] = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+    return out
+
+
 def blast3d(n, seed=3, r_cells=3.0, p_in=1e4, p_out=1e-5, noise=0.01, gamma=GAMMA):
     rng = np.random.Generator(np.random.PCG64(seed))
     rho = 1.0 + noise * rng.uniform(-1.0, 1.0, size=(n, n, n))

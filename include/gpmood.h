@@ -132,6 +132,9 @@ gpm_status gpm_get_state(gpm_ctx *ctx, double *U_host);
    next stages; if dt_host is non-NULL the call synchronises and returns it. */
 gpm_status gpm_compute_dt(gpm_ctx *ctx, double cfl, double *dt_host);
 
+/* The same from a caller device state U (SoA [4][ny][nx], context precision). */
+gpm_status gpm_compute_dt_dev(gpm_ctx *ctx, const void *U, double cfl, double *dt_host);
+
 /* Set the device dt directly (for replays and fixed-step runs). */
 gpm_status gpm_set_dt(gpm_ctx *ctx, double dt);
 
@@ -188,6 +191,30 @@ gpm_status gpm_instrument(gpm_ctx *ctx, int mode);
 gpm_status gpm_instrument_read(gpm_ctx *ctx, double *first_pass_ms, long long *first_pass_launches,
                                double *cascade_ms, long long *stages, long long level_cells[4],
                                long long *mood_iters);
+
+/* Device address of the context's per-cell order array (uint8 [ny][nx], the GP
+   radius of every cell; after a stage, its final orders).  Errors: GPM_ESTATE if
+   not bound. */
+gpm_status gpm_order_ptr(const gpm_ctx *ctx, void **order_dev);
+
+/* Adjoint of one stage (vector-Jacobian product) with the forward stage's final
+   cell orders and its dt held fixed: the stage is then the smooth map of eq.
+   (fvm_discrete) with eq. (fvm_F) and eq. (gp_reconstructor) at each face's
+   EDP_1 radius and the combination of eq. (rk3); HLLC is differentiated on the
+   branch the forward took.  Inputs (device, the context's precision, SoA
+   [4][ny][nx]): the stage's Un and Us (Un ignored for s = 0, where Un = Us), its
+   final orders `order` (uint8 [ny][nx], e.g. a copy of gpm_order_ptr's array
+   taken right after the forward stage), dt, and lam_out = dL/dU_out.  Outputs:
+   lam_Us = dL/dU_s (overwritten); for s > 0, lam_Un += dL/dU^n; for s = 0 a
+   non-NULL lam_Un (the adjoint of U^n gathered from stages 1 and 2) is added to
+   lam_Us, which then holds the total dL/dU^n of the step.  If dL_dell is
+   non-NULL, the stage's contribution to dL/d(ell) (ell the physical GP length
+   scale; through the ell-dependence of the reconstruction weights only, the
+   detection being frozen) is added to *dL_dell (synchronising).  The context's
+   stored face fluxes are overwritten (scratch).  Errors: GPM_EINVAL (bad stage,
+   NULL or aliased buffers, dt <= 0), GPM_ESTATE. */
+gpm_status gpm_stage_vjp(gpm_ctx *ctx, int s, const void *Un, const void *Us, const void *order, double dt,
+                         const void *lam_out, void *lam_Us, void *lam_Un, double *dL_dell);
 
 /* ---------------------------------------------------------------------------
    Batched ensemble: many independent problems of uneven size advanced

@@ -11,6 +11,8 @@ Parts:
                     (gp_reconstructor), (normalized_z), App. B.
   gpmood_oracle.c   the stage: GP reconstruction, HLLC, candidate, MOOD loop
                     (Steps 3-10), SSP-RK3, dt, totals; plain loops in FP64.
+  weights3d_mp.py   the same weights in 3D (L1-ball stencil, tensor Gauss nodes).
+  gpmood_oracle3d.c the 3D stage (five variables), same steps.
   exact_riemann.py  Toro's exact Riemann solver for the 1D shock-tube pins.
 
 Pins: see tests/test_oracle_*.py.  Every function here is pinned by at least
@@ -29,21 +31,28 @@ from . import weights_mp
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gpmood_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_SRC3 = os.path.join(_HERE, "gpmood_oracle3d.c")
+_LIB3 = os.path.join(_HERE, "liboracle3d.so")
 
 ORC_CSD, ORC_PLATEAU, ORC_U2, ORC_RSCAD = 1, 2, 4, 8
 ORC_ALL = ORC_CSD | ORC_PLATEAU | ORC_U2 | ORC_RSCAD
 
 
-def build(force=True):
-    """Compile the oracle with gcc (plain -O2, no FP contraction, no fast-math)."""
-    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
-        return _LIB
-    tmp = _LIB + ".tmp"
+def _compile(src, out, force):
+    if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(src):
+        return out
+    tmp = out + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-           "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+           "-fPIC", "-shared", "-o", tmp, src, "-lm"]
     subprocess.check_call(cmd)
-    os.replace(tmp, _LIB)
-    return _LIB
+    os.replace(tmp, out)
+    return out
+
+
+def build(force=True):
+    """Compile the 2D and 3D oracles with gcc (plain -O2, no FP contraction, no fast-math)."""
+    _compile(_SRC3, _LIB3, force)
+    return _compile(_SRC, _LIB, force)
 
 
 _lib = None
@@ -230,3 +239,122 @@ def hllc(UL, UR, direction=0, gamma=1.4):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+# ---------------------------------------------------------------------------- 3D
+class _Cfg3(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int * 3),
+        ("d", ctypes.c_double * 3),
+        ("bc", ctypes.c_int * 3),
+        ("gamma", ctypes.c_double),
+        ("nlev", ctypes.c_int),
+        ("rad", ctypes.c_int * 4),
+        ("nst", ctypes.c_int * 4),
+        ("off", ctypes.POINTER(ctypes.c_int) * 4),
+        ("nq", ctypes.c_int * 4),
+        ("qw", ctypes.POINTER(ctypes.c_double) * 4),
+        ("z", ctypes.POINTER(ctypes.c_double) * 4),
+        ("w2", ctypes.POINTER(ctypes.c_double)),
+        ("off1", ctypes.POINTER(ctypes.c_int)),
+        ("sigma_v", ctypes.c_double), ("sigma_p", ctypes.c_double),
+        ("flags", ctypes.c_uint),
+    ]
+
+
+_lib3 = None
+
+
+def lib3():
+    global _lib3
+    if _lib3 is None:
+        _compile(_SRC3, _LIB3, False)
+        L = ctypes.CDLL(_LIB3)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        cp = ctypes.POINTER(_Cfg3)
+        L.orc3_stage.argtypes = [cp, ctypes.c_int, dp, dp, ctypes.c_double, dp, ip, ctypes.POINTER(ctypes.c_longlong)]
+        L.orc3_stage.restype = ctypes.c_int
+        L.orc3_dt.argtypes = [cp, dp, ctypes.c_double]
+        L.orc3_dt.restype = ctypes.c_double
+        L.orc3_run.argtypes = [cp, dp, ctypes.c_double, ctypes.c_int, dp, ip, ctypes.POINTER(ctypes.c_longlong)]
+        L.orc3_hllc.argtypes = [ctypes.c_double, dp, dp, ctypes.c_int, dp]
+        _lib3 = L
+    return _lib3
+
+
+class Oracle3D:
+    """3D GP-MOOD oracle on [lo, hi] with n = (nx, ny, nz) cells, five variables
+    (rho, rho u, rho v, rho w, E) in SoA (5, nz, ny, nx).  bc: per axis, 0 periodic /
+    1 outflow.  cascade: radii (at most 2), strictly decreasing, ending in 0."""
+
+    def __init__(self, n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(1, 1, 1), cascade=(2, 1, 0),
+                 ell=None, gamma=1.4, sigma_v=5.0, sigma_p=5.0, flags=ORC_ALL):
+        from . import weights3d_mp as w3
+        self.n = tuple(int(x) for x in n)
+        self.d = tuple((hi[k] - lo[k]) / self.n[k] for k in range(3))
+        if ell is None:
+            ell = 12.0 * min(self.d)
+        self.ell = ell
+        self.cascade = tuple(cascade)
+        a = [ell / self.d[k] for k in range(3)]
+        self._keep = []
+        c = _Cfg3()
+        for k in range(3):
+            c.n[k], c.d[k], c.bc[k] = self.n[k], self.d[k], int(bc[k])
+        c.gamma = gamma
+        c.nlev = len(cascade)
+        for l, R in enumerate(cascade):
+            st = np.array(w3.stencil3(R), dtype=np.int32).reshape(-1)
+            z = np.array(w3.weights3(R, a[0], a[1], a[2]), dtype=np.float64).reshape(-1)
+            qw = np.array(w3.node_weights3(R), dtype=np.float64)
+            self._keep += [st, z, qw]
+            c.rad[l] = R
+            c.nst[l] = len(st) // 3
+            c.off[l] = _ip(st)
+            c.nq[l] = len(qw)
+            c.qw[l] = _dp(qw)
+            c.z[l] = _dp(z)
+        w2 = np.array(w3.d2_weights3(a[0], a[1], a[2], ell), dtype=np.float64).reshape(-1)
+        off1 = np.array(w3.stencil3(1), dtype=np.int32).reshape(-1)
+        self._keep += [w2, off1]
+        c.w2 = _dp(w2)
+        c.off1 = _ip(off1)
+        c.sigma_v, c.sigma_p, c.flags = sigma_v, sigma_p, flags
+        self.cfg = c
+
+    def _arr(self, U):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        assert U.shape == (5, self.n[2], self.n[1], self.n[0])
+        return U
+
+    def stage(self, s, Un, Us, dt):
+        """One stage with the full MOOD loop.  Returns (Uout, order, counts, iters)."""
+        Un, Us = self._arr(Un), self._arr(Us)
+        out = np.empty_like(Us)
+        order = np.empty((self.n[2], self.n[1], self.n[0]), dtype=np.int32)
+        counts = np.zeros(len(self.cascade), dtype=np.int64)
+        it = lib3().orc3_stage(ctypes.byref(self.cfg), int(s), _dp(Un), _dp(Us), float(dt), _dp(out),
+                               _ip(order), counts.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)))
+        return out, order, counts, it
+
+    def dt(self, U, cfl):
+        return lib3().orc3_dt(ctypes.byref(self.cfg), _dp(self._arr(U)), float(cfl))
+
+    def run(self, U, cfl=0.3, nsteps=1):
+        """nsteps SSP-RK3 steps.  Returns (U, dts, iters[nsteps, 3], counts of the last stage)."""
+        U = self._arr(U).copy()
+        dts = np.zeros(nsteps)
+        iters = np.zeros((nsteps, 3), dtype=np.int32)
+        counts = np.zeros(len(self.cascade), dtype=np.int64)
+        lib3().orc3_run(ctypes.byref(self.cfg), _dp(U), float(cfl), int(nsteps), _dp(dts), _ip(iters),
+                        counts.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)))
+        return U, dts, iters, counts
+
+
+def hllc3(gamma, UL, UR, d):
+    UL = np.ascontiguousarray(UL, dtype=np.float64)
+    UR = np.ascontiguousarray(UR, dtype=np.float64)
+    F = np.zeros(5)
+    lib3().orc3_hllc(float(gamma), _dp(UL), _dp(UR), int(d), _dp(F))
+    return F

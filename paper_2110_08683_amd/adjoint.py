@@ -1,0 +1,93 @@
+"""Reverse-mode differentiation of GP-MOOD rollouts through the stage adjoint.
+
+`rollout(g, U0, nsteps, cfl, checkpoint_every)` is a torch.autograd.Function over a
+single-problem context `g` (GPMood): the forward advances U0 by nsteps SSP-RK3
+steps on the GPU and keeps the state every `checkpoint_every` steps; the backward
+recomputes each segment from its checkpoint (keeping that segment's stage inputs,
+final cell orders and dt) and runs gpm_stage_vjp stage by stage in reverse.  The
+cell orders and every dt are those of the forward, held fixed (the detection and
+the CFL reduction are not differentiated).  Besides dL/dU0 the backward returns
+dL/d(ell) through the GP weights (as the gradient of the `ell` input).
+
+Only control flow and buffer handling live here: every arithmetic step of the
+forward and of the adjoint runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import torch
+
+
+class _Rollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, U0, ell, g, nsteps, cfl, every):
+        ctx.g, ctx.nsteps, ctx.cfl, ctx.every = g, int(nsteps), float(cfl), int(every)
+        U = U0.detach().to(device=g.device, dtype=g.dtype).contiguous().clone()
+        checkpoints = []
+        dts = []
+        with torch.cuda.stream(g.stream):
+            for n in range(ctx.nsteps):
+                if n % ctx.every == 0:
+                    checkpoints.append(U.clone())
+                U, dt, _, _ = _step(g, U, ctx.cfl, keep=False)
+                dts.append(dt)
+        ctx.checkpoints = checkpoints
+        ctx.dts = dts
+        return U
+
+    @staticmethod
+    def backward(ctx, lam_T):
+        g = ctx.g
+        lam = lam_T.detach().to(device=g.device, dtype=g.dtype).contiguous().clone()
+        dl_dell = 0.0
+        with torch.cuda.stream(g.stream):
+            nseg = len(ctx.checkpoints)
+            for seg in reversed(range(nseg)):
+                n0 = seg * ctx.every
+                n1 = min(ctx.nsteps, n0 + ctx.every)
+                # recompute the segment, keeping every stage's inputs and orders
+                U = ctx.checkpoints[seg].clone()
+                tape = []
+                for n in range(n0, n1):
+                    U, dt, stages, orders = _step(g, U, ctx.cfl, keep=True)
+                    tape.append((dt, stages, orders))
+                for dt, (Un, U1, U2), (o0, o1, o2) in reversed(tape):
+                    lam_n = torch.zeros_like(lam)
+                    l2 = torch.empty_like(lam)
+                    dl_dell += g.gpm_stage_vjp(2, Un, U2, o2, dt, lam, l2, lam_n)
+                    l1 = torch.empty_like(lam)
+                    dl_dell += g.gpm_stage_vjp(1, Un, U1, o1, dt, l2, l1, lam_n)
+                    l0 = torch.empty_like(lam)
+                    dl_dell += g.gpm_stage_vjp(0, Un, Un, o0, dt, l1, l0, lam_n)
+                    lam = l0
+        grad_ell = torch.tensor(dl_dell, dtype=torch.float64)
+        return lam, grad_ell, None, None, None, None
+
+
+def _step(g, Un, cfl, keep):
+    """One SSP-RK3 step of context g from the device tensor Un (4, ny, nx)."""
+    dt = g.gpm_compute_dt_dev(Un, cfl)
+    U1 = torch.empty_like(Un)
+    U2 = torch.empty_like(Un)
+    U3 = torch.empty_like(Un)
+    orders = []
+    g.gpm_stage_dev(0, Un, Un, U1)
+    if keep:
+        orders.append(g.gpm_order_ptr().clone())
+    g.gpm_stage_dev(1, Un, U1, U2)
+    if keep:
+        orders.append(g.gpm_order_ptr().clone())
+    g.gpm_stage_dev(2, Un, U2, U3)
+    if keep:
+        orders.append(g.gpm_order_ptr().clone())
+    return U3, dt, (Un, U1, U2), orders
+
+
+def rollout(g, U0, nsteps, cfl=0.8, checkpoint_every=20, ell=None):
+    """Differentiable nsteps-step rollout of context g from U0 (torch (4, ny, nx)).
+
+    `ell` (a 0-dim tensor, default the context's length scale) receives dL/d(ell);
+    its value must equal the context's ell (the weights are built by set_scheme).
+    """
+    if ell is None:
+        ell = torch.tensor(g.ell, dtype=torch.float64, requires_grad=True)
+    return _Rollout.apply(U0, ell, g, nsteps, cfl, checkpoint_every)

@@ -23,9 +23,10 @@ GPM_FLAGS_ALL = 15
 
 # every symbol include/gpmood.h declares
 EXPORTS = ("gpm_create", "gpm_set_scheme", "gpm_workspace_size", "gpm_bind", "gpm_state_ptr",
-           "gpm_init_state", "gpm_get_state", "gpm_compute_dt", "gpm_set_dt", "gpm_stage_dev",
+           "gpm_init_state", "gpm_get_state", "gpm_compute_dt", "gpm_compute_dt_dev", "gpm_set_dt", "gpm_stage_dev",
            "gpm_step", "gpm_troubled_counts", "gpm_get_order_mask", "gpm_totals", "gpm_totals_dev",
-           "gpm_set_tuning", "gpm_instrument", "gpm_instrument_read", "gpm_batch_create",
+           "gpm_set_tuning", "gpm_instrument", "gpm_instrument_read", "gpm_order_ptr", "gpm_stage_vjp",
+           "gpm_batch_create",
            "gpm_batch_set_scheme", "gpm_batch_workspace_size", "gpm_batch_bind", "gpm_batch_set_tuning",
            "gpm_batch_init_state", "gpm_batch_get_state", "gpm_batch_step", "gpm_batch_status",
            "gpm_batch_troubled_counts", "gpm_batch_get_order_mask", "gpm_batch_last_error",
@@ -69,6 +70,7 @@ def lib():
         "gpm_init_state": ([ctxp, dp], st),
         "gpm_get_state": ([ctxp, dp], st),
         "gpm_compute_dt": ([ctxp, ctypes.c_double, dp], st),
+        "gpm_compute_dt_dev": ([ctxp, vp, ctypes.c_double, dp], st),
         "gpm_set_dt": ([ctxp, ctypes.c_double], st),
         "gpm_stage_dev": ([ctxp, ctypes.c_int, vp, vp, vp], st),
         "gpm_step": ([ctxp, ctypes.c_double, ctypes.c_int], st),
@@ -80,6 +82,8 @@ def lib():
         "gpm_instrument": ([ctxp, ctypes.c_int], st),
         "gpm_instrument_read": ([ctxp, dp, ctypes.POINTER(ctypes.c_longlong), dp, ctypes.POINTER(ctypes.c_longlong),
                                  ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)], st),
+        "gpm_order_ptr": ([ctxp, ctypes.POINTER(vp)], st),
+        "gpm_stage_vjp": ([ctxp, ctypes.c_int, vp, vp, vp, ctypes.c_double, vp, vp, vp, dp], st),
         "gpm_batch_create": ([ctypes.c_int, ctypes.POINTER(gpm_grid), ctypes.c_int, vp, ctypes.POINTER(ctxp)], st),
         "gpm_batch_set_scheme": ([ctxp, ctypes.POINTER(gpm_scheme)], st),
         "gpm_batch_workspace_size": ([ctxp, ctypes.POINTER(ctypes.c_size_t)], st),
@@ -146,6 +150,8 @@ class GPMood:
         s.ell = 0.0 if ell is None else float(ell)
         s.sigma_v, s.sigma_p, s.flags = sigma_v, sigma_p, flags
         self._check(L.gpm_set_scheme(self.ctx, ctypes.byref(s)))
+        dx, dy = (hi[0] - lo[0]) / self.nx, (hi[1] - lo[1]) / self.ny
+        self.ell = 12.0 * min(dx, dy) if ell is None else float(ell)
         sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
         self._check(L.gpm_workspace_size(self.ctx, ctypes.byref(sb), ctypes.byref(wb)))
         self.state_buf = torch.empty(sb.value, dtype=torch.uint8, device=self.device)
@@ -206,6 +212,13 @@ class GPMood:
         self._check(lib().gpm_compute_dt(self.ctx, float(cfl), None))
         return None
 
+    def gpm_compute_dt_dev(self, U, cfl):
+        """dt from a device state U (torch (4, ny, nx)); kept on the device for the next stages."""
+        assert U.dtype == self.dtype and U.is_contiguous() and U.numel() == 4 * self.nx * self.ny
+        dt = ctypes.c_double()
+        self._check(lib().gpm_compute_dt_dev(self.ctx, ctypes.c_void_p(U.data_ptr()), float(cfl), ctypes.byref(dt)))
+        return dt.value
+
     def gpm_set_dt(self, dt):
         self._check(lib().gpm_set_dt(self.ctx, float(dt)))
 
@@ -239,6 +252,27 @@ class GPMood:
         t = np.zeros(4)
         self._check(lib().gpm_totals_dev(self.ctx, ctypes.c_void_p(U.data_ptr()), _dp(t)))
         return t
+
+    def gpm_order_ptr(self):
+        """Torch uint8 view (ny, nx) of the context's order array (device memory)."""
+        p = ctypes.c_void_p()
+        self._check(lib().gpm_order_ptr(self.ctx, ctypes.byref(p)))
+        off = p.value - self.work_buf.data_ptr()
+        return self.work_buf[off:off + self.nx * self.ny].view(self.ny, self.nx)
+
+    def gpm_stage_vjp(self, s, Un, Us, order, dt, lam_out, lam_Us, lam_Un=None, want_dell=True):
+        """Stage adjoint; torch device tensors.  Returns this stage's dL/d(ell) (or None)."""
+        for t in (Us, lam_out, lam_Us) + (() if s == 0 else (Un,)) + (() if lam_Un is None else (lam_Un,)):
+            assert t.dtype == self.dtype and t.is_contiguous() and t.numel() == 4 * self.nx * self.ny
+        assert order.dtype == self.torch.uint8 and order.numel() == self.nx * self.ny
+        d = ctypes.c_double(0.0)
+        vp = ctypes.c_void_p
+        self._check(lib().gpm_stage_vjp(self.ctx, int(s), vp(Un.data_ptr() if Un is not None else 0),
+                                        vp(Us.data_ptr()), vp(order.data_ptr()), float(dt),
+                                        vp(lam_out.data_ptr()), vp(lam_Us.data_ptr()),
+                                        vp(lam_Un.data_ptr() if lam_Un is not None else 0),
+                                        ctypes.byref(d) if want_dell else None))
+        return d.value if want_dell else None
 
     def gpm_set_tuning(self, passes_per_check=4, rows_per_wave=16, tail_threshold=48):
         self._check(lib().gpm_set_tuning(self.ctx, int(passes_per_check), int(rows_per_wave), int(tail_threshold)))

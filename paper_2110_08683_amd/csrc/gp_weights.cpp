@@ -120,12 +120,11 @@ int index_of(const std::vector<Cell> &st, int di, int dj)
 
 }  // namespace
 
-int gpw_level(int R, double ax_d, double ay_d, GpwLevel *out)
+namespace {
+
+// Quarter-basis weights of radius R at (ax, ay) = ell / (dx, dy), in quad precision.
+int level_q(int R, qf ax, qf ay, qf W[2][2][25], qf qw[2])
 {
-    std::memset(out, 0, sizeof(*out));
-    out->R = R;
-    if (R <= 0) return 0;
-    const qf ax = ax_d, ay = ay_d;
     std::vector<Cell> st = diamond(R);
     const int n = (int)st.size();
     std::vector<qf> L(n * n);
@@ -133,12 +132,8 @@ int gpw_level(int R, double ax_d, double ay_d, GpwLevel *out)
         for (int k = 0; k < n; ++k)
             L[m * n + k] = c_factor((qf)(st[k].di - st[m].di), ax) * c_factor((qf)(st[k].dj - st[m].dj), ay);
     if (!cholesky(L, n)) return -1;
-    qf g[2], w[2];
-    gauss_slots(R, g, w);
-    for (int k = 0; k < slots_of(R); ++k) {
-        out->qw64[k] = (double)w[k];
-        out->qw32[k] = (float)w[k];
-    }
+    qf g[2];
+    gauss_slots(R, g, qw);
     for (int dir = 0; dir < 2; ++dir)
         for (int k = 0; k < slots_of(R); ++k) {
             // x faces: x* = (+1/2, g); y faces: x* = (g, +1/2)
@@ -153,24 +148,55 @@ int gpw_level(int R, double ax_d, double ay_d, GpwLevel *out)
             auto Z = [&](int di, int dj) { return z[index_of(st, di, dj)]; };
             for (int e = 0; e < kNQ[R]; ++e) {
                 const int a = kQ[e].a, b = kQ[e].b, c = kQ[e].comp;
-                qf W;
+                qf w;
                 if (a == 0 && b == 0) {
-                    W = Z(0, 0);
+                    w = Z(0, 0);
                 } else if (b == 0) {
-                    W = c == C_EE ? (Z(a, 0) + Z(-a, 0)) / 2 : (Z(a, 0) - Z(-a, 0)) / 2;
+                    w = c == C_EE ? (Z(a, 0) + Z(-a, 0)) / 2 : (Z(a, 0) - Z(-a, 0)) / 2;
                 } else if (a == 0) {
-                    W = c == C_EE ? (Z(0, b) + Z(0, -b)) / 2 : (Z(0, b) - Z(0, -b)) / 2;
+                    w = c == C_EE ? (Z(0, b) + Z(0, -b)) / 2 : (Z(0, b) - Z(0, -b)) / 2;
                 } else {
                     qf pp = Z(a, b), mp = Z(-a, b), pm = Z(a, -b), mm = Z(-a, -b);
-                    if (c == C_EE) W = (pp + mp + pm + mm) / 4;
-                    else if (c == C_OE) W = (pp - mp + pm - mm) / 4;
-                    else if (c == C_EO) W = (pp + mp - pm - mm) / 4;
-                    else W = (pp - mp - pm + mm) / 4;
+                    if (c == C_EE) w = (pp + mp + pm + mm) / 4;
+                    else if (c == C_OE) w = (pp - mp + pm - mm) / 4;
+                    else if (c == C_EO) w = (pp + mp - pm - mm) / 4;
+                    else w = (pp - mp - pm + mm) / 4;
                 }
-                out->w64[dir][k][e] = (double)W;
-                out->w32[dir][k][e] = (float)W;
+                W[dir][k][e] = w;
             }
         }
+    return 0;
+}
+
+}  // namespace
+
+int gpw_level(int R, double ax_d, double ay_d, GpwLevel *out)
+{
+    std::memset(out, 0, sizeof(*out));
+    out->R = R;
+    if (R <= 0) return 0;
+    qf W[2][2][25] = {}, qw[2] = {0, 0};
+    if (level_q(R, ax_d, ay_d, W, qw) != 0) return -1;
+    for (int k = 0; k < slots_of(R); ++k) {
+        out->qw64[k] = (double)qw[k];
+        out->qw32[k] = (float)qw[k];
+    }
+    for (int dir = 0; dir < 2; ++dir)
+        for (int k = 0; k < slots_of(R); ++k)
+            for (int e = 0; e < kNQ[R]; ++e) {
+                out->w64[dir][k][e] = (double)W[dir][k][e];
+                out->w32[dir][k][e] = (float)W[dir][k][e];
+            }
+    // d w / d log(ell): central difference in quad precision, ell scaled by 1 +- h
+    // (both ax and ay scale with ell); the step keeps truncation (h^2) and the
+    // rounding of the ill-conditioned solve (~1e-19 / h) below 1e-12
+    const qf h = (qf)1 / 1000000;
+    qf Wp[2][2][25] = {}, Wm[2][2][25] = {}, q2[2];
+    if (level_q(R, (qf)ax_d * (1 + h), (qf)ay_d * (1 + h), Wp, q2) != 0) return -1;
+    if (level_q(R, (qf)ax_d * (1 - h), (qf)ay_d * (1 - h), Wm, q2) != 0) return -1;
+    for (int dir = 0; dir < 2; ++dir)
+        for (int k = 0; k < slots_of(R); ++k)
+            for (int e = 0; e < kNQ[R]; ++e) out->dlw64[dir][k][e] = (double)((Wp[dir][k][e] - Wm[dir][k][e]) / (2 * h));
     return 0;
 }
 

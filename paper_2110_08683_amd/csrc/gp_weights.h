@@ -14,6 +14,7 @@ struct GpwLevel {
     float w32[2][2][25];
     double qw64[2];  // Gauss weights of the stored slots (pair member / centre node)
     float qw32[2];
+    double dlw64[2][2][25];  // d w / d log(ell) (the adjoint's ell gradient)
 };
 
 // u2 curvature weights (App. B, GP-R1 stencil, at the cell centre, unnormalised),

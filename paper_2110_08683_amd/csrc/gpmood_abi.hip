@@ -93,8 +93,9 @@ gpm_status gpm_set_scheme(gpm_ctx *c, const gpm_scheme *s)
     const double ax = ell / c->dx, ay = ell / c->dy;
     std::memset(&c->w64, 0, sizeof(c->w64));
     std::memset(&c->w32, 0, sizeof(c->w32));
-    std::vector<double> g64(kGtabSize, 0.0);
-    std::vector<float> g32(kGtabSize, 0.0f);
+    // the compact table, then its derivative with respect to ell (same layout)
+    std::vector<double> g64(2 * kGtabSize, 0.0);
+    std::vector<float> g32(2 * kGtabSize, 0.0f);
     // FOG: the cell value itself (gathered 4x at the centre), one node of weight 1
     for (int d = 0; d < 2; ++d) {
         g64[(0 * 2 + d) * kGtabPerDir + C_EE] = 0.25;
@@ -125,6 +126,8 @@ gpm_status gpm_set_scheme(gpm_ctx *c, const gpm_scheme *s)
                     const int k = (R * 2 + d) * kGtabPerDir + p * (kNPos * 4) + pos * 4 + kQ[e].comp;
                     g64[k] = L.w64[d][p][e] * f;
                     g32[k] = L.w32[d][p][e] * (float)f;
+                    g64[kGtabSize + k] = L.dlw64[d][p][e] * f / ell;
+                    g32[kGtabSize + k] = (float)(L.dlw64[d][p][e] * f / ell);
                 }
         for (int p = 0; p < slots_of(R); ++p) {
             g64[kGtabNodeOff + R * 2 + p] = L.qw64[p];
@@ -255,6 +258,20 @@ gpm_status gpm_compute_dt(gpm_ctx *c, double cfl, double *dt_host)
     if (!c->state) return fail(c, GPM_ESTATE, "not bound");
     if (!(cfl > 0.0)) return fail(c, GPM_EINVAL, "cfl must be > 0");
     gpm_status st = compute_dt_from(c, slot_ptr(c, c->cur), cfl);
+    if (st != GPM_OK) return st;
+    if (dt_host) {
+        HIPCHK(c, hipMemcpyAsync(dt_host, &c->ctl->dt, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return GPM_OK;
+}
+
+gpm_status gpm_compute_dt_dev(gpm_ctx *c, const void *U, double cfl, double *dt_host)
+{
+    if (!c || !U) return GPM_EINVAL;
+    if (!c->state) return fail(c, GPM_ESTATE, "not bound");
+    if (!(cfl > 0.0)) return fail(c, GPM_EINVAL, "cfl must be > 0");
+    gpm_status st = compute_dt_from(c, U, cfl);
     if (st != GPM_OK) return st;
     if (dt_host) {
         HIPCHK(c, hipMemcpyAsync(dt_host, &c->ctl->dt, sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -422,6 +439,68 @@ gpm_status gpm_step(gpm_ctx *c, double cfl, int nsteps)
         c->cur = a;
     }
     return GPM_OK;
+}
+
+gpm_status gpm_order_ptr(const gpm_ctx *c, void **order_dev)
+{
+    if (!c || !order_dev) return GPM_EINVAL;
+    if (!c->state) return GPM_ESTATE;
+    *order_dev = c->order;
+    return GPM_OK;
+}
+
+}  // extern "C"
+
+template <typename real>
+static gpm_status stage_vjp(gpm_ctx *c, const Weights<real> &W, int s, const void *Un, const void *Us,
+                            const void *order, double dt, const void *lam_out, void *lam_Us, void *lam_Un,
+                            double *dL_dell)
+{
+    AdjArgs<real> J;
+    fill_args(c, W, J.A);
+    J.A.s = s;
+    J.A.Un = (const real *)Un;
+    J.A.Us = (const real *)Us;
+    J.A.Uout = nullptr;
+    J.A.order = (uint8_t *)order;
+    J.lam_out = (const real *)lam_out;
+    J.lam_Us = (real *)lam_Us;
+    J.lam_Un = (real *)lam_Un;
+    // scratch: the face-flux arrays (FX then GY, contiguous) hold the FP64
+    // accumulator; the reduction partials hold the ell terms
+    J.acc = (double *)c->FX;
+    J.dl_partial = c->partial;
+    hipError_t e = launch_set_dt(c->ctl, dt, c->stream);
+    if (e != hipSuccess) return fail(c, GPM_EHIP, hipGetErrorString(e));
+    J.A.dt = &c->ctl->dt;
+    const size_t nft = nfaces_x(c) + nfaces_y(c);
+    int nblk = (int)((nft + 127) / 128);
+    if (nblk > kTotBlocks * 8) nblk = kTotBlocks * 8;
+    e = launch_stage_vjp<real>(J, nblk, &c->ctl->totals[0], c->stream);
+    if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("stage adjoint: ") + hipGetErrorString(e));
+    if (dL_dell) {
+        double d = 0.0;
+        HIPCHK(c, hipMemcpyAsync(&d, &c->ctl->totals[0], sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        *dL_dell += d;
+    }
+    return GPM_OK;
+}
+
+extern "C" {
+
+gpm_status gpm_stage_vjp(gpm_ctx *c, int s, const void *Un, const void *Us, const void *order, double dt,
+                         const void *lam_out, void *lam_Us, void *lam_Un, double *dL_dell)
+{
+    if (!c) return GPM_EINVAL;
+    if (!c->have_scheme) return fail(c, GPM_ESTATE, "no scheme set");
+    if (!c->state) return fail(c, GPM_ESTATE, "not bound");
+    if (s < 0 || s > 2 || !Us || !order || !lam_out || !lam_Us || (s > 0 && (!Un || !lam_Un)) || !(dt > 0.0))
+        return fail(c, GPM_EINVAL, "bad adjoint arguments");
+    if (lam_Us == lam_out || (s > 0 && (lam_Un == lam_out || lam_Un == lam_Us)))
+        return fail(c, GPM_EINVAL, "adjoint outputs must not alias");
+    return c->prec == GPM_F64 ? stage_vjp<double>(c, c->w64, s, Un, Us, order, dt, lam_out, lam_Us, lam_Un, dL_dell)
+                              : stage_vjp<float>(c, c->w32, s, Un, Us, order, dt, lam_out, lam_Us, lam_Un, dL_dell);
 }
 
 gpm_status gpm_troubled_counts(gpm_ctx *c, long long counts[4], int *mood_iters)

@@ -295,6 +295,12 @@ gpm_status gpm_batch_set_scheme(gpm_batch *b, const gpm_scheme *s)
             c->w32 = d->w32;
             c->gtab64 = d->gtab64;
             c->gtab32 = d->gtab32;
+            // the ell-derivative part scales with 1 / ell
+            const double elld = d->scheme.ell;
+            for (int k = kGtabSize; k < 2 * kGtabSize; ++k) {
+                c->gtab64[k] = d->gtab64[k] * (elld / ell);
+                c->gtab32[k] = (float)c->gtab64[k];
+            }
             c->scheme = d->scheme;
             c->scheme.ell = ell;
             c->top = d->top;

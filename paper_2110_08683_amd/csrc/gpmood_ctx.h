@@ -84,7 +84,7 @@ static inline gpm_status upload_gtab(gpm_ctx *c)
 {
     if (!c->gtab || !c->have_scheme) return GPM_OK;
     const void *src = c->prec == GPM_F64 ? (const void *)c->gtab64.data() : (const void *)c->gtab32.data();
-    const size_t bytes = (size_t)kGtabSize * (c->prec == GPM_F64 ? 8 : 4);
+    const size_t bytes = (size_t)2 * kGtabSize * (c->prec == GPM_F64 ? 8 : 4);
     hipError_t e = hipMemcpyAsync(c->gtab, src, bytes, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("weight upload: ") + hipGetErrorString(e));
@@ -115,7 +115,7 @@ static inline size_t work_layout(const gpm_ctx *c, size_t off[W_N])
     const size_t esz = c->prec == GPM_F64 ? 8 : 4;
     const size_t sz[W_N] = {c->ncell, 4 * c->ncell, 4 * nf, 4 * nf, 4 * nf, 4 * c->ncell, 4 * c->ncell,
                             4 * esz * nfaces_x(c), 4 * esz * nfaces_y(c), nfaces_x(c), nfaces_y(c), sizeof(Ctl),
-                            (size_t)kTotBlocks * 4 * 2 * sizeof(double), (size_t)kGtabSize * esz};
+                            (size_t)kTotBlocks * 4 * 2 * sizeof(double), (size_t)2 * kGtabSize * esz};
     size_t o = 0;
     for (int k = 0; k < W_N; ++k) {
         off[k] = o;
@@ -156,6 +156,7 @@ static inline void fill_args(const gpm_ctx *c, const Weights<real> &W, StageArgs
     A.FXf = c->FXf;
     A.GYf = c->GYf;
     A.gtab = (const real *)c->gtab;
+    A.gtab_dl = (const real *)c->gtab + kGtabSize;
     A.cstamp = c->cstamp;
     A.fstamp = c->fstamp;
     for (int r = 0; r < 4; ++r) A.next[r] = c->next[r];

@@ -66,6 +66,7 @@ struct StageArgs {
     double dx64, dy64, gamma64;  // the same in FP64 (the dt reduction)
     Weights<real> W;
     const real *gtab;     // compact cascade weights, kGtabSize values (device)
+    const real *gtab_dl;  // their derivative with respect to ell (same layout, no Gauss weights)
 };
 
 // Outputs of one evaluation: the troubled count, and the faces and cells that the
@@ -235,6 +236,17 @@ __device__ __forceinline__ void states_dir(const real (&Q)[kNQ[R]], const Weight
     }
 }
 
+// Parity sums of the four mirror cells (+-a, +-b) of one variable, as in build_Q.
+template <typename real>
+__device__ __forceinline__ void parity4(real pp, real mp, real pm, real mm, real (&Q)[4])
+{
+    const real s1 = pp + mp, d1 = pp - mp, s2 = pm + mm, d2 = pm - mm;
+    Q[C_EE] = s1 + s2;
+    Q[C_OE] = d1 + d2;
+    Q[C_EO] = s1 - s2;
+    Q[C_OO] = d1 - d2;
+}
+
 // HLLC flux through a face normal to axis DIR.  badL / badR: the density or the
 // pressure of the left / right state is not finite (CAD on Riemann states).
 template <int DIR, typename real>
@@ -402,6 +414,20 @@ struct BatchTabs {
     const int *blk;
     const int *dblk;
     int nprob;
+};
+
+// Arguments of the stage adjoint: A carries U^n, U_s, the frozen final orders of
+// the forward stage (A.order), dt and the weights; lam_* are [4][ny][nx] in the
+// state precision; acc is an FP64 [4][ny][nx] accumulator; dl_partial holds one
+// dL/d(ell) partial per block of the face kernel.
+template <typename real>
+struct AdjArgs {
+    StageArgs<real> A;
+    const real *lam_out;
+    real *lam_Us;
+    real *lam_Un;
+    double *acc;
+    double *dl_partial;
 };
 
 struct LevIdx {

@@ -328,17 +328,6 @@ __device__ __forceinline__ void load_gtab(const real *gtab, real *wl)
     for (int k = threadIdx.x; k < kGtabSize; k += blockDim.x) wl[k] = gtab[k];
 }
 
-// Parity sums of the four mirror cells (+-a, +-b) of one variable, as in build_Q.
-template <typename real>
-__device__ __forceinline__ void parity4(real pp, real mp, real pm, real mm, real (&Q)[4])
-{
-    const real s1 = pp + mp, d1 = pp - mp, s2 = pm + mm, d2 = pm - mm;
-    Q[C_EE] = s1 + s2;
-    Q[C_OE] = d1 + d2;
-    Q[C_EO] = s1 - s2;
-    Q[C_OO] = d1 - d2;
-}
-
 // Cascade pass, part 1: recompute the listed faces at their EDP_1 order (the
 // smaller radius of the two cells), four lanes per face.  Lane v of a quad
 // gathers variable v of both cells' quarter positions (all loads issued at once),
