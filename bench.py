@@ -23,7 +23,8 @@ first two steps of the same 2048^2 problem, about 15-20 s of CPU work.
 A second leg times the batched ensemble (256 four-quadrant problems of sides 128
 to 1024, FP32, one HIP-graph replay per step) and the same work done one problem
 at a time; it is reported under "batched".  A third leg times a reverse-mode rollout
-(512^2 vortex + density bump, 200 steps, checkpoints every 20) under "adjoint".
+(512^2 vortex + density bump, 200 steps, checkpoints every 20) under "adjoint", and
+a fourth the 384^3 3D blast (GP-MOOD5, FP32) under "blast3d".
 
 Usage: python bench.py [--gpus 1] [--steps 500] [--warmup 20] [--batch-steps 10] [--no-cpu-baseline]
 """
@@ -242,6 +243,33 @@ def run_adjoint(steps, every):
             "loss": float(loss), "grad_rho0_norm": gn, "dL_dell": float(ell.grad)}
 
 
+def run_3d(steps, warmup, n=384):
+    """3D blast (GP-MOOD5, FP32 bulk, FP64 dt and totals): n^3 unit cube, outflow,
+    rho = 1 +- 1% (PCG64 seed 3), p = 1e-5, p = 1e4 within 3 dx of the centre, CFL 0.3."""
+    import torch
+
+    import gpmood_inputs as gi
+    from paper_2110_08683_amd import GPMood3D
+    g = GPMood3D((n, n, n), bc=(1, 1, 1), prec="f32", cascade=(2, 1, 0), device="cuda:0")
+    g.gpm3_init_state(gi.blast3d(n))
+    t0 = g.gpm3_totals()
+    g.gpm3_step(0.3, warmup)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g.gpm3_step(0.3, steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    counts, iters = g.gpm3_troubled_counts()
+    tot = g.gpm3_totals()
+    g.close()
+    return {"value": n ** 3 * 3 * steps / el, "unit": "cell-updates/s", "cells": n ** 3, "steps": steps,
+            "warmup": warmup, "ms_per_step": 1e3 * el / steps, "mood_iters_last_stage": iters,
+            "final_order_fraction_last_stage": [float(x) / n ** 3 for x in counts],
+            "mass_drift": float(abs(tot[0] - t0[0]) / t0[0]),
+            "workload": f"3D blast {n}^3, outflow, rho 1 +- 1% (seed 3), p 1e-5 / 1e4 within 3 dx, "
+                        "GP-MOOD5 5-3-1, FP32, CFL 0.3"}
+
+
 def cpu_baseline(U0):
     import oracle
     o = oracle.Oracle(N, N, bc=(1, 1), cascade=CASCADE)
@@ -266,6 +294,7 @@ def main():
                     help="steps of the batched-ensemble leg (0 skips it)")
     ap.add_argument("--adjoint-steps", type=int, default=200,
                     help="steps of the reverse-mode leg (0 skips it)")
+    ap.add_argument("--steps-3d", type=int, default=5, help="steps of the 3D blast leg (0 skips it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB device copy (calibrates HBM byte counters)")
     a = ap.parse_args()
@@ -319,6 +348,10 @@ def main():
         print(f"[bench] batched ensemble {a.batch_steps} steps", file=sys.stderr, flush=True)
         line["batched"] = run_batch(a.batch_steps, 2)
         print(f"[bench] batched done: {line['batched']['value']:.3e} cell-updates/s", file=sys.stderr, flush=True)
+    if a.steps_3d > 0:
+        print(f"[bench] 3d blast {a.steps_3d} steps", file=sys.stderr, flush=True)
+        line["blast3d"] = run_3d(a.steps_3d, 1)
+        print(f"[bench] 3d done: {line['blast3d']['value']:.3e} cell-updates/s", file=sys.stderr, flush=True)
     if a.adjoint_steps > 0:
         print(f"[bench] adjoint rollout {a.adjoint_steps} steps", file=sys.stderr, flush=True)
         line["adjoint"] = run_adjoint(a.adjoint_steps, 20)

@@ -85,8 +85,9 @@ typedef struct {
 
 /* Create a context for a grid, a precision and a HIP stream (hipStream_t, may be
    NULL).  Allocates host memory only.  Errors: GPM_EINVAL (bad grid, gamma <= 1,
-   n < 1 or > 32768 per axis), GPM_EUNSUPPORTED (dim != 2, or a periodic axis
-   with fewer than 4 cells: the radius-3 stencil reaches 4 cells past a face). */
+   n < 1 or > 32768 per axis), GPM_EUNSUPPORTED (dim != 2 (3D: gpm3_create), or
+   a periodic axis with fewer than 4 cells: the radius-3 stencil reaches 4 cells
+   past a face). */
 gpm_status gpm_create(const gpm_grid *grid, int prec, void *hip_stream, gpm_ctx **out);
 
 /* Set the cascade, ell, CSD thresholds and flags.  Builds the GP prediction
@@ -271,6 +272,36 @@ gpm_status gpm_batch_get_order_mask(gpm_batch *b, int p, unsigned char *mask_hos
 
 const char *gpm_batch_last_error(const gpm_batch *b);
 void gpm_batch_destroy(gpm_batch *b);
+
+/* ---------------------------------------------------------------------------
+   3D stage (five variables rho, rho u, rho v, rho w, E; SoA [5][nz][ny][nx]).
+   The 3D form of the method: GP stencil of radius R <= 2 on the L1 ball
+   (|di|+|dj|+|dk| <= R: 7 / 25 cells), q x q tensor Gauss nodes per face (q = R+1),
+   EDP_1 face orders, HLLC with two tangential momenta, detection over the six
+   face neighbours (DMP eq. (DMP_RK), plateau eq. (plateau), CSD eqs. (divV),
+   (gradP) with the z terms, u2 eqs. (u2_a), (u2_b) per direction with GP-R1
+   second derivatives), SSP-RK3 eq. (rk3), FP64 dt = CFL min Delta_d/(|u_d|+c).
+   The calls mirror the 2D ones; grid.dim must be 3, n <= 4096 per axis,
+   periodic axes need >= 3 cells, cascades use radii 2, 1, 0 (GP-MOOD5 = {2,1,0}).
+   Not thread-safe per context. */
+typedef struct gpm3_ctx gpm3_ctx;
+gpm_status gpm3_create(const gpm_grid *grid, int prec, void *hip_stream, gpm3_ctx **out);
+gpm_status gpm3_set_scheme(gpm3_ctx *ctx, const gpm_scheme *scheme);
+gpm_status gpm3_workspace_size(const gpm3_ctx *ctx, size_t *state_bytes, size_t *work_bytes);
+gpm_status gpm3_bind(gpm3_ctx *ctx, void *state, void *work);
+gpm_status gpm3_init_state(gpm3_ctx *ctx, const double *U_host);
+gpm_status gpm3_get_state(gpm3_ctx *ctx, double *U_host);
+/* dt from the current state (synchronising if dt_host != NULL). */
+gpm_status gpm3_compute_dt(gpm3_ctx *ctx, double cfl, double *dt_host);
+/* nsteps SSP-RK3 steps, each with its own CFL dt (cfl > 0). */
+gpm_status gpm3_step(gpm3_ctx *ctx, double cfl, int nsteps);
+/* Final-order counts per cascade level and evaluations of the last stage. */
+gpm_status gpm3_troubled_counts(gpm3_ctx *ctx, long long counts[3], int *mood_iters);
+gpm_status gpm3_get_order_mask(gpm3_ctx *ctx, unsigned char *mask_host);
+/* Compensated FP64 totals of the five variables times the cell volume. */
+gpm_status gpm3_totals(gpm3_ctx *ctx, double totals[5]);
+const char *gpm3_last_error(const gpm3_ctx *ctx);
+void gpm3_destroy(gpm3_ctx *ctx);
 
 const char *gpm_strerror(gpm_status st);
 const char *gpm_last_error(const gpm_ctx *ctx);

@@ -30,7 +30,10 @@ EXPORTS = ("gpm_create", "gpm_set_scheme", "gpm_workspace_size", "gpm_bind", "gp
            "gpm_batch_set_scheme", "gpm_batch_workspace_size", "gpm_batch_bind", "gpm_batch_set_tuning",
            "gpm_batch_init_state", "gpm_batch_get_state", "gpm_batch_step", "gpm_batch_status",
            "gpm_batch_troubled_counts", "gpm_batch_get_order_mask", "gpm_batch_last_error",
-           "gpm_batch_destroy", "gpm_strerror", "gpm_last_error", "gpm_destroy")
+           "gpm_batch_destroy", "gpm3_create", "gpm3_set_scheme", "gpm3_workspace_size", "gpm3_bind",
+           "gpm3_init_state", "gpm3_get_state", "gpm3_compute_dt", "gpm3_step", "gpm3_troubled_counts",
+           "gpm3_get_order_mask", "gpm3_totals", "gpm3_last_error", "gpm3_destroy",
+           "gpm_strerror", "gpm_last_error", "gpm_destroy")
 
 
 class gpm_grid(ctypes.Structure):
@@ -98,6 +101,19 @@ def lib():
         "gpm_batch_get_order_mask": ([ctxp, ctypes.c_int, ctypes.POINTER(ctypes.c_ubyte)], st),
         "gpm_batch_last_error": ([ctxp], ctypes.c_char_p),
         "gpm_batch_destroy": ([ctxp], None),
+        "gpm3_create": ([ctypes.POINTER(gpm_grid), ctypes.c_int, vp, ctypes.POINTER(ctxp)], st),
+        "gpm3_set_scheme": ([ctxp, ctypes.POINTER(gpm_scheme)], st),
+        "gpm3_workspace_size": ([ctxp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)], st),
+        "gpm3_bind": ([ctxp, vp, vp], st),
+        "gpm3_init_state": ([ctxp, dp], st),
+        "gpm3_get_state": ([ctxp, dp], st),
+        "gpm3_compute_dt": ([ctxp, ctypes.c_double, dp], st),
+        "gpm3_step": ([ctxp, ctypes.c_double, ctypes.c_int], st),
+        "gpm3_troubled_counts": ([ctxp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_int)], st),
+        "gpm3_get_order_mask": ([ctxp, ctypes.POINTER(ctypes.c_ubyte)], st),
+        "gpm3_totals": ([ctxp, dp], st),
+        "gpm3_last_error": ([ctxp], ctypes.c_char_p),
+        "gpm3_destroy": ([ctxp], None),
         "gpm_strerror": ([st], ctypes.c_char_p),
         "gpm_last_error": ([ctxp], ctypes.c_char_p),
         "gpm_destroy": ([ctxp], None),
@@ -385,3 +401,98 @@ class GPMoodBatch:
         m = np.empty((ny, nx), dtype=np.uint8)
         self._check(lib().gpm_batch_get_order_mask(self.b, int(p), m.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))))
         return m
+
+
+class GPMood3D:
+    """One 3D problem (GP-MOOD5 and lower) on the GPU: torch buffers and a gpm3 context.
+
+    n = (nx, ny, nz); lo, hi, bc per axis (0 periodic / 1 outflow); state arrays are
+    float64 host arrays (5, nz, ny, nx).
+    """
+
+    def __init__(self, n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(1, 1, 1), prec="f32", cascade=(2, 1, 0),
+                 ell=None, gamma=1.4, sigma_v=5.0, sigma_p=5.0, flags=GPM_FLAGS_ALL, stream=None, device=None):
+        import torch
+        L = lib()
+        self.device = torch.device(device if device is not None else "cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.n = tuple(int(x) for x in n)
+        self.prec = prec
+        g = gpm_grid()
+        g.dim = 3
+        for a in range(3):
+            g.n[a], g.lo[a], g.hi[a], g.bc[a] = self.n[a], lo[a], hi[a], bc[a]
+        g.gamma = gamma
+        ctx = ctypes.c_void_p()
+        st = L.gpm3_create(ctypes.byref(g), GPM_F64 if prec == "f64" else GPM_F32,
+                           ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+        if st != GPM_OK:
+            raise GpmError(f"status {st}: {L.gpm_strerror(st).decode()}")
+        self.ctx = ctx
+        s = gpm_scheme()
+        s.nlev = len(cascade)
+        for k, r in enumerate(cascade):
+            s.radius[k] = r
+        s.ell = 0.0 if ell is None else float(ell)
+        s.sigma_v, s.sigma_p, s.flags = sigma_v, sigma_p, flags
+        self._check(L.gpm3_set_scheme(self.ctx, ctypes.byref(s)))
+        sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(L.gpm3_workspace_size(self.ctx, ctypes.byref(sb), ctypes.byref(wb)))
+        self.state_buf = torch.empty(sb.value, dtype=torch.uint8, device=self.device)
+        self.work_buf = torch.empty(wb.value, dtype=torch.uint8, device=self.device)
+        self._check(L.gpm3_bind(self.ctx, ctypes.c_void_p(self.state_buf.data_ptr()),
+                                ctypes.c_void_p(self.work_buf.data_ptr())))
+
+    def _check(self, st):
+        if st != GPM_OK:
+            L = lib()
+            raise GpmError(f"status {st}: {L.gpm_strerror(st).decode()}: "
+                           f"{(L.gpm3_last_error(self.ctx) or b'').decode()}")
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            lib().gpm3_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _shape(self):
+        return (5, self.n[2], self.n[1], self.n[0])
+
+    def gpm3_init_state(self, U):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        assert U.shape == self._shape()
+        self._check(lib().gpm3_init_state(self.ctx, _dp(U)))
+
+    def gpm3_get_state(self):
+        U = np.empty(self._shape())
+        self._check(lib().gpm3_get_state(self.ctx, _dp(U)))
+        return U
+
+    def gpm3_compute_dt(self, cfl):
+        dt = ctypes.c_double()
+        self._check(lib().gpm3_compute_dt(self.ctx, float(cfl), ctypes.byref(dt)))
+        return dt.value
+
+    def gpm3_step(self, cfl=0.3, nsteps=1):
+        self._check(lib().gpm3_step(self.ctx, float(cfl), int(nsteps)))
+
+    def gpm3_troubled_counts(self):
+        c = (ctypes.c_longlong * 3)()
+        it = ctypes.c_int()
+        self._check(lib().gpm3_troubled_counts(self.ctx, c, ctypes.byref(it)))
+        return np.array(list(c), dtype=np.int64), it.value
+
+    def gpm3_get_order_mask(self):
+        m = np.empty(self._shape()[1:], dtype=np.uint8)
+        self._check(lib().gpm3_get_order_mask(self.ctx, m.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))))
+        return m
+
+    def gpm3_totals(self):
+        t = np.zeros(5)
+        self._check(lib().gpm3_totals(self.ctx, _dp(t)))
+        return t

@@ -233,4 +233,109 @@ int gpw_curvature(double ax_d, double ay_d, double ell_d, GpwCurv *out)
     return 0;
 }
 
+// ---------------------------------------------------------------- 3D
+namespace {
+
+void ball_cov(int n, const qf a[3], std::vector<qf> &L)
+{
+    L.assign((size_t)n * n, 0);
+    for (int m = 0; m < n; ++m)
+        for (int k = 0; k < n; ++k) {
+            qf v = 1;
+            for (int d = 0; d < 3; ++d) v *= c_factor((qf)(kBall[k][d] - kBall[m][d]), a[d]);
+            L[(size_t)m * n + k] = v;
+        }
+}
+
+}  // namespace
+
+int gpw3_level(int R, double ax_d, double ay_d, double az_d, Gpw3Level *out)
+{
+    std::memset(out, 0, sizeof(*out));
+    out->R = R;
+    if (R < 1 || R > 2) return -1;
+    const qf a[3] = {ax_d, ay_d, az_d};
+    const int n = kNBall[R];
+    std::vector<qf> L;
+    ball_cov(n, a, L);
+    if (!cholesky(L, n)) return -1;
+    // 1D Gauss rule on [-1/2, 1/2] with q = R + 1 nodes, from the 2D slots
+    qf g2[2], w2[2], g[3], w[3];
+    gauss_slots(R, g2, w2);
+    int q;
+    if (R == 1) {
+        q = 2;
+        g[0] = g2[0]; g[1] = -g2[0];
+        w[0] = w2[0]; w[1] = w2[0];
+    } else {
+        q = 3;
+        g[0] = g2[0]; g[1] = 0; g[2] = -g2[0];
+        w[0] = w2[0]; w[1] = w2[1]; w[2] = w2[0];
+    }
+    out->nq = q * q;
+    for (int f = 0; f < 6; ++f) {
+        const int ax = f / 2;
+        const qf side = (f & 1) ? (qf)0.5 : (qf)-0.5;
+        const int t1 = ax == 0 ? 1 : 0, t2 = ax == 2 ? 1 : 2;
+        for (int i1 = 0; i1 < q; ++i1)
+            for (int i2 = 0; i2 < q; ++i2) {
+                qf x[3];
+                x[ax] = side;
+                x[t1] = g[i1];
+                x[t2] = g[i2];
+                std::vector<qf> z(n);
+                for (int m = 0; m < n; ++m) {
+                    qf v = 1;
+                    for (int d = 0; d < 3; ++d) v *= t_factor(x[d] - kBall[m][d], a[d]);
+                    z[m] = v;
+                }
+                chol_solve(L, n, z);
+                qf sum = 0;
+                for (int m = 0; m < n; ++m) sum += z[m];
+                const int k = i1 * q + i2;
+                for (int m = 0; m < n; ++m) {
+                    out->z64[f][k][m] = (double)(z[m] / sum);
+                    out->z32[f][k][m] = (float)(z[m] / sum);
+                }
+                out->qw64[k] = (double)(w[i1] * w[i2]);
+                out->qw32[k] = (float)(w[i1] * w[i2]);
+            }
+    }
+    return 0;
+}
+
+int gpw3_curvature(double ax_d, double ay_d, double az_d, double ell_d, Gpw3Curv *out)
+{
+    std::memset(out, 0, sizeof(*out));
+    const qf a[3] = {ax_d, ay_d, az_d}, ell = ell_d;
+    const int n = kNBall[1];
+    std::vector<qf> L;
+    ball_cov(n, a, L);
+    if (!cholesky(L, n)) return -1;
+    for (int d = 0; d < 3; ++d) {
+        std::vector<qf> w(n);
+        for (int m = 0; m < n; ++m) {
+            qf v = 1;
+            for (int e = 0; e < 3; ++e) {
+                const qf s = -(qf)kBall[m][e];  // x* = cell centre
+                v *= e == d ? d2_t_factor(s, a[e], ell) : t_factor(s, a[e]);
+            }
+            w[m] = v;
+        }
+        chol_solve(L, n, w);
+        // kBall ring 1: (-x, +x, -y, +y, -z, +z) at entries 1..6
+        qf v[4];
+        v[0] = w[0];
+        v[1] = (w[1 + 2 * d] + w[2 + 2 * d]) / 2;
+        int k = 2;
+        for (int e = 0; e < 3; ++e)
+            if (e != d) v[k++] = (w[1 + 2 * e] + w[2 + 2 * e]) / 2;
+        for (int j = 0; j < 4; ++j) {
+            out->w64[d][j] = (double)v[j];
+            out->w32[d][j] = (float)v[j];
+        }
+    }
+    return 0;
+}
+
 }  // namespace gpm

@@ -25,10 +25,33 @@ struct GpwCurv {
     float w32[2][3];
 };
 
+// 3D weights of radius R (1 or 2) on the L1-ball stencil (kBall order): for each
+// face f (x-, x+, y-, y+, z-, z+) and node k (q x q tensor nodes, q = R + 1, first
+// tangential axis outer) the normalised prediction vector over the stencil, and
+// the node weights.
+struct Gpw3Level {
+    int R;
+    int nq;  // nodes per face
+    double z64[6][9][25];
+    float z32[6][9][25];
+    double qw64[9];
+    float qw32[9];
+};
+
+// 3D u2 curvature weights per direction d on the R = 1 ball: [0] centre, [1] the
+// two neighbours along d, [2] and [3] the two neighbours along each other axis
+// (in x, y, z order).
+struct Gpw3Curv {
+    double w64[3][4];
+    float w32[3][4];
+};
+
 // ax = ell/dx, ay = ell/dy.  Returns 0, or -1 if the covariance matrix is not
 // numerically positive definite in quad precision.
 int gpw_level(int R, double ax, double ay, GpwLevel *out);
 int gpw_curvature(double ax, double ay, double ell, GpwCurv *out);
+int gpw3_level(int R, double ax, double ay, double az, Gpw3Level *out);
+int gpw3_curvature(double ax, double ay, double az, double ell, Gpw3Curv *out);
 
 }  // namespace gpm
 

@@ -65,6 +65,20 @@ constexpr int kGtabPerDir = 2 * kNPos * 4;
 constexpr int kGtabNodeOff = 4 * 2 * kGtabPerDir;
 constexpr int kGtabSize = kGtabNodeOff + 4 * 2;
 
+// 3D (GP-MOOD5 and lower): the stencil of radius R is the L1 ball |di|+|dj|+|dk|
+// <= R, listed ring by ring so that radius 1 (7 cells) is a prefix of radius 2
+// (25 cells).  A face carries q x q tensor Gauss nodes (q = R + 1), the first
+// tangential axis (in x, y, z order) outer.
+constexpr int kBall[25][3] = {
+    {0, 0, 0},
+    {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1},
+    {-2, 0, 0}, {2, 0, 0}, {0, -2, 0}, {0, 2, 0}, {0, 0, -2}, {0, 0, 2},
+    {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 1, 0},
+    {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1}, {1, 0, 1},
+    {0, -1, -1}, {0, 1, -1}, {0, -1, 1}, {0, 1, 1},
+};
+constexpr int kNBall[3] = {1, 7, 25};
+
 }  // namespace gpm
 
 #endif
