@@ -251,7 +251,7 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     us[v] = ring[slot][v][lane + 3];
-                    ust[v] = us[v] - dt * (dFxP[v] / A.dx + (G[v] - Gprev[v]) / A.dy);
+                    ust[v] = us[v] - dt * (dv(dFxP[v], A.dx) + dv(G[v] - Gprev[v], A.dy));
                 }
                 const bool rs = rsxP || rsymP || badLy;
                 auto nb = [&](int di, int dj, int v) { return ring[(jr + dj) & 7][v][lane + 3 + di]; };
@@ -285,7 +285,7 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
 }
 
 template <typename real, int RT, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_first_pass(const StageArgs<real> A, const PassOut P)
+__global__ __launch_bounds__(64 * WPB, sizeof(real) == 4 ? 2 : 1) void k_first_pass(const StageArgs<real> A, const PassOut P)
 {
     __shared__ real ring_all[WPB][8][4][LW];
     const int wv = threadIdx.x >> 6;
@@ -552,7 +552,7 @@ __device__ __forceinline__ void cells_phase(const StageArgs<real> &A, const int 
             for (int w = 0; w < 4; ++w) {
                 const real us = w == 0 ? rho[0] : mom[0][w - 1];
                 const real dFx = fx[w][1] - fx[w][0];
-                ust[w] = us - dt * (dFx / A.dx + (gy[w][1] - gy[w][0]) / A.dy);
+                ust[w] = us - dt * (dv(dFx, A.dx) + dv(gy[w][1] - gy[w][0], A.dy));
             }
             auto nb = [&](int di, int dj, int w) -> real {
                 int m = 0;
