@@ -94,7 +94,7 @@ __device__ __forceinline__ void hllc3(real g, int a, const real (&UL)[5], const 
     const real pr = (g - real(1)) * (Er - real(0.5) * rr * (ur * ur + vr * vr + wr * wr));
     badL = !(finite(rl) && finite(pl));
     badR = !(finite(rr) && finite(pr));
-    const real cl = sqrt(g * pl * irl), cr = sqrt(g * pr * irr);
+    const real cl = sq(g * pl * irl), cr = sq(g * pr * irr);
     const real SL = vmin(ul - cl, ur - cr);
     const real SR = vmax(ul + cl, ur + cr);
     const real Ss = (pr - pl + rl * ul * (SL - ul) - rr * ur * (SR - ur)) / (rl * (SL - ul) - rr * (SR - ur));

@@ -55,6 +55,7 @@ struct gpm_batch {
     int *st_iters = nullptr;    // [nprob]
     double *st_dt = nullptr;    // [nprob]
     int nfp = 0, ndt = 0;
+    int iso = 0;                // every problem has isotropic weights
     // graphs: one captured SSP-RK3 step per rotation
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
@@ -169,6 +170,8 @@ static gpm_status build_tables(gpm_batch *b)
         blk[p + 1] = blk[p] + fp_blocks(c, b->rows);
         dblk[p + 1] = dblk[p] + dt_blocks(c);
     }
+    b->iso = 1;
+    for (size_t k = 0; k < args.size(); ++k) b->iso &= args[k].iso;
     b->nfp = blk[P];
     b->ndt = dblk[P];
     const BatchLayout L = batch_layout(b);
@@ -202,6 +205,7 @@ static BatchTabs<real> tabs(const gpm_batch *b, int rot, int s)
     B.blk = b->blk;
     B.dblk = b->dblk;
     B.nprob = b->nprob;
+    B.iso = b->iso;
     return B;
 }
 

@@ -126,6 +126,25 @@ static inline size_t work_layout(const gpm_ctx *c, size_t off[W_N])
 
 static inline void *slot_ptr(gpm_ctx *c, int slot) { return c->state + slot * state_slot_bytes(c); }
 
+// Are the y-face weights of radius <= top bit for bit the x-face weights of the
+// transposed parity entries (equal spacing and length scale in x and y)?  The
+// first pass then reads one table for both directions, with identical products.
+template <typename real>
+static inline int weights_isotropic(const Weights<real> &W, int top)
+{
+    for (int R = 1; R <= top; ++R)
+        for (int p = 0; p < slots_of(R); ++p)
+            for (int e = 0; e < kNQ[R]; ++e) {
+                // the centre node of R = 2 does not use its odd-along-the-face entries
+                if (slot_is_zero(R, p) && (kQ[e].comp == C_OE || kQ[e].comp == C_OO)) continue;
+                const int t = transposed_entry(e);
+                const real wy = R == 3 ? W.w3[1][p][e] : (R == 2 ? W.w2[1][p][e] : W.w1[1][p][e]);
+                const real wx = R == 3 ? W.w3[0][p][t] : (R == 2 ? W.w2[0][p][t] : W.w1[0][p][t]);
+                if (std::memcmp(&wx, &wy, sizeof(real)) != 0) return 0;
+            }
+    return 1;
+}
+
 template <typename real>
 static inline void fill_args(const gpm_ctx *c, const Weights<real> &W, StageArgs<real> &A)
 {
@@ -135,6 +154,7 @@ static inline void fill_args(const gpm_ctx *c, const Weights<real> &W, StageArgs
     A.bcy = c->grid.bc[1];
     A.rows = c->rows;
     A.top = c->top;
+    A.iso = weights_isotropic(W, c->top);
     A.flags = c->scheme.flags;
     A.dx = (real)c->dx;
     A.dy = (real)c->dy;

@@ -60,6 +60,7 @@ struct StageArgs {
     int s;                // RK stage 0..2
     int rows;             // rows per wavefront march (first pass)
     int top;              // top radius
+    int iso;              // 1: the y weights are exactly the transposed x weights
     unsigned flags;
     int next[4];          // next radius of the cascade after radius r
     real dx, dy, gamma, sigma_v, sigma_p, plat_thr, delta;
@@ -142,6 +143,13 @@ __device__ __forceinline__ real dv(real a, real b) { return a / b; }
 template <>
 __device__ __forceinline__ float dv<float>(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
+// Square root likewise: correctly rounded in FP64, the hardware v_sqrt_f32 (1 ulp)
+// in FP32 instead of the compiler's ~12-instruction correctly rounded sequence.
+template <typename real>
+__device__ __forceinline__ real sq(real a) { return sqrt(a); }
+template <>
+__device__ __forceinline__ float sq<float>(float a) { return __builtin_amdgcn_sqrtf(a); }
+
 template <typename real>
 __device__ __forceinline__ real vmin(real a, real b) { return a < b ? a : b; }
 template <typename real>
@@ -171,6 +179,11 @@ __device__ __forceinline__ real node_weight(const Weights<real> &W, int k)
     else if constexpr (R == 1) return W.qw1;
     else return real(1);
 }
+
+// Pointer into the constant address space (kernel arguments, tables read as such):
+// loads through it are scalar and cached in the scalar cache.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
 
 template <int R, typename real>
 __device__ __forceinline__ real wq(const Weights<real> &W, int dir, int slot, int e)
@@ -210,9 +223,21 @@ __device__ __forceinline__ void build_Q(real (&Q)[kNQ[R]], Load ld)
     }
 }
 
+// Index of the transposed entry (b, a) of kQ entry e, with OE and EO exchanged.
+constexpr int transposed_entry(int e)
+{
+    const int c = kQ[e].comp == C_OE ? C_EO : (kQ[e].comp == C_EO ? C_OE : kQ[e].comp);
+    for (int k = 0; k < 25; ++k)
+        if (kQ[k].a == kQ[e].b && kQ[k].b == kQ[e].a && kQ[k].comp == c) return k;
+    return -1;
+}
+
 // The 2q face states of one variable for direction DIR (0: x faces, 1: y faces):
-// sm[k] on the - face, sp[k] on the + face, node k in table order.
-template <int R, int DIR, typename real>
+// sm[k] on the - face, sp[k] on the + face, node k in table order.  ISO: the grid
+// is isotropic (equal spacing and length scale, so the y weights are exactly the
+// transposed x weights) and the y states read the x table; the products and their
+// order are unchanged.
+template <int R, int DIR, bool ISO = false, typename real>
 __device__ __forceinline__ void states_dir(const real (&Q)[kNQ[R]], const Weights<real> &W,
                                            real (&sm)[nodes_of(R)], real (&sp)[nodes_of(R)])
 {
@@ -227,7 +252,8 @@ __device__ __forceinline__ void states_dir(const real (&Q)[kNQ[R]], const Weight
         for (int e = 0; e < kNQ[R]; ++e) {
             const int c = kQ[e].comp;
             if (zero && (c == cN || c == C_OO)) continue;
-            P[c] = fma(wq<R>(W, DIR, p, e), Q[e], P[c]);
+            const real w = (ISO && DIR == 1) ? wq<R>(W, 0, p, transposed_entry(e)) : wq<R>(W, DIR, p, e);
+            P[c] = fma(w, Q[e], P[c]);
         }
         const real A = P[C_EE] + P[cF];
         const real Bm = P[C_EE] - P[cF];
@@ -268,7 +294,7 @@ __device__ __forceinline__ void hllc(real g, const real *UL, const real *UR, rea
     const real pr = (g - real(1)) * (Er - real(0.5) * rr * (ur * ur + vr * vr));
     badL = !(finite(rl) && finite(pl));
     badR = !(finite(rr) && finite(pr));
-    const real cl = sqrt(g * pl * irl), cr = sqrt(g * pr * irr);
+    const real cl = sq(g * pl * irl), cr = sq(g * pr * irr);
     const real SL = vmin(ul - cl, ur - cr);
     const real SR = vmax(ul + cl, ur + cr);
     const real Ss = dv(pr - pl + rl * ul * (SL - ul) - rr * ur * (SR - ur), rl * (SL - ul) - rr * (SR - ur));
@@ -423,6 +449,7 @@ struct BatchTabs {
     const int *blk;
     const int *dblk;
     int nprob;
+    int iso;  // every problem's A.iso is 1
 };
 
 // Arguments of the stage adjoint: A carries U^n, U_s, the frozen final orders of

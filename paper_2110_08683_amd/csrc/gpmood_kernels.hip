@@ -110,8 +110,8 @@ __device__ __forceinline__ void claim_after_lowering(const StageArgs<real> &A, c
 }
 
 // One wavefront's strip (tile wid of the problem) of the first pass; ring is the
-// wavefront's LDS ring.
-template <typename real, int RT>
+// wavefront's LDS ring.  ISO: A.iso is 1 (the y states read the x weights).
+template <typename real, int RT, bool ISO>
 __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const PassOut &P, int wid,
                                                 real (*ring)[4][LW])
 {
@@ -180,12 +180,11 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
             real Q[NQ];
             build_Q<RT>(Q, [&](int di, int dj) { return ring[(j + dj) & 7][v][lane + 3 + di]; });
             real m_[q], p_[q];
-            if (doX) {
-                states_dir<RT, 0>(Q, A.W, m_, p_);
+            // x states also on the two rows that do not use them: no branch here
+            states_dir<RT, 0, ISO>(Q, A.W, m_, p_);
 #pragma unroll
-                for (int k = 0; k < q; ++k) { sxm[k][v] = m_[k]; sxp[k][v] = p_[k]; }
-            }
-            states_dir<RT, 1>(Q, A.W, m_, p_);
+            for (int k = 0; k < q; ++k) { sxm[k][v] = m_[k]; sxp[k][v] = p_[k]; }
+            states_dir<RT, 1, ISO>(Q, A.W, m_, p_);
 #pragma unroll
             for (int k = 0; k < q; ++k) { sym[k][v] = m_[k]; syp[k][v] = p_[k]; }
         }
@@ -284,14 +283,14 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
     }
 }
 
-template <typename real, int RT, int WPB>
+template <typename real, int RT, int WPB, bool ISO>
 __global__ __launch_bounds__(64 * WPB, sizeof(real) == 4 ? 2 : 1) void k_first_pass(const StageArgs<real> A, const PassOut P)
 {
     __shared__ real ring_all[WPB][8][4][LW];
     const int wv = threadIdx.x >> 6;
     PassOut Q = P;
     Q.stamp = *A.stamp0;
-    first_pass_wave<real, RT>(A, Q, xcd_tile(blockIdx.x, gridDim.x) * WPB + wv, ring_all[wv]);
+    first_pass_wave<real, RT, ISO>(A, Q, xcd_tile(blockIdx.x, gridDim.x) * WPB + wv, ring_all[wv]);
 }
 
 // ------------------------------------------------------------- cascade pass
@@ -890,9 +889,6 @@ __global__ void k_totals_final(const double *partial, int nblk, double area, Ctl
 // per-problem dt in three small launches.  The per-problem arguments live in
 // device tables written once; they are read through the constant address space
 // (scalar loads: the tables do not change while the kernels run).
-template <typename T>
-using cptr = const __attribute__((address_space(4))) T *;
-
 // Generic reference to entry p of a device table, loaded as constant memory.
 template <typename T>
 __device__ __forceinline__ const T &table_entry(const T *tab, int p)
@@ -911,8 +907,8 @@ __device__ __forceinline__ int find_problem(cptr<int> prefix, int n, int b)
     return lo;
 }
 
-template <typename real, int RT, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_first_pass_batch(const BatchTabs<real> B)
+template <typename real, int RT, int WPB, bool ISO>
+__global__ __launch_bounds__(64 * WPB, sizeof(real) == 4 ? 2 : 1) void k_first_pass_batch(const BatchTabs<real> B)
 {
     __shared__ real ring_all[WPB][8][4][LW];
     cptr<int> blk = (cptr<int>)B.blk;
@@ -921,7 +917,7 @@ __global__ __launch_bounds__(64 * WPB) void k_first_pass_batch(const BatchTabs<r
     PassOut Q = table_entry(B.pout, p);
     Q.stamp = *A.stamp0;
     const int wv = threadIdx.x >> 6;
-    first_pass_wave<real, RT>(A, Q, (blockIdx.x - blk[p]) * WPB + wv, ring_all[wv]);
+    first_pass_wave<real, RT, ISO>(A, Q, (blockIdx.x - blk[p]) * WPB + wv, ring_all[wv]);
 }
 
 // Problem p = blockIdx.x runs its whole cascade (no hand-back).
@@ -1006,10 +1002,14 @@ hipError_t launch_batch_stage(const BatchTabs<real> &B, int top, int nfp_blocks,
     constexpr int WPB = sizeof(real) == 8 ? 2 : 4;
     const int nb = (B.nprob + 255) / 256;
     hipLaunchKernelGGL(k_reset_batch, dim3(nb), dim3(256), 0, st, casc, B.nprob);
-    switch (top) {
-    case 3: hipLaunchKernelGGL((k_first_pass_batch<real, 3, WPB>), dim3(nfp_blocks), dim3(64 * WPB), 0, st, B); break;
-    case 2: hipLaunchKernelGGL((k_first_pass_batch<real, 2, WPB>), dim3(nfp_blocks), dim3(64 * WPB), 0, st, B); break;
-    case 1: hipLaunchKernelGGL((k_first_pass_batch<real, 1, WPB>), dim3(nfp_blocks), dim3(64 * WPB), 0, st, B); break;
+    const dim3 g(nfp_blocks), t(64 * WPB);
+    switch (top * 2 + (B.iso ? 1 : 0)) {
+    case 7: hipLaunchKernelGGL((k_first_pass_batch<real, 3, WPB, true>), g, t, 0, st, B); break;
+    case 6: hipLaunchKernelGGL((k_first_pass_batch<real, 3, WPB, false>), g, t, 0, st, B); break;
+    case 5: hipLaunchKernelGGL((k_first_pass_batch<real, 2, WPB, true>), g, t, 0, st, B); break;
+    case 4: hipLaunchKernelGGL((k_first_pass_batch<real, 2, WPB, false>), g, t, 0, st, B); break;
+    case 3: hipLaunchKernelGGL((k_first_pass_batch<real, 1, WPB, true>), g, t, 0, st, B); break;
+    case 2: hipLaunchKernelGGL((k_first_pass_batch<real, 1, WPB, false>), g, t, 0, st, B); break;
     default: return hipErrorInvalidValue;
     }
     hipLaunchKernelGGL(k_tail_batch<real>, dim3(B.nprob), dim3(kTailThreads), 0, st, B);
@@ -1045,7 +1045,8 @@ static hipError_t launch_first_pass_rt(const StageArgs<real> &A, const PassOut &
     const int nstrip = (A.nx + 61) / 62, nseg = (A.ny + A.rows - 1) / A.rows;
     const int nwave = nstrip * nseg;
     const int nblk = (nwave + WPB - 1) / WPB;
-    hipLaunchKernelGGL((k_first_pass<real, RT, WPB>), dim3(nblk), dim3(64 * WPB), 0, st, A, P);
+    if (A.iso) hipLaunchKernelGGL((k_first_pass<real, RT, WPB, true>), dim3(nblk), dim3(64 * WPB), 0, st, A, P);
+    else hipLaunchKernelGGL((k_first_pass<real, RT, WPB, false>), dim3(nblk), dim3(64 * WPB), 0, st, A, P);
     return hipGetLastError();
 }
 

@@ -87,20 +87,23 @@ def _replay_stage(torch_cuda, g, o, s, Un, Us, dt):
     return Ug, mask, counts, iters, Uo, order, ocounts, oiters
 
 
-@pytest.mark.parametrize("n,seed,bc,cascade", [
-    (96, 1, (1, 1), (3, 2, 1, 0)),
-    (75, 2, (0, 0), (3, 2, 1, 0)),
-    (64, 3, (1, 0), (3, 1, 0)),
-    (70, 4, (1, 1), (2, 1, 0)),
-    (66, 5, (0, 1), (1, 0)),
+@pytest.mark.parametrize("nx,ny,seed,bc,cascade", [
+    (96, 96, 1, (1, 1), (3, 2, 1, 0)),
+    (75, 75, 2, (0, 0), (3, 2, 1, 0)),
+    (64, 64, 3, (1, 0), (3, 1, 0)),
+    (70, 70, 4, (1, 1), (2, 1, 0)),
+    (66, 66, 5, (0, 1), (1, 0)),
+    # dx != dy on the unit square: separate x and y weight tables in the first pass
+    (96, 64, 7, (1, 0), (3, 2, 1, 0)),
+    (60, 90, 8, (0, 1), (2, 1, 0)),
 ])
-def test_quadrants_stage_replay_fp64(torch_cuda, n, seed, bc, cascade):
+def test_quadrants_stage_replay_fp64(torch_cuda, nx, ny, seed, bc, cascade):
     """Four-quadrant shocks: each RK stage replayed on the oracle's own stage inputs.
     Candidates within 1e-12 and masks identical (ties are reported if they occur)."""
-    _note(f"quadrant replay n={n} seed={seed} bc={bc} cascade={cascade}")
-    U0 = gi.quadrants(n, n, seed=seed)
-    o = oracle.Oracle(n, n, bc=bc, cascade=cascade)
-    g = _gp(torch_cuda, n, n, bc=bc, prec="f64", cascade=cascade)
+    _note(f"quadrant replay {nx}x{ny} seed={seed} bc={bc} cascade={cascade}")
+    U0 = gi.quadrants(nx, ny, seed=seed)
+    o = oracle.Oracle(nx, ny, bc=bc, cascade=cascade)
+    g = _gp(torch_cuda, nx, ny, bc=bc, prec="f64", cascade=cascade)
     U = o.run(U0, cfl=0.8, nsteps=3)[0]  # let the waves develop
     dt = o.dt(U, 0.8)
     U1 = o.stage(0, U, U, dt)[0]
