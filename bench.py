@@ -77,7 +77,7 @@ HBM_PEAK = 8.0e12
 # (mean over the launches of 3 steps, so 1/3 stage-0 launches that read no U^n),
 # scaled by the counters' reading of a 512 MiB device copy (FETCH x 2.0, WRITE x
 # 1.0).  Valid for the kernel sources with this hash only; see profiles/.
-TRAFFIC = {"src": "58acef9f349e8ca8", "f32": 355.3e6, "f64": None}
+TRAFFIC = {"src": "cb0b8af2d9b95c80", "f32": 400.4e6, "f64": 709.6e6}
 KERNEL_SOURCES = ["gpmood_kernels.hip", "gpmood_device.h", "gpmood_tables.h"]
 
 

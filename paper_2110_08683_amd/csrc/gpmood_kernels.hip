@@ -497,13 +497,91 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
 // pass.  Detection reads no other cell's order, so lowering in place is safe.
 // Everything a cell needs (fluxes, flags, its radius-2 neighbourhood) is loaded
 // at once, up front.  The number of rounds is uniform across the wavefront.
+//
+// cell_load gathers what does not depend on this pass's fluxes (the stage input
+// around the cell, U^n and its order); cell_finish reads the fluxes and flags,
+// forms the candidate, detects, writes the result and lowers.  The tail issues
+// cell_load while other wavefronts still recompute the faces.
+constexpr int kDi13[13] = {0, -1, 1, 0, 0, -2, 2, 0, 0, -1, 1, -1, 1};
+constexpr int kDj13[13] = {0, 0, 0, -1, 1, 0, 0, -2, 2, -1, -1, 1, 1};
+
 template <typename real>
-__device__ __forceinline__ void cells_phase(const StageArgs<real> &A, const int *clist, int n, int t0, int stride,
-                                            const PassOut &P)
+struct CellIn {
+    int c, i, j, o;
+    real rho[13];     // radius-2 diamond of densities (kDi13, kDj13)
+    real mom[5][3];   // the other variables of the cell and its face neighbours
+    real un[4];       // U^n of the cell (stages 1, 2)
+};
+
+template <typename real>
+__device__ __forceinline__ void cell_load(const StageArgs<real> &A, int c, CellIn<real> &X)
+{
+    const int nx = A.nx, ny = A.ny;
+    const size_t plane = (size_t)nx * ny;
+    X.c = c;
+    X.j = c / nx;
+    X.i = c - X.j * nx;
+    size_t yr[5];
+    int xc[5];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+        yr[d] = (size_t)wrap(X.j + d - 2, ny, A.bcy) * nx;
+        xc[d] = wrap(X.i + d - 2, nx, A.bcx);
+    }
+#pragma unroll
+    for (int m = 0; m < 13; ++m) X.rho[m] = A.Us[yr[kDj13[m] + 2] + xc[kDi13[m] + 2]];
+#pragma unroll
+    for (int m = 0; m < 5; ++m)
+#pragma unroll
+        for (int w = 1; w < 4; ++w) X.mom[m][w - 1] = A.Us[w * plane + yr[kDj13[m] + 2] + xc[kDi13[m] + 2]];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) X.un[w] = A.s == 0 ? real(0) : A.Un[w * plane + c];
+    X.o = A.order[c];
+}
+
+// Returns whether the cell is troubled (it has then been lowered).
+template <typename real>
+__device__ __forceinline__ bool cell_finish(const StageArgs<real> &A, const CellIn<real> &X, real dt)
 {
     const int nx = A.nx, ny = A.ny;
     const size_t plane = (size_t)nx * ny;
     const size_t nfx = (size_t)(nx + 1) * ny, nfy = (size_t)nx * (ny + 1);
+    const size_t fxm = (size_t)X.j * (nx + 1) + X.i, gym = (size_t)X.j * nx + X.i;  // faces i-1/2, j-1/2
+    real fx[4][2], gy[4][2];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        fx[w][0] = A.FX[w * nfx + fxm];
+        fx[w][1] = A.FX[w * nfx + fxm + 1];
+        gy[w][0] = A.GY[w * nfy + gym];
+        gy[w][1] = A.GY[w * nfy + gym + nx];
+    }
+    // the cell's own states: right state of its - faces, left state of its + faces
+    const bool rs = (A.FXf[fxm] & 2) || (A.FXf[fxm + 1] & 1) || (A.GYf[gym] & 2) || (A.GYf[gym + nx] & 1);
+    real ust[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const real us = w == 0 ? X.rho[0] : X.mom[0][w - 1];
+        const real dFx = fx[w][1] - fx[w][0];
+        ust[w] = us - dt * (dv(dFx, A.dx) + dv(gy[w][1] - gy[w][0], A.dy));
+    }
+    auto nb = [&](int di, int dj, int w) -> real {
+        int m = 0;
+#pragma unroll
+        for (int t = 0; t < 13; ++t)
+            if (kDi13[t] == di && kDj13[t] == dj) m = t;
+        return w == 0 ? X.rho[m] : X.mom[m < 5 ? m : 0][w - 1];
+    };
+    const bool tr = troubled(A, X.o, ust, rs, nb);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) A.Uout[w * plane + X.c] = combine(A.s, X.un[w], ust[w]);
+    if (tr) A.order[X.c] = (uint8_t)A.next[X.o];
+    return tr;
+}
+
+template <typename real>
+__device__ __forceinline__ void cells_phase(const StageArgs<real> &A, const int *clist, int n, int t0, int stride,
+                                            const PassOut &P)
+{
     const int nround = (n + stride - 1) / stride;
     const real dt = (real)(*A.dt);
     for (int r = 0; r < nround; ++r) {
@@ -512,58 +590,11 @@ __device__ __forceinline__ void cells_phase(const StageArgs<real> &A, const int 
         bool tr = false;
         int i = 0, j = 0;
         if (valid) {
-            const int c = clist[idx];
-            j = c / nx;
-            i = c - j * nx;
-            const size_t fxm = (size_t)j * (nx + 1) + i, gym = (size_t)j * nx + i;
-            size_t yr[5];
-            int xc[5];
-#pragma unroll
-            for (int d = 0; d < 5; ++d) {
-                yr[d] = (size_t)wrap(j + d - 2, ny, A.bcy) * nx;
-                xc[d] = wrap(i + d - 2, nx, A.bcx);
-            }
-            // radius-2 diamond of densities and the other variables of the cell and
-            // its face neighbours: every value detection may read
-            constexpr int di13[13] = {0, -1, 1, 0, 0, -2, 2, 0, 0, -1, 1, -1, 1};
-            constexpr int dj13[13] = {0, 0, 0, -1, 1, 0, 0, -2, 2, -1, -1, 1, 1};
-            real rho[13], mom[5][3];
-#pragma unroll
-            for (int m = 0; m < 13; ++m) rho[m] = A.Us[yr[dj13[m] + 2] + xc[di13[m] + 2]];
-#pragma unroll
-            for (int m = 0; m < 5; ++m)
-#pragma unroll
-                for (int w = 1; w < 4; ++w) mom[m][w - 1] = A.Us[w * plane + yr[dj13[m] + 2] + xc[di13[m] + 2]];
-            real fx[4][2], gy[4][2], un[4];
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                fx[w][0] = A.FX[w * nfx + fxm];
-                fx[w][1] = A.FX[w * nfx + fxm + 1];
-                gy[w][0] = A.GY[w * nfy + gym];
-                gy[w][1] = A.GY[w * nfy + gym + nx];
-                un[w] = A.s == 0 ? real(0) : A.Un[w * plane + c];
-            }
-            const int o = A.order[c];
-            // the cell's own states: right state of its - faces, left state of its + faces
-            const bool rs = (A.FXf[fxm] & 2) || (A.FXf[fxm + 1] & 1) || (A.GYf[gym] & 2) || (A.GYf[gym + nx] & 1);
-            real ust[4];
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                const real us = w == 0 ? rho[0] : mom[0][w - 1];
-                const real dFx = fx[w][1] - fx[w][0];
-                ust[w] = us - dt * (dv(dFx, A.dx) + dv(gy[w][1] - gy[w][0], A.dy));
-            }
-            auto nb = [&](int di, int dj, int w) -> real {
-                int m = 0;
-#pragma unroll
-                for (int t = 0; t < 13; ++t)
-                    if (di13[t] == di && dj13[t] == dj) m = t;
-                return w == 0 ? rho[m] : mom[m < 5 ? m : 0][w - 1];
-            };
-            tr = troubled(A, o, ust, rs, nb);
-#pragma unroll
-            for (int w = 0; w < 4; ++w) A.Uout[w * plane + c] = combine(A.s, un[w], ust[w]);
-            if (tr) A.order[c] = (uint8_t)A.next[o];
+            CellIn<real> X;
+            cell_load(A, clist[idx], X);
+            tr = cell_finish(A, X, dt);
+            i = X.i;
+            j = X.j;
         }
         wave_count(tr, P.tcount);
         claim_after_lowering(A, P, i, j, tr);
@@ -665,8 +696,11 @@ __device__ __forceinline__ void tail_body(const StageArgs<real> &A, const Cascad
     bool back = false;
     for (; k < kend; ++k) {
         __syncthreads();  // the previous pass's lists, counts and fluxes are complete
-        int nf = S.cnt[k & 1][0], nc = S.cnt[k & 1][1];
-        const int nt = S.cnt[k & 1][2];
+        // the same value in every lane: held in scalar registers, so the branches
+        // below (some around block barriers) are scalar
+        int nf = __builtin_amdgcn_readfirstlane(S.cnt[k & 1][0]);
+        int nc = __builtin_amdgcn_readfirstlane(S.cnt[k & 1][1]);
+        const int nt = __builtin_amdgcn_readfirstlane(S.cnt[k & 1][2]);
         if (threadIdx.x == 0 && k > k0) {
             ctl->nface[k] = nf;
             ctl->ncell[k] = nc;
@@ -680,13 +714,35 @@ __device__ __forceinline__ void tail_body(const StageArgs<real> &A, const Cascad
             break;
         }
         if (threadIdx.x == 0) S.cnt[(k + 1) & 1][0] = S.cnt[(k + 1) & 1][1] = S.cnt[(k + 1) & 1][2] = 0;
-        faces_phase(A, S.wl, S.xch[threadIdx.x >> 6], C.flist[k & 1], nf, threadIdx.x, blockDim.x);
-        __syncthreads();
         PassOut P = pass_out(C, k, stamp0);
         P.fcount = &S.cnt[(k + 1) & 1][0];
         P.ccount = &S.cnt[(k + 1) & 1][1];
         P.tcount = &S.cnt[(k + 1) & 1][2];
-        cells_phase(A, C.clist[k & 1], nc, threadIdx.x, blockDim.x, P);
+        const int fw = (4 * nf + 63) >> 6, cw = (nc + 63) >> 6;  // wavefronts of faces, of cells
+        const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);  // uniform per wavefront
+        if (fw + cw <= kTailThreads / 64) {
+            // one round each, on separate wavefronts: the cell wavefronts gather
+            // their inputs while the face wavefronts recompute the fluxes
+            const int c0 = kTailThreads / 64 - cw;  // first cell wavefront
+            const bool cellwave = wv >= c0;
+            const int idx = (int)threadIdx.x - 64 * c0;
+            const bool valid = cellwave && idx < nc;
+            CellIn<real> X;
+            X.i = X.j = 0;
+            if (valid) cell_load(A, C.clist[k & 1][idx], X);
+            if (!cellwave && wv < fw) faces_phase(A, S.wl, S.xch[wv], C.flist[k & 1], nf, threadIdx.x, 64 * fw);
+            __syncthreads();
+            if (cellwave) {
+                bool tr = false;
+                if (valid) tr = cell_finish(A, X, (real)(*A.dt));
+                wave_count(tr, P.tcount);
+                claim_after_lowering(A, P, X.i, X.j, tr);
+            }
+        } else {
+            faces_phase(A, S.wl, S.xch[wv], C.flist[k & 1], nf, threadIdx.x, blockDim.x);
+            __syncthreads();
+            cells_phase(A, C.clist[k & 1], nc, threadIdx.x, blockDim.x, P);
+        }
     }
     if (k >= kend) {
         __syncthreads();
