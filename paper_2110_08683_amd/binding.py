@@ -290,7 +290,7 @@ class GPMood:
                                         ctypes.byref(d) if want_dell else None))
         return d.value if want_dell else None
 
-    def gpm_set_tuning(self, passes_per_check=4, rows_per_wave=16, tail_threshold=48):
+    def gpm_set_tuning(self, passes_per_check=4, rows_per_wave=12, tail_threshold=32):
         self._check(lib().gpm_set_tuning(self.ctx, int(passes_per_check), int(rows_per_wave), int(tail_threshold)))
 
     def gpm_instrument(self, mode=1):
@@ -365,7 +365,7 @@ class GPMoodBatch:
         except Exception:
             pass
 
-    def gpm_batch_set_tuning(self, rows_per_wave=16):
+    def gpm_batch_set_tuning(self, rows_per_wave=12):
         self._check(lib().gpm_batch_set_tuning(self.b, int(rows_per_wave)))
 
     def gpm_batch_init_state(self, p, U):

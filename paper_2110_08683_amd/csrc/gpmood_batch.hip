@@ -44,7 +44,7 @@ struct gpm_batch {
     std::vector<gpm_ctx *> ctx;
     bool have_scheme = false;
     char *mem = nullptr;
-    int rows = 16;
+    int rows = 12;
     int cur = 0;  // slot rotation of the next step (the same for every problem)
     // device tables (inside the caller buffer)
     void *args = nullptr;       // StageArgs<real>[3 rotations][3 stages][nprob]

@@ -60,8 +60,8 @@ struct gpm_ctx {
     unsigned pass = 0;
     int passes_per_check = 4;  // smallest batch of multi-block cascade passes
     int head_guess = 4;        // batch length: the previous stage's multi-block passes + 2
-    int tail_threshold = 48;   // troubled cells at or below which one workgroup finishes the cascade
-    int rows = 16;
+    int tail_threshold = 32;   // troubled cells at or below which one workgroup finishes the cascade
+    int rows = 12;
     int last_npass = 0;
     bool fresh_ctl = true;
     int *pinned = nullptr;

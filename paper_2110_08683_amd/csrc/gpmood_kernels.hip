@@ -319,12 +319,24 @@ struct FaceXchg {
     int fl[64];
 };
 
-// Copy the compact weight table into LDS (all threads of the block; a block
-// barrier must follow before it is read).
-template <typename real>
+// Copy the compact weight table into LDS (all NT threads of the block, every
+// load issued before the first store; a block barrier must follow before it is
+// read).
+template <int NT, typename real>
 __device__ __forceinline__ void load_gtab(const real *gtab, real *wl)
 {
-    for (int k = threadIdx.x; k < kGtabSize; k += blockDim.x) wl[k] = gtab[k];
+    constexpr int per = (kGtabSize + NT - 1) / NT;
+    real v[per];
+#pragma unroll
+    for (int m = 0; m < per; ++m) {
+        const int t = (int)threadIdx.x + m * NT;
+        v[m] = t < kGtabSize ? gtab[t] : real(0);
+    }
+#pragma unroll
+    for (int m = 0; m < per; ++m) {
+        const int t = (int)threadIdx.x + m * NT;
+        if (t < kGtabSize) wl[t] = v[m];
+    }
 }
 
 // Cascade pass, part 1: recompute the listed faces at their EDP_1 order (the
@@ -340,9 +352,12 @@ __device__ __forceinline__ void load_gtab(const real *gtab, real *wl)
 // is below the top radius: at most 2 for GP-MOOD7.  Radius 3 (positions 6..9) is
 // still handled, by a rolled loop.  The number of rounds is uniform across the
 // wavefront (LDS exchange); wl is the LDS copy of the compact weight table.
+// pre: when use_pre, this thread's list entry of round 0, loaded by the caller
+// (while the count was still unknown).
 template <typename real>
 __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real *wl, FaceXchg<real> &X,
-                                            const int *flist, int n, int t0, int stride)
+                                            const int *flist, int n, int t0, int stride, int pre = 0,
+                                            bool use_pre = false)
 {
     const int nx = A.nx, ny = A.ny;
     const int nfx = (nx + 1) * ny, nfy = nx * (ny + 1);
@@ -359,7 +374,7 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
 #pragma unroll
             for (int c = 0; c < 4; ++c) PL[p][c] = PR[p][c] = real(0);
         if (valid) {
-            const int f = flist[idx];
+            const int f = (use_pre && r == 0) ? pre : flist[idx];
             int iL, jL, cL, cR;
             if (f < nfx) {
                 const int j = f / (nx + 1), i = f - j * (nx + 1);  // between cells i-1 and i
@@ -580,7 +595,7 @@ __device__ __forceinline__ bool cell_finish(const StageArgs<real> &A, const Cell
 
 template <typename real>
 __device__ __forceinline__ void cells_phase(const StageArgs<real> &A, const int *clist, int n, int t0, int stride,
-                                            const PassOut &P)
+                                            const PassOut &P, int pre = 0, bool use_pre = false)
 {
     const int nround = (n + stride - 1) / stride;
     const real dt = (real)(*A.dt);
@@ -591,7 +606,7 @@ __device__ __forceinline__ void cells_phase(const StageArgs<real> &A, const int 
         int i = 0, j = 0;
         if (valid) {
             CellIn<real> X;
-            cell_load(A, clist[idx], X);
+            cell_load(A, (use_pre && r == 0) ? pre : clist[idx], X);
             tr = cell_finish(A, X, dt);
             i = X.i;
             j = X.j;
@@ -626,29 +641,36 @@ __global__ __launch_bounds__(256) void k_faces(const StageArgs<real> A, const Ca
 {
     __shared__ real wl[kGtabSize];
     __shared__ FaceXchg<real> xch[4];
+    const int cap = (A.nx + 1) * A.ny + A.nx * (A.ny + 1);
+    const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
+    // issued together, before the counts are known: this thread's first list
+    // entry (in bounds; used only if the pass runs and covers it) and the weights
+    const int i0 = t0 >> 2;
+    const int pre = C.flist[k & 1][i0 < cap ? i0 : cap - 1];
+    load_gtab<256>(A.gtab, wl);
     if (!pass_runs(C, k)) {
         if (blockIdx.x == 0 && threadIdx.x == 0 && C.ctl->ncell[k] > 0) C.ctl->tail_k0 = k;
         return;
     }
-    const int cap = (A.nx + 1) * A.ny + A.nx * (A.ny + 1);
     int n = C.ctl->nface[k];
     n = n < cap ? n : cap;  // a list holds each face at most once
     if (4 * n <= (int)(blockIdx.x * blockDim.x)) return;  // no face for this block
-    load_gtab(A.gtab, wl);
     __syncthreads();
-    faces_phase(A, wl, xch[threadIdx.x >> 6], C.flist[k & 1], n, blockIdx.x * blockDim.x + threadIdx.x,
-                gridDim.x * blockDim.x);
+    faces_phase(A, wl, xch[threadIdx.x >> 6], C.flist[k & 1], n, t0, gridDim.x * blockDim.x, pre, true);
 }
 
 template <typename real>
 __global__ __launch_bounds__(64) void k_cells(const StageArgs<real> A, const Cascade C, int k)
 {
+    const int cap = A.nx * A.ny;
+    const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
+    // this thread's first list entry, issued before the counts are known (in bounds)
+    const int pre = C.clist[k & 1][t0 < cap ? t0 : cap - 1];
     if (!pass_runs(C, k)) return;
     int n = C.ctl->ncell[k];
-    n = n < A.nx * A.ny ? n : A.nx * A.ny;  // a list holds each cell at most once
+    n = n < cap ? n : cap;  // a list holds each cell at most once
     if (n <= (int)(blockIdx.x * blockDim.x)) return;
-    cells_phase(A, C.clist[k & 1], n, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x,
-                pass_out(C, k, C.ctl->stamp0));
+    cells_phase(A, C.clist[k & 1], n, t0, gridDim.x * blockDim.x, pass_out(C, k, C.ctl->stamp0), pre, true);
 }
 
 // The tail of a long cascade (few troubled cells per pass) in one workgroup:
@@ -675,7 +697,7 @@ __device__ __forceinline__ void tail_body(const StageArgs<real> &A, const Cascad
     const int capf = (A.nx + 1) * A.ny + A.nx * (A.ny + 1), capc = A.nx * A.ny;
     Ctl *ctl = C.ctl;
     const unsigned stamp0 = ctl->stamp0;
-    load_gtab(A.gtab, S.wl);
+    load_gtab<kTailThreads>(A.gtab, S.wl);
     int k0 = ctl->tail_k0 > 0 ? ctl->tail_k0 : kdef;
     if (ctl->tail_k0 <= 0 && kbeg < kdef) {
         // no hand-over: the cascade either ended inside the batch kbeg..kdef-1 (at
