@@ -78,7 +78,7 @@ __device__ __forceinline__ size_t cell3(const Stage3<real> &S, int i, int j, int
 template <typename real>
 __device__ __forceinline__ real p3(real g, const real (&q)[5])
 {
-    return (g - real(1)) * (q[4] - real(0.5) * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0]);
+    return (g - real(1)) * (q[4] - dv(real(0.5) * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]), q[0]));
 }
 
 // HLLC with normal axis a (1 + a is the normal momentum), as the 2D solver with a
@@ -88,8 +88,8 @@ __device__ __forceinline__ void hllc3(real g, int a, const real (&UL)[5], const 
                                       bool &badL, bool &badR)
 {
     const int n = 1 + a, t1 = 1 + (a + 1) % 3, t2 = 1 + (a + 2) % 3;
-    const real rl = UL[0], irl = real(1) / rl, ul = UL[n] * irl, vl = UL[t1] * irl, wl = UL[t2] * irl, El = UL[4];
-    const real rr = UR[0], irr = real(1) / rr, ur = UR[n] * irr, vr = UR[t1] * irr, wr = UR[t2] * irr, Er = UR[4];
+    const real rl = UL[0], irl = dv(real(1), rl), ul = UL[n] * irl, vl = UL[t1] * irl, wl = UL[t2] * irl, El = UL[4];
+    const real rr = UR[0], irr = dv(real(1), rr), ur = UR[n] * irr, vr = UR[t1] * irr, wr = UR[t2] * irr, Er = UR[4];
     const real pl = (g - real(1)) * (El - real(0.5) * rl * (ul * ul + vl * vl + wl * wl));
     const real pr = (g - real(1)) * (Er - real(0.5) * rr * (ur * ur + vr * vr + wr * wr));
     badL = !(finite(rl) && finite(pl));
@@ -97,15 +97,15 @@ __device__ __forceinline__ void hllc3(real g, int a, const real (&UL)[5], const 
     const real cl = sq(g * pl * irl), cr = sq(g * pr * irr);
     const real SL = vmin(ul - cl, ur - cr);
     const real SR = vmax(ul + cl, ur + cr);
-    const real Ss = (pr - pl + rl * ul * (SL - ul) - rr * ur * (SR - ur)) / (rl * (SL - ul) - rr * (SR - ur));
+    const real Ss = dv(pr - pl + rl * ul * (SL - ul) - rr * ur * (SR - ur), rl * (SL - ul) - rr * (SR - ur));
     const bool useL = Ss >= real(0);
     const real rk = useL ? rl : rr, uk = useL ? ul : ur, vk = useL ? vl : vr, wk = useL ? wl : wr;
     const real Ek = useL ? El : Er, pk = useL ? pl : pr, Sk = useL ? SL : SR, irk = useL ? irl : irr;
     const real sku = Sk - uk;
-    const real fac = rk * sku / (Sk - Ss);
+    const real fac = dv(rk * sku, Sk - Ss);
     const real fk[5] = {rk * uk, rk * uk * uk + pk, rk * uk * vk, rk * uk * wk, uk * (Ek + pk)};
     const real uc[5] = {rk, rk * uk, rk * vk, rk * wk, Ek};
-    const real us[5] = {fac, fac * Ss, fac * vk, fac * wk, fac * (Ek * irk + (Ss - uk) * (Ss + pk / (rk * sku)))};
+    const real us[5] = {fac, fac * Ss, fac * vk, fac * wk, fac * (Ek * irk + (Ss - uk) * (Ss + dv(pk, rk * sku)))};
     const real fL[5] = {rl * ul, rl * ul * ul + pl, rl * ul * vl, rl * ul * wl, ul * (El + pl)};
     const real fR[5] = {rr * ur, rr * ur * ur + pr, rr * ur * vr, rr * ur * wr, ur * (Er + pr)};
     const bool takeL = SL >= real(0);
