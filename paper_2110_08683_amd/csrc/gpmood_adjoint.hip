@@ -283,14 +283,24 @@ __global__ void k_adj_zero(double *acc, size_t n)
         acc[k] = 0.0;
 }
 
-// Fixed-order sum of the per-block partials into *out.
-__global__ void k_adj_dl_final(const double *partial, int n, double *out)
+// Fixed-order sum of the per-block partials into *out (one block of 256 threads):
+// thread t sums the contiguous chunk t in order, then a pairwise tree in LDS.  The
+// order does not depend on timing, so the result is the same on every run.
+__global__ __launch_bounds__(256) void k_adj_dl_final(const double *partial, int n, double *out)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int k = 0; k < n; ++k) s += partial[k];
-        *out = s;
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    const int chunk = (n + 255) / 256;
+    const int k0 = t * chunk, k1 = min(n, k0 + chunk);
+    double s = 0.0;
+    for (int k = k0; k < k1; ++k) s += partial[k];
+    red[t] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
     }
+    if (t == 0) *out = red[0];
 }
 
 template <typename real>
@@ -302,7 +312,7 @@ hipError_t launch_stage_vjp(const AdjArgs<real> &J, int nblk_faces, double *dl_o
     size_t nb = (4 * n + 255) / 256;
     if (nb > 4096) nb = 4096;
     hipLaunchKernelGGL(k_adj_cells<real>, dim3((unsigned)nb), dim3(256), 0, st, J);
-    hipLaunchKernelGGL(k_adj_dl_final, dim3(1), dim3(64), 0, st, J.dl_partial, nblk_faces, dl_out);
+    hipLaunchKernelGGL(k_adj_dl_final, dim3(1), dim3(256), 0, st, J.dl_partial, nblk_faces, dl_out);
     return hipGetLastError();
 }
 
