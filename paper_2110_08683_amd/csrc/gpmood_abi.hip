@@ -348,9 +348,9 @@ static gpm_status run_stage(gpm_ctx *c, const Weights<real> &W, int s, const voi
         ++c->nev_used;
         HIPCHK(c, hipEventRecord(ev[0], c->stream));
     }
-    e = launch_first_pass<real>(A, P, c->stream);
+    // ev[1] is recorded between the first pass and its claims
+    e = launch_first_pass<real>(A, P, C, ev ? ev[1] : nullptr, c->stream);
     if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("first pass: ") + hipGetErrorString(e));
-    if (ev) HIPCHK(c, hipEventRecord(ev[1], c->stream));
 
     // Cascade: a batch of multi-block passes (each returns at once when it has no
     // work or when the tail takes over), then the single-workgroup tail, then one

@@ -96,6 +96,7 @@ struct Ctl {
     unsigned long long acc_iters;   // summed MOOD iterations
     unsigned long long acc_stages;
     // cascade control, written by the pass kernels and the single-workgroup tail
+    int nlow;         // cells lowered by the first pass (listed for the deferred claims)
     int tail_end;     // first pass the tail did not run
     int tail_k0;      // first pass left to the tail by the multi-block passes (0: none)
     int tail_back;    // 1: the tail stopped at tail_end because the pass grew large
@@ -410,6 +411,24 @@ __device__ __forceinline__ void wave_count(bool flag, int *count)
 {
     const unsigned long long mask = __ballot(flag);
     if (mask != 0ull && (threadIdx.x & 63) == 0) atomicAdd(count, (int)__popcll(mask));
+}
+
+// Reserve n slots per lane (n < 1024) in one list with one atomic per wavefront;
+// returns the lane's first slot.  Must be reached by all 64 lanes together.
+__device__ __forceinline__ int wave_reserve(int n, int *count)
+{
+    const int lane = threadIdx.x & 63;
+    int incl = n;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(incl, d);
+        if (lane >= d) incl += t;
+    }
+    const int tot = __shfl(incl, 63);
+    int b = 0;
+    if (lane == 63 && tot != 0) b = atomicAdd(count, tot);
+    b = __shfl(b, 63);
+    return b + incl - n;
 }
 
 // Reserve n slots per lane in two lists at once (n = count0 + 65536 * count1,

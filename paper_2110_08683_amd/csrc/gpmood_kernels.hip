@@ -111,7 +111,10 @@ __device__ __forceinline__ void claim_after_lowering(const StageArgs<real> &A, c
 
 // One wavefront's strip (tile wid of the problem) of the first pass; ring is the
 // wavefront's LDS ring.  ISO: A.iso is 1 (the y states read the x weights).
-template <typename real, int RT, bool ISO>
+// DEFER: a lowered cell is only appended to P.clist (count P.ccount), and
+// k_claims_first makes its claims after the pass; otherwise the claims are made
+// at once (with atomics that hold the wavefront until they return).
+template <typename real, int RT, bool ISO, bool DEFER>
 __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const PassOut &P, int wid,
                                                 real (*ring)[4][LW])
 {
@@ -265,7 +268,12 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
                     A.order[c] = (uint8_t)(tr ? A.next[RT] : RT);
                 }
                 wave_count(tr, P.tcount);
-                claim_after_lowering(A, P, i, jr, tr);
+                if constexpr (DEFER) {
+                    const int b = wave_reserve(tr ? 1 : 0, P.ccount);
+                    if (tr) P.clist[b] = jr * nx + i;
+                } else {
+                    claim_after_lowering(A, P, i, jr, tr);
+                }
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) Gprev[v] = G[v];
@@ -290,7 +298,31 @@ __global__ __launch_bounds__(64 * WPB, sizeof(real) == 4 ? 2 : 1) void k_first_p
     const int wv = threadIdx.x >> 6;
     PassOut Q = P;
     Q.stamp = *A.stamp0;
-    first_pass_wave<real, RT, ISO>(A, Q, xcd_tile(blockIdx.x, gridDim.x) * WPB + wv, ring_all[wv]);
+    first_pass_wave<real, RT, ISO, true>(A, Q, xcd_tile(blockIdx.x, gridDim.x) * WPB + wv, ring_all[wv]);
+}
+
+// The claims of the cells the first pass lowered (listed in low, count *nlow):
+// the same claims, stamps and lists as if they had been made in the pass.
+template <typename real>
+__global__ __launch_bounds__(256) void k_claims_first(const StageArgs<real> A, const PassOut P, const int *low,
+                                                      const int *nlow)
+{
+    const int n = *nlow;
+    PassOut Q = P;
+    Q.stamp = *A.stamp0;
+    const int stride = gridDim.x * blockDim.x;
+    const int nround = (n + stride - 1) / stride;
+    for (int r = 0; r < nround; ++r) {
+        const int t = r * stride + blockIdx.x * blockDim.x + threadIdx.x;
+        const bool act = t < n;
+        int i = 0, j = 0;
+        if (act) {
+            const int c = low[t];
+            j = c / A.nx;
+            i = c - j * A.nx;
+        }
+        claim_after_lowering(A, Q, i, j, act);
+    }
 }
 
 // ------------------------------------------------------------- cascade pass
@@ -802,6 +834,7 @@ __global__ void k_reset(Ctl *ctl, int nzero, unsigned stamp0)
         ctl->tail_k0 = 0;
         ctl->tail_back = 0;
         ctl->stamp0 = stamp0;
+        ctl->nlow = 0;
     }
 }
 
@@ -995,7 +1028,7 @@ __global__ __launch_bounds__(64 * WPB, sizeof(real) == 4 ? 2 : 1) void k_first_p
     PassOut Q = table_entry(B.pout, p);
     Q.stamp = *A.stamp0;
     const int wv = threadIdx.x >> 6;
-    first_pass_wave<real, RT, ISO>(A, Q, (blockIdx.x - blk[p]) * WPB + wv, ring_all[wv]);
+    first_pass_wave<real, RT, ISO, false>(A, Q, (blockIdx.x - blk[p]) * WPB + wv, ring_all[wv]);
 }
 
 // Problem p = blockIdx.x runs its whole cascade (no hand-back).
@@ -1128,13 +1161,35 @@ static hipError_t launch_first_pass_rt(const StageArgs<real> &A, const PassOut &
     return hipGetLastError();
 }
 
+// First pass, then the claims of the cells it lowered (listed in C.clist[0],
+// which pass 1 only writes after reading its own list C.clist[1]); `mid`, if
+// given, is recorded between the two.
 template <typename real>
-hipError_t launch_first_pass(const StageArgs<real> &A, const PassOut &P, hipStream_t st)
+static hipError_t launch_first_pass_and_claims(const StageArgs<real> &A, const PassOut &P, const Cascade &C,
+                                               hipError_t (*fp)(const StageArgs<real> &, const PassOut &, hipStream_t),
+                                               hipEvent_t mid, hipStream_t st)
+{
+    PassOut L = P;
+    L.clist = C.clist[0];
+    L.ccount = &C.ctl->nlow;
+    hipError_t e = fp(A, L, st);
+    if (e != hipSuccess) return e;
+    if (mid) {
+        e = hipEventRecord(mid, st);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_claims_first<real>, dim3(256), dim3(256), 0, st, A, P, C.clist[0], &C.ctl->nlow);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_first_pass(const StageArgs<real> &A, const PassOut &P, const Cascade &C, hipEvent_t mid,
+                             hipStream_t st)
 {
     switch (A.top) {
-    case 3: return launch_first_pass_rt<real, 3>(A, P, st);
-    case 2: return launch_first_pass_rt<real, 2>(A, P, st);
-    case 1: return launch_first_pass_rt<real, 1>(A, P, st);
+    case 3: return launch_first_pass_and_claims<real>(A, P, C, launch_first_pass_rt<real, 3>, mid, st);
+    case 2: return launch_first_pass_and_claims<real>(A, P, C, launch_first_pass_rt<real, 2>, mid, st);
+    case 1: return launch_first_pass_and_claims<real>(A, P, C, launch_first_pass_rt<real, 1>, mid, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1204,8 +1259,10 @@ hipError_t launch_totals(const real *U, size_t ncell, double area, double *parti
     return hipGetLastError();
 }
 
-template hipError_t launch_first_pass<float>(const StageArgs<float> &, const PassOut &, hipStream_t);
-template hipError_t launch_first_pass<double>(const StageArgs<double> &, const PassOut &, hipStream_t);
+template hipError_t launch_first_pass<float>(const StageArgs<float> &, const PassOut &, const Cascade &, hipEvent_t,
+                                             hipStream_t);
+template hipError_t launch_first_pass<double>(const StageArgs<double> &, const PassOut &, const Cascade &,
+                                              hipEvent_t, hipStream_t);
 template hipError_t launch_cascade_pass<float>(const StageArgs<float> &, const Cascade &, int, int, hipStream_t);
 template hipError_t launch_cascade_pass<double>(const StageArgs<double> &, const Cascade &, int, int, hipStream_t);
 template hipError_t launch_cascade_tail<float>(const StageArgs<float> &, const Cascade &, int, int, int, hipStream_t);

@@ -9,7 +9,7 @@
 namespace gpm {
 
 template <typename real>
-hipError_t launch_first_pass(const StageArgs<real> &A, const PassOut &P, hipStream_t st);
+hipError_t launch_first_pass(const StageArgs<real> &A, const PassOut &P, const Cascade &C, hipEvent_t mid, hipStream_t st);
 template <typename real>
 hipError_t launch_cascade_pass(const StageArgs<real> &A, const Cascade &C, int k, int nblocks, hipStream_t st);
 template <typename real>
