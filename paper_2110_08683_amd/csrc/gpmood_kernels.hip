@@ -11,9 +11,10 @@
 // HLLC on its own x face, and evaluates the y face below it against the y+ states
 // it kept from row j-1.  Cell (i, j-1) is then complete: candidate, detection,
 // RK combine.  Every face flux (and its Riemann-state CAD flags) is stored for the
-// cascade.  A troubled cell takes the next scheme of the cascade at once and claims
-// its four faces and the five cells whose candidates they change.  No block
-// barrier is needed: each wavefront only reads LDS it wrote itself.
+// cascade.  A troubled cell takes the next scheme of the cascade at once and is
+// listed; a follow-up kernel claims its four faces and the five cells whose
+// candidates they change.  No block barrier is needed: each wavefront only reads
+// LDS it wrote itself.
 //
 // Cascade pass k (k_faces, then k_cells): recompute the claimed faces at their new
 // EDP_1 order (min of the two cells' radii), then re-evaluate the claimed cells
@@ -111,10 +112,10 @@ __device__ __forceinline__ void claim_after_lowering(const StageArgs<real> &A, c
 
 // One wavefront's strip (tile wid of the problem) of the first pass; ring is the
 // wavefront's LDS ring.  ISO: A.iso is 1 (the y states read the x weights).
-// DEFER: a lowered cell is only appended to P.clist (count P.ccount), and
-// k_claims_first makes its claims after the pass; otherwise the claims are made
-// at once (with atomics that hold the wavefront until they return).
-template <typename real, int RT, bool ISO, bool DEFER>
+// A lowered cell is only appended to P.clist (count P.ccount); its claims are
+// made after the pass (k_claims_first, or k_tail_batch in a batch), which keeps
+// the claim atomics, and the wait for their results, out of the march.
+template <typename real, int RT, bool ISO>
 __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const PassOut &P, int wid,
                                                 real (*ring)[4][LW])
 {
@@ -268,12 +269,8 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
                     A.order[c] = (uint8_t)(tr ? A.next[RT] : RT);
                 }
                 wave_count(tr, P.tcount);
-                if constexpr (DEFER) {
-                    const int b = wave_reserve(tr ? 1 : 0, P.ccount);
-                    if (tr) P.clist[b] = jr * nx + i;
-                } else {
-                    claim_after_lowering(A, P, i, jr, tr);
-                }
+                const int b = wave_reserve(tr ? 1 : 0, P.ccount);
+                if (tr) P.clist[b] = jr * nx + i;
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) Gprev[v] = G[v];
@@ -296,9 +293,7 @@ __global__ __launch_bounds__(64 * WPB, sizeof(real) == 4 ? 2 : 1) void k_first_p
 {
     __shared__ real ring_all[WPB][8][4][LW];
     const int wv = threadIdx.x >> 6;
-    PassOut Q = P;
-    Q.stamp = *A.stamp0;
-    first_pass_wave<real, RT, ISO, true>(A, Q, xcd_tile(blockIdx.x, gridDim.x) * WPB + wv, ring_all[wv]);
+    first_pass_wave<real, RT, ISO>(A, P, xcd_tile(blockIdx.x, gridDim.x) * WPB + wv, ring_all[wv]);
 }
 
 // The claims of the cells the first pass lowered (listed in low, count *nlow):
@@ -1025,13 +1020,17 @@ __global__ __launch_bounds__(64 * WPB, sizeof(real) == 4 ? 2 : 1) void k_first_p
     cptr<int> blk = (cptr<int>)B.blk;
     const int p = find_problem(blk, B.nprob, blockIdx.x);
     const StageArgs<real> &A = table_entry(B.args, p);
+    const Cascade &C = table_entry(B.casc, p);
     PassOut Q = table_entry(B.pout, p);
-    Q.stamp = *A.stamp0;
+    // lowered cells are listed in clist[0]; k_tail_batch makes their claims
+    Q.clist = C.clist[0];
+    Q.ccount = &C.ctl->nlow;
     const int wv = threadIdx.x >> 6;
-    first_pass_wave<real, RT, ISO, false>(A, Q, (blockIdx.x - blk[p]) * WPB + wv, ring_all[wv]);
+    first_pass_wave<real, RT, ISO>(A, Q, (blockIdx.x - blk[p]) * WPB + wv, ring_all[wv]);
 }
 
-// Problem p = blockIdx.x runs its whole cascade (no hand-back).
+// Problem p = blockIdx.x makes the claims of the cells its first pass lowered,
+// then runs its whole cascade (no hand-back).
 template <typename real>
 __global__ __launch_bounds__(kTailThreads) void k_tail_batch(const BatchTabs<real> B)
 {
@@ -1039,6 +1038,23 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_batch(const BatchTabs<rea
     const int p = blockIdx.x;
     const StageArgs<real> &A = table_entry(B.args, p);
     const Cascade &C = table_entry(B.casc, p);
+    PassOut P = table_entry(B.pout, p);
+    P.stamp = *A.stamp0;
+    const int n = C.ctl->nlow;
+    const int nround = (n + kTailThreads - 1) / kTailThreads;
+    for (int r = 0; r < nround; ++r) {
+        const int t = r * kTailThreads + (int)threadIdx.x;
+        const bool act = t < n;
+        int i = 0, j = 0;
+        if (act) {
+            const int c = C.clist[0][t];
+            j = c / A.nx;
+            i = c - j * A.nx;
+        }
+        claim_after_lowering(A, P, i, j, act);
+    }
+    __threadfence();  // the claims' counts and lists are read below from device memory
+    __syncthreads();
     tail_body(A, C, 1, 1, kMaxPasses, S);
 }
 
@@ -1055,6 +1071,7 @@ __global__ void k_reset_batch(const Cascade *casc, int nprob)
     ctl->tail_end = 0;
     ctl->tail_k0 = 0;
     ctl->tail_back = 0;
+    ctl->nlow = 0;
     ctl->stamp0 += (unsigned)kMaxPasses + 2;
 }
 
