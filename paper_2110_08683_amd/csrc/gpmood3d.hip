@@ -221,6 +221,77 @@ __global__ __launch_bounds__(128) void k3_faces(const Stage3<real> S, const int 
         face3_flux(S, all ? t : list[t]);
 }
 
+// First evaluation: every face of axis A at the top radius R (every cell starts the
+// stage at the top order), with the products and sums of face3_flux in the same
+// order.  All 2 x 5 stencils are loaded once into registers; the node loop is
+// rolled and reads each node's 2 x 25 weights through the scalar path (R and A
+// are uniform), so no lane loads a weight.
+template <typename real, int R, int A>
+__global__ __launch_bounds__(128, 1) void k3_faces_top(const Stage3<real> S)
+{
+    constexpr int ns = R == 1 ? 7 : 25, nq = R == 1 ? 4 : 9;
+    const int m0 = S.n[0] + (A == 0), m1 = S.n[1] + (A == 1), m2 = S.n[2] + (A == 2);
+    const int nfa = m0 * m1 * m2;
+    const int loc = blockIdx.x * blockDim.x + threadIdx.x;
+    if (loc >= nfa) return;
+    const size_t plane = (size_t)S.n[0] * S.n[1] * S.n[2];
+    const int i = loc % m0, rr = loc / m0, j = rr % m1, k = rr / m1;
+    const int iL = i - (A == 0), jL = j - (A == 1), kL = k - (A == 2);
+    real qL[5][ns], qR[5][ns];
+#pragma unroll
+    for (int m = 0; m < ns; ++m) {
+        const size_t cl = cell3(S, iL + kBall[m][0], jL + kBall[m][1], kL + kBall[m][2]);
+        const size_t cr = cell3(S, i + kBall[m][0], j + kBall[m][1], k + kBall[m][2]);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            qL[v][m] = S.Us[v * plane + cl];
+            qR[v][m] = S.Us[v * plane + cr];
+        }
+    }
+    const cptr<real> zL = (cptr<real>)S.z + ((R - 1) * 6 + 2 * A + 1) * 9 * 25;  // + face of the left cell
+    const cptr<real> zR = (cptr<real>)S.z + ((R - 1) * 6 + 2 * A) * 9 * 25;      // - face of the right cell
+    const cptr<real> w = (cptr<real>)S.qw + (R - 1) * 9;
+    real Fs[5] = {real(0), real(0), real(0), real(0), real(0)};
+    bool bl = false, br = false;
+#pragma unroll 1
+    for (int q = 0; q < nq; ++q) {
+        real sl[5], sr[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            real a = real(0), b = real(0);
+#pragma unroll
+            for (int m = 0; m < ns; ++m) {
+                a = fma(zL[q * 25 + m], qL[v][m], a);
+                b = fma(zR[q * 25 + m], qR[v][m], b);
+            }
+            sl[v] = a;
+            sr[v] = b;
+        }
+        real fl[5];
+        bool b1, b2;
+        hllc3(S.gamma, A, sl, sr, fl, b1, b2);
+        bl = bl || b1;
+        br = br || b2;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Fs[v] = fma(w[q], fl[v], Fs[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) S.F[A][(size_t)v * nfa + loc] = Fs[v];
+    S.Ff[A][loc] = (uint8_t)((bl ? 1 : 0) | (br ? 2 : 0));
+}
+
+template <typename real, int R>
+static void launch_faces_top(const Stage3<real> &S, hipStream_t st)
+{
+    for (int a = 0; a < 3; ++a) {
+        const long long nfa = (long long)(S.n[0] + (a == 0)) * (S.n[1] + (a == 1)) * (S.n[2] + (a == 2));
+        const dim3 g((unsigned)((nfa + 127) / 128)), t(128);
+        if (a == 0) hipLaunchKernelGGL((k3_faces_top<real, R, 0>), g, t, 0, st, S);
+        if (a == 1) hipLaunchKernelGGL((k3_faces_top<real, R, 1>), g, t, 0, st, S);
+        if (a == 2) hipLaunchKernelGGL((k3_faces_top<real, R, 2>), g, t, 0, st, S);
+    }
+}
+
 // Face id of axis a at cell (i, j, k) (the - face; + face: the next index along a).
 template <typename real>
 __device__ __forceinline__ int face3_id(const Stage3<real> &S, int a, int i, int j, int k)
@@ -669,7 +740,9 @@ static gpm_status stage3(gpm3_ctx *c, int s, const void *Un, const void *Us, voi
     if (nbf > 65536) nbf = 65536;
     int nbc = (int)((c->ncell + 127) / 128);
     if (nbc > 65536) nbc = 65536;
-    hipLaunchKernelGGL(k3_faces<real>, dim3(nbf), dim3(128), 0, c->stream, S, (const int *)nullptr, (const int *)nullptr, 1);
+    if (c->top == 2) launch_faces_top<real, 2>(S, c->stream);
+    else if (c->top == 1) launch_faces_top<real, 1>(S, c->stream);
+    else hipLaunchKernelGGL(k3_faces<real>, dim3(nbf), dim3(128), 0, c->stream, S, (const int *)nullptr, (const int *)nullptr, 1);
     PassOut3 P;
     P.flist = c->flist[1];
     P.clist = c->clist[1];
