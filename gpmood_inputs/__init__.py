@@ -194,6 +194,21 @@ def shock_tube(nx, ny, left, right, x0=0.5, gamma=GAMMA):
 
 
 # --------------------------------------------------------------------------
+# Random cell-wise state (stress input: most cells troubled)
+# --------------------------------------------------------------------------
+def noise(nx, ny, seed=11, sigma=0.6, gamma=GAMMA):
+    """Cell-wise random state: log-normal density and pressure (log-sd sigma),
+    standard-normal velocities (PCG64 seed).  Almost every cell is rough, so a
+    stage lowers a large share of the grid."""
+    rng = np.random.default_rng(seed)
+    rho = np.exp(rng.normal(0.0, sigma, (ny, nx)))
+    u = rng.normal(0.0, 1.0, (ny, nx))
+    v = rng.normal(0.0, 1.0, (ny, nx))
+    p = np.exp(rng.normal(0.0, sigma, (ny, nx)))
+    return prim_to_cons(rho, u, v, p, gamma)
+
+
+# --------------------------------------------------------------------------
 # 3D blast (seeded density noise)
 # --------------------------------------------------------------------------
 def density_wave3d(n, amp=0.2, u=1.0, v=1.0, w=1.0, p=1.0, t=0.0, gamma=GAMMA):

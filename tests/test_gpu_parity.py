@@ -125,6 +125,29 @@ def test_quadrants_stage_replay_fp64(torch_cuda, nx, ny, seed, bc, cascade):
     assert exercised > 0
 
 
+def test_noise_mass_lowering_stage_fp64(torch_cuda):
+    """A random cell-wise state at 512^2 (x periodic, y outflow): the first pass
+    lowers tens of thousands of cells (more than one round of the follow-up claims
+    kernel) and the cascade runs with large multi-block passes.  Each stage replayed
+    on the oracle's inputs: candidates within 1e-12, masks, per-level counts and
+    evaluations identical."""
+    n = 512
+    _note("noise 512 f64 stage replay")
+    U = gi.noise(n, n, seed=11)
+    o = oracle.Oracle(n, n, bc=(0, 1), cascade=(3, 2, 1, 0))
+    g = _gp(torch_cuda, n, n, bc=(0, 1), prec="f64", cascade=(3, 2, 1, 0))
+    dt = o.dt(U, 0.8)
+    U1 = o.stage(0, U, U, dt)[0]
+    for s, Us in ((0, U), (1, U1)):
+        Ug, mask, counts, iters, Uo, order, ocounts, oiters = _replay_stage(torch_cuda, g, o, s, U, Us, dt)
+        assert (order < 3).sum() > 65536  # the deferred claims take several rounds
+        assert np.array_equal(mask, order), int((mask != order).sum())
+        np.testing.assert_array_equal(counts[:4], ocounts)
+        assert iters == oiters
+        err = _rel_l1(Ug, Uo)
+        assert np.all(err <= 1e-12), (s, err)
+
+
 def test_quadrants_steps_conservation_fp64(torch_cuda):
     """Periodic four-quadrant run, 10 GPU steps: totals conserved to roundoff and the final
     state close to the oracle's (masks may diverge slowly through ties over many steps)."""

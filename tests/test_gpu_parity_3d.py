@@ -26,15 +26,19 @@ def torch_cuda():
     return torch
 
 
-@pytest.mark.parametrize("n,bc,case,nsteps", [(12, (1, 1, 1), "blast", 2), (10, (0, 1, 0), "blast", 2),
-                                              (12, (0, 0, 0), "wave", 2), (9, (1, 0, 1), "blast", 1)])
-def test_3d_matches_oracle_fp64(torch_cuda, n, bc, case, nsteps):
+@pytest.mark.parametrize("n,bc,case,nsteps,cascade", [(12, (1, 1, 1), "blast", 2, (2, 1, 0)),
+                                                      (10, (0, 1, 0), "blast", 2, (2, 1, 0)),
+                                                      (12, (0, 0, 0), "wave", 2, (2, 1, 0)),
+                                                      (9, (1, 0, 1), "blast", 1, (2, 1, 0)),
+                                                      # GP-MOOD3: the radius-1 first-evaluation kernel
+                                                      (11, (1, 0, 1), "blast", 2, (1, 0))])
+def test_3d_matches_oracle_fp64(torch_cuda, n, bc, case, nsteps, cascade):
     from paper_2110_08683_amd import GPMood3D
-    _note(f"3d f64 n={n} bc={bc} {case} steps={nsteps}")
+    _note(f"3d f64 n={n} bc={bc} {case} steps={nsteps} cascade={cascade}")
     U0 = gi.blast3d(n, r_cells=2.0, p_in=10.0, p_out=0.1) if case == "blast" else gi.density_wave3d(n)
-    g = GPMood3D((n, n, n), bc=bc, prec="f64", cascade=(2, 1, 0), device="cuda:0")
+    g = GPMood3D((n, n, n), bc=bc, prec="f64", cascade=cascade, device="cuda:0")
     g.gpm3_init_state(U0)
-    o = oracle.Oracle3D((n, n, n), bc=bc, cascade=(2, 1, 0))
+    o = oracle.Oracle3D((n, n, n), bc=bc, cascade=cascade)
     Uo, dts, iters, counts = o.run(U0, cfl=0.3, nsteps=nsteps)
     g.gpm3_step(0.3, nsteps)
     U = g.gpm3_get_state()
