@@ -48,7 +48,7 @@ def test_3d_matches_oracle_fp64(torch_cuda, n, bc, case, nsteps, cascade):
     assert err <= 1e-12
     for v in (1, 2, 3):  # momenta may vanish: absolute scale of rho and E
         assert np.abs(U[v] - Uo[v]).sum() <= 1e-12 * np.abs(Uo[0]).sum()
-    assert list(c) == list(counts) and it == iters[-1, 2]
+    assert list(c[:len(cascade)]) == list(counts) and it == iters[-1, 2]
     g.close()
 
 
