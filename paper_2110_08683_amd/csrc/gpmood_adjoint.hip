@@ -43,11 +43,13 @@ __device__ __forceinline__ Dual<real> operator*(Dual<real> a, Dual<real> b)
 {
     return Dual<real>(a.v * b.v, a.d * b.v + a.v * b.d);
 }
+// Division and square root go through dv / sq: IEEE in FP64, the hardware
+// reciprocal and square root in FP32 (as in the forward stage).
 template <typename real>
 __device__ __forceinline__ Dual<real> operator/(Dual<real> a, Dual<real> b)
 {
-    const real q = a.v / b.v;
-    return Dual<real>(q, (a.d - q * b.d) / b.v);
+    const real q = dv(a.v, b.v);
+    return Dual<real>(q, dv(a.d - q * b.d, b.v));
 }
 template <typename real>
 __device__ __forceinline__ bool operator<(Dual<real> a, Dual<real> b) { return a.v < b.v; }
@@ -58,8 +60,8 @@ __device__ __forceinline__ bool operator>=(Dual<real> a, Dual<real> b) { return 
 template <typename real>
 __device__ __forceinline__ Dual<real> sqrt(Dual<real> a)
 {
-    const real r = ::sqrt(a.v);
-    return Dual<real>(r, a.d / (real(2) * r));
+    const real r = sq(a.v);
+    return Dual<real>(r, dv(a.d, real(2) * r));
 }
 template <typename real>
 __device__ __forceinline__ bool finite(Dual<real> a) { return __builtin_isfinite(a.v); }
