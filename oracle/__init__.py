@@ -58,6 +58,26 @@ def build(force=True):
 _lib = None
 
 
+def rk4_stages():
+    """The five-stage 4th-order SSP-RK of eqs. (rk4) and (rk4_substeps) as general
+    stages U_out = a B + b (Us - cf dt F(Us)).  Sub-step i (i = 1..4):
+    U(i) = alpha_i U^n + beta_i U(i-1) - gamma_i dt F(U(i-1)), so a = alpha_i,
+    b = beta_i, cf = gamma_i / beta_i.  Reading: the last combination has both
+    dt F terms subtracted, as every sub-step (the printed "+" on the U(3) term
+    would not be 4th order); it is U^{n+1} = W + b5 (U(4) - cf5 dt F(U(4)))
+    with W = c2 U(2) + c3 U(3) - d3 dt F(U(3)), where dt F(U(3)) is recovered
+    from sub-step 4, dt F(U(3)) = (beta_4 U(3) + alpha_4 U^n - U(4)) / gamma_4,
+    so W = w2 U(2) + w3 U(3) + w4 U(4) + wn U^n."""
+    alpha = [0.0, 0.444370493651235, 0.620101851488403, 0.178079954393132]
+    beta = [1.0, 0.555629506348765, 0.379898148511597, 0.821920045606868]
+    gam = [0.391752226571890, 0.368410593050371, 0.251891774271694, 0.544974750228521]
+    c2, c3, d3 = 0.517231671970585, 0.096059710526147, 0.063692468666290
+    b5, d4 = 0.386708617503269, 0.226007483236906
+    sub = [(alpha[i], beta[i], gam[i] / beta[i]) for i in range(4)]
+    w = (c2, c3 - d3 * beta[3] / gam[3], d3 / gam[3], -d3 * alpha[3] / gam[3])
+    return {"sub": sub, "w": w, "last": (1.0, b5, d4 / b5)}
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -70,6 +90,9 @@ def lib():
         L.orc_stage.argtypes = [cp, ctypes.c_int, dp, dp, ctypes.c_double, dp, ip,
                                 ctypes.POINTER(ctypes.c_longlong)]
         L.orc_stage.restype = ctypes.c_int
+        L.orc_stage_coef.argtypes = [cp, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, dp, ip, ctypes.POINTER(ctypes.c_longlong)]
+        L.orc_stage_coef.restype = ctypes.c_int
         L.orc_stage_forced.argtypes = [cp, ctypes.c_int, dp, dp, ctypes.c_double, ip, dp]
         L.orc_candidate.argtypes = [cp, dp, ctypes.c_double, ip, dp, ip]
         L.orc_criteria.argtypes = [cp, dp, dp, ip, ip, ctypes.POINTER(ctypes.c_uint), ip]
@@ -174,6 +197,37 @@ class Oracle:
         it = lib().orc_stage(ctypes.byref(self.cfg), int(s), _dp(Un), _dp(Us), float(dt), _dp(out),
                              _ip(order), counts.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)))
         return out, order, counts, it
+
+    def stage_coef(self, B, Us, dt, a, b, cf):
+        """General SSP-RK stage: U_out = a B + b U*, U* = Us - (cf dt) F(Us), with the
+        full MOOD loop on U*.  Returns (Uout, order, counts, iters)."""
+        B, Us = self._arr(B), self._arr(Us)
+        out = np.empty_like(Us)
+        order = np.empty((self.ny, self.nx), dtype=np.int32)
+        counts = np.zeros(len(self.cascade), dtype=np.int64)
+        it = lib().orc_stage_coef(ctypes.byref(self.cfg), _dp(B), _dp(Us), float(dt), float(a), float(b),
+                                  float(cf), _dp(out), _ip(order),
+                                  counts.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)))
+        return out, order, counts, it
+
+    def rk4_step(self, U, dt):
+        """One step of the five-stage SSP-RK4 of eqs. (rk4) and (rk4_substeps),
+        every stage with its own MOOD loop (rk4_stages).  Returns (U_next, iters)."""
+        U = self._arr(U)
+        st = rk4_stages()
+        Ui = U
+        keep = {}
+        iters = []
+        for i, (a, b, cf) in enumerate(st["sub"]):
+            Ui, _, _, it = self.stage_coef(U, Ui, dt, a, b, cf)
+            keep[i + 1] = Ui
+            iters.append(it)
+        k2, k3, k4, kn = st["w"]
+        W = k2 * keep[2] + k3 * keep[3] + k4 * keep[4] + kn * U
+        a, b, cf = st["last"]
+        Un1, _, _, it = self.stage_coef(W, keep[4], dt, a, b, cf)
+        iters.append(it)
+        return Un1, iters
 
     def stage_forced(self, s, Un, Us, dt, order):
         Un, Us = self._arr(Un), self._arr(Us)

@@ -330,11 +330,13 @@ static void combine(const orc_cfg *c, int s, const double *Un, const double *Ust
 }
 
 /* --------------------------------------------------------------- stage */
-/* One SSP-RK3 stage with the full MOOD loop.
-   order_out: final radius per cell; counts[l]: cells ending at level l;
-   returns the number of MOOD iterations (candidate evaluations). */
-int orc_stage(const orc_cfg *c, int s, const double *Un, const double *Us, double dt,
-              double *Uout, int *order_out, long long *counts)
+/* The MOOD loop of one stage (Sec. "Step-by-step GP-MOOD algorithm"): the
+   candidate U* = Us - dt F(Us) at the top order, detection, lowering of the
+   troubled cells to the next scheme of the cascade, until no cell is troubled.
+   order_out: final radius per cell; counts[l]: cells ending at level l; returns
+   the number of MOOD iterations (candidate evaluations). */
+static int mood_loop(const orc_cfg *c, const double *Us, double dt, double *Ustar, int *order_out,
+                     long long *counts)
 {
     int nx = c->nx, ny = c->ny;
     size_t ncell = (size_t)nx * ny;
@@ -347,7 +349,6 @@ int orc_stage(const orc_cfg *c, int s, const double *Un, const double *Us, doubl
 
     int *order = (int *)malloc(sizeof(int) * ncell);
     for (size_t k = 0; k < ncell; ++k) order[k] = c->rad[0]; /* every stage starts at the top order */
-    double *Ustar = (double *)malloc(sizeof(double) * NV * ncell);
     int *rsbad = (int *)malloc(sizeof(int) * ncell);
     int *trouble = (int *)malloc(sizeof(int) * ncell);
     int iters = 0;
@@ -366,14 +367,40 @@ int orc_stage(const orc_cfg *c, int s, const double *Un, const double *Us, doubl
         for (size_t k = 0; k < ncell; ++k)
             if (trouble[k]) order[k] = c->rad[level_of(c, order[k]) + 1]; /* next scheme in the cascade */
     }
-    combine(c, s, Un, Ustar, Uout);
     if (counts)
         for (int l = 0; l < c->nlev; ++l) counts[l] = 0;
     for (size_t k = 0; k < ncell; ++k) {
         if (order_out) order_out[k] = order[k];
         if (counts) counts[level_of(c, order[k])]++;
     }
-    free(order); free(Ustar); free(rsbad); free(trouble); free(rx); free(g.u);
+    free(order); free(rsbad); free(trouble); free(rx); free(g.u);
+    return iters;
+}
+
+/* One SSP-RK3 stage (eq. (rk3)) with the full MOOD loop. */
+int orc_stage(const orc_cfg *c, int s, const double *Un, const double *Us, double dt,
+              double *Uout, int *order_out, long long *counts)
+{
+    double *Ustar = (double *)malloc(sizeof(double) * NV * c->nx * c->ny);
+    int iters = mood_loop(c, Us, dt, Ustar, order_out, counts);
+    combine(c, s, Un, Ustar, Uout);
+    free(Ustar);
+    return iters;
+}
+
+/* A stage of an explicit SSP-RK method in the form
+       U_out = a B + b U*,   U* = Us - (cf dt) F(Us),
+   with the full MOOD loop on U* (every sub-step of eqs. (rk4_substeps) and the
+   last combination of eq. (rk4) can be written so, B being U^n or an already
+   formed linear combination).  a = 0 takes U_out = b U*. */
+int orc_stage_coef(const orc_cfg *c, const double *B, const double *Us, double dt, double a, double b, double cf,
+                   double *Uout, int *order_out, long long *counts)
+{
+    size_t n = (size_t)NV * c->nx * c->ny;
+    double *Ustar = (double *)malloc(sizeof(double) * n);
+    int iters = mood_loop(c, Us, cf * dt, Ustar, order_out, counts);
+    for (size_t k = 0; k < n; ++k) Uout[k] = (a == 0.0 ? 0.0 : a * B[k]) + b * Ustar[k];
+    free(Ustar);
     return iters;
 }
 
