@@ -148,6 +148,25 @@ gpm_status gpm_set_dt(gpm_ctx *ctx, double dt);
    GPM_ENOTCONV (pass limit). */
 gpm_status gpm_stage_dev(gpm_ctx *ctx, int s, const void *U_n, const void *U_s, void *U_out);
 
+/* A general stage of an explicit SSP-RK method in Shu-Osher form (Sec. "Time
+   integration": every sub-step of the five-stage SSP-RK4, eq. (rk4_substeps),
+   and its last combination, eq. (rk4), take this form):
+       U_out = a B + b U*,   U* = U_s - (cf dt) F(U_s),
+   with the MOOD loop run to completion on U* (the same detection and cascade as
+   gpm_stage_dev); dt is the context's device dt (gpm_set_dt, gpm_compute_dt*).
+   B, U_s, U_out: device buffers of 4*nx*ny elements of the context's precision;
+   B is not read when a = 0 and may then be NULL; U_out must not alias U_s.
+   Errors: GPM_ESTATE, GPM_EINVAL (pointers, cf <= 0, non-finite a, b or cf),
+   GPM_ENOTCONV. */
+gpm_status gpm_stage_coef(gpm_ctx *ctx, const void *B, const void *U_s, void *U_out, double a, double b,
+                          double cf);
+
+/* out = w0 X0 + w1 X1 + w2 X2 + w3 X3 on device buffers of 4*nx*ny elements of
+   the context's precision, element by element, evaluated left to right (the
+   state combination W of the last SSP-RK4 stage).  out may alias an input. */
+gpm_status gpm_lincomb4(gpm_ctx *ctx, void *out, const void *X0, double w0, const void *X1, double w1,
+                        const void *X2, double w2, const void *X3, double w3);
+
 /* nsteps full steps on the bound slots: dt from the current state (cfl > 0) or
    the device dt set by gpm_set_dt (cfl <= 0), then stages 0, 1, 2. */
 gpm_status gpm_step(gpm_ctx *ctx, double cfl, int nsteps);

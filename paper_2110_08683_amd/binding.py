@@ -24,6 +24,7 @@ GPM_FLAGS_ALL = 15
 # every symbol include/gpmood.h declares
 EXPORTS = ("gpm_create", "gpm_set_scheme", "gpm_workspace_size", "gpm_bind", "gpm_state_ptr",
            "gpm_init_state", "gpm_get_state", "gpm_compute_dt", "gpm_compute_dt_dev", "gpm_set_dt", "gpm_stage_dev",
+           "gpm_stage_coef", "gpm_lincomb4",
            "gpm_step", "gpm_troubled_counts", "gpm_get_order_mask", "gpm_totals", "gpm_totals_dev",
            "gpm_set_tuning", "gpm_instrument", "gpm_instrument_read", "gpm_order_ptr", "gpm_stage_vjp",
            "gpm_batch_create",
@@ -76,6 +77,9 @@ def lib():
         "gpm_compute_dt_dev": ([ctxp, vp, ctypes.c_double, dp], st),
         "gpm_set_dt": ([ctxp, ctypes.c_double], st),
         "gpm_stage_dev": ([ctxp, ctypes.c_int, vp, vp, vp], st),
+        "gpm_stage_coef": ([ctxp, vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double], st),
+        "gpm_lincomb4": ([ctxp, vp, vp, ctypes.c_double, vp, ctypes.c_double, vp, ctypes.c_double, vp,
+                          ctypes.c_double], st),
         "gpm_step": ([ctxp, ctypes.c_double, ctypes.c_int], st),
         "gpm_troubled_counts": ([ctxp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_int)], st),
         "gpm_get_order_mask": ([ctxp, ctypes.POINTER(ctypes.c_ubyte)], st),
@@ -244,6 +248,24 @@ class GPMood:
             assert t.dtype == self.dtype and t.is_contiguous() and t.numel() == 4 * self.nx * self.ny
         self._check(lib().gpm_stage_dev(self.ctx, int(s), ctypes.c_void_p(Un.data_ptr()),
                                         ctypes.c_void_p(Us.data_ptr()), ctypes.c_void_p(Uout.data_ptr())))
+
+    def gpm_stage_coef(self, B, Us, Uout, a, b, cf):
+        """General SSP-RK stage Uout = a B + b (Us - cf dt F(Us)) with the MOOD loop
+        (B may be None when a == 0); torch tensors (4, ny, nx) on the device."""
+        for t in (Us, Uout) + ((B,) if B is not None else ()):
+            assert t.dtype == self.dtype and t.is_contiguous() and t.numel() == 4 * self.nx * self.ny
+        self._check(lib().gpm_stage_coef(self.ctx, ctypes.c_void_p(B.data_ptr() if B is not None else 0),
+                                         ctypes.c_void_p(Us.data_ptr()), ctypes.c_void_p(Uout.data_ptr()),
+                                         float(a), float(b), float(cf)))
+
+    def gpm_lincomb4(self, out, X0, w0, X1, w1, X2, w2, X3, w3):
+        """out = w0 X0 + w1 X1 + w2 X2 + w3 X3 (device tensors, left to right)."""
+        for t in (out, X0, X1, X2, X3):
+            assert t.dtype == self.dtype and t.is_contiguous() and t.numel() == 4 * self.nx * self.ny
+        self._check(lib().gpm_lincomb4(self.ctx, ctypes.c_void_p(out.data_ptr()),
+                                       ctypes.c_void_p(X0.data_ptr()), float(w0), ctypes.c_void_p(X1.data_ptr()),
+                                       float(w1), ctypes.c_void_p(X2.data_ptr()), float(w2),
+                                       ctypes.c_void_p(X3.data_ptr()), float(w3)))
 
     def gpm_step(self, cfl=0.8, nsteps=1):
         self._check(lib().gpm_step(self.ctx, float(cfl), int(nsteps)))

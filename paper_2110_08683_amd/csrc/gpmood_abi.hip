@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -304,11 +305,17 @@ gpm_status gpm_set_tuning(gpm_ctx *c, int passes_per_check, int rows_per_wave, i
 }  // extern "C"
 
 template <typename real>
-static gpm_status run_stage(gpm_ctx *c, const Weights<real> &W, int s, const void *Un, const void *Us, void *Uout)
+static gpm_status run_stage(gpm_ctx *c, const Weights<real> &W, int s, const void *Un, const void *Us, void *Uout,
+                           double ca = 0.0, double cb = 1.0, double dtf = 1.0)
 {
     StageArgs<real> A;
     fill_args(c, W, A);
     A.s = s;
+    if (s == 3) {
+        A.ca = (real)ca;
+        A.cb = (real)cb;
+        A.dtf = dtf;
+    }
     A.Un = (const real *)Un;
     A.Us = (const real *)Us;
     A.Uout = (real *)Uout;
@@ -407,6 +414,38 @@ static gpm_status run_stage(gpm_ctx *c, const Weights<real> &W, int s, const voi
 }
 
 extern "C" {
+
+gpm_status gpm_stage_coef(gpm_ctx *c, const void *B, const void *Us, void *Uout, double a, double b, double cf)
+{
+    if (!c) return GPM_EINVAL;
+    if (!c->have_scheme) return fail(c, GPM_ESTATE, "no scheme set");
+    if (!c->state) return fail(c, GPM_ESTATE, "not bound");
+    if (!Us || !Uout || (a != 0.0 && !B) || !(cf > 0.0) || !std::isfinite(a) || !std::isfinite(b) ||
+        !std::isfinite(cf))
+        return fail(c, GPM_EINVAL, "bad stage arguments");
+    if (Uout == Us) return fail(c, GPM_EINVAL, "U_out must not alias U_s");
+    const void *Bp = B ? B : Us;  // not read when a == 0
+    return c->prec == GPM_F64 ? run_stage<double>(c, c->w64, 3, Bp, Us, Uout, a, b, cf)
+                              : run_stage<float>(c, c->w32, 3, Bp, Us, Uout, a, b, cf);
+}
+
+gpm_status gpm_lincomb4(gpm_ctx *c, void *out, const void *x0, double w0, const void *x1, double w1, const void *x2,
+                        double w2, const void *x3, double w3)
+{
+    if (!c) return GPM_EINVAL;
+    if (!c->state) return fail(c, GPM_ESTATE, "not bound");
+    if (!out || !x0 || !x1 || !x2 || !x3) return fail(c, GPM_EINVAL, "null array");
+    const size_t n = 4 * c->ncell;
+    const hipError_t e = c->prec == GPM_F64
+                             ? launch_lincomb4<double>((double *)out, (const double *)x0, (const double *)x1,
+                                                       (const double *)x2, (const double *)x3, w0, w1, w2, w3, n,
+                                                       c->stream)
+                             : launch_lincomb4<float>((float *)out, (const float *)x0, (const float *)x1,
+                                                      (const float *)x2, (const float *)x3, w0, w1, w2, w3, n,
+                                                      c->stream);
+    if (e != hipSuccess) return fail(c, GPM_EHIP, hipGetErrorString(e));
+    return GPM_OK;
+}
 
 gpm_status gpm_stage_dev(gpm_ctx *c, int s, const void *Un, const void *Us, void *Uout)
 {

@@ -154,6 +154,9 @@ static inline void fill_args(const gpm_ctx *c, const Weights<real> &W, StageArgs
     A.bcy = c->grid.bc[1];
     A.rows = c->rows;
     A.top = c->top;
+    A.dtf = 1.0;
+    A.ca = real(0);
+    A.cb = real(1);
     A.iso = weights_isotropic(W, c->top);
     A.flags = c->scheme.flags;
     A.dx = (real)c->dx;

@@ -57,7 +57,7 @@ struct StageArgs {
     unsigned *cstamp;     // claim stamps of cells [nx*ny] and faces [NFX + NFY]
     unsigned *fstamp;
     int nx, ny, bcx, bcy;
-    int s;                // RK stage 0..2
+    int s;                // RK stage 0..2 of eq. (rk3); 3: general stage (ca, cb, dtf)
     int rows;             // rows per wavefront march (first pass)
     int top;              // top radius
     int iso;              // 1: the y weights are exactly the transposed x weights
@@ -65,6 +65,10 @@ struct StageArgs {
     int next[4];          // next radius of the cascade after radius r
     real dx, dy, gamma, sigma_v, sigma_p, plat_thr, delta;
     double dx64, dy64, gamma64;  // the same in FP64 (the dt reduction)
+    // general stage (s == 3): U_out = ca B + cb U*, U* = U_s - (dtf dt) F(U_s), B
+    // passed as Un; dtf = 1 for the stages of eq. (rk3)
+    double dtf;
+    real ca, cb;
     Weights<real> W;
     const real *gtab;     // compact cascade weights, kGtabSize values (device)
     const real *gtab_dl;  // their derivative with respect to ell (same layout, no Gauss weights)
@@ -325,12 +329,14 @@ __device__ __forceinline__ void hllc(real g, const real *UL, const real *UR, rea
 }
 
 // Stage combination of eq. (rk3): U^(1) = U*, hat U^(2) = (3 U^n + U*)/4,
-// U^(n+1) = (U^n + 2 U*)/3.
+// U^(n+1) = (U^n + 2 U*)/3; s == 3: the general stage ca B + cb U* (ca = 0
+// ignores B), un holding B.
 template <typename real>
-__device__ __forceinline__ real combine(int s, real un, real ust)
+__device__ __forceinline__ real combine(int s, real un, real ust, real ca = real(0), real cb = real(1))
 {
     if (s == 0) return ust;
     if (s == 1) return real(0.25) * (real(3) * un + ust);
+    if (s == 3) return (ca == real(0) ? real(0) : ca * un) + cb * ust;
     return dv(un + real(2) * ust, real(3));
 }
 

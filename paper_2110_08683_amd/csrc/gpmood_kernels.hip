@@ -163,7 +163,7 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
     }
     wave_lds_sync();
 
-    const real dt = (real)(*A.dt);
+    const real dt = (real)(*A.dt * A.dtf);
     const real g = A.gamma;
     real sypP[q][4];   // y+ states of row j-1
     real Gprev[4];     // flux through face j-3/2
@@ -264,7 +264,7 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const real un = A.s == 0 ? real(0) : A.Un[v * plane + c];
-                        A.Uout[v * plane + c] = combine(A.s, un, ust[v]);
+                        A.Uout[v * plane + c] = combine(A.s, un, ust[v], A.ca, A.cb);
                     }
                     A.order[c] = (uint8_t)(tr ? A.next[RT] : RT);
                 }
@@ -615,7 +615,7 @@ __device__ __forceinline__ bool cell_finish(const StageArgs<real> &A, const Cell
     };
     const bool tr = troubled(A, X.o, ust, rs, nb);
 #pragma unroll
-    for (int w = 0; w < 4; ++w) A.Uout[w * plane + X.c] = combine(A.s, X.un[w], ust[w]);
+    for (int w = 0; w < 4; ++w) A.Uout[w * plane + X.c] = combine(A.s, X.un[w], ust[w], A.ca, A.cb);
     if (tr) A.order[X.c] = (uint8_t)A.next[X.o];
     return tr;
 }
@@ -625,7 +625,7 @@ __device__ __forceinline__ void cells_phase(const StageArgs<real> &A, const int 
                                             const PassOut &P, int pre = 0, bool use_pre = false)
 {
     const int nround = (n + stride - 1) / stride;
-    const real dt = (real)(*A.dt);
+    const real dt = (real)(*A.dt * A.dtf);
     for (int r = 0; r < nround; ++r) {
         const int idx = r * stride + t0;
         const bool valid = idx < n;
@@ -783,7 +783,7 @@ __device__ __forceinline__ void tail_body(const StageArgs<real> &A, const Cascad
             __syncthreads();
             if (cellwave) {
                 bool tr = false;
-                if (valid) tr = cell_finish(A, X, (real)(*A.dt));
+                if (valid) tr = cell_finish(A, X, (real)(*A.dt * A.dtf));
                 wave_count(tr, P.tcount);
                 claim_after_lowering(A, P, X.i, X.j, tr);
             }
@@ -931,6 +931,15 @@ __global__ void k_dt_set(Ctl *ctl, double dt, int clear_lambda)
 {
     if (clear_lambda) ctl->lam_bits = 0ull;
     else ctl->dt = dt;
+}
+
+// out = w0 x0 + w1 x1 + w2 x2 + w3 x3, evaluated left to right, element by element.
+template <typename real>
+__global__ __launch_bounds__(256) void k_lincomb4(real *out, const real *x0, const real *x1, const real *x2,
+                                                  const real *x3, real w0, real w1, real w2, real w3, size_t n)
+{
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+        out[k] = ((w0 * x0[k] + w1 * x1[k]) + w2 * x2[k]) + w3 * x3[k];
 }
 
 // Compensated totals: per-block double-double partial sums in a fixed order.
@@ -1243,6 +1252,17 @@ hipError_t launch_level_hist(const uint8_t *order, size_t ncell, const LevIdx &l
 }
 
 template <typename real>
+hipError_t launch_lincomb4(real *out, const real *x0, const real *x1, const real *x2, const real *x3, double w0,
+                           double w1, double w2, double w3, size_t n, hipStream_t st)
+{
+    size_t nb = (n + 255) / 256;
+    if (nb > 8192) nb = 8192;
+    hipLaunchKernelGGL(k_lincomb4<real>, dim3((unsigned)nb), dim3(256), 0, st, out, x0, x1, x2, x3, (real)w0,
+                       (real)w1, (real)w2, (real)w3, n);
+    return hipGetLastError();
+}
+
+template <typename real>
 hipError_t launch_dt(const real *U, size_t ncell, double gamma, double dx, double dy, double cfl, Ctl *ctl,
                      hipStream_t st)
 {
@@ -1285,6 +1305,10 @@ template hipError_t launch_cascade_pass<double>(const StageArgs<double> &, const
 template hipError_t launch_cascade_tail<float>(const StageArgs<float> &, const Cascade &, int, int, int, hipStream_t);
 template hipError_t launch_cascade_tail<double>(const StageArgs<double> &, const Cascade &, int, int, int,
                                                 hipStream_t);
+template hipError_t launch_lincomb4<float>(float *, const float *, const float *, const float *, const float *,
+                                           double, double, double, double, size_t, hipStream_t);
+template hipError_t launch_lincomb4<double>(double *, const double *, const double *, const double *,
+                                            const double *, double, double, double, double, size_t, hipStream_t);
 template hipError_t launch_dt<float>(const float *, size_t, double, double, double, double, Ctl *, hipStream_t);
 template hipError_t launch_dt<double>(const double *, size_t, double, double, double, double, Ctl *, hipStream_t);
 template hipError_t launch_totals<float>(const float *, size_t, double, double *, int, Ctl *, hipStream_t);

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "gpmood.h")).read()
-    return set(re.findall(r"^\S.*?\b(gpm3?_[a-z_]+)\s*\(", src, flags=re.M))
+    return set(re.findall(r"^\S.*?\b(gpm3?_[a-z_0-9]+)\s*\(", src, flags=re.M))
 
 
 def test_header_names_match_binding():

@@ -1,0 +1,124 @@
+"""GPU tests of the five-stage SSP-RK4 (eqs. (rk4), (rk4_substeps); driver
+paper_2110_08683_amd.rk4 over gpm_stage_coef and gpm_lincomb4).
+
+1. Parity with the oracle's RK4 (FP64, MOOD loop in every stage): whole steps
+   within 1e-12 relative L1, on the smooth vortex and on four-quadrant shocks where
+   the cascade runs in the stages.
+2. The paper's convergence table for the isentropic vortex (Table
+   "convergence-gp-mood-diamond"; values in tests/golden/): GP-MOOD7 (7->3->1) and
+   GP-MOOD5 (5->3->1) with SSP-RK4, GP-MOOD3 (3->1) with SSP-RK3, on [0,20]^2 with
+   ell = 1 up to t = 20.  Time step: CFL 0.8 on the 50^2 initial state, scaled by
+   (50/N)^((2R+1)/4) for SSP-RK4 and by 50/N for SSP-RK3 (the reading of the
+   reduced step of the section), rounded down to an integer number of steps.
+   Every L1 error within 1% of the printed value."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import gpmood_inputs as gi
+import oracle
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _note(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rel_l1(a, b):
+    return np.array([np.abs(a[v] - b[v]).sum() / np.abs(b[v]).sum() for v in range(4)])
+
+
+@pytest.mark.parametrize("case", ["vortex", "quadrants"])
+def test_rk4_steps_match_oracle_fp64(torch_cuda, case):
+    from paper_2110_08683_amd import GPMood, rk4
+    torch = torch_cuda
+    n = 48
+    _note(f"rk4 parity {case} {n}x{n}")
+    if case == "vortex":
+        U0 = gi.vortex(n, n, hi=(10.0, 10.0))
+        kw = dict(hi=(10.0, 10.0), bc=(0, 0), cascade=(3, 1, 0))
+    else:
+        U0 = gi.quadrants(n, n, seed=4)
+        kw = dict(bc=(1, 1), cascade=(3, 2, 1, 0))
+    o = oracle.Oracle(n, n, **kw)
+    g = GPMood(n, n, prec="f64", device="cuda:0", **kw)
+    U = torch.from_numpy(U0).cuda().contiguous()
+    Uo = U0
+    lowered = 0
+    for _ in range(3):
+        dt = o.dt(Uo, 0.6)
+        U = rk4.step(g, U, dt)
+        Uo, iters = o.rk4_step(Uo, dt)
+        lowered += sum(i - 1 for i in iters)
+    err = _rel_l1(U.cpu().numpy(), Uo)
+    _note(f"  rel L1 {err}  cascade passes {lowered}")
+    assert np.all(err <= 1e-12), err
+    if case == "quadrants":
+        assert lowered > 0  # the cascade ran inside the RK4 stages
+    g.close()
+
+
+def _table():
+    rows = [l.split() for l in open(os.path.join(HERE, "golden", "convergence_gp_mood_diamond.txt"))
+            if l.strip() and not l.startswith("#")]
+    return {int(r[0]): tuple(float(x) for x in r[1:]) for r in rows}
+
+
+def _vortex_l1(torch, N, cascade, method, dt50):
+    from paper_2110_08683_amd import GPMood, rk4
+    L = 20.0
+    U0 = gi.vortex(N, N, lo=(0.0, 0.0), hi=(L, L))
+    g = GPMood(N, N, lo=(0.0, 0.0), hi=(L, L), bc=(0, 0), prec="f64", cascade=cascade, ell=1.0, device="cuda:0")
+    p = (2 * cascade[0] + 1) / 4.0 if method == "rk4" else 1.0
+    nst = int(math.ceil(20.0 / (dt50 * (50.0 / N) ** p)))
+    dt = 20.0 / nst
+    U = torch.from_numpy(U0).cuda().contiguous()
+    for _ in range(nst):
+        if method == "rk4":
+            U = rk4.step(g, U, dt)
+        else:
+            g.gpm_set_dt(dt)
+            U1, U2, U3 = torch.empty_like(U), torch.empty_like(U), torch.empty_like(U)
+            g.gpm_stage_dev(0, U, U, U1)
+            g.gpm_stage_dev(1, U, U1, U2)
+            g.gpm_stage_dev(2, U, U2, U3)
+            U = U3
+    e = float(np.abs(U.cpu().numpy()[0] - U0[0]).sum() * (L / N) ** 2)
+    g.close()
+    return e
+
+
+@pytest.mark.parametrize("col,cascade,method", [(2, (3, 1, 0), "rk4"), (1, (2, 1, 0), "rk4"), (0, (1, 0), "rk3")])
+def test_paper_vortex_convergence_table(torch_cuda, col, cascade, method):
+    from paper_2110_08683_amd import GPMood
+    torch = torch_cuda
+    L = 20.0
+    g = GPMood(50, 50, lo=(0.0, 0.0), hi=(L, L), bc=(0, 0), prec="f64", cascade=(3, 2, 1, 0), ell=1.0,
+               device="cuda:0")
+    g.gpm_init_state(gi.vortex(50, 50, lo=(0.0, 0.0), hi=(L, L)))
+    dt50 = g.gpm_compute_dt(0.8)
+    g.close()
+    table = _table()
+    errs = []
+    for N in (50, 100, 200, 400):
+        e = _vortex_l1(torch, N, cascade, method, dt50)
+        paper = table[N][col]
+        _note(f"GP-MOOD{2 * cascade[0] + 1} {method} N={N}: L1 {e:.6e}  paper {paper:.6e}  ratio {e / paper:.4f}")
+        errs.append(e)
+        assert abs(e / paper - 1.0) < 0.01, (N, e, paper)
+    eoc = [math.log(errs[i] / errs[i + 1], 2) for i in range(3)]
+    _note(f"  EOC {eoc}")
