@@ -140,7 +140,9 @@ class Oracle:
     """2D GP-MOOD oracle on a uniform grid [lo, hi] with nx-by-ny cells.
 
     bc: (bcx, bcy), 0 periodic / 1 outflow.  cascade: radii, strictly decreasing,
-    ending in 0 (FOG).  ell: physical GP length scale.
+    ending in 0 (FOG).  ell: physical GP length scale.  shape: "diamond" (the
+    blocky diamond), "cross" (the cross-shaped stencils of Sec. "Isentropic
+    vortex") or "poly3" (POL-MOOD3: radius 1 with the polynomial weights).
     """
 
     def __init__(self, nx, ny, lo=(0.0, 0.0), hi=(1.0, 1.0), bc=(0, 0), cascade=(3, 2, 1, 0),
@@ -159,9 +161,15 @@ class Oracle:
         c.bcx, c.bcy = int(bc[0]), int(bc[1])
         c.gamma = gamma
         c.nlev = len(cascade)
+        if shape == "poly3" and max(cascade) > 1:
+            raise ValueError("POL-MOOD3 has radius 1 (then FOG) only")
         for l, R in enumerate(cascade):
-            st = np.array(weights_mp.stencil(R, shape), dtype=np.int32).reshape(-1)
-            z = np.array(weights_mp.weights(R, ax, ay, shape), dtype=np.float64).reshape(-1)
+            if shape == "poly3" and R == 1:
+                st = np.array(weights_mp.stencil(1), dtype=np.int32).reshape(-1)
+                z = np.array(weights_mp.poly3_weights(), dtype=np.float64).reshape(-1)
+            else:
+                st = np.array(weights_mp.stencil(R, shape), dtype=np.int32).reshape(-1)
+                z = np.array(weights_mp.weights(R, ax, ay, shape), dtype=np.float64).reshape(-1)
             q = weights_mp.nq(R)
             _, qw = weights_mp.gauss_rule_float(q)
             qw = np.array(qw, dtype=np.float64)

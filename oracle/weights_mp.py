@@ -195,6 +195,44 @@ def weights(R, ax, ay=None, shape="diamond", as_float=True):
     return z
 
 
+def poly3_weights(as_float=True):
+    """POL-MOOD3 (Sec. "POL-MOOD3", eqs. (poly3), (p3_coeffs)): point values of the
+    quadratic p3(x, y) = a0 + a1 x + a2 x^2 + a3 y + a4 y^2 whose cell averages
+    match the five cells of the radius-1 stencil, in the layout of weights(1, ...)
+    (faces x-, x+, y-, y+; 2-point rule; stencil order stencil(1)).  Along the
+    face's normal the 1D quadratic gives -1/6, 5/6, 1/3; along the face only the
+    linear term survives at the Gauss nodes (x*^2 = 1/12 cancels the average of
+    the quadratic), so the two tangential neighbours weigh +-x*/2."""
+    _ctx()
+    g, _ = gauss_rule(2)
+    st = stencil(1)
+    out = []
+    for f in range(4):
+        rows = []
+        for gk in g:
+            xs, ys = face_point(f, gk)
+            w = {}
+            if f < 2:  # x faces: normal along x, tangential along y
+                s = 1 if xs > 0 else -1
+                w[(0, 0)] = mp.mpf(5) / 6
+                w[(s, 0)] = mp.mpf(1) / 3
+                w[(-s, 0)] = -mp.mpf(1) / 6
+                w[(0, 1)] = ys / 2
+                w[(0, -1)] = -ys / 2
+            else:
+                s = 1 if ys > 0 else -1
+                w[(0, 0)] = mp.mpf(5) / 6
+                w[(0, s)] = mp.mpf(1) / 3
+                w[(0, -s)] = -mp.mpf(1) / 6
+                w[(1, 0)] = xs / 2
+                w[(-1, 0)] = -xs / 2
+            rows.append([w[o] for o in st])
+        out.append(rows)
+    if as_float:
+        return [[[float(v) for v in row] for row in face] for face in out]
+    return out
+
+
 def raw_weight_sum(R, ax, ay=None, face=1, point=0):
     """Sum of the un-normalised z = C^{-1} t (for the normalisation pin)."""
     _ctx()

@@ -207,3 +207,54 @@ def test_second_derivative_weights():
         assert abs(sum(wm * v for wm, v in zip(w[0], avg_y2))) < 1e-3
         assert abs(sum(wm * v for wm, v in zip(w[1], avg_y2)) - 2.0) < 1e-3
         assert abs(sum(w[0])) < 1e-3 and abs(sum(w[1])) < 1e-3
+
+
+def test_poly3_closed_form_weights():
+    """The oracle's POL-MOOD3 weights (eqs. (poly3), (p3_coeffs)) equal the printed
+    x+ face values, are the mirror images on the other faces, sum to 1, and are the
+    flat-kernel limit of the GP-R1 weights on every face."""
+    r = 1.0 / (4.0 * math.sqrt(3.0))
+    gold = {}
+    for line in open(os.path.join(GOLD, "poly3_weights.txt")):
+        line = line.split("#")[0].strip()
+        if line.startswith("g"):
+            k, vals = line.split(":")
+            gold[k] = np.array([float(eval(v.replace("r", repr(r)))) for v in vals.split()])
+    P = np.array(W.poly3_weights())
+    g, _ = W.gauss_rule(2)
+    first_is_plus = float(g[0]) > 0
+    np.testing.assert_allclose(P[1][0], gold["g1"] if first_is_plus else gold["g2"], atol=1e-15)
+    np.testing.assert_allclose(P[1][1], gold["g2"] if first_is_plus else gold["g1"], atol=1e-15)
+    np.testing.assert_allclose(P.sum(axis=2), 1.0, atol=1e-15)
+    flat = np.array(W.weights(1, 3000.0))
+    assert np.abs(flat - P).max() < 1e-6
+
+
+def test_cross_stencils():
+    """Cross-shaped stencils (Sec. "Isentropic vortex"): 5 / 9 / 13 cells on the
+    axes; radius 1 equals the diamond; weights normalised; in the flat limit the
+    radius-2 cross reproduces the face average of x^k on its axis (k <= 4) but not
+    of the mixed monomial x y, which the diamond reproduces."""
+    for R, n in ((1, 5), (2, 9), (3, 13)):
+        st = W.stencil(R, "cross")
+        assert len(st) == n and all(a == 0 or b == 0 for a, b in st)
+    np.testing.assert_allclose(np.array(W.weights(1, 12.0, shape="cross")), np.array(W.weights(1, 12.0)),
+                               rtol=0, atol=0)
+    zc = np.array(W.weights(2, 12.0, shape="cross"))
+    np.testing.assert_allclose(zc.sum(axis=2), 1.0, atol=1e-13)
+    # flat limit: cell averages of x^k on the x+ face at its Gauss nodes
+    a = 400.0
+    for shape, mixed_ok in (("cross", False), ("diamond", True)):
+        st = W.stencil(2, shape)
+        z = np.array(W.weights(2, a, shape=shape))
+        g, _ = W.gauss_rule(3)
+
+        def avg(c, k):
+            return ((c + 0.5) ** (k + 1) - (c - 0.5) ** (k + 1)) / (k + 1)
+        for k in range(5):
+            cav = np.array([avg(di, k) * avg(dj, 0) for di, dj in st])
+            for q in range(3):
+                assert abs(z[1][q] @ cav - 0.5 ** k) < 1e-3
+        cav = np.array([avg(di, 1) * avg(dj, 1) for di, dj in st])
+        errs = [abs(z[1][q] @ cav - 0.5 * float(g[q])) for q in range(3)]
+        assert (max(errs) < 1e-3) == mixed_ok
