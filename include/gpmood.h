@@ -81,7 +81,15 @@ typedef struct {
     double ell;
     double sigma_v, sigma_p; /* CSD thresholds (paper: 5, 5) */
     unsigned flags;          /* GPM_* detection switches */
+    int stencil;             /* GPM_STENCIL_*; 2D only (the 3D engine takes DIAMOND) */
 } gpm_scheme;
+
+/* Stencil of the GP levels (gpm_scheme.stencil): the blocky diamond (Sec. "The GP
+   stencil"); the cross-shaped stencils of the convergence study (Sec. "Isentropic
+   vortex": the diamond's cells on the axes, 5 / 9 / 13 cells); POL-MOOD3 (Sec.
+   "POL-MOOD3": radius 1 with the polynomial weights of eqs. (poly3),
+   (p3_coeffs); cascade {1, 0} only). */
+enum { GPM_STENCIL_DIAMOND = 0, GPM_STENCIL_CROSS = 1, GPM_STENCIL_POLY3 = 2 };
 
 /* Create a context for a grid, a precision and a HIP stream (hipStream_t, may be
    NULL).  Allocates host memory only.  Errors: GPM_EINVAL (bad grid, gamma <= 1,

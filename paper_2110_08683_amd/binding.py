@@ -44,7 +44,11 @@ class gpm_grid(ctypes.Structure):
 
 class gpm_scheme(ctypes.Structure):
     _fields_ = [("nlev", ctypes.c_int), ("radius", ctypes.c_int * 4), ("ell", ctypes.c_double),
-                ("sigma_v", ctypes.c_double), ("sigma_p", ctypes.c_double), ("flags", ctypes.c_uint)]
+                ("sigma_v", ctypes.c_double), ("sigma_p", ctypes.c_double), ("flags", ctypes.c_uint),
+                ("stencil", ctypes.c_int)]
+
+
+GPM_STENCILS = {"diamond": 0, "cross": 1, "poly3": 2}
 
 
 class GpmError(RuntimeError):
@@ -143,7 +147,7 @@ class GPMood:
 
     def __init__(self, nx, ny, lo=(0.0, 0.0), hi=(1.0, 1.0), bc=(0, 0), prec="f64",
                  cascade=(3, 2, 1, 0), ell=None, gamma=1.4, sigma_v=5.0, sigma_p=5.0,
-                 flags=GPM_FLAGS_ALL, stream=None, device=None):
+                 flags=GPM_FLAGS_ALL, stream=None, device=None, stencil="diamond"):
         import torch
         L = lib()
         self.torch = torch
@@ -169,6 +173,7 @@ class GPMood:
             s.radius[k] = r
         s.ell = 0.0 if ell is None else float(ell)
         s.sigma_v, s.sigma_p, s.flags = sigma_v, sigma_p, flags
+        s.stencil = GPM_STENCILS[stencil]
         self._check(L.gpm_set_scheme(self.ctx, ctypes.byref(s)))
         dx, dy = (hi[0] - lo[0]) / self.nx, (hi[1] - lo[1]) / self.ny
         self.ell = 12.0 * min(dx, dy) if ell is None else float(ell)

@@ -122,16 +122,22 @@ int index_of(const std::vector<Cell> &st, int di, int dj)
 
 namespace {
 
-// Quarter-basis weights of radius R at (ax, ay) = ell / (dx, dy), in quad precision.
-int level_q(int R, qf ax, qf ay, qf W[2][2][25], qf qw[2])
+// Quarter-basis weights of radius R at (ax, ay) = ell / (dx, dy), in quad precision,
+// for the stencil shape (GPW_DIAMOND, GPW_CROSS: the cells of the diamond on the
+// axes; GPW_POLY3, radius 1 only: the POL-MOOD3 polynomial weights).  Cells
+// outside the stencil get weight 0.
+int level_q(int R, qf ax, qf ay, qf W[2][2][25], qf qw[2], int shape)
 {
-    std::vector<Cell> st = diamond(R);
+    std::vector<Cell> st;
+    for (const Cell &x : diamond(R))
+        if (shape == GPW_DIAMOND || x.di == 0 || x.dj == 0) st.push_back(x);
     const int n = (int)st.size();
     std::vector<qf> L(n * n);
     for (int m = 0; m < n; ++m)
         for (int k = 0; k < n; ++k)
             L[m * n + k] = c_factor((qf)(st[k].di - st[m].di), ax) * c_factor((qf)(st[k].dj - st[m].dj), ay);
-    if (!cholesky(L, n)) return -1;
+    if (shape != GPW_POLY3 && !cholesky(L, n)) return -1;
+    if (shape == GPW_POLY3 && R != 1) return -1;
     qf g[2];
     gauss_slots(R, g, qw);
     for (int dir = 0; dir < 2; ++dir)
@@ -140,12 +146,27 @@ int level_q(int R, qf ax, qf ay, qf W[2][2][25], qf qw[2])
             qf xs = dir == 0 ? (qf)0.5 : g[k];
             qf ys = dir == 0 ? g[k] : (qf)0.5;
             std::vector<qf> z(n);
-            for (int m = 0; m < n; ++m) z[m] = t_factor(xs - st[m].di, ax) * t_factor(ys - st[m].dj, ay);
-            chol_solve(L, n, z);
-            qf sum = 0;
-            for (int m = 0; m < n; ++m) sum += z[m];
-            for (int m = 0; m < n; ++m) z[m] /= sum;
-            auto Z = [&](int di, int dj) { return z[index_of(st, di, dj)]; };
+            if (shape == GPW_POLY3) {
+                // eqs. (poly3), (p3_coeffs): the quadratic matching the five cell
+                // averages; normal to the face -1/6, 5/6, 1/3, along the face the
+                // linear term only (the tangential node coordinate t: +-t/2)
+                const qf t = dir == 0 ? ys : xs;
+                for (int m = 0; m < n; ++m) {
+                    const int nrm = dir == 0 ? st[m].di : st[m].dj, tan = dir == 0 ? st[m].dj : st[m].di;
+                    z[m] = nrm == 0 && tan == 0 ? (qf)5 / 6
+                           : (nrm == 1 ? (qf)1 / 3 : (nrm == -1 ? -(qf)1 / 6 : (qf)tan * t / 2));
+                }
+            } else {
+                for (int m = 0; m < n; ++m) z[m] = t_factor(xs - st[m].di, ax) * t_factor(ys - st[m].dj, ay);
+                chol_solve(L, n, z);
+                qf sum = 0;
+                for (int m = 0; m < n; ++m) sum += z[m];
+                for (int m = 0; m < n; ++m) z[m] /= sum;
+            }
+            auto Z = [&](int di, int dj) {
+                const int m = index_of(st, di, dj);
+                return m < 0 ? (qf)0 : z[m];
+            };
             for (int e = 0; e < kNQ[R]; ++e) {
                 const int a = kQ[e].a, b = kQ[e].b, c = kQ[e].comp;
                 qf w;
@@ -170,13 +191,13 @@ int level_q(int R, qf ax, qf ay, qf W[2][2][25], qf qw[2])
 
 }  // namespace
 
-int gpw_level(int R, double ax_d, double ay_d, GpwLevel *out)
+int gpw_level(int R, double ax_d, double ay_d, int shape, GpwLevel *out)
 {
     std::memset(out, 0, sizeof(*out));
     out->R = R;
     if (R <= 0) return 0;
     qf W[2][2][25] = {}, qw[2] = {0, 0};
-    if (level_q(R, ax_d, ay_d, W, qw) != 0) return -1;
+    if (level_q(R, ax_d, ay_d, W, qw, shape) != 0) return -1;
     for (int k = 0; k < slots_of(R); ++k) {
         out->qw64[k] = (double)qw[k];
         out->qw32[k] = (float)qw[k];
@@ -192,8 +213,8 @@ int gpw_level(int R, double ax_d, double ay_d, GpwLevel *out)
     // rounding of the ill-conditioned solve (~1e-19 / h) below 1e-12
     const qf h = (qf)1 / 1000000;
     qf Wp[2][2][25] = {}, Wm[2][2][25] = {}, q2[2];
-    if (level_q(R, (qf)ax_d * (1 + h), (qf)ay_d * (1 + h), Wp, q2) != 0) return -1;
-    if (level_q(R, (qf)ax_d * (1 - h), (qf)ay_d * (1 - h), Wm, q2) != 0) return -1;
+    if (level_q(R, (qf)ax_d * (1 + h), (qf)ay_d * (1 + h), Wp, q2, shape) != 0) return -1;
+    if (level_q(R, (qf)ax_d * (1 - h), (qf)ay_d * (1 - h), Wm, q2, shape) != 0) return -1;
     for (int dir = 0; dir < 2; ++dir)
         for (int k = 0; k < slots_of(R); ++k)
             for (int e = 0; e < kNQ[R]; ++e) out->dlw64[dir][k][e] = (double)((Wp[dir][k][e] - Wm[dir][k][e]) / (2 * h));

@@ -48,7 +48,10 @@ struct Gpw3Curv {
 
 // ax = ell/dx, ay = ell/dy.  Returns 0, or -1 if the covariance matrix is not
 // numerically positive definite in quad precision.
-int gpw_level(int R, double ax, double ay, GpwLevel *out);
+// Stencil shapes of gpw_level: the blocky diamond, the cross (its cells on the
+// axes), and POL-MOOD3 (radius 1, polynomial weights).
+enum { GPW_DIAMOND = 0, GPW_CROSS = 1, GPW_POLY3 = 2 };
+int gpw_level(int R, double ax, double ay, int shape, GpwLevel *out);
 int gpw_curvature(double ax, double ay, double ell, GpwCurv *out);
 int gpw3_level(int R, double ax, double ay, double az, Gpw3Level *out);
 int gpw3_curvature(double ax, double ay, double az, double ell, Gpw3Curv *out);

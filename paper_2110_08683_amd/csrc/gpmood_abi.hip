@@ -90,6 +90,10 @@ gpm_status gpm_set_scheme(gpm_ctx *c, const gpm_scheme *s)
     if (s->radius[s->nlev - 1] != 0) return fail(c, GPM_EINVAL, "cascade must end at radius 0 (FOG)");
     if (s->radius[0] == 0) return fail(c, GPM_EINVAL, "top scheme must have radius >= 1");
     if (!(s->ell >= 0.0)) return fail(c, GPM_EINVAL, "ell must be >= 0");
+    if (s->stencil < GPM_STENCIL_DIAMOND || s->stencil > GPM_STENCIL_POLY3)
+        return fail(c, GPM_EINVAL, "unknown stencil");
+    if (s->stencil == GPM_STENCIL_POLY3 && s->radius[0] != 1)
+        return fail(c, GPM_EINVAL, "POL-MOOD3 has radius 1 (cascade {1, 0})");
     const double ell = s->ell > 0.0 ? s->ell : 12.0 * (c->dx < c->dy ? c->dx : c->dy);
     const double ax = ell / c->dx, ay = ell / c->dy;
     std::memset(&c->w64, 0, sizeof(c->w64));
@@ -109,7 +113,8 @@ gpm_status gpm_set_scheme(gpm_ctx *c, const gpm_scheme *s)
         for (int l = 0; l < s->nlev; ++l) used = used || s->radius[l] == R;
         if (!used) continue;
         GpwLevel L;
-        if (gpw_level(R, ax, ay, &L) != 0) return fail(c, GPM_EINVAL, "GP covariance matrix not positive definite");
+        const int shape = s->stencil == GPM_STENCIL_CROSS ? GPW_CROSS : (s->stencil == GPM_STENCIL_POLY3 ? GPW_POLY3 : GPW_DIAMOND);
+        if (gpw_level(R, ax, ay, shape, &L) != 0) return fail(c, GPM_EINVAL, "GP covariance matrix not positive definite");
         for (int d = 0; d < 2; ++d)
             for (int p = 0; p < slots_of(R); ++p)
                 for (int e = 0; e < kNQ[R]; ++e) {

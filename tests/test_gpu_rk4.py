@@ -4,8 +4,10 @@ paper_2110_08683_amd.rk4 over gpm_stage_coef and gpm_lincomb4).
 1. Parity with the oracle's RK4 (FP64, MOOD loop in every stage): whole steps
    within 1e-12 relative L1, on the smooth vortex and on four-quadrant shocks where
    the cascade runs in the stages.
-2. The paper's convergence table for the isentropic vortex (Table
-   "convergence-gp-mood-diamond"; values in tests/golden/): GP-MOOD7 (7->3->1) and
+2. The paper's convergence tables for the isentropic vortex (Tables
+   "convergence-gp-mood-diamond" and "convergence-gp-mood-cross", the latter on
+   the cross-shaped stencils and for POL-MOOD3; values in tests/golden/):
+   GP-MOOD7 (7->3->1) and
    GP-MOOD5 (5->3->1) with SSP-RK4, GP-MOOD3 (3->1) with SSP-RK3, on [0,20]^2 with
    ell = 1 up to t = 20.  Time step: CFL 0.8 on the 50^2 initial state, scaled by
    (50/N)^((2R+1)/4) for SSP-RK4 and by 50/N for SSP-RK3 (the reading of the
@@ -42,6 +44,41 @@ def _rel_l1(a, b):
     return np.array([np.abs(a[v] - b[v]).sum() / np.abs(b[v]).sum() for v in range(4)])
 
 
+@pytest.mark.parametrize("stencil,cascade", [("cross", (3, 2, 1, 0)), ("cross", (2, 1, 0)), ("poly3", (1, 0))])
+def test_stencil_variants_stage_replay_fp64(torch_cuda, stencil, cascade):
+    """Cross-shaped GP stencils and POL-MOOD3: each SSP-RK3 stage on four-quadrant
+    shocks replayed on the oracle's inputs, masks and counts identical."""
+    from paper_2110_08683_amd import GPMood
+    torch = torch_cuda
+    n = 64
+    _note(f"stage replay {stencil} {cascade}")
+    U0 = gi.quadrants(n, n, seed=5)
+    o = oracle.Oracle(n, n, bc=(1, 0), cascade=cascade, shape=stencil)
+    g = GPMood(n, n, bc=(1, 0), prec="f64", cascade=cascade, device="cuda:0", stencil=stencil)
+    U = o.run(U0, cfl=0.8, nsteps=3)[0]
+    dt = o.dt(U, 0.8)
+    U1 = o.stage(0, U, U, dt)[0]
+    U2 = o.stage(1, U, U1, dt)[0]
+    dev = torch.device("cuda")
+    lowered = 0
+    for s, Us in ((0, U), (1, U1), (2, U2)):
+        tout = torch.empty((4, n, n), dtype=torch.float64, device=dev)
+        g.gpm_set_dt(dt)
+        g.gpm_stage_dev(s, torch.from_numpy(U).to(dev), torch.from_numpy(Us).to(dev), tout)
+        torch.cuda.synchronize()
+        Uo, order, ocounts, oiters = o.stage(s, U, Us, dt)
+        mask = g.gpm_get_order_mask().astype(np.int32)
+        counts, iters = g.gpm_troubled_counts()
+        assert np.array_equal(mask, order), int((mask != order).sum())
+        np.testing.assert_array_equal(counts[:len(cascade)], ocounts)
+        assert iters == oiters
+        err = _rel_l1(tout.cpu().numpy(), Uo)
+        assert np.all(err <= 1e-12), (s, err)
+        lowered += int(ocounts[1:].sum())
+    assert lowered > 0
+    g.close()
+
+
 @pytest.mark.parametrize("case", ["vortex", "quadrants"])
 def test_rk4_steps_match_oracle_fp64(torch_cuda, case):
     from paper_2110_08683_amd import GPMood, rk4
@@ -72,17 +109,18 @@ def test_rk4_steps_match_oracle_fp64(torch_cuda, case):
     g.close()
 
 
-def _table():
-    rows = [l.split() for l in open(os.path.join(HERE, "golden", "convergence_gp_mood_diamond.txt"))
+def _table(name="diamond"):
+    rows = [l.split() for l in open(os.path.join(HERE, "golden", f"convergence_gp_mood_{name}.txt"))
             if l.strip() and not l.startswith("#")]
     return {int(r[0]): tuple(float(x) for x in r[1:]) for r in rows}
 
 
-def _vortex_l1(torch, N, cascade, method, dt50):
+def _vortex_l1(torch, N, cascade, method, dt50, stencil="diamond"):
     from paper_2110_08683_amd import GPMood, rk4
     L = 20.0
     U0 = gi.vortex(N, N, lo=(0.0, 0.0), hi=(L, L))
-    g = GPMood(N, N, lo=(0.0, 0.0), hi=(L, L), bc=(0, 0), prec="f64", cascade=cascade, ell=1.0, device="cuda:0")
+    g = GPMood(N, N, lo=(0.0, 0.0), hi=(L, L), bc=(0, 0), prec="f64", cascade=cascade, ell=1.0, device="cuda:0",
+               stencil=stencil)
     p = (2 * cascade[0] + 1) / 4.0 if method == "rk4" else 1.0
     nst = int(math.ceil(20.0 / (dt50 * (50.0 / N) ** p)))
     dt = 20.0 / nst
@@ -102,8 +140,12 @@ def _vortex_l1(torch, N, cascade, method, dt50):
     return e
 
 
-@pytest.mark.parametrize("col,cascade,method", [(2, (3, 1, 0), "rk4"), (1, (2, 1, 0), "rk4"), (0, (1, 0), "rk3")])
-def test_paper_vortex_convergence_table(torch_cuda, col, cascade, method):
+@pytest.mark.parametrize("table,col,cascade,method,stencil", [
+    ("diamond", 2, (3, 1, 0), "rk4", "diamond"), ("diamond", 1, (2, 1, 0), "rk4", "diamond"),
+    ("diamond", 0, (1, 0), "rk3", "diamond"),
+    ("cross", 1, (3, 1, 0), "rk4", "cross"), ("cross", 0, (2, 1, 0), "rk4", "cross"),
+    ("cross", 2, (1, 0), "rk3", "poly3")])
+def test_paper_vortex_convergence_table(torch_cuda, table, col, cascade, method, stencil):
     from paper_2110_08683_amd import GPMood
     torch = torch_cuda
     L = 20.0
@@ -112,12 +154,12 @@ def test_paper_vortex_convergence_table(torch_cuda, col, cascade, method):
     g.gpm_init_state(gi.vortex(50, 50, lo=(0.0, 0.0), hi=(L, L)))
     dt50 = g.gpm_compute_dt(0.8)
     g.close()
-    table = _table()
+    tab = _table(table)
     errs = []
     for N in (50, 100, 200, 400):
-        e = _vortex_l1(torch, N, cascade, method, dt50)
-        paper = table[N][col]
-        _note(f"GP-MOOD{2 * cascade[0] + 1} {method} N={N}: L1 {e:.6e}  paper {paper:.6e}  ratio {e / paper:.4f}")
+        e = _vortex_l1(torch, N, cascade, method, dt50, stencil)
+        paper = tab[N][col]
+        _note(f"{stencil} MOOD{2 * cascade[0] + 1} {method} N={N}: L1 {e:.6e}  paper {paper:.6e}  ratio {e / paper:.4f}")
         errs.append(e)
         assert abs(e / paper - 1.0) < 0.01, (N, e, paper)
     eoc = [math.log(errs[i] / errs[i + 1], 2) for i in range(3)]
