@@ -20,7 +20,11 @@ synthetic stand-ins shaped like the paper's shock problems):
   * smooth density wave advected at constant velocity and pressure (exact solution
     is a translation), used for convergence checks,
   * 3D blast: ambient rho = 1 with seeded +-1% noise, p = 1e-5, and p = 1e4 in the
-    cells whose centres lie within r = 3 dx of the cube centre.
+    cells whose centres lie within r = 3 dx of the cube centre,
+  * implosion (Sec. "The implosion problem in 2D", the set-up of Liska and
+    Wendroff that it cites): [0, 0.3]^2 at rest, rho = 0.125, p = 0.14 below the
+    line x + y = 0.15 and rho = 1, p = 1 above it, exact cell averages by the
+    area below the line; the state is symmetric under x <-> y.
 """
 from __future__ import annotations
 
@@ -206,6 +210,26 @@ def noise(nx, ny, seed=11, sigma=0.6, gamma=GAMMA):
     v = rng.normal(0.0, 1.0, (ny, nx))
     p = np.exp(rng.normal(0.0, sigma, (ny, nx)))
     return prim_to_cons(rho, u, v, p, gamma)
+
+
+# --------------------------------------------------------------------------
+# Implosion in a box with reflecting walls
+# --------------------------------------------------------------------------
+def implosion(n, L=0.3, cut=0.15, inner=(0.125, 0.14), outer=(1.0, 1.0), gamma=GAMMA):
+    """Cell averages on an n-by-n grid of [0, L]^2: (rho, p) = inner below the line
+    x + y = cut, outer above it, at rest.  The fraction of cell (i, j) below the line
+    is the area of {a + b < s} in the unit square, s = cut/dx - i - j."""
+    dx = L / n
+    idx = np.arange(n, dtype=np.float64)
+    s = cut / dx - (idx[None, :] + idx[:, None])
+    frac = np.where(s <= 0.0, 0.0, np.where(s >= 2.0, 1.0,
+                    np.where(s <= 1.0, 0.5 * s * s, 1.0 - 0.5 * (2.0 - s) ** 2)))
+    rho = inner[0] * frac + outer[0] * (1.0 - frac)
+    E = (inner[1] * frac + outer[1] * (1.0 - frac)) / (gamma - 1.0)
+    out = np.zeros((4, n, n))
+    out[0] = rho
+    out[3] = E
+    return out
 
 
 # --------------------------------------------------------------------------

@@ -139,7 +139,8 @@ def _ip(a):
 class Oracle:
     """2D GP-MOOD oracle on a uniform grid [lo, hi] with nx-by-ny cells.
 
-    bc: (bcx, bcy), 0 periodic / 1 outflow.  cascade: radii, strictly decreasing,
+    bc: (bcx, bcy), 0 periodic / 1 outflow / 2 reflecting wall (mirror image with
+    the normal momentum reversed; at least 4 cells, the ghost depth).  cascade: radii, strictly decreasing,
     ending in 0 (FOG).  ell: physical GP length scale.  shape: "diamond" (the
     blocky diamond), "cross" (the cross-shaped stencils of Sec. "Isentropic
     vortex") or "poly3" (POL-MOOD3: radius 1 with the polynomial weights).
@@ -159,6 +160,9 @@ class Oracle:
         c = _Cfg()
         c.nx, c.ny, c.dx, c.dy = self.nx, self.ny, self.dx, self.dy
         c.bcx, c.bcy = int(bc[0]), int(bc[1])
+        for b, n in ((c.bcx, self.nx), (c.bcy, self.ny)):
+            if b not in (0, 1, 2) or (b != 1 and n < 4):
+                raise ValueError("bc 0 (periodic), 1 (outflow) or 2 (reflecting); 0 and 2 need >= 4 cells")
         c.gamma = gamma
         c.nlev = len(cascade)
         if shape == "poly3" and max(cascade) > 1:

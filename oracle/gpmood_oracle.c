@@ -38,7 +38,7 @@ enum { ORC_CSD = 1u, ORC_PLATEAU = 2u, ORC_U2 = 4u, ORC_RSCAD = 8u };
 typedef struct {
     int nx, ny;
     double dx, dy;
-    int bcx, bcy; /* 0 periodic, 1 outflow (zero gradient) */
+    int bcx, bcy; /* 0 periodic, 1 outflow (zero gradient), 2 reflecting wall */
     double gamma;
     int nlev;
     int rad[4];         /* cascade radii, strictly decreasing, last one 0 (FOG) */
@@ -57,9 +57,12 @@ typedef struct {
 static double dmin(double a, double b) { return a < b ? a : b; }
 static double dmax(double a, double b) { return a > b ? a : b; }
 
+/* Source cell of index i on an axis of n cells: bc 0 periodic, 1 outflow (zero
+   gradient: the edge cell), 2 reflecting (the mirror image across the wall). */
 static int src_index(int i, int n, int bc)
 {
     if (bc == 0) { int r = i % n; return r < 0 ? r + n : r; }
+    if (bc == 2) return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i);
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
@@ -79,7 +82,11 @@ static void fill_ghosted(const orc_cfg *c, const double *U, ghosted *g)
         for (int j = -GH; j < c->ny + GH; ++j)
             for (int i = -GH; i < c->nx + GH; ++i) {
                 int si = src_index(i, c->nx, c->bcx), sj = src_index(j, c->ny, c->bcy);
-                g->u[gidx(g, v, i, j)] = U[((size_t)v * c->ny + sj) * c->nx + si];
+                /* a reflecting wall mirrors the cell and reverses its normal momentum */
+                double sg = 1.0;
+                if (v == 1 && c->bcx == 2 && (i < 0 || i >= c->nx)) sg = -sg;
+                if (v == 2 && c->bcy == 2 && (j < 0 || j >= c->ny)) sg = -sg;
+                g->u[gidx(g, v, i, j)] = sg * U[((size_t)v * c->ny + sj) * c->nx + si];
             }
 }
 

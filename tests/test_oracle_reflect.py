@@ -1,0 +1,125 @@
+"""Pins of the oracle's reflecting walls (bc = 2: the ghost cells past a wall are the
+mirror images of the interior cells with the normal momentum reversed, the walls of
+Sec. "The implosion problem in 2D").
+
+Reflecting walls on [0, 1]^2 are, exactly in the mathematics, the periodic problem on
+[-1, 1]^2 whose state is the mirror extension of the box's state (the extension stays
+mirror-symmetric about both walls of each axis).  That pin goes through the oracle's
+periodic ghosts, a different code path from the mirror, and fails for a wrong mirror
+index or a missing momentum reversal.  The doubled run keeps its symmetry in floating
+point only while every reconstructed face state has a positive pressure (HLLC's wave
+speed bounds take the sound speed, undefined otherwise, and the min/max of a NaN
+depends on the argument order) and no detection threshold falls within rounding; the
+seeded four-quadrant cases below are ones where it does, which each test asserts
+first.  A closed box conserves mass and energy, and the implosion's diagonal symmetry
+survives the steps."""
+import numpy as np
+import pytest
+
+import gpmood_inputs as gi
+import oracle
+
+
+def mirror_extend(U):
+    """(4, ny, nx) state of [0,1]^2 -> (4, 2ny, 2nx) periodic state of [-1,1]^2."""
+    ny, nx = U.shape[1:]
+    sx = np.array([1.0, -1.0, 1.0, 1.0])[:, None, None]
+    sy = np.array([1.0, 1.0, -1.0, 1.0])[:, None, None]
+    out = np.empty((4, 2 * ny, 2 * nx))
+    out[:, ny:, nx:] = U
+    out[:, ny:, :nx] = sx * U[:, :, ::-1]
+    out[:, :ny, nx:] = sy * U[:, ::-1, :]
+    out[:, :ny, :nx] = sx * sy * U[:, ::-1, ::-1]
+    return out
+
+
+def rel_l1(a, b):
+    return max(np.abs(a[v] - b[v]).sum() / max(np.abs(b[v]).sum(), 1e-300) for v in range(4))
+
+
+@pytest.mark.parametrize("seed", [1, 8])
+def test_reflect_equals_mirrored_periodic(seed):
+    n = 16
+    U0 = gi.quadrants(n, n, seed=seed, split=(0.4, 0.6))
+    ell = 12.0 / n
+    box = oracle.Oracle(n, n, bc=(2, 2), ell=ell)
+    per = oracle.Oracle(2 * n, 2 * n, lo=(-1.0, -1.0), hi=(1.0, 1.0), bc=(0, 0), ell=ell)
+    Ub, dtb, cb, _ = box.run(U0, cfl=0.8, nsteps=3)
+    Up, dtp, cp, _ = per.run(mirror_extend(U0), cfl=0.8, nsteps=3)
+    # precondition: the doubled periodic run stayed mirror-symmetric
+    assert rel_l1(mirror_extend(Up[:, n:, n:]), Up) < 1e-14
+    np.testing.assert_allclose(dtb, dtp, rtol=1e-13)
+    assert rel_l1(Ub, Up[:, n:, n:]) < 1e-14
+    # the cascade lowered the same cells in every image
+    assert np.array_equal(4 * cb, cp)
+    assert cb[:, :, 1:].sum() > 100  # the shock problem exercised the cascade
+
+
+def test_reflect_single_axis_against_mirror():
+    # walls in x only, periodic in y: the doubled domain is periodic in both
+    nx, ny = 12, 10
+    hi = (1.0, ny / nx)
+    U0 = gi.quadrants(nx, ny, seed=4, hi=hi, split=(0.4, 0.45))
+    ell = 12.0 / nx
+    sx = np.array([1.0, -1.0, 1.0, 1.0])[:, None, None]
+    ext = lambda U: np.concatenate([sx * U[:, :, ::-1], U], axis=2)
+    box = oracle.Oracle(nx, ny, hi=hi, bc=(2, 0), ell=ell)
+    per = oracle.Oracle(2 * nx, ny, lo=(-1.0, 0.0), hi=hi, bc=(0, 0), ell=ell)
+    Ub, _, cb, _ = box.run(U0, cfl=0.8, nsteps=3)
+    Up, _, cp, _ = per.run(ext(U0), cfl=0.8, nsteps=3)
+    assert rel_l1(ext(Up[:, :, nx:]), Up) < 1e-14
+    assert rel_l1(Ub, Up[:, :, nx:]) < 1e-14
+    assert np.array_equal(2 * cb, cp)
+    assert cb[:, :, 1:].sum() > 100
+
+
+def test_hllc_mirror_symmetry_needs_positive_pressure():
+    # the reason for the precondition above: the mirrored Riemann problem's flux is
+    # the mirrored flux when both pressures are positive, not otherwise
+    G = 1.4
+    cons = lambda r, u, v, p: np.array([r, r * u, r * v, p / (G - 1) + 0.5 * r * (u * u + v * v)])
+    M = np.array([1.0, -1.0, 1.0, 1.0])
+    UR = cons(0.5, -0.1, 0.4, 0.8)
+    UL = cons(1.0, 0.3, 0.2, 0.5)
+    assert np.array_equal(oracle.hllc(UL, UR, 0), -M * oracle.hllc(M * UR, M * UL, 0))
+    UL = cons(1.0, 0.3, 0.2, -0.05)
+    assert not np.allclose(oracle.hllc(UL, UR, 0), -M * oracle.hllc(M * UR, M * UL, 0))
+
+
+def test_closed_box_conserves_mass_and_energy():
+    # A wall face carries no mass or energy when its two Riemann states are mirror
+    # images with positive pressures.  The implosion's own contrast (0.125, 0.14)
+    # reconstructs some face states with negative pressure at R >= 1, whose flux
+    # HLLC takes one-sidedly (its wave speeds are then NaN), so the walls leak a few
+    # 1e-6 of the mass over these steps; a milder contrast keeps every face state
+    # physical and the box's totals exact.
+    n = 32
+    U0 = gi.implosion(n, inner=(0.5, 0.6))
+    o = oracle.Oracle(n, n, hi=(0.3, 0.3), bc=(2, 2))
+    t0 = o.totals(U0)
+    U, _, counts, _ = o.run(U0, cfl=0.8, nsteps=6)
+    t1 = o.totals(U)
+    assert abs(t1[0] - t0[0]) <= 1e-13 * t0[0]
+    assert abs(t1[3] - t0[3]) <= 1e-13 * t0[3]
+    # the walls push back: the momenta change, by the same amount on both axes
+    assert abs(t1[1]) > 1e-6
+    assert abs(t1[1] - t1[2]) <= 1e-12 * abs(t1[1])
+    assert counts[:, :, 1:].sum() > 100
+
+
+def test_implosion_keeps_diagonal_symmetry():
+    n = 24
+    U0 = gi.implosion(n)
+    o = oracle.Oracle(n, n, hi=(0.3, 0.3), bc=(2, 2))
+    U, _, _, _ = o.run(U0, cfl=0.8, nsteps=5)
+    assert np.all(U[0] > 0)
+    scale = np.abs(U).max(axis=(1, 2))
+    assert np.abs(U[0] - U[0].T).max() <= 1e-12 * scale[0]
+    assert np.abs(U[3] - U[3].T).max() <= 1e-12 * scale[3]
+    assert np.abs(U[1] - U[2].T).max() <= 1e-12 * scale[1]
+
+
+def test_reflect_needs_four_cells():
+    with pytest.raises(ValueError):
+        oracle.Oracle(3, 8, bc=(2, 1))
+    oracle.Oracle(3, 8, bc=(1, 2))  # outflow has no such bound
