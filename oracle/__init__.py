@@ -161,8 +161,8 @@ class Oracle:
         c.nx, c.ny, c.dx, c.dy = self.nx, self.ny, self.dx, self.dy
         c.bcx, c.bcy = int(bc[0]), int(bc[1])
         for b, n in ((c.bcx, self.nx), (c.bcy, self.ny)):
-            if b not in (0, 1, 2) or (b != 1 and n < 4):
-                raise ValueError("bc 0 (periodic), 1 (outflow) or 2 (reflecting); 0 and 2 need >= 4 cells")
+            if b not in (0, 1, 2) or (b == 2 and n < 4):
+                raise ValueError("bc 0 (periodic), 1 (outflow) or 2 (reflecting, >= 4 cells)")
         c.gamma = gamma
         c.nlev = len(cascade)
         if shape == "poly3" and max(cascade) > 1:

@@ -159,9 +159,15 @@ static void recon(const orc_cfg *c, const ghosted *g, int l, int f, int k, int i
     }
 }
 
-static int state_nonfinite(double gam, const double *q)
+/* CAD on a reconstructed Riemann state (Sec. CAD): the state is inadmissible unless
+   its density and pressure are finite and positive.  A non-positive value makes the
+   sound speed the square root of a negative number, an invalid operation that CAD
+   exists to catch, and HLLC's wave speeds then order its two states arbitrarily,
+   which breaks the symmetry the Riemann-state check is there to keep. */
+static int state_inadmissible(double gam, const double *q)
 {
-    return !isfinite(q[0]) || !isfinite(pressure(gam, q));
+    double p = pressure(gam, q);
+    return !(isfinite(q[0]) && isfinite(p) && q[0] > 0.0 && p > 0.0);
 }
 
 /* --------------------------------------------- per-stage relaxation data */
@@ -277,8 +283,8 @@ static void candidate(const orc_cfg *c, const ghosted *g, const int *order, doub
                 double qL[4], qR[4], f[4];
                 recon(c, g, l, 1, k, i - 1, j, qL); /* x+ face of the left cell */
                 recon(c, g, l, 0, k, i, j, qR);     /* x- face of the right cell */
-                if (state_nonfinite(gam, qL)) bad |= 1;
-                if (state_nonfinite(gam, qR)) bad |= 2;
+                if (state_inadmissible(gam, qL)) bad |= 1;
+                if (state_inadmissible(gam, qR)) bad |= 2;
                 hllc(gam, qL, qR, 0, f);
                 for (int v = 0; v < NV; ++v) F[v] += c->qw[l][k] * f[v];
             }
@@ -298,8 +304,8 @@ static void candidate(const orc_cfg *c, const ghosted *g, const int *order, doub
                 double qL[4], qR[4], f[4];
                 recon(c, g, l, 3, k, i, j - 1, qL); /* y+ face of the lower cell */
                 recon(c, g, l, 2, k, i, j, qR);     /* y- face of the upper cell */
-                if (state_nonfinite(gam, qL)) bad |= 1;
-                if (state_nonfinite(gam, qR)) bad |= 2;
+                if (state_inadmissible(gam, qL)) bad |= 1;
+                if (state_inadmissible(gam, qR)) bad |= 2;
                 hllc(gam, qL, qR, 1, f);
                 for (int v = 0; v < NV; ++v) G[v] += c->qw[l][k] * f[v];
             }

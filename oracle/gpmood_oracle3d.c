@@ -148,7 +148,13 @@ static void recon3(const orc3_cfg *c, const ghosted3 *g, int l, int f, int q, in
     }
 }
 
-static int state_nonfinite(double gam, const double *q) { return !isfinite(q[0]) || !isfinite(pressure(gam, q)); }
+/* CAD on a reconstructed Riemann state (Sec. CAD): density and pressure finite and
+   positive (a non-positive one gives an invalid sound speed). */
+static int state_inadmissible(double gam, const double *q)
+{
+    double p = pressure(gam, q);
+    return !(isfinite(q[0]) && isfinite(p) && q[0] > 0.0 && p > 0.0);
+}
 
 typedef struct { double rmin, rmax; int plat, csd, u2; } relax3_t;
 
@@ -247,8 +253,8 @@ static void candidate3(const orc3_cfg *c, const ghosted3 *g, const int *order, d
                         double qL[NV], qR[NV], f[NV];
                         recon3(c, g, l, 2 * d + 1, q, L[0], L[1], L[2], qL); /* + face of the left cell */
                         recon3(c, g, l, 2 * d, q, R[0], R[1], R[2], qR);     /* - face of the right cell */
-                        if (state_nonfinite(gam, qL)) bad |= 1;
-                        if (state_nonfinite(gam, qR)) bad |= 2;
+                        if (state_inadmissible(gam, qL)) bad |= 1;
+                        if (state_inadmissible(gam, qR)) bad |= 2;
                         hllc3(gam, qL, qR, d, f);
                         for (int v = 0; v < NV; ++v) Fs[v] += c->qw[l][q] * f[v];
                     }

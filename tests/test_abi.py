@@ -49,3 +49,16 @@ def test_strerror_and_argument_errors_without_gpu():
     g.bc[0], g.bc[1] = 0, 1
     g.gamma = 1.4
     assert L.gpm_create(ctypes.byref(g), 0, None, ctypes.byref(ctx)) == B.GPM_EUNSUPPORTED
+    # so must a reflecting one (the mirror image of 4 ghost cells); unknown bc values fail
+    g.bc[0] = B.GPM_BC_REFLECT
+    assert L.gpm_create(ctypes.byref(g), 0, None, ctypes.byref(ctx)) == B.GPM_EUNSUPPORTED
+    g.bc[0] = 3
+    assert L.gpm_create(ctypes.byref(g), 0, None, ctypes.byref(ctx)) == B.GPM_EINVAL
+    # reflecting walls are 2D only
+    g3 = B.gpm_grid()
+    g3.dim = 3
+    for a in range(3):
+        g3.n[a], g3.lo[a], g3.hi[a], g3.bc[a] = 8, 0.0, 1.0, 1
+    g3.bc[2] = B.GPM_BC_REFLECT
+    g3.gamma = 1.4
+    assert L.gpm3_create(ctypes.byref(g3), 0, None, ctypes.byref(ctx)) == B.GPM_EUNSUPPORTED
