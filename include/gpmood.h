@@ -49,10 +49,14 @@ typedef enum {
 } gpm_status;
 
 typedef enum { GPM_F32 = 0, GPM_F64 = 1 } gpm_prec;
-typedef enum { GPM_BC_PERIODIC = 0, GPM_BC_OUTFLOW = 1 } gpm_bc;
+typedef enum { GPM_BC_PERIODIC = 0, GPM_BC_OUTFLOW = 1, GPM_BC_REFLECT = 2 } gpm_bc;
 
 /* Grid: n[d] cells on [lo[d], hi[d]], one boundary condition per axis
-   (periodic wraps, outflow copies the nearest interior cell: zero gradient). */
+   (periodic wraps, outflow copies the nearest interior cell: zero gradient,
+   reflect is a slip wall: the ghost cell k past the wall is the image of the k-th
+   interior cell with its momentum normal to the wall reversed: the four walls of
+   Sec. "The implosion problem in 2D"; 2D stages only, not gpm3_* nor
+   gpm_stage_vjp). */
 typedef struct {
     int dim;        /* 2 */
     int n[3];       /* nx, ny (n[2] ignored in 2D) */
@@ -94,8 +98,8 @@ enum { GPM_STENCIL_DIAMOND = 0, GPM_STENCIL_CROSS = 1, GPM_STENCIL_POLY3 = 2 };
 /* Create a context for a grid, a precision and a HIP stream (hipStream_t, may be
    NULL).  Allocates host memory only.  Errors: GPM_EINVAL (bad grid, gamma <= 1,
    n < 1 or > 32768 per axis), GPM_EUNSUPPORTED (dim != 2 (3D: gpm3_create), or
-   a periodic axis with fewer than 4 cells: the radius-3 stencil reaches 4 cells
-   past a face). */
+   a periodic or reflecting axis with fewer than 4 cells: the radius-3 stencil
+   reaches 4 cells past a face). */
 gpm_status gpm_create(const gpm_grid *grid, int prec, void *hip_stream, gpm_ctx **out);
 
 /* Set the cascade, ell, CSD thresholds and flags.  Builds the GP prediction
@@ -240,7 +244,8 @@ gpm_status gpm_order_ptr(const gpm_ctx *ctx, void **order_dev);
    scale; through the ell-dependence of the reconstruction weights only, the
    detection being frozen) is added to *dL_dell (synchronising).  The context's
    stored face fluxes are overwritten (scratch).  Errors: GPM_EINVAL (bad stage,
-   NULL or aliased buffers, dt <= 0), GPM_ESTATE. */
+   NULL or aliased buffers, dt <= 0), GPM_ESTATE, GPM_EUNSUPPORTED (a reflecting
+   axis). */
 gpm_status gpm_stage_vjp(gpm_ctx *ctx, int s, const void *Un, const void *Us, const void *order, double dt,
                          const void *lam_out, void *lam_Us, void *lam_Un, double *dL_dell);
 
@@ -309,7 +314,8 @@ void gpm_batch_destroy(gpm_batch *b);
    (gradP) with the z terms, u2 eqs. (u2_a), (u2_b) per direction with GP-R1
    second derivatives), SSP-RK3 eq. (rk3), FP64 dt = CFL min Delta_d/(|u_d|+c).
    The calls mirror the 2D ones; grid.dim must be 3, n <= 4096 per axis,
-   periodic axes need >= 3 cells, cascades use radii 2, 1, 0 (GP-MOOD5 = {2,1,0}).
+   periodic axes need >= 3 cells, reflecting walls are not built (GPM_EUNSUPPORTED),
+   cascades use radii 2, 1, 0 (GP-MOOD5 = {2,1,0}).
    Not thread-safe per context. */
 typedef struct gpm3_ctx gpm3_ctx;
 gpm_status gpm3_create(const gpm_grid *grid, int prec, void *hip_stream, gpm3_ctx **out);

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libgpmood.so")
 
 GPM_OK, GPM_EINVAL, GPM_ENOMEM, GPM_EHIP, GPM_ESTATE, GPM_ENOTCONV, GPM_EUNSUPPORTED = range(7)
 GPM_F32, GPM_F64 = 0, 1
-GPM_BC_PERIODIC, GPM_BC_OUTFLOW = 0, 1
+GPM_BC_PERIODIC, GPM_BC_OUTFLOW, GPM_BC_REFLECT = 0, 1, 2
 GPM_CSD, GPM_PLATEAU, GPM_U2, GPM_RSCAD = 1, 2, 4, 8
 GPM_FLAGS_ALL = 15
 
@@ -141,7 +141,7 @@ def _dp(a):
 class GPMood:
     """One 2D problem on the GPU: owns torch device buffers and a library context.
 
-    nx, ny, lo, hi, bc=(bcx, bcy) with 0 periodic / 1 outflow, prec 'f32' | 'f64',
+    nx, ny, lo, hi, bc=(bcx, bcy) with 0 periodic / 1 outflow / 2 reflecting wall, prec 'f32' | 'f64',
     cascade = GP radii ending in 0, ell = physical length scale (None: 12 min(dx, dy)).
     """
 

@@ -43,7 +43,7 @@ struct Stage3 {
     const double *dt;
     uint8_t *order;
     real *F[3];          // per axis a: [5][nz + (a == 2)][ny + (a == 1)][nx + (a == 0)]
-    uint8_t *Ff[3];      // bit 0 / 1: the left / right state is not finite
+    uint8_t *Ff[3];      // bit 0 / 1: the left / right state is inadmissible
     unsigned *cstamp;    // [ncell]
     unsigned *fstamp;    // [all faces, axes concatenated]
     int n[3], bc[3];
@@ -92,8 +92,8 @@ __device__ __forceinline__ void hllc3(real g, int a, const real (&UL)[5], const 
     const real rr = UR[0], irr = dv(real(1), rr), ur = UR[n] * irr, vr = UR[t1] * irr, wr = UR[t2] * irr, Er = UR[4];
     const real pl = (g - real(1)) * (El - real(0.5) * rl * (ul * ul + vl * vl + wl * wl));
     const real pr = (g - real(1)) * (Er - real(0.5) * rr * (ur * ur + vr * vr + wr * wr));
-    badL = !(finite(rl) && finite(pl));
-    badR = !(finite(rr) && finite(pr));
+    badL = !(pos_finite(rl) && pos_finite(pl));
+    badR = !(pos_finite(rr) && pos_finite(pr));
     const real cl = sq(g * pl * irl), cr = sq(g * pr * irr);
     const real SL = vmin(ul - cl, ur - cr);
     const real SR = vmax(ul + cl, ur + cr);
@@ -807,6 +807,7 @@ gpm_status gpm3_create(const gpm_grid *grid, int prec, void *hip_stream, gpm3_ct
     for (int a = 0; a < 3; ++a) {
         if (grid->n[a] < 1 || grid->n[a] > 4096) return GPM_EINVAL;
         if (!(grid->hi[a] > grid->lo[a])) return GPM_EINVAL;
+        if (grid->bc[a] == GPM_BC_REFLECT) return GPM_EUNSUPPORTED;  // 2D only
         if (grid->bc[a] != GPM_BC_PERIODIC && grid->bc[a] != GPM_BC_OUTFLOW) return GPM_EINVAL;
         if (grid->bc[a] == GPM_BC_PERIODIC && grid->n[a] < 3) return GPM_EUNSUPPORTED;
         ncell *= (size_t)grid->n[a];

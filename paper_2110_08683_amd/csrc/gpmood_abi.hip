@@ -48,9 +48,11 @@ gpm_status gpm_create(const gpm_grid *grid, int prec, void *hip_stream, gpm_ctx 
     for (int d = 0; d < 2; ++d) {
         if (grid->n[d] < 1 || grid->n[d] > 32768) return GPM_EINVAL;
         if (!(grid->hi[d] > grid->lo[d])) return GPM_EINVAL;
-        if (grid->bc[d] != GPM_BC_PERIODIC && grid->bc[d] != GPM_BC_OUTFLOW) return GPM_EINVAL;
-        // the widest stencil reaches 4 cells past an edge; a periodic axis must hold it
-        if (grid->bc[d] == GPM_BC_PERIODIC && grid->n[d] < 4) return GPM_EUNSUPPORTED;
+        if (grid->bc[d] != GPM_BC_PERIODIC && grid->bc[d] != GPM_BC_OUTFLOW && grid->bc[d] != GPM_BC_REFLECT)
+            return GPM_EINVAL;
+        // the widest stencil reaches 4 cells past an edge; a periodic or reflecting
+        // axis must hold its image
+        if (grid->bc[d] != GPM_BC_OUTFLOW && grid->n[d] < 4) return GPM_EUNSUPPORTED;
     }
     if (!(grid->gamma > 1.0)) return GPM_EINVAL;
     gpm_ctx *c = new (std::nothrow) gpm_ctx;
@@ -543,6 +545,8 @@ gpm_status gpm_stage_vjp(gpm_ctx *c, int s, const void *Un, const void *Us, cons
         return fail(c, GPM_EINVAL, "bad adjoint arguments");
     if (lam_Us == lam_out || (s > 0 && (lam_Un == lam_out || lam_Un == lam_Us)))
         return fail(c, GPM_EINVAL, "adjoint outputs must not alias");
+    if (c->grid.bc[0] == GPM_BC_REFLECT || c->grid.bc[1] == GPM_BC_REFLECT)
+        return fail(c, GPM_EUNSUPPORTED, "the stage adjoint has periodic and outflow boundaries only");
     return c->prec == GPM_F64 ? stage_vjp<double>(c, c->w64, s, Un, Us, order, dt, lam_out, lam_Us, lam_Un, dL_dell)
                               : stage_vjp<float>(c, c->w32, s, Un, Us, order, dt, lam_out, lam_Us, lam_Un, dL_dell);
 }

@@ -65,6 +65,8 @@ __device__ __forceinline__ Dual<real> sqrt(Dual<real> a)
 }
 template <typename real>
 __device__ __forceinline__ bool finite(Dual<real> a) { return __builtin_isfinite(a.v); }
+template <typename real>
+__device__ __forceinline__ bool pos_finite(Dual<real> a) { return pos_finite(a.v); }
 
 // ------------------------------------------------------------ per-face adjoint
 template <typename real>

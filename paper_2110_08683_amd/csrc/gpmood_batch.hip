@@ -17,6 +17,7 @@
 
 #include "gpmood.h"
 #include "gpmood_ctx.h"
+#include "gp_weights.h"
 
 namespace {
 
@@ -56,6 +57,7 @@ struct gpm_batch {
     double *st_dt = nullptr;    // [nprob]
     int nfp = 0, ndt = 0;
     int iso = 0;                // every problem has isotropic weights
+    int walls = 0;              // some problem has a reflecting axis
     // graphs: one captured SSP-RK3 step per rotation
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
@@ -171,7 +173,11 @@ static gpm_status build_tables(gpm_batch *b)
         dblk[p + 1] = dblk[p] + dt_blocks(c);
     }
     b->iso = 1;
-    for (size_t k = 0; k < args.size(); ++k) b->iso &= args[k].iso;
+    b->walls = 0;
+    for (size_t k = 0; k < args.size(); ++k) {
+        b->iso &= args[k].iso;
+        b->walls |= (args[k].bcx == GPM_BC_REFLECT || args[k].bcy == GPM_BC_REFLECT) ? 1 : 0;
+    }
     b->nfp = blk[P];
     b->ndt = dblk[P];
     const BatchLayout L = batch_layout(b);
@@ -206,6 +212,7 @@ static BatchTabs<real> tabs(const gpm_batch *b, int rot, int s)
     B.dblk = b->dblk;
     B.nprob = b->nprob;
     B.iso = b->iso;
+    B.walls = b->walls;
     return B;
 }
 
@@ -297,6 +304,17 @@ gpm_status gpm_batch_set_scheme(gpm_batch *b, const gpm_scheme *s)
             const gpm_ctx *d = b->ctx[q];
             c->w64 = d->w64;
             c->w32 = d->w32;
+            // the u2 curvature weights are second derivatives in physical units
+            // (they scale with 1 / dx^2): this problem's own
+            GpwCurv K;
+            if (gpw_curvature(ell / c->dx, ell / c->dy, ell, &K) != 0)
+                return bfail(b, GPM_EINVAL, std::string("problem ") + std::to_string(p) +
+                                                ": GP-R1 covariance matrix not positive definite");
+            for (int dd = 0; dd < 2; ++dd)
+                for (int k = 0; k < 3; ++k) {
+                    c->w64.curv[dd][k] = K.w64[dd][k];
+                    c->w32.curv[dd][k] = K.w32[dd][k];
+                }
             c->gtab64 = d->gtab64;
             c->gtab32 = d->gtab32;
             // the ell-derivative part scales with 1 / ell

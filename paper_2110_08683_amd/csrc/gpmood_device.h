@@ -49,7 +49,8 @@ struct StageArgs {
     uint8_t *order;       // GP radius per cell (final after the stage)
     // face fluxes of this stage: x faces [4][ny][nx+1] (face i between cells i-1
     // and i), y faces [4][ny+1][nx]; per face, bit 0 / bit 1: the left (lower) /
-    // right (upper) reconstructed state has a non-finite density or pressure
+    // right (upper) reconstructed state is inadmissible (density or pressure not
+    // finite and positive)
     real *FX;
     real *GY;
     uint8_t *FXf;
@@ -121,22 +122,37 @@ struct Cascade {
 };
 
 // ------------------------------------------------------------------ helpers
+// Source cell of index i on an axis of n cells with boundary bc: 0 periodic,
+// 1 outflow (the edge cell), 2 reflecting wall (the mirror image; an index more
+// than n cells outside, which only the unused lanes of a strip reach, is clamped).
 __device__ __forceinline__ int remap(int i, int n, int bc)
 {
     if (bc == 0) {
         int r = i % n;
         return r < 0 ? r + n : r;
     }
+    if (bc == 2) i = i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i);
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
 // remap() for an index at most one period outside the axis (-n <= i < 2n): the
-// cascade reaches at most 4 cells beyond the domain, and periodic axes have at
-// least 4 cells.
+// cascade reaches at most 4 cells beyond the domain, and periodic and reflecting
+// axes have at least 4 cells.  WALLS = false: the build for grids without a
+// reflecting axis (or for in-domain indices), which leaves out the mirror branch.
+template <bool WALLS = true>
 __device__ __forceinline__ int wrap(int i, int n, int bc)
 {
     if (bc == 0) return i < 0 ? i + n : (i >= n ? i - n : i);
+    if (WALLS && bc == 2) return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i);
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// Factor of the momentum normal to an axis in the image of cell index i: -1 when
+// a reflecting wall (refl) mirrored the index, which reverses that momentum.
+template <typename real>
+__device__ __forceinline__ real msign(int i, int n, bool refl)
+{
+    return refl && (i < 0 || i >= n) ? real(-1) : real(1);
 }
 
 // Division of the stage arithmetic: IEEE in FP64 (the parity path), in FP32 the
@@ -161,6 +177,9 @@ template <typename real>
 __device__ __forceinline__ real vmax(real a, real b) { return a > b ? a : b; }
 template <typename real>
 __device__ __forceinline__ bool finite(real x) { return __builtin_isfinite(x); }
+// x is finite and > 0 (a positive normal or subnormal number): one class test
+__device__ __forceinline__ bool pos_finite(float x) { return __builtin_amdgcn_classf(x, 0x180); }
+__device__ __forceinline__ bool pos_finite(double x) { return __builtin_amdgcn_class(x, 0x180); }
 
 // Ideal-gas pressure from conservative variables (detection form).
 template <typename real>
@@ -288,7 +307,8 @@ __device__ __forceinline__ void parity4(real pp, real mp, real pm, real mm, real
 }
 
 // HLLC flux through a face normal to axis DIR.  badL / badR: the density or the
-// pressure of the left / right state is not finite (CAD on Riemann states).
+// pressure of the left / right state is not finite and positive (CAD on Riemann
+// states: a non-positive value makes the sound speed an invalid square root).
 template <int DIR, typename real>
 __device__ __forceinline__ void hllc(real g, const real *UL, const real *UR, real *F, bool &badL, bool &badR)
 {
@@ -297,8 +317,8 @@ __device__ __forceinline__ void hllc(real g, const real *UL, const real *UR, rea
     const real rr = UR[0], irr = dv(real(1), rr), ur = UR[n] * irr, vr = UR[t] * irr, Er = UR[3];
     const real pl = (g - real(1)) * (El - real(0.5) * rl * (ul * ul + vl * vl));
     const real pr = (g - real(1)) * (Er - real(0.5) * rr * (ur * ur + vr * vr));
-    badL = !(finite(rl) && finite(pl));
-    badR = !(finite(rr) && finite(pr));
+    badL = !(pos_finite(rl) && pos_finite(pl));
+    badR = !(pos_finite(rr) && pos_finite(pr));
     const real cl = sq(g * pl * irl), cr = sq(g * pr * irr);
     const real SL = vmin(ul - cl, ur - cr);
     const real SR = vmax(ul + cl, ur + cr);
@@ -474,7 +494,8 @@ struct BatchTabs {
     const int *blk;
     const int *dblk;
     int nprob;
-    int iso;  // every problem's A.iso is 1
+    int iso;    // every problem's A.iso is 1
+    int walls;  // some problem has a reflecting axis
 };
 
 // Arguments of the stage adjoint: A carries U^n, U_s, the frozen final orders of

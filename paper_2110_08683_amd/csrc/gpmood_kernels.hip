@@ -70,7 +70,8 @@ __device__ __forceinline__ void claim_after_lowering(const StageArgs<real> &A, c
     for (int k = 0; k < 5; ++k) {
         const int ii = i + di[k], jj = j + dj[k];
         cok[k] = (A.bcx == 0 || (ii >= 0 && ii < nx)) && (A.bcy == 0 || (jj >= 0 && jj < ny));
-        cid[k] = cok[k] ? wrap(jj, ny, A.bcy) * nx + wrap(ii, nx, A.bcx) : j * nx + i;
+        // (on a non-periodic axis only in-domain indices get here: no mirror needed)
+        cid[k] = cok[k] ? wrap<false>(jj, ny, A.bcy) * nx + wrap<false>(ii, nx, A.bcx) : j * nx + i;
     }
     bool fmine[6], cmine[5];
     int nmine = 0;
@@ -148,8 +149,19 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
             pf[v][1] = has1 ? Us[v * plane + rowoff + sc1] : real(0);
         }
     };
-    auto store_row = [&](int jr, const real (&pf)[4][2]) {
+    // Reflecting walls reverse the x momentum of mirrored columns and the y
+    // momentum of mirrored rows; applied here, not at the load, which stays in flight.
+    auto store_row = [&](int jr, real (&pf)[4][2]) {
         const int slot = jr & 7;
+        if (A.bcx == 2) {
+            const int c0 = x0 - 4 + lane, c1 = c0 + 64;
+            if (c0 < 0 || c0 >= nx) pf[1][0] = -pf[1][0];
+            if (c1 >= nx) pf[1][1] = -pf[1][1];
+        }
+        if (A.bcy == 2 && (jr < 0 || jr >= ny)) {
+            pf[2][0] = -pf[2][0];
+            pf[2][1] = -pf[2][1];
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             ring[slot][v][lane] = pf[v][0];
@@ -381,7 +393,7 @@ __device__ __forceinline__ void load_gtab(const real *gtab, real *wl)
 // wavefront (LDS exchange); wl is the LDS copy of the compact weight table.
 // pre: when use_pre, this thread's list entry of round 0, loaded by the caller
 // (while the count was still unknown).
-template <typename real>
+template <bool WALLS, typename real>
 __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real *wl, FaceXchg<real> &X,
                                             const int *flist, int n, int t0, int stride, int pre = 0,
                                             bool use_pre = false)
@@ -409,8 +421,8 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
                 fo = f;
                 iL = i - 1;
                 jL = j;
-                cL = j * nx + wrap(i - 1, nx, A.bcx);
-                cR = j * nx + wrap(i, nx, A.bcx);
+                cL = j * nx + wrap<WALLS>(i - 1, nx, A.bcx);
+                cR = j * nx + wrap<WALLS>(i, nx, A.bcx);
             } else {
                 const int g = f - nfx;
                 const int j = g / nx, i = g - j * nx;  // between cells (i, j-1) and (i, j)
@@ -418,24 +430,33 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
                 fo = g;
                 iL = i;
                 jL = j - 1;
-                cL = wrap(j - 1, ny, A.bcy) * nx + i;
-                cR = wrap(j, ny, A.bcy) * nx + i;
+                cL = wrap<WALLS>(j - 1, ny, A.bcy) * nx + i;
+                cR = wrap<WALLS>(j, ny, A.bcy) * nx + i;
             }
             const int iR = iL + (dir == 0), jR = jL + (dir == 1);
             const real *U = A.Us + v * plane;
+            // reflecting walls reverse the normal momentum of mirrored cells (WALLS:
+            // the variant built for grids with a reflecting axis)
+            const bool fx = WALLS && v == 1 && A.bcx == 2, fy = WALLS && v == 2 && A.bcy == 2;
             // quarter positions 0..5 (radius <= 2) of both cells: 48 independent loads
             constexpr int pa[6] = {0, 1, 0, 2, 0, 1}, pb[6] = {0, 0, 1, 0, 2, 1};
             real QL[6][4], QR[6][4];
 #pragma unroll
             for (int e = 0; e < 6; ++e) {
-                const int xLp = wrap(iL + pa[e], nx, A.bcx), xLm = wrap(iL - pa[e], nx, A.bcx);
-                const int xRp = wrap(iR + pa[e], nx, A.bcx), xRm = wrap(iR - pa[e], nx, A.bcx);
-                const size_t yLp = (size_t)wrap(jL + pb[e], ny, A.bcy) * nx;
-                const size_t yLm = (size_t)wrap(jL - pb[e], ny, A.bcy) * nx;
-                const size_t yRp = (size_t)wrap(jR + pb[e], ny, A.bcy) * nx;
-                const size_t yRm = (size_t)wrap(jR - pb[e], ny, A.bcy) * nx;
-                parity4(U[yLp + xLp], U[yLp + xLm], U[yLm + xLp], U[yLm + xLm], QL[e]);
-                parity4(U[yRp + xRp], U[yRp + xRm], U[yRm + xRp], U[yRm + xRm], QR[e]);
+                const int xLp = wrap<WALLS>(iL + pa[e], nx, A.bcx), xLm = wrap<WALLS>(iL - pa[e], nx, A.bcx);
+                const int xRp = wrap<WALLS>(iR + pa[e], nx, A.bcx), xRm = wrap<WALLS>(iR - pa[e], nx, A.bcx);
+                const size_t yLp = (size_t)wrap<WALLS>(jL + pb[e], ny, A.bcy) * nx;
+                const size_t yLm = (size_t)wrap<WALLS>(jL - pb[e], ny, A.bcy) * nx;
+                const size_t yRp = (size_t)wrap<WALLS>(jR + pb[e], ny, A.bcy) * nx;
+                const size_t yRm = (size_t)wrap<WALLS>(jR - pb[e], ny, A.bcy) * nx;
+                const real sLp = msign<real>(iL + pa[e], nx, fx), sLm = msign<real>(iL - pa[e], nx, fx);
+                const real sRp = msign<real>(iR + pa[e], nx, fx), sRm = msign<real>(iR - pa[e], nx, fx);
+                const real tLp = msign<real>(jL + pb[e], ny, fy), tLm = msign<real>(jL - pb[e], ny, fy);
+                const real tRp = msign<real>(jR + pb[e], ny, fy), tRm = msign<real>(jR - pb[e], ny, fy);
+                parity4(sLp * tLp * U[yLp + xLp], sLm * tLp * U[yLp + xLm], sLp * tLm * U[yLm + xLp],
+                        sLm * tLm * U[yLm + xLm], QL[e]);
+                parity4(sRp * tRp * U[yRp + xRp], sRm * tRp * U[yRp + xRm], sRp * tRm * U[yRm + xRp],
+                        sRm * tRm * U[yRm + xRm], QR[e]);
             }
             R = min((int)A.order[cL], (int)A.order[cR]);
             const real *wt = wl + (R * 2 + dir) * kGtabPerDir;
@@ -456,13 +477,19 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
 #pragma unroll 1
             for (int e = 6; e < np; ++e) {
                 const int a = (int)((kPosA >> (4 * e)) & 15u), b = (int)((kPosB >> (4 * e)) & 15u);
-                const int xLp = wrap(iL + a, nx, A.bcx), xLm = wrap(iL - a, nx, A.bcx);
-                const int xRp = wrap(iR + a, nx, A.bcx), xRm = wrap(iR - a, nx, A.bcx);
-                const size_t yLp = (size_t)wrap(jL + b, ny, A.bcy) * nx, yLm = (size_t)wrap(jL - b, ny, A.bcy) * nx;
-                const size_t yRp = (size_t)wrap(jR + b, ny, A.bcy) * nx, yRm = (size_t)wrap(jR - b, ny, A.bcy) * nx;
+                const int xLp = wrap<WALLS>(iL + a, nx, A.bcx), xLm = wrap<WALLS>(iL - a, nx, A.bcx);
+                const int xRp = wrap<WALLS>(iR + a, nx, A.bcx), xRm = wrap<WALLS>(iR - a, nx, A.bcx);
+                const size_t yLp = (size_t)wrap<WALLS>(jL + b, ny, A.bcy) * nx, yLm = (size_t)wrap<WALLS>(jL - b, ny, A.bcy) * nx;
+                const size_t yRp = (size_t)wrap<WALLS>(jR + b, ny, A.bcy) * nx, yRm = (size_t)wrap<WALLS>(jR - b, ny, A.bcy) * nx;
+                const real sLp = msign<real>(iL + a, nx, fx), sLm = msign<real>(iL - a, nx, fx);
+                const real sRp = msign<real>(iR + a, nx, fx), sRm = msign<real>(iR - a, nx, fx);
+                const real tLp = msign<real>(jL + b, ny, fy), tLm = msign<real>(jL - b, ny, fy);
+                const real tRp = msign<real>(jR + b, ny, fy), tRm = msign<real>(jR - b, ny, fy);
                 real ql[4], qr[4];
-                parity4(U[yLp + xLp], U[yLp + xLm], U[yLm + xLp], U[yLm + xLm], ql);
-                parity4(U[yRp + xRp], U[yRp + xRm], U[yRm + xRp], U[yRm + xRm], qr);
+                parity4(sLp * tLp * U[yLp + xLp], sLm * tLp * U[yLp + xLm], sLp * tLm * U[yLm + xLp],
+                        sLm * tLm * U[yLm + xLm], ql);
+                parity4(sRp * tRp * U[yRp + xRp], sRm * tRp * U[yRp + xRm], sRp * tRm * U[yRm + xRp],
+                        sRm * tRm * U[yRm + xRm], qr);
 #pragma unroll
                 for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -555,7 +582,7 @@ struct CellIn {
     real un[4];       // U^n of the cell (stages 1, 2)
 };
 
-template <typename real>
+template <bool WALLS, typename real>
 __device__ __forceinline__ void cell_load(const StageArgs<real> &A, int c, CellIn<real> &X)
 {
     const int nx = A.nx, ny = A.ny;
@@ -567,8 +594,8 @@ __device__ __forceinline__ void cell_load(const StageArgs<real> &A, int c, CellI
     int xc[5];
 #pragma unroll
     for (int d = 0; d < 5; ++d) {
-        yr[d] = (size_t)wrap(X.j + d - 2, ny, A.bcy) * nx;
-        xc[d] = wrap(X.i + d - 2, nx, A.bcx);
+        yr[d] = (size_t)wrap<WALLS>(X.j + d - 2, ny, A.bcy) * nx;
+        xc[d] = wrap<WALLS>(X.i + d - 2, nx, A.bcx);
     }
 #pragma unroll
     for (int m = 0; m < 13; ++m) X.rho[m] = A.Us[yr[kDj13[m] + 2] + xc[kDi13[m] + 2]];
@@ -576,6 +603,14 @@ __device__ __forceinline__ void cell_load(const StageArgs<real> &A, int c, CellI
     for (int m = 0; m < 5; ++m)
 #pragma unroll
         for (int w = 1; w < 4; ++w) X.mom[m][w - 1] = A.Us[w * plane + yr[kDj13[m] + 2] + xc[kDi13[m] + 2]];
+    // reflecting walls reverse the normal momentum of a mirrored face neighbour
+    if (WALLS) {
+#pragma unroll
+        for (int m = 1; m < 5; ++m) {
+            X.mom[m][0] *= msign<real>(X.i + kDi13[m], nx, A.bcx == 2);
+            X.mom[m][1] *= msign<real>(X.j + kDj13[m], ny, A.bcy == 2);
+        }
+    }
 #pragma unroll
     for (int w = 0; w < 4; ++w) X.un[w] = A.s == 0 ? real(0) : A.Un[w * plane + c];
     X.o = A.order[c];
@@ -620,7 +655,7 @@ __device__ __forceinline__ bool cell_finish(const StageArgs<real> &A, const Cell
     return tr;
 }
 
-template <typename real>
+template <bool WALLS, typename real>
 __device__ __forceinline__ void cells_phase(const StageArgs<real> &A, const int *clist, int n, int t0, int stride,
                                             const PassOut &P, int pre = 0, bool use_pre = false)
 {
@@ -633,7 +668,7 @@ __device__ __forceinline__ void cells_phase(const StageArgs<real> &A, const int 
         int i = 0, j = 0;
         if (valid) {
             CellIn<real> X;
-            cell_load(A, (use_pre && r == 0) ? pre : clist[idx], X);
+            cell_load<WALLS>(A, (use_pre && r == 0) ? pre : clist[idx], X);
             tr = cell_finish(A, X, dt);
             i = X.i;
             j = X.j;
@@ -663,7 +698,7 @@ __device__ __forceinline__ bool pass_runs(const Cascade &C, int k)
     return C.ctl->ncell[k] > 0 && C.ctl->ntroub[k - 1] > C.tail_thr;
 }
 
-template <typename real>
+template <typename real, bool WALLS>
 __global__ __launch_bounds__(256) void k_faces(const StageArgs<real> A, const Cascade C, int k)
 {
     __shared__ real wl[kGtabSize];
@@ -683,10 +718,10 @@ __global__ __launch_bounds__(256) void k_faces(const StageArgs<real> A, const Ca
     n = n < cap ? n : cap;  // a list holds each face at most once
     if (4 * n <= (int)(blockIdx.x * blockDim.x)) return;  // no face for this block
     __syncthreads();
-    faces_phase(A, wl, xch[threadIdx.x >> 6], C.flist[k & 1], n, t0, gridDim.x * blockDim.x, pre, true);
+    faces_phase<WALLS>(A, wl, xch[threadIdx.x >> 6], C.flist[k & 1], n, t0, gridDim.x * blockDim.x, pre, true);
 }
 
-template <typename real>
+template <typename real, bool WALLS>
 __global__ __launch_bounds__(64) void k_cells(const StageArgs<real> A, const Cascade C, int k)
 {
     const int cap = A.nx * A.ny;
@@ -697,7 +732,7 @@ __global__ __launch_bounds__(64) void k_cells(const StageArgs<real> A, const Cas
     int n = C.ctl->ncell[k];
     n = n < cap ? n : cap;  // a list holds each cell at most once
     if (n <= (int)(blockIdx.x * blockDim.x)) return;
-    cells_phase(A, C.clist[k & 1], n, t0, gridDim.x * blockDim.x, pass_out(C, k, C.ctl->stamp0), pre, true);
+    cells_phase<WALLS>(A, C.clist[k & 1], n, t0, gridDim.x * blockDim.x, pass_out(C, k, C.ctl->stamp0), pre, true);
 }
 
 // The tail of a long cascade (few troubled cells per pass) in one workgroup:
@@ -717,7 +752,7 @@ struct TailShared {
     int kfirst;
 };
 
-template <typename real>
+template <bool WALLS, typename real>
 __device__ __forceinline__ void tail_body(const StageArgs<real> &A, const Cascade &C, int kbeg, int kdef, int kend,
                                           TailShared<real> &S)
 {
@@ -778,8 +813,8 @@ __device__ __forceinline__ void tail_body(const StageArgs<real> &A, const Cascad
             const bool valid = cellwave && idx < nc;
             CellIn<real> X;
             X.i = X.j = 0;
-            if (valid) cell_load(A, C.clist[k & 1][idx], X);
-            if (!cellwave && wv < fw) faces_phase(A, S.wl, S.xch[wv], C.flist[k & 1], nf, threadIdx.x, 64 * fw);
+            if (valid) cell_load<WALLS>(A, C.clist[k & 1][idx], X);
+            if (!cellwave && wv < fw) faces_phase<WALLS>(A, S.wl, S.xch[wv], C.flist[k & 1], nf, threadIdx.x, 64 * fw);
             __syncthreads();
             if (cellwave) {
                 bool tr = false;
@@ -788,9 +823,9 @@ __device__ __forceinline__ void tail_body(const StageArgs<real> &A, const Cascad
                 claim_after_lowering(A, P, X.i, X.j, tr);
             }
         } else {
-            faces_phase(A, S.wl, S.xch[wv], C.flist[k & 1], nf, threadIdx.x, blockDim.x);
+            faces_phase<WALLS>(A, S.wl, S.xch[wv], C.flist[k & 1], nf, threadIdx.x, blockDim.x);
             __syncthreads();
-            cells_phase(A, C.clist[k & 1], nc, threadIdx.x, blockDim.x, P);
+            cells_phase<WALLS>(A, C.clist[k & 1], nc, threadIdx.x, blockDim.x, P);
         }
     }
     if (k >= kend) {
@@ -808,12 +843,12 @@ __device__ __forceinline__ void tail_body(const StageArgs<real> &A, const Cascad
     }
 }
 
-template <typename real>
+template <typename real, bool WALLS>
 __global__ __launch_bounds__(kTailThreads) void k_tail(const StageArgs<real> A, const Cascade C, int kbeg, int kdef,
                                                        int kend)
 {
     __shared__ TailShared<real> S;
-    tail_body(A, C, kbeg, kdef, kend, S);
+    tail_body<WALLS>(A, C, kbeg, kdef, kend, S);
 }
 
 // -------------------------------------------------------- small kernels
@@ -1040,7 +1075,7 @@ __global__ __launch_bounds__(64 * WPB, sizeof(real) == 4 ? 2 : 1) void k_first_p
 
 // Problem p = blockIdx.x makes the claims of the cells its first pass lowered,
 // then runs its whole cascade (no hand-back).
-template <typename real>
+template <typename real, bool WALLS>
 __global__ __launch_bounds__(kTailThreads) void k_tail_batch(const BatchTabs<real> B)
 {
     __shared__ TailShared<real> S;
@@ -1064,7 +1099,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_batch(const BatchTabs<rea
     }
     __threadfence();  // the claims' counts and lists are read below from device memory
     __syncthreads();
-    tail_body(A, C, 1, 1, kMaxPasses, S);
+    tail_body<WALLS>(A, C, 1, 1, kMaxPasses, S);
 }
 
 // Stage start of every problem: counts of evaluation 0 and pass 1, tail state,
@@ -1149,7 +1184,10 @@ hipError_t launch_batch_stage(const BatchTabs<real> &B, int top, int nfp_blocks,
     case 2: hipLaunchKernelGGL((k_first_pass_batch<real, 1, WPB, false>), g, t, 0, st, B); break;
     default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(k_tail_batch<real>, dim3(B.nprob), dim3(kTailThreads), 0, st, B);
+    if (B.walls)
+        hipLaunchKernelGGL((k_tail_batch<real, true>), dim3(B.nprob), dim3(kTailThreads), 0, st, B);
+    else
+        hipLaunchKernelGGL((k_tail_batch<real, false>), dim3(B.nprob), dim3(kTailThreads), 0, st, B);
     return hipGetLastError();
 }
 
@@ -1223,8 +1261,13 @@ hipError_t launch_first_pass(const StageArgs<real> &A, const PassOut &P, const C
 template <typename real>
 hipError_t launch_cascade_pass(const StageArgs<real> &A, const Cascade &C, int k, int nblocks, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_faces<real>, dim3(nblocks), dim3(256), 0, st, A, C, k);
-    hipLaunchKernelGGL(k_cells<real>, dim3(nblocks), dim3(64), 0, st, A, C, k);
+    if (A.bcx == 2 || A.bcy == 2) {
+        hipLaunchKernelGGL((k_faces<real, true>), dim3(nblocks), dim3(256), 0, st, A, C, k);
+        hipLaunchKernelGGL((k_cells<real, true>), dim3(nblocks), dim3(64), 0, st, A, C, k);
+    } else {
+        hipLaunchKernelGGL((k_faces<real, false>), dim3(nblocks), dim3(256), 0, st, A, C, k);
+        hipLaunchKernelGGL((k_cells<real, false>), dim3(nblocks), dim3(64), 0, st, A, C, k);
+    }
     return hipGetLastError();
 }
 
@@ -1232,7 +1275,10 @@ template <typename real>
 hipError_t launch_cascade_tail(const StageArgs<real> &A, const Cascade &C, int kbeg, int kdef, int kend,
                                hipStream_t st)
 {
-    hipLaunchKernelGGL(k_tail<real>, dim3(1), dim3(kTailThreads), 0, st, A, C, kbeg, kdef, kend);
+    if (A.bcx == 2 || A.bcy == 2)
+        hipLaunchKernelGGL((k_tail<real, true>), dim3(1), dim3(kTailThreads), 0, st, A, C, kbeg, kdef, kend);
+    else
+        hipLaunchKernelGGL((k_tail<real, false>), dim3(1), dim3(kTailThreads), 0, st, A, C, kbeg, kdef, kend);
     return hipGetLastError();
 }
 

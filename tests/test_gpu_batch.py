@@ -46,7 +46,7 @@ def _batch(torch_cuda, sizes, bc, cascade, prec, seed0):
 
 
 @pytest.mark.parametrize("bc,cascade,use_graph", [((1, 1), (3, 2, 1, 0), False), ((0, 0), (3, 1, 0), True),
-                                                  ((1, 0), (2, 1, 0), True)])
+                                                  ((1, 0), (2, 1, 0), True), ((2, 2), (3, 2, 1, 0), True)])
 def test_batch_matches_oracle_fp64(torch_cuda, bc, cascade, use_graph):
     nsteps = 2
     _note(f"batch f64 sizes={SIZES} bc={bc} cascade={cascade} graph={use_graph} steps={nsteps}")
@@ -101,4 +101,26 @@ def test_batch_equals_single_problem_contexts_fp32(torch_cuda):
         assert np.array_equal(g.gpm_get_state(), b.gpm_batch_get_state(k)), k
         assert np.array_equal(g.gpm_get_order_mask(), b.gpm_batch_get_order_mask(k)), k
         g.close()
+    b.close()
+
+
+def test_batch_u2_weights_are_per_problem(torch_cuda):
+    """Problems whose length scale is the same in cells share their reconstruction
+    weights, but not the u2 curvature weights, which are second derivatives in
+    physical units (1 / dx^2).  An 8^2 problem ahead of a 96^2 one: the 96^2 problem
+    (y walls, where u2 decides cells near the wall in the second step) must match the
+    oracle run of it alone."""
+    from paper_2110_08683_amd import GPMoodBatch
+    sizes = [(8, 8), (96, 96)]
+    _note("batch u2 weights per problem: 8^2 + 96^2, bc (1, 2), cascade (1, 0), 2 steps")
+    b = GPMoodBatch(sizes, bc=(1, 2), prec="f64", cascade=(1, 0), device="cuda:0")
+    U0s = [gi.density_wave(8, 8), gi.quadrants(96, 96, seed=23)]
+    for k, U0 in enumerate(U0s):
+        b.gpm_batch_init_state(k, U0)
+    b.gpm_batch_step(0.8, 2, use_graph=False)
+    for k, (nx, ny) in enumerate(sizes):
+        Uo = oracle.Oracle(nx, ny, bc=(1, 2), cascade=(1, 0)).run(U0s[k], cfl=0.8, nsteps=2)[0]
+        err = _rel_l1(b.gpm_batch_get_state(k), Uo)
+        _note(f"  problem {k} {nx}x{ny}: rel L1 {err:.2e}")
+        assert err <= 1e-12
     b.close()
