@@ -217,6 +217,30 @@ __device__ __forceinline__ real wq(const Weights<real> &W, int dir, int slot, in
     else return W.w1[dir][0][e];
 }
 
+// The four parity sums of the mirror cells pp = (+a,+b), mp = (-a,+b),
+// pm = (+a,-b), mm = (-a,-b), paired along the diagonals so that exchanging the
+// axes (pm <-> mp) leaves EE and OO unchanged and swaps OE and EO bit for bit: a
+// problem symmetric under x <-> y stays exactly symmetric.
+template <typename real>
+__device__ __forceinline__ void parity_sums(real pp, real mp, real pm, real mm, real &ee, real &oe, real &eo,
+                                            real &oo)
+{
+    const real s = pp + mm, t = pm + mp, d = pp - mm, u = pm - mp;
+    ee = s + t;
+    oo = s - t;
+    oe = d + u;
+    eo = d - u;
+}
+
+// Sum of an x and a y term that is not fused with the products that formed them
+// (a fused form would round the two axes differently).
+template <typename real>
+__device__ __forceinline__ real axis_sum(real x, real y)
+{
+#pragma clang fp contract(off)
+    return x + y;
+}
+
 // Parity sums Q[e] of one variable's radius-R stencil values; ld(di, dj) returns
 // the cell average at offset (di, dj).
 template <int R, typename real, typename Load>
@@ -237,11 +261,7 @@ __device__ __forceinline__ void build_Q(real (&Q)[kNQ[R]], Load ld)
             // four entries per (a, b): EE, OE, EO, OO in that order (see kQ)
             if (c == C_EE) {
                 const real pp = ld(a, b), mp = ld(-a, b), pm = ld(a, -b), mm = ld(-a, -b);
-                const real s1 = pp + mp, d1 = pp - mp, s2 = pm + mm, d2 = pm - mm;
-                Q[e] = s1 + s2;
-                Q[e + 1] = d1 + d2;
-                Q[e + 2] = s1 - s2;
-                Q[e + 3] = d1 - d2;
+                parity_sums(pp, mp, pm, mm, Q[e], Q[e + 1], Q[e + 2], Q[e + 3]);
             }
         }
     }
@@ -259,8 +279,10 @@ constexpr int transposed_entry(int e)
 // The 2q face states of one variable for direction DIR (0: x faces, 1: y faces):
 // sm[k] on the - face, sp[k] on the + face, node k in table order.  ISO: the grid
 // is isotropic (equal spacing and length scale, so the y weights are exactly the
-// transposed x weights) and the y states read the x table; the products and their
-// order are unchanged.
+// transposed x weights) and a y face computes what an x face computes on the
+// transposed grid: x weight e times the transposed entry, accumulated in the x
+// faces' order, so both axes round alike.  Without ISO the y weights are read at
+// the transposed entry in the same order (the same bits when they are isotropic).
 template <int R, int DIR, bool ISO = false, typename real>
 __device__ __forceinline__ void states_dir(const real (&Q)[kNQ[R]], const Weights<real> &W,
                                            real (&sm)[nodes_of(R)], real (&sp)[nodes_of(R)])
@@ -274,10 +296,13 @@ __device__ __forceinline__ void states_dir(const real (&Q)[kNQ[R]], const Weight
         const bool zero = slot_is_zero(R, p);
 #pragma unroll
         for (int e = 0; e < kNQ[R]; ++e) {
-            const int c = kQ[e].comp;
+            // y faces take the entries in the transposed order in both builds, so an
+            // isotropic grid gives the same bits whichever build runs it
+            const int et = DIR == 1 ? transposed_entry(e) : e;
+            const int c = kQ[et].comp;
             if (zero && (c == cN || c == C_OO)) continue;
-            const real w = (ISO && DIR == 1) ? wq<R>(W, 0, p, transposed_entry(e)) : wq<R>(W, DIR, p, e);
-            P[c] = fma(w, Q[e], P[c]);
+            const real w = DIR == 0 ? wq<R>(W, 0, p, e) : (ISO ? wq<R>(W, 0, p, e) : wq<R>(W, 1, p, et));
+            P[c] = fma(w, Q[et], P[c]);
         }
         const real A = P[C_EE] + P[cF];
         const real Bm = P[C_EE] - P[cF];
@@ -299,11 +324,7 @@ __device__ __forceinline__ void states_dir(const real (&Q)[kNQ[R]], const Weight
 template <typename real>
 __device__ __forceinline__ void parity4(real pp, real mp, real pm, real mm, real (&Q)[4])
 {
-    const real s1 = pp + mp, d1 = pp - mp, s2 = pm + mm, d2 = pm - mm;
-    Q[C_EE] = s1 + s2;
-    Q[C_OE] = d1 + d2;
-    Q[C_EO] = s1 - s2;
-    Q[C_OO] = d1 - d2;
+    parity_sums(pp, mp, pm, mm, Q[C_EE], Q[C_OE], Q[C_EO], Q[C_OO]);
 }
 
 // HLLC flux through a face normal to axis DIR.  badL / badR: the density or the

@@ -266,7 +266,7 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     us[v] = ring[slot][v][lane + 3];
-                    ust[v] = us[v] - dt * (dv(dFxP[v], A.dx) + dv(G[v] - Gprev[v], A.dy));
+                    ust[v] = us[v] - dt * axis_sum(dv(dFxP[v], A.dx), dv(G[v] - Gprev[v], A.dy));
                 }
                 const bool rs = rsxP || rsymP || badLy;
                 auto nb = [&](int di, int dj, int v) { return ring[(jr + dj) & 7][v][lane + 3 + di]; };
@@ -407,6 +407,7 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
         const int idx = (r * stride + t0) >> 2;
         const bool valid = idx < n;
         int dir = 0, R = 0, fo = 0;
+        bool tr = false;
         real PL[2][4], PR[2][4];  // [slot][component] of variable v, left and right cell
 #pragma unroll
         for (int p = 0; p < 2; ++p)
@@ -434,6 +435,9 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
                 cR = wrap<WALLS>(j, ny, A.bcy) * nx + i;
             }
             const int iR = iL + (dir == 0), jR = jL + (dir == 1);
+            // an isotropic y face computes what an x face computes on the transposed
+            // grid: position (a, b) is gathered at offset (b, a) and the x table used
+            tr = dir == 1 && A.iso;
             const real *U = A.Us + v * plane;
             // reflecting walls reverse the normal momentum of mirrored cells (WALLS:
             // the variant built for grids with a reflecting axis)
@@ -443,23 +447,29 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
             real QL[6][4], QR[6][4];
 #pragma unroll
             for (int e = 0; e < 6; ++e) {
-                const int xLp = wrap<WALLS>(iL + pa[e], nx, A.bcx), xLm = wrap<WALLS>(iL - pa[e], nx, A.bcx);
-                const int xRp = wrap<WALLS>(iR + pa[e], nx, A.bcx), xRm = wrap<WALLS>(iR - pa[e], nx, A.bcx);
-                const size_t yLp = (size_t)wrap<WALLS>(jL + pb[e], ny, A.bcy) * nx;
-                const size_t yLm = (size_t)wrap<WALLS>(jL - pb[e], ny, A.bcy) * nx;
-                const size_t yRp = (size_t)wrap<WALLS>(jR + pb[e], ny, A.bcy) * nx;
-                const size_t yRm = (size_t)wrap<WALLS>(jR - pb[e], ny, A.bcy) * nx;
-                const real sLp = msign<real>(iL + pa[e], nx, fx), sLm = msign<real>(iL - pa[e], nx, fx);
-                const real sRp = msign<real>(iR + pa[e], nx, fx), sRm = msign<real>(iR - pa[e], nx, fx);
-                const real tLp = msign<real>(jL + pb[e], ny, fy), tLm = msign<real>(jL - pb[e], ny, fy);
-                const real tRp = msign<real>(jR + pb[e], ny, fy), tRm = msign<real>(jR - pb[e], ny, fy);
-                parity4(sLp * tLp * U[yLp + xLp], sLm * tLp * U[yLp + xLm], sLp * tLm * U[yLm + xLp],
-                        sLm * tLm * U[yLm + xLm], QL[e]);
-                parity4(sRp * tRp * U[yRp + xRp], sRm * tRp * U[yRp + xRm], sRp * tRm * U[yRm + xRp],
-                        sRm * tRm * U[yRm + xRm], QR[e]);
+                const int ea = tr ? pb[e] : pa[e], eb = tr ? pa[e] : pb[e];  // x and y offsets
+                const int xLp = wrap<WALLS>(iL + ea, nx, A.bcx), xLm = wrap<WALLS>(iL - ea, nx, A.bcx);
+                const int xRp = wrap<WALLS>(iR + ea, nx, A.bcx), xRm = wrap<WALLS>(iR - ea, nx, A.bcx);
+                const size_t yLp = (size_t)wrap<WALLS>(jL + eb, ny, A.bcy) * nx;
+                const size_t yLm = (size_t)wrap<WALLS>(jL - eb, ny, A.bcy) * nx;
+                const size_t yRp = (size_t)wrap<WALLS>(jR + eb, ny, A.bcy) * nx;
+                const size_t yRm = (size_t)wrap<WALLS>(jR - eb, ny, A.bcy) * nx;
+                const real sLp = msign<real>(iL + ea, nx, fx), sLm = msign<real>(iL - ea, nx, fx);
+                const real sRp = msign<real>(iR + ea, nx, fx), sRm = msign<real>(iR - ea, nx, fx);
+                const real tLp = msign<real>(jL + eb, ny, fy), tLm = msign<real>(jL - eb, ny, fy);
+                const real tRp = msign<real>(jR + eb, ny, fy), tRm = msign<real>(jR - eb, ny, fy);
+                // mirror cells in the frame of the face: first index across it
+                const real Lpp = sLp * tLp * U[yLp + xLp], Lmm = sLm * tLm * U[yLm + xLm];
+                const real Lpm = tr ? sLm * tLp * U[yLp + xLm] : sLp * tLm * U[yLm + xLp];
+                const real Lmp = tr ? sLp * tLm * U[yLm + xLp] : sLm * tLp * U[yLp + xLm];
+                const real Rpp = sRp * tRp * U[yRp + xRp], Rmm = sRm * tRm * U[yRm + xRm];
+                const real Rpm = tr ? sRm * tRp * U[yRp + xRm] : sRp * tRm * U[yRm + xRp];
+                const real Rmp = tr ? sRp * tRm * U[yRm + xRp] : sRm * tRp * U[yRp + xRm];
+                parity4(Lpp, Lmp, Lpm, Lmm, QL[e]);
+                parity4(Rpp, Rmp, Rpm, Rmm, QR[e]);
             }
             R = min((int)A.order[cL], (int)A.order[cR]);
-            const real *wt = wl + (R * 2 + dir) * kGtabPerDir;
+            const real *wt = wl + (R * 2 + (tr ? 0 : dir)) * kGtabPerDir;
             const int np = R <= 0 ? 1 : (R == 1 ? 3 : (R == 2 ? 6 : 10));
 #pragma unroll
             for (int e = 0; e < 6; ++e) {
@@ -476,7 +486,8 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
             }
 #pragma unroll 1
             for (int e = 6; e < np; ++e) {
-                const int a = (int)((kPosA >> (4 * e)) & 15u), b = (int)((kPosB >> (4 * e)) & 15u);
+                const int a0 = (int)((kPosA >> (4 * e)) & 15u), b0 = (int)((kPosB >> (4 * e)) & 15u);
+                const int a = tr ? b0 : a0, b = tr ? a0 : b0;  // x and y offsets
                 const int xLp = wrap<WALLS>(iL + a, nx, A.bcx), xLm = wrap<WALLS>(iL - a, nx, A.bcx);
                 const int xRp = wrap<WALLS>(iR + a, nx, A.bcx), xRm = wrap<WALLS>(iR - a, nx, A.bcx);
                 const size_t yLp = (size_t)wrap<WALLS>(jL + b, ny, A.bcy) * nx, yLm = (size_t)wrap<WALLS>(jL - b, ny, A.bcy) * nx;
@@ -485,11 +496,15 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
                 const real sRp = msign<real>(iR + a, nx, fx), sRm = msign<real>(iR - a, nx, fx);
                 const real tLp = msign<real>(jL + b, ny, fy), tLm = msign<real>(jL - b, ny, fy);
                 const real tRp = msign<real>(jR + b, ny, fy), tRm = msign<real>(jR - b, ny, fy);
+                const real Lpp = sLp * tLp * U[yLp + xLp], Lmm = sLm * tLm * U[yLm + xLm];
+                const real Lpm = tr ? sLm * tLp * U[yLp + xLm] : sLp * tLm * U[yLm + xLp];
+                const real Lmp = tr ? sLp * tLm * U[yLm + xLp] : sLm * tLp * U[yLp + xLm];
+                const real Rpp = sRp * tRp * U[yRp + xRp], Rmm = sRm * tRm * U[yRm + xRm];
+                const real Rpm = tr ? sRm * tRp * U[yRp + xRm] : sRp * tRm * U[yRm + xRp];
+                const real Rmp = tr ? sRp * tRm * U[yRm + xRp] : sRm * tRp * U[yRp + xRm];
                 real ql[4], qr[4];
-                parity4(sLp * tLp * U[yLp + xLp], sLm * tLp * U[yLp + xLm], sLp * tLm * U[yLm + xLp],
-                        sLm * tLm * U[yLm + xLm], ql);
-                parity4(sRp * tRp * U[yRp + xRp], sRm * tRp * U[yRp + xRm], sRp * tRm * U[yRm + xRp],
-                        sRm * tRm * U[yRm + xRm], qr);
+                parity4(Lpp, Lmp, Lpm, Lmm, ql);
+                parity4(Rpp, Rmp, Rpm, Rmm, qr);
 #pragma unroll
                 for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -512,8 +527,10 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
             const real leo = slot ? PL[1][C_EO] : PL[0][C_EO], loo = slot ? PL[1][C_OO] : PL[0][C_OO];
             const real ree = slot ? PR[1][C_EE] : PR[0][C_EE], roe = slot ? PR[1][C_OE] : PR[0][C_OE];
             const real reo = slot ? PR[1][C_EO] : PR[0][C_EO], roo = slot ? PR[1][C_OO] : PR[0][C_OO];
-            const real lF = dir ? leo : loe, lN = dir ? loe : leo;  // odd across / along the face
-            const real rF = dir ? reo : roe, rN = dir ? roe : reo;
+            // odd across / along the face (a transposed y face is in the x-face frame)
+            const bool yframe = dir == 1 && !tr;
+            const real lF = yframe ? leo : loe, lN = yframe ? loe : leo;
+            const real rF = yframe ? reo : roe, rN = yframe ? roe : reo;
             const real Ap = lee + lF, Cp = lN + loo;  // + face of the left cell
             const real Bm = ree - rF, Dm = rN - roo;  // - face of the right cell
             X.s[lane][k] = single ? Ap : (plus ? Ap + Cp : Ap - Cp);
@@ -639,7 +656,7 @@ __device__ __forceinline__ bool cell_finish(const StageArgs<real> &A, const Cell
     for (int w = 0; w < 4; ++w) {
         const real us = w == 0 ? X.rho[0] : X.mom[0][w - 1];
         const real dFx = fx[w][1] - fx[w][0];
-        ust[w] = us - dt * (dv(dFx, A.dx) + dv(gy[w][1] - gy[w][0], A.dy));
+        ust[w] = us - dt * axis_sum(dv(dFx, A.dx), dv(gy[w][1] - gy[w][0], A.dy));
     }
     auto nb = [&](int di, int dj, int w) -> real {
         int m = 0;
