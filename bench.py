@@ -283,6 +283,70 @@ def cpu_baseline(U0):
                       % (CPU_STEPS, 3 * CPU_STEPS, int(iters.sum()), el)}
 
 
+# The implosion of Sec. "The implosion problem in 2D" as the paper runs it (400^2,
+# t = 2.5, SSP-RK3, CFL 0.8, ell = 12 dx), its six method variants: name, stencil,
+# cascade, CSD on.
+IMPLOSION_VARIANTS = [
+    ("POL-MOOD3 without CSD", "poly3", (1, 0), False),
+    ("GP-MOOD3 without CSD", "diamond", (1, 0), False),
+    ("POL-MOOD3 with CSD", "poly3", (1, 0), True),
+    ("GP-MOOD3 with CSD", "diamond", (1, 0), True),
+    ("GP-MOOD5 with CSD", "diamond", (2, 1, 0), True),
+    ("GP-MOOD7 with CSD", "diamond", (3, 1, 0), True),
+]
+
+
+def run_implosion(name, stencil, cascade, csd, prec, n=400, tend=2.5, cfl=0.8):
+    """One implosion run to t = tend (the last step clipped): steps, wall time, the
+    largest x <-> y asymmetry seen (max |rho - rho^T| / max rho, checked every 100
+    steps and at the end), the largest fraction of cells a step ends below the top
+    order, and the densest point on the diagonal (the jet)."""
+    import numpy as np
+    import gpmood_inputs as gi
+    from paper_2110_08683_amd import GPM_CSD, GPM_FLAGS_ALL, GPMood
+    flags = GPM_FLAGS_ALL if csd else GPM_FLAGS_ALL & ~GPM_CSD
+    g = GPMood(n, n, hi=(0.3, 0.3), bc=(2, 2), prec=prec, cascade=cascade, flags=flags, stencil=stencil)
+    g.gpm_init_state(gi.implosion(n))
+    t, k, frac, asym = 0.0, 0, 0.0, 0.0
+    t0 = time.time()
+    while t < tend * (1.0 - 1e-14):
+        dt = min(g.gpm_compute_dt(cfl), tend - t)
+        g.gpm_set_dt(dt)
+        g.gpm_step(0.0, 1)
+        t += dt
+        k += 1
+        c, _ = g.gpm_troubled_counts()
+        frac = max(frac, float(c[1:].sum()) / (n * n))
+        if k % 100 == 0:
+            U = g.gpm_get_state()
+            asym = max(asym, float(np.abs(U[0] - U[0].T).max() / U[0].max()))
+    wall = time.time() - t0
+    U = g.gpm_get_state()
+    asym = max(asym, float(np.abs(U[0] - U[0].T).max() / U[0].max()))
+    diag = np.diagonal(U[0])
+    kmax = int(np.argmax(diag))
+    return {"variant": name, "prec": prec, "steps": k, "t": t, "wall_s": wall,
+            "asymmetry_max": asym, "lowered_fraction_max": frac,
+            "rho_min": float(U[0].min()), "diag_rho_max": float(diag[kmax]),
+            "diag_rho_max_distance": float((kmax + 0.5) * 0.3 / n * np.sqrt(2.0))}
+
+
+def implosion_line():
+    out = []
+    for name, stencil, cascade, csd in IMPLOSION_VARIANTS:
+        r = run_implosion(name, stencil, cascade, csd, "f64")
+        print(f"[bench] implosion {name} f64: {r['steps']} steps {r['wall_s']:.1f} s, "
+              f"asymmetry {r['asymmetry_max']:.1e}", file=sys.stderr, flush=True)
+        out.append(r)
+    name, stencil, cascade, csd = IMPLOSION_VARIANTS[-1]
+    r = run_implosion(name, stencil, cascade, csd, "f32")
+    print(f"[bench] implosion {name} f32: {r['steps']} steps {r['wall_s']:.1f} s, "
+          f"asymmetry {r['asymmetry_max']:.1e}", file=sys.stderr, flush=True)
+    out.append(r)
+    return {"workload": "implosion 400^2 on [0,0.3]^2, reflecting walls, t = 2.5, SSP-RK3, CFL 0.8, ell = 12 dx",
+            "data": "synthetic", "runs": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -297,10 +361,15 @@ def main():
     ap.add_argument("--steps-3d", type=int, default=5, help="steps of the 3D blast leg (0 skips it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--implosion", action="store_true",
+                    help="instead of the throughput line, run the paper's implosion variants (400^2 to t = 2.5)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {a.gpus})", file=sys.stderr)
         sys.exit(2)
+    if a.implosion:
+        print(json.dumps(implosion_line()), flush=True)
+        return
     import gpmood_inputs as gi
     if a.copy_probe:
         import torch

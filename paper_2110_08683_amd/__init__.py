@@ -8,7 +8,7 @@
 
 The binding only marshals arguments; all arithmetic runs in libgpmood.so.
 """
-from .binding import (EXPORTS, GPM_BC_OUTFLOW, GPM_BC_PERIODIC, GPM_CSD, GPM_F32, GPM_F64,
+from .binding import (EXPORTS, GPM_BC_OUTFLOW, GPM_BC_PERIODIC, GPM_BC_REFLECT, GPM_CSD, GPM_F32, GPM_F64,
                       GPM_FLAGS_ALL, GPM_PLATEAU, GPM_RSCAD, GPM_U2, GPMood, GPMood3D, GPMoodBatch, GpmError, LIB_PATH, lib)
 
 __all__ = ["GPMood", "GPMood3D", "GPMoodBatch", "GpmError", "lib", "LIB_PATH", "EXPORTS", "GPM_F32", "GPM_F64",
