@@ -447,26 +447,58 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
             real QL[6][4], QR[6][4];
 #pragma unroll
             for (int e = 0; e < 6; ++e) {
-                const int ea = tr ? pb[e] : pa[e], eb = tr ? pa[e] : pb[e];  // x and y offsets
-                const int xLp = wrap<WALLS>(iL + ea, nx, A.bcx), xLm = wrap<WALLS>(iL - ea, nx, A.bcx);
-                const int xRp = wrap<WALLS>(iR + ea, nx, A.bcx), xRm = wrap<WALLS>(iR - ea, nx, A.bcx);
-                const size_t yLp = (size_t)wrap<WALLS>(jL + eb, ny, A.bcy) * nx;
-                const size_t yLm = (size_t)wrap<WALLS>(jL - eb, ny, A.bcy) * nx;
-                const size_t yRp = (size_t)wrap<WALLS>(jR + eb, ny, A.bcy) * nx;
-                const size_t yRm = (size_t)wrap<WALLS>(jR - eb, ny, A.bcy) * nx;
-                const real sLp = msign<real>(iL + ea, nx, fx), sLm = msign<real>(iL - ea, nx, fx);
-                const real sRp = msign<real>(iR + ea, nx, fx), sRm = msign<real>(iR - ea, nx, fx);
-                const real tLp = msign<real>(jL + eb, ny, fy), tLm = msign<real>(jL - eb, ny, fy);
-                const real tRp = msign<real>(jR + eb, ny, fy), tRm = msign<real>(jR - eb, ny, fy);
-                // mirror cells in the frame of the face: first index across it
-                const real Lpp = sLp * tLp * U[yLp + xLp], Lmm = sLm * tLm * U[yLm + xLm];
-                const real Lpm = tr ? sLm * tLp * U[yLp + xLm] : sLp * tLm * U[yLm + xLp];
-                const real Lmp = tr ? sLp * tLm * U[yLm + xLp] : sLm * tLp * U[yLp + xLm];
-                const real Rpp = sRp * tRp * U[yRp + xRp], Rmm = sRm * tRm * U[yRm + xRm];
-                const real Rpm = tr ? sRm * tRp * U[yRp + xRm] : sRp * tRm * U[yRm + xRp];
-                const real Rmp = tr ? sRp * tRm * U[yRm + xRp] : sRm * tRp * U[yRp + xRm];
-                parity4(Lpp, Lmp, Lpm, Lmm, QL[e]);
-                parity4(Rpp, Rmp, Rpm, Rmm, QR[e]);
+                const int xLp = wrap<WALLS>(iL + pa[e], nx, A.bcx), xLm = wrap<WALLS>(iL - pa[e], nx, A.bcx);
+                const int xRp = wrap<WALLS>(iR + pa[e], nx, A.bcx), xRm = wrap<WALLS>(iR - pa[e], nx, A.bcx);
+                const size_t yLp = (size_t)wrap<WALLS>(jL + pb[e], ny, A.bcy) * nx;
+                const size_t yLm = (size_t)wrap<WALLS>(jL - pb[e], ny, A.bcy) * nx;
+                const size_t yRp = (size_t)wrap<WALLS>(jR + pb[e], ny, A.bcy) * nx;
+                const size_t yRm = (size_t)wrap<WALLS>(jR - pb[e], ny, A.bcy) * nx;
+                const real sLp = msign<real>(iL + pa[e], nx, fx), sLm = msign<real>(iL - pa[e], nx, fx);
+                const real sRp = msign<real>(iR + pa[e], nx, fx), sRm = msign<real>(iR - pa[e], nx, fx);
+                const real tLp = msign<real>(jL + pb[e], ny, fy), tLm = msign<real>(jL - pb[e], ny, fy);
+                const real tRp = msign<real>(jR + pb[e], ny, fy), tRm = msign<real>(jR - pb[e], ny, fy);
+                parity4(sLp * tLp * U[yLp + xLp], sLm * tLp * U[yLp + xLm], sLp * tLm * U[yLm + xLp],
+                        sLm * tLm * U[yLm + xLm], QL[e]);
+                parity4(sRp * tRp * U[yRp + xRp], sRm * tRp * U[yRp + xRm], sRp * tRm * U[yRm + xRp],
+                        sRm * tRm * U[yRm + xRm], QR[e]);
+            }
+            // a transposed y face takes position (a, b) from the gathered (b, a), OE and
+            // EO exchanged: with the diagonal pairing these are the bits a transposed
+            // gather would give
+            constexpr int T6[6] = {0, 2, 1, 4, 3, 5};
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                if (T6[e] == e) {
+                    const real lo = QL[e][C_OE], ro = QR[e][C_OE];
+                    QL[e][C_OE] = tr ? QL[e][C_EO] : lo;
+                    QL[e][C_EO] = tr ? lo : QL[e][C_EO];
+                    QR[e][C_OE] = tr ? QR[e][C_EO] : ro;
+                    QR[e][C_EO] = tr ? ro : QR[e][C_EO];
+                } else if (T6[e] > e) {
+                    const int f = T6[e];
+                    real l0[4], l1[4], r0[4], r1[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        l0[c] = QL[e][c]; l1[c] = QL[f][c];
+                        r0[c] = QR[e][c]; r1[c] = QR[f][c];
+                    }
+                    QL[e][C_EE] = tr ? l1[C_EE] : l0[C_EE];
+                    QL[e][C_OO] = tr ? l1[C_OO] : l0[C_OO];
+                    QL[e][C_OE] = tr ? l1[C_EO] : l0[C_OE];
+                    QL[e][C_EO] = tr ? l1[C_OE] : l0[C_EO];
+                    QL[f][C_EE] = tr ? l0[C_EE] : l1[C_EE];
+                    QL[f][C_OO] = tr ? l0[C_OO] : l1[C_OO];
+                    QL[f][C_OE] = tr ? l0[C_EO] : l1[C_OE];
+                    QL[f][C_EO] = tr ? l0[C_OE] : l1[C_EO];
+                    QR[e][C_EE] = tr ? r1[C_EE] : r0[C_EE];
+                    QR[e][C_OO] = tr ? r1[C_OO] : r0[C_OO];
+                    QR[e][C_OE] = tr ? r1[C_EO] : r0[C_OE];
+                    QR[e][C_EO] = tr ? r1[C_OE] : r0[C_EO];
+                    QR[f][C_EE] = tr ? r0[C_EE] : r1[C_EE];
+                    QR[f][C_OO] = tr ? r0[C_OO] : r1[C_OO];
+                    QR[f][C_OE] = tr ? r0[C_EO] : r1[C_OE];
+                    QR[f][C_EO] = tr ? r0[C_OE] : r1[C_EO];
+                }
             }
             R = min((int)A.order[cL], (int)A.order[cR]);
             const real *wt = wl + (R * 2 + (tr ? 0 : dir)) * kGtabPerDir;
