@@ -152,3 +152,19 @@ def test_implosion_diagonal_symmetry_is_exact(torch_cuda, prec):
     assert np.array_equal(U[3], U[3].T)
     assert np.array_equal(U[1], U[2].T)
     assert lowered > 0
+
+
+def test_stage_adjoint_rejects_walls(torch_cuda):
+    """The stage adjoint has periodic and outflow boundaries only: with a reflecting
+    axis it returns GPM_EUNSUPPORTED before any device work."""
+    from paper_2110_08683_amd.binding import GpmError
+    torch = torch_cuda
+    n = 16
+    g = _gp(n, n, bc=(2, 1), prec="f64")
+    dev = torch.device("cuda")
+    U = torch.from_numpy(gi.quadrants(n, n, seed=1)).to(dev)
+    lam = torch.zeros_like(U)
+    out = torch.empty_like(U)
+    order = torch.full((n, n), 3, dtype=torch.uint8, device=dev)
+    with pytest.raises(GpmError, match="periodic and outflow"):
+        g.gpm_stage_vjp(0, None, U, order, 1e-3, lam, out)
