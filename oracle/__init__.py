@@ -103,6 +103,7 @@ def lib():
                               ctypes.POINTER(ctypes.c_longlong), ip]
         L.orc_totals.argtypes = [cp, dp, dp]
         L.orc_hllc.argtypes = [ctypes.c_double, dp, dp, ctypes.c_int, dp]
+        L.orc_hll.argtypes = [ctypes.c_double, dp, dp, ctypes.c_int, dp]
         L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -125,6 +126,7 @@ class _Cfg(ctypes.Structure):
         ("off1", ctypes.POINTER(ctypes.c_int)),
         ("sigma_v", ctypes.c_double), ("sigma_p", ctypes.c_double),
         ("flags", ctypes.c_uint),
+        ("solver", ctypes.c_int),
     ]
 
 
@@ -144,10 +146,11 @@ class Oracle:
     ending in 0 (FOG).  ell: physical GP length scale.  shape: "diamond" (the
     blocky diamond), "cross" (the cross-shaped stencils of Sec. "Isentropic
     vortex") or "poly3" (POL-MOOD3: radius 1 with the polynomial weights).
+    solver: "hllc" (the default) or "hll" (the paper's solver for the Mach jets).
     """
 
     def __init__(self, nx, ny, lo=(0.0, 0.0), hi=(1.0, 1.0), bc=(0, 0), cascade=(3, 2, 1, 0),
-                 ell=None, gamma=1.4, sigma_v=5.0, sigma_p=5.0, flags=ORC_ALL, shape="diamond"):
+                 ell=None, gamma=1.4, sigma_v=5.0, sigma_p=5.0, flags=ORC_ALL, shape="diamond", solver="hllc"):
         self.nx, self.ny = int(nx), int(ny)
         self.dx = (hi[0] - lo[0]) / nx
         self.dy = (hi[1] - lo[1]) / ny
@@ -191,6 +194,9 @@ class Oracle:
         c.off1 = _ip(off1)
         c.sigma_v, c.sigma_p = sigma_v, sigma_p
         c.flags = flags
+        if solver not in ("hllc", "hll"):
+            raise ValueError("solver is 'hllc' or 'hll'")
+        c.solver = 1 if solver == "hll" else 0
         self.cfg = c
         self.gamma = gamma
 
@@ -300,6 +306,14 @@ def hllc(UL, UR, direction=0, gamma=1.4):
     UR = np.ascontiguousarray(UR, dtype=np.float64)
     F = np.zeros(4)
     lib().orc_hllc(float(gamma), _dp(UL), _dp(UR), int(direction), _dp(F))
+    return F
+
+
+def hll(UL, UR, direction=0, gamma=1.4):
+    UL = np.ascontiguousarray(UL, dtype=np.float64)
+    UR = np.ascontiguousarray(UR, dtype=np.float64)
+    F = np.zeros(4)
+    lib().orc_hll(float(gamma), _dp(UL), _dp(UR), int(direction), _dp(F))
     return F
 
 

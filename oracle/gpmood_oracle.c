@@ -51,6 +51,7 @@ typedef struct {
     const int *off1;    /* [5][2] R = 1 stencil offsets matching w2 */
     double sigma_v, sigma_p;
     unsigned flags;
+    int solver;         /* Riemann solver: 0 HLLC (the default), 1 HLL */
 } orc_cfg;
 
 /* ---------------------------------------------------------------- helpers */
@@ -143,6 +144,43 @@ static void hllc(double g, const double *UL, const double *UR, int dir, double *
 void orc_hllc(double g, const double *UL, const double *UR, int dir, double *F)
 {
     hllc(g, UL, UR, dir, F);
+}
+
+/* HLL flux (Sec. "Numerical results": the solver of the Mach-jet problems, after
+   Harten, Lax and van Leer), with HLLC's wave speed bounds: the left or right
+   physical flux outside [S_L, S_R], else the single intermediate state's flux
+   (S_R F_L - S_L F_R + S_L S_R (U_R - U_L)) / (S_R - S_L). */
+static void hll(double g, const double *UL, const double *UR, int dir, double *F)
+{
+    int n = 1 + dir, t = 2 - dir;
+    double rl = UL[0], ul = UL[n] / rl, vl = UL[t] / rl, El = UL[3];
+    double rr = UR[0], ur = UR[n] / rr, vr = UR[t] / rr, Er = UR[3];
+    double pl = (g - 1.0) * (El - 0.5 * rl * (ul * ul + vl * vl));
+    double pr = (g - 1.0) * (Er - 0.5 * rr * (ur * ur + vr * vr));
+    double cl = sqrt(g * pl / rl), cr = sqrt(g * pr / rr);
+    double SL = dmin(ul - cl, ur - cr);
+    double SR = dmax(ul + cl, ur + cr);
+    double uk[2][4] = {{rl, rl * ul, rl * vl, El}, {rr, rr * ur, rr * vr, Er}};
+    double fk[2][4] = {{rl * ul, rl * ul * ul + pl, rl * ul * vl, ul * (El + pl)},
+                       {rr * ur, rr * ur * ur + pr, rr * ur * vr, ur * (Er + pr)}};
+    double f[4];
+    for (int k = 0; k < 4; ++k) {
+        if (SL >= 0.0) f[k] = fk[0][k];
+        else if (SR <= 0.0) f[k] = fk[1][k];
+        else f[k] = (SR * fk[0][k] - SL * fk[1][k] + SL * SR * (uk[1][k] - uk[0][k])) / (SR - SL);
+    }
+    F[0] = f[0]; F[n] = f[1]; F[t] = f[2]; F[3] = f[3];
+}
+
+void orc_hll(double g, const double *UL, const double *UR, int dir, double *F)
+{
+    hll(g, UL, UR, dir, F);
+}
+
+static void riemann(const orc_cfg *c, const double *UL, const double *UR, int dir, double *F)
+{
+    if (c->solver == 1) hll(c->gamma, UL, UR, dir, F);
+    else hllc(c->gamma, UL, UR, dir, F);
 }
 
 /* --------------------------------------------------- GP reconstruction */
@@ -285,7 +323,7 @@ static void candidate(const orc_cfg *c, const ghosted *g, const int *order, doub
                 recon(c, g, l, 0, k, i, j, qR);     /* x- face of the right cell */
                 if (state_inadmissible(gam, qL)) bad |= 1;
                 if (state_inadmissible(gam, qR)) bad |= 2;
-                hllc(gam, qL, qR, 0, f);
+                riemann(c, qL, qR, 0, f);
                 for (int v = 0; v < NV; ++v) F[v] += c->qw[l][k] * f[v];
             }
             for (int v = 0; v < NV; ++v) Fx[((size_t)v * ny + j) * (nx + 1) + i] = F[v];
@@ -306,7 +344,7 @@ static void candidate(const orc_cfg *c, const ghosted *g, const int *order, doub
                 recon(c, g, l, 2, k, i, j, qR);     /* y- face of the upper cell */
                 if (state_inadmissible(gam, qL)) bad |= 1;
                 if (state_inadmissible(gam, qR)) bad |= 2;
-                hllc(gam, qL, qR, 1, f);
+                riemann(c, qL, qR, 1, f);
                 for (int v = 0; v < NV; ++v) G[v] += c->qw[l][k] * f[v];
             }
             for (int v = 0; v < NV; ++v) Gy[((size_t)v * (ny + 1) + j) * nx + i] = G[v];

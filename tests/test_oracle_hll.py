@@ -1,0 +1,94 @@
+"""Pins of the oracle's HLL solver (the Riemann solver the paper uses for its Mach-jet
+problems, with HLLC's wave speed bounds): consistency and upwinding, the closed form
+of its flux at a stationary contact (which HLLC resolves exactly and HLL diffuses),
+FOG + HLL converging to the exact Riemann solution, and the HLL scheme conserving
+on a periodic shock problem with the cascade at work."""
+import math
+
+import numpy as np
+import pytest
+
+import gpmood_inputs as gi
+import oracle
+from tests import exact_riemann
+
+G = 1.4
+
+
+def cons(r, u, v, p):
+    return np.array([r, r * u, r * v, p / (G - 1) + 0.5 * r * (u * u + v * v)])
+
+
+def phys_flux_x(U):
+    r, mx, my, E = U
+    u, v = mx / r, my / r
+    p = (G - 1) * (E - 0.5 * r * (u * u + v * v))
+    return np.array([mx, mx * u + p, my * u, u * (E + p)])
+
+
+def test_hll_consistency_and_upwinding():
+    rng = np.random.default_rng(17)
+    for _ in range(20):
+        U = cons(rng.uniform(0.1, 2), rng.uniform(-2, 2), rng.uniform(-2, 2), rng.uniform(0.05, 2))
+        np.testing.assert_allclose(oracle.hll(U, U, 0), phys_flux_x(U), rtol=1e-13, atol=1e-13)
+        Uy = U[[0, 2, 1, 3]]
+        np.testing.assert_allclose(oracle.hll(Uy, Uy, 1)[[0, 2, 1, 3]], phys_flux_x(U), rtol=1e-13, atol=1e-13)
+    # supersonic to the right / left: the upwind physical flux
+    UL, UR = cons(1.0, 5.0, 0.3, 1.0), cons(0.5, 4.5, -0.2, 0.8)
+    np.testing.assert_allclose(oracle.hll(UL, UR, 0), phys_flux_x(UL), rtol=1e-14)
+    UL, UR = cons(1.0, -5.0, 0.3, 1.0), cons(0.5, -4.5, -0.2, 0.8)
+    np.testing.assert_allclose(oracle.hll(UL, UR, 0), phys_flux_x(UR), rtol=1e-14)
+
+
+def test_hll_diffuses_a_stationary_contact():
+    # rho jumps 1 -> 0.1 at rest with p = 1: HLLC carries no mass; HLL, with bounds
+    # -c and +c (c the larger sound speed), carries -c (rho_R - rho_L) / 2 and a
+    # tangential-momentum and energy flux of the same form
+    rl, rr, p = 1.0, 0.1, 1.0
+    UL, UR = cons(rl, 0.0, 0.0, p), cons(rr, 0.0, 0.0, p)
+    c = math.sqrt(G * p / rr)
+    F = oracle.hll(UL, UR, 0)
+    assert abs(F[0] - (-c * (rr - rl) / 2)) <= 1e-14 * abs(F[0])
+    assert abs(F[1] - p) <= 1e-14  # the pressure, momentum differences vanish
+    assert F[3] == pytest.approx(0.0, abs=1e-14)  # equal energies (same p, at rest)
+    Fc = oracle.hllc(UL, UR, 0)
+    assert Fc[0] == 0.0 and abs(Fc[1] - p) <= 1e-14
+
+
+def test_fog_hll_shock_tube_matches_exact_riemann():
+    """FOG (cascade (0,)) + HLL on a Sod tube converges to the exact solution (more
+    diffusively than HLLC at the contact)."""
+    left, right, T = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 0.15
+    errs, errs_c = [], []
+    for nx in (100, 200, 400):
+        U0 = gi.shock_tube(nx, 2, left, right)
+        ex = exact_riemann.cell_average_density(left, right, nx, T)
+        for solver, out in (("hll", errs), ("hllc", errs_c)):
+            o = oracle.Oracle(nx, 2, hi=(1.0, 2.0 / nx), bc=(1, 0), cascade=(0,), solver=solver)
+            U = U0.copy()
+            t = 0.0
+            while t < T - 1e-14:
+                dt = min(o.dt(U, 0.8), T - t)
+                U, _, _, _ = o.run(U, fixed_dt=dt, nsteps=1)
+                t += dt
+            out.append(np.abs(U[0, 0] - ex).mean())
+            assert np.all(U[0] > 0)
+    assert errs[2] < 0.015
+    assert errs[0] / errs[1] > 1.3 and errs[1] / errs[2] > 1.3
+    assert all(e > ec for e, ec in zip(errs, errs_c))
+
+
+def test_hll_scheme_conserves_on_a_periodic_shock_problem():
+    n = 32
+    U0 = gi.quadrants(n, n, seed=2)
+    o = oracle.Oracle(n, n, bc=(0, 0), solver="hll")
+    t0 = o.totals(U0)
+    U, _, counts, _ = o.run(U0, cfl=0.8, nsteps=4)
+    np.testing.assert_allclose(o.totals(U), t0, rtol=1e-13, atol=1e-13)
+    assert counts[:, :, 1:].sum() > 0
+    assert np.all(U[0] > 0)
+    # and it is a different scheme from HLLC on the same problem
+    Uc = oracle.Oracle(n, n, bc=(0, 0)).run(U0, cfl=0.8, nsteps=4)[0]
+    assert np.abs(U - Uc).max() > 1e-6
+    with pytest.raises(ValueError):
+        oracle.Oracle(n, n, solver="roe")
