@@ -86,7 +86,13 @@ typedef struct {
     double sigma_v, sigma_p; /* CSD thresholds (paper: 5, 5) */
     unsigned flags;          /* GPM_* detection switches */
     int stencil;             /* GPM_STENCIL_*; 2D only (the 3D engine takes DIAMOND) */
+    int solver;              /* GPM_SOLVER_*; 2D stages only (3D and the stage adjoint take HLLC) */
 } gpm_scheme;
+
+/* Riemann solver (gpm_scheme.solver): HLLC, the paper's default, or HLL, the
+   solver of its Mach-jet problems (Sec. "Numerical results"), with HLLC's wave
+   speed bounds. */
+enum { GPM_SOLVER_HLLC = 0, GPM_SOLVER_HLL = 1 };
 
 /* Stencil of the GP levels (gpm_scheme.stencil): the blocky diamond (Sec. "The GP
    stencil"); the cross-shaped stencils of the convergence study (Sec. "Isentropic

@@ -45,10 +45,11 @@ class gpm_grid(ctypes.Structure):
 class gpm_scheme(ctypes.Structure):
     _fields_ = [("nlev", ctypes.c_int), ("radius", ctypes.c_int * 4), ("ell", ctypes.c_double),
                 ("sigma_v", ctypes.c_double), ("sigma_p", ctypes.c_double), ("flags", ctypes.c_uint),
-                ("stencil", ctypes.c_int)]
+                ("stencil", ctypes.c_int), ("solver", ctypes.c_int)]
 
 
 GPM_STENCILS = {"diamond": 0, "cross": 1, "poly3": 2}
+GPM_SOLVERS = {"hllc": 0, "hll": 1}
 
 
 class GpmError(RuntimeError):
@@ -142,12 +143,13 @@ class GPMood:
     """One 2D problem on the GPU: owns torch device buffers and a library context.
 
     nx, ny, lo, hi, bc=(bcx, bcy) with 0 periodic / 1 outflow / 2 reflecting wall, prec 'f32' | 'f64',
-    cascade = GP radii ending in 0, ell = physical length scale (None: 12 min(dx, dy)).
+    cascade = GP radii ending in 0, ell = physical length scale (None: 12 min(dx, dy)),
+    stencil "diamond" / "cross" / "poly3", solver "hllc" / "hll".
     """
 
     def __init__(self, nx, ny, lo=(0.0, 0.0), hi=(1.0, 1.0), bc=(0, 0), prec="f64",
                  cascade=(3, 2, 1, 0), ell=None, gamma=1.4, sigma_v=5.0, sigma_p=5.0,
-                 flags=GPM_FLAGS_ALL, stream=None, device=None, stencil="diamond"):
+                 flags=GPM_FLAGS_ALL, stream=None, device=None, stencil="diamond", solver="hllc"):
         import torch
         L = lib()
         self.torch = torch
@@ -174,6 +176,7 @@ class GPMood:
         s.ell = 0.0 if ell is None else float(ell)
         s.sigma_v, s.sigma_p, s.flags = sigma_v, sigma_p, flags
         s.stencil = GPM_STENCILS[stencil]
+        s.solver = GPM_SOLVERS[solver]
         self._check(L.gpm_set_scheme(self.ctx, ctypes.byref(s)))
         dx, dy = (hi[0] - lo[0]) / self.nx, (hi[1] - lo[1]) / self.ny
         self.ell = 12.0 * min(dx, dy) if ell is None else float(ell)
@@ -341,7 +344,8 @@ class GPMoodBatch:
     """
 
     def __init__(self, sizes, lo=(0.0, 0.0), hi=(1.0, 1.0), bc=(0, 0), prec="f32", cascade=(3, 2, 1, 0),
-                 ell=None, gamma=1.4, sigma_v=5.0, sigma_p=5.0, flags=GPM_FLAGS_ALL, stream=None, device=None):
+                 ell=None, gamma=1.4, sigma_v=5.0, sigma_p=5.0, flags=GPM_FLAGS_ALL, stream=None, device=None,
+                 solver="hllc"):
         import torch
         L = lib()
         self.device = torch.device(device if device is not None else "cuda")
@@ -369,6 +373,7 @@ class GPMoodBatch:
             s.radius[k] = r
         s.ell = 0.0 if ell is None else float(ell)
         s.sigma_v, s.sigma_p, s.flags = sigma_v, sigma_p, flags
+        s.solver = GPM_SOLVERS[solver]
         self._check(L.gpm_batch_set_scheme(self.b, ctypes.byref(s)))
         nb = ctypes.c_size_t()
         self._check(L.gpm_batch_workspace_size(self.b, ctypes.byref(nb)))

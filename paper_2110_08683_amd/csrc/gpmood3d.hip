@@ -868,6 +868,7 @@ gpm_status gpm3_set_scheme(gpm3_ctx *c, const gpm_scheme *s)
     if (!c || !s) return GPM_EINVAL;
     if (s->nlev < 1 || s->nlev > 3) return f3(c, GPM_EINVAL, "nlev must be 1..3");
     if (s->stencil != GPM_STENCIL_DIAMOND) return f3(c, GPM_EUNSUPPORTED, "the 3D engine uses the L1-ball stencil");
+    if (s->solver != GPM_SOLVER_HLLC) return f3(c, GPM_EUNSUPPORTED, "the 3D engine uses HLLC");
     for (int l = 0; l < s->nlev; ++l) {
         if (s->radius[l] < 0 || s->radius[l] > 2) return f3(c, GPM_EINVAL, "3D radius must be 0..2");
         if (l > 0 && !(s->radius[l] < s->radius[l - 1])) return f3(c, GPM_EINVAL, "cascade must strictly decrease");

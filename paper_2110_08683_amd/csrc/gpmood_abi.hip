@@ -94,6 +94,7 @@ gpm_status gpm_set_scheme(gpm_ctx *c, const gpm_scheme *s)
     if (!(s->ell >= 0.0)) return fail(c, GPM_EINVAL, "ell must be >= 0");
     if (s->stencil < GPM_STENCIL_DIAMOND || s->stencil > GPM_STENCIL_POLY3)
         return fail(c, GPM_EINVAL, "unknown stencil");
+    if (s->solver != GPM_SOLVER_HLLC && s->solver != GPM_SOLVER_HLL) return fail(c, GPM_EINVAL, "unknown solver");
     if (s->stencil == GPM_STENCIL_POLY3 && s->radius[0] != 1)
         return fail(c, GPM_EINVAL, "POL-MOOD3 has radius 1 (cascade {1, 0})");
     const double ell = s->ell > 0.0 ? s->ell : 12.0 * (c->dx < c->dy ? c->dx : c->dy);
@@ -547,6 +548,8 @@ gpm_status gpm_stage_vjp(gpm_ctx *c, int s, const void *Un, const void *Us, cons
         return fail(c, GPM_EINVAL, "adjoint outputs must not alias");
     if (c->grid.bc[0] == GPM_BC_REFLECT || c->grid.bc[1] == GPM_BC_REFLECT)
         return fail(c, GPM_EUNSUPPORTED, "the stage adjoint has periodic and outflow boundaries only");
+    if (c->scheme.solver != GPM_SOLVER_HLLC)
+        return fail(c, GPM_EUNSUPPORTED, "the stage adjoint differentiates the HLLC scheme only");
     return c->prec == GPM_F64 ? stage_vjp<double>(c, c->w64, s, Un, Us, order, dt, lam_out, lam_Us, lam_Un, dL_dell)
                               : stage_vjp<float>(c, c->w32, s, Un, Us, order, dt, lam_out, lam_Us, lam_Un, dL_dell);
 }

@@ -213,6 +213,7 @@ static BatchTabs<real> tabs(const gpm_batch *b, int rot, int s)
     B.nprob = b->nprob;
     B.iso = b->iso;
     B.walls = b->walls;
+    B.solver = b->ctx[0]->scheme.solver;
     return B;
 }
 

@@ -158,6 +158,7 @@ static inline void fill_args(const gpm_ctx *c, const Weights<real> &W, StageArgs
     A.ca = real(0);
     A.cb = real(1);
     A.iso = weights_isotropic(W, c->top);
+    A.solver = c->scheme.solver;
     A.flags = c->scheme.flags;
     A.dx = (real)c->dx;
     A.dy = (real)c->dy;

@@ -62,6 +62,7 @@ struct StageArgs {
     int rows;             // rows per wavefront march (first pass)
     int top;              // top radius
     int iso;              // 1: the y weights are exactly the transposed x weights
+    int solver;           // 0 HLLC, 1 HLL
     unsigned flags;
     int next[4];          // next radius of the cascade after radius r
     real dx, dy, gamma, sigma_v, sigma_p, plat_thr, delta;
@@ -369,6 +370,49 @@ __device__ __forceinline__ void hllc(real g, const real *UL, const real *UR, rea
     F[3] = f[3];
 }
 
+// HLL flux through a face normal to axis DIR (the solver of the Mach-jet problems,
+// after Harten, Lax and van Leer), with HLLC's wave speed bounds: the left or
+// right physical flux outside [S_L, S_R], else the flux of the single intermediate
+// state, (S_R F_L - S_L F_R + S_L S_R (U_R - U_L)) / (S_R - S_L).  badL / badR as
+// for hllc.
+template <int DIR, typename real>
+__device__ __forceinline__ void hll(real g, const real *UL, const real *UR, real *F, bool &badL, bool &badR)
+{
+    constexpr int n = 1 + DIR, t = 2 - DIR;
+    const real rl = UL[0], irl = dv(real(1), rl), ul = UL[n] * irl, vl = UL[t] * irl, El = UL[3];
+    const real rr = UR[0], irr = dv(real(1), rr), ur = UR[n] * irr, vr = UR[t] * irr, Er = UR[3];
+    const real pl = (g - real(1)) * (El - real(0.5) * rl * (ul * ul + vl * vl));
+    const real pr = (g - real(1)) * (Er - real(0.5) * rr * (ur * ur + vr * vr));
+    badL = !(pos_finite(rl) && pos_finite(pl));
+    badR = !(pos_finite(rr) && pos_finite(pr));
+    const real cl = sq(g * pl * irl), cr = sq(g * pr * irr);
+    const real SL = vmin(ul - cl, ur - cr);
+    const real SR = vmax(ul + cl, ur + cr);
+    const real fL[4] = {rl * ul, rl * ul * ul + pl, rl * ul * vl, ul * (El + pl)};
+    const real fR[4] = {rr * ur, rr * ur * ur + pr, rr * ur * vr, ur * (Er + pr)};
+    const real uL[4] = {rl, rl * ul, rl * vl, El};
+    const real uR[4] = {rr, rr * ur, rr * vr, Er};
+    const real iw = dv(real(1), SR - SL), ss = SL * SR;
+    real f[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const real fh = (SR * fL[k] - SL * fR[k] + ss * (uR[k] - uL[k])) * iw;
+        f[k] = SL >= real(0) ? fL[k] : (SR <= real(0) ? fR[k] : fh);
+    }
+    F[0] = f[0];
+    F[n] = f[1];
+    F[t] = f[2];
+    F[3] = f[3];
+}
+
+// The scheme's Riemann solver: HLLC, or HLL when HLL is set (a build of its own).
+template <int DIR, bool HLL, typename real>
+__device__ __forceinline__ void riemann(real g, const real *UL, const real *UR, real *F, bool &badL, bool &badR)
+{
+    if constexpr (HLL) hll<DIR>(g, UL, UR, F, badL, badR);
+    else hllc<DIR>(g, UL, UR, F, badL, badR);
+}
+
 // Stage combination of eq. (rk3): U^(1) = U*, hat U^(2) = (3 U^n + U*)/4,
 // U^(n+1) = (U^n + 2 U*)/3; s == 3: the general stage ca B + cb U* (ca = 0
 // ignores B), un holding B.
@@ -515,8 +559,9 @@ struct BatchTabs {
     const int *blk;
     const int *dblk;
     int nprob;
-    int iso;    // every problem's A.iso is 1
-    int walls;  // some problem has a reflecting axis
+    int iso;     // every problem's A.iso is 1
+    int walls;   // some problem has a reflecting axis
+    int solver;  // the scheme's Riemann solver (shared by the batch)
 };
 
 // Arguments of the stage adjoint: A carries U^n, U_s, the frozen final orders of

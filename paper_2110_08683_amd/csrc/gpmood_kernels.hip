@@ -116,7 +116,7 @@ __device__ __forceinline__ void claim_after_lowering(const StageArgs<real> &A, c
 // A lowered cell is only appended to P.clist (count P.ccount); its claims are
 // made after the pass (k_claims_first, or k_tail_batch in a batch), which keeps
 // the claim atomics, and the wait for their results, out of the march.
-template <typename real, int RT, bool ISO>
+template <typename real, int RT, bool ISO, bool HLL>
 __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const PassOut &P, int wid,
                                                 real (*ring)[4][LW])
 {
@@ -216,7 +216,7 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
 #pragma unroll
                 for (int v = 0; v < 4; ++v) ur[v] = __shfl_down(sxm[k][v], 1);
                 bool bl, br;
-                hllc<0>(g, sxp[k], ur, f, bl, br);
+                riemann<0, HLL>(g, sxp[k], ur, f, bl, br);
                 rsx = rsx || bl;
                 badNb = badNb || br;
                 const real w = node_weight<RT>(A.W, k);
@@ -243,7 +243,7 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
             for (int k = 0; k < q; ++k) {
                 real f[4];
                 bool bl, br;
-                hllc<1>(g, sypP[k], sym[k], f, bl, br);
+                riemann<1, HLL>(g, sypP[k], sym[k], f, bl, br);
                 badLy = badLy || bl;
                 badRy = badRy || br;
                 const real w = node_weight<RT>(A.W, k);
@@ -300,12 +300,12 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
     }
 }
 
-template <typename real, int RT, int WPB, bool ISO>
+template <typename real, int RT, int WPB, bool ISO, bool HLL>
 __global__ __launch_bounds__(64 * WPB, sizeof(real) == 4 ? 2 : 1) void k_first_pass(const StageArgs<real> A, const PassOut P)
 {
     __shared__ real ring_all[WPB][8][4][LW];
     const int wv = threadIdx.x >> 6;
-    first_pass_wave<real, RT, ISO>(A, P, xcd_tile(blockIdx.x, gridDim.x) * WPB + wv, ring_all[wv]);
+    first_pass_wave<real, RT, ISO, HLL>(A, P, xcd_tile(blockIdx.x, gridDim.x) * WPB + wv, ring_all[wv]);
 }
 
 // The claims of the cells the first pass lowered (listed in low, count *nlow):
@@ -333,16 +333,16 @@ __global__ __launch_bounds__(256) void k_claims_first(const StageArgs<real> A, c
 }
 
 // ------------------------------------------------------------- cascade pass
-// HLLC through a face normal to axis dir (runtime): the momenta are swapped into
-// the x-face form and back, so the arithmetic is that of hllc<dir>.
-template <typename real>
+// The Riemann solver through a face normal to axis dir (runtime): the momenta are
+// swapped into the x-face form and back, so the arithmetic is that of riemann<dir>.
+template <bool HLL, typename real>
 __device__ __forceinline__ void hllc_rt(real g, int dir, const real (&UL)[4], const real (&UR)[4], real (&F)[4],
                                         bool &badL, bool &badR)
 {
     const real L[4] = {UL[0], dir ? UL[2] : UL[1], dir ? UL[1] : UL[2], UL[3]};
     const real Rr[4] = {UR[0], dir ? UR[2] : UR[1], dir ? UR[1] : UR[2], UR[3]};
     real f[4];
-    hllc<0>(g, L, Rr, f, badL, badR);
+    riemann<0, HLL>(g, L, Rr, f, badL, badR);
     F[0] = f[0];
     F[1] = dir ? f[2] : f[1];
     F[2] = dir ? f[1] : f[2];
@@ -393,7 +393,7 @@ __device__ __forceinline__ void load_gtab(const real *gtab, real *wl)
 // wavefront (LDS exchange); wl is the LDS copy of the compact weight table.
 // pre: when use_pre, this thread's list entry of round 0, loaded by the caller
 // (while the count was still unknown).
-template <bool WALLS, typename real>
+template <bool WALLS, bool HLL, typename real>
 __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real *wl, FaceXchg<real> &X,
                                             const int *flist, int n, int t0, int stride, int pre = 0,
                                             bool use_pre = false)
@@ -579,7 +579,7 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
                 UR[w] = X.s[q0 + w][4 + v];
             }
             bool bl, br;
-            hllc_rt(A.gamma, dir, UL, UR, fk, bl, br);
+            hllc_rt<HLL>(A.gamma, dir, UL, UR, fk, bl, br);
             flg = (bl ? 1 : 0) | (br ? 2 : 0);
         }
         wave_lds_sync();
@@ -747,7 +747,7 @@ __device__ __forceinline__ bool pass_runs(const Cascade &C, int k)
     return C.ctl->ncell[k] > 0 && C.ctl->ntroub[k - 1] > C.tail_thr;
 }
 
-template <typename real, bool WALLS>
+template <typename real, bool WALLS, bool HLL>
 __global__ __launch_bounds__(256) void k_faces(const StageArgs<real> A, const Cascade C, int k)
 {
     __shared__ real wl[kGtabSize];
@@ -767,7 +767,7 @@ __global__ __launch_bounds__(256) void k_faces(const StageArgs<real> A, const Ca
     n = n < cap ? n : cap;  // a list holds each face at most once
     if (4 * n <= (int)(blockIdx.x * blockDim.x)) return;  // no face for this block
     __syncthreads();
-    faces_phase<WALLS>(A, wl, xch[threadIdx.x >> 6], C.flist[k & 1], n, t0, gridDim.x * blockDim.x, pre, true);
+    faces_phase<WALLS, HLL>(A, wl, xch[threadIdx.x >> 6], C.flist[k & 1], n, t0, gridDim.x * blockDim.x, pre, true);
 }
 
 template <typename real, bool WALLS>
@@ -801,7 +801,7 @@ struct TailShared {
     int kfirst;
 };
 
-template <bool WALLS, typename real>
+template <bool WALLS, bool HLL, typename real>
 __device__ __forceinline__ void tail_body(const StageArgs<real> &A, const Cascade &C, int kbeg, int kdef, int kend,
                                           TailShared<real> &S)
 {
@@ -863,7 +863,8 @@ __device__ __forceinline__ void tail_body(const StageArgs<real> &A, const Cascad
             CellIn<real> X;
             X.i = X.j = 0;
             if (valid) cell_load<WALLS>(A, C.clist[k & 1][idx], X);
-            if (!cellwave && wv < fw) faces_phase<WALLS>(A, S.wl, S.xch[wv], C.flist[k & 1], nf, threadIdx.x, 64 * fw);
+            if (!cellwave && wv < fw)
+                faces_phase<WALLS, HLL>(A, S.wl, S.xch[wv], C.flist[k & 1], nf, threadIdx.x, 64 * fw);
             __syncthreads();
             if (cellwave) {
                 bool tr = false;
@@ -872,7 +873,7 @@ __device__ __forceinline__ void tail_body(const StageArgs<real> &A, const Cascad
                 claim_after_lowering(A, P, X.i, X.j, tr);
             }
         } else {
-            faces_phase<WALLS>(A, S.wl, S.xch[wv], C.flist[k & 1], nf, threadIdx.x, blockDim.x);
+            faces_phase<WALLS, HLL>(A, S.wl, S.xch[wv], C.flist[k & 1], nf, threadIdx.x, blockDim.x);
             __syncthreads();
             cells_phase<WALLS>(A, C.clist[k & 1], nc, threadIdx.x, blockDim.x, P);
         }
@@ -892,12 +893,12 @@ __device__ __forceinline__ void tail_body(const StageArgs<real> &A, const Cascad
     }
 }
 
-template <typename real, bool WALLS>
+template <typename real, bool WALLS, bool HLL>
 __global__ __launch_bounds__(kTailThreads) void k_tail(const StageArgs<real> A, const Cascade C, int kbeg, int kdef,
                                                        int kend)
 {
     __shared__ TailShared<real> S;
-    tail_body<WALLS>(A, C, kbeg, kdef, kend, S);
+    tail_body<WALLS, HLL>(A, C, kbeg, kdef, kend, S);
 }
 
 // -------------------------------------------------------- small kernels
@@ -1106,7 +1107,7 @@ __device__ __forceinline__ int find_problem(cptr<int> prefix, int n, int b)
     return lo;
 }
 
-template <typename real, int RT, int WPB, bool ISO>
+template <typename real, int RT, int WPB, bool ISO, bool HLL>
 __global__ __launch_bounds__(64 * WPB, sizeof(real) == 4 ? 2 : 1) void k_first_pass_batch(const BatchTabs<real> B)
 {
     __shared__ real ring_all[WPB][8][4][LW];
@@ -1119,12 +1120,12 @@ __global__ __launch_bounds__(64 * WPB, sizeof(real) == 4 ? 2 : 1) void k_first_p
     Q.clist = C.clist[0];
     Q.ccount = &C.ctl->nlow;
     const int wv = threadIdx.x >> 6;
-    first_pass_wave<real, RT, ISO>(A, Q, (blockIdx.x - blk[p]) * WPB + wv, ring_all[wv]);
+    first_pass_wave<real, RT, ISO, HLL>(A, Q, (blockIdx.x - blk[p]) * WPB + wv, ring_all[wv]);
 }
 
 // Problem p = blockIdx.x makes the claims of the cells its first pass lowered,
 // then runs its whole cascade (no hand-back).
-template <typename real, bool WALLS>
+template <typename real, bool WALLS, bool HLL>
 __global__ __launch_bounds__(kTailThreads) void k_tail_batch(const BatchTabs<real> B)
 {
     __shared__ TailShared<real> S;
@@ -1148,7 +1149,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_batch(const BatchTabs<rea
     }
     __threadfence();  // the claims' counts and lists are read below from device memory
     __syncthreads();
-    tail_body<WALLS>(A, C, 1, 1, kMaxPasses, S);
+    tail_body<WALLS, HLL>(A, C, 1, 1, kMaxPasses, S);
 }
 
 // Stage start of every problem: counts of evaluation 0 and pass 1, tail state,
@@ -1224,19 +1225,35 @@ hipError_t launch_batch_stage(const BatchTabs<real> &B, int top, int nfp_blocks,
     const int nb = (B.nprob + 255) / 256;
     hipLaunchKernelGGL(k_reset_batch, dim3(nb), dim3(256), 0, st, casc, B.nprob);
     const dim3 g(nfp_blocks), t(64 * WPB);
+    if (B.solver == 1) {
+        switch (top * 2 + (B.iso ? 1 : 0)) {
+        case 7: hipLaunchKernelGGL((k_first_pass_batch<real, 3, WPB, true, true>), g, t, 0, st, B); break;
+        case 6: hipLaunchKernelGGL((k_first_pass_batch<real, 3, WPB, false, true>), g, t, 0, st, B); break;
+        case 5: hipLaunchKernelGGL((k_first_pass_batch<real, 2, WPB, true, true>), g, t, 0, st, B); break;
+        case 4: hipLaunchKernelGGL((k_first_pass_batch<real, 2, WPB, false, true>), g, t, 0, st, B); break;
+        case 3: hipLaunchKernelGGL((k_first_pass_batch<real, 1, WPB, true, true>), g, t, 0, st, B); break;
+        case 2: hipLaunchKernelGGL((k_first_pass_batch<real, 1, WPB, false, true>), g, t, 0, st, B); break;
+        default: return hipErrorInvalidValue;
+        }
+        if (B.walls)
+            hipLaunchKernelGGL((k_tail_batch<real, true, true>), dim3(B.nprob), dim3(kTailThreads), 0, st, B);
+        else
+            hipLaunchKernelGGL((k_tail_batch<real, false, true>), dim3(B.nprob), dim3(kTailThreads), 0, st, B);
+        return hipGetLastError();
+    }
     switch (top * 2 + (B.iso ? 1 : 0)) {
-    case 7: hipLaunchKernelGGL((k_first_pass_batch<real, 3, WPB, true>), g, t, 0, st, B); break;
-    case 6: hipLaunchKernelGGL((k_first_pass_batch<real, 3, WPB, false>), g, t, 0, st, B); break;
-    case 5: hipLaunchKernelGGL((k_first_pass_batch<real, 2, WPB, true>), g, t, 0, st, B); break;
-    case 4: hipLaunchKernelGGL((k_first_pass_batch<real, 2, WPB, false>), g, t, 0, st, B); break;
-    case 3: hipLaunchKernelGGL((k_first_pass_batch<real, 1, WPB, true>), g, t, 0, st, B); break;
-    case 2: hipLaunchKernelGGL((k_first_pass_batch<real, 1, WPB, false>), g, t, 0, st, B); break;
+    case 7: hipLaunchKernelGGL((k_first_pass_batch<real, 3, WPB, true, false>), g, t, 0, st, B); break;
+    case 6: hipLaunchKernelGGL((k_first_pass_batch<real, 3, WPB, false, false>), g, t, 0, st, B); break;
+    case 5: hipLaunchKernelGGL((k_first_pass_batch<real, 2, WPB, true, false>), g, t, 0, st, B); break;
+    case 4: hipLaunchKernelGGL((k_first_pass_batch<real, 2, WPB, false, false>), g, t, 0, st, B); break;
+    case 3: hipLaunchKernelGGL((k_first_pass_batch<real, 1, WPB, true, false>), g, t, 0, st, B); break;
+    case 2: hipLaunchKernelGGL((k_first_pass_batch<real, 1, WPB, false, false>), g, t, 0, st, B); break;
     default: return hipErrorInvalidValue;
     }
     if (B.walls)
-        hipLaunchKernelGGL((k_tail_batch<real, true>), dim3(B.nprob), dim3(kTailThreads), 0, st, B);
+        hipLaunchKernelGGL((k_tail_batch<real, true, false>), dim3(B.nprob), dim3(kTailThreads), 0, st, B);
     else
-        hipLaunchKernelGGL((k_tail_batch<real, false>), dim3(B.nprob), dim3(kTailThreads), 0, st, B);
+        hipLaunchKernelGGL((k_tail_batch<real, false, false>), dim3(B.nprob), dim3(kTailThreads), 0, st, B);
     return hipGetLastError();
 }
 
@@ -1269,8 +1286,14 @@ static hipError_t launch_first_pass_rt(const StageArgs<real> &A, const PassOut &
     const int nstrip = (A.nx + 61) / 62, nseg = (A.ny + A.rows - 1) / A.rows;
     const int nwave = nstrip * nseg;
     const int nblk = (nwave + WPB - 1) / WPB;
-    if (A.iso) hipLaunchKernelGGL((k_first_pass<real, RT, WPB, true>), dim3(nblk), dim3(64 * WPB), 0, st, A, P);
-    else hipLaunchKernelGGL((k_first_pass<real, RT, WPB, false>), dim3(nblk), dim3(64 * WPB), 0, st, A, P);
+    const dim3 g(nblk), t(64 * WPB);
+    if (A.solver == 1) {
+        if (A.iso) hipLaunchKernelGGL((k_first_pass<real, RT, WPB, true, true>), g, t, 0, st, A, P);
+        else hipLaunchKernelGGL((k_first_pass<real, RT, WPB, false, true>), g, t, 0, st, A, P);
+    } else {
+        if (A.iso) hipLaunchKernelGGL((k_first_pass<real, RT, WPB, true, false>), g, t, 0, st, A, P);
+        else hipLaunchKernelGGL((k_first_pass<real, RT, WPB, false, false>), g, t, 0, st, A, P);
+    }
     return hipGetLastError();
 }
 
@@ -1310,13 +1333,19 @@ hipError_t launch_first_pass(const StageArgs<real> &A, const PassOut &P, const C
 template <typename real>
 hipError_t launch_cascade_pass(const StageArgs<real> &A, const Cascade &C, int k, int nblocks, hipStream_t st)
 {
-    if (A.bcx == 2 || A.bcy == 2) {
-        hipLaunchKernelGGL((k_faces<real, true>), dim3(nblocks), dim3(256), 0, st, A, C, k);
+    const bool walls = A.bcx == 2 || A.bcy == 2;
+    if (walls && A.solver == 1)
+        hipLaunchKernelGGL((k_faces<real, true, true>), dim3(nblocks), dim3(256), 0, st, A, C, k);
+    else if (walls)
+        hipLaunchKernelGGL((k_faces<real, true, false>), dim3(nblocks), dim3(256), 0, st, A, C, k);
+    else if (A.solver == 1)
+        hipLaunchKernelGGL((k_faces<real, false, true>), dim3(nblocks), dim3(256), 0, st, A, C, k);
+    else
+        hipLaunchKernelGGL((k_faces<real, false, false>), dim3(nblocks), dim3(256), 0, st, A, C, k);
+    if (walls)
         hipLaunchKernelGGL((k_cells<real, true>), dim3(nblocks), dim3(64), 0, st, A, C, k);
-    } else {
-        hipLaunchKernelGGL((k_faces<real, false>), dim3(nblocks), dim3(256), 0, st, A, C, k);
+    else
         hipLaunchKernelGGL((k_cells<real, false>), dim3(nblocks), dim3(64), 0, st, A, C, k);
-    }
     return hipGetLastError();
 }
 
@@ -1324,10 +1353,15 @@ template <typename real>
 hipError_t launch_cascade_tail(const StageArgs<real> &A, const Cascade &C, int kbeg, int kdef, int kend,
                                hipStream_t st)
 {
-    if (A.bcx == 2 || A.bcy == 2)
-        hipLaunchKernelGGL((k_tail<real, true>), dim3(1), dim3(kTailThreads), 0, st, A, C, kbeg, kdef, kend);
+    const bool walls = A.bcx == 2 || A.bcy == 2;
+    if (walls && A.solver == 1)
+        hipLaunchKernelGGL((k_tail<real, true, true>), dim3(1), dim3(kTailThreads), 0, st, A, C, kbeg, kdef, kend);
+    else if (walls)
+        hipLaunchKernelGGL((k_tail<real, true, false>), dim3(1), dim3(kTailThreads), 0, st, A, C, kbeg, kdef, kend);
+    else if (A.solver == 1)
+        hipLaunchKernelGGL((k_tail<real, false, true>), dim3(1), dim3(kTailThreads), 0, st, A, C, kbeg, kdef, kend);
     else
-        hipLaunchKernelGGL((k_tail<real, false>), dim3(1), dim3(kTailThreads), 0, st, A, C, kbeg, kdef, kend);
+        hipLaunchKernelGGL((k_tail<real, false, false>), dim3(1), dim3(kTailThreads), 0, st, A, C, kbeg, kdef, kend);
     return hipGetLastError();
 }
 
