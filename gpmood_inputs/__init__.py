@@ -24,7 +24,10 @@ synthetic stand-ins shaped like the paper's shock problems):
   * implosion (Sec. "The implosion problem in 2D", the set-up of Liska and
     Wendroff that it cites): [0, 0.3]^2 at rest, rho = 0.125, p = 0.14 below the
     line x + y = 0.15 and rho = 1, p = 1 above it, exact cell averages by the
-    area below the line; the state is symmetric under x <-> y.
+    area below the line; the state is symmetric under x <-> y,
+  * Mach 100 light jet (Sec. "Numerical results", Mach jets): [0, 1.5]^2 at rest
+    with rho = 10 gamma, p = 1; the jet (rho, u, v, p) = (gamma, 0, 100, 1) enters
+    through the slit 0.7 <= x <= 0.8 of the bottom boundary (`MACH_JET_SLIT`).
 """
 from __future__ import annotations
 
@@ -230,6 +233,20 @@ def implosion(n, L=0.3, cut=0.15, inner=(0.125, 0.14), outer=(1.0, 1.0), gamma=G
     out[0] = rho
     out[3] = E
     return out
+
+
+# --------------------------------------------------------------------------
+# Mach 100 light jet
+# --------------------------------------------------------------------------
+MACH_JET_SLIT = (1, 0.7, 0.8, (GAMMA, 0.0, 100.0, 1.0))  # bottom side, x range, (rho, u, v, p)
+
+
+def mach_jet(n, gamma=GAMMA):
+    """The ambient state (rho, u, v, p) = (10 gamma, 0, 0, 1) on an n-by-n grid of
+    [0, 1.5]^2; the jet enters through the boundary slit MACH_JET_SLIT."""
+    rho = np.full((n, n), 10.0 * gamma)
+    z = np.zeros((n, n))
+    return prim_to_cons(rho, z, z, np.ones((n, n)), gamma)
 
 
 # --------------------------------------------------------------------------

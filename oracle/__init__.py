@@ -127,6 +127,8 @@ class _Cfg(ctypes.Structure):
         ("sigma_v", ctypes.c_double), ("sigma_p", ctypes.c_double),
         ("flags", ctypes.c_uint),
         ("solver", ctypes.c_int),
+        ("slit", ctypes.c_int), ("slit_i0", ctypes.c_int), ("slit_i1", ctypes.c_int),
+        ("slit_u", ctypes.c_double * 4),
     ]
 
 
@@ -147,10 +149,13 @@ class Oracle:
     blocky diamond), "cross" (the cross-shaped stencils of Sec. "Isentropic
     vortex") or "poly3" (POL-MOOD3: radius 1 with the polynomial weights).
     solver: "hllc" (the default) or "hll" (the paper's solver for the Mach jets).
+    slit: None, or (sides, x0, x1, (rho, u, v, p)), an inflow slit on the y
+    boundaries (bit 0 bottom, bit 1 top) over the cells with centres in [x0, x1].
     """
 
     def __init__(self, nx, ny, lo=(0.0, 0.0), hi=(1.0, 1.0), bc=(0, 0), cascade=(3, 2, 1, 0),
-                 ell=None, gamma=1.4, sigma_v=5.0, sigma_p=5.0, flags=ORC_ALL, shape="diamond", solver="hllc"):
+                 ell=None, gamma=1.4, sigma_v=5.0, sigma_p=5.0, flags=ORC_ALL, shape="diamond", solver="hllc",
+                 slit=None):
         self.nx, self.ny = int(nx), int(ny)
         self.dx = (hi[0] - lo[0]) / nx
         self.dy = (hi[1] - lo[1]) / ny
@@ -197,6 +202,17 @@ class Oracle:
         if solver not in ("hllc", "hll"):
             raise ValueError("solver is 'hllc' or 'hll'")
         c.solver = 1 if solver == "hll" else 0
+        if slit is not None:
+            # slit = (sides, x0, x1, (rho, u, v, p)): sides bit 0 bottom, bit 1 top;
+            # the cells whose centres lie in [x0, x1]; an outflow y axis elsewhere
+            sides, x0, x1, prim = slit
+            if c.bcy != 1 or not 0 < sides < 4:
+                raise ValueError("an inflow slit sits on outflow y boundaries")
+            xc = lo[0] + (np.arange(self.nx) + 0.5) * self.dx
+            inside = np.nonzero((xc >= x0) & (xc <= x1))[0]
+            c.slit, c.slit_i0, c.slit_i1 = int(sides), int(inside[0]), int(inside[-1]) + 1
+            r, u, v, p = (float(x) for x in prim)
+            c.slit_u[:] = [r, r * u, r * v, p / (gamma - 1.0) + 0.5 * r * (u * u + v * v)]
         self.cfg = c
         self.gamma = gamma
 

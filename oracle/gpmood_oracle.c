@@ -52,6 +52,9 @@ typedef struct {
     double sigma_v, sigma_p;
     unsigned flags;
     int solver;         /* Riemann solver: 0 HLLC (the default), 1 HLL */
+    int slit;           /* inflow slit on the y boundaries: bit 0 bottom, bit 1 top */
+    int slit_i0, slit_i1;   /* its cells: columns slit_i0 <= i < slit_i1 */
+    double slit_u[4];   /* the fixed inflow state (conservative) */
 } orc_cfg;
 
 /* ---------------------------------------------------------------- helpers */
@@ -88,6 +91,10 @@ static void fill_ghosted(const orc_cfg *c, const double *U, ghosted *g)
                 if (v == 1 && c->bcx == 2 && (i < 0 || i >= c->nx)) sg = -sg;
                 if (v == 2 && c->bcy == 2 && (j < 0 || j >= c->ny)) sg = -sg;
                 g->u[gidx(g, v, i, j)] = sg * U[((size_t)v * c->ny + sj) * c->nx + si];
+                /* an inflow slit (the Mach-jet problems of Sec. "Numerical results"):
+                   the ghost cells below / above it hold the injected state */
+                if (i >= c->slit_i0 && i < c->slit_i1 && (((c->slit & 1) && j < 0) || ((c->slit & 2) && j >= c->ny)))
+                    g->u[gidx(g, v, i, j)] = c->slit_u[v];
             }
 }
 
@@ -534,6 +541,13 @@ double orc_dt(const orc_cfg *c, const double *U, double cfl)
         double lx = (fabs(q[1] / q[0]) + cs) / c->dx;
         double ly = (fabs(q[2] / q[0]) + cs) / c->dy;
         lam = dmax(lam, dmax(lx, ly));
+    }
+    if (c->slit) {
+        /* the injected state enters the domain: its waves bound the step too */
+        const double *q = c->slit_u;
+        double p = pressure(c->gamma, q);
+        double cs = sqrt(c->gamma * p / q[0]);
+        lam = dmax(lam, dmax((fabs(q[1] / q[0]) + cs) / c->dx, (fabs(q[2] / q[0]) + cs) / c->dy));
     }
     return cfl / lam;
 }
