@@ -56,13 +56,20 @@ typedef enum { GPM_BC_PERIODIC = 0, GPM_BC_OUTFLOW = 1, GPM_BC_REFLECT = 2 } gpm
    reflect is a slip wall: the ghost cell k past the wall is the image of the k-th
    interior cell with its momentum normal to the wall reversed: the four walls of
    Sec. "The implosion problem in 2D"; 2D stages only, not gpm3_* nor
-   gpm_stage_vjp). */
+   gpm_stage_vjp).  An inflow slit (the injection of the Mach-jet problems,
+   Sec. "Numerical results") on an outflow y axis gives the ghost cells below
+   (bit 0) / above (bit 1) the slit's cells the injected state; the CFL step then
+   also bounds that state's waves.  2D single problems only (not gpm3_*,
+   gpm_batch_* nor gpm_stage_vjp): GPM_EUNSUPPORTED there. */
 typedef struct {
     int dim;        /* 2 */
     int n[3];       /* nx, ny (n[2] ignored in 2D) */
     double lo[3], hi[3];
     int bc[3];      /* gpm_bc per axis */
     double gamma;   /* ratio of specific heats, > 1 (paper: 1.4) */
+    int slit;       /* inflow slit on the y boundaries: 0 none, bit 0 bottom, bit 1 top */
+    double slit_x[2];     /* it covers the cells whose centres lie in [slit_x[0], slit_x[1]] */
+    double slit_prim[4];  /* the injected state (rho, u, v, p), rho > 0, p > 0 */
 } gpm_grid;
 
 /* Detection switches (gpm_scheme.flags); GPM_FLAGS_ALL is the paper's method. */

@@ -39,7 +39,8 @@ EXPORTS = ("gpm_create", "gpm_set_scheme", "gpm_workspace_size", "gpm_bind", "gp
 
 class gpm_grid(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("lo", ctypes.c_double * 3),
-                ("hi", ctypes.c_double * 3), ("bc", ctypes.c_int * 3), ("gamma", ctypes.c_double)]
+                ("hi", ctypes.c_double * 3), ("bc", ctypes.c_int * 3), ("gamma", ctypes.c_double),
+                ("slit", ctypes.c_int), ("slit_x", ctypes.c_double * 2), ("slit_prim", ctypes.c_double * 4)]
 
 
 class gpm_scheme(ctypes.Structure):
@@ -144,12 +145,14 @@ class GPMood:
 
     nx, ny, lo, hi, bc=(bcx, bcy) with 0 periodic / 1 outflow / 2 reflecting wall, prec 'f32' | 'f64',
     cascade = GP radii ending in 0, ell = physical length scale (None: 12 min(dx, dy)),
-    stencil "diamond" / "cross" / "poly3", solver "hllc" / "hll".
+    stencil "diamond" / "cross" / "poly3", solver "hllc" / "hll", slit None or
+    (sides, x0, x1, (rho, u, v, p)): an inflow slit on the y boundaries (bit 0
+    bottom, bit 1 top) over the cells with centres in [x0, x1].
     """
 
     def __init__(self, nx, ny, lo=(0.0, 0.0), hi=(1.0, 1.0), bc=(0, 0), prec="f64",
                  cascade=(3, 2, 1, 0), ell=None, gamma=1.4, sigma_v=5.0, sigma_p=5.0,
-                 flags=GPM_FLAGS_ALL, stream=None, device=None, stencil="diamond", solver="hllc"):
+                 flags=GPM_FLAGS_ALL, stream=None, device=None, stencil="diamond", solver="hllc", slit=None):
         import torch
         L = lib()
         self.torch = torch
@@ -165,6 +168,11 @@ class GPMood:
         g.hi[0], g.hi[1] = hi
         g.bc[0], g.bc[1] = bc
         g.gamma = gamma
+        if slit is not None:
+            # (sides, x0, x1, (rho, u, v, p)): an inflow slit on the y boundaries
+            g.slit, g.slit_x[0], g.slit_x[1] = int(slit[0]), float(slit[1]), float(slit[2])
+            for k in range(4):
+                g.slit_prim[k] = float(slit[3][k])
         ctx = ctypes.c_void_p()
         self._check(L.gpm_create(ctypes.byref(g), GPM_F64 if prec == "f64" else GPM_F32,
                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)), None)

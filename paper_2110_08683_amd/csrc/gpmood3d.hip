@@ -807,7 +807,7 @@ gpm_status gpm3_create(const gpm_grid *grid, int prec, void *hip_stream, gpm3_ct
     for (int a = 0; a < 3; ++a) {
         if (grid->n[a] < 1 || grid->n[a] > 4096) return GPM_EINVAL;
         if (!(grid->hi[a] > grid->lo[a])) return GPM_EINVAL;
-        if (grid->bc[a] == GPM_BC_REFLECT) return GPM_EUNSUPPORTED;  // 2D only
+        if (grid->bc[a] == GPM_BC_REFLECT || grid->slit != 0) return GPM_EUNSUPPORTED;  // 2D only
         if (grid->bc[a] != GPM_BC_PERIODIC && grid->bc[a] != GPM_BC_OUTFLOW) return GPM_EINVAL;
         if (grid->bc[a] == GPM_BC_PERIODIC && grid->n[a] < 3) return GPM_EUNSUPPORTED;
         ncell *= (size_t)grid->n[a];

@@ -55,6 +55,22 @@ gpm_status gpm_create(const gpm_grid *grid, int prec, void *hip_stream, gpm_ctx 
         if (grid->bc[d] != GPM_BC_OUTFLOW && grid->n[d] < 4) return GPM_EUNSUPPORTED;
     }
     if (!(grid->gamma > 1.0)) return GPM_EINVAL;
+    int si0 = 0, si1 = 0;
+    if (grid->slit != 0) {
+        if (grid->slit < 0 || grid->slit > 3 || grid->bc[1] != GPM_BC_OUTFLOW || !(grid->slit_x[1] > grid->slit_x[0]) ||
+            !(grid->slit_prim[0] > 0.0) || !(grid->slit_prim[3] > 0.0))
+            return GPM_EINVAL;
+        const double dx = (grid->hi[0] - grid->lo[0]) / grid->n[0];
+        si0 = grid->n[0];
+        for (int i = 0; i < grid->n[0]; ++i) {
+            const double xc = grid->lo[0] + (i + 0.5) * dx;
+            if (xc >= grid->slit_x[0] && xc <= grid->slit_x[1]) {
+                si0 = i < si0 ? i : si0;
+                si1 = i + 1;
+            }
+        }
+        if (si1 <= si0) return GPM_EINVAL;  // no cell centre in the slit
+    }
     gpm_ctx *c = new (std::nothrow) gpm_ctx;
     if (!c) return GPM_ENOMEM;
     c->grid = *grid;
@@ -65,6 +81,22 @@ gpm_status gpm_create(const gpm_grid *grid, int prec, void *hip_stream, gpm_ctx 
     c->ncell = (size_t)c->nx * c->ny;
     c->dx = (grid->hi[0] - grid->lo[0]) / c->nx;
     c->dy = (grid->hi[1] - grid->lo[1]) / c->ny;
+    c->si0 = si0;
+    c->si1 = si1;
+    if (grid->slit != 0) {
+        const double r = grid->slit_prim[0], u = grid->slit_prim[1], v = grid->slit_prim[2], p = grid->slit_prim[3];
+        const double g = grid->gamma;
+        c->slit_u[0] = r;
+        c->slit_u[1] = r * u;
+        c->slit_u[2] = r * v;
+        c->slit_u[3] = p / (g - 1.0) + 0.5 * r * (u * u + v * v);
+        // its waves bound the CFL step, in the form of the cells' bound
+        const double q1 = c->slit_u[1], q2 = c->slit_u[2];
+        const double pp = (g - 1.0) * (c->slit_u[3] - 0.5 * (q1 * q1 + q2 * q2) / r);
+        const double cs = std::sqrt(g * pp / r);
+        const double lx = (std::fabs(q1 / r) + cs) / c->dx, ly = (std::fabs(q2 / r) + cs) / c->dy;
+        c->slit_lam = lx > ly ? lx : ly;
+    }
     if (hipHostMalloc((void **)&c->pinned, 64, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return GPM_EHIP;
@@ -255,8 +287,10 @@ gpm_status gpm_get_state(gpm_ctx *c, double *U)
 static gpm_status compute_dt_from(gpm_ctx *c, const void *U, double cfl)
 {
     hipError_t e = c->prec == GPM_F64
-                       ? launch_dt<double>((const double *)U, c->ncell, c->grid.gamma, c->dx, c->dy, cfl, c->ctl, c->stream)
-                       : launch_dt<float>((const float *)U, c->ncell, c->grid.gamma, c->dx, c->dy, cfl, c->ctl, c->stream);
+                       ? launch_dt<double>((const double *)U, c->ncell, c->grid.gamma, c->dx, c->dy, cfl, c->slit_lam,
+                                           c->ctl, c->stream)
+                       : launch_dt<float>((const float *)U, c->ncell, c->grid.gamma, c->dx, c->dy, cfl, c->slit_lam,
+                                          c->ctl, c->stream);
     if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("dt kernels: ") + hipGetErrorString(e));
     return GPM_OK;
 }
@@ -550,6 +584,7 @@ gpm_status gpm_stage_vjp(gpm_ctx *c, int s, const void *Un, const void *Us, cons
         return fail(c, GPM_EUNSUPPORTED, "the stage adjoint has periodic and outflow boundaries only");
     if (c->scheme.solver != GPM_SOLVER_HLLC)
         return fail(c, GPM_EUNSUPPORTED, "the stage adjoint differentiates the HLLC scheme only");
+    if (c->grid.slit != 0) return fail(c, GPM_EUNSUPPORTED, "the stage adjoint has no inflow slit");
     return c->prec == GPM_F64 ? stage_vjp<double>(c, c->w64, s, Un, Us, order, dt, lam_out, lam_Us, lam_Un, dL_dell)
                               : stage_vjp<float>(c, c->w32, s, Un, Us, order, dt, lam_out, lam_Us, lam_Un, dL_dell);
 }

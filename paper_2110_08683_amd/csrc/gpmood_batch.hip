@@ -260,6 +260,8 @@ gpm_status gpm_batch_create(int nprob, const gpm_grid *grids, int prec, void *hi
     b->nprob = nprob;
     b->prec = prec;
     b->stream = (hipStream_t)hip_stream;
+    for (int p = 0; p < nprob; ++p)
+        if (grids[p].slit != 0) return GPM_EUNSUPPORTED;  // single problems only
     for (int p = 0; p < nprob; ++p) {
         gpm_ctx *c = nullptr;
         const gpm_status st = gpm_create(&grids[p], prec, hip_stream, &c);

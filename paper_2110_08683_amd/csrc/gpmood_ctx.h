@@ -62,6 +62,9 @@ struct gpm_ctx {
     int head_guess = 4;        // batch length: the previous stage's multi-block passes + 2
     int tail_threshold = 32;   // troubled cells at or below which one workgroup finishes the cascade
     int rows = 12;
+    int si0 = 0, si1 = 0;  // inflow slit cells [si0, si1)
+    double slit_u[4] = {0.0, 0.0, 0.0, 0.0};
+    double slit_lam = 0.0;  // the slit state's CFL bound (0: none)
     int last_npass = 0;
     bool fresh_ctl = true;
     int *pinned = nullptr;
@@ -159,6 +162,10 @@ static inline void fill_args(const gpm_ctx *c, const Weights<real> &W, StageArgs
     A.cb = real(1);
     A.iso = weights_isotropic(W, c->top);
     A.solver = c->scheme.solver;
+    A.slit = c->grid.slit;
+    A.si0 = c->si0;
+    A.si1 = c->si1;
+    for (int v = 0; v < 4; ++v) A.slitU[v] = (real)c->slit_u[v];
     A.flags = c->scheme.flags;
     A.dx = (real)c->dx;
     A.dy = (real)c->dy;

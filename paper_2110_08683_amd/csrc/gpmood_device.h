@@ -63,6 +63,8 @@ struct StageArgs {
     int top;              // top radius
     int iso;              // 1: the y weights are exactly the transposed x weights
     int solver;           // 0 HLLC, 1 HLL
+    int slit, si0, si1;   // inflow slit: bit 0 bottom, bit 1 top; its cells si0 <= i < si1
+    real slitU[4];        // the injected state
     unsigned flags;
     int next[4];          // next radius of the cascade after radius r
     real dx, dy, gamma, sigma_v, sigma_p, plat_thr, delta;
@@ -146,6 +148,13 @@ __device__ __forceinline__ int wrap(int i, int n, int bc)
     if (bc == 0) return i < 0 ? i + n : (i >= n ? i - n : i);
     if (WALLS && bc == 2) return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i);
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// Is the gathered cell (i, j) (unwrapped indices) a ghost cell of the inflow slit?
+template <typename real>
+__device__ __forceinline__ bool in_slit(const StageArgs<real> &A, int i, int j)
+{
+    return i >= A.si0 && i < A.si1 && (((A.slit & 1) && j < 0) || ((A.slit & 2) && j >= A.ny));
 }
 
 // Factor of the momentum normal to an axis in the image of cell index i: -1 when

@@ -116,7 +116,7 @@ __device__ __forceinline__ void claim_after_lowering(const StageArgs<real> &A, c
 // A lowered cell is only appended to P.clist (count P.ccount); its claims are
 // made after the pass (k_claims_first, or k_tail_batch in a batch), which keeps
 // the claim atomics, and the wait for their results, out of the march.
-template <typename real, int RT, bool ISO, bool HLL>
+template <typename real, int RT, bool ISO, bool HLL, bool BND>
 __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const PassOut &P, int wid,
                                                 real (*ring)[4][LW])
 {
@@ -153,14 +153,24 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
     // momentum of mirrored rows; applied here, not at the load, which stays in flight.
     auto store_row = [&](int jr, real (&pf)[4][2]) {
         const int slot = jr & 7;
-        if (A.bcx == 2) {
+        // (BND: the build for grids with a reflecting axis or an inflow slit)
+        if (BND && A.bcx == 2) {
             const int c0 = x0 - 4 + lane, c1 = c0 + 64;
             if (c0 < 0 || c0 >= nx) pf[1][0] = -pf[1][0];
             if (c1 >= nx) pf[1][1] = -pf[1][1];
         }
-        if (A.bcy == 2 && (jr < 0 || jr >= ny)) {
+        if (BND && A.bcy == 2 && (jr < 0 || jr >= ny)) {
             pf[2][0] = -pf[2][0];
             pf[2][1] = -pf[2][1];
+        }
+        if (BND && A.slit && (((A.slit & 1) && jr < 0) || ((A.slit & 2) && jr >= ny))) {
+            // ghost rows of an inflow slit hold the injected state
+            const int c0 = x0 - 4 + lane, c1 = c0 + 64;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                if (c0 >= A.si0 && c0 < A.si1) pf[v][0] = A.slitU[v];
+                if (c1 >= A.si0 && c1 < A.si1) pf[v][1] = A.slitU[v];
+            }
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -300,12 +310,12 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
     }
 }
 
-template <typename real, int RT, int WPB, bool ISO, bool HLL>
+template <typename real, int RT, int WPB, bool ISO, bool HLL, bool BND>
 __global__ __launch_bounds__(64 * WPB, sizeof(real) == 4 ? 2 : 1) void k_first_pass(const StageArgs<real> A, const PassOut P)
 {
     __shared__ real ring_all[WPB][8][4][LW];
     const int wv = threadIdx.x >> 6;
-    first_pass_wave<real, RT, ISO, HLL>(A, P, xcd_tile(blockIdx.x, gridDim.x) * WPB + wv, ring_all[wv]);
+    first_pass_wave<real, RT, ISO, HLL, BND>(A, P, xcd_tile(blockIdx.x, gridDim.x) * WPB + wv, ring_all[wv]);
 }
 
 // The claims of the cells the first pass lowered (listed in low, count *nlow):
@@ -439,6 +449,12 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
             // grid: position (a, b) is gathered at offset (b, a) and the x table used
             tr = dir == 1 && A.iso;
             const real *U = A.Us + v * plane;
+            // a gathered cell (xr, yr) (unwrapped) at wrapped offset yo + xo, sign sg;
+            // the walls build also puts an inflow slit's state in its ghost cells
+            const real slitv = A.slitU[v];
+            auto gv = [&](int xr, int yr, size_t yo, int xo, real sg) -> real {
+                return (WALLS && A.slit && in_slit(A, xr, yr)) ? slitv : sg * U[yo + xo];
+            };
             // reflecting walls reverse the normal momentum of mirrored cells (WALLS:
             // the variant built for grids with a reflecting axis)
             const bool fx = WALLS && v == 1 && A.bcx == 2, fy = WALLS && v == 2 && A.bcy == 2;
@@ -457,10 +473,11 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
                 const real sRp = msign<real>(iR + pa[e], nx, fx), sRm = msign<real>(iR - pa[e], nx, fx);
                 const real tLp = msign<real>(jL + pb[e], ny, fy), tLm = msign<real>(jL - pb[e], ny, fy);
                 const real tRp = msign<real>(jR + pb[e], ny, fy), tRm = msign<real>(jR - pb[e], ny, fy);
-                parity4(sLp * tLp * U[yLp + xLp], sLm * tLp * U[yLp + xLm], sLp * tLm * U[yLm + xLp],
-                        sLm * tLm * U[yLm + xLm], QL[e]);
-                parity4(sRp * tRp * U[yRp + xRp], sRm * tRp * U[yRp + xRm], sRp * tRm * U[yRm + xRp],
-                        sRm * tRm * U[yRm + xRm], QR[e]);
+                const int a = pa[e], b = pb[e];
+                parity4(gv(iL + a, jL + b, yLp, xLp, sLp * tLp), gv(iL - a, jL + b, yLp, xLm, sLm * tLp),
+                        gv(iL + a, jL - b, yLm, xLp, sLp * tLm), gv(iL - a, jL - b, yLm, xLm, sLm * tLm), QL[e]);
+                parity4(gv(iR + a, jR + b, yRp, xRp, sRp * tRp), gv(iR - a, jR + b, yRp, xRm, sRm * tRp),
+                        gv(iR + a, jR - b, yRm, xRp, sRp * tRm), gv(iR - a, jR - b, yRm, xRm, sRm * tRm), QR[e]);
             }
             // a transposed y face takes position (a, b) from the gathered (b, a), OE and
             // EO exchanged: with the diagonal pairing these are the bits a transposed
@@ -528,12 +545,12 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
                 const real sRp = msign<real>(iR + a, nx, fx), sRm = msign<real>(iR - a, nx, fx);
                 const real tLp = msign<real>(jL + b, ny, fy), tLm = msign<real>(jL - b, ny, fy);
                 const real tRp = msign<real>(jR + b, ny, fy), tRm = msign<real>(jR - b, ny, fy);
-                const real Lpp = sLp * tLp * U[yLp + xLp], Lmm = sLm * tLm * U[yLm + xLm];
-                const real Lpm = tr ? sLm * tLp * U[yLp + xLm] : sLp * tLm * U[yLm + xLp];
-                const real Lmp = tr ? sLp * tLm * U[yLm + xLp] : sLm * tLp * U[yLp + xLm];
-                const real Rpp = sRp * tRp * U[yRp + xRp], Rmm = sRm * tRm * U[yRm + xRm];
-                const real Rpm = tr ? sRm * tRp * U[yRp + xRm] : sRp * tRm * U[yRm + xRp];
-                const real Rmp = tr ? sRp * tRm * U[yRm + xRp] : sRm * tRp * U[yRp + xRm];
+                const real Lpp = gv(iL + a, jL + b, yLp, xLp, sLp * tLp), Lmm = gv(iL - a, jL - b, yLm, xLm, sLm * tLm);
+                const real Lx = gv(iL - a, jL + b, yLp, xLm, sLm * tLp), Ly = gv(iL + a, jL - b, yLm, xLp, sLp * tLm);
+                const real Lpm = tr ? Lx : Ly, Lmp = tr ? Ly : Lx;
+                const real Rpp = gv(iR + a, jR + b, yRp, xRp, sRp * tRp), Rmm = gv(iR - a, jR - b, yRm, xRm, sRm * tRm);
+                const real Rx = gv(iR - a, jR + b, yRp, xRm, sRm * tRp), Ry = gv(iR + a, jR - b, yRm, xRp, sRp * tRm);
+                const real Rpm = tr ? Rx : Ry, Rmp = tr ? Ry : Rx;
                 real ql[4], qr[4];
                 parity4(Lpp, Lmp, Lpm, Lmm, ql);
                 parity4(Rpp, Rmp, Rpm, Rmm, qr);
@@ -652,12 +669,23 @@ __device__ __forceinline__ void cell_load(const StageArgs<real> &A, int c, CellI
     for (int m = 0; m < 5; ++m)
 #pragma unroll
         for (int w = 1; w < 4; ++w) X.mom[m][w - 1] = A.Us[w * plane + yr[kDj13[m] + 2] + xc[kDi13[m] + 2]];
-    // reflecting walls reverse the normal momentum of a mirrored face neighbour
+    // reflecting walls reverse the normal momentum of a mirrored face neighbour;
+    // an inflow slit's ghost cells hold the injected state
     if (WALLS) {
 #pragma unroll
         for (int m = 1; m < 5; ++m) {
             X.mom[m][0] *= msign<real>(X.i + kDi13[m], nx, A.bcx == 2);
             X.mom[m][1] *= msign<real>(X.j + kDj13[m], ny, A.bcy == 2);
+        }
+        if (A.slit) {
+#pragma unroll
+            for (int m = 1; m < 13; ++m) {
+                const bool s = in_slit(A, X.i + kDi13[m], X.j + kDj13[m]);
+                X.rho[m] = s ? A.slitU[0] : X.rho[m];
+                if (m < 5)
+#pragma unroll
+                    for (int w = 1; w < 4; ++w) X.mom[m][w - 1] = s ? A.slitU[w] : X.mom[m][w - 1];
+            }
         }
     }
 #pragma unroll
@@ -1006,10 +1034,12 @@ __global__ __launch_bounds__(256) void k_dt_reduce(const real *U, size_t ncell, 
                    (size_t)gridDim.x * blockDim.x, red);
 }
 
-__global__ void k_dt_finalize(Ctl *ctl, double cfl)
+// lam0: a lower bound of the largest wave speed over cell size (an inflow slit's
+// state), 0 if none.
+__global__ void k_dt_finalize(Ctl *ctl, double cfl, double lam0)
 {
     const double lam = __longlong_as_double((long long)ctl->lam_bits);
-    ctl->dt = cfl / lam;
+    ctl->dt = cfl / (lam > lam0 ? lam : lam0);
 }
 
 __global__ void k_dt_set(Ctl *ctl, double dt, int clear_lambda)
@@ -1107,7 +1137,7 @@ __device__ __forceinline__ int find_problem(cptr<int> prefix, int n, int b)
     return lo;
 }
 
-template <typename real, int RT, int WPB, bool ISO, bool HLL>
+template <typename real, int RT, int WPB, bool ISO, bool HLL, bool BND>
 __global__ __launch_bounds__(64 * WPB, sizeof(real) == 4 ? 2 : 1) void k_first_pass_batch(const BatchTabs<real> B)
 {
     __shared__ real ring_all[WPB][8][4][LW];
@@ -1120,7 +1150,7 @@ __global__ __launch_bounds__(64 * WPB, sizeof(real) == 4 ? 2 : 1) void k_first_p
     Q.clist = C.clist[0];
     Q.ccount = &C.ctl->nlow;
     const int wv = threadIdx.x >> 6;
-    first_pass_wave<real, RT, ISO, HLL>(A, Q, (blockIdx.x - blk[p]) * WPB + wv, ring_all[wv]);
+    first_pass_wave<real, RT, ISO, HLL, BND>(A, Q, (blockIdx.x - blk[p]) * WPB + wv, ring_all[wv]);
 }
 
 // Problem p = blockIdx.x makes the claims of the cells its first pass lowered,
@@ -1217,9 +1247,10 @@ __global__ void k_batch_status(const Cascade *casc, int nprob, int *iters, doubl
     }
 }
 
-template <typename real>
-hipError_t launch_batch_stage(const BatchTabs<real> &B, int top, int nfp_blocks, const Cascade *casc,
-                              hipStream_t st)
+// BW: the first-pass build with the boundary handling (some problem has walls).
+template <typename real, bool BW>
+static hipError_t launch_batch_stage_bw(const BatchTabs<real> &B, int top, int nfp_blocks, const Cascade *casc,
+                                        hipStream_t st)
 {
     constexpr int WPB = sizeof(real) == 8 ? 2 : 4;
     const int nb = (B.nprob + 255) / 256;
@@ -1227,12 +1258,12 @@ hipError_t launch_batch_stage(const BatchTabs<real> &B, int top, int nfp_blocks,
     const dim3 g(nfp_blocks), t(64 * WPB);
     if (B.solver == 1) {
         switch (top * 2 + (B.iso ? 1 : 0)) {
-        case 7: hipLaunchKernelGGL((k_first_pass_batch<real, 3, WPB, true, true>), g, t, 0, st, B); break;
-        case 6: hipLaunchKernelGGL((k_first_pass_batch<real, 3, WPB, false, true>), g, t, 0, st, B); break;
-        case 5: hipLaunchKernelGGL((k_first_pass_batch<real, 2, WPB, true, true>), g, t, 0, st, B); break;
-        case 4: hipLaunchKernelGGL((k_first_pass_batch<real, 2, WPB, false, true>), g, t, 0, st, B); break;
-        case 3: hipLaunchKernelGGL((k_first_pass_batch<real, 1, WPB, true, true>), g, t, 0, st, B); break;
-        case 2: hipLaunchKernelGGL((k_first_pass_batch<real, 1, WPB, false, true>), g, t, 0, st, B); break;
+        case 7: hipLaunchKernelGGL((k_first_pass_batch<real, 3, WPB, true, true, BW>), g, t, 0, st, B); break;
+        case 6: hipLaunchKernelGGL((k_first_pass_batch<real, 3, WPB, false, true, BW>), g, t, 0, st, B); break;
+        case 5: hipLaunchKernelGGL((k_first_pass_batch<real, 2, WPB, true, true, BW>), g, t, 0, st, B); break;
+        case 4: hipLaunchKernelGGL((k_first_pass_batch<real, 2, WPB, false, true, BW>), g, t, 0, st, B); break;
+        case 3: hipLaunchKernelGGL((k_first_pass_batch<real, 1, WPB, true, true, BW>), g, t, 0, st, B); break;
+        case 2: hipLaunchKernelGGL((k_first_pass_batch<real, 1, WPB, false, true, BW>), g, t, 0, st, B); break;
         default: return hipErrorInvalidValue;
         }
         if (B.walls)
@@ -1242,12 +1273,12 @@ hipError_t launch_batch_stage(const BatchTabs<real> &B, int top, int nfp_blocks,
         return hipGetLastError();
     }
     switch (top * 2 + (B.iso ? 1 : 0)) {
-    case 7: hipLaunchKernelGGL((k_first_pass_batch<real, 3, WPB, true, false>), g, t, 0, st, B); break;
-    case 6: hipLaunchKernelGGL((k_first_pass_batch<real, 3, WPB, false, false>), g, t, 0, st, B); break;
-    case 5: hipLaunchKernelGGL((k_first_pass_batch<real, 2, WPB, true, false>), g, t, 0, st, B); break;
-    case 4: hipLaunchKernelGGL((k_first_pass_batch<real, 2, WPB, false, false>), g, t, 0, st, B); break;
-    case 3: hipLaunchKernelGGL((k_first_pass_batch<real, 1, WPB, true, false>), g, t, 0, st, B); break;
-    case 2: hipLaunchKernelGGL((k_first_pass_batch<real, 1, WPB, false, false>), g, t, 0, st, B); break;
+    case 7: hipLaunchKernelGGL((k_first_pass_batch<real, 3, WPB, true, false, BW>), g, t, 0, st, B); break;
+    case 6: hipLaunchKernelGGL((k_first_pass_batch<real, 3, WPB, false, false, BW>), g, t, 0, st, B); break;
+    case 5: hipLaunchKernelGGL((k_first_pass_batch<real, 2, WPB, true, false, BW>), g, t, 0, st, B); break;
+    case 4: hipLaunchKernelGGL((k_first_pass_batch<real, 2, WPB, false, false, BW>), g, t, 0, st, B); break;
+    case 3: hipLaunchKernelGGL((k_first_pass_batch<real, 1, WPB, true, false, BW>), g, t, 0, st, B); break;
+    case 2: hipLaunchKernelGGL((k_first_pass_batch<real, 1, WPB, false, false, BW>), g, t, 0, st, B); break;
     default: return hipErrorInvalidValue;
     }
     if (B.walls)
@@ -1255,6 +1286,14 @@ hipError_t launch_batch_stage(const BatchTabs<real> &B, int top, int nfp_blocks,
     else
         hipLaunchKernelGGL((k_tail_batch<real, false, false>), dim3(B.nprob), dim3(kTailThreads), 0, st, B);
     return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_batch_stage(const BatchTabs<real> &B, int top, int nfp_blocks, const Cascade *casc,
+                              hipStream_t st)
+{
+    return B.walls ? launch_batch_stage_bw<real, true>(B, top, nfp_blocks, casc, st)
+                   : launch_batch_stage_bw<real, false>(B, top, nfp_blocks, casc, st);
 }
 
 template <typename real>
@@ -1287,12 +1326,16 @@ static hipError_t launch_first_pass_rt(const StageArgs<real> &A, const PassOut &
     const int nwave = nstrip * nseg;
     const int nblk = (nwave + WPB - 1) / WPB;
     const dim3 g(nblk), t(64 * WPB);
-    if (A.solver == 1) {
-        if (A.iso) hipLaunchKernelGGL((k_first_pass<real, RT, WPB, true, true>), g, t, 0, st, A, P);
-        else hipLaunchKernelGGL((k_first_pass<real, RT, WPB, false, true>), g, t, 0, st, A, P);
-    } else {
-        if (A.iso) hipLaunchKernelGGL((k_first_pass<real, RT, WPB, true, false>), g, t, 0, st, A, P);
-        else hipLaunchKernelGGL((k_first_pass<real, RT, WPB, false, false>), g, t, 0, st, A, P);
+    const int bnd = (A.bcx == 2 || A.bcy == 2 || A.slit != 0) ? 4 : 0;
+    switch (bnd + (A.solver == 1 ? 2 : 0) + (A.iso ? 1 : 0)) {
+    case 0: hipLaunchKernelGGL((k_first_pass<real, RT, WPB, false, false, false>), g, t, 0, st, A, P); break;
+    case 1: hipLaunchKernelGGL((k_first_pass<real, RT, WPB, true, false, false>), g, t, 0, st, A, P); break;
+    case 2: hipLaunchKernelGGL((k_first_pass<real, RT, WPB, false, true, false>), g, t, 0, st, A, P); break;
+    case 3: hipLaunchKernelGGL((k_first_pass<real, RT, WPB, true, true, false>), g, t, 0, st, A, P); break;
+    case 4: hipLaunchKernelGGL((k_first_pass<real, RT, WPB, false, false, true>), g, t, 0, st, A, P); break;
+    case 5: hipLaunchKernelGGL((k_first_pass<real, RT, WPB, true, false, true>), g, t, 0, st, A, P); break;
+    case 6: hipLaunchKernelGGL((k_first_pass<real, RT, WPB, false, true, true>), g, t, 0, st, A, P); break;
+    default: hipLaunchKernelGGL((k_first_pass<real, RT, WPB, true, true, true>), g, t, 0, st, A, P); break;
     }
     return hipGetLastError();
 }
@@ -1333,7 +1376,7 @@ hipError_t launch_first_pass(const StageArgs<real> &A, const PassOut &P, const C
 template <typename real>
 hipError_t launch_cascade_pass(const StageArgs<real> &A, const Cascade &C, int k, int nblocks, hipStream_t st)
 {
-    const bool walls = A.bcx == 2 || A.bcy == 2;
+    const bool walls = A.bcx == 2 || A.bcy == 2 || A.slit != 0;
     if (walls && A.solver == 1)
         hipLaunchKernelGGL((k_faces<real, true, true>), dim3(nblocks), dim3(256), 0, st, A, C, k);
     else if (walls)
@@ -1353,7 +1396,7 @@ template <typename real>
 hipError_t launch_cascade_tail(const StageArgs<real> &A, const Cascade &C, int kbeg, int kdef, int kend,
                                hipStream_t st)
 {
-    const bool walls = A.bcx == 2 || A.bcy == 2;
+    const bool walls = A.bcx == 2 || A.bcy == 2 || A.slit != 0;
     if (walls && A.solver == 1)
         hipLaunchKernelGGL((k_tail<real, true, true>), dim3(1), dim3(kTailThreads), 0, st, A, C, kbeg, kdef, kend);
     else if (walls)
@@ -1392,7 +1435,7 @@ hipError_t launch_lincomb4(real *out, const real *x0, const real *x1, const real
 }
 
 template <typename real>
-hipError_t launch_dt(const real *U, size_t ncell, double gamma, double dx, double dy, double cfl, Ctl *ctl,
+hipError_t launch_dt(const real *U, size_t ncell, double gamma, double dx, double dy, double cfl, double lam0, Ctl *ctl,
                      hipStream_t st)
 {
     hipLaunchKernelGGL(k_dt_set, dim3(1), dim3(1), 0, st, ctl, 0.0, 1);
@@ -1400,7 +1443,7 @@ hipError_t launch_dt(const real *U, size_t ncell, double gamma, double dx, doubl
     if (nblk > 4096) nblk = 4096;
     hipLaunchKernelGGL(k_dt_reduce<real>, dim3((unsigned)nblk), dim3(256), 0, st, U, ncell, gamma, dx, dy,
                        &ctl->lam_bits);
-    hipLaunchKernelGGL(k_dt_finalize, dim3(1), dim3(1), 0, st, ctl, cfl);
+    hipLaunchKernelGGL(k_dt_finalize, dim3(1), dim3(1), 0, st, ctl, cfl, lam0);
     return hipGetLastError();
 }
 
@@ -1438,8 +1481,8 @@ template hipError_t launch_lincomb4<float>(float *, const float *, const float *
                                            double, double, double, double, size_t, hipStream_t);
 template hipError_t launch_lincomb4<double>(double *, const double *, const double *, const double *,
                                             const double *, double, double, double, double, size_t, hipStream_t);
-template hipError_t launch_dt<float>(const float *, size_t, double, double, double, double, Ctl *, hipStream_t);
-template hipError_t launch_dt<double>(const double *, size_t, double, double, double, double, Ctl *, hipStream_t);
+template hipError_t launch_dt<float>(const float *, size_t, double, double, double, double, double, Ctl *, hipStream_t);
+template hipError_t launch_dt<double>(const double *, size_t, double, double, double, double, double, Ctl *, hipStream_t);
 template hipError_t launch_totals<float>(const float *, size_t, double, double *, int, Ctl *, hipStream_t);
 template hipError_t launch_totals<double>(const double *, size_t, double, double *, int, Ctl *, hipStream_t);
 

@@ -21,7 +21,7 @@ template <typename real>
 hipError_t launch_lincomb4(real *out, const real *x0, const real *x1, const real *x2, const real *x3, double w0,
                            double w1, double w2, double w3, size_t n, hipStream_t st);
 template <typename real>
-hipError_t launch_dt(const real *U, size_t ncell, double gamma, double dx, double dy, double cfl, Ctl *ctl,
+hipError_t launch_dt(const real *U, size_t ncell, double gamma, double dx, double dy, double cfl, double lam0, Ctl *ctl,
                      hipStream_t st);
 hipError_t launch_set_dt(Ctl *ctl, double dt, hipStream_t st);
 hipError_t launch_stats(Ctl *ctl, int npass, int reset, hipStream_t st);

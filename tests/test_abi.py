@@ -62,3 +62,7 @@ def test_strerror_and_argument_errors_without_gpu():
     g3.bc[2] = B.GPM_BC_REFLECT
     g3.gamma = 1.4
     assert L.gpm3_create(ctypes.byref(g3), 0, None, ctypes.byref(ctx)) == B.GPM_EUNSUPPORTED
+    # and so is an inflow slit
+    g3.bc[2] = 1
+    g3.slit = 1
+    assert L.gpm3_create(ctypes.byref(g3), 0, None, ctypes.byref(ctx)) == B.GPM_EUNSUPPORTED
