@@ -77,7 +77,7 @@ HBM_PEAK = 8.0e12
 # (mean over the launches of 3 steps, so 1/3 stage-0 launches that read no U^n),
 # scaled by the counters' reading of a 512 MiB device copy (FETCH x 2.0, WRITE x
 # 1.0).  Valid for the kernel sources with this hash only; see profiles/.
-TRAFFIC = {"src": "72112e7febdc6d73", "f32": 388.7e6, "f64": 727.2e6}
+TRAFFIC = {"src": "1a66cae8dd9f39f7", "f32": 388.5e6, "f64": 727.0e6}
 KERNEL_SOURCES = ["gpmood_kernels.hip", "gpmood_device.h", "gpmood_tables.h"]
 
 
