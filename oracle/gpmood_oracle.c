@@ -175,6 +175,11 @@ static void hll(double g, const double *UL, const double *UR, int dir, double *F
         if (SL >= 0.0) f[k] = fk[0][k];
         else if (SR <= 0.0) f[k] = fk[1][k];
         else f[k] = (SR * fk[0][k] - SL * fk[1][k] + SL * SR * (uk[1][k] - uk[0][k])) / (SR - SL);
+        /* a pair with an invalid sound speed (a non-positive pressure or density)
+           has no valid flux: NaN, which fails CAD on both cells of the face
+           (Sec. CAD); the min/max of the wave bounds would otherwise drop the NaN
+           by argument order and break mirror symmetry */
+        if (isnan(cl) || isnan(cr)) f[k] = NAN;
     }
     F[0] = f[0]; F[n] = f[1]; F[t] = f[2]; F[3] = f[3];
 }

@@ -92,3 +92,13 @@ def test_hll_scheme_conserves_on_a_periodic_shock_problem():
     assert np.abs(U - Uc).max() > 1e-6
     with pytest.raises(ValueError):
         oracle.Oracle(n, n, solver="roe")
+
+
+def test_hll_flux_of_an_invalid_pair_is_nan():
+    # a state with negative pressure has no sound speed: the pair's flux is NaN
+    # (whichever side it is on), so CAD flags both cells of the face
+    good = cons(1.0, 0.2, 0.1, 1.0)
+    bad = cons(1.0, 0.2, 0.1, -0.1)
+    assert np.all(np.isnan(oracle.hll(bad, good, 0)))
+    assert np.all(np.isnan(oracle.hll(good, bad, 0)))
+    assert np.all(np.isfinite(oracle.hll(good, good, 0)))
