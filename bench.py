@@ -77,7 +77,7 @@ HBM_PEAK = 8.0e12
 # (mean over the launches of 3 steps, so 1/3 stage-0 launches that read no U^n),
 # scaled by the counters' reading of a 512 MiB device copy (FETCH x 2.0, WRITE x
 # 1.0).  Valid for the kernel sources with this hash only; see profiles/.
-TRAFFIC = {"src": "1a66cae8dd9f39f7", "f32": 388.5e6, "f64": 727.0e6}
+TRAFFIC = {"src": "cba57a860ba56f90", "f32": 388.6e6, "f64": 727.0e6}
 KERNEL_SOURCES = ["gpmood_kernels.hip", "gpmood_device.h", "gpmood_tables.h"]
 
 
@@ -347,6 +347,54 @@ def implosion_line():
             "data": "synthetic", "runs": out}
 
 
+# The Mach 100 light jet as the paper runs it (600^2, t = 0.04, HLL, SSP-RK3,
+# CFL 0.8, ell = 12 dx): GP-MOOD3, 5 and 7.
+JET_VARIANTS = [("GP-MOOD3", (1, 0)), ("GP-MOOD5", (2, 1, 0)), ("GP-MOOD7", (3, 1, 0))]
+
+
+def run_jet(name, cascade, prec, n=600, tend=0.04, cfl=0.8):
+    """One jet run to t = tend (the last step clipped): steps, wall time, the
+    largest fraction of cells a step ends below the top order, min density and
+    pressure, and the largest mirror asymmetry about x = 0.75 (max |rho - rho
+    mirrored| / max rho, checked every 100 steps and at the end)."""
+    import numpy as np
+    import gpmood_inputs as gi
+    from paper_2110_08683_amd import GPMood
+    g = GPMood(n, n, hi=(1.5, 1.5), bc=(1, 1), prec=prec, cascade=cascade, solver="hll", slit=gi.MACH_JET_SLIT)
+    g.gpm_init_state(gi.mach_jet(n))
+    t, k, frac, asym = 0.0, 0, 0.0, 0.0
+    t0 = time.time()
+    while t < tend * (1.0 - 1e-14):
+        dt = min(g.gpm_compute_dt(cfl), tend - t)
+        g.gpm_set_dt(dt)
+        g.gpm_step(0.0, 1)
+        t += dt
+        k += 1
+        c, _ = g.gpm_troubled_counts()
+        frac = max(frac, float(c[1:].sum()) / (n * n))
+        if k % 100 == 0:
+            U = g.gpm_get_state()
+            asym = max(asym, float(np.abs(U[0] - U[0][:, ::-1]).max() / U[0].max()))
+    wall = time.time() - t0
+    U = g.gpm_get_state()
+    asym = max(asym, float(np.abs(U[0] - U[0][:, ::-1]).max() / U[0].max()))
+    p = 0.4 * (U[3] - 0.5 * (U[1] ** 2 + U[2] ** 2) / U[0])
+    return {"variant": name, "prec": prec, "steps": k, "t": t, "wall_s": wall, "lowered_fraction_max": frac,
+            "rho_min": float(U[0].min()), "p_min": float(p.min()), "mirror_asymmetry_max": asym,
+            "jet_head_y": float((np.nonzero((U[0] < 13.0).any(axis=1))[0].max() + 1) * 1.5 / n)}
+
+
+def jet_line():
+    out = []
+    for name, cascade in JET_VARIANTS:
+        r = run_jet(name, cascade, "f64")
+        print(f"[bench] jet {name} f64: {r['steps']} steps {r['wall_s']:.1f} s, lowered <= "
+              f"{100 * r['lowered_fraction_max']:.2f}%", file=sys.stderr, flush=True)
+        out.append(r)
+    return {"workload": "Mach 100 light jet 600^2 on [0,1.5]^2, slit 0.7 <= x <= 0.8, t = 0.04, HLL, SSP-RK3, "
+                        "CFL 0.8, ell = 12 dx", "data": "synthetic", "runs": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -363,12 +411,17 @@ def main():
                     help="also run a plain 512 MiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--implosion", action="store_true",
                     help="instead of the throughput line, run the paper's implosion variants (400^2 to t = 2.5)")
+    ap.add_argument("--jet", action="store_true",
+                    help="instead of the throughput line, run the paper's Mach 100 jet (600^2 to t = 0.04)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {a.gpus})", file=sys.stderr)
         sys.exit(2)
     if a.implosion:
         print(json.dumps(implosion_line()), flush=True)
+        return
+    if a.jet:
+        print(json.dumps(jet_line()), flush=True)
         return
     import gpmood_inputs as gi
     if a.copy_probe:

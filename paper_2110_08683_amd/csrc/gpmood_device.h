@@ -387,6 +387,9 @@ __device__ __forceinline__ void hllc(real g, const real *UL, const real *UR, rea
 template <int DIR, typename real>
 __device__ __forceinline__ void hll(real g, const real *UL, const real *UR, real *F, bool &badL, bool &badR)
 {
+    // unfused: the mirrored Riemann problem then gives exactly the mirrored flux,
+    // which keeps a mirror-symmetric jet symmetric
+#pragma clang fp contract(off)
     constexpr int n = 1 + DIR, t = 2 - DIR;
     const real rl = UL[0], irl = dv(real(1), rl), ul = UL[n] * irl, vl = UL[t] * irl, El = UL[3];
     const real rr = UR[0], irr = dv(real(1), rr), ur = UR[n] * irr, vr = UR[t] * irr, Er = UR[3];
@@ -402,11 +405,15 @@ __device__ __forceinline__ void hll(real g, const real *UL, const real *UR, real
     const real uL[4] = {rl, rl * ul, rl * vl, El};
     const real uR[4] = {rr, rr * ur, rr * vr, Er};
     const real iw = dv(real(1), SR - SL), ss = SL * SR;
+    // a pair with an invalid sound speed has no valid flux: NaN, which fails CAD on
+    // both cells of the face whichever side the invalid state is on
+    const bool valid = cl == cl && cr == cr;
     real f[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const real fh = (SR * fL[k] - SL * fR[k] + ss * (uR[k] - uL[k])) * iw;
         f[k] = SL >= real(0) ? fL[k] : (SR <= real(0) ? fR[k] : fh);
+        f[k] = valid ? f[k] : __builtin_nan("");
     }
     F[0] = f[0];
     F[n] = f[1];

@@ -249,6 +249,7 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
         if (!first) {
             real G[4] = {real(0), real(0), real(0), real(0)};
             bool badLy = false, badRy = false;
+            real fh[q / 2 > 0 ? q / 2 : 1][4];  // HLL builds: fluxes of nodes 0 .. q/2-1, paired below
 #pragma unroll
             for (int k = 0; k < q; ++k) {
                 real f[4];
@@ -257,8 +258,24 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
                 badLy = badLy || bl;
                 badRy = badRy || br;
                 const real w = node_weight<RT>(A.W, k);
+                if constexpr (HLL) {
+                    // mirror-paired quadrature, (f_k + f_{q-1-k}) w_k: a mirror in x
+                    // reverses the nodes of a y face, and the pairs keep the sum exact
+                    if (2 * k + 1 < q) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) G[v] = fma(w, f[v], G[v]);
+                        for (int v = 0; v < 4; ++v) fh[k < q / 2 ? k : 0][v] = f[v];
+                    } else if (2 * k + 1 == q) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) G[v] = fma(w, f[v], G[v]);
+                    } else {
+                        const int m = q - 1 - k;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) G[v] = fma(w, f[v] + fh[m < q / 2 ? m : 0][v], G[v]);
+                    }
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) G[v] = fma(w, f[v], G[v]);
+                }
             }
             // store face j-1/2 (y index j): the segment's faces above its first row,
             // plus the domain's bottom face
@@ -611,7 +628,14 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
             for (int k = 0; k < 4; ++k) {
                 if (k < q) {
                     const int slot = (R >= 2 && k >= 1 && k <= q - 2) ? 1 : 0;
-                    F = fma(wl[kGtabNodeOff + R * 2 + slot], X.s[q0 + k][v], F);
+                    if constexpr (HLL) {
+                        // mirror-paired quadrature (see the first pass's y faces)
+                        if (2 * k + 1 == q) F = fma(wl[kGtabNodeOff + R * 2 + slot], X.s[q0 + k][v], F);
+                        else if (2 * k + 1 > q)
+                            F = fma(wl[kGtabNodeOff + R * 2 + slot], X.s[q0 + k][v] + X.s[q0 + q - 1 - k][v], F);
+                    } else {
+                        F = fma(wl[kGtabNodeOff + R * 2 + slot], X.s[q0 + k][v], F);
+                    }
                     fl |= X.fl[q0 + k];
                 }
             }
