@@ -77,7 +77,7 @@ HBM_PEAK = 8.0e12
 # (mean over the launches of 3 steps, so 1/3 stage-0 launches that read no U^n),
 # scaled by the counters' reading of a 512 MiB device copy (FETCH x 2.0, WRITE x
 # 1.0).  Valid for the kernel sources with this hash only; see profiles/.
-TRAFFIC = {"src": "cba57a860ba56f90", "f32": 388.6e6, "f64": 727.0e6}
+TRAFFIC = {"src": "df0dca43864017aa", "f32": 388.5e6, "f64": 726.9e6}
 KERNEL_SOURCES = ["gpmood_kernels.hip", "gpmood_device.h", "gpmood_tables.h"]
 
 
@@ -325,7 +325,7 @@ def run_implosion(name, stencil, cascade, csd, prec, n=400, tend=2.5, cfl=0.8):
     asym = max(asym, float(np.abs(U[0] - U[0].T).max() / U[0].max()))
     diag = np.diagonal(U[0])
     kmax = int(np.argmax(diag))
-    return {"variant": name, "prec": prec, "steps": k, "t": t, "wall_s": wall,
+    return {"problem": "double Mach 800 jets" if double else "Mach 100 jet", "variant": name, "prec": prec, "steps": k, "t": t, "wall_s": wall,
             "asymmetry_max": asym, "lowered_fraction_max": frac,
             "rho_min": float(U[0].min()), "diag_rho_max": float(diag[kmax]),
             "diag_rho_max_distance": float((kmax + 0.5) * 0.3 / n * np.sqrt(2.0))}
@@ -352,7 +352,7 @@ def implosion_line():
 JET_VARIANTS = [("GP-MOOD3", (1, 0)), ("GP-MOOD5", (2, 1, 0)), ("GP-MOOD7", (3, 1, 0))]
 
 
-def run_jet(name, cascade, prec, n=600, tend=0.04, cfl=0.8):
+def run_jet(name, cascade, prec, n=600, tend=0.04, cfl=0.8, double=False):
     """One jet run to t = tend (the last step clipped): steps, wall time, the
     largest fraction of cells a step ends below the top order, min density and
     pressure, and the largest mirror asymmetry about x = 0.75 (max |rho - rho
@@ -360,8 +360,9 @@ def run_jet(name, cascade, prec, n=600, tend=0.04, cfl=0.8):
     import numpy as np
     import gpmood_inputs as gi
     from paper_2110_08683_amd import GPMood
-    g = GPMood(n, n, hi=(1.5, 1.5), bc=(1, 1), prec=prec, cascade=cascade, solver="hll", slit=gi.MACH_JET_SLIT)
-    g.gpm_init_state(gi.mach_jet(n))
+    slit = gi.DOUBLE_JET_SLIT if double else gi.MACH_JET_SLIT
+    g = GPMood(n, n, hi=(1.5, 1.5), bc=(1, 1), prec=prec, cascade=cascade, solver="hll", slit=slit)
+    g.gpm_init_state(gi.double_jet(n) if double else gi.mach_jet(n))
     t, k, frac, asym = 0.0, 0, 0.0, 0.0
     t0 = time.time()
     while t < tend * (1.0 - 1e-14):
@@ -379,7 +380,7 @@ def run_jet(name, cascade, prec, n=600, tend=0.04, cfl=0.8):
     U = g.gpm_get_state()
     asym = max(asym, float(np.abs(U[0] - U[0][:, ::-1]).max() / U[0].max()))
     p = 0.4 * (U[3] - 0.5 * (U[1] ** 2 + U[2] ** 2) / U[0])
-    return {"variant": name, "prec": prec, "steps": k, "t": t, "wall_s": wall, "lowered_fraction_max": frac,
+    return {"problem": "double Mach 800 jets" if double else "Mach 100 jet", "variant": name, "prec": prec, "steps": k, "t": t, "wall_s": wall, "lowered_fraction_max": frac,
             "rho_min": float(U[0].min()), "p_min": float(p.min()), "mirror_asymmetry_max": asym,
             "jet_head_y": float((np.nonzero((U[0] < 13.0).any(axis=1))[0].max() + 1) * 1.5 / n)}
 
@@ -391,8 +392,14 @@ def jet_line():
         print(f"[bench] jet {name} f64: {r['steps']} steps {r['wall_s']:.1f} s, lowered <= "
               f"{100 * r['lowered_fraction_max']:.2f}%", file=sys.stderr, flush=True)
         out.append(r)
-    return {"workload": "Mach 100 light jet 600^2 on [0,1.5]^2, slit 0.7 <= x <= 0.8, t = 0.04, HLL, SSP-RK3, "
-                        "CFL 0.8, ell = 12 dx", "data": "synthetic", "runs": out}
+    for name, cascade in JET_VARIANTS:
+        r = run_jet(name, cascade, "f64", tend=0.005, double=True)
+        print(f"[bench] double jet {name} f64: {r['steps']} steps {r['wall_s']:.1f} s, lowered <= "
+              f"{100 * r['lowered_fraction_max']:.2f}%", file=sys.stderr, flush=True)
+        out.append(r)
+    return {"workload": "Mach 100 light jet (t = 0.04) and the double Mach 800 jet collision (t = 0.005), 600^2 "
+                        "on [0,1.5]^2, slits 0.7 <= x <= 0.8, HLL, SSP-RK3, CFL 0.8, ell = 12 dx",
+            "data": "synthetic", "runs": out}
 
 
 def main():

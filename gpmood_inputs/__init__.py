@@ -241,6 +241,19 @@ def implosion(n, L=0.3, cut=0.15, inner=(0.125, 0.14), outer=(1.0, 1.0), gamma=G
 MACH_JET_SLIT = (1, 0.7, 0.8, (GAMMA, 0.0, 100.0, 1.0))  # bottom side, x range, (rho, u, v, p)
 
 
+DOUBLE_JET_SLIT = (3, 0.7, 0.8, (GAMMA, 0.0, 800.0, 1.0), (GAMMA, 0.0, -800.0, 1.0))  # both sides
+
+
+def double_jet(n, gamma=GAMMA):
+    """The double Mach 800 jet collision: the stratified ambient rho = -9.24 y + 14
+    (cell averages of a linear profile: its value at the centre), p = 1, at rest, on
+    [0, 1.5]^2; jets (gamma, 0, +-800, 1) enter through DOUBLE_JET_SLIT."""
+    y = (np.arange(n) + 0.5) * 1.5 / n
+    rho = np.repeat((-9.24 * y + 14.0)[:, None], n, axis=1)
+    z = np.zeros((n, n))
+    return prim_to_cons(rho, z, z, np.ones((n, n)), gamma)
+
+
 def mach_jet(n, gamma=GAMMA):
     """The ambient state (rho, u, v, p) = (10 gamma, 0, 0, 1) on an n-by-n grid of
     [0, 1.5]^2; the jet enters through the boundary slit MACH_JET_SLIT."""

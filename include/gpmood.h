@@ -69,7 +69,8 @@ typedef struct {
     double gamma;   /* ratio of specific heats, > 1 (paper: 1.4) */
     int slit;       /* inflow slit on the y boundaries: 0 none, bit 0 bottom, bit 1 top */
     double slit_x[2];     /* it covers the cells whose centres lie in [slit_x[0], slit_x[1]] */
-    double slit_prim[4];  /* the injected state (rho, u, v, p), rho > 0, p > 0 */
+    double slit_prim[4];  /* the injected state (rho, u, v, p), rho > 0, p > 0 (bottom side) */
+    double slit_prim_top[4];  /* the same for the top side (bit 1) */
 } gpm_grid;
 
 /* Detection switches (gpm_scheme.flags); GPM_FLAGS_ALL is the paper's method. */

@@ -128,7 +128,7 @@ class _Cfg(ctypes.Structure):
         ("flags", ctypes.c_uint),
         ("solver", ctypes.c_int),
         ("slit", ctypes.c_int), ("slit_i0", ctypes.c_int), ("slit_i1", ctypes.c_int),
-        ("slit_u", ctypes.c_double * 4),
+        ("slit_u", ctypes.c_double * 4), ("slit_u2", ctypes.c_double * 4),
     ]
 
 
@@ -149,8 +149,9 @@ class Oracle:
     blocky diamond), "cross" (the cross-shaped stencils of Sec. "Isentropic
     vortex") or "poly3" (POL-MOOD3: radius 1 with the polynomial weights).
     solver: "hllc" (the default) or "hll" (the paper's solver for the Mach jets).
-    slit: None, or (sides, x0, x1, (rho, u, v, p)), an inflow slit on the y
-    boundaries (bit 0 bottom, bit 1 top) over the cells with centres in [x0, x1].
+    slit: None, or (sides, x0, x1, (rho, u, v, p)[, (rho, u, v, p) top]), an inflow
+    slit on the y boundaries (bit 0 bottom, bit 1 top) over the cells with centres
+    in [x0, x1]; the top side takes the second state if given.
     """
 
     def __init__(self, nx, ny, lo=(0.0, 0.0), hi=(1.0, 1.0), bc=(0, 0), cascade=(3, 2, 1, 0),
@@ -205,14 +206,16 @@ class Oracle:
         if slit is not None:
             # slit = (sides, x0, x1, (rho, u, v, p)): sides bit 0 bottom, bit 1 top;
             # the cells whose centres lie in [x0, x1]; an outflow y axis elsewhere
-            sides, x0, x1, prim = slit
+            sides, x0, x1, prim = slit[:4]
+            prim_top = slit[4] if len(slit) > 4 else prim
             if c.bcy != 1 or not 0 < sides < 4:
                 raise ValueError("an inflow slit sits on outflow y boundaries")
             xc = lo[0] + (np.arange(self.nx) + 0.5) * self.dx
             inside = np.nonzero((xc >= x0) & (xc <= x1))[0]
             c.slit, c.slit_i0, c.slit_i1 = int(sides), int(inside[0]), int(inside[-1]) + 1
-            r, u, v, p = (float(x) for x in prim)
-            c.slit_u[:] = [r, r * u, r * v, p / (gamma - 1.0) + 0.5 * r * (u * u + v * v)]
+            for field, pr in ((c.slit_u, prim), (c.slit_u2, prim_top)):
+                r, u, v, p = (float(x) for x in pr)
+                field[:] = [r, r * u, r * v, p / (gamma - 1.0) + 0.5 * r * (u * u + v * v)]
         self.cfg = c
         self.gamma = gamma
 

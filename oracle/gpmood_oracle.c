@@ -54,7 +54,8 @@ typedef struct {
     int solver;         /* Riemann solver: 0 HLLC (the default), 1 HLL */
     int slit;           /* inflow slit on the y boundaries: bit 0 bottom, bit 1 top */
     int slit_i0, slit_i1;   /* its cells: columns slit_i0 <= i < slit_i1 */
-    double slit_u[4];   /* the fixed inflow state (conservative) */
+    double slit_u[4];   /* the fixed inflow state (conservative), bottom side */
+    double slit_u2[4];  /* the same, top side */
 } orc_cfg;
 
 /* ---------------------------------------------------------------- helpers */
@@ -94,7 +95,7 @@ static void fill_ghosted(const orc_cfg *c, const double *U, ghosted *g)
                 /* an inflow slit (the Mach-jet problems of Sec. "Numerical results"):
                    the ghost cells below / above it hold the injected state */
                 if (i >= c->slit_i0 && i < c->slit_i1 && (((c->slit & 1) && j < 0) || ((c->slit & 2) && j >= c->ny)))
-                    g->u[gidx(g, v, i, j)] = c->slit_u[v];
+                    g->u[gidx(g, v, i, j)] = j < 0 ? c->slit_u[v] : c->slit_u2[v];
             }
 }
 
@@ -547,9 +548,10 @@ double orc_dt(const orc_cfg *c, const double *U, double cfl)
         double ly = (fabs(q[2] / q[0]) + cs) / c->dy;
         lam = dmax(lam, dmax(lx, ly));
     }
-    if (c->slit) {
+    for (int side = 0; side < 2; ++side) {
+        if (!(c->slit & (1 << side))) continue;
         /* the injected state enters the domain: its waves bound the step too */
-        const double *q = c->slit_u;
+        const double *q = side ? c->slit_u2 : c->slit_u;
         double p = pressure(c->gamma, q);
         double cs = sqrt(c->gamma * p / q[0]);
         lam = dmax(lam, dmax((fabs(q[1] / q[0]) + cs) / c->dx, (fabs(q[2] / q[0]) + cs) / c->dy));

@@ -40,7 +40,8 @@ EXPORTS = ("gpm_create", "gpm_set_scheme", "gpm_workspace_size", "gpm_bind", "gp
 class gpm_grid(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("lo", ctypes.c_double * 3),
                 ("hi", ctypes.c_double * 3), ("bc", ctypes.c_int * 3), ("gamma", ctypes.c_double),
-                ("slit", ctypes.c_int), ("slit_x", ctypes.c_double * 2), ("slit_prim", ctypes.c_double * 4)]
+                ("slit", ctypes.c_int), ("slit_x", ctypes.c_double * 2), ("slit_prim", ctypes.c_double * 4),
+                ("slit_prim_top", ctypes.c_double * 4)]
 
 
 class gpm_scheme(ctypes.Structure):
@@ -171,8 +172,10 @@ class GPMood:
         if slit is not None:
             # (sides, x0, x1, (rho, u, v, p)): an inflow slit on the y boundaries
             g.slit, g.slit_x[0], g.slit_x[1] = int(slit[0]), float(slit[1]), float(slit[2])
+            top = slit[4] if len(slit) > 4 else slit[3]
             for k in range(4):
                 g.slit_prim[k] = float(slit[3][k])
+                g.slit_prim_top[k] = float(top[k])
         ctx = ctypes.c_void_p()
         self._check(L.gpm_create(ctypes.byref(g), GPM_F64 if prec == "f64" else GPM_F32,
                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)), None)

@@ -58,7 +58,8 @@ gpm_status gpm_create(const gpm_grid *grid, int prec, void *hip_stream, gpm_ctx 
     int si0 = 0, si1 = 0;
     if (grid->slit != 0) {
         if (grid->slit < 0 || grid->slit > 3 || grid->bc[1] != GPM_BC_OUTFLOW || !(grid->slit_x[1] > grid->slit_x[0]) ||
-            !(grid->slit_prim[0] > 0.0) || !(grid->slit_prim[3] > 0.0))
+            ((grid->slit & 1) && !(grid->slit_prim[0] > 0.0 && grid->slit_prim[3] > 0.0)) ||
+            ((grid->slit & 2) && !(grid->slit_prim_top[0] > 0.0 && grid->slit_prim_top[3] > 0.0)))
             return GPM_EINVAL;
         const double dx = (grid->hi[0] - grid->lo[0]) / grid->n[0];
         si0 = grid->n[0];
@@ -83,19 +84,22 @@ gpm_status gpm_create(const gpm_grid *grid, int prec, void *hip_stream, gpm_ctx 
     c->dy = (grid->hi[1] - grid->lo[1]) / c->ny;
     c->si0 = si0;
     c->si1 = si1;
-    if (grid->slit != 0) {
-        const double r = grid->slit_prim[0], u = grid->slit_prim[1], v = grid->slit_prim[2], p = grid->slit_prim[3];
+    for (int side = 0; side < 2; ++side) {
+        if (!(grid->slit & (1 << side))) continue;
+        const double *pr = side ? grid->slit_prim_top : grid->slit_prim;
+        const double r = pr[0], u = pr[1], v = pr[2], p = pr[3];
         const double g = grid->gamma;
-        c->slit_u[0] = r;
-        c->slit_u[1] = r * u;
-        c->slit_u[2] = r * v;
-        c->slit_u[3] = p / (g - 1.0) + 0.5 * r * (u * u + v * v);
+        double *q = c->slit_u[side];
+        q[0] = r;
+        q[1] = r * u;
+        q[2] = r * v;
+        q[3] = p / (g - 1.0) + 0.5 * r * (u * u + v * v);
         // its waves bound the CFL step, in the form of the cells' bound
-        const double q1 = c->slit_u[1], q2 = c->slit_u[2];
-        const double pp = (g - 1.0) * (c->slit_u[3] - 0.5 * (q1 * q1 + q2 * q2) / r);
+        const double pp = (g - 1.0) * (q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) / r);
         const double cs = std::sqrt(g * pp / r);
-        const double lx = (std::fabs(q1 / r) + cs) / c->dx, ly = (std::fabs(q2 / r) + cs) / c->dy;
-        c->slit_lam = lx > ly ? lx : ly;
+        const double lx = (std::fabs(q[1] / r) + cs) / c->dx, ly = (std::fabs(q[2] / r) + cs) / c->dy;
+        const double lam = lx > ly ? lx : ly;
+        c->slit_lam = lam > c->slit_lam ? lam : c->slit_lam;
     }
     if (hipHostMalloc((void **)&c->pinned, 64, hipHostMallocDefault) != hipSuccess) {
         delete c;

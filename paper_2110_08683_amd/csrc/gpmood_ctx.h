@@ -63,7 +63,7 @@ struct gpm_ctx {
     int tail_threshold = 32;   // troubled cells at or below which one workgroup finishes the cascade
     int rows = 12;
     int si0 = 0, si1 = 0;  // inflow slit cells [si0, si1)
-    double slit_u[4] = {0.0, 0.0, 0.0, 0.0};
+    double slit_u[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};  // bottom, top
     double slit_lam = 0.0;  // the slit state's CFL bound (0: none)
     int last_npass = 0;
     bool fresh_ctl = true;
@@ -165,7 +165,10 @@ static inline void fill_args(const gpm_ctx *c, const Weights<real> &W, StageArgs
     A.slit = c->grid.slit;
     A.si0 = c->si0;
     A.si1 = c->si1;
-    for (int v = 0; v < 4; ++v) A.slitU[v] = (real)c->slit_u[v];
+    for (int v = 0; v < 4; ++v) {
+        A.slitU[0][v] = (real)c->slit_u[0][v];
+        A.slitU[1][v] = (real)c->slit_u[1][v];
+    }
     A.flags = c->scheme.flags;
     A.dx = (real)c->dx;
     A.dy = (real)c->dy;

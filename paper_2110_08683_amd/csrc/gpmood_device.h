@@ -64,7 +64,7 @@ struct StageArgs {
     int iso;              // 1: the y weights are exactly the transposed x weights
     int solver;           // 0 HLLC, 1 HLL
     int slit, si0, si1;   // inflow slit: bit 0 bottom, bit 1 top; its cells si0 <= i < si1
-    real slitU[4];        // the injected state
+    real slitU[2][4];     // the injected states, bottom and top
     unsigned flags;
     int next[4];          // next radius of the cascade after radius r
     real dx, dy, gamma, sigma_v, sigma_p, plat_thr, delta;

@@ -166,10 +166,11 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
         if (BND && A.slit && (((A.slit & 1) && jr < 0) || ((A.slit & 2) && jr >= ny))) {
             // ghost rows of an inflow slit hold the injected state
             const int c0 = x0 - 4 + lane, c1 = c0 + 64;
+            const int side = jr < 0 ? 0 : 1;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                if (c0 >= A.si0 && c0 < A.si1) pf[v][0] = A.slitU[v];
-                if (c1 >= A.si0 && c1 < A.si1) pf[v][1] = A.slitU[v];
+                if (c0 >= A.si0 && c0 < A.si1) pf[v][0] = A.slitU[side][v];
+                if (c1 >= A.si0 && c1 < A.si1) pf[v][1] = A.slitU[side][v];
             }
         }
 #pragma unroll
@@ -468,9 +469,9 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
             const real *U = A.Us + v * plane;
             // a gathered cell (xr, yr) (unwrapped) at wrapped offset yo + xo, sign sg;
             // the walls build also puts an inflow slit's state in its ghost cells
-            const real slitv = A.slitU[v];
+            const real slitb = A.slitU[0][v], slitt = A.slitU[1][v];
             auto gv = [&](int xr, int yr, size_t yo, int xo, real sg) -> real {
-                return (WALLS && A.slit && in_slit(A, xr, yr)) ? slitv : sg * U[yo + xo];
+                return (WALLS && A.slit && in_slit(A, xr, yr)) ? (yr < 0 ? slitb : slitt) : sg * U[yo + xo];
             };
             // reflecting walls reverse the normal momentum of mirrored cells (WALLS:
             // the variant built for grids with a reflecting axis)
@@ -705,10 +706,11 @@ __device__ __forceinline__ void cell_load(const StageArgs<real> &A, int c, CellI
 #pragma unroll
             for (int m = 1; m < 13; ++m) {
                 const bool s = in_slit(A, X.i + kDi13[m], X.j + kDj13[m]);
-                X.rho[m] = s ? A.slitU[0] : X.rho[m];
+                const int side = X.j + kDj13[m] < 0 ? 0 : 1;
+                X.rho[m] = s ? A.slitU[side][0] : X.rho[m];
                 if (m < 5)
 #pragma unroll
-                    for (int w = 1; w < 4; ++w) X.mom[m][w - 1] = s ? A.slitU[w] : X.mom[m][w - 1];
+                    for (int w = 1; w < 4; ++w) X.mom[m][w - 1] = s ? A.slitU[side][w] : X.mom[m][w - 1];
             }
         }
     }

@@ -36,13 +36,16 @@ def _jet(n, prec):
     return GPMood(n, n, hi=(1.5, 1.5), bc=(1, 1), prec=prec, solver="hll", slit=gi.MACH_JET_SLIT)
 
 
-@pytest.mark.parametrize("n,pre", [(60, 0), (60, 6), (150, 3)])
-def test_jet_stage_replay_fp64(torch_cuda, n, pre):
+@pytest.mark.parametrize("n,pre,double", [(60, 0, False), (60, 6, False), (150, 3, False), (60, 0, True),
+                                          (60, 5, True)])
+def test_jet_stage_replay_fp64(torch_cuda, n, pre, double):
+    from paper_2110_08683_amd import GPMood
     torch = torch_cuda
-    _note(f"mach jet replay {n}^2 after {pre} steps")
-    o = oracle.Oracle(n, n, hi=(1.5, 1.5), bc=(1, 1), solver="hll", slit=gi.MACH_JET_SLIT)
-    g = _jet(n, "f64")
-    U0 = gi.mach_jet(n)
+    _note(f"mach jet replay {n}^2 after {pre} steps, double={double}")
+    slit = gi.DOUBLE_JET_SLIT if double else gi.MACH_JET_SLIT
+    o = oracle.Oracle(n, n, hi=(1.5, 1.5), bc=(1, 1), solver="hll", slit=slit)
+    g = GPMood(n, n, hi=(1.5, 1.5), bc=(1, 1), prec="f64", solver="hll", slit=slit)
+    U0 = gi.double_jet(n) if double else gi.mach_jet(n)
     U = o.run(U0, cfl=0.8, nsteps=pre)[0] if pre else U0
     dt = o.dt(U, 0.8)
     U1 = o.stage(0, U, U, dt)[0]

@@ -72,3 +72,29 @@ def test_step_size_includes_the_jet():
 def test_slit_needs_outflow_y_boundaries():
     with pytest.raises(ValueError):
         oracle.Oracle(16, 16, bc=(1, 0), slit=(1, 0.4, 0.6, (1.0, 0.0, 1.0, 1.0)))
+
+
+def test_top_slit_is_the_bottom_slit_upside_down():
+    # a top-only slit injecting downward into the uniform ambient is the bottom
+    # jet flipped about y = 0.75 with v reversed
+    n = 40
+    r, u, v, p = gi.MACH_JET_SLIT[3]
+    top = oracle.Oracle(n, n, hi=(1.5, 1.5), bc=(1, 1), solver="hll",
+                        slit=(2, 0.7, 0.8, (r, u, v, p), (r, u, -v, p)))
+    U0 = gi.mach_jet(n)
+    Ub, _, cb, _ = jet(n).run(U0, cfl=0.8, nsteps=6)
+    Ut, _, ct, _ = top.run(U0, cfl=0.8, nsteps=6)
+    flip = np.array([1.0, 1.0, -1.0, 1.0])[:, None, None] * Ut[:, ::-1, :]
+    scale = np.abs(Ub).max(axis=(1, 2))
+    assert np.abs(flip - Ub).max(axis=(1, 2)).max() <= 1e-12 * scale.max()
+    assert np.array_equal(cb, ct)
+
+
+def test_double_jet_two_states():
+    n = 60
+    o = oracle.Oracle(n, n, hi=(1.5, 1.5), bc=(1, 1), solver="hll", slit=gi.DOUBLE_JET_SLIT)
+    U0 = gi.double_jet(n)
+    assert abs(o.dt(U0, 0.8) - 0.8 * (1.5 / n) / 801.0) <= 1e-15
+    U, _, counts, _ = o.run(U0, cfl=0.8, nsteps=10)
+    assert U[2, :3].max() > 1.0 and U[2, -3:].min() < -1.0  # both jets entered, opposite ways
+    assert np.all(np.isfinite(U)) and np.all(U[0] > 0)
