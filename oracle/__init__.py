@@ -378,6 +378,7 @@ def lib3():
         L.orc3_dt.restype = ctypes.c_double
         L.orc3_run.argtypes = [cp, dp, ctypes.c_double, ctypes.c_int, dp, ip, ctypes.POINTER(ctypes.c_longlong)]
         L.orc3_hllc.argtypes = [ctypes.c_double, dp, dp, ctypes.c_int, dp]
+        L.orc3_relax.argtypes = [cp, dp, dp]
         _lib3 = L
     return _lib3
 
@@ -436,6 +437,14 @@ class Oracle3D:
         it = lib3().orc3_stage(ctypes.byref(self.cfg), int(s), _dp(Un), _dp(Us), float(dt), _dp(out),
                                _ip(order), counts.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)))
         return out, order, counts, it
+
+    def relax(self, Us):
+        """Per cell (nz, ny, nx, 5): rmin, rmax of the density over the cell and its six
+        face neighbours, and the plateau, CSD and u2 verdicts (0/1)."""
+        Us = self._arr(Us)
+        out = np.empty((self.n[2], self.n[1], self.n[0], 5))
+        lib3().orc3_relax(ctypes.byref(self.cfg), _dp(Us), _dp(out))
+        return out
 
     def dt(self, U, cfl):
         return lib3().orc3_dt(ctypes.byref(self.cfg), _dp(self._arr(U)), float(cfl))

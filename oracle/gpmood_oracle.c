@@ -270,8 +270,12 @@ static void cell_relax(const orc_cfg *c, const ghosted *g, int i, int j, relax_t
             if (k == 0) { cmin = kap; cmax = kap; }
             else { cmin = dmin(cmin, kap); cmax = dmax(cmax, kap); }
         }
+        /* eq. (u2_b)'s ratio |Cmin|/|Cmax| >= 1/2 multiplied through by |Cmax|:
+           half of |Cmax| is exact in binary arithmetic, so the comparison decides
+           the paper's inequality exactly (a rounded quotient can accept a ratio
+           just below 1/2); Cmax = Cmin = 0 is accepted by (a) either way */
         int a = (cmin * cmax > -delta) && (dmax(fabs(cmax), fabs(cmin)) < delta);
-        int b = (cmin * cmax > -delta) && (fabs(cmin) / fabs(cmax) >= 0.5);
+        int b = (cmin * cmax > -delta) && (fabs(cmin) >= 0.5 * fabs(cmax));
         ok = ok && (a || b);
     }
     r->u2 = ok;

@@ -198,10 +198,27 @@ static void cell_relax3(const orc3_cfg *c, const ghosted3 *g, int i, int j, int 
             else { cmin = dmin(cmin, kap); cmax = dmax(cmax, kap); }
         }
         int a = (cmin * cmax > -delta) && (dmax(fabs(cmax), fabs(cmin)) < delta);
-        int b = (cmin * cmax > -delta) && (fabs(cmin) / fabs(cmax) >= 0.5);
+        /* eq. (u2_b) multiplied through by |Cmax|, as in the 2D oracle */
+        int b = (cmin * cmax > -delta) && (fabs(cmin) >= 0.5 * fabs(cmax));
         ok = ok && (a || b);
     }
     r->u2 = ok;
+}
+
+/* Relaxation data of every cell: rmin, rmax and (plateau, csd, u2) as 0/1 doubles. */
+void orc3_relax(const orc3_cfg *c, const double *Us, double *out /* [ncell][5] */)
+{
+    ghosted3 g;
+    fill_ghosted(c, Us, &g);
+    for (int k = 0; k < c->n[2]; ++k)
+        for (int j = 0; j < c->n[1]; ++j)
+            for (int i = 0; i < c->n[0]; ++i) {
+                relax3_t r;
+                cell_relax3(c, &g, i, j, k, &r);
+                double *o = out + 5 * cidx(c, i, j, k);
+                o[0] = r.rmin; o[1] = r.rmax; o[2] = r.plat; o[3] = r.csd; o[4] = r.u2;
+            }
+    free(g.u);
 }
 
 static int detect3(const orc3_cfg *c, int order, const relax3_t *r, const double *us, int rs_bad)
