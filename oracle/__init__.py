@@ -379,6 +379,7 @@ def lib3():
         L.orc3_run.argtypes = [cp, dp, ctypes.c_double, ctypes.c_int, dp, ip, ctypes.POINTER(ctypes.c_longlong)]
         L.orc3_hllc.argtypes = [ctypes.c_double, dp, dp, ctypes.c_int, dp]
         L.orc3_relax.argtypes = [cp, dp, dp]
+        L.orc3_candidate.argtypes = [cp, dp, ctypes.c_double, ip, dp, ip]
         _lib3 = L
     return _lib3
 
@@ -437,6 +438,16 @@ class Oracle3D:
         it = lib3().orc3_stage(ctypes.byref(self.cfg), int(s), _dp(Un), _dp(Us), float(dt), _dp(out),
                                _ip(order), counts.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)))
         return out, order, counts, it
+
+    def candidate(self, Us, dt, order):
+        """U* = Us - dt F(Us) for the given per-cell radii, and the per-cell
+        Riemann-state CAD flags."""
+        Us = self._arr(Us)
+        order = np.ascontiguousarray(order, dtype=np.int32)
+        out = np.empty_like(Us)
+        rs = np.empty(order.shape, dtype=np.int32)
+        lib3().orc3_candidate(ctypes.byref(self.cfg), _dp(Us), float(dt), _ip(order), _dp(out), _ip(rs))
+        return out, rs
 
     def relax(self, Us):
         """Per cell (nz, ny, nx, 5): rmin, rmax of the density over the cell and its six

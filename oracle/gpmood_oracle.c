@@ -176,11 +176,6 @@ static void hll(double g, const double *UL, const double *UR, int dir, double *F
         if (SL >= 0.0) f[k] = fk[0][k];
         else if (SR <= 0.0) f[k] = fk[1][k];
         else f[k] = (SR * fk[0][k] - SL * fk[1][k] + SL * SR * (uk[1][k] - uk[0][k])) / (SR - SL);
-        /* a pair with an invalid sound speed (a non-positive pressure or density)
-           has no valid flux: NaN, which fails CAD on both cells of the face
-           (Sec. CAD); the min/max of the wave bounds would otherwise drop the NaN
-           by argument order and break mirror symmetry */
-        if (isnan(cl) || isnan(cr)) f[k] = NAN;
     }
     F[0] = f[0]; F[n] = f[1]; F[t] = f[2]; F[3] = f[3];
 }
@@ -213,8 +208,10 @@ static void recon(const orc_cfg *c, const ghosted *g, int l, int f, int k, int i
 /* CAD on a reconstructed Riemann state (Sec. CAD): the state is inadmissible unless
    its density and pressure are finite and positive.  A non-positive value makes the
    sound speed the square root of a negative number, an invalid operation that CAD
-   exists to catch, and HLLC's wave speeds then order its two states arbitrarily,
-   which breaks the symmetry the Riemann-state check is there to keep. */
+   exists to catch, and the solver's wave speeds then order its two states
+   arbitrarily, which breaks the symmetry the Riemann-state check is there to keep.
+   The flux of such a pair enters the candidates of both cells of the face, so both
+   are troubled, whichever side holds the state and whichever solver runs. */
 static int state_inadmissible(double gam, const double *q)
 {
     double p = pressure(gam, q);
@@ -378,11 +375,9 @@ static void candidate(const orc_cfg *c, const ghosted *g, const int *order, doub
                 double dG = Gy[((size_t)v * (ny + 1) + j + 1) * nx + i] - Gy[((size_t)v * (ny + 1) + j) * nx + i];
                 Ustar[(size_t)v * ncell + cidx] = us - dt * (dF / c->dx + dG / c->dy);
             }
-            /* the cell owns the right state of its left faces and the left state of its right faces */
-            rsbad[cidx] = ((rsx[(size_t)j * (nx + 1) + i] & 2) != 0) ||
-                          ((rsx[(size_t)j * (nx + 1) + i + 1] & 1) != 0) ||
-                          ((rsy[(size_t)j * nx + i] & 2) != 0) ||
-                          ((rsy[(size_t)(j + 1) * nx + i] & 1) != 0);
+            /* an inadmissible state on either side of any of the cell's four faces */
+            rsbad[cidx] = rsx[(size_t)j * (nx + 1) + i] != 0 || rsx[(size_t)j * (nx + 1) + i + 1] != 0 ||
+                          rsy[(size_t)j * nx + i] != 0 || rsy[(size_t)(j + 1) * nx + i] != 0;
         }
     free(Fx); free(Gy); free(rsx); free(rsy);
 }

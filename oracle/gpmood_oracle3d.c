@@ -149,7 +149,8 @@ static void recon3(const orc3_cfg *c, const ghosted3 *g, int l, int f, int q, in
 }
 
 /* CAD on a reconstructed Riemann state (Sec. CAD): density and pressure finite and
-   positive (a non-positive one gives an invalid sound speed). */
+   positive (a non-positive one gives an invalid sound speed); an inadmissible state
+   troubles both cells of its face, as in 2D. */
 static int state_inadmissible(double gam, const double *q)
 {
     double p = pressure(gam, q);
@@ -294,12 +295,21 @@ static void candidate3(const orc3_cfg *c, const ghosted3 *g, const int *order, d
                     P[d] += 1;
                     size_t fp = ((size_t)P[2] * fn[d][1] + P[1]) * fn[d][0] + P[0];
                     for (int v = 0; v < NV; ++v) div[v] += (F[d][(size_t)v * nf + fp] - F[d][(size_t)v * nf + fm]) / c->d[d];
-                    bad = bad || (rs[d][fm] & 2) || (rs[d][fp] & 1);
+                    bad = bad || rs[d][fm] != 0 || rs[d][fp] != 0;
                 }
                 for (int v = 0; v < NV; ++v) Ustar[(size_t)v * nc + ci] = g->u[gidx(g, v, i, j, k)] - dt * div[v];
                 rsbad[ci] = bad;
             }
     for (int d = 0; d < 3; ++d) { free(F[d]); free(rs[d]); }
+}
+
+/* Candidate only (U* and the per-cell Riemann-state CAD flags) for given orders. */
+void orc3_candidate(const orc3_cfg *c, const double *Us, double dt, const int *order, double *Ustar, int *rsbad)
+{
+    ghosted3 g;
+    fill_ghosted(c, Us, &g);
+    candidate3(c, &g, order, dt, Ustar, rsbad);
+    free(g.u);
 }
 
 static void combine3(size_t n, int s, const double *Un, const double *Ustar, double *Uout)

@@ -479,7 +479,7 @@ __global__ __launch_bounds__(128) void k3_cells(const Stage3<real> S, const int 
                 const int fp = ((k + (a == 2)) * m1 + j + (a == 1)) * m0 + i + (a == 0);
 #pragma unroll
                 for (int v = 0; v < 5; ++v) div[v] = div[v] + (S.F[a][v * nfa + fp] - S.F[a][v * nfa + fm]) / S.d[a];
-                rs = rs || (S.Ff[a][fm] & 2) || (S.Ff[a][fp] & 1);
+                rs = rs || (S.Ff[a][fm] | S.Ff[a][fp]) != 0;  // either side of either face
             }
 #pragma unroll
             for (int v = 0; v < 5; ++v) ust[v] = S.Us[v * plane + c] - dt * div[v];

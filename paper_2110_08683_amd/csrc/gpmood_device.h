@@ -339,7 +339,8 @@ __device__ __forceinline__ void parity4(real pp, real mp, real pm, real mm, real
 
 // HLLC flux through a face normal to axis DIR.  badL / badR: the density or the
 // pressure of the left / right state is not finite and positive (CAD on Riemann
-// states: a non-positive value makes the sound speed an invalid square root).
+// states: a non-positive value makes the sound speed an invalid square root, and
+// either flag troubles both cells of the face).
 template <int DIR, typename real>
 __device__ __forceinline__ void hllc(real g, const real *UL, const real *UR, real *F, bool &badL, bool &badR)
 {
@@ -405,15 +406,11 @@ __device__ __forceinline__ void hll(real g, const real *UL, const real *UR, real
     const real uL[4] = {rl, rl * ul, rl * vl, El};
     const real uR[4] = {rr, rr * ur, rr * vr, Er};
     const real iw = dv(real(1), SR - SL), ss = SL * SR;
-    // a pair with an invalid sound speed has no valid flux: NaN, which fails CAD on
-    // both cells of the face whichever side the invalid state is on
-    const bool valid = cl == cl && cr == cr;
     real f[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const real fh = (SR * fL[k] - SL * fR[k] + ss * (uR[k] - uL[k])) * iw;
         f[k] = SL >= real(0) ? fL[k] : (SR <= real(0) ? fR[k] : fh);
-        f[k] = valid ? f[k] : __builtin_nan("");
     }
     F[0] = f[0];
     F[n] = f[1];

@@ -241,8 +241,11 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
                 for (int v = 0; v < 4; ++v) A.FX[v * nfx + fi] = F[v];
                 A.FXf[fi] = (uint8_t)((rsx ? 1 : 0) | (badNb ? 2 : 0));
             }
-            const int badm = __shfl_up((int)badNb, 1);
-            rsx = rsx || (badm != 0);
+            // an inadmissible state on either side of the face troubles both of its
+            // cells: this lane's cell takes faces i+1/2 and i-1/2 (the lane below's)
+            const bool fbad = rsx || badNb;
+            const int badm = __shfl_up((int)fbad, 1);
+            rsx = fbad || (badm != 0);
 #pragma unroll
             for (int v = 0; v < 4; ++v) dFx[v] = F[v] - __shfl_up(F[v], 1);
         }
@@ -296,7 +299,7 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
                     us[v] = ring[slot][v][lane + 3];
                     ust[v] = us[v] - dt * axis_sum(dv(dFxP[v], A.dx), dv(G[v] - Gprev[v], A.dy));
                 }
-                const bool rs = rsxP || rsymP || badLy;
+                const bool rs = rsxP || rsymP || badLy || badRy;
                 auto nb = [&](int di, int dj, int v) { return ring[(jr + dj) & 7][v][lane + 3 + di]; };
                 const bool tr = own && troubled(A, RT, ust, rs, nb);
                 if (own) {
@@ -314,7 +317,7 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) Gprev[v] = G[v];
-            rsymP = badRy;
+            rsymP = badLy || badRy;
         }
 #pragma unroll
         for (int k = 0; k < q; ++k)
@@ -735,8 +738,8 @@ __device__ __forceinline__ bool cell_finish(const StageArgs<real> &A, const Cell
         gy[w][0] = A.GY[w * nfy + gym];
         gy[w][1] = A.GY[w * nfy + gym + nx];
     }
-    // the cell's own states: right state of its - faces, left state of its + faces
-    const bool rs = (A.FXf[fxm] & 2) || (A.FXf[fxm + 1] & 1) || (A.GYf[gym] & 2) || (A.GYf[gym + nx] & 1);
+    // an inadmissible state on either side of any of the cell's faces
+    const bool rs = (A.FXf[fxm] | A.FXf[fxm + 1] | A.GYf[gym] | A.GYf[gym + nx]) != 0;
     real ust[4];
 #pragma unroll
     for (int w = 0; w < 4; ++w) {

@@ -120,7 +120,8 @@ def test_slit_is_for_single_2d_problems(torch_cuda):
 def test_jet_mirror_symmetry_is_exact(torch_cuda, prec):
     """The jet is symmetric about x = 0.75 (the paper: the symmetry is to be kept).
     With HLL unfused, mirror-paired quadrature on y faces, the diagonally paired
-    parity sums and a NaN flux for invalid Riemann pairs, the state stays bit-for-bit
+    parity sums and an inadmissible Riemann state troubling both cells of its face,
+    the state stays bit-for-bit
     mirror-symmetric through 300 steps in both precisions."""
     n = 150
     _note(f"mach jet exact mirror symmetry {n}^2 {prec} 300 steps")

@@ -54,6 +54,94 @@ def test_hllc_resolves_stationary_contact():
         assert abs(F[1] - 0.4) < 1e-15
 
 
+def _pressure_jump(n=16):
+    """Fluid at rest, rho = 1, p = 1e-3 left of the middle and 100 right of it: the
+    radius-3 reconstruction of the cells next to the jump undershoots to a negative
+    pressure at some faces."""
+    rho = np.ones((n, n))
+    p = np.where(np.arange(n)[None, :] < n // 2, 1e-3, 100.0) * np.ones((n, n))
+    return np.stack([rho, 0 * rho, 0 * rho, p / (G - 1)])
+
+
+@pytest.mark.parametrize("solver", ["hllc", "hll"])
+def test_inadmissible_riemann_state_troubles_both_cells_of_its_face(solver):
+    """Sec. CAD, the note on Riemann states: the flux of a pair with an inadmissible
+    state enters the candidates of both cells of the face, so both fail the
+    Riemann-state CAD, whichever side holds the state and in either solver.  Some
+    cells own no inadmissible state and are flagged only through a shared face (an
+    owner-only reading would leave them unflagged)."""
+    n = 16
+    U = _pressure_jump(n)
+    o = oracle.Oracle(n, n, bc=(1, 0), cascade=(3, 2, 1, 0), solver=solver)
+    dt = o.dt(U, 0.8)
+    order = np.full((n, n), 3, np.int32)
+    cand, rs = o.candidate(U, dt, order)
+    # the inadmissible states: reconstruct every face state of the cells near the jump
+    # at radius 3 with the oracle's own weights (the pressure of the x-face states)
+    from oracle import weights_mp
+    st = weights_mp.stencil(3)
+    z = np.array(weights_mp.weights(3, 12.0, 12.0))  # [4 faces][4 nodes][25]
+    owners = set()
+    for i in range(4, 12):
+        for f in (0, 1):  # x- and x+ faces
+            for k in range(4):
+                q = [sum(z[f, k, m] * U[v, 8, min(max(i + di, 0), n - 1)] for m, (di, dj) in enumerate(st))
+                     for v in range(4)]
+                if (G - 1) * (q[3] - 0.5 * (q[1] ** 2 + q[2] ** 2) / q[0]) <= 0 or q[0] <= 0:
+                    owners.add((i, f))
+    assert owners
+    expect = set()
+    for i, f in owners:  # both cells of the face
+        expect |= {i, i - 1} if f == 0 else {i, i + 1}
+    assert set(np.nonzero(rs[8])[0]) == expect
+    assert expect - {i for i, _ in owners}   # flagged through a face only
+    _, tr = o.criteria(U, cand, order, rs)
+    assert np.all(tr[8, sorted(expect)] == 1)
+
+
+def test_inadmissible_riemann_state_rule_is_solver_independent():
+    n = 16
+    U = _pressure_jump(n)
+    flags = []
+    for solver in ("hllc", "hll"):
+        o = oracle.Oracle(n, n, bc=(1, 0), cascade=(3, 2, 1, 0), solver=solver)
+        flags.append(o.candidate(U, o.dt(U, 0.8), np.full((n, n), 3, np.int32))[1])
+    np.testing.assert_array_equal(flags[0], flags[1])
+
+
+def test_inadmissible_riemann_state_troubles_both_cells_3d():
+    """The same rule in the 3D oracle: a jump along x in a 16 x 4 x 4 box, rho 1 | 0.1
+    and p 1e-3 | 100."""
+    n = (16, 4, 4)
+    left = np.arange(n[0])[None, None, :] < n[0] // 2
+    rho = np.where(left, 1.0, 0.1) * np.ones(n[::-1])
+    p = np.where(left, 1e-3, 100.0) * np.ones(n[::-1])
+    U = np.stack([rho, 0 * rho, 0 * rho, 0 * rho, p / (G - 1)])
+    o3 = oracle.Oracle3D(n, hi=(1.0, 0.25, 0.25), bc=(1, 0, 0), cascade=(2, 1, 0))
+    cand, rs = o3.candidate(U, o3.dt(U, 0.3), np.full(n[::-1], 2, np.int32))
+    row = rs[1, 1]
+    assert np.all(rs == row[None, None, :])
+    from oracle import weights3d_mp as w3
+    st = w3.stencil3(2)
+    a = o3.ell / o3.d[0]
+    z = np.array(w3.weights3(2, a, a, a))  # [6 faces][9 nodes][25]
+    line = U[:, 1, 1, :]
+    owners = set()
+    for i in range(n[0]):
+        for f in (0, 1):  # x- and x+ faces
+            for k in range(z.shape[1]):
+                q = [sum(z[f, k, m] * line[v, min(max(i + di, 0), n[0] - 1)] for m, (di, dj, dk) in enumerate(st))
+                     for v in range(5)]
+                if (G - 1) * (q[4] - 0.5 * (q[1] ** 2 + q[2] ** 2 + q[3] ** 2) / q[0]) <= 0 or q[0] <= 0:
+                    owners.add((i, f))
+    assert owners
+    expect = set()
+    for i, f in owners:
+        expect |= {i, i - 1} if f == 0 else {i, i + 1}
+    assert set(np.nonzero(row)[0]) == expect
+    assert expect - {i for i, _ in owners}
+
+
 def test_fog_hllc_shock_tube_matches_exact_riemann():
     """FOG (cascade (0,)) + HLLC on Sod-type tubes converges to the exact solution."""
     for left, right, T in (((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 0.15),

@@ -50,8 +50,8 @@ def test_jet_run_stays_positive_with_the_cascade_at_work():
 
 def test_jet_stays_mirror_symmetric():
     # the problem is symmetric about x = 0.75; the oracle keeps it to its own
-    # summation-order rounding (an invalid Riemann pair gives a NaN flux on either
-    # side, so no decision depends on which side it is on)
+    # summation-order rounding (an inadmissible Riemann state troubles both cells of
+    # its face, so no decision depends on which side it is on)
     n = 60
     U, _, counts, _ = jet(n).run(gi.mach_jet(n), cfl=0.8, nsteps=10)
     assert counts[:, :, 1:].sum() > 0
