@@ -10,7 +10,9 @@ Parts:
                     (80 digits, rounded to double), eqs. (SE-pred), (SE-cov),
                     (gp_reconstructor), (normalized_z), App. B.
   gpmood_oracle.c   the stage: GP reconstruction, HLLC, candidate, MOOD loop
-                    (Steps 3-10), SSP-RK3, dt, totals; plain loops in FP64.
+                    (Steps 3-10), SSP-RK3, dt, totals; plain loops in FP64; the
+                    derivatives of a stage with frozen orders and dt (JVP with
+                    dual numbers, and its transpose, the VJP).
   weights3d_mp.py   the same weights in 3D (L1-ball stencil, tensor Gauss nodes).
   gpmood_oracle3d.c the 3D stage (five variables), same steps.
   exact_riemann.py  Toro's exact Riemann solver for the 1D shock-tube pins.
@@ -105,6 +107,8 @@ def lib():
         L.orc_hllc.argtypes = [ctypes.c_double, dp, dp, ctypes.c_int, dp]
         L.orc_hll.argtypes = [ctypes.c_double, dp, dp, ctypes.c_int, dp]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_stage_jvp.argtypes = [cp, ctypes.c_int, dp, dp, dp, ctypes.c_double, ip, dp]
+        L.orc_stage_vjp.argtypes = [cp, ctypes.c_int, dp, ctypes.c_double, ip, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -273,6 +277,29 @@ class Oracle:
         lib().orc_stage_forced(ctypes.byref(self.cfg), int(s), _dp(Un), _dp(Us), float(dt),
                                _ip(order), _dp(out))
         return out
+
+    def stage_jvp(self, s, Us, dUs, dUn, dt, order):
+        """Directional derivative of the stage with the orders `order` and dt fixed
+        (stage_forced): dU_out for tangents dUs of U_s and dUn of U^n (s = 0: U^n is
+        U_s, dUn ignored)."""
+        Us, dUs = self._arr(Us), self._arr(dUs)
+        dUn = self._arr(dUn) if dUn is not None else np.zeros_like(Us)
+        order = np.ascontiguousarray(order, dtype=np.int32)
+        out = np.empty_like(Us)
+        lib().orc_stage_jvp(ctypes.byref(self.cfg), int(s), _dp(Us), _dp(dUs), _dp(dUn), float(dt), _ip(order),
+                            _dp(out))
+        return out
+
+    def stage_vjp(self, s, Us, dt, order, lam_out):
+        """Transpose of stage_jvp: (lam_Us, lam_Un) for the adjoint lam_out of U_out
+        (lam_Un is None for s = 0, where U^n is U_s)."""
+        Us, lam_out = self._arr(Us), self._arr(lam_out)
+        order = np.ascontiguousarray(order, dtype=np.int32)
+        lus = np.empty_like(Us)
+        lun = np.zeros_like(Us)
+        lib().orc_stage_vjp(ctypes.byref(self.cfg), int(s), _dp(Us), float(dt), _ip(order), _dp(lam_out), _dp(lus),
+                            _dp(lun))
+        return lus, (lun if s > 0 else None)
 
     def candidate(self, Us, dt, order):
         Us = self._arr(Us)

@@ -607,3 +607,283 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* ============================================================ derivatives
+   Derivatives of one stage with the per-cell orders (and dt) held fixed: the
+   stage is then the smooth map of eq. (fvm_discrete) with eq. (fvm_F), the linear
+   reconstruction of eq. (gp_reconstructor) at each face's EDP_1 level, and the
+   combination of eq. (rk3),
+       U_out = beta U^n + alpha (U_s - dt (dF/dx + dG/dy)),
+   alpha, beta = (1, 0), (1/4, 3/4), (2/3, 1/3) for s = 0, 1, 2.  The Riemann
+   solver is differentiated on the branch its values take, with forward-mode dual
+   numbers (value, derivative).  orc_stage_jvp is the directional derivative;
+   orc_stage_vjp its transpose, written as the reverse sweep of the same loops. */
+typedef struct { double v, d; } dual;
+
+static dual dc(double x) { dual r = {x, 0.0}; return r; }
+static dual dadd(dual a, dual b) { dual r = {a.v + b.v, a.d + b.d}; return r; }
+static dual dsub(dual a, dual b) { dual r = {a.v - b.v, a.d - b.d}; return r; }
+static dual dmul(dual a, dual b) { dual r = {a.v * b.v, a.d * b.v + a.v * b.d}; return r; }
+static dual ddiv(dual a, dual b)
+{
+    double q = a.v / b.v;
+    dual r = {q, (a.d - q * b.d) / b.v};
+    return r;
+}
+static dual dsqrt(dual a)
+{
+    double s = sqrt(a.v);
+    dual r = {s, a.d / (2.0 * s)};
+    return r;
+}
+static dual dmin2(dual a, dual b) { return a.v < b.v ? a : b; }
+static dual dmax2(dual a, dual b) { return a.v > b.v ? a : b; }
+
+/* HLLC of hllc() in dual numbers, the same branches taken on the values. */
+static void hllc_d(double g, const dual *UL, const dual *UR, int dir, dual *F)
+{
+    int n = 1 + dir, t = 2 - dir;
+    dual G1 = dc(g - 1.0), half = dc(0.5);
+    dual rl = UL[0], ul = ddiv(UL[n], rl), vl = ddiv(UL[t], rl), El = UL[3];
+    dual rr = UR[0], ur = ddiv(UR[n], rr), vr = ddiv(UR[t], rr), Er = UR[3];
+    dual pl = dmul(G1, dsub(El, dmul(half, dmul(rl, dadd(dmul(ul, ul), dmul(vl, vl))))));
+    dual pr = dmul(G1, dsub(Er, dmul(half, dmul(rr, dadd(dmul(ur, ur), dmul(vr, vr))))));
+    dual cl = dsqrt(ddiv(dmul(dc(g), pl), rl)), cr = dsqrt(ddiv(dmul(dc(g), pr), rr));
+    dual SL = dmin2(dsub(ul, cl), dsub(ur, cr));
+    dual SR = dmax2(dadd(ul, cl), dadd(ur, cr));
+    dual Ss = ddiv(dsub(dadd(dsub(pr, pl), dmul(dmul(rl, ul), dsub(SL, ul))), dmul(dmul(rr, ur), dsub(SR, ur))),
+                   dsub(dmul(rl, dsub(SL, ul)), dmul(rr, dsub(SR, ur))));
+    dual f[4];
+    if (SL.v >= 0.0) {
+        f[0] = dmul(rl, ul); f[1] = dadd(dmul(dmul(rl, ul), ul), pl); f[2] = dmul(dmul(rl, ul), vl);
+        f[3] = dmul(ul, dadd(El, pl));
+    } else if (Ss.v >= 0.0 || SR.v > 0.0) {
+        int left = Ss.v >= 0.0;
+        dual rk = left ? rl : rr, uk = left ? ul : ur, vk = left ? vl : vr, Ek = left ? El : Er;
+        dual pk = left ? pl : pr, Sk = left ? SL : SR;
+        dual fac = ddiv(dmul(rk, dsub(Sk, uk)), dsub(Sk, Ss));
+        dual us[4] = {fac, dmul(fac, Ss), dmul(fac, vk),
+                      dmul(fac, dadd(ddiv(Ek, rk), dmul(dsub(Ss, uk), dadd(Ss, ddiv(pk, dmul(rk, dsub(Sk, uk)))))))};
+        dual uk4[4] = {rk, dmul(rk, uk), dmul(rk, vk), Ek};
+        dual fk[4] = {dmul(rk, uk), dadd(dmul(dmul(rk, uk), uk), pk), dmul(dmul(rk, uk), vk), dmul(uk, dadd(Ek, pk))};
+        for (int k = 0; k < 4; ++k) f[k] = dadd(fk[k], dmul(Sk, dsub(us[k], uk4[k])));
+    } else {
+        f[0] = dmul(rr, ur); f[1] = dadd(dmul(dmul(rr, ur), ur), pr); f[2] = dmul(dmul(rr, ur), vr);
+        f[3] = dmul(ur, dadd(Er, pr));
+    }
+    F[0] = f[0]; F[n] = f[1]; F[t] = f[2]; F[3] = f[3];
+}
+
+/* HLL of hll() in dual numbers. */
+static void hll_d(double g, const dual *UL, const dual *UR, int dir, dual *F)
+{
+    int n = 1 + dir, t = 2 - dir;
+    dual G1 = dc(g - 1.0), half = dc(0.5);
+    dual rl = UL[0], ul = ddiv(UL[n], rl), vl = ddiv(UL[t], rl), El = UL[3];
+    dual rr = UR[0], ur = ddiv(UR[n], rr), vr = ddiv(UR[t], rr), Er = UR[3];
+    dual pl = dmul(G1, dsub(El, dmul(half, dmul(rl, dadd(dmul(ul, ul), dmul(vl, vl))))));
+    dual pr = dmul(G1, dsub(Er, dmul(half, dmul(rr, dadd(dmul(ur, ur), dmul(vr, vr))))));
+    dual cl = dsqrt(ddiv(dmul(dc(g), pl), rl)), cr = dsqrt(ddiv(dmul(dc(g), pr), rr));
+    dual SL = dmin2(dsub(ul, cl), dsub(ur, cr));
+    dual SR = dmax2(dadd(ul, cl), dadd(ur, cr));
+    dual uk[2][4] = {{rl, dmul(rl, ul), dmul(rl, vl), El}, {rr, dmul(rr, ur), dmul(rr, vr), Er}};
+    dual fk[2][4] = {{dmul(rl, ul), dadd(dmul(dmul(rl, ul), ul), pl), dmul(dmul(rl, ul), vl), dmul(ul, dadd(El, pl))},
+                     {dmul(rr, ur), dadd(dmul(dmul(rr, ur), ur), pr), dmul(dmul(rr, ur), vr), dmul(ur, dadd(Er, pr))}};
+    dual f[4];
+    for (int k = 0; k < 4; ++k) {
+        if (SL.v >= 0.0) f[k] = fk[0][k];
+        else if (SR.v <= 0.0) f[k] = fk[1][k];
+        else f[k] = ddiv(dadd(dsub(dmul(SR, fk[0][k]), dmul(SL, fk[1][k])), dmul(dmul(SL, SR), dsub(uk[1][k], uk[0][k]))),
+                         dsub(SR, SL));
+    }
+    F[0] = f[0]; F[n] = f[1]; F[t] = f[2]; F[3] = f[3];
+}
+
+static void riemann_d(const orc_cfg *c, const dual *UL, const dual *UR, int dir, dual *F)
+{
+    if (c->solver == 1) hll_d(c->gamma, UL, UR, dir, F);
+    else hllc_d(c->gamma, UL, UR, dir, F);
+}
+
+static void stage_alpha_beta(int s, double *alpha, double *beta)
+{
+    *alpha = s == 0 ? 1.0 : (s == 1 ? 0.25 : 2.0 / 3.0);
+    *beta = s == 0 ? 0.0 : (s == 1 ? 0.75 : 1.0 / 3.0);
+}
+
+/* Derivative of ghosted cell (i, j) (ghost indices allowed) with respect to the
+   interior cell it copies: its source cell and the factor (-1 for the normal
+   momentum mirrored by a reflecting wall, 0 for the fixed state of an inflow slit). */
+static size_t ghost_source(const orc_cfg *c, int v, int i, int j, double *factor)
+{
+    int si = src_index(i, c->nx, c->bcx), sj = src_index(j, c->ny, c->bcy);
+    double sg = 1.0;
+    if (v == 1 && c->bcx == 2 && (i < 0 || i >= c->nx)) sg = -sg;
+    if (v == 2 && c->bcy == 2 && (j < 0 || j >= c->ny)) sg = -sg;
+    if (i >= c->slit_i0 && i < c->slit_i1 && (((c->slit & 1) && j < 0) || ((c->slit & 2) && j >= c->ny))) sg = 0.0;
+    *factor = sg;
+    return ((size_t)v * c->ny + sj) * c->nx + si;
+}
+
+/* The flux of one face (direction dir, between ghosted cells (iL, jL) and its
+   neighbour along dir) in dual numbers: tangent dU (interior layout) along U_s. */
+static void face_flux_d(const orc_cfg *c, const ghosted *g, const double *dU, int l, int dir, int iL, int jL,
+                        dual *Fout)
+{
+    int iR = iL + (dir == 0), jR = jL + (dir == 1);
+    int fL = dir == 0 ? 1 : 3, fR = dir == 0 ? 0 : 2; /* + face of the left cell, - face of the right one */
+    for (int v = 0; v < NV; ++v) Fout[v] = dc(0.0);
+    for (int k = 0; k < c->nq[l]; ++k) {
+        dual qL[4], qR[4], f[4];
+        int ns = c->nst[l];
+        const double *zL = c->z[l] + ((size_t)fL * c->nq[l] + k) * ns;
+        const double *zR = c->z[l] + ((size_t)fR * c->nq[l] + k) * ns;
+        for (int v = 0; v < NV; ++v) {
+            dual sl = dc(0.0), sr = dc(0.0);
+            for (int m = 0; m < ns; ++m) {
+                int oi = c->off[l][2 * m], oj = c->off[l][2 * m + 1];
+                double fa, fb;
+                size_t a = ghost_source(c, v, iL + oi, jL + oj, &fa);
+                size_t b = ghost_source(c, v, iR + oi, jR + oj, &fb);
+                dual xl = {g->u[gidx(g, v, iL + oi, jL + oj)], fa * dU[a]};
+                dual xr = {g->u[gidx(g, v, iR + oi, jR + oj)], fb * dU[b]};
+                sl = dadd(sl, dmul(dc(zL[m]), xl));
+                sr = dadd(sr, dmul(dc(zR[m]), xr));
+            }
+            qL[v] = sl;
+            qR[v] = sr;
+        }
+        riemann_d(c, qL, qR, dir, f);
+        for (int v = 0; v < NV; ++v) Fout[v] = dadd(Fout[v], dmul(dc(c->qw[l][k]), f[v]));
+    }
+}
+
+static int face_level(const orc_cfg *c, const int *order, int dir, int iL, int jL)
+{
+    int iR = iL + (dir == 0), jR = jL + (dir == 1);
+    int oL = order[(size_t)src_index(jL, c->ny, c->bcy) * c->nx + src_index(iL, c->nx, c->bcx)];
+    int oR = order[(size_t)src_index(jR, c->ny, c->bcy) * c->nx + src_index(iR, c->nx, c->bcx)];
+    return level_of(c, oL < oR ? oL : oR); /* EDP_1 */
+}
+
+/* Directional derivative of the forced-order stage: dUout for the tangents dUs of
+   U_s and dUn of U^n (s = 0 takes U^n = U_s and ignores dUn). */
+void orc_stage_jvp(const orc_cfg *c, int s, const double *Us, const double *dUs, const double *dUn, double dt,
+                   const int *order, double *dUout)
+{
+    int nx = c->nx, ny = c->ny;
+    size_t ncell = (size_t)nx * ny;
+    double alpha, beta;
+    stage_alpha_beta(s, &alpha, &beta);
+    ghosted g;
+    fill_ghosted(c, Us, &g);
+    double *dFx = (double *)calloc((size_t)NV * (nx + 1) * ny, sizeof(double));
+    double *dGy = (double *)calloc((size_t)NV * nx * (ny + 1), sizeof(double));
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i <= nx; ++i) {
+            dual F[4];
+            face_flux_d(c, &g, dUs, face_level(c, order, 0, i - 1, j), 0, i - 1, j, F);
+            for (int v = 0; v < NV; ++v) dFx[((size_t)v * ny + j) * (nx + 1) + i] = F[v].d;
+        }
+    for (int j = 0; j <= ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            dual F[4];
+            face_flux_d(c, &g, dUs, face_level(c, order, 1, i, j - 1), 1, i, j - 1, F);
+            for (int v = 0; v < NV; ++v) dGy[((size_t)v * (ny + 1) + j) * nx + i] = F[v].d;
+        }
+    for (int v = 0; v < NV; ++v)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t k = (size_t)v * ncell + (size_t)j * nx + i;
+                double ddF = dFx[((size_t)v * ny + j) * (nx + 1) + i + 1] - dFx[((size_t)v * ny + j) * (nx + 1) + i];
+                double ddG = dGy[((size_t)v * (ny + 1) + j + 1) * nx + i] - dGy[((size_t)v * (ny + 1) + j) * nx + i];
+                double dstar = dUs[k] - dt * (ddF / c->dx + ddG / c->dy);
+                dUout[k] = alpha * dstar + (s == 0 ? 0.0 : beta * dUn[k]);
+            }
+    free(dFx); free(dGy); free(g.u);
+}
+
+/* Transpose of orc_stage_jvp: for the adjoint lam_out of U_out, lam_Us = the
+   adjoint of U_s and, for s > 0, lam_Un = the adjoint of U^n (for s = 0, U^n is
+   U_s and lam_Un is not written).  Each face's flux adjoint is pulled back through
+   the solver's Jacobian (one dual evaluation per input component) and the
+   reconstruction weights onto the stencil cells. */
+void orc_stage_vjp(const orc_cfg *c, int s, const double *Us, double dt, const int *order, const double *lam_out,
+                   double *lam_Us, double *lam_Un)
+{
+    int nx = c->nx, ny = c->ny;
+    size_t ncell = (size_t)nx * ny;
+    double alpha, beta;
+    stage_alpha_beta(s, &alpha, &beta);
+    ghosted g;
+    fill_ghosted(c, Us, &g);
+    /* U_out = beta U^n + alpha U*: lam_U* = alpha lam_out; U* = U_s - dt div F */
+    for (size_t k = 0; k < (size_t)NV * ncell; ++k) {
+        lam_Us[k] = alpha * lam_out[k];
+        if (s > 0 && lam_Un) lam_Un[k] = beta * lam_out[k];
+    }
+    for (int dir = 0; dir < 2; ++dir) {
+        int nfi = dir == 0 ? nx + 1 : nx, nfj = dir == 0 ? ny : ny + 1;
+        double h = dir == 0 ? c->dx : c->dy;
+        for (int j = 0; j < nfj; ++j)
+            for (int i = 0; i < nfi; ++i) {
+                int iL = dir == 0 ? i - 1 : i, jL = dir == 0 ? j : j - 1;
+                int iR = iL + (dir == 0), jR = jL + (dir == 1);
+                /* the face flux enters U*(R) with +dt/h and U*(L) with -dt/h */
+                double lF[4];
+                int any = 0;
+                for (int v = 0; v < NV; ++v) {
+                    double lr = (iR < nx && jR < ny) ? lam_out[(size_t)v * ncell + (size_t)jR * nx + iR] : 0.0;
+                    double ll = (iL >= 0 && jL >= 0) ? lam_out[(size_t)v * ncell + (size_t)jL * nx + iL] : 0.0;
+                    lF[v] = alpha * dt / h * (lr - ll);
+                    any = any || lF[v] != 0.0;
+                }
+                if (!any) continue;
+                int l = face_level(c, order, dir, iL, jL);
+                int fL = dir == 0 ? 1 : 3, fR = dir == 0 ? 0 : 2;
+                int ns = c->nst[l];
+                for (int k = 0; k < c->nq[l]; ++k) {
+                    /* node states */
+                    dual qL[4], qR[4];
+                    const double *zL = c->z[l] + ((size_t)fL * c->nq[l] + k) * ns;
+                    const double *zR = c->z[l] + ((size_t)fR * c->nq[l] + k) * ns;
+                    for (int v = 0; v < NV; ++v) {
+                        double sl = 0.0, sr = 0.0;
+                        for (int m = 0; m < ns; ++m) {
+                            int oi = c->off[l][2 * m], oj = c->off[l][2 * m + 1];
+                            sl += zL[m] * g.u[gidx(&g, v, iL + oi, jL + oj)];
+                            sr += zR[m] * g.u[gidx(&g, v, iR + oi, jR + oj)];
+                        }
+                        qL[v] = dc(sl);
+                        qR[v] = dc(sr);
+                    }
+                    /* lam_q = w_k J^T lam_F, one Jacobian column per input component */
+                    double gq[8];
+                    for (int col = 0; col < 8; ++col) {
+                        dual a[4], b[4], f[4];
+                        for (int v = 0; v < NV; ++v) {
+                            a[v] = qL[v];
+                            b[v] = qR[v];
+                        }
+                        if (col < 4) a[col].d = 1.0;
+                        else b[col - 4].d = 1.0;
+                        riemann_d(c, a, b, dir, f);
+                        double sacc = 0.0;
+                        for (int v = 0; v < NV; ++v) sacc += lF[v] * f[v].d;
+                        gq[col] = c->qw[l][k] * sacc;
+                    }
+                    /* through the reconstruction onto the stencil cells */
+                    for (int v = 0; v < NV; ++v)
+                        for (int m = 0; m < ns; ++m) {
+                            int oi = c->off[l][2 * m], oj = c->off[l][2 * m + 1];
+                            double fa, fb;
+                            size_t a = ghost_source(c, v, iL + oi, jL + oj, &fa);
+                            size_t b = ghost_source(c, v, iR + oi, jR + oj, &fb);
+                            lam_Us[a] += fa * zL[m] * gq[v];
+                            lam_Us[b] += fb * zR[m] * gq[4 + v];
+                        }
+                }
+            }
+    }
+    free(g.u);
+}
