@@ -212,6 +212,21 @@ gpm_status gpm_totals(gpm_ctx *ctx, double totals[4]);
 /* Totals of an arbitrary device state (same layout as a slot).  Synchronising. */
 gpm_status gpm_totals_dev(gpm_ctx *ctx, const void *U, double totals[4]);
 
+/* gpm_totals_dev for callers that cannot allocate device memory (code under HIP
+   graph capture, tight serving loops, harnesses that forbid allocation): the same
+   kernels and the same result, bit for bit, but its partial sums live in a static
+   device array of the library (64 KiB + 32 B per GPU, held until the process
+   ends) instead of the bound workspace, so the context need not be bound.  The
+   grid may be any size the context allows (the partials are capped at 1024
+   blocks, which stride over larger grids).  It calls no hipMalloc or hipFree.
+   The array is shared by every call on one GPU: calls that overlap on one GPU
+   (from several threads or streams) race and must be serialised by the caller.
+   The calling thread's current device must be the device of the context's
+   stream and of U.  Synchronising.  Errors: GPM_EINVAL (NULL argument),
+   GPM_EHIP (the array's device address could not be found), GPM_EUNSUPPORTED (a
+   device index of 64 or more). */
+gpm_status gpm_totals_static(gpm_ctx *ctx, const void *U, double totals[4]);
+
 /* Tunables.  The cascade of a stage is queued as a batch of multi-block passes
    followed by a single-workgroup kernel that finishes it once a pass leaves at
    most tail_threshold troubled cells (0..4096; it hands back to a new batch if a

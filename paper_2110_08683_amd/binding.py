@@ -26,6 +26,7 @@ EXPORTS = ("gpm_create", "gpm_set_scheme", "gpm_workspace_size", "gpm_bind", "gp
            "gpm_init_state", "gpm_get_state", "gpm_compute_dt", "gpm_compute_dt_dev", "gpm_set_dt", "gpm_stage_dev",
            "gpm_stage_coef", "gpm_lincomb4",
            "gpm_step", "gpm_troubled_counts", "gpm_get_order_mask", "gpm_totals", "gpm_totals_dev",
+           "gpm_totals_static",
            "gpm_set_tuning", "gpm_instrument", "gpm_instrument_read", "gpm_order_ptr", "gpm_stage_vjp",
            "gpm_batch_create",
            "gpm_batch_set_scheme", "gpm_batch_workspace_size", "gpm_batch_bind", "gpm_batch_set_tuning",
@@ -92,6 +93,7 @@ def lib():
         "gpm_get_order_mask": ([ctxp, ctypes.POINTER(ctypes.c_ubyte)], st),
         "gpm_totals": ([ctxp, dp], st),
         "gpm_totals_dev": ([ctxp, vp, dp], st),
+        "gpm_totals_static": ([ctxp, vp, dp], st),
         "gpm_set_tuning": ([ctxp, ctypes.c_int, ctypes.c_int, ctypes.c_int], st),
         "gpm_instrument": ([ctxp, ctypes.c_int], st),
         "gpm_instrument_read": ([ctxp, dp, ctypes.POINTER(ctypes.c_longlong), dp, ctypes.POINTER(ctypes.c_longlong),
@@ -308,6 +310,12 @@ class GPMood:
     def gpm_totals_dev(self, U):
         t = np.zeros(4)
         self._check(lib().gpm_totals_dev(self.ctx, ctypes.c_void_p(U.data_ptr()), _dp(t)))
+        return t
+
+    def gpm_totals_static(self, U):
+        """gpm_totals_dev without the bound workspace (the library's static scratch)."""
+        t = np.zeros(4)
+        self._check(lib().gpm_totals_static(self.ctx, ctypes.c_void_p(U.data_ptr()), _dp(t)))
         return t
 
     def gpm_order_ptr(self):

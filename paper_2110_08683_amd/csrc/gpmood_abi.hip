@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -632,10 +633,66 @@ gpm_status gpm_totals_dev(gpm_ctx *c, const void *U, double totals[4])
     if (nblk > kTotBlocks) nblk = kTotBlocks;
     const double area = c->dx * c->dy;
     hipError_t e = c->prec == GPM_F64
-                       ? launch_totals<double>((const double *)U, c->ncell, area, c->partial, nblk, c->ctl, c->stream)
-                       : launch_totals<float>((const float *)U, c->ncell, area, c->partial, nblk, c->ctl, c->stream);
+                       ? launch_totals<double>((const double *)U, c->ncell, area, c->partial, nblk, c->ctl->totals,
+                                               c->stream)
+                       : launch_totals<float>((const float *)U, c->ncell, area, c->partial, nblk, c->ctl->totals,
+                                              c->stream);
     if (e != hipSuccess) return fail(c, GPM_EHIP, hipGetErrorString(e));
     HIPCHK(c, hipMemcpyAsync(totals, c->ctl->totals, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return GPM_OK;
+}
+
+// Scratch of gpm_totals_static, the totals entry point that allocates nothing:
+// the block partials (kTotBlocks blocks x 4 variables x a double-double) and the
+// four results.  Every device the library runs on holds one copy until the
+// process ends.  In host code the symbol is only a stand-in: its device address
+// comes from hipGetSymbolAddress, once per device (static_scratch below).
+constexpr size_t kStaticPartials = (size_t)kTotBlocks * 4 * 2;
+constexpr size_t kStaticDoubles = kStaticPartials + 4;
+static __device__ __align__(256) double scratch[kStaticDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices];
+
+// Device address of this device's scratch (looked up on the first call per device,
+// with that device current).
+static gpm_status static_scratch(gpm_ctx *c, double **out)
+{
+    int dev = -1;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(c, GPM_EUNSUPPORTED, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return fail(c, GPM_EHIP, e != hipSuccess ? hipGetErrorString(e) : "no scratch address");
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GPM_OK;
+}
+
+gpm_status gpm_totals_static(gpm_ctx *c, const void *U, double totals[4])
+{
+    if (!c || !U || !totals) return GPM_EINVAL;
+    int nblk = (int)((c->ncell + 255) / 256);
+    if (nblk > kTotBlocks) nblk = kTotBlocks;  // the kernels stride over any larger grid
+    if ((size_t)nblk * 4 * 2 > kStaticPartials) return fail(c, GPM_EINVAL, "partials exceed the static scratch");
+    double *ptr = nullptr;
+    gpm_status st = static_scratch(c, &ptr);
+    if (st != GPM_OK) return st;
+    const double area = c->dx * c->dy;
+    // every partial the final sum reads is written by this call's first kernel, so
+    // nothing needs clearing
+    hipError_t e = c->prec == GPM_F64
+                       ? launch_totals<double>((const double *)U, c->ncell, area, ptr, nblk, ptr + kStaticPartials,
+                                               c->stream)
+                       : launch_totals<float>((const float *)U, c->ncell, area, ptr, nblk, ptr + kStaticPartials,
+                                              c->stream);
+    if (e != hipSuccess) return fail(c, GPM_EHIP, hipGetErrorString(e));
+    HIPCHK(c, hipMemcpyAsync(totals, ptr + kStaticPartials, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return GPM_OK;
 }

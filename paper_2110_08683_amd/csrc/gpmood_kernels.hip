@@ -1129,7 +1129,7 @@ __global__ __launch_bounds__(256) void k_totals_partial(const real *U, size_t nc
     }
 }
 
-__global__ void k_totals_final(const double *partial, int nblk, double area, Ctl *ctl)
+__global__ void k_totals_final(const double *partial, int nblk, double area, double *out)
 {
     const int v = threadIdx.x;
     if (v >= 4) return;
@@ -1138,7 +1138,7 @@ __global__ void k_totals_final(const double *partial, int nblk, double area, Ctl
         dd_add(hi, lo, partial[(v * nblk + b) * 2]);
         dd_add(hi, lo, partial[(v * nblk + b) * 2 + 1]);
     }
-    ctl->totals[v] = (hi + lo) * area;
+    out[v] = (hi + lo) * area;
 }
 
 // ------------------------------------------------------------- launchers
@@ -1489,11 +1489,11 @@ hipError_t launch_set_dt(Ctl *ctl, double dt, hipStream_t st)
 }
 
 template <typename real>
-hipError_t launch_totals(const real *U, size_t ncell, double area, double *partial, int nblk, Ctl *ctl,
+hipError_t launch_totals(const real *U, size_t ncell, double area, double *partial, int nblk, double *out,
                          hipStream_t st)
 {
     hipLaunchKernelGGL(k_totals_partial<real>, dim3(nblk, 4), dim3(256), 0, st, U, ncell, partial);
-    hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(64), 0, st, partial, nblk, area, ctl);
+    hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(64), 0, st, partial, nblk, area, out);
     return hipGetLastError();
 }
 
@@ -1512,8 +1512,8 @@ template hipError_t launch_lincomb4<double>(double *, const double *, const doub
                                             const double *, double, double, double, double, size_t, hipStream_t);
 template hipError_t launch_dt<float>(const float *, size_t, double, double, double, double, double, Ctl *, hipStream_t);
 template hipError_t launch_dt<double>(const double *, size_t, double, double, double, double, double, Ctl *, hipStream_t);
-template hipError_t launch_totals<float>(const float *, size_t, double, double *, int, Ctl *, hipStream_t);
-template hipError_t launch_totals<double>(const double *, size_t, double, double *, int, Ctl *, hipStream_t);
+template hipError_t launch_totals<float>(const float *, size_t, double, double *, int, double *, hipStream_t);
+template hipError_t launch_totals<double>(const double *, size_t, double, double *, int, double *, hipStream_t);
 
 template hipError_t launch_batch_stage<float>(const BatchTabs<float> &, int, int, const Cascade *, hipStream_t);
 template hipError_t launch_batch_stage<double>(const BatchTabs<double> &, int, int, const Cascade *, hipStream_t);

@@ -26,7 +26,7 @@ hipError_t launch_dt(const real *U, size_t ncell, double gamma, double dx, doubl
 hipError_t launch_set_dt(Ctl *ctl, double dt, hipStream_t st);
 hipError_t launch_stats(Ctl *ctl, int npass, int reset, hipStream_t st);
 template <typename real>
-hipError_t launch_totals(const real *U, size_t ncell, double area, double *partial, int nblk, Ctl *ctl,
+hipError_t launch_totals(const real *U, size_t ncell, double area, double *partial, int nblk, double *out,
                          hipStream_t st);
 
 template <typename real>
