@@ -8,8 +8,9 @@ PCG64 seed 1 (rho in [0.1, 2], |u|,|v| <= 1.5, p in [0.02, 2]), GP-MOOD7 with th
 A step is one full SSP-RK3 step: the FP64 dt max-reduction and three stages, each
 with its complete MOOD cascade.  The metric is cell-updates per second per RK
 stage: cells * 3 * steps / elapsed, where elapsed is wall time between two
-torch.cuda.synchronize() calls around exactly `steps` steps.  The FP32 bulk path
-is the headline value; the FP64 path is reported beside it.
+torch.cuda.synchronize() calls around exactly `steps` steps after `warmup` steps.
+The value is the FP64 path (the precision the method is stated in); the FP32 bulk
+path (FP64 dt and totals) is reported beside it under "fp32".
 
 The roofline object is for the dominant kernel (the first pass at the top order),
 whose launches are bracketed by HIP events on the library's stream during the
@@ -17,16 +18,20 @@ timed region.  The kernel is bound by vector ALU work, so `achieved` is its
 algorithmic flop count per launch (4.4 kflop per cell x 2048^2 cells) divided by
 its mean launch time; `traffic` is the HBM bytes per launch measured with
 rocprofv3 counters for the current kernel sources (null if they changed).
-cpu_baseline times the plain FP64 oracle (OpenMP over rows, all host cores) on the
-first two steps of the same 2048^2 problem, about 15-20 s of CPU work.
 
-A second leg times the batched ensemble (256 four-quadrant problems of sides 128
-to 1024, FP32, one HIP-graph replay per step) and the same work done one problem
-at a time; it is reported under "batched".  A third leg times a reverse-mode rollout
-(512^2 vortex + density bump, 200 steps, checkpoints every 20) under "adjoint", and
-a fourth the 384^3 3D blast (GP-MOOD5, FP32) under "blast3d".
+"configured_run" runs the configuration as specified, 500 steps from the initial
+state, in both precisions, and states the FP32 error: against the FP64 run after
+500 steps, and against the FP64 oracle after one step.  cpu_baseline times the
+plain FP64 oracle (OpenMP over rows, all host cores) on the first two steps of the
+2048^2 problem, plus a single-thread sample (512^2, two steps).
 
-Usage: python bench.py [--gpus 1] [--steps 500] [--warmup 20] [--batch-steps 10] [--no-cpu-baseline]
+Further legs: the batched ensemble (256 four-quadrant problems of sides 128 to
+1024, FP32, one HIP-graph replay per step) against the same work one problem at a
+time ("batched"); a reverse-mode rollout (512^2 vortex + density bump, 200 steps,
+checkpoints every 20, "adjoint"); the 384^3 3D blast (GP-MOOD5, FP32, "blast3d").
+
+Usage: python bench.py [--gpus 1] [--steps 500] [--warmup 20] [--configured-steps 500]
+                       [--batch-steps 10] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -46,6 +51,7 @@ CASCADE = (3, 2, 1, 0)
 CFL = 0.8
 ORDER_SAMPLE_STEPS = 5   # untimed steps after the timed region that sample the final-order fractions
 CPU_STEPS = 2            # full SSP-RK3 steps of the oracle for the CPU baseline
+CPU_1T_N = 512           # grid of the single-thread oracle sample
 BATCH_N = 256            # problems of the batched ensemble
 COPY_PROBE_BYTES = 512 << 20
 METRIC = "cell-updates/s per RK stage (GP-MOOD7 2D, incl. cascade), % HBM peak; FP32 vs FP64"
@@ -165,31 +171,46 @@ def batch_sizes():
 
 def run_batch(steps, warmup):
     """The batched ensemble: every problem a four-quadrant problem with its own seed
-    (1000 + k), GP-MOOD7 FP32, one HIP-graph replay per SSP-RK3 step."""
+    (1000 + k), GP-MOOD7 FP32, one HIP-graph replay per SSP-RK3 step; timed with the
+    default first-pass march length and again, from the same initial states, with
+    the library's autotuned march lengths per size class."""
     import torch
 
     import gpmood_inputs as gi
     from paper_2110_08683_amd import GPMood, GPMoodBatch
     sides = batch_sizes()
-    b = GPMoodBatch([(n, n) for n in sides], bc=(1, 1), prec="f32", cascade=CASCADE, device="cuda:0")
-    for k, n in enumerate(sides):
-        b.gpm_batch_init_state(k, gi.quadrants(n, n, seed=1000 + k))
-    b.gpm_batch_step(CFL, warmup, use_graph=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.gpm_batch_step(CFL, steps, use_graph=True)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    iters, _ = b.gpm_batch_status()
+    U0s = [gi.quadrants(n, n, seed=1000 + k) for k, n in enumerate(sides)]
+    timed = {}
+    tune = None
+    for mode in ("default", "autotuned"):
+        b = GPMoodBatch([(n, n) for n in sides], bc=(1, 1), prec="f32", cascade=CASCADE, device="cuda:0")
+        for k in range(len(sides)):
+            b.gpm_batch_init_state(k, U0s[k])
+        if mode == "autotuned":
+            t0 = time.perf_counter()
+            rows, gain = b.gpm_batch_autotune(CFL, reps=3)
+            by_side = {}
+            for n, r in zip(sides, rows):
+                by_side[n] = r
+            tune = {"seconds": time.perf_counter() - t0, "first_pass_gain": gain,
+                    "rows_per_wave_by_side": {str(n): by_side[n] for n in sorted(by_side)}}
+        b.gpm_batch_step(CFL, warmup, use_graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.gpm_batch_step(CFL, steps, use_graph=True)
+        torch.cuda.synchronize()
+        timed[mode] = time.perf_counter() - t0
+        iters, _ = b.gpm_batch_status()
+        b.close()
+    el = timed["autotuned"]
     cells = sum(n * n for n in sides)
-    b.close()
     # the same work one problem at a time: one single-problem context per distinct
     # side (its first problem's initial state), weighted by the side's multiplicity
     seq = 0.0
     for n in sorted(set(sides)):
         k = sides.index(n)
         g = GPMood(n, n, bc=(1, 1), prec="f32", cascade=CASCADE, device="cuda:0")
-        g.gpm_init_state(gi.quadrants(n, n, seed=1000 + k))
+        g.gpm_init_state(U0s[k])
         g.gpm_step(CFL, warmup)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -199,6 +220,8 @@ def run_batch(steps, warmup):
         g.close()
     return {"value": cells * 3 * steps / el, "unit": "cell-updates/s", "problems": BATCH_N, "cells": cells,
             "steps": steps, "warmup": warmup, "ms_per_step": 1e3 * el / steps,
+            "default_tuning_value": cells * 3 * steps / timed["default"],
+            "autotuned_over_default": timed["default"] / el, "autotune": tune,
             "mood_iters_last_stage_mean": float(iters.mean()),
             "one_at_a_time_value": cells * 3 * steps / seq, "speedup_vs_one_at_a_time": seq / el,
             "workload": "256 four-quadrant problems (seeds 1000+k), square sides uniform over "
@@ -270,17 +293,107 @@ def run_3d(steps, warmup, n=384):
                         "GP-MOOD5 5-3-1, FP32, CFL 0.3"}
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(U0):
+    """The plain FP64 oracle on the host: the first CPU_STEPS steps of the 2048^2
+    problem on all threads (the state after the first step is returned for the
+    error statement), then a single-thread sample at 512^2."""
     import oracle
+    import gpmood_inputs as gi
     o = oracle.Oracle(N, N, bc=(1, 1), cascade=CASCADE)
+    dt1 = o.dt(U0, CFL)
     t0 = time.perf_counter()
-    _, _, counts, iters = o.run(U0, cfl=CFL, nsteps=CPU_STEPS)
+    U1, _, _, it1 = o.run(U0, fixed_dt=dt1, nsteps=1)
+    U2, _, _, it2 = o.run(U1, cfl=CFL, nsteps=CPU_STEPS - 1)
     el = time.perf_counter() - t0
-    return {"value": N * N * 3 * CPU_STEPS / el, "unit": "cell-updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "the first %d SSP-RK3 steps (%d stages, full MOOD loops, %d evaluations in all, dt "
-                      "reductions included) of the same 2048^2 four-quadrant problem, FP64, %.1f s"
-                      % (CPU_STEPS, 3 * CPU_STEPS, int(iters.sum()), el)}
+    threads = oracle.num_threads()
+    # single-thread sample
+    n1 = CPU_1T_N
+    o1 = oracle.Oracle(n1, n1, bc=(1, 1), cascade=CASCADE)
+    oracle.set_num_threads(1)
+    t1 = time.perf_counter()
+    _, _, _, it_1t = o1.run(gi.quadrants(n1, n1, seed=SEED), cfl=CFL, nsteps=CPU_STEPS)
+    el1 = time.perf_counter() - t1
+    oracle.set_num_threads(threads)
+    out = {"value": N * N * 3 * CPU_STEPS / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+           "cpu_model": cpu_model(),
+           "sample": "the first %d SSP-RK3 steps (%d stages, full MOOD loops, %d evaluations in all, dt "
+                     "reductions included) of the same 2048^2 four-quadrant problem, FP64, %d threads, %.1f s"
+                     % (CPU_STEPS, 3 * CPU_STEPS, int(it1.sum() + it2.sum()), threads, el),
+           "single_thread": {"value": n1 * n1 * 3 * CPU_STEPS / el1, "unit": "cell-updates/s", "cores": 1,
+                             "sample": "the first %d steps of the %d^2 four-quadrant problem (seed %d), FP64, "
+                                       "1 thread, %.1f s" % (CPU_STEPS, n1, SEED, el1)}}
+    return out, U1, dt1
+
+
+def field_errors(U, ref):
+    """Per field: relative L1 (sum |U - ref| / sum |ref|) and relative Linf (max |U -
+    ref| / max |ref|)."""
+    import numpy as np
+    d = np.abs(U - ref)
+    return {"rel_l1": [float(d[v].sum() / max(np.abs(ref[v]).sum(), 1e-300)) for v in range(4)],
+            "rel_linf": [float(d[v].max() / max(np.abs(ref[v]).max(), 1e-300)) for v in range(4)]}
+
+
+def run_configured(steps, U0):
+    """The configuration as specified: `steps` SSP-RK3 steps from the initial state,
+    FP64 and FP32 (no warm-up: the run itself is the workload; the library's first
+    launches are warmed on a separate 2-step run).  Returns each precision's rate,
+    MOOD evaluations per stage and cascade time, and the FP32 error against FP64 at
+    the end."""
+    import torch
+
+    from paper_2110_08683_amd import GPMood
+    out, finals = {}, {}
+    for prec in ("f64", "f32"):
+        w = GPMood(N, N, bc=(1, 1), prec=prec, cascade=CASCADE, device="cuda:0")
+        w.gpm_init_state(U0)
+        w.gpm_step(CFL, 2)
+        w.close()
+        g = GPMood(N, N, bc=(1, 1), prec=prec, cascade=CASCADE, device="cuda:0")
+        g.gpm_init_state(U0)
+        g.gpm_instrument(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.gpm_step(CFL, steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ins = g.gpm_instrument_read()
+        stages = max(1, ins["stages"])
+        finals[prec] = g.gpm_get_state()
+        out[prec] = {"value": N * N * 3 * steps / el, "ms_per_step": 1e3 * el / steps,
+                     "mood_iters_per_stage": ins["mood_iters"] / stages,
+                     "cascade_ms_per_stage": ins["cascade_ms"] / stages,
+                     "first_pass_ms": ins["first_pass_ms"] / max(1, ins["first_pass_launches"]),
+                     "finite": bool((finals[prec] == finals[prec]).all())}
+        g.close()
+    out["fp32_over_fp64"] = out["f32"]["value"] / out["f64"]["value"]
+    out["fp32_vs_fp64_after_run"] = field_errors(finals["f32"], finals["f64"])
+    out["workload"] = ("2048^2 four-quadrant problem, seed 1, %d SSP-RK3 steps from the initial state, "
+                       "GP-MOOD7 7-5-3-1, CFL 0.8" % steps)
+    return out
+
+
+def one_step(prec, U0, dt):
+    """One SSP-RK3 step of the 2048^2 problem at a fixed dt on the GPU (host result)."""
+    from paper_2110_08683_amd import GPMood
+    g = GPMood(N, N, bc=(1, 1), prec=prec, cascade=CASCADE, device="cuda:0")
+    g.gpm_init_state(U0)
+    g.gpm_set_dt(dt)
+    g.gpm_step(0.0, 1)
+    U = g.gpm_get_state()
+    g.close()
+    return U
 
 
 # The implosion of Sec. "The implosion problem in 2D" as the paper runs it (400^2,
@@ -325,7 +438,7 @@ def run_implosion(name, stencil, cascade, csd, prec, n=400, tend=2.5, cfl=0.8):
     asym = max(asym, float(np.abs(U[0] - U[0].T).max() / U[0].max()))
     diag = np.diagonal(U[0])
     kmax = int(np.argmax(diag))
-    return {"problem": "double Mach 800 jets" if double else "Mach 100 jet", "variant": name, "prec": prec, "steps": k, "t": t, "wall_s": wall,
+    return {"variant": name, "prec": prec, "steps": k, "t": t, "wall_s": wall,
             "asymmetry_max": asym, "lowered_fraction_max": frac,
             "rho_min": float(U[0].min()), "diag_rho_max": float(diag[kmax]),
             "diag_rho_max_distance": float((kmax + 0.5) * 0.3 / n * np.sqrt(2.0))}
@@ -408,7 +521,9 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 leg of the timed run")
+    ap.add_argument("--configured-steps", type=int, default=500,
+                    help="steps of the configured run from the initial state, both precisions (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=10,
                     help="steps of the batched-ensemble leg (0 skips it)")
     ap.add_argument("--adjoint-steps", type=int, default=200,
@@ -441,43 +556,52 @@ def main():
         print(f"[bench] copy probe: 3 copies of {COPY_PROBE_BYTES} bytes", file=sys.stderr, flush=True)
         del src, dst
     U0 = gi.quadrants(N, N, seed=SEED)
-    print(f"[bench] fp32 {a.steps} steps after {a.warmup} warmup", file=sys.stderr, flush=True)
-    r32 = run_gpu("f32", a.steps, a.warmup, U0)
-    print(f"[bench] fp32 done: {r32['value']:.3e} cell-updates/s", file=sys.stderr, flush=True)
-    r64 = None
-    if not a.no_fp64:
-        r64 = run_gpu("f64", a.steps, a.warmup, U0)
-        print(f"[bench] fp64 done: {r64['value']:.3e} cell-updates/s", file=sys.stderr, flush=True)
+    print(f"[bench] fp64 {a.steps} steps after {a.warmup} warmup", file=sys.stderr, flush=True)
+    r64 = run_gpu("f64", a.steps, a.warmup, U0)
+    print(f"[bench] fp64 done: {r64['value']:.3e} cell-updates/s", file=sys.stderr, flush=True)
+    r32 = None
+    if not a.no_fp32:
+        r32 = run_gpu("f32", a.steps, a.warmup, U0)
+        print(f"[bench] fp32 done: {r32['value']:.3e} cell-updates/s", file=sys.stderr, flush=True)
+
+    def mood(r):
+        # the cascade is bound by the latency of its dependent passes (one MOOD
+        # evaluation each), not by a throughput roof: its figure is the time per
+        # evaluation and the share of the stage
+        return {"iters_per_stage": r["mood_iters_mean"], "final_order_fraction": r["final_order_fraction"],
+                "cascade_ms_per_stage": r["cascade_ms_mean"], "first_pass_ms": r["first_pass_ms_mean"],
+                "cascade_us_per_evaluation": 1e3 * r["cascade_ms_mean"] / max(r["mood_iters_mean"] - 1.0, 1.0),
+                "cascade_share_of_stage": r["cascade_ms_mean"] / (r["ms_per_step"] / 3.0)}
+
     line = {
         "metric": METRIC,
-        "value": r32["value"],
+        "value": r64["value"],
         "unit": "cell-updates/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": r32["ms_per_step"],
+        "ms_per_step": r64["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "2D four-quadrant Riemann problem, 2048x2048 on [0,1]^2, outflow, PCG64 seed 1, "
                                "GP-MOOD7 cascade 7-5-3-1, ell=12dx, HLLC, SSP-RK3, CFL 0.8",
-                   "cells": N * N, "precision_bulk": "f32", "dt_reduction": "f64"},
-        "roofline": roofline("f32", r32),
-        # the cascade is bound by the latency of its dependent passes (one MOOD
-        # evaluation each), not by a throughput roof: its figure is the time per
-        # evaluation and the share of the stage
-        "mood": {"iters_per_stage": r32["mood_iters_mean"], "final_order_fraction": r32["final_order_fraction"],
-                 "cascade_ms_per_stage": r32["cascade_ms_mean"], "first_pass_ms": r32["first_pass_ms_mean"],
-                 "cascade_us_per_evaluation": 1e3 * r32["cascade_ms_mean"] / max(r32["mood_iters_mean"] - 1.0, 1.0),
-                 "cascade_share_of_stage": r32["cascade_ms_mean"] / (r32["ms_per_step"] / 3.0)},
+                   "cells": N * N, "precision": "f64"},
+        "roofline": roofline("f64", r64),
+        "mood": mood(r64),
     }
-    if r64 is not None:
-        line["fp64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"], "roofline": roofline("f64", r64),
-                        "mood_iters_per_stage": r64["mood_iters_mean"],
-                        "final_order_fraction": r64["final_order_fraction"]}
+    if r32 is not None:
+        line["fp32"] = {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "roofline": roofline("f32", r32),
+                        "mood": mood(r32), "precision": "f32 bulk, f64 dt reduction and totals"}
         line["fp32_over_fp64"] = r32["value"] / r64["value"]
+    if a.configured_steps > 0:
+        print(f"[bench] configured run: {a.configured_steps} steps, fp64 and fp32", file=sys.stderr, flush=True)
+        line["configured_run"] = run_configured(a.configured_steps, U0)
+        cr = line["configured_run"]
+        print(f"[bench] configured run done: fp64 {cr['f64']['value']:.3e}, fp32 {cr['f32']['value']:.3e}",
+              file=sys.stderr, flush=True)
     if a.batch_steps > 0:
         print(f"[bench] batched ensemble {a.batch_steps} steps", file=sys.stderr, flush=True)
         line["batched"] = run_batch(a.batch_steps, 2)
@@ -493,7 +617,13 @@ def main():
               file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(U0)
+        cb, U1o, dt1 = cpu_baseline(U0)
+        line["cpu_baseline"] = cb
+        # the error of each GPU path against the oracle after one step at the oracle's dt
+        line["error_vs_oracle_one_step"] = {"f64": field_errors(one_step("f64", U0, dt1), U1o),
+                                            "f32": field_errors(one_step("f32", U0, dt1), U1o),
+                                            "workload": "2048^2 four-quadrant problem, seed 1, one SSP-RK3 step at "
+                                                        "the oracle's CFL 0.8 dt"}
     print(json.dumps(line))
 
 

@@ -236,6 +236,12 @@ gpm_status gpm_totals_static(gpm_ctx *ctx, const void *U, double totals[4]);
    rows per wavefront march in the first pass.  Defaults 4, 12 and 32. */
 gpm_status gpm_set_tuning(gpm_ctx *ctx, int passes_per_check, int rows_per_wave, int tail_threshold);
 
+/* Which single-workgroup tail finishes a cascade (the schedule only: both give
+   the same bits): lds = 1 keeps each pass's lists, claims and recomputed fluxes in
+   LDS (used while tail_threshold <= 42, so that every pass it runs fits its LDS
+   lists), lds = 0 passes them through global memory.  Errors: GPM_EINVAL. */
+gpm_status gpm_set_cascade_tail(gpm_ctx *ctx, int lds);
+
 /* Instrumentation for measurement (not part of the method).  mode bit 0: every
    first-pass launch and every stage's cascade are bracketed by HIP events on the
    context stream and MOOD iterations are counted on the host (no extra kernels);
@@ -253,10 +259,29 @@ gpm_status gpm_instrument_read(gpm_ctx *ctx, double *first_pass_ms, long long *f
                                double *cascade_ms, long long *stages, long long level_cells[4],
                                long long *mood_iters);
 
+/* Where the last stage's cascade passes ran (measurement, not part of the
+   method): stats[0] = passes run by multi-block kernels, stats[1] = passes run by
+   the single-workgroup tail, stats[2] = hand-backs from the tail to new batches of
+   multi-block passes.  stats[0] + stats[1] + 1 is the number of MOOD evaluations.
+   Not synchronising (host counters, complete once a stage call has returned). */
+gpm_status gpm_cascade_stats(const gpm_ctx *ctx, long long stats[3]);
+
 /* Device address of the context's per-cell order array (uint8 [ny][nx], the GP
    radius of every cell; after a stage, its final orders).  Errors: GPM_ESTATE if
    not bound. */
 gpm_status gpm_order_ptr(const gpm_ctx *ctx, void **order_dev);
+
+/* Bytes of the device workspace the stage adjoint needs (gpm_stage_vjp), bound
+   separately so that a context used only forward does not carry it: one slot per
+   (face direction, face side, stencil offset) and cell of the grid with 4 ghost
+   layers, 100 x 4 x (nx+8) x (ny+8) values of the context's precision, and the
+   FP64 derivative of the weight table with respect to ell. */
+gpm_status gpm_adjoint_workspace_size(const gpm_ctx *ctx, size_t *bytes);
+
+/* Bind caller-owned device memory (>= gpm_adjoint_workspace_size, 256-byte
+   aligned) as the adjoint workspace and write its weight table (synchronising;
+   gpm_set_scheme rewrites it).  Errors: GPM_EINVAL for NULL or misalignment. */
+gpm_status gpm_bind_adjoint(gpm_ctx *ctx, void *adj_work);
 
 /* Adjoint of one stage (vector-Jacobian product) with the forward stage's final
    cell orders and its dt held fixed: the stage is then the smooth map of eq.
@@ -271,10 +296,12 @@ gpm_status gpm_order_ptr(const gpm_ctx *ctx, void **order_dev);
    lam_Us, which then holds the total dL/dU^n of the step.  If dL_dell is
    non-NULL, the stage's contribution to dL/d(ell) (ell the physical GP length
    scale; through the ell-dependence of the reconstruction weights only, the
-   detection being frozen) is added to *dL_dell (synchronising).  The context's
-   stored face fluxes are overwritten (scratch).  Errors: GPM_EINVAL (bad stage,
-   NULL or aliased buffers, dt <= 0), GPM_ESTATE, GPM_EUNSUPPORTED (a reflecting
-   axis). */
+   detection being frozen) is added to *dL_dell (synchronising).  Deterministic:
+   every face writes its contributions to the stencil cells into slots of the
+   adjoint workspace (no atomics), and each cell sums its slots in a fixed order,
+   so repeated calls give the same bits.  Errors: GPM_EINVAL (bad stage, NULL or
+   aliased buffers, dt <= 0), GPM_ESTATE (no adjoint workspace bound),
+   GPM_EUNSUPPORTED (a reflecting axis, HLL, a slit). */
 gpm_status gpm_stage_vjp(gpm_ctx *ctx, int s, const void *Un, const void *Us, const void *order, double dt,
                          const void *lam_out, void *lam_Us, void *lam_Un, double *dL_dell);
 
@@ -307,8 +334,25 @@ gpm_status gpm_batch_workspace_size(const gpm_batch *b, size_t *bytes);
    clears it.  Synchronising.  Errors: GPM_EINVAL for NULL or misalignment. */
 gpm_status gpm_batch_bind(gpm_batch *b, void *mem);
 
-/* First-pass rows per wavefront for every problem (4..256, default 16). */
+/* First-pass rows per wavefront for every problem (4..256, default 12). */
 gpm_status gpm_batch_set_tuning(gpm_batch *b, int rows_per_wave);
+
+/* First-pass rows per wavefront of each problem (nprob values, 4..256). */
+gpm_status gpm_batch_set_tuning_per_problem(gpm_batch *b, const int *rows_per_wave);
+
+/* Autotune the first pass's march length (rows per wavefront) per size class of
+   problem (problems whose cell counts share a power of two): one sweep of
+   coordinate descent over 4, 6, 8, 12, 16, 24, 32 and 64 rows, the classes with the
+   most cells first, each candidate timed on the device with HIP events over reps
+   (1..64) launches of the batch's stage-0 first pass, with the dt of the current
+   states at this CFL.  Stage 0 reads the current state slot and writes another,
+   so the problems' states are left as they were.  The choice is kept (as
+   gpm_batch_set_tuning_per_problem) and returned in rows_out (nprob values,
+   nullable); gain (nullable) receives the first-pass time of the default march
+   length over the chosen ones.  The march length changes the schedule only:
+   every result is the same bits whatever the choice.  Synchronising.  Errors:
+   GPM_EINVAL, GPM_ESTATE (not bound or no scheme), GPM_EHIP. */
+gpm_status gpm_batch_autotune(gpm_batch *b, double cfl, int reps, int *rows_out, double *gain);
 
 /* Initial state / current state of problem p (host double SoA [4][ny_p][nx_p]).
    Synchronising. */

@@ -107,6 +107,7 @@ def lib():
         L.orc_hllc.argtypes = [ctypes.c_double, dp, dp, ctypes.c_int, dp]
         L.orc_hll.argtypes = [ctypes.c_double, dp, dp, ctypes.c_int, dp]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         L.orc_stage_jvp.argtypes = [cp, ctypes.c_int, dp, dp, dp, ctypes.c_double, ip, dp]
         L.orc_stage_vjp.argtypes = [cp, ctypes.c_int, dp, ctypes.c_double, ip, dp, dp, dp]
         _lib = L
@@ -365,6 +366,11 @@ def hll(UL, UR, direction=0, gamma=1.4):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    """OpenMP threads of the oracle's loops from now on (timing only)."""
+    lib().orc_set_num_threads(int(n))
 
 
 # ---------------------------------------------------------------------------- 3D

@@ -608,6 +608,17 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads of the OpenMP loops from now on (timing only; results do not depend on it). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
 /* ============================================================ derivatives
    Derivatives of one stage with the per-cell orders (and dt) held fixed: the
    stage is then the smooth map of eq. (fvm_discrete) with eq. (fvm_F), the linear

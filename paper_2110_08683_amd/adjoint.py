@@ -3,10 +3,12 @@
 `rollout(g, U0, nsteps, cfl, checkpoint_every)` is a torch.autograd.Function over a
 single-problem context `g` (GPMood): the forward advances U0 by nsteps SSP-RK3
 steps on the GPU and keeps the state every `checkpoint_every` steps; the backward
-recomputes each segment from its checkpoint (keeping that segment's stage inputs,
-final cell orders and dt) and runs gpm_stage_vjp stage by stage in reverse.  The
-cell orders and every dt are those of the forward, held fixed (the detection and
-the CFL reduction are not differentiated).  Besides dL/dU0 the backward returns
+recomputes each segment from its checkpoint (keeping that segment's stage inputs
+and final cell orders, with the dt recorded in the forward, which the
+recomputation must reproduce bit for bit) and runs gpm_stage_vjp stage by stage in
+reverse.  The cell orders and every dt are those of the forward, held fixed (the
+detection and the CFL reduction are not differentiated).  The stage adjoint is
+deterministic, so a backward gives the same bits every time.  Besides dL/dU0 the backward returns
 dL/d(ell) through the GP weights (as the gradient of the `ell` input).
 
 Only control flow and buffer handling live here: every arithmetic step of the
@@ -48,7 +50,7 @@ class _Rollout(torch.autograd.Function):
                 U = ctx.checkpoints[seg].clone()
                 tape = []
                 for n in range(n0, n1):
-                    U, dt, stages, orders = _step(g, U, ctx.cfl, keep=True)
+                    U, dt, stages, orders = _step(g, U, ctx.cfl, keep=True, dt_forward=ctx.dts[n])
                     tape.append((dt, stages, orders))
                 for dt, (Un, U1, U2), (o0, o1, o2) in reversed(tape):
                     lam_n = torch.zeros_like(lam)
@@ -63,9 +65,17 @@ class _Rollout(torch.autograd.Function):
         return lam, grad_ell, None, None, None, None
 
 
-def _step(g, Un, cfl, keep):
-    """One SSP-RK3 step of context g from the device tensor Un (4, ny, nx)."""
+def _step(g, Un, cfl, keep, dt_forward=None):
+    """One SSP-RK3 step of context g from the device tensor Un (4, ny, nx).  With
+    dt_forward (the recomputation of a recorded step), the step uses that dt; the
+    dt recomputed from Un must equal it bit for bit (the forward is deterministic),
+    else the recorded orders would not belong to this state."""
     dt = g.gpm_compute_dt_dev(Un, cfl)
+    if dt_forward is not None:
+        if dt != dt_forward:
+            raise RuntimeError(f"recomputed dt {dt!r} differs from the forward's {dt_forward!r}")
+        g.gpm_set_dt(dt_forward)
+        dt = dt_forward
     U1 = torch.empty_like(Un)
     U2 = torch.empty_like(Un)
     U3 = torch.empty_like(Un)

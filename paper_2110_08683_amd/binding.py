@@ -27,9 +27,11 @@ EXPORTS = ("gpm_create", "gpm_set_scheme", "gpm_workspace_size", "gpm_bind", "gp
            "gpm_stage_coef", "gpm_lincomb4",
            "gpm_step", "gpm_troubled_counts", "gpm_get_order_mask", "gpm_totals", "gpm_totals_dev",
            "gpm_totals_static",
-           "gpm_set_tuning", "gpm_instrument", "gpm_instrument_read", "gpm_order_ptr", "gpm_stage_vjp",
+           "gpm_set_tuning", "gpm_set_cascade_tail", "gpm_instrument", "gpm_instrument_read", "gpm_cascade_stats", "gpm_order_ptr", "gpm_adjoint_workspace_size",
+           "gpm_bind_adjoint", "gpm_stage_vjp",
            "gpm_batch_create",
            "gpm_batch_set_scheme", "gpm_batch_workspace_size", "gpm_batch_bind", "gpm_batch_set_tuning",
+           "gpm_batch_set_tuning_per_problem", "gpm_batch_autotune",
            "gpm_batch_init_state", "gpm_batch_get_state", "gpm_batch_step", "gpm_batch_status",
            "gpm_batch_troubled_counts", "gpm_batch_get_order_mask", "gpm_batch_last_error",
            "gpm_batch_destroy", "gpm3_create", "gpm3_set_scheme", "gpm3_workspace_size", "gpm3_bind",
@@ -95,16 +97,22 @@ def lib():
         "gpm_totals_dev": ([ctxp, vp, dp], st),
         "gpm_totals_static": ([ctxp, vp, dp], st),
         "gpm_set_tuning": ([ctxp, ctypes.c_int, ctypes.c_int, ctypes.c_int], st),
+        "gpm_set_cascade_tail": ([ctxp, ctypes.c_int], st),
         "gpm_instrument": ([ctxp, ctypes.c_int], st),
         "gpm_instrument_read": ([ctxp, dp, ctypes.POINTER(ctypes.c_longlong), dp, ctypes.POINTER(ctypes.c_longlong),
                                  ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)], st),
+        "gpm_cascade_stats": ([ctxp, ctypes.POINTER(ctypes.c_longlong)], st),
         "gpm_order_ptr": ([ctxp, ctypes.POINTER(vp)], st),
+        "gpm_adjoint_workspace_size": ([ctxp, ctypes.POINTER(ctypes.c_size_t)], st),
+        "gpm_bind_adjoint": ([ctxp, vp], st),
         "gpm_stage_vjp": ([ctxp, ctypes.c_int, vp, vp, vp, ctypes.c_double, vp, vp, vp, dp], st),
         "gpm_batch_create": ([ctypes.c_int, ctypes.POINTER(gpm_grid), ctypes.c_int, vp, ctypes.POINTER(ctxp)], st),
         "gpm_batch_set_scheme": ([ctxp, ctypes.POINTER(gpm_scheme)], st),
         "gpm_batch_workspace_size": ([ctxp, ctypes.POINTER(ctypes.c_size_t)], st),
         "gpm_batch_bind": ([ctxp, vp], st),
         "gpm_batch_set_tuning": ([ctxp, ctypes.c_int], st),
+        "gpm_batch_set_tuning_per_problem": ([ctxp, ctypes.POINTER(ctypes.c_int)], st),
+        "gpm_batch_autotune": ([ctxp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp], st),
         "gpm_batch_init_state": ([ctxp, ctypes.c_int, dp], st),
         "gpm_batch_get_state": ([ctxp, ctypes.c_int, dp], st),
         "gpm_batch_step": ([ctxp, ctypes.c_double, ctypes.c_int, ctypes.c_int], st),
@@ -312,6 +320,12 @@ class GPMood:
         self._check(lib().gpm_totals_dev(self.ctx, ctypes.c_void_p(U.data_ptr()), _dp(t)))
         return t
 
+    def gpm_cascade_stats(self):
+        """(multi-block passes, tail passes, hand-backs) of the last stage's cascade."""
+        st = (ctypes.c_longlong * 3)()
+        self._check(lib().gpm_cascade_stats(self.ctx, st))
+        return tuple(int(x) for x in st)
+
     def gpm_totals_static(self, U):
         """gpm_totals_dev without the bound workspace (the library's static scratch)."""
         t = np.zeros(4)
@@ -325,8 +339,18 @@ class GPMood:
         off = p.value - self.work_buf.data_ptr()
         return self.work_buf[off:off + self.nx * self.ny].view(self.ny, self.nx)
 
+    def bind_adjoint(self):
+        """Allocate and bind the adjoint workspace (once; torch device memory)."""
+        if getattr(self, "adj_buf", None) is None:
+            nb = ctypes.c_size_t()
+            self._check(lib().gpm_adjoint_workspace_size(self.ctx, ctypes.byref(nb)))
+            self.adj_buf = self.torch.empty(nb.value, dtype=self.torch.uint8, device=self.device)
+            self._check(lib().gpm_bind_adjoint(self.ctx, ctypes.c_void_p(self.adj_buf.data_ptr())))
+
     def gpm_stage_vjp(self, s, Un, Us, order, dt, lam_out, lam_Us, lam_Un=None, want_dell=True):
-        """Stage adjoint; torch device tensors.  Returns this stage's dL/d(ell) (or None)."""
+        """Stage adjoint; torch device tensors.  Returns this stage's dL/d(ell) (or None).
+        Binds the adjoint workspace on first use."""
+        self.bind_adjoint()
         for t in (Us, lam_out, lam_Us) + (() if s == 0 else (Un,)) + (() if lam_Un is None else (lam_Un,)):
             assert t.dtype == self.dtype and t.is_contiguous() and t.numel() == 4 * self.nx * self.ny
         assert order.dtype == self.torch.uint8 and order.numel() == self.nx * self.ny
@@ -341,6 +365,9 @@ class GPMood:
 
     def gpm_set_tuning(self, passes_per_check=4, rows_per_wave=12, tail_threshold=32):
         self._check(lib().gpm_set_tuning(self.ctx, int(passes_per_check), int(rows_per_wave), int(tail_threshold)))
+
+    def gpm_set_cascade_tail(self, lds=True):
+        self._check(lib().gpm_set_cascade_tail(self.ctx, 1 if lds else 0))
 
     def gpm_instrument(self, mode=1):
         """mode 0: off, 1: events and iteration counts, 3: also final-order counts (True means 1)."""
@@ -370,7 +397,10 @@ class GPMoodBatch:
         self.device = torch.device(device if device is not None else "cuda")
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.sizes = [(int(a), int(b)) for a, b in sizes]
+        self.nprob = len(self.sizes)
         self.prec = prec
+        self.top = int(cascade[0])
+        self.torch = torch
         grids = (gpm_grid * len(self.sizes))()
         for k, (nx, ny) in enumerate(self.sizes):
             g = grids[k]
@@ -418,6 +448,46 @@ class GPMoodBatch:
 
     def gpm_batch_set_tuning(self, rows_per_wave=12):
         self._check(lib().gpm_batch_set_tuning(self.b, int(rows_per_wave)))
+
+    def gpm_batch_set_tuning_per_problem(self, rows):
+        arr = (ctypes.c_int * self.nprob)(*[int(r) for r in rows])
+        self._check(lib().gpm_batch_set_tuning_per_problem(self.b, arr))
+
+    def gpm_batch_autotune(self, cfl=0.8, reps=3):
+        """Run the library's autotuner; returns (rows per problem, first-pass gain
+        of the choice over the default march length)."""
+        arr = (ctypes.c_int * self.nprob)()
+        gain = ctypes.c_double()
+        self._check(lib().gpm_batch_autotune(self.b, float(cfl), int(reps), arr, ctypes.byref(gain)))
+        return [int(x) for x in arr], gain.value
+
+    def autotune(self, cfl=0.8, reps=3, cache=None):
+        """Autotuned march lengths with an on-disk cache (JSON file `cache`, keyed by
+        device, precision, top radius and size class of problem): a batch whose
+        classes are all cached takes the cached choice without timing anything.
+        Returns (rows per problem, gain or None when taken from the cache)."""
+        import json
+        import os
+        classes = [int(nx * ny).bit_length() - 1 for nx, ny in self.sizes]
+        dev = self.torch.cuda.get_device_name(self.device)
+        keys = [f"{dev}|{self.prec}|r{self.top}|c{k}" for k in classes]
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+        if all(k in table for k in keys):
+            rows = [int(table[k]) for k in keys]
+            self.gpm_batch_set_tuning_per_problem(rows)
+            return rows, None
+        rows, gain = self.gpm_batch_autotune(cfl, reps)
+        if cache:
+            for k, r in zip(keys, rows):
+                table[k] = r
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return rows, gain
 
     def gpm_batch_init_state(self, p, U):
         nx, ny = self.sizes[p]

@@ -24,7 +24,7 @@ HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
              "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-munsafe-fp-atomics", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 HIP_SOURCES = ["gpmood_kernels.hip", "gpmood_abi.hip", "gpmood_batch.hip", "gpmood_adjoint.hip", "gpmood3d.hip"]
 
 

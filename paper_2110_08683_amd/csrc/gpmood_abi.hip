@@ -203,7 +203,8 @@ gpm_status gpm_set_scheme(gpm_ctx *c, const gpm_scheme *s)
         c->next[s->radius[l]] = l + 1 < s->nlev ? s->radius[l + 1] : 0;
     }
     c->have_scheme = true;
-    return upload_gtab(c);
+    const gpm_status st = upload_gtab(c);
+    return st != GPM_OK ? st : upload_adj_dl(c);
 }
 
 gpm_status gpm_workspace_size(const gpm_ctx *c, size_t *state_bytes, size_t *work_bytes)
@@ -384,6 +385,7 @@ static gpm_status run_stage(gpm_ctx *c, const Weights<real> &W, int s, const voi
     C.ctl = c->ctl;
     C.tail_thr = c->tail_threshold;
     C.back_thr = 4 * c->tail_threshold;
+    C.lds_tail = c->lds_tail;
     PassOut P;
     P.flist = c->flist[1];
     P.clist = c->clist[1];
@@ -412,6 +414,7 @@ static gpm_status run_stage(gpm_ctx *c, const Weights<real> &W, int s, const voi
     // length follows the previous stage's number of multi-block passes.
     int nb = (int)((c->ncell + 63) / 64);
     if (nb > 512) nb = 512;
+    c->cstat[0] = c->cstat[1] = c->cstat[2] = 0;
     int k = 1;  // next cascade pass
     int batch = c->head_guess;
     for (;;) {
@@ -426,13 +429,18 @@ static gpm_status run_stage(gpm_ctx *c, const Weights<real> &W, int s, const voi
         }
         e = launch_cascade_tail<real>(A, C, k, k + batch, kMaxPasses, c->stream);
         if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("cascade tail: ") + hipGetErrorString(e));
-        HIPCHK(c, hipMemcpyAsync(c->pinned, &c->ctl->tail_end, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->pinned, &c->ctl->tail_end, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        const int tail_end = c->pinned[0], tail_k0 = c->pinned[1], back = c->pinned[2];
+        const int tail_end = c->pinned[0], tail_k0 = c->pinned[1], back = c->pinned[2], tail_start = c->pinned[3];
         if (tail_end >= kMaxPasses) {
             c->last_npass = kMaxPasses - 1;
             return fail(c, GPM_ENOTCONV, "MOOD loop exceeded the pass limit");
         }
+        // where the passes of this batch ran: multi-block k .. tail_start-1, the
+        // tail tail_start .. tail_end-1
+        c->cstat[0] += tail_start - k;
+        c->cstat[1] += tail_end - tail_start;
+        c->cstat[2] += back ? 1 : 0;
         if (!back) {
             // multi-block passes this stage needed before the tail (or the end)
             const int head = (tail_k0 > 0 ? tail_k0 : tail_end) - 1;
@@ -527,6 +535,20 @@ gpm_status gpm_step(gpm_ctx *c, double cfl, int nsteps)
     return GPM_OK;
 }
 
+gpm_status gpm_set_cascade_tail(gpm_ctx *c, int lds)
+{
+    if (!c || (lds != 0 && lds != 1)) return GPM_EINVAL;
+    c->lds_tail = lds;
+    return GPM_OK;
+}
+
+gpm_status gpm_cascade_stats(const gpm_ctx *c, long long stats[3])
+{
+    if (!c || !stats) return GPM_EINVAL;
+    for (int q = 0; q < 3; ++q) stats[q] = c->cstat[q];
+    return GPM_OK;
+}
+
 gpm_status gpm_order_ptr(const gpm_ctx *c, void **order_dev)
 {
     if (!c || !order_dev) return GPM_EINVAL;
@@ -552,9 +574,10 @@ static gpm_status stage_vjp(gpm_ctx *c, const Weights<real> &W, int s, const voi
     J.lam_out = (const real *)lam_out;
     J.lam_Us = (real *)lam_Us;
     J.lam_Un = (real *)lam_Un;
-    // scratch: the face-flux arrays (FX then GY, contiguous) hold the FP64
-    // accumulator; the reduction partials hold the ell terms
-    J.acc = (double *)c->FX;
+    // the adjoint workspace holds the contribution slots and the FP64 ell table;
+    // the reduction partials hold the ell terms
+    J.slots = (real *)c->adj;
+    J.dl64 = (const double *)(c->adj + adj_slot_bytes(c));
     J.dl_partial = c->partial;
     hipError_t e = launch_set_dt(c->ctl, dt, c->stream);
     if (e != hipSuccess) return fail(c, GPM_EHIP, hipGetErrorString(e));
@@ -590,8 +613,23 @@ gpm_status gpm_stage_vjp(gpm_ctx *c, int s, const void *Un, const void *Us, cons
     if (c->scheme.solver != GPM_SOLVER_HLLC)
         return fail(c, GPM_EUNSUPPORTED, "the stage adjoint differentiates the HLLC scheme only");
     if (c->grid.slit != 0) return fail(c, GPM_EUNSUPPORTED, "the stage adjoint has no inflow slit");
+    if (!c->adj) return fail(c, GPM_ESTATE, "no adjoint workspace bound (gpm_bind_adjoint)");
     return c->prec == GPM_F64 ? stage_vjp<double>(c, c->w64, s, Un, Us, order, dt, lam_out, lam_Us, lam_Un, dL_dell)
                               : stage_vjp<float>(c, c->w32, s, Un, Us, order, dt, lam_out, lam_Us, lam_Un, dL_dell);
+}
+
+gpm_status gpm_adjoint_workspace_size(const gpm_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return GPM_EINVAL;
+    *bytes = adj_bytes(c);
+    return GPM_OK;
+}
+
+gpm_status gpm_bind_adjoint(gpm_ctx *c, void *adj_work)
+{
+    if (!c || !adj_work || ((uintptr_t)adj_work & 255u)) return fail(c, GPM_EINVAL, "adjoint workspace: NULL or not 256-byte aligned");
+    c->adj = (char *)adj_work;
+    return upload_adj_dl(c);
 }
 
 gpm_status gpm_troubled_counts(gpm_ctx *c, long long counts[4], int *mood_iters)

@@ -68,6 +68,117 @@ __device__ __forceinline__ bool finite(Dual<real> a) { return __builtin_isfinite
 template <typename real>
 __device__ __forceinline__ bool pos_finite(Dual<real> a) { return pos_finite(a.v); }
 
+// ----------------------------------------------------- contribution slots
+// Offsets (da, db) with |da| + |db| <= 3, row by row (db = -3 .. 3): slot offset
+// index of (da, db), and the offsets by index.
+__device__ __forceinline__ int adj_off(int da, int db)
+{
+    const int base = db == -3 ? 0 : (db == -2 ? 1 : (db == -1 ? 4 : (db == 0 ? 9 : (db == 1 ? 16 : (db == 2 ? 21 : 24)))));
+    return base + da + 3 - (db < 0 ? -db : db);
+}
+constexpr int kAdjDa[kAdjOffsets] = {0, -1, 0, 1, -2, -1, 0, 1, 2, -3, -2, -1, 0, 1, 2, 3, -2, -1, 0, 1, 2, -1, 0, 1, 0};
+constexpr int kAdjDb[kAdjOffsets] = {-3, -2, -2, -2, -1, -1, -1, -1, -1, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 2, 2, 2, 3};
+
+// Index of (slot, variable, unwrapped cell (ux, uy)) in the slot array.
+template <typename real>
+__device__ __forceinline__ size_t slot_index(const AdjArgs<real> &J, int slot, int v, int ux, int uy)
+{
+    const size_t EX = (size_t)(J.A.nx + 2 * kAdjGhost), EY = (size_t)(J.A.ny + 2 * kAdjGhost);
+    return ((size_t)slot * 4 + v) * EX * EY + (size_t)(uy + kAdjGhost) * EX + (size_t)(ux + kAdjGhost);
+}
+
+// Store the contributions of a face side whose stencil is centred at (ic, jc)
+// (unwrapped): position (a, b) with mirror values at (+a,+b), (-a,+b), (+a,-b),
+// (-a,-b); mirror cells that coincide (a = 0 or b = 0) share one slot, their
+// values summed in a fixed order.
+template <typename real>
+__device__ __forceinline__ void store_mirrors(const AdjArgs<real> &J, int base, int v, int ic, int jc, int a, int b,
+                                              real pp, real mp, real pm, real mm)
+{
+    real *S = J.slots;
+    if (a == 0 && b == 0) {
+        S[slot_index(J, base + adj_off(0, 0), v, ic, jc)] = ((pp + mp) + pm) + mm;
+    } else if (a == 0) {
+        S[slot_index(J, base + adj_off(0, b), v, ic, jc + b)] = pp + mp;
+        S[slot_index(J, base + adj_off(0, -b), v, ic, jc - b)] = pm + mm;
+    } else if (b == 0) {
+        S[slot_index(J, base + adj_off(a, 0), v, ic + a, jc)] = pp + pm;
+        S[slot_index(J, base + adj_off(-a, 0), v, ic - a, jc)] = mp + mm;
+    } else {
+        S[slot_index(J, base + adj_off(a, b), v, ic + a, jc + b)] = pp;
+        S[slot_index(J, base + adj_off(-a, b), v, ic - a, jc + b)] = mp;
+        S[slot_index(J, base + adj_off(a, -b), v, ic + a, jc - b)] = pm;
+        S[slot_index(J, base + adj_off(-a, -b), v, ic - a, jc - b)] = mm;
+    }
+}
+
+template <typename real>
+__device__ __forceinline__ void zero_face_slots(const AdjArgs<real> &J, int dir, int iL, int jL, int iR, int jR)
+{
+    const int bL = (dir * 2 + 0) * kAdjOffsets, bR = (dir * 2 + 1) * kAdjOffsets;
+    for (int o = 0; o < kAdjOffsets; ++o)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            J.slots[slot_index(J, bL + o, v, iL + kAdjDa[o], jL + kAdjDb[o])] = real(0);
+            J.slots[slot_index(J, bR + o, v, iR + kAdjDa[o], jR + kAdjDb[o])] = real(0);
+        }
+}
+
+// The transposed reconstruction of one face: node adjoints gL, gR of the quarter
+// accumulators (per variable, weight slot and parity component) -> contributions
+// to the stencil cells of both sides, through the same compact weights as the
+// forward; positions beyond the face's radius store zeros.  dl += the face's
+// dL/d(ell) term, the sum over positions of dz/d(ell) x accumulator adjoint x
+// parity sum, formed in FP64.
+template <typename real>
+__device__ __forceinline__ void store_face_slots(const AdjArgs<real> &J, int dir, int iL, int jL, int iR, int jR,
+                                                 int np, int R, const real (&gL)[4][2][4], const real (&gR)[4][2][4],
+                                                 double &dl)
+{
+    const StageArgs<real> &A = J.A;
+    const int nx = A.nx, ny = A.ny;
+    const size_t plane = (size_t)nx * ny;
+    const real *wt = A.gtab + (R * 2 + dir) * kGtabPerDir;
+    const double *dwt = J.dl64 + (R * 2 + dir) * kGtabPerDir;
+    const int bL = (dir * 2 + 0) * kAdjOffsets, bR = (dir * 2 + 1) * kAdjOffsets;
+    for (int e = 0; e < kNPos; ++e) {
+        const int a = (int)((kPosA >> (4 * e)) & 15u), b = (int)((kPosB >> (4 * e)) & 15u);
+        const bool live = e < np;
+        const int xLp = wrap(iL + a, nx, A.bcx), xLm = wrap(iL - a, nx, A.bcx);
+        const int xRp = wrap(iR + a, nx, A.bcx), xRm = wrap(iR - a, nx, A.bcx);
+        const size_t yLp = (size_t)wrap(jL + b, ny, A.bcy) * nx, yLm = (size_t)wrap(jL - b, ny, A.bcy) * nx;
+        const size_t yRp = (size_t)wrap(jR + b, ny, A.bcy) * nx, yRm = (size_t)wrap(jR - b, ny, A.bcy) * nx;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            real hl[4] = {real(0), real(0), real(0), real(0)}, hr[4] = {real(0), real(0), real(0), real(0)};
+            if (live) {
+                const real *U = A.Us + v * plane;
+                double ql[4], qr[4];
+                parity4((double)U[yLp + xLp], (double)U[yLp + xLm], (double)U[yLm + xLp], (double)U[yLm + xLm], ql);
+                parity4((double)U[yRp + xRp], (double)U[yRp + xRm], (double)U[yRm + xRp], (double)U[yRm + xRm], qr);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) {
+                        const real w = wt[p * (kNPos * 4) + e * 4 + c];
+                        const double dw = dwt[p * (kNPos * 4) + e * 4 + c];
+                        hl[c] += w * gL[v][p][c];
+                        hr[c] += w * gR[v][p][c];
+                        dl += dw * ((double)gL[v][p][c] * ql[c] + (double)gR[v][p][c] * qr[c]);
+                    }
+                }
+            }
+            // transpose of the parity sums (pp, mp, pm, mm) -> (EE, OE, EO, OO)
+            store_mirrors(J, bL, v, iL, jL, a, b, hl[C_EE] + hl[C_OE] + hl[C_EO] + hl[C_OO],
+                          hl[C_EE] - hl[C_OE] + hl[C_EO] - hl[C_OO], hl[C_EE] + hl[C_OE] - hl[C_EO] - hl[C_OO],
+                          hl[C_EE] - hl[C_OE] - hl[C_EO] + hl[C_OO]);
+            store_mirrors(J, bR, v, iR, jR, a, b, hr[C_EE] + hr[C_OE] + hr[C_EO] + hr[C_OO],
+                          hr[C_EE] - hr[C_OE] + hr[C_EO] - hr[C_OO], hr[C_EE] + hr[C_OE] - hr[C_EO] - hr[C_OO],
+                          hr[C_EE] - hr[C_OE] - hr[C_EO] + hr[C_OO]);
+        }
+    }
+}
+
 // ------------------------------------------------------------ per-face adjoint
 template <typename real>
 __global__ __launch_bounds__(128) void k_adj_faces(const AdjArgs<real> J)
@@ -112,14 +223,17 @@ __global__ __launch_bounds__(128) void k_adj_faces(const AdjArgs<real> J)
             lF[v] = (alpha * lr - alpha * ll) * inv;
             any = any || lF[v] != real(0);
         }
-        if (!any) continue;
+        if (!any) {
+            // nothing flows through this face: its slots hold zeros
+            zero_face_slots(J, dir, iL, jL, iR, jR);
+            continue;
+        }
         const int cL = wrap(jL, ny, A.bcy) * nx + wrap(iL, nx, A.bcx);
         const int cR = wrap(jR, ny, A.bcy) * nx + wrap(iR, nx, A.bcx);
         const int R = min((int)A.order[cL], (int)A.order[cR]);
         const int np = R <= 0 ? 1 : (R == 1 ? 3 : (R == 2 ? 6 : 10));
         const int q = R <= 0 ? 1 : R + 1;
         const real *wt = A.gtab + (R * 2 + dir) * kGtabPerDir;
-        const real *dwt = A.gtab_dl + (R * 2 + dir) * kGtabPerDir;
         // 1. accumulators of both cells (quarter basis, as the forward)
         real PL[4][2][4], PR[4][2][4];
 #pragma unroll
@@ -211,45 +325,10 @@ __global__ __launch_bounds__(128) void k_adj_faces(const AdjArgs<real> J)
                 }
             }
         }
-        // 4-5. transposed reconstruction into the mirror cells, and the ell term
-        for (int e = 0; e < np; ++e) {
-            const int a = (int)((kPosA >> (4 * e)) & 15u), b = (int)((kPosB >> (4 * e)) & 15u);
-            const int xLp = wrap(iL + a, nx, A.bcx), xLm = wrap(iL - a, nx, A.bcx);
-            const int xRp = wrap(iR + a, nx, A.bcx), xRm = wrap(iR - a, nx, A.bcx);
-            const size_t yLp = (size_t)wrap(jL + b, ny, A.bcy) * nx, yLm = (size_t)wrap(jL - b, ny, A.bcy) * nx;
-            const size_t yRp = (size_t)wrap(jR + b, ny, A.bcy) * nx, yRm = (size_t)wrap(jR - b, ny, A.bcy) * nx;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const real *U = A.Us + v * plane;
-                real ql[4], qr[4];
-                parity4(U[yLp + xLp], U[yLp + xLm], U[yLm + xLp], U[yLm + xLm], ql);
-                parity4(U[yRp + xRp], U[yRp + xRm], U[yRm + xRp], U[yRm + xRm], qr);
-                real hl[4], hr[4];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    hl[c] = real(0);
-                    hr[c] = real(0);
-#pragma unroll
-                    for (int p = 0; p < 2; ++p) {
-                        const real w = wt[p * (kNPos * 4) + e * 4 + c];
-                        const real dw = dwt[p * (kNPos * 4) + e * 4 + c];
-                        hl[c] += w * gL[v][p][c];
-                        hr[c] += w * gR[v][p][c];
-                        dl += (double)(dw * (gL[v][p][c] * ql[c] + gR[v][p][c] * qr[c]));
-                    }
-                }
-                // transpose of the parity sums (pp, mp, pm, mm) -> (EE, OE, EO, OO)
-                double *acc = J.acc + v * plane;
-                atomicAdd(&acc[yLp + xLp], (double)(hl[C_EE] + hl[C_OE] + hl[C_EO] + hl[C_OO]));
-                atomicAdd(&acc[yLp + xLm], (double)(hl[C_EE] - hl[C_OE] + hl[C_EO] - hl[C_OO]));
-                atomicAdd(&acc[yLm + xLp], (double)(hl[C_EE] + hl[C_OE] - hl[C_EO] - hl[C_OO]));
-                atomicAdd(&acc[yLm + xLm], (double)(hl[C_EE] - hl[C_OE] - hl[C_EO] + hl[C_OO]));
-                atomicAdd(&acc[yRp + xRp], (double)(hr[C_EE] + hr[C_OE] + hr[C_EO] + hr[C_OO]));
-                atomicAdd(&acc[yRp + xRm], (double)(hr[C_EE] - hr[C_OE] + hr[C_EO] - hr[C_OO]));
-                atomicAdd(&acc[yRm + xRp], (double)(hr[C_EE] + hr[C_OE] - hr[C_EO] - hr[C_OO]));
-                atomicAdd(&acc[yRm + xRm], (double)(hr[C_EE] - hr[C_OE] - hr[C_EO] + hr[C_OO]));
-            }
-        }
+        // 4-5. transposed reconstruction: each side's contribution to each of its
+        // stencil cells goes to that cell's (direction, side, offset) slot, and
+        // the ell term (in FP64, with the FP64 derivative table)
+        store_face_slots(J, dir, iL, jL, iR, jR, np, R, gL, gR, dl);
     }
     // dL/d(ell) partial of this block, summed in a fixed order
     red[threadIdx.x] = dl;
@@ -261,30 +340,68 @@ __global__ __launch_bounds__(128) void k_adj_faces(const AdjArgs<real> J)
     if (threadIdx.x == 0) J.dl_partial[blockIdx.x] = red[0];
 }
 
+// Unwrapped images of interior index m on an axis of n cells (periodic: m and
+// m -+ n; outflow: the ghost cells that copy an edge cell) within the 4 ghost
+// layers; returns their number (at most 9).
+__device__ __forceinline__ int axis_images(int m, int n, int bc, int (&u)[9])
+{
+    int k = 0;
+    u[k++] = m;
+    if (bc == 0) {
+        for (int w = m - n; w >= -kAdjGhost; w -= n) u[k++] = w;
+        for (int w = m + n; w <= n - 1 + kAdjGhost; w += n) u[k++] = w;
+    } else {
+        if (m == 0)
+            for (int g = 1; g <= kAdjGhost; ++g) u[k++] = -g;
+        if (m == n - 1)
+            for (int g = 0; g < kAdjGhost; ++g) u[k++] = n + g;
+    }
+    return k;
+}
+
+// Per cell and variable: the sum, in a fixed order, of every face side's
+// contribution to the cell (over the cell's unwrapped images, then the slots
+// whose face exists), then dL/dU_s = alpha lam_out + that sum and dL/dU^n.
 template <typename real>
 __global__ __launch_bounds__(256) void k_adj_cells(const AdjArgs<real> J)
 {
     const StageArgs<real> &A = J.A;
-    const size_t n = (size_t)A.nx * A.ny;
+    const int nx = A.nx, ny = A.ny;
+    const size_t n = (size_t)nx * ny;
     const real alpha = A.s == 0 ? real(1) : (A.s == 1 ? real(0.25) : real(2) / real(3));
     const real beta = A.s == 0 ? real(0) : (A.s == 1 ? real(0.75) : real(1) / real(3));
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < 4 * n; k += (size_t)gridDim.x * blockDim.x) {
-        const real lo = J.lam_out[k];
-        const real ls = alpha * lo + (real)J.acc[k];
-        if (A.s > 0) {
-            J.lam_Us[k] = ls;
-            J.lam_Un[k] += beta * lo;
-        } else {
-            // U^n feeds both arguments of stage 0: fold in its other adjoint if given
-            J.lam_Us[k] = J.lam_Un ? ls + J.lam_Un[k] : ls;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+        const int mi = (int)(k % nx), mj = (int)(k / nx);
+        int ux[9], uy[9];
+        const int nix = axis_images(mi, nx, A.bcx, ux), niy = axis_images(mj, ny, A.bcy, uy);
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int qy = 0; qy < niy; ++qy)
+            for (int qx = 0; qx < nix; ++qx)
+                for (int slot = 0; slot < kAdjSlots; ++slot) {
+                    const int dir = slot / (2 * kAdjOffsets), side = (slot / kAdjOffsets) & 1, o = slot % kAdjOffsets;
+                    // the face side whose stencil centre is the image minus the offset
+                    const int ci = ux[qx] - kAdjDa[o], cj = uy[qy] - kAdjDb[o];
+                    bool ok;
+                    if (dir == 0) ok = cj >= 0 && cj < ny && (side == 0 ? (ci >= -1 && ci <= nx - 1) : (ci >= 0 && ci <= nx));
+                    else ok = ci >= 0 && ci < nx && (side == 0 ? (cj >= -1 && cj <= ny - 1) : (cj >= 0 && cj <= ny));
+                    if (!ok) continue;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[v] += (double)J.slots[slot_index(J, slot, v, ux[qx], uy[qy])];
+                }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const size_t q = v * n + k;
+            const real lo = J.lam_out[q];
+            const real ls = (real)((double)(alpha * lo) + acc[v]);
+            if (A.s > 0) {
+                J.lam_Us[q] = ls;
+                J.lam_Un[q] += beta * lo;
+            } else {
+                // U^n feeds both arguments of stage 0: fold in its other adjoint if given
+                J.lam_Us[q] = J.lam_Un ? ls + J.lam_Un[q] : ls;
+            }
         }
     }
-}
-
-__global__ void k_adj_zero(double *acc, size_t n)
-{
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
-        acc[k] = 0.0;
 }
 
 // Fixed-order sum of the per-block partials into *out (one block of 256 threads):
@@ -311,9 +428,8 @@ template <typename real>
 hipError_t launch_stage_vjp(const AdjArgs<real> &J, int nblk_faces, double *dl_out, hipStream_t st)
 {
     const size_t n = (size_t)J.A.nx * J.A.ny;
-    hipLaunchKernelGGL(k_adj_zero, dim3(1024), dim3(256), 0, st, J.acc, 4 * n);
     hipLaunchKernelGGL(k_adj_faces<real>, dim3(nblk_faces), dim3(128), 0, st, J);
-    size_t nb = (4 * n + 255) / 256;
+    size_t nb = (n + 255) / 256;
     if (nb > 4096) nb = 4096;
     hipLaunchKernelGGL(k_adj_cells<real>, dim3((unsigned)nb), dim3(256), 0, st, J);
     hipLaunchKernelGGL(k_adj_dl_final, dim3(1), dim3(256), 0, st, J.dl_partial, nblk_faces, dl_out);

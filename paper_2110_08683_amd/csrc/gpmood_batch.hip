@@ -9,6 +9,7 @@
 // captured step graph can be replayed: the claim stamps advance on the device.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 #include <new>
@@ -46,6 +47,7 @@ struct gpm_batch {
     bool have_scheme = false;
     char *mem = nullptr;
     int rows = 12;
+    std::vector<int> prow;      // first-pass rows per wavefront of each problem (empty: rows)
     int cur = 0;  // slot rotation of the next step (the same for every problem)
     // device tables (inside the caller buffer)
     void *args = nullptr;       // StageArgs<real>[3 rotations][3 stages][nprob]
@@ -138,7 +140,7 @@ static gpm_status build_tables(gpm_batch *b)
     blk[0] = dblk[0] = 0;
     for (int p = 0; p < P; ++p) {
         gpm_ctx *c = b->ctx[p];
-        c->rows = b->rows;
+        c->rows = b->prow.empty() ? b->rows : b->prow[p];
         const Weights<real> &W = *(const Weights<real> *)(sizeof(real) == 8 ? (const void *)&c->w64 : (const void *)&c->w32);
         for (int r = 0; r < 3; ++r) {
             const int u0 = r, a = (r + 1) % 3, bb = (r + 2) % 3;
@@ -169,7 +171,8 @@ static gpm_status build_tables(gpm_batch *b)
         C.ctl = c->ctl;
         C.tail_thr = 0;
         C.back_thr = 0x7fffffff;  // one workgroup per problem runs the whole cascade
-        blk[p + 1] = blk[p] + fp_blocks(c, b->rows);
+        C.lds_tail = 0;
+        blk[p + 1] = blk[p] + fp_blocks(c, c->rows);
         dblk[p + 1] = dblk[p] + dt_blocks(c);
     }
     b->iso = 1;
@@ -249,19 +252,38 @@ static gpm_status stamps_guard(gpm_batch *b, int nsteps)
     return GPM_OK;
 }
 
+// Candidate march lengths of the autotuner, and the time of `reps` batch stage-0
+// first passes (after one untimed launch) between two HIP events.
+static const int kTuneRows[] = {4, 6, 8, 12, 16, 24, 32, 64};
+
+template <typename real>
+static gpm_status time_first_pass(gpm_batch *b, int reps, hipEvent_t e0, hipEvent_t e1, float *ms)
+{
+    const int top = b->ctx[0]->top;
+    BHIPCHK(b, launch_batch_first_pass<real>(tabs<real>(b, b->cur, 0), top, b->nfp, b->casc, b->stream));
+    BHIPCHK(b, hipEventRecord(e0, b->stream));
+    for (int r = 0; r < reps; ++r)
+        BHIPCHK(b, launch_batch_first_pass<real>(tabs<real>(b, b->cur, 0), top, b->nfp, b->casc, b->stream));
+    BHIPCHK(b, hipEventRecord(e1, b->stream));
+    BHIPCHK(b, hipEventSynchronize(e1));
+    BHIPCHK(b, hipEventElapsedTime(ms, e0, e1));
+    b->stages_run += (unsigned long long)reps + 1;
+    return GPM_OK;
+}
+
 extern "C" {
 
 gpm_status gpm_batch_create(int nprob, const gpm_grid *grids, int prec, void *hip_stream, gpm_batch **out)
 {
     if (!out || !grids || nprob < 1 || nprob > 65536) return GPM_EINVAL;
     *out = nullptr;
+    for (int p = 0; p < nprob; ++p)
+        if (grids[p].slit != 0) return GPM_EUNSUPPORTED;  // single problems only (checked before allocating)
     gpm_batch *b = new (std::nothrow) gpm_batch;
     if (!b) return GPM_ENOMEM;
     b->nprob = nprob;
     b->prec = prec;
     b->stream = (hipStream_t)hip_stream;
-    for (int p = 0; p < nprob; ++p)
-        if (grids[p].slit != 0) return GPM_EUNSUPPORTED;  // single problems only
     for (int p = 0; p < nprob; ++p) {
         gpm_ctx *c = nullptr;
         const gpm_status st = gpm_create(&grids[p], prec, hip_stream, &c);
@@ -376,7 +398,103 @@ gpm_status gpm_batch_set_tuning(gpm_batch *b, int rows_per_wave)
 {
     if (!b || rows_per_wave < 4 || rows_per_wave > 256) return GPM_EINVAL;
     b->rows = rows_per_wave;
+    b->prow.clear();
     return rebuild(b);
+}
+
+gpm_status gpm_batch_set_tuning_per_problem(gpm_batch *b, const int *rows)
+{
+    if (!b || !rows) return GPM_EINVAL;
+    for (int p = 0; p < b->nprob; ++p)
+        if (rows[p] < 4 || rows[p] > 256) return bfail(b, GPM_EINVAL, "rows per wave must be 4..256");
+    b->prow.assign(rows, rows + b->nprob);
+    return rebuild(b);
+}
+
+// The autotuner: the first pass's march length (rows per wavefront) chosen per
+// size class of problem (problems whose cell counts share a power of two), by
+// timing the batch's stage-0 first pass on the device with HIP events.  Stage 0
+// reads the current slot and writes another, so the timed launches leave the
+// problems' states as they were.  One sweep of coordinate descent, the classes
+// with the most cells first, each over the candidates below; ties keep the
+// shorter march.  The choice changes the schedule only: every stage gives the same
+// bits whatever the march length.
+gpm_status gpm_batch_autotune(gpm_batch *b, double cfl, int reps, int *rows_out, double *gain)
+{
+    if (!b || reps < 1 || reps > 64 || !(cfl > 0.0)) return GPM_EINVAL;
+    if (!b->mem || !b->have_scheme) return bfail(b, GPM_ESTATE, "not bound or no scheme");
+    const int P = b->nprob;
+    // size classes
+    std::vector<int> cls(P);
+    std::vector<long long> cells(64, 0);
+    for (int p = 0; p < P; ++p) {
+        int k = 0;
+        while (k < 62 && (1ull << (k + 1)) <= (unsigned long long)b->ctx[p]->ncell) ++k;
+        cls[p] = k;
+        cells[k] += (long long)b->ctx[p]->ncell;
+    }
+    std::vector<int> order;
+    for (int k = 0; k < 64; ++k)
+        if (cells[k] > 0) order.push_back(k);
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return cells[x] > cells[y]; });
+    // the stages' dt (as a step would compute it) for realistic detection work
+    gpm_status st = stamps_guard(b, 64 * (int)(sizeof(kTuneRows) / sizeof(int)) * (int)order.size());
+    if (st != GPM_OK) return st;
+    const hipError_t de = b->prec == GPM_F64
+                              ? launch_batch_dt<double>(tabs<double>(b, b->cur, 0), b->ndt, b->casc, cfl, b->stream)
+                              : launch_batch_dt<float>(tabs<float>(b, b->cur, 0), b->ndt, b->casc, cfl, b->stream);
+    BHIPCHK(b, de);
+    std::vector<int> rows(P);
+    for (int p = 0; p < P; ++p) rows[p] = b->prow.empty() ? b->rows : b->prow[p];
+    hipEvent_t e0, e1;
+    BHIPCHK(b, hipEventCreate(&e0));
+    BHIPCHK(b, hipEventCreate(&e1));
+    for (size_t oi = 0; oi < order.size() && st == GPM_OK; ++oi) {
+        const int k = order[oi];
+        int best = -1;
+        float tbest = 0.f;
+        for (int cand : kTuneRows) {
+            for (int p = 0; p < P; ++p)
+                if (cls[p] == k) rows[p] = cand;
+            b->prow = rows;
+            st = rebuild(b);
+            float ms = 0.f;
+            if (st == GPM_OK)
+                st = b->prec == GPM_F64 ? time_first_pass<double>(b, reps, e0, e1, &ms)
+                                        : time_first_pass<float>(b, reps, e0, e1, &ms);
+            if (st != GPM_OK) break;
+            if (best < 0 || ms < tbest) {
+                best = cand;
+                tbest = ms;
+            }
+        }
+        if (st != GPM_OK) break;
+        for (int p = 0; p < P; ++p)
+            if (cls[p] == k) rows[p] = best;
+    }
+    // the default march length and the chosen ones, timed alike
+    float tdef = 0.f, ttun = 0.f;
+    if (st == GPM_OK) {
+        b->prow.clear();
+        st = rebuild(b);
+        if (st == GPM_OK)
+            st = b->prec == GPM_F64 ? time_first_pass<double>(b, reps, e0, e1, &tdef)
+                                    : time_first_pass<float>(b, reps, e0, e1, &tdef);
+    }
+    if (st == GPM_OK) {
+        b->prow = rows;
+        st = rebuild(b);
+        if (st == GPM_OK)
+            st = b->prec == GPM_F64 ? time_first_pass<double>(b, reps, e0, e1, &ttun)
+                                    : time_first_pass<float>(b, reps, e0, e1, &ttun);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != GPM_OK) return st;
+    if (rows_out)
+        for (int p = 0; p < P; ++p) rows_out[p] = rows[p];
+    if (gain) *gain = ttun > 0.f ? (double)tdef / (double)ttun : 1.0;
+    return st;
 }
 
 gpm_status gpm_batch_init_state(gpm_batch *b, int p, const double *U)

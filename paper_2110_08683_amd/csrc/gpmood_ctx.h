@@ -61,6 +61,7 @@ struct gpm_ctx {
     int passes_per_check = 4;  // smallest batch of multi-block cascade passes
     int head_guess = 4;        // batch length: the previous stage's multi-block passes + 2
     int tail_threshold = 32;   // troubled cells at or below which one workgroup finishes the cascade
+    int lds_tail = 0;          // 1: that workgroup keeps its pass-to-pass traffic in LDS
     int rows = 12;
     int si0 = 0, si1 = 0;  // inflow slit cells [si0, si1)
     double slit_u[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};  // bottom, top
@@ -71,6 +72,10 @@ struct gpm_ctx {
     // instrumentation
     int instrument = 0;           // bit 0: stage events and iteration counts, bit 1: level statistics
     long long acc_iters = 0, acc_stages = 0;
+    long long cstat[3] = {0, 0, 0};  // last stage: multi-block passes, tail passes, hand-backs
+    // adjoint workspace (gpm_bind_adjoint): contribution slots, then the FP64
+    // derivative of the compact weight table with respect to ell
+    char *adj = nullptr;
     std::vector<hipEvent_t> evs;  // 3 per instrumented stage: first pass start/end, stage end
     size_t nev_used = 0;
     std::string err;
@@ -80,6 +85,26 @@ static inline gpm_status fail(gpm_ctx *c, gpm_status st, const std::string &msg)
 {
     if (c) c->err = msg;
     return st;
+}
+
+// Adjoint workspace: [kAdjSlots][4][ny+8][nx+8] values of the state precision,
+// then kGtabSize doubles (256-byte aligned parts).
+static inline size_t adj_slot_bytes(const gpm_ctx *c)
+{
+    const size_t esz = c->prec == GPM_F64 ? 8 : 4;
+    return align_up((size_t)kAdjSlots * 4 * (size_t)(c->nx + 2 * kAdjGhost) * (size_t)(c->ny + 2 * kAdjGhost) * esz);
+}
+static inline size_t adj_bytes(const gpm_ctx *c) { return adj_slot_bytes(c) + align_up((size_t)kGtabSize * 8); }
+
+// Copy the FP64 ell-derivative of the compact weights into the adjoint workspace.
+static inline gpm_status upload_adj_dl(gpm_ctx *c)
+{
+    if (!c->adj || !c->have_scheme) return GPM_OK;
+    hipError_t e = hipMemcpyAsync(c->adj + adj_slot_bytes(c), c->gtab64.data() + kGtabSize,
+                                  (size_t)kGtabSize * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("adjoint table upload: ") + hipGetErrorString(e));
+    return GPM_OK;
 }
 
 // Copy the compact cascade weights into the workspace (synchronous: a setup step).

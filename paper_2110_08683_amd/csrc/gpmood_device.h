@@ -108,6 +108,7 @@ struct Ctl {
     int tail_end;     // first pass the tail did not run
     int tail_k0;      // first pass left to the tail by the multi-block passes (0: none)
     int tail_back;    // 1: the tail stopped at tail_end because the pass grew large
+    int tail_start;   // first pass the tail ran (instrumentation)
     unsigned stamp0;  // claim stamp of this stage's first pass; pass k claims with stamp0 + k
 };
 
@@ -122,6 +123,7 @@ struct Cascade {
     int *clist[2];
     Ctl *ctl;
     int tail_thr, back_thr;
+    int lds_tail;  // 1: the single-workgroup tail keeps its lists, claims and fluxes in LDS
 };
 
 // ------------------------------------------------------------------ helpers
@@ -579,15 +581,23 @@ struct BatchTabs {
 
 // Arguments of the stage adjoint: A carries U^n, U_s, the frozen final orders of
 // the forward stage (A.order), dt and the weights; lam_* are [4][ny][nx] in the
-// state precision; acc is an FP64 [4][ny][nx] accumulator; dl_partial holds one
-// dL/d(ell) partial per block of the face kernel.
+// state precision.  slots: the per-face contributions to the stencil cells, one
+// slot per (face direction, side, stencil offset) on the grid with 4 ghost layers
+// ([kAdjSlots][4][ny+8][nx+8], state precision), each (slot, cell) written by
+// exactly one face; dl64: the FP64 derivative of the compact weight table with
+// respect to ell; dl_partial holds one dL/d(ell) partial per block of the face
+// kernel.
+constexpr int kAdjOffsets = 25;  // offsets (da, db) with |da| + |db| <= 3
+constexpr int kAdjSlots = 4 * kAdjOffsets;
+constexpr int kAdjGhost = 4;
 template <typename real>
 struct AdjArgs {
     StageArgs<real> A;
     const real *lam_out;
     real *lam_Us;
     real *lam_Un;
-    double *acc;
+    real *slots;
+    const double *dl64;
     double *dl_partial;
 };
 

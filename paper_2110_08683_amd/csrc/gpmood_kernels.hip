@@ -46,14 +46,12 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
 // re-evaluation.  A stamp per face and per cell keeps each list duplicate-free.
 // Must be reached by all 64 lanes of the wavefront together.
 template <typename real>
-__device__ __forceinline__ void claim_after_lowering(const StageArgs<real> &A, const PassOut &P, int i, int j,
-                                                     bool act)
+__device__ __forceinline__ void claim_ids(const StageArgs<real> &A, int i, int j, int (&fid)[6], bool (&fok)[6],
+                                          int (&cid)[5], bool (&cok)[5])
 {
     const int nx = A.nx, ny = A.ny;
     const int nfx = (nx + 1) * ny;
     // faces: x faces i, i+1 of row j; y faces j, j+1 of column i; periodic duplicates
-    int fid[6];
-    bool fok[6];
     fid[0] = j * (nx + 1) + i;
     fid[1] = j * (nx + 1) + i + 1;
     fid[2] = nfx + j * nx + i;
@@ -64,8 +62,6 @@ __device__ __forceinline__ void claim_after_lowering(const StageArgs<real> &A, c
     fok[5] = A.bcy == 0 && (j == 0 || j == ny - 1);
     fid[5] = fok[5] ? (j == 0 ? nfx + ny * nx + i : nfx + i) : fid[2];      // copy of face 0 / face ny
     const int di[5] = {0, -1, 1, 0, 0}, dj[5] = {0, 0, 0, -1, 1};
-    int cid[5];
-    bool cok[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
         const int ii = i + di[k], jj = j + dj[k];
@@ -73,6 +69,15 @@ __device__ __forceinline__ void claim_after_lowering(const StageArgs<real> &A, c
         // (on a non-periodic axis only in-domain indices get here: no mirror needed)
         cid[k] = cok[k] ? wrap<false>(jj, ny, A.bcy) * nx + wrap<false>(ii, nx, A.bcx) : j * nx + i;
     }
+}
+
+template <typename real>
+__device__ __forceinline__ void claim_after_lowering(const StageArgs<real> &A, const PassOut &P, int i, int j,
+                                                     bool act)
+{
+    int fid[6], cid[5];
+    bool fok[6], cok[5];
+    claim_ids(A, i, j, fid, fok, cid, cok);
     bool fmine[6], cmine[5];
     int nmine = 0;
     if (act) {
@@ -427,7 +432,8 @@ __device__ __forceinline__ void load_gtab(const real *gtab, real *wl)
 template <bool WALLS, bool HLL, typename real>
 __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real *wl, FaceXchg<real> &X,
                                             const int *flist, int n, int t0, int stride, int pre = 0,
-                                            bool use_pre = false)
+                                            bool use_pre = false, real (*lflux)[4] = nullptr,
+                                            int *lflag = nullptr)
 {
     const int nx = A.nx, ny = A.ny;
     const int nfx = (nx + 1) * ny, nfy = nx * (ny + 1);
@@ -650,6 +656,10 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
                 A.GY[(size_t)v * nfy + fo] = F;
                 if (v == 0) A.GYf[fo] = (uint8_t)fl;
             }
+            if (lflux) {  // the LDS copy at the face's list index (the LDS cascade)
+                lflux[idx][v] = F;
+                if (v == 0) lflag[idx] = fl;
+            }
         }
         wave_lds_sync();  // the next round overwrites X
     }
@@ -722,30 +732,52 @@ __device__ __forceinline__ void cell_load(const StageArgs<real> &A, int c, CellI
     X.o = A.order[c];
 }
 
-// Returns whether the cell is troubled (it has then been lowered).
+// The stored fluxes and Riemann-state flags of a cell's four faces (faces i-1/2,
+// i+1/2, j-1/2, j+1/2; fid: their face ids as the claims list them).
 template <typename real>
-__device__ __forceinline__ bool cell_finish(const StageArgs<real> &A, const CellIn<real> &X, real dt)
+struct CellFlux {
+    real f[4][4];  // [face][variable]
+    int fl[4];
+    int fid[4];
+};
+
+template <typename real>
+__device__ __forceinline__ void cell_fetch(const StageArgs<real> &A, const CellIn<real> &X, CellFlux<real> &F)
 {
     const int nx = A.nx, ny = A.ny;
-    const size_t plane = (size_t)nx * ny;
     const size_t nfx = (size_t)(nx + 1) * ny, nfy = (size_t)nx * (ny + 1);
     const size_t fxm = (size_t)X.j * (nx + 1) + X.i, gym = (size_t)X.j * nx + X.i;  // faces i-1/2, j-1/2
-    real fx[4][2], gy[4][2];
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
-        fx[w][0] = A.FX[w * nfx + fxm];
-        fx[w][1] = A.FX[w * nfx + fxm + 1];
-        gy[w][0] = A.GY[w * nfy + gym];
-        gy[w][1] = A.GY[w * nfy + gym + nx];
+        F.f[0][w] = A.FX[w * nfx + fxm];
+        F.f[1][w] = A.FX[w * nfx + fxm + 1];
+        F.f[2][w] = A.GY[w * nfy + gym];
+        F.f[3][w] = A.GY[w * nfy + gym + nx];
     }
+    F.fl[0] = A.FXf[fxm];
+    F.fl[1] = A.FXf[fxm + 1];
+    F.fl[2] = A.GYf[gym];
+    F.fl[3] = A.GYf[gym + nx];
+    F.fid[0] = (int)fxm;
+    F.fid[1] = (int)fxm + 1;
+    F.fid[2] = (int)(nfx + gym);
+    F.fid[3] = (int)(nfx + gym + nx);
+}
+
+// Returns whether the cell is troubled (it has then been lowered).
+template <typename real>
+__device__ __forceinline__ bool cell_finish_flux(const StageArgs<real> &A, const CellIn<real> &X,
+                                                 const CellFlux<real> &F, real dt)
+{
+    const size_t plane = (size_t)A.nx * A.ny;
     // an inadmissible state on either side of any of the cell's faces
-    const bool rs = (A.FXf[fxm] | A.FXf[fxm + 1] | A.GYf[gym] | A.GYf[gym + nx]) != 0;
+    const bool rs = (F.fl[0] | F.fl[1] | F.fl[2] | F.fl[3]) != 0;
     real ust[4];
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
         const real us = w == 0 ? X.rho[0] : X.mom[0][w - 1];
-        const real dFx = fx[w][1] - fx[w][0];
-        ust[w] = us - dt * axis_sum(dv(dFx, A.dx), dv(gy[w][1] - gy[w][0], A.dy));
+        const real dFx = F.f[1][w] - F.f[0][w];
+        ust[w] = us - dt * axis_sum(dv(dFx, A.dx), dv(F.f[3][w] - F.f[2][w], A.dy));
     }
     auto nb = [&](int di, int dj, int w) -> real {
         int m = 0;
@@ -759,6 +791,14 @@ __device__ __forceinline__ bool cell_finish(const StageArgs<real> &A, const Cell
     for (int w = 0; w < 4; ++w) A.Uout[w * plane + X.c] = combine(A.s, X.un[w], ust[w], A.ca, A.cb);
     if (tr) A.order[X.c] = (uint8_t)A.next[X.o];
     return tr;
+}
+
+template <typename real>
+__device__ __forceinline__ bool cell_finish(const StageArgs<real> &A, const CellIn<real> &X, real dt)
+{
+    CellFlux<real> F;
+    cell_fetch(A, X, F);
+    return cell_finish_flux(A, X, F, dt);
 }
 
 template <bool WALLS, typename real>
@@ -946,6 +986,7 @@ __device__ __forceinline__ void tail_body(const StageArgs<real> &A, const Cascad
     if (threadIdx.x == 0) {
         ctl->tail_end = k;
         ctl->tail_back = back ? 1 : 0;
+        ctl->tail_start = k0;
         if (back) ctl->tail_k0 = 0;  // the next multi-block batch starts afresh
     }
 }
@@ -956,6 +997,295 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const StageArgs<real> A, 
 {
     __shared__ TailShared<real> S;
     tail_body<WALLS, HLL>(A, C, kbeg, kdef, kend, S);
+}
+
+// ------------------------------------------------------ the LDS cascade tail
+// The tail of a long cascade with its pass-to-pass traffic kept in LDS: the face
+// and cell lists of the next pass, the claims that build them (hash sets instead
+// of stamps in global memory), and the fluxes of the faces a pass recomputes,
+// which the pass's cells read from LDS.  Within a pass only LDS is waited for;
+// the global stores (fluxes, stage outputs, lowered orders) complete by the
+// barrier that ends the pass, before the next pass reads them.  The arithmetic is
+// that of the faces and cells kernels, so the results are the same bits; only
+// the order of list entries differs.  Used while every pass's claims fit its
+// lists: the previous evaluation left at most kLdsTroubled troubled cells
+// (the tail hands back above back_thr <= kLdsTroubled).
+constexpr int kLdsCap = 1024;                    // list entries per pass
+constexpr int kLdsTroubled = kLdsCap / 6;        // troubled cells whose claims always fit
+constexpr int kLdsHash = 2048;                   // hash set slots (load <= 1/2)
+
+template <typename real>
+struct LdsTailShared {
+    real wl[kGtabSize];
+    FaceXchg<real> xch[kTailThreads / 64];
+    int fl[2][kLdsCap];        // face list of the pass of each parity
+    int cl[2][kLdsCap];        // cell list
+    int fkey[2][kLdsHash];     // face id -> list index of the pass of each parity
+    int fval[2][kLdsHash];
+    int ckey[2][kLdsHash];     // cells claimed for the pass of each parity
+    real flux[kLdsCap][4];     // fluxes of this pass's faces, by list index
+    int fflag[kLdsCap];
+    int tl[kLdsCap];           // troubled cells of this pass's evaluation
+    int cnt[2][3];             // [parity][faces, cells, troubled cells of the previous evaluation]
+    int nlow;                  // troubled cells listed in tl
+    int kfirst;
+};
+
+__device__ __forceinline__ int lds_hash(int key) { return (int)(((unsigned)key * 2654435761u) >> 21); }
+
+// Insert key into an LDS hash set; returns its slot if this call inserted it, -1
+// if it was already there.
+__device__ __forceinline__ int lds_insert(int *keys, int key)
+{
+    int h = lds_hash(key);
+    for (;;) {
+        const int old = atomicCAS(&keys[h], -1, key);
+        if (old == -1) return h;
+        if (old == key) return -1;
+        h = (h + 1) & (kLdsHash - 1);
+    }
+}
+
+__device__ __forceinline__ int lds_find(const int *keys, int key)
+{
+    int h = lds_hash(key);
+    for (;;) {
+        const int k = keys[h];
+        if (k == key) return h;
+        if (k == -1) return -1;
+        h = (h + 1) & (kLdsHash - 1);
+    }
+}
+
+// Block barrier that orders LDS only: global stores issued before it may still be
+// in flight.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// A cell of the current pass: its inputs and the stored fluxes of its faces, then
+// the fluxes of those recomputed in this pass taken from LDS.
+template <bool WALLS, typename real>
+__device__ __forceinline__ void lds_cell_load(const StageArgs<real> &A, int c, CellIn<real> &X, CellFlux<real> &F)
+{
+    cell_load<WALLS>(A, c, X);
+    cell_fetch(A, X, F);
+}
+
+template <typename real>
+__device__ __forceinline__ void lds_cell_patch(const LdsTailShared<real> &S, int par, CellFlux<real> &F)
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int h = lds_find(S.fkey[par], F.fid[q]);
+        if (h >= 0) {
+            const int idx = S.fval[par][h];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) F.f[q][w] = S.flux[idx][w];
+            F.fl[q] = S.fflag[idx];
+        }
+    }
+}
+
+// Claims of lowered cell (i, j) for the pass of parity par, into the LDS lists.
+template <typename real>
+__device__ __forceinline__ void lds_claim(const StageArgs<real> &A, LdsTailShared<real> &S, int par, int i, int j)
+{
+    int fid[6], cid[5];
+    bool fok[6], cok[5];
+    claim_ids(A, i, j, fid, fok, cid, cok);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        if (!fok[k]) continue;
+        const int h = lds_insert(S.fkey[par], fid[k]);
+        if (h >= 0) {
+            const int idx = atomicAdd(&S.cnt[par][0], 1);
+            S.fl[par][idx] = fid[k];
+            S.fval[par][h] = idx;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        if (!cok[k]) continue;
+        if (lds_insert(S.ckey[par], cid[k]) >= 0) S.cl[par][atomicAdd(&S.cnt[par][1], 1)] = cid[k];
+    }
+}
+
+template <bool WALLS, bool HLL, typename real>
+__device__ __forceinline__ void lds_tail_body(const StageArgs<real> &A, const Cascade &C, int kbeg, int kdef,
+                                              int kend, LdsTailShared<real> &S)
+{
+    const int capf = (A.nx + 1) * A.ny + A.nx * (A.ny + 1), capc = A.nx * A.ny;
+    Ctl *ctl = C.ctl;
+    const unsigned stamp0 = ctl->stamp0;
+    const int tid = threadIdx.x, NT = blockDim.x;
+    load_gtab<kTailThreads>(A.gtab, S.wl);
+    for (int t = tid; t < 2 * kLdsHash; t += NT) {
+        (&S.fkey[0][0])[t] = -1;
+        (&S.ckey[0][0])[t] = -1;
+    }
+    int k0 = ctl->tail_k0 > 0 ? ctl->tail_k0 : kdef;
+    if (ctl->tail_k0 <= 0 && kbeg < kdef) {
+        // no hand-over: the cascade either ended inside the batch kbeg..kdef-1 (at
+        // the first pass with no cell) or continues at kdef
+        if (tid == 0) S.kfirst = kdef;
+        __syncthreads();
+        for (int kk = kbeg + tid; kk < kdef; kk += NT)
+            if (ctl->ncell[kk] <= 0) atomicMin(&S.kfirst, kk);
+        __syncthreads();
+        k0 = S.kfirst;
+    }
+    if (tid == 0) {
+        S.cnt[k0 & 1][0] = ctl->nface[k0];
+        S.cnt[k0 & 1][1] = ctl->ncell[k0];
+        S.cnt[k0 & 1][2] = ctl->ntroub[k0 - 1];
+    }
+    __syncthreads();
+    // the first pass's lists come from global memory (the kernels before the tail)
+    bool from_global = true;
+    int k = k0;
+    bool back = false;
+    const real dt = (real)(*A.dt * A.dtf);
+    for (; k < kend; ++k) {
+        const int par = k & 1, nxt = (k + 1) & 1;
+        __syncthreads();  // the previous pass's LDS and global writes are complete
+        int nf = __builtin_amdgcn_readfirstlane(S.cnt[par][0]);
+        int nc = __builtin_amdgcn_readfirstlane(S.cnt[par][1]);
+        const int nt = __builtin_amdgcn_readfirstlane(S.cnt[par][2]);
+        if (tid == 0 && k > k0) {
+            ctl->nface[k] = nf;
+            ctl->ncell[k] = nc;
+            ctl->ntroub[k - 1] = nt;
+        }
+        nc = nc < capc ? nc : capc;
+        nf = nf < capf ? nf : capf;
+        if (nc <= 0) break;  // same values in every thread: the block leaves together
+        if (nt > C.back_thr || (from_global && (nf > kLdsCap || nc > kLdsCap))) {
+            back = true;
+            if (!from_global) {  // hand the LDS lists to the multi-block passes
+                for (int t = tid; t < nf; t += NT) C.flist[par][t] = S.fl[par][t];
+                for (int t = tid; t < nc; t += NT) C.clist[par][t] = S.cl[par][t];
+            }
+            break;
+        }
+        if (from_global) {
+            // this pass's lists from global memory into LDS, and its face index
+            for (int t = tid; t < nf; t += NT) {
+                const int f = C.flist[par][t];
+                S.fl[par][t] = f;
+                const int h = lds_insert(S.fkey[par], f);  // the list holds each face once
+                if (h >= 0) S.fval[par][h] = t;
+            }
+            for (int t = tid; t < nc; t += NT) S.cl[par][t] = C.clist[par][t];
+            lds_barrier();
+        }
+        // the sets of the next pass start empty (last used two passes ago)
+        for (int t = tid; t < kLdsHash; t += NT) {
+            S.fkey[nxt][t] = -1;
+            S.ckey[nxt][t] = -1;
+        }
+        if (tid == 0) {
+            S.cnt[nxt][0] = S.cnt[nxt][1] = S.cnt[nxt][2] = 0;
+            S.nlow = 0;
+        }
+        const int fw = (4 * nf + 63) >> 6, cw = (nc + 63) >> 6;  // wavefronts of faces, of cells
+        const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wavefront
+        if (fw + cw <= kTailThreads / 64) {
+            // one round each, on separate wavefronts: the cell wavefronts gather
+            // their inputs and stored fluxes while the face wavefronts recompute
+            // (each wavefront takes one branch, uniformly, and meets the barrier once
+            // in it: a cell's inputs are not live across the face code)
+            const int c0 = kTailThreads / 64 - cw;  // first cell wavefront
+            if (wv >= c0) {
+                const int idx = tid - 64 * c0;
+                const bool valid = idx < nc;
+                CellIn<real> X;
+                CellFlux<real> F;
+                if (valid) lds_cell_load<WALLS>(A, S.cl[par][idx], X, F);
+                lds_barrier();
+                if (valid) {
+                    lds_cell_patch(S, par, F);
+                    if (cell_finish_flux(A, X, F, dt)) S.tl[atomicAdd(&S.nlow, 1)] = X.c;
+                }
+            } else {
+                if (wv < fw)
+                    faces_phase<WALLS, HLL>(A, S.wl, S.xch[wv], S.fl[par], nf, tid, 64 * fw, 0, false, S.flux,
+                                            S.fflag);
+                lds_barrier();
+            }
+        } else {
+            faces_phase<WALLS, HLL>(A, S.wl, S.xch[wv], S.fl[par], nf, tid, NT, 0, false, S.flux, S.fflag);
+            lds_barrier();
+            for (int t = tid; t < nc; t += NT) {
+                CellIn<real> X;
+                CellFlux<real> F;
+                lds_cell_load<WALLS>(A, S.cl[par][t], X, F);
+                lds_cell_patch(S, par, F);
+                if (cell_finish_flux(A, X, F, dt)) S.tl[atomicAdd(&S.nlow, 1)] = X.c;
+            }
+        }
+        lds_barrier();  // the evaluation's troubled cells are listed
+        const int ntr = __builtin_amdgcn_readfirstlane(S.nlow);
+        if (tid == 0) S.cnt[nxt][2] = ntr;
+        if (ntr <= kLdsTroubled) {
+            for (int t = tid; t < ntr; t += NT) {
+                const int c = S.tl[t];
+                const int j = c / A.nx;
+                lds_claim(A, S, nxt, c - j * A.nx, j);
+            }
+            from_global = false;
+        } else {
+            // too many claims for the LDS lists: claim into the global lists with the
+            // pass's stamp (the next pass then hands back)
+            PassOut P = pass_out(C, k, stamp0);
+            P.fcount = &S.cnt[nxt][0];
+            P.ccount = &S.cnt[nxt][1];
+            P.tcount = &S.cnt[nxt][2];
+            const int nround = (ntr + NT - 1) / NT;
+            for (int r = 0; r < nround; ++r) {
+                const int t = r * NT + tid;
+                const bool act = t < ntr;
+                int i = 0, j = 0;
+                if (act) {
+                    const int c = S.tl[t];
+                    j = c / A.nx;
+                    i = c - j * A.nx;
+                }
+                claim_after_lowering(A, P, i, j, act);
+            }
+            from_global = true;
+        }
+    }
+    if (k >= kend) {
+        __syncthreads();
+        if (tid == 0) {
+            ctl->nface[k] = S.cnt[k & 1][0];
+            ctl->ncell[k] = S.cnt[k & 1][1];
+            ctl->ntroub[k - 1] = S.cnt[k & 1][2];
+        }
+        if (!from_global) {  // the next pass's lists, for the host's continuation
+            const int nf = S.cnt[k & 1][0], nc = S.cnt[k & 1][1];
+            for (int t = tid; t < nf; t += NT) C.flist[k & 1][t] = S.fl[k & 1][t];
+            for (int t = tid; t < nc; t += NT) C.clist[k & 1][t] = S.cl[k & 1][t];
+        }
+    }
+    if (tid == 0) {
+        ctl->tail_end = k;
+        ctl->tail_back = back ? 1 : 0;
+        ctl->tail_start = k0;
+        if (back) ctl->tail_k0 = 0;  // the next multi-block batch starts afresh
+    }
+}
+
+template <typename real, bool WALLS, bool HLL>
+__global__ __launch_bounds__(kTailThreads) void k_tail_lds(const StageArgs<real> A, const Cascade C, int kbeg,
+                                                           int kdef, int kend)
+{
+    __shared__ LdsTailShared<real> S;
+    lds_tail_body<WALLS, HLL>(A, C, kbeg, kdef, kend, S);
 }
 
 // -------------------------------------------------------- small kernels
@@ -1279,7 +1609,7 @@ __global__ void k_batch_status(const Cascade *casc, int nprob, int *iters, doubl
 // BW: the first-pass build with the boundary handling (some problem has walls).
 template <typename real, bool BW>
 static hipError_t launch_batch_stage_bw(const BatchTabs<real> &B, int top, int nfp_blocks, const Cascade *casc,
-                                        hipStream_t st)
+                                        hipStream_t st, bool tail = true)
 {
     constexpr int WPB = sizeof(real) == 8 ? 2 : 4;
     const int nb = (B.nprob + 255) / 256;
@@ -1295,6 +1625,7 @@ static hipError_t launch_batch_stage_bw(const BatchTabs<real> &B, int top, int n
         case 2: hipLaunchKernelGGL((k_first_pass_batch<real, 1, WPB, false, true, BW>), g, t, 0, st, B); break;
         default: return hipErrorInvalidValue;
         }
+        if (!tail) return hipGetLastError();
         if (B.walls)
             hipLaunchKernelGGL((k_tail_batch<real, true, true>), dim3(B.nprob), dim3(kTailThreads), 0, st, B);
         else
@@ -1310,6 +1641,7 @@ static hipError_t launch_batch_stage_bw(const BatchTabs<real> &B, int top, int n
     case 2: hipLaunchKernelGGL((k_first_pass_batch<real, 1, WPB, false, false, BW>), g, t, 0, st, B); break;
     default: return hipErrorInvalidValue;
     }
+    if (!tail) return hipGetLastError();
     if (B.walls)
         hipLaunchKernelGGL((k_tail_batch<real, true, false>), dim3(B.nprob), dim3(kTailThreads), 0, st, B);
     else
@@ -1323,6 +1655,15 @@ hipError_t launch_batch_stage(const BatchTabs<real> &B, int top, int nfp_blocks,
 {
     return B.walls ? launch_batch_stage_bw<real, true>(B, top, nfp_blocks, casc, st)
                    : launch_batch_stage_bw<real, false>(B, top, nfp_blocks, casc, st);
+}
+
+// The reset and the first pass of a batch stage without its cascade (timing).
+template <typename real>
+hipError_t launch_batch_first_pass(const BatchTabs<real> &B, int top, int nfp_blocks, const Cascade *casc,
+                                   hipStream_t st)
+{
+    return B.walls ? launch_batch_stage_bw<real, true>(B, top, nfp_blocks, casc, st, false)
+                   : launch_batch_stage_bw<real, false>(B, top, nfp_blocks, casc, st, false);
 }
 
 template <typename real>
@@ -1426,6 +1767,17 @@ hipError_t launch_cascade_tail(const StageArgs<real> &A, const Cascade &C, int k
                                hipStream_t st)
 {
     const bool walls = A.bcx == 2 || A.bcy == 2 || A.slit != 0;
+    if (C.lds_tail && C.back_thr <= kLdsTroubled) {  // every pass the tail runs fits the LDS lists
+        if (walls && A.solver == 1)
+            hipLaunchKernelGGL((k_tail_lds<real, true, true>), dim3(1), dim3(kTailThreads), 0, st, A, C, kbeg, kdef, kend);
+        else if (walls)
+            hipLaunchKernelGGL((k_tail_lds<real, true, false>), dim3(1), dim3(kTailThreads), 0, st, A, C, kbeg, kdef, kend);
+        else if (A.solver == 1)
+            hipLaunchKernelGGL((k_tail_lds<real, false, true>), dim3(1), dim3(kTailThreads), 0, st, A, C, kbeg, kdef, kend);
+        else
+            hipLaunchKernelGGL((k_tail_lds<real, false, false>), dim3(1), dim3(kTailThreads), 0, st, A, C, kbeg, kdef, kend);
+        return hipGetLastError();
+    }
     if (walls && A.solver == 1)
         hipLaunchKernelGGL((k_tail<real, true, true>), dim3(1), dim3(kTailThreads), 0, st, A, C, kbeg, kdef, kend);
     else if (walls)
@@ -1516,6 +1868,8 @@ template hipError_t launch_totals<float>(const float *, size_t, double, double *
 template hipError_t launch_totals<double>(const double *, size_t, double, double *, int, double *, hipStream_t);
 
 template hipError_t launch_batch_stage<float>(const BatchTabs<float> &, int, int, const Cascade *, hipStream_t);
+template hipError_t launch_batch_first_pass<float>(const BatchTabs<float> &, int, int, const Cascade *, hipStream_t);
+template hipError_t launch_batch_first_pass<double>(const BatchTabs<double> &, int, int, const Cascade *, hipStream_t);
 template hipError_t launch_batch_stage<double>(const BatchTabs<double> &, int, int, const Cascade *, hipStream_t);
 template hipError_t launch_batch_dt<float>(const BatchTabs<float> &, int, const Cascade *, double, hipStream_t);
 template hipError_t launch_batch_dt<double>(const BatchTabs<double> &, int, const Cascade *, double, hipStream_t);

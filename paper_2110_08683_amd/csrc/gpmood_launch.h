@@ -32,6 +32,9 @@ hipError_t launch_totals(const real *U, size_t ncell, double area, double *parti
 template <typename real>
 hipError_t launch_batch_stage(const BatchTabs<real> &B, int top, int nfp_blocks, const Cascade *casc, hipStream_t st);
 template <typename real>
+hipError_t launch_batch_first_pass(const BatchTabs<real> &B, int top, int nfp_blocks, const Cascade *casc,
+                                   hipStream_t st);
+template <typename real>
 hipError_t launch_batch_dt(const BatchTabs<real> &B, int ndt_blocks, const Cascade *casc, double cfl, hipStream_t st);
 hipError_t launch_batch_status(const Cascade *casc, int nprob, int *iters, double *dts, hipStream_t st);
 hipError_t launch_batch_stamp_restart(const Cascade *casc, int nprob, hipStream_t st);

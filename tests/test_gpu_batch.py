@@ -12,6 +12,7 @@ import pytest
 
 import gpmood_inputs as gi
 import oracle
+from tests.parity_util import assert_fields_close
 
 pytestmark = pytest.mark.gpu
 
@@ -58,6 +59,7 @@ def test_batch_matches_oracle_fp64(torch_cuda, bc, cascade, use_graph):
         Uo, dto, co, io = o.run(U0s[k], cfl=0.8, nsteps=nsteps)
         U = b.gpm_batch_get_state(k)
         err = _rel_l1(U, Uo)
+        assert_fields_close(U, Uo, what=f"problem {k}")
         counts, it = b.gpm_batch_troubled_counts(k)
         _note(f"  problem {k} {nx}x{ny}: rel L1 {err:.2e} dt {dts[k]:.6e}/{dto[-1]:.6e} "
               f"counts {counts[:len(cascade)]}/{co[-1, 2]} iters {it}/{io[-1, 2]}")
@@ -121,6 +123,40 @@ def test_batch_u2_weights_are_per_problem(torch_cuda):
     for k, (nx, ny) in enumerate(sizes):
         Uo = oracle.Oracle(nx, ny, bc=(1, 2), cascade=(1, 0)).run(U0s[k], cfl=0.8, nsteps=2)[0]
         err = _rel_l1(b.gpm_batch_get_state(k), Uo)
+        assert_fields_close(b.gpm_batch_get_state(k), Uo, what=f"problem {k}")
         _note(f"  problem {k} {nx}x{ny}: rel L1 {err:.2e}")
         assert err <= 1e-12
+    b.close()
+
+
+def test_autotuned_batch_is_bitwise_equal(torch_cuda, tmp_path):
+    """The library's autotuner picks a first-pass march length per size class; the
+    tuned batch gives the same bits as the default one (FP32, uneven sizes, graph
+    replay), its timing launches leave the states unchanged, and a cached choice is
+    applied without timing."""
+    from paper_2110_08683_amd import GPMoodBatch
+    sizes = [(64, 64), (96, 96), (128, 128), (200, 200), (256, 256), (300, 300)]
+    _note(f"batch autotune f32 sizes={sizes}")
+    U0s = [gi.quadrants(nx, ny, seed=60 + k) for k, (nx, ny) in enumerate(sizes)]
+    states = []
+    for tuned in (False, True):
+        b = GPMoodBatch(sizes, bc=(1, 1), prec="f32", cascade=(3, 2, 1, 0), device="cuda:0")
+        for k, U0 in enumerate(U0s):
+            b.gpm_batch_init_state(k, U0)
+        if tuned:
+            rows, gain = b.autotune(0.8, reps=2, cache=str(tmp_path / "tune.json"))
+            _note(f"  chosen rows per problem {rows}, first-pass gain over the default {gain:.3f}")
+            assert all(4 <= r <= 64 for r in rows) and gain > 0
+            # the timing launches did not touch the states
+            for k, U0 in enumerate(U0s):
+                assert np.array_equal(b.gpm_batch_get_state(k), U0.astype(np.float32).astype(np.float64))
+        b.gpm_batch_step(0.8, 3, use_graph=True)
+        states.append([b.gpm_batch_get_state(k) for k in range(len(sizes))])
+        b.close()
+    for k in range(len(sizes)):
+        assert np.array_equal(states[0][k], states[1][k]), k
+    # a second batch takes the cached choice
+    b = GPMoodBatch(sizes, bc=(1, 1), prec="f32", cascade=(3, 2, 1, 0), device="cuda:0")
+    rows2, gain2 = b.autotune(0.8, reps=2, cache=str(tmp_path / "tune.json"))
+    assert gain2 is None and rows2 == rows
     b.close()

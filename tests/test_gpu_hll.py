@@ -11,6 +11,7 @@ import pytest
 
 import gpmood_inputs as gi
 import oracle
+from tests.parity_util import assert_fields_close
 
 pytestmark = pytest.mark.gpu
 
@@ -65,6 +66,7 @@ def test_hll_stage_replay_fp64(torch_cuda, nx, ny, seed, bc, cascade):
         assert iters == oiters
         err = _rel_l1(Ug, Uo)
         assert np.all(err <= 1e-12), (s, err)
+        assert_fields_close(Ug, Uo, what=f"stage {s}")
         exercised += int(ocounts[1:].sum())
     assert exercised > 0
     # and the HLLC scheme gives another answer on the same stage
@@ -89,6 +91,7 @@ def test_hll_batch_matches_oracle_fp64(torch_cuda):
     for k, (nx, ny) in enumerate(sizes):
         Uo = oracle.Oracle(nx, ny, bc=(1, 1), solver="hll").run(U0s[k], cfl=0.8, nsteps=2)[0]
         err = _rel_l1(b.gpm_batch_get_state(k), Uo).max()
+        assert_fields_close(b.gpm_batch_get_state(k), Uo, what=f"problem {k}")
         _note(f"  problem {k} {nx}x{ny}: rel L1 {err:.2e}")
         assert err <= 1e-12
     b.close()

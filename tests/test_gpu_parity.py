@@ -12,6 +12,7 @@ import pytest
 
 import gpmood_inputs as gi
 import oracle
+from tests.parity_util import assert_fields_close
 
 pytestmark = pytest.mark.gpu
 
@@ -63,6 +64,7 @@ def test_vortex_fp64_matches_oracle(torch_cuda):
     Ug = g.gpm_get_state()
     err = _rel_l1(Ug, Uo)
     assert np.all(err <= 1e-12), err
+    assert_fields_close(Ug, Uo, what="vortex")
     mask = g.gpm_get_order_mask()
     assert np.all(mask == 3)
     c, it = g.gpm_troubled_counts()
@@ -121,6 +123,7 @@ def test_quadrants_stage_replay_fp64(torch_cuda, nx, ny, seed, bc, cascade):
         assert iters == oiters
         err = _rel_l1(Ug, Uo)
         assert np.all(err <= 1e-12), (s, err)
+        assert_fields_close(Ug, Uo, what=f"stage {s}")
         exercised += int(ocounts[1:].sum())
     assert exercised > 0
 
@@ -146,6 +149,7 @@ def test_noise_mass_lowering_stage_fp64(torch_cuda):
         assert iters == oiters
         err = _rel_l1(Ug, Uo)
         assert np.all(err <= 1e-12), (s, err)
+        assert_fields_close(Ug, Uo, what=f"noise stage {s}")
 
 
 def test_quadrants_steps_conservation_fp64(torch_cuda):

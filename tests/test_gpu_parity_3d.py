@@ -9,6 +9,7 @@ import pytest
 
 import gpmood_inputs as gi
 import oracle
+from tests.parity_util import assert_fields_close
 
 pytestmark = pytest.mark.gpu
 
@@ -46,6 +47,7 @@ def test_3d_matches_oracle_fp64(torch_cuda, n, bc, case, nsteps, cascade):
     c, it = g.gpm3_troubled_counts()
     _note(f"  rel L1 {err:.2e} counts {c} / {counts} evaluations {it} / {iters[-1, 2]}")
     assert err <= 1e-12
+    assert_fields_close(U, Uo, what=f"3d {case} {n}")
     for v in (1, 2, 3):  # momenta may vanish: absolute scale of rho and E
         assert np.abs(U[v] - Uo[v]).sum() <= 1e-12 * np.abs(Uo[0]).sum()
     assert list(c[:len(cascade)]) == list(counts) and it == iters[-1, 2]

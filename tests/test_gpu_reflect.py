@@ -14,6 +14,7 @@ import pytest
 
 import gpmood_inputs as gi
 import oracle
+from tests.parity_util import assert_fields_close
 
 pytestmark = pytest.mark.gpu
 
@@ -82,6 +83,7 @@ def test_reflect_stage_replay_fp64(torch_cuda, nx, ny, kind, bc, cascade, hi, pr
         assert iters == oiters
         err = _rel_l1(Ug, Uo)
         assert np.all(err <= 1e-12), (s, err)
+        assert_fields_close(Ug, Uo, what=f"stage {s}")
         exercised += int(ocounts[1:].sum())
     assert exercised > 0
 

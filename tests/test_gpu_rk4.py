@@ -22,6 +22,7 @@ import pytest
 
 import gpmood_inputs as gi
 import oracle
+from tests.parity_util import assert_fields_close
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -74,6 +75,7 @@ def test_stencil_variants_stage_replay_fp64(torch_cuda, stencil, cascade):
         assert iters == oiters
         err = _rel_l1(tout.cpu().numpy(), Uo)
         assert np.all(err <= 1e-12), (s, err)
+        assert_fields_close(tout.cpu().numpy(), Uo, what=f"stage {s}")
         lowered += int(ocounts[1:].sum())
     assert lowered > 0
     g.close()
@@ -102,6 +104,7 @@ def test_rk4_steps_match_oracle_fp64(torch_cuda, case):
         Uo, iters = o.rk4_step(Uo, dt)
         lowered += sum(i - 1 for i in iters)
     err = _rel_l1(U.cpu().numpy(), Uo)
+    assert_fields_close(U.cpu().numpy(), Uo, what="rk4 steps")
     _note(f"  rel L1 {err}  cascade passes {lowered}")
     assert np.all(err <= 1e-12), err
     if case == "quadrants":
