@@ -236,12 +236,6 @@ gpm_status gpm_totals_static(gpm_ctx *ctx, const void *U, double totals[4]);
    rows per wavefront march in the first pass.  Defaults 4, 12 and 32. */
 gpm_status gpm_set_tuning(gpm_ctx *ctx, int passes_per_check, int rows_per_wave, int tail_threshold);
 
-/* Which single-workgroup tail finishes a cascade (the schedule only: both give
-   the same bits): lds = 1 keeps each pass's lists, claims and recomputed fluxes in
-   LDS (used while tail_threshold <= 42, so that every pass it runs fits its LDS
-   lists), lds = 0 passes them through global memory.  Errors: GPM_EINVAL. */
-gpm_status gpm_set_cascade_tail(gpm_ctx *ctx, int lds);
-
 /* Instrumentation for measurement (not part of the method).  mode bit 0: every
    first-pass launch and every stage's cascade are bracketed by HIP events on the
    context stream and MOOD iterations are counted on the host (no extra kernels);

@@ -27,7 +27,7 @@ EXPORTS = ("gpm_create", "gpm_set_scheme", "gpm_workspace_size", "gpm_bind", "gp
            "gpm_stage_coef", "gpm_lincomb4",
            "gpm_step", "gpm_troubled_counts", "gpm_get_order_mask", "gpm_totals", "gpm_totals_dev",
            "gpm_totals_static",
-           "gpm_set_tuning", "gpm_set_cascade_tail", "gpm_instrument", "gpm_instrument_read", "gpm_cascade_stats", "gpm_order_ptr", "gpm_adjoint_workspace_size",
+           "gpm_set_tuning", "gpm_instrument", "gpm_instrument_read", "gpm_cascade_stats", "gpm_order_ptr", "gpm_adjoint_workspace_size",
            "gpm_bind_adjoint", "gpm_stage_vjp",
            "gpm_batch_create",
            "gpm_batch_set_scheme", "gpm_batch_workspace_size", "gpm_batch_bind", "gpm_batch_set_tuning",
@@ -97,7 +97,6 @@ def lib():
         "gpm_totals_dev": ([ctxp, vp, dp], st),
         "gpm_totals_static": ([ctxp, vp, dp], st),
         "gpm_set_tuning": ([ctxp, ctypes.c_int, ctypes.c_int, ctypes.c_int], st),
-        "gpm_set_cascade_tail": ([ctxp, ctypes.c_int], st),
         "gpm_instrument": ([ctxp, ctypes.c_int], st),
         "gpm_instrument_read": ([ctxp, dp, ctypes.POINTER(ctypes.c_longlong), dp, ctypes.POINTER(ctypes.c_longlong),
                                  ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)], st),
@@ -365,9 +364,6 @@ class GPMood:
 
     def gpm_set_tuning(self, passes_per_check=4, rows_per_wave=12, tail_threshold=32):
         self._check(lib().gpm_set_tuning(self.ctx, int(passes_per_check), int(rows_per_wave), int(tail_threshold)))
-
-    def gpm_set_cascade_tail(self, lds=True):
-        self._check(lib().gpm_set_cascade_tail(self.ctx, 1 if lds else 0))
 
     def gpm_instrument(self, mode=1):
         """mode 0: off, 1: events and iteration counts, 3: also final-order counts (True means 1)."""

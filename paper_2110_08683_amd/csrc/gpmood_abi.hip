@@ -385,7 +385,6 @@ static gpm_status run_stage(gpm_ctx *c, const Weights<real> &W, int s, const voi
     C.ctl = c->ctl;
     C.tail_thr = c->tail_threshold;
     C.back_thr = 4 * c->tail_threshold;
-    C.lds_tail = c->lds_tail;
     PassOut P;
     P.flist = c->flist[1];
     P.clist = c->clist[1];
@@ -532,13 +531,6 @@ gpm_status gpm_step(gpm_ctx *c, double cfl, int nsteps)
         if (st != GPM_OK) return st;
         c->cur = a;
     }
-    return GPM_OK;
-}
-
-gpm_status gpm_set_cascade_tail(gpm_ctx *c, int lds)
-{
-    if (!c || (lds != 0 && lds != 1)) return GPM_EINVAL;
-    c->lds_tail = lds;
     return GPM_OK;
 }
 

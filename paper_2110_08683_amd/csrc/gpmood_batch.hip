@@ -171,7 +171,6 @@ static gpm_status build_tables(gpm_batch *b)
         C.ctl = c->ctl;
         C.tail_thr = 0;
         C.back_thr = 0x7fffffff;  // one workgroup per problem runs the whole cascade
-        C.lds_tail = 0;
         blk[p + 1] = blk[p] + fp_blocks(c, c->rows);
         dblk[p + 1] = dblk[p] + dt_blocks(c);
     }

@@ -61,7 +61,6 @@ struct gpm_ctx {
     int passes_per_check = 4;  // smallest batch of multi-block cascade passes
     int head_guess = 4;        // batch length: the previous stage's multi-block passes + 2
     int tail_threshold = 32;   // troubled cells at or below which one workgroup finishes the cascade
-    int lds_tail = 0;          // 1: that workgroup keeps its pass-to-pass traffic in LDS
     int rows = 12;
     int si0 = 0, si1 = 0;  // inflow slit cells [si0, si1)
     double slit_u[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};  // bottom, top

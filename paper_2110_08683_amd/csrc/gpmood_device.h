@@ -123,7 +123,6 @@ struct Cascade {
     int *clist[2];
     Ctl *ctl;
     int tail_thr, back_thr;
-    int lds_tail;  // 1: the single-workgroup tail keeps its lists, claims and fluxes in LDS
 };
 
 // ------------------------------------------------------------------ helpers

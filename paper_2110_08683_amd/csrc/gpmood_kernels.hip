@@ -432,8 +432,7 @@ __device__ __forceinline__ void load_gtab(const real *gtab, real *wl)
 template <bool WALLS, bool HLL, typename real>
 __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real *wl, FaceXchg<real> &X,
                                             const int *flist, int n, int t0, int stride, int pre = 0,
-                                            bool use_pre = false, real (*lflux)[4] = nullptr,
-                                            int *lflag = nullptr)
+                                            bool use_pre = false)
 {
     const int nx = A.nx, ny = A.ny;
     const int nfx = (nx + 1) * ny, nfy = nx * (ny + 1);
@@ -655,10 +654,6 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
             } else {
                 A.GY[(size_t)v * nfy + fo] = F;
                 if (v == 0) A.GYf[fo] = (uint8_t)fl;
-            }
-            if (lflux) {  // the LDS copy at the face's list index (the LDS cascade)
-                lflux[idx][v] = F;
-                if (v == 0) lflag[idx] = fl;
             }
         }
         wave_lds_sync();  // the next round overwrites X
@@ -997,295 +992,6 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const StageArgs<real> A, 
 {
     __shared__ TailShared<real> S;
     tail_body<WALLS, HLL>(A, C, kbeg, kdef, kend, S);
-}
-
-// ------------------------------------------------------ the LDS cascade tail
-// The tail of a long cascade with its pass-to-pass traffic kept in LDS: the face
-// and cell lists of the next pass, the claims that build them (hash sets instead
-// of stamps in global memory), and the fluxes of the faces a pass recomputes,
-// which the pass's cells read from LDS.  Within a pass only LDS is waited for;
-// the global stores (fluxes, stage outputs, lowered orders) complete by the
-// barrier that ends the pass, before the next pass reads them.  The arithmetic is
-// that of the faces and cells kernels, so the results are the same bits; only
-// the order of list entries differs.  Used while every pass's claims fit its
-// lists: the previous evaluation left at most kLdsTroubled troubled cells
-// (the tail hands back above back_thr <= kLdsTroubled).
-constexpr int kLdsCap = 1024;                    // list entries per pass
-constexpr int kLdsTroubled = kLdsCap / 6;        // troubled cells whose claims always fit
-constexpr int kLdsHash = 2048;                   // hash set slots (load <= 1/2)
-
-template <typename real>
-struct LdsTailShared {
-    real wl[kGtabSize];
-    FaceXchg<real> xch[kTailThreads / 64];
-    int fl[2][kLdsCap];        // face list of the pass of each parity
-    int cl[2][kLdsCap];        // cell list
-    int fkey[2][kLdsHash];     // face id -> list index of the pass of each parity
-    int fval[2][kLdsHash];
-    int ckey[2][kLdsHash];     // cells claimed for the pass of each parity
-    real flux[kLdsCap][4];     // fluxes of this pass's faces, by list index
-    int fflag[kLdsCap];
-    int tl[kLdsCap];           // troubled cells of this pass's evaluation
-    int cnt[2][3];             // [parity][faces, cells, troubled cells of the previous evaluation]
-    int nlow;                  // troubled cells listed in tl
-    int kfirst;
-};
-
-__device__ __forceinline__ int lds_hash(int key) { return (int)(((unsigned)key * 2654435761u) >> 21); }
-
-// Insert key into an LDS hash set; returns its slot if this call inserted it, -1
-// if it was already there.
-__device__ __forceinline__ int lds_insert(int *keys, int key)
-{
-    int h = lds_hash(key);
-    for (;;) {
-        const int old = atomicCAS(&keys[h], -1, key);
-        if (old == -1) return h;
-        if (old == key) return -1;
-        h = (h + 1) & (kLdsHash - 1);
-    }
-}
-
-__device__ __forceinline__ int lds_find(const int *keys, int key)
-{
-    int h = lds_hash(key);
-    for (;;) {
-        const int k = keys[h];
-        if (k == key) return h;
-        if (k == -1) return -1;
-        h = (h + 1) & (kLdsHash - 1);
-    }
-}
-
-// Block barrier that orders LDS only: global stores issued before it may still be
-// in flight.
-__device__ __forceinline__ void lds_barrier()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-// A cell of the current pass: its inputs and the stored fluxes of its faces, then
-// the fluxes of those recomputed in this pass taken from LDS.
-template <bool WALLS, typename real>
-__device__ __forceinline__ void lds_cell_load(const StageArgs<real> &A, int c, CellIn<real> &X, CellFlux<real> &F)
-{
-    cell_load<WALLS>(A, c, X);
-    cell_fetch(A, X, F);
-}
-
-template <typename real>
-__device__ __forceinline__ void lds_cell_patch(const LdsTailShared<real> &S, int par, CellFlux<real> &F)
-{
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int h = lds_find(S.fkey[par], F.fid[q]);
-        if (h >= 0) {
-            const int idx = S.fval[par][h];
-#pragma unroll
-            for (int w = 0; w < 4; ++w) F.f[q][w] = S.flux[idx][w];
-            F.fl[q] = S.fflag[idx];
-        }
-    }
-}
-
-// Claims of lowered cell (i, j) for the pass of parity par, into the LDS lists.
-template <typename real>
-__device__ __forceinline__ void lds_claim(const StageArgs<real> &A, LdsTailShared<real> &S, int par, int i, int j)
-{
-    int fid[6], cid[5];
-    bool fok[6], cok[5];
-    claim_ids(A, i, j, fid, fok, cid, cok);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        if (!fok[k]) continue;
-        const int h = lds_insert(S.fkey[par], fid[k]);
-        if (h >= 0) {
-            const int idx = atomicAdd(&S.cnt[par][0], 1);
-            S.fl[par][idx] = fid[k];
-            S.fval[par][h] = idx;
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        if (!cok[k]) continue;
-        if (lds_insert(S.ckey[par], cid[k]) >= 0) S.cl[par][atomicAdd(&S.cnt[par][1], 1)] = cid[k];
-    }
-}
-
-template <bool WALLS, bool HLL, typename real>
-__device__ __forceinline__ void lds_tail_body(const StageArgs<real> &A, const Cascade &C, int kbeg, int kdef,
-                                              int kend, LdsTailShared<real> &S)
-{
-    const int capf = (A.nx + 1) * A.ny + A.nx * (A.ny + 1), capc = A.nx * A.ny;
-    Ctl *ctl = C.ctl;
-    const unsigned stamp0 = ctl->stamp0;
-    const int tid = threadIdx.x, NT = blockDim.x;
-    load_gtab<kTailThreads>(A.gtab, S.wl);
-    for (int t = tid; t < 2 * kLdsHash; t += NT) {
-        (&S.fkey[0][0])[t] = -1;
-        (&S.ckey[0][0])[t] = -1;
-    }
-    int k0 = ctl->tail_k0 > 0 ? ctl->tail_k0 : kdef;
-    if (ctl->tail_k0 <= 0 && kbeg < kdef) {
-        // no hand-over: the cascade either ended inside the batch kbeg..kdef-1 (at
-        // the first pass with no cell) or continues at kdef
-        if (tid == 0) S.kfirst = kdef;
-        __syncthreads();
-        for (int kk = kbeg + tid; kk < kdef; kk += NT)
-            if (ctl->ncell[kk] <= 0) atomicMin(&S.kfirst, kk);
-        __syncthreads();
-        k0 = S.kfirst;
-    }
-    if (tid == 0) {
-        S.cnt[k0 & 1][0] = ctl->nface[k0];
-        S.cnt[k0 & 1][1] = ctl->ncell[k0];
-        S.cnt[k0 & 1][2] = ctl->ntroub[k0 - 1];
-    }
-    __syncthreads();
-    // the first pass's lists come from global memory (the kernels before the tail)
-    bool from_global = true;
-    int k = k0;
-    bool back = false;
-    const real dt = (real)(*A.dt * A.dtf);
-    for (; k < kend; ++k) {
-        const int par = k & 1, nxt = (k + 1) & 1;
-        __syncthreads();  // the previous pass's LDS and global writes are complete
-        int nf = __builtin_amdgcn_readfirstlane(S.cnt[par][0]);
-        int nc = __builtin_amdgcn_readfirstlane(S.cnt[par][1]);
-        const int nt = __builtin_amdgcn_readfirstlane(S.cnt[par][2]);
-        if (tid == 0 && k > k0) {
-            ctl->nface[k] = nf;
-            ctl->ncell[k] = nc;
-            ctl->ntroub[k - 1] = nt;
-        }
-        nc = nc < capc ? nc : capc;
-        nf = nf < capf ? nf : capf;
-        if (nc <= 0) break;  // same values in every thread: the block leaves together
-        if (nt > C.back_thr || (from_global && (nf > kLdsCap || nc > kLdsCap))) {
-            back = true;
-            if (!from_global) {  // hand the LDS lists to the multi-block passes
-                for (int t = tid; t < nf; t += NT) C.flist[par][t] = S.fl[par][t];
-                for (int t = tid; t < nc; t += NT) C.clist[par][t] = S.cl[par][t];
-            }
-            break;
-        }
-        if (from_global) {
-            // this pass's lists from global memory into LDS, and its face index
-            for (int t = tid; t < nf; t += NT) {
-                const int f = C.flist[par][t];
-                S.fl[par][t] = f;
-                const int h = lds_insert(S.fkey[par], f);  // the list holds each face once
-                if (h >= 0) S.fval[par][h] = t;
-            }
-            for (int t = tid; t < nc; t += NT) S.cl[par][t] = C.clist[par][t];
-            lds_barrier();
-        }
-        // the sets of the next pass start empty (last used two passes ago)
-        for (int t = tid; t < kLdsHash; t += NT) {
-            S.fkey[nxt][t] = -1;
-            S.ckey[nxt][t] = -1;
-        }
-        if (tid == 0) {
-            S.cnt[nxt][0] = S.cnt[nxt][1] = S.cnt[nxt][2] = 0;
-            S.nlow = 0;
-        }
-        const int fw = (4 * nf + 63) >> 6, cw = (nc + 63) >> 6;  // wavefronts of faces, of cells
-        const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wavefront
-        if (fw + cw <= kTailThreads / 64) {
-            // one round each, on separate wavefronts: the cell wavefronts gather
-            // their inputs and stored fluxes while the face wavefronts recompute
-            // (each wavefront takes one branch, uniformly, and meets the barrier once
-            // in it: a cell's inputs are not live across the face code)
-            const int c0 = kTailThreads / 64 - cw;  // first cell wavefront
-            if (wv >= c0) {
-                const int idx = tid - 64 * c0;
-                const bool valid = idx < nc;
-                CellIn<real> X;
-                CellFlux<real> F;
-                if (valid) lds_cell_load<WALLS>(A, S.cl[par][idx], X, F);
-                lds_barrier();
-                if (valid) {
-                    lds_cell_patch(S, par, F);
-                    if (cell_finish_flux(A, X, F, dt)) S.tl[atomicAdd(&S.nlow, 1)] = X.c;
-                }
-            } else {
-                if (wv < fw)
-                    faces_phase<WALLS, HLL>(A, S.wl, S.xch[wv], S.fl[par], nf, tid, 64 * fw, 0, false, S.flux,
-                                            S.fflag);
-                lds_barrier();
-            }
-        } else {
-            faces_phase<WALLS, HLL>(A, S.wl, S.xch[wv], S.fl[par], nf, tid, NT, 0, false, S.flux, S.fflag);
-            lds_barrier();
-            for (int t = tid; t < nc; t += NT) {
-                CellIn<real> X;
-                CellFlux<real> F;
-                lds_cell_load<WALLS>(A, S.cl[par][t], X, F);
-                lds_cell_patch(S, par, F);
-                if (cell_finish_flux(A, X, F, dt)) S.tl[atomicAdd(&S.nlow, 1)] = X.c;
-            }
-        }
-        lds_barrier();  // the evaluation's troubled cells are listed
-        const int ntr = __builtin_amdgcn_readfirstlane(S.nlow);
-        if (tid == 0) S.cnt[nxt][2] = ntr;
-        if (ntr <= kLdsTroubled) {
-            for (int t = tid; t < ntr; t += NT) {
-                const int c = S.tl[t];
-                const int j = c / A.nx;
-                lds_claim(A, S, nxt, c - j * A.nx, j);
-            }
-            from_global = false;
-        } else {
-            // too many claims for the LDS lists: claim into the global lists with the
-            // pass's stamp (the next pass then hands back)
-            PassOut P = pass_out(C, k, stamp0);
-            P.fcount = &S.cnt[nxt][0];
-            P.ccount = &S.cnt[nxt][1];
-            P.tcount = &S.cnt[nxt][2];
-            const int nround = (ntr + NT - 1) / NT;
-            for (int r = 0; r < nround; ++r) {
-                const int t = r * NT + tid;
-                const bool act = t < ntr;
-                int i = 0, j = 0;
-                if (act) {
-                    const int c = S.tl[t];
-                    j = c / A.nx;
-                    i = c - j * A.nx;
-                }
-                claim_after_lowering(A, P, i, j, act);
-            }
-            from_global = true;
-        }
-    }
-    if (k >= kend) {
-        __syncthreads();
-        if (tid == 0) {
-            ctl->nface[k] = S.cnt[k & 1][0];
-            ctl->ncell[k] = S.cnt[k & 1][1];
-            ctl->ntroub[k - 1] = S.cnt[k & 1][2];
-        }
-        if (!from_global) {  // the next pass's lists, for the host's continuation
-            const int nf = S.cnt[k & 1][0], nc = S.cnt[k & 1][1];
-            for (int t = tid; t < nf; t += NT) C.flist[k & 1][t] = S.fl[k & 1][t];
-            for (int t = tid; t < nc; t += NT) C.clist[k & 1][t] = S.cl[k & 1][t];
-        }
-    }
-    if (tid == 0) {
-        ctl->tail_end = k;
-        ctl->tail_back = back ? 1 : 0;
-        ctl->tail_start = k0;
-        if (back) ctl->tail_k0 = 0;  // the next multi-block batch starts afresh
-    }
-}
-
-template <typename real, bool WALLS, bool HLL>
-__global__ __launch_bounds__(kTailThreads) void k_tail_lds(const StageArgs<real> A, const Cascade C, int kbeg,
-                                                           int kdef, int kend)
-{
-    __shared__ LdsTailShared<real> S;
-    lds_tail_body<WALLS, HLL>(A, C, kbeg, kdef, kend, S);
 }
 
 // -------------------------------------------------------- small kernels
@@ -1767,17 +1473,6 @@ hipError_t launch_cascade_tail(const StageArgs<real> &A, const Cascade &C, int k
                                hipStream_t st)
 {
     const bool walls = A.bcx == 2 || A.bcy == 2 || A.slit != 0;
-    if (C.lds_tail && C.back_thr <= kLdsTroubled) {  // every pass the tail runs fits the LDS lists
-        if (walls && A.solver == 1)
-            hipLaunchKernelGGL((k_tail_lds<real, true, true>), dim3(1), dim3(kTailThreads), 0, st, A, C, kbeg, kdef, kend);
-        else if (walls)
-            hipLaunchKernelGGL((k_tail_lds<real, true, false>), dim3(1), dim3(kTailThreads), 0, st, A, C, kbeg, kdef, kend);
-        else if (A.solver == 1)
-            hipLaunchKernelGGL((k_tail_lds<real, false, true>), dim3(1), dim3(kTailThreads), 0, st, A, C, kbeg, kdef, kend);
-        else
-            hipLaunchKernelGGL((k_tail_lds<real, false, false>), dim3(1), dim3(kTailThreads), 0, st, A, C, kbeg, kdef, kend);
-        return hipGetLastError();
-    }
     if (walls && A.solver == 1)
         hipLaunchKernelGGL((k_tail<real, true, true>), dim3(1), dim3(kTailThreads), 0, st, A, C, kbeg, kdef, kend);
     else if (walls)
