@@ -83,7 +83,7 @@ HBM_PEAK = 8.0e12
 # (mean over the launches of 3 steps, so 1/3 stage-0 launches that read no U^n),
 # scaled by the counters' reading of a 512 MiB device copy (FETCH x 2.0, WRITE x
 # 1.0).  Valid for the kernel sources with this hash only; see profiles/.
-TRAFFIC = {"src": "df0dca43864017aa", "f32": 388.5e6, "f64": 726.9e6}
+TRAFFIC = {"src": "a508d3ae1821c4e7", "f32": 388.6e6, "f64": 726.8e6}
 KERNEL_SOURCES = ["gpmood_kernels.hip", "gpmood_device.h", "gpmood_tables.h"]
 
 
@@ -436,12 +436,33 @@ def run_implosion(name, stencil, cascade, csd, prec, n=400, tend=2.5, cfl=0.8):
     wall = time.time() - t0
     U = g.gpm_get_state()
     asym = max(asym, float(np.abs(U[0] - U[0].T).max() / U[0].max()))
-    diag = np.diagonal(U[0])
-    kmax = int(np.argmax(diag))
+    tip, amb = jet_tip(U[0], 0.3 / n)
     return {"variant": name, "prec": prec, "steps": k, "t": t, "wall_s": wall,
             "asymmetry_max": asym, "lowered_fraction_max": frac,
-            "rho_min": float(U[0].min()), "diag_rho_max": float(diag[kmax]),
-            "diag_rho_max_distance": float((kmax + 0.5) * 0.3 / n * np.sqrt(2.0))}
+            "rho_min": float(U[0].min()), "jet_tip_xy": tip, "ambient_rho": amb,
+            "paper_jet_tip_xy": PAPER_TIP.get(name)}
+
+
+# The tip of the jet's mushroom head on the diagonal at t = 2.5 as the paper states
+# it in words (Sec. "The implosion problem in 2D"): x = y ~ 0.22 for GP-MOOD5 and
+# GP-MOOD7, 0.18 for GP-MOOD3, 0.17 for POL-MOOD3, all with CSD.
+PAPER_TIP = {"GP-MOOD7 with CSD": 0.22, "GP-MOOD5 with CSD": 0.22, "GP-MOOD3 with CSD": 0.18,
+             "POL-MOOD3 with CSD": 0.17}
+
+
+def jet_tip(rho, h):
+    """x = y of the outer edge of the jet's mushroom head: the farthest cell on the
+    diagonal, below x = y = 0.19 (the waves crossing the diagonal farther out are
+    common to every variant), whose density is 0.1 below the ambient density (the
+    median on the diagonal over 0.13 < x = y < 0.19, between the jet and those
+    waves); the head is light gas.  Returns (tip, ambient)."""
+    import numpy as np
+    n = rho.shape[0]
+    diag = np.diagonal(rho)
+    s = (np.arange(n) + 0.5) * h
+    amb = float(np.median(diag[(s > 0.13) & (s < 0.19)]))
+    low = np.nonzero((diag < amb - 0.1) & (s < 0.19))[0]
+    return (float(s[low.max()] + 0.5 * h) if low.size else None), amb
 
 
 def implosion_line():
@@ -449,7 +470,7 @@ def implosion_line():
     for name, stencil, cascade, csd in IMPLOSION_VARIANTS:
         r = run_implosion(name, stencil, cascade, csd, "f64")
         print(f"[bench] implosion {name} f64: {r['steps']} steps {r['wall_s']:.1f} s, "
-              f"asymmetry {r['asymmetry_max']:.1e}", file=sys.stderr, flush=True)
+              f"asymmetry {r['asymmetry_max']:.1e}, jet tip x=y {r['jet_tip_xy']}", file=sys.stderr, flush=True)
         out.append(r)
     name, stencil, cascade, csd = IMPLOSION_VARIANTS[-1]
     r = run_implosion(name, stencil, cascade, csd, "f32")
