@@ -10,8 +10,8 @@
 //   1. lambda_F = (alpha lambda_out(R) - alpha lambda_out(L)) dt / Delta, from the
 //      cells whose update uses this copy of the face (alpha = 1, 1/4, 2/3);
 //   2. the node states are rebuilt in the quarter basis (as in the cascade);
-//   3. per Gauss node, J^T (w_g lambda_F) for both states, with J from eight
-//      forward-mode (dual-number) evaluations of the same HLLC code;
+//   3. per Gauss node, J^T (w_g lambda_F) for both states, by reverse mode
+//      through the HLLC flux with the forward's branches;
 //   4. the transposed reconstruction: node adjoints -> accumulator adjoints ->
 //      parity-sum adjoints -> the four mirror cells, added with FP64 atomics into
 //      an accumulator (stencil cells remapped exactly as the forward gathers them);
@@ -24,49 +24,139 @@
 
 namespace gpm {
 
-// ------------------------------------------------------------ dual numbers
+// ------------------------------------------------- reverse-mode HLLC
+// Reverse mode through the x-face HLLC flux: given weights w (the adjoint of the
+// flux), gl = w^T dF/dUL and gr = w^T dF/dUR, with every branch (the wave-speed
+// minimum and maximum, the sign of S*, the side of the fan) taken as the flux
+// takes it.  One pass recomputes the flux's intermediates, a second runs the
+// chain rule backwards through them: about three times the cost of the flux
+// itself, where eight forward-mode (dual-number) passes cost about twenty.
+// Adjoints of the primitive values (density r, normal and tangential velocity
+// u, v, energy E, pressure p, inverse density ir) are held per side (0 = left,
+// 1 = right) and mapped to the conserved variables at the end.
 template <typename real>
-struct Dual {
-    real v, d;
-    __device__ Dual() {}
-    __device__ Dual(real x) : v(x), d(real(0)) {}
-    __device__ Dual(real x, real y) : v(x), d(y) {}
+struct SideAdj {
+    real r, u, v, E, p, ir;
+    __device__ void zero() { r = u = v = E = p = ir = real(0); }
 };
+
+// w . (physical flux of (r, u, v, E, p)), back to the primitives.
 template <typename real>
-__device__ __forceinline__ Dual<real> operator+(Dual<real> a, Dual<real> b) { return Dual<real>(a.v + b.v, a.d + b.d); }
-template <typename real>
-__device__ __forceinline__ Dual<real> operator-(Dual<real> a, Dual<real> b) { return Dual<real>(a.v - b.v, a.d - b.d); }
-template <typename real>
-__device__ __forceinline__ Dual<real> operator-(Dual<real> a) { return Dual<real>(-a.v, -a.d); }
-template <typename real>
-__device__ __forceinline__ Dual<real> operator*(Dual<real> a, Dual<real> b)
+__device__ __forceinline__ void flux_adj(const real (&w)[4], real r, real u, real v, real E, real p, SideAdj<real> &a)
 {
-    return Dual<real>(a.v * b.v, a.d * b.v + a.v * b.d);
+    a.r += w[0] * u + w[1] * u * u + w[2] * u * v;
+    a.u += w[0] * r + real(2) * w[1] * r * u + w[2] * r * v + w[3] * (E + p);
+    a.v += w[2] * r * u;
+    a.E += w[3] * u;
+    a.p += w[1] + w[3] * u;
 }
-// Division and square root go through dv / sq: IEEE in FP64, the hardware
-// reciprocal and square root in FP32 (as in the forward stage).
+
 template <typename real>
-__device__ __forceinline__ Dual<real> operator/(Dual<real> a, Dual<real> b)
+__device__ __forceinline__ void hllc_vjp(real g, const real (&UL)[4], const real (&UR)[4], const real (&w)[4],
+                                         real (&gl)[4], real (&gr)[4])
 {
-    const real q = dv(a.v, b.v);
-    return Dual<real>(q, dv(a.d - q * b.d, b.v));
+    // forward: the intermediates of hllc<0>
+    const real rl = UL[0], irl = dv(real(1), rl), ul = UL[1] * irl, vl = UL[2] * irl, El = UL[3];
+    const real rr = UR[0], irr = dv(real(1), rr), ur = UR[1] * irr, vr = UR[2] * irr, Er = UR[3];
+    const real pl = (g - real(1)) * (El - real(0.5) * rl * (ul * ul + vl * vl));
+    const real pr = (g - real(1)) * (Er - real(0.5) * rr * (ur * ur + vr * vr));
+    const real cl = sq(g * pl * irl), cr = sq(g * pr * irr);
+    const bool minL = (ul - cl) < (ur - cr), maxL = (ul + cl) > (ur + cr);
+    const real SL = minL ? ul - cl : ur - cr;
+    const real SR = maxL ? ul + cl : ur + cr;
+    const real dL = SL - ul, dR = SR - ur;
+    const real den = rl * dL - rr * dR;
+    const real Ss = dv(pr - pl + rl * ul * dL - rr * ur * dR, den);
+    const bool useL = Ss >= real(0);
+    const bool takeL = SL >= real(0);
+    const bool takeStar = !takeL && (useL || SR > real(0));
+    // backward
+    SideAdj<real> a[2];
+    a[0].zero();
+    a[1].zero();
+    real aSL = real(0), aSR = real(0);
+    if (takeL) {
+        flux_adj(w, rl, ul, vl, El, pl, a[0]);
+    } else if (!takeStar) {
+        flux_adj(w, rr, ur, vr, Er, pr, a[1]);
+    } else {
+        SideAdj<real> &k = useL ? a[0] : a[1];
+        const real r = useL ? rl : rr, u = useL ? ul : ur, v = useL ? vl : vr, E = useL ? El : Er;
+        const real p = useL ? pl : pr, ir = useL ? irl : irr, S = useL ? SL : SR;
+        const real sku = S - u, den2 = S - Ss, rs = r * sku;
+        const real fac = dv(rs, den2), q = dv(p, rs);
+        const real Y = Ss + q, Z = Ss - u, X = E * ir + Z * Y;
+        // F* = F_k + S (U* - U_k), U* = fac (1, Ss, v, X)
+        flux_adj(w, r, u, v, E, p, k);
+        const real us[4] = {fac, fac * Ss, fac * v, fac * X};
+        const real uc[4] = {r, r * u, r * v, E};
+        real aS = real(0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) aS += w[i] * (us[i] - uc[i]);
+        // U_k = (r, r u, r v, E)
+        k.r -= S * (w[0] + w[1] * u + w[2] * v);
+        k.u -= S * w[1] * r;
+        k.v -= S * w[2] * r;
+        k.E -= S * w[3];
+        const real afac = S * (w[0] + w[1] * Ss + w[2] * v + w[3] * X);
+        real aSs = S * w[1] * fac;
+        k.v += S * w[2] * fac;
+        const real aX = S * w[3] * fac;
+        k.E += aX * ir;
+        k.ir += aX * E;
+        const real aZ = aX * Y, aY = aX * Z;
+        aSs += aZ + aY;
+        k.u -= aZ;
+        k.p += dv(aY, rs);
+        const real ars = dv(afac, den2) - dv(aY * q, rs);  // rs enters fac and q
+        const real aden2 = -dv(afac * fac, den2);
+        k.r += ars * sku;
+        const real asku = ars * r;
+        aS += aden2 + asku;
+        aSs -= aden2;
+        k.u -= asku;
+        if (useL) aSL += aS;
+        else aSR += aS;
+        // S* = num / den
+        const real anum = dv(aSs, den), aden = -dv(aSs * Ss, den);
+        a[1].p += anum;
+        a[0].p -= anum;
+        a[0].r += anum * ul * dL + aden * dL;
+        a[0].u += anum * rl * (dL - ul) - aden * rl;
+        aSL += anum * rl * ul + aden * rl;
+        a[1].r -= anum * ur * dR + aden * dR;
+        a[1].u -= anum * rr * (dR - ur) - aden * rr;
+        aSR -= anum * rr * ur + aden * rr;
+    }
+    // wave-speed bounds: S_L = u - c and S_R = u + c of the side each takes
+    real acl = real(0), acr = real(0);
+    if (minL) { a[0].u += aSL; acl -= aSL; }
+    else { a[1].u += aSL; acr -= aSL; }
+    if (maxL) { a[0].u += aSR; acl += aSR; }
+    else { a[1].u += aSR; acr += aSR; }
+    // c = sqrt(g p ir), then p = (g - 1) (E - r (u^2 + v^2) / 2), u = m ir, v = n ir, ir = 1 / r
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+        SideAdj<real> &b = a[sd];
+        const real c = sd ? cr : cl, p = sd ? pr : pl, ir = sd ? irr : irl, r = sd ? rr : rl;
+        const real u = sd ? ur : ul, v = sd ? vr : vl;
+        const real ax = dv(sd ? acr : acl, real(2) * c);
+        b.p += ax * g * ir;
+        b.ir += ax * g * p;
+        const real gp = (g - real(1)) * b.p;
+        b.E += gp;
+        b.r -= gp * real(0.5) * (u * u + v * v);
+        b.u -= gp * r * u;
+        b.v -= gp * r * v;
+        const real *U = sd ? UR : UL;
+        b.ir += b.u * U[1] + b.v * U[2];
+        real *out = sd ? gr : gl;
+        out[0] = b.r - b.ir * ir * ir;
+        out[1] = b.u * ir;
+        out[2] = b.v * ir;
+        out[3] = b.E;
+    }
 }
-template <typename real>
-__device__ __forceinline__ bool operator<(Dual<real> a, Dual<real> b) { return a.v < b.v; }
-template <typename real>
-__device__ __forceinline__ bool operator>(Dual<real> a, Dual<real> b) { return a.v > b.v; }
-template <typename real>
-__device__ __forceinline__ bool operator>=(Dual<real> a, Dual<real> b) { return a.v >= b.v; }
-template <typename real>
-__device__ __forceinline__ Dual<real> sqrt(Dual<real> a)
-{
-    const real r = sq(a.v);
-    return Dual<real>(r, dv(a.d, real(2) * r));
-}
-template <typename real>
-__device__ __forceinline__ bool finite(Dual<real> a) { return __builtin_isfinite(a.v); }
-template <typename real>
-__device__ __forceinline__ bool pos_finite(Dual<real> a) { return pos_finite(a.v); }
 
 // ----------------------------------------------------- contribution slots
 // Offsets (da, db) with |da| + |db| <= 3, row by row (db = -3 .. 3): slot offset
@@ -292,23 +382,14 @@ __global__ __launch_bounds__(128) void k_adj_faces(const AdjArgs<real> J)
                 UR[v] = single ? Bm : (plus ? Bm + Dm : Bm - Dm);
             }
             const real wq_ = A.gtab[kGtabNodeOff + R * 2 + slot];
-            real gs[8];  // d(w_g lambda_F . F) / d(UL, UR)
-#pragma unroll
-            for (int jv = 0; jv < 8; ++jv) {
-                Dual<real> dl_[4], dr_[4], fd[4];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    dl_[v] = Dual<real>(UL[v], jv == v ? real(1) : real(0));
-                    dr_[v] = Dual<real>(UR[v], jv == 4 + v ? real(1) : real(0));
-                }
-                // rotate the momenta into the x-face form, as hllc_rt does
-                const Dual<real> L4[4] = {dl_[0], dir ? dl_[2] : dl_[1], dir ? dl_[1] : dl_[2], dl_[3]};
-                const Dual<real> R4[4] = {dr_[0], dir ? dr_[2] : dr_[1], dir ? dr_[1] : dr_[2], dr_[3]};
-                bool bl, br;
-                hllc<0>(Dual<real>(A.gamma), L4, R4, fd, bl, br);
-                const real f1 = dir ? fd[2].d : fd[1].d, f2 = dir ? fd[1].d : fd[2].d;
-                gs[jv] = wq_ * (lF[0] * fd[0].d + lF[1] * f1 + lF[2] * f2 + lF[3] * fd[3].d);
-            }
+            // d(w_g lambda_F . F) / d(UL, UR), momenta rotated into the x-face form
+            const real wx[4] = {wq_ * lF[0], wq_ * (dir ? lF[2] : lF[1]), wq_ * (dir ? lF[1] : lF[2]), wq_ * lF[3]};
+            const real L4[4] = {UL[0], dir ? UL[2] : UL[1], dir ? UL[1] : UL[2], UL[3]};
+            const real R4[4] = {UR[0], dir ? UR[2] : UR[1], dir ? UR[1] : UR[2], UR[3]};
+            real gxl[4], gxr[4];
+            hllc_vjp(A.gamma, L4, R4, wx, gxl, gxr);
+            const real gs[8] = {gxl[0], dir ? gxl[2] : gxl[1], dir ? gxl[1] : gxl[2], gxl[3],
+                                gxr[0], dir ? gxr[2] : gxr[1], dir ? gxr[1] : gxr[2], gxr[3]};
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 // left state A + sg C with A = EE + F, C = N + OO; right state
