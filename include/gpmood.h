@@ -266,10 +266,10 @@ gpm_status gpm_cascade_stats(const gpm_ctx *ctx, long long stats[3]);
 gpm_status gpm_order_ptr(const gpm_ctx *ctx, void **order_dev);
 
 /* Bytes of the device workspace the stage adjoint needs (gpm_stage_vjp), bound
-   separately so that a context used only forward does not carry it: one slot per
-   (face direction, face side, stencil offset) and cell of the grid with 4 ghost
-   layers, 100 x 4 x (nx+8) x (ny+8) values of the context's precision, and the
-   FP64 derivative of the weight table with respect to ell. */
+   separately so that a context used only forward does not carry it: one record
+   per face, the adjoints of both sides' reconstruction accumulators, 2 x 64 x
+   (nx+1) x (ny+1) values of the context's precision, and the FP64 derivative of
+   the weight table with respect to ell. */
 gpm_status gpm_adjoint_workspace_size(const gpm_ctx *ctx, size_t *bytes);
 
 /* Bind caller-owned device memory (>= gpm_adjoint_workspace_size, 256-byte
@@ -291,9 +291,9 @@ gpm_status gpm_bind_adjoint(gpm_ctx *ctx, void *adj_work);
    non-NULL, the stage's contribution to dL/d(ell) (ell the physical GP length
    scale; through the ell-dependence of the reconstruction weights only, the
    detection being frozen) is added to *dL_dell (synchronising).  Deterministic:
-   every face writes its contributions to the stencil cells into slots of the
-   adjoint workspace (no atomics), and each cell sums its slots in a fixed order,
-   so repeated calls give the same bits.  Errors: GPM_EINVAL (bad stage, NULL or
+   every face writes its record into the adjoint workspace (no atomics), and each
+   cell sums the contributions of the faces whose stencils hold it in a fixed
+   order, so repeated calls give the same bits.  Errors: GPM_EINVAL (bad stage, NULL or
    aliased buffers, dt <= 0), GPM_ESTATE (no adjoint workspace bound),
    GPM_EUNSUPPORTED (a reflecting axis, HLL, a slit). */
 gpm_status gpm_stage_vjp(gpm_ctx *ctx, int s, const void *Un, const void *Us, const void *order, double dt,

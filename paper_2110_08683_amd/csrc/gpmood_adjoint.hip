@@ -158,113 +158,63 @@ __device__ __forceinline__ void hllc_vjp(real g, const real (&UL)[4], const real
     }
 }
 
-// ----------------------------------------------------- contribution slots
-// Offsets (da, db) with |da| + |db| <= 3, row by row (db = -3 .. 3): slot offset
-// index of (da, db), and the offsets by index.
-__device__ __forceinline__ int adj_off(int da, int db)
-{
-    const int base = db == -3 ? 0 : (db == -2 ? 1 : (db == -1 ? 4 : (db == 0 ? 9 : (db == 1 ? 16 : (db == 2 ? 21 : 24)))));
-    return base + da + 3 - (db < 0 ? -db : db);
-}
+// ------------------------------------------------ per-face adjoint layout
+// Offsets (da, db) of a stencil cell from its face side's centre, |da| + |db| <= 3,
+// in the fixed order of the gather.
 constexpr int kAdjDa[kAdjOffsets] = {0, -1, 0, 1, -2, -1, 0, 1, 2, -3, -2, -1, 0, 1, 2, 3, -2, -1, 0, 1, 2, -1, 0, 1, 0};
 constexpr int kAdjDb[kAdjOffsets] = {-3, -2, -2, -2, -1, -1, -1, -1, -1, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 2, 2, 2, 3};
 
-// Index of (slot, variable, unwrapped cell (ux, uy)) in the slot array.
-template <typename real>
-__device__ __forceinline__ size_t slot_index(const AdjArgs<real> &J, int slot, int v, int ux, int uy)
+__host__ __device__ constexpr int iabs_c(int x) { return x < 0 ? -x : x; }
+// Index of position (a, b) = (|da|, |db|) in the compact weight table, and the
+// smallest face radius whose stencil holds it.
+__host__ __device__ constexpr int pos_of(int a, int b)
 {
-    const size_t EX = (size_t)(J.A.nx + 2 * kAdjGhost), EY = (size_t)(J.A.ny + 2 * kAdjGhost);
-    return ((size_t)slot * 4 + v) * EX * EY + (size_t)(uy + kAdjGhost) * EX + (size_t)(ux + kAdjGhost);
+    return a == 0 && b == 0 ? 0 : a == 1 && b == 0 ? 1 : a == 0 && b == 1 ? 2 : a == 2 && b == 0 ? 3
+         : a == 0 && b == 2 ? 4 : a == 1 && b == 1 ? 5 : a == 3 && b == 0 ? 6 : a == 0 && b == 3 ? 7
+         : a == 2 && b == 1 ? 8 : 9;
+}
+__host__ __device__ constexpr int min_radius(int e) { return e == 0 ? 0 : (e <= 2 ? 1 : (e <= 5 ? 2 : 3)); }
+
+// The per-face record: the adjoints of both sides' quarter accumulators,
+// component side * 32 + v * 8 + p * 4 + c, in planes [dir][component][ny+1][nx+1].
+constexpr int kFaceComps = 64;
+template <typename real>
+__device__ __forceinline__ size_t gface_index(const AdjArgs<real> &J, int dir, int comp, int i, int j)
+{
+    const size_t FX = (size_t)J.A.nx + 1, FY = (size_t)J.A.ny + 1;
+    return (((size_t)dir * kFaceComps + comp) * FY + (size_t)j) * FX + (size_t)i;
 }
 
-// Store the contributions of a face side whose stencil is centred at (ic, jc)
-// (unwrapped): position (a, b) with mirror values at (+a,+b), (-a,+b), (+a,-b),
-// (-a,-b); mirror cells that coincide (a = 0 or b = 0) share one slot, their
-// values summed in a fixed order.
+// dL/d(ell) of one face, in FP64: the sum over both sides' stencil positions of
+// d(weight)/d(ell) x accumulator adjoint x parity sum (positions within the
+// face's radius).
 template <typename real>
-__device__ __forceinline__ void store_mirrors(const AdjArgs<real> &J, int base, int v, int ic, int jc, int a, int b,
-                                              real pp, real mp, real pm, real mm)
-{
-    real *S = J.slots;
-    if (a == 0 && b == 0) {
-        S[slot_index(J, base + adj_off(0, 0), v, ic, jc)] = ((pp + mp) + pm) + mm;
-    } else if (a == 0) {
-        S[slot_index(J, base + adj_off(0, b), v, ic, jc + b)] = pp + mp;
-        S[slot_index(J, base + adj_off(0, -b), v, ic, jc - b)] = pm + mm;
-    } else if (b == 0) {
-        S[slot_index(J, base + adj_off(a, 0), v, ic + a, jc)] = pp + pm;
-        S[slot_index(J, base + adj_off(-a, 0), v, ic - a, jc)] = mp + mm;
-    } else {
-        S[slot_index(J, base + adj_off(a, b), v, ic + a, jc + b)] = pp;
-        S[slot_index(J, base + adj_off(-a, b), v, ic - a, jc + b)] = mp;
-        S[slot_index(J, base + adj_off(a, -b), v, ic + a, jc - b)] = pm;
-        S[slot_index(J, base + adj_off(-a, -b), v, ic - a, jc - b)] = mm;
-    }
-}
-
-template <typename real>
-__device__ __forceinline__ void zero_face_slots(const AdjArgs<real> &J, int dir, int iL, int jL, int iR, int jR)
-{
-    const int bL = (dir * 2 + 0) * kAdjOffsets, bR = (dir * 2 + 1) * kAdjOffsets;
-    for (int o = 0; o < kAdjOffsets; ++o)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            J.slots[slot_index(J, bL + o, v, iL + kAdjDa[o], jL + kAdjDb[o])] = real(0);
-            J.slots[slot_index(J, bR + o, v, iR + kAdjDa[o], jR + kAdjDb[o])] = real(0);
-        }
-}
-
-// The transposed reconstruction of one face: node adjoints gL, gR of the quarter
-// accumulators (per variable, weight slot and parity component) -> contributions
-// to the stencil cells of both sides, through the same compact weights as the
-// forward; positions beyond the face's radius store zeros.  dl += the face's
-// dL/d(ell) term, the sum over positions of dz/d(ell) x accumulator adjoint x
-// parity sum, formed in FP64.
-template <typename real>
-__device__ __forceinline__ void store_face_slots(const AdjArgs<real> &J, int dir, int iL, int jL, int iR, int jR,
-                                                 int np, int R, const real (&gL)[4][2][4], const real (&gR)[4][2][4],
-                                                 double &dl)
+__device__ __forceinline__ void face_dl(const AdjArgs<real> &J, int dir, int iL, int jL, int iR, int jR, int np, int R,
+                                        const real (&gL)[4][2][4], const real (&gR)[4][2][4], double &dl)
 {
     const StageArgs<real> &A = J.A;
     const int nx = A.nx, ny = A.ny;
     const size_t plane = (size_t)nx * ny;
-    const real *wt = A.gtab + (R * 2 + dir) * kGtabPerDir;
     const double *dwt = J.dl64 + (R * 2 + dir) * kGtabPerDir;
-    const int bL = (dir * 2 + 0) * kAdjOffsets, bR = (dir * 2 + 1) * kAdjOffsets;
-    for (int e = 0; e < kNPos; ++e) {
+    for (int e = 0; e < np; ++e) {
         const int a = (int)((kPosA >> (4 * e)) & 15u), b = (int)((kPosB >> (4 * e)) & 15u);
-        const bool live = e < np;
         const int xLp = wrap(iL + a, nx, A.bcx), xLm = wrap(iL - a, nx, A.bcx);
         const int xRp = wrap(iR + a, nx, A.bcx), xRm = wrap(iR - a, nx, A.bcx);
         const size_t yLp = (size_t)wrap(jL + b, ny, A.bcy) * nx, yLm = (size_t)wrap(jL - b, ny, A.bcy) * nx;
         const size_t yRp = (size_t)wrap(jR + b, ny, A.bcy) * nx, yRm = (size_t)wrap(jR - b, ny, A.bcy) * nx;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            real hl[4] = {real(0), real(0), real(0), real(0)}, hr[4] = {real(0), real(0), real(0), real(0)};
-            if (live) {
-                const real *U = A.Us + v * plane;
-                double ql[4], qr[4];
-                parity4((double)U[yLp + xLp], (double)U[yLp + xLm], (double)U[yLm + xLp], (double)U[yLm + xLm], ql);
-                parity4((double)U[yRp + xRp], (double)U[yRp + xRm], (double)U[yRm + xRp], (double)U[yRm + xRm], qr);
+            const real *U = A.Us + v * plane;
+            double ql[4], qr[4];
+            parity4((double)U[yLp + xLp], (double)U[yLp + xLm], (double)U[yLm + xLp], (double)U[yLm + xLm], ql);
+            parity4((double)U[yRp + xRp], (double)U[yRp + xRm], (double)U[yRm + xRp], (double)U[yRm + xRm], qr);
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
+            for (int c = 0; c < 4; ++c)
 #pragma unroll
-                    for (int p = 0; p < 2; ++p) {
-                        const real w = wt[p * (kNPos * 4) + e * 4 + c];
-                        const double dw = dwt[p * (kNPos * 4) + e * 4 + c];
-                        hl[c] += w * gL[v][p][c];
-                        hr[c] += w * gR[v][p][c];
-                        dl += dw * ((double)gL[v][p][c] * ql[c] + (double)gR[v][p][c] * qr[c]);
-                    }
+                for (int p = 0; p < 2; ++p) {
+                    const double dw = dwt[p * (kNPos * 4) + e * 4 + c];
+                    dl += dw * ((double)gL[v][p][c] * ql[c] + (double)gR[v][p][c] * qr[c]);
                 }
-            }
-            // transpose of the parity sums (pp, mp, pm, mm) -> (EE, OE, EO, OO)
-            store_mirrors(J, bL, v, iL, jL, a, b, hl[C_EE] + hl[C_OE] + hl[C_EO] + hl[C_OO],
-                          hl[C_EE] - hl[C_OE] + hl[C_EO] - hl[C_OO], hl[C_EE] + hl[C_OE] - hl[C_EO] - hl[C_OO],
-                          hl[C_EE] - hl[C_OE] - hl[C_EO] + hl[C_OO]);
-            store_mirrors(J, bR, v, iR, jR, a, b, hr[C_EE] + hr[C_OE] + hr[C_EO] + hr[C_OO],
-                          hr[C_EE] - hr[C_OE] + hr[C_EO] - hr[C_OO], hr[C_EE] + hr[C_OE] - hr[C_EO] - hr[C_OO],
-                          hr[C_EE] - hr[C_OE] - hr[C_EO] + hr[C_OO]);
         }
     }
 }
@@ -277,7 +227,10 @@ __global__ __launch_bounds__(128) void k_adj_faces(const AdjArgs<real> J)
     const StageArgs<real> &A = J.A;
     const int nx = A.nx, ny = A.ny;
     const size_t plane = (size_t)nx * ny;
-    const int nfx = (nx + 1) * ny, nft = nfx + nx * (ny + 1);
+    // a periodic axis has one face per cell along it (the face at the wrap joins
+    // cells n-1 and 0), an outflow axis n + 1
+    const int fxn = A.bcx == 0 ? nx : nx + 1, fyn = A.bcy == 0 ? ny : ny + 1;
+    const int nfx = fxn * ny, nft = nfx + nx * fyn;
     const real alpha = A.s == 0 ? real(1) : (A.s == 1 ? real(0.25) : real(2) / real(3));
     const real dt = (real)(*A.dt);
     double dl = 0.0;
@@ -286,12 +239,12 @@ __global__ __launch_bounds__(128) void k_adj_faces(const AdjArgs<real> J)
         bool hasL, hasR;
         if (f < nfx) {
             dir = 0;
-            j = f / (nx + 1);
-            i = f - j * (nx + 1);  // between cells i-1 and i
+            j = f / fxn;
+            i = f - j * fxn;  // between cells i-1 and i
             iL = i - 1;
             jL = j;
-            hasL = i >= 1;
-            hasR = i < nx;
+            hasL = A.bcx == 0 || i >= 1;
+            hasR = A.bcx == 0 || i < nx;
         } else {
             dir = 1;
             const int g = f - nfx;
@@ -299,27 +252,27 @@ __global__ __launch_bounds__(128) void k_adj_faces(const AdjArgs<real> J)
             i = g - j * nx;  // between cells (i, j-1) and (i, j)
             iL = i;
             jL = j - 1;
-            hasL = j >= 1;
-            hasR = j < ny;
+            hasL = A.bcy == 0 || j >= 1;
+            hasR = A.bcy == 0 || j < ny;
         }
         const int iR = iL + (dir == 0), jR = jL + (dir == 1);
+        const int cL = wrap(jL, ny, A.bcy) * nx + wrap(iL, nx, A.bcx);
+        const int cR = wrap(jR, ny, A.bcy) * nx + wrap(iR, nx, A.bcx);
         const real inv = dt / (dir == 0 ? A.dx : A.dy);
         real lF[4];
         bool any = false;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const real lr = hasR ? J.lam_out[v * plane + (size_t)jR * nx + iR] : real(0);
-            const real ll = hasL ? J.lam_out[v * plane + (size_t)jL * nx + iL] : real(0);
+            const real lr = hasR ? J.lam_out[v * plane + cR] : real(0);
+            const real ll = hasL ? J.lam_out[v * plane + cL] : real(0);
             lF[v] = (alpha * lr - alpha * ll) * inv;
             any = any || lF[v] != real(0);
         }
         if (!any) {
-            // nothing flows through this face: its slots hold zeros
-            zero_face_slots(J, dir, iL, jL, iR, jR);
+            // nothing flows through this face: its record holds zeros
+            for (int k = 0; k < kFaceComps; ++k) J.gface[gface_index(J, dir, k, i, j)] = real(0);
             continue;
         }
-        const int cL = wrap(jL, ny, A.bcy) * nx + wrap(iL, nx, A.bcx);
-        const int cR = wrap(jR, ny, A.bcy) * nx + wrap(iR, nx, A.bcx);
         const int R = min((int)A.order[cL], (int)A.order[cR]);
         const int np = R <= 0 ? 1 : (R == 1 ? 3 : (R == 2 ? 6 : 10));
         const int q = R <= 0 ? 1 : R + 1;
@@ -406,10 +359,18 @@ __global__ __launch_bounds__(128) void k_adj_faces(const AdjArgs<real> J)
                 }
             }
         }
-        // 4-5. transposed reconstruction: each side's contribution to each of its
-        // stencil cells goes to that cell's (direction, side, offset) slot, and
-        // the ell term (in FP64, with the FP64 derivative table)
-        store_face_slots(J, dir, iL, jL, iR, jR, np, R, gL, gR, dl);
+        // 4-5. the face's record (the transposed reconstruction is applied by the
+        // cells that gather it) and its ell term
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    J.gface[gface_index(J, dir, v * 8 + p * 4 + c, i, j)] = gL[v][p][c];
+                    J.gface[gface_index(J, dir, 32 + v * 8 + p * 4 + c, i, j)] = gR[v][p][c];
+                }
+        face_dl(J, dir, iL, jL, iR, jR, np, R, gL, gR, dl);
     }
     // dL/d(ell) partial of this block, summed in a fixed order
     red[threadIdx.x] = dl;
@@ -421,66 +382,273 @@ __global__ __launch_bounds__(128) void k_adj_faces(const AdjArgs<real> J)
     if (threadIdx.x == 0) J.dl_partial[blockIdx.x] = red[0];
 }
 
-// Unwrapped images of interior index m on an axis of n cells (periodic: m and
-// m -+ n; outflow: the ghost cells that copy an edge cell) within the 4 ghost
-// layers; returns their number (at most 9).
-__device__ __forceinline__ int axis_images(int m, int n, int bc, int (&u)[9])
+// ------------------------------------------------------------ per-cell gather
+// A 16 x 16 tile of cells gathers from the faces whose stencils reach it: face
+// indices [t0 - 3, t0 + 19] on both axes (a 23 x 23 window), staged in LDS one
+// (direction, variable) at a time with the faces' radii and the direction's
+// compact weights.  Each cell sums, in a fixed order, over its unwrapped images
+// (its own index, and on an outflow axis the ghost indices that copy an edge cell)
+// and over the 2 sides x 25 offsets of each direction, the contribution of the
+// face side centred at image - offset: the weighted accumulator adjoints
+// (h_c = sum_p w[p][e][c] g[p][c] at position e = (|da|, |db|)), combined with
+// the signs of the mirror image (+-a, +-b) that reads this cell, both mirrors
+// when a or b is 0.
+constexpr int kTile = 16;
+constexpr int kWin = kTile + 7;
+template <typename real>
+struct GatherLds {
+    static constexpr int kStride = sizeof(real) == 4 ? 20 : 18;  // 16 values, padded against bank conflicts
+    alignas(16) real g[kWin * kWin * kStride];
+    alignas(16) real w[4 * kGtabPerDir];
+    signed char r[kWin * kWin];
+};
+
+// Four values read together (one 16-byte LDS access per four floats).
+template <typename real>
+struct alignas(16) Quad {
+    real x[4];
+};
+
+// Contribution of the face side whose LDS record is g (8 values: p, c) to the
+// stencil cell at offset (DA, DB) from the side's centre, with the compact
+// weights w0 = w[0][e][.], w1 = w[1][e][.] of its position e:
+// h_c = w0_c g0_c + w1_c g1_c, combined with the signs of the mirror image
+// (+-a, +-b) that reads the cell: x-odd parts carry sign(DA), y-odd parts
+// sign(DB), and a zero offset takes both mirrors, doubling the even part and
+// cancelling the odd one.
+template <typename real, int DA, int DB>
+__device__ __forceinline__ real side_term(const Quad<real> &w0, const Quad<real> &w1, const real *g)
 {
-    int k = 0;
-    u[k++] = m;
-    if (bc == 0) {
-        for (int w = m - n; w >= -kAdjGhost; w -= n) u[k++] = w;
-        for (int w = m + n; w <= n - 1 + kAdjGhost; w += n) u[k++] = w;
+#pragma clang fp contract(fast)
+    const Quad<real> g0 = *reinterpret_cast<const Quad<real> *>(g);
+    const Quad<real> g1 = *reinterpret_cast<const Quad<real> *>(g + 4);
+    real h[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) h[c] = w0.x[c] * g0.x[c] + w1.x[c] * g1.x[c];
+    if constexpr (DA == 0 && DB == 0) {
+        return real(4) * h[C_EE];
+    } else if constexpr (DA == 0) {
+        return real(2) * (DB > 0 ? h[C_EE] + h[C_EO] : h[C_EE] - h[C_EO]);
+    } else if constexpr (DB == 0) {
+        return real(2) * (DA > 0 ? h[C_EE] + h[C_OE] : h[C_EE] - h[C_OE]);
     } else {
-        if (m == 0)
-            for (int g = 1; g <= kAdjGhost; ++g) u[k++] = -g;
-        if (m == n - 1)
-            for (int g = 0; g < kAdjGhost; ++g) u[k++] = n + g;
+        const real x = DA > 0 ? h[C_EE] + h[C_OE] : h[C_EE] - h[C_OE];
+        const real y = DA > 0 ? h[C_EO] + h[C_OO] : h[C_EO] - h[C_OO];
+        return DB > 0 ? x + y : x - y;
     }
-    return k;
 }
 
-// Per cell and variable: the sum, in a fixed order, of every face side's
-// contribution to the cell (over the cell's unwrapped images, then the slots
-// whose face exists), then dL/dU_s = alpha lam_out + that sum and dL/dU^n.
-template <typename real>
-__global__ __launch_bounds__(256) void k_adj_cells(const AdjArgs<real> J)
+// The 25 offsets in gather order: grouped by stencil position e, so that one
+// position's weights serve consecutive terms.
+constexpr int kGatherDa[kAdjOffsets] = {0, 1, -1, 0, 0, 2, -2, 0, 0, 1, -1, 1, -1, 3, -3, 0, 0, 2, -2, 2, -2, 1, -1, 1, -1};
+constexpr int kGatherDb[kAdjOffsets] = {0, 0, 0, 1, -1, 0, 0, 2, -2, 1, 1, -1, -1, 0, 0, 3, -3, 1, 1, -1, -1, 2, 2, -2, -2};
+
+// The contributions to one cell image at window coordinates (bx, by) from the
+// faces of direction DIR, summed over (offset, side) in a fixed order.  TOP:
+// every face of the window has the top radius 3 or does not exist (then its
+// record is zero), so the weights are the block-uniform radius-3 weights wtop
+// and no radius test is needed: the sum has the same bits as the general path's.
+// CHECK: the image may reach outside the window (ghost images of edge cells).
+template <typename real, int DIR, bool CHECK, bool TOP, int O = 0>
+__device__ __forceinline__ void gather_sides(const GatherLds<real> &L, const Quad<real> (&wtop)[2 * kNPos], int bx,
+                                             int by, real &sum)
 {
+    if constexpr (O < 2 * kAdjOffsets) {
+        constexpr int o = O / 2, side = O % 2;
+        constexpr int da = kGatherDa[o], db = kGatherDb[o];
+        constexpr int e = pos_of(iabs_c(da), iabs_c(db));
+        const int wx = bx - da + (DIR == 0 && side == 0 ? 1 : 0);
+        const int wy = by - db + (DIR == 1 && side == 0 ? 1 : 0);
+        const int f = wy * kWin + wx;
+        const real *g = L.g + f * GatherLds<real>::kStride + side * 8;
+        if constexpr (TOP) {
+            sum += side_term<real, da, db>(wtop[e], wtop[kNPos + e], g);
+        } else {
+            if (!CHECK || (wx >= 0 && wx < kWin && wy >= 0 && wy < kWin)) {
+                const int R = L.r[f];
+                if (R == 3) {
+                    sum += side_term<real, da, db>(wtop[e], wtop[kNPos + e], g);
+                } else if (R >= min_radius(e)) {  // not: no face (-1), or beyond its radius
+                    const real *w = L.w + R * kGtabPerDir + e * 4;
+                    sum += side_term<real, da, db>(*reinterpret_cast<const Quad<real> *>(w),
+                                                   *reinterpret_cast<const Quad<real> *>(w + kNPos * 4), g);
+                }
+            }
+        }
+        gather_sides<real, DIR, CHECK, TOP, O + 1>(L, wtop, bx, by, sum);
+    }
+}
+
+// A value the whole wavefront holds, made scalar.
+__device__ __forceinline__ float uniform(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
+__device__ __forceinline__ double uniform(double x)
+{
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll)), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ __forceinline__ int mod_n(int i, int n)
+{
+    const int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+// Unwrapped images of index m on an axis of n cells: m, and on an outflow axis
+// the ghost indices that copy an edge cell (face-side centres run from -1 to n,
+// so radius-3 stencils read ghosts -1..-4 and n..n+3).  Count, and image q.
+__device__ __forceinline__ int n_images(int m, int n, int bc)
+{
+    return 1 + (bc != 0 && m == 0 ? 4 : 0) + (bc != 0 && m == n - 1 ? 4 : 0);
+}
+__device__ __forceinline__ int image(int m, int n, int bc, int q)
+{
+    if (q == 0) return m;
+    if (bc != 0 && m == 0 && q <= 4) return -q;
+    return n - 1 + (q - (m == 0 ? 4 : 0));
+}
+
+// Window face q of direction dir: its face indices (periodic axes wrapped) and
+// whether it exists.
+struct WinFace {
+    int fi, fj;
+    bool ok;
+};
+__device__ __forceinline__ WinFace win_face(int q, int dir, int i0, int j0, int nx, int ny, int bcx, int bcy)
+{
+    WinFace w;
+    w.fi = i0 - 3 + q % kWin;
+    w.fj = j0 - 3 + q / kWin;
+    w.ok = true;
+    const int fxn = dir == 0 ? (bcx == 0 ? nx : nx + 1) : nx;
+    const int fyn = dir == 1 ? (bcy == 0 ? ny : ny + 1) : ny;
+    if (bcx == 0) w.fi = mod_n(w.fi, nx);
+    else w.ok = w.ok && w.fi >= 0 && w.fi < fxn;
+    if (bcy == 0) w.fj = mod_n(w.fj, ny);
+    else w.ok = w.ok && w.fj >= 0 && w.fj < fyn;
+    return w;
+}
+
+constexpr int kWinPerThread = (kWin * kWin + 255) / 256;
+
+// This thread's share of the window records of round r (direction r / 4,
+// variable r % 4): 16 values (side, p, c) per face, zero for absent faces.
+template <typename real>
+__device__ __forceinline__ void fetch_round(const AdjArgs<real> &J, int r, int i0, int j0,
+                                            Quad<real> (&pre)[kWinPerThread][4])
+{
+    const int dir = r >> 2, v = r & 3;
+#pragma unroll
+    for (int t = 0; t < kWinPerThread; ++t) {
+        const int q = threadIdx.x + t * 256;
+        const WinFace w = win_face(q, dir, i0, j0, J.A.nx, J.A.ny, J.A.bcx, J.A.bcy);
+        const bool ok = q < kWin * kWin && w.ok;
+#pragma unroll
+        for (int k4 = 0; k4 < 4; ++k4)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int comp = (k4 >> 1) * 32 + v * 8 + (k4 & 1) * 4 + c;  // side, v, p, c
+                pre[t][k4].x[c] = ok ? J.gface[gface_index(J, dir, comp, w.fi, w.fj)] : real(0);
+            }
+    }
+}
+
+template <typename real>
+__global__ __launch_bounds__(256, sizeof(real) == 4 ? 3 : 2) void k_adj_cells(const AdjArgs<real> J)
+{
+    __shared__ GatherLds<real> L;
     const StageArgs<real> &A = J.A;
     const int nx = A.nx, ny = A.ny;
     const size_t n = (size_t)nx * ny;
+    const int i0 = blockIdx.x * kTile, j0 = blockIdx.y * kTile;
+    const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
+    const int mi = i0 + tx, mj = j0 + ty;
+    const bool own = mi < nx && mj < ny;
+    const int nix = own ? n_images(mi, nx, A.bcx) : 0, niy = own ? n_images(mj, ny, A.bcy) : 0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    constexpr int KS = GatherLds<real>::kStride;
+    // eight rounds (direction, variable); the next round's records are fetched
+    // into registers while this round's are gathered
+    Quad<real> pre[kWinPerThread][4];
+    fetch_round(J, 0, i0, j0, pre);
+    bool top = false;
+    Quad<real> wtop[2 * kNPos];
+    for (int r = 0; r < 8; ++r) {
+        const int dir = r >> 2, v = r & 3;
+        __syncthreads();  // the previous round's readers are done
+#pragma unroll
+        for (int t = 0; t < kWinPerThread; ++t) {
+            const int q = threadIdx.x + t * 256;
+            if (q < kWin * kWin) {
+                Quad<real> *dst = reinterpret_cast<Quad<real> *>(L.g + q * KS);
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) dst[k4] = pre[t][k4];
+            }
+        }
+        if (v == 0) {
+            // this direction's face radii and weights
+            bool notop = false;
+            for (int q = threadIdx.x; q < kWin * kWin; q += blockDim.x) {
+                const WinFace w = win_face(q, dir, i0, j0, nx, ny, A.bcx, A.bcy);
+                int R = -1;
+                if (w.ok) {
+                    const int iL = w.fi - (dir == 0), jL = w.fj - (dir == 1);
+                    const int cL = wrap(jL, ny, A.bcy) * nx + wrap(iL, nx, A.bcx);
+                    const int cR = wrap(w.fj, ny, A.bcy) * nx + wrap(w.fi, nx, A.bcx);
+                    R = min((int)A.order[cL], (int)A.order[cR]);
+                }
+                L.r[q] = (signed char)R;
+                notop = notop || (R >= 0 && R != 3);
+            }
+            for (int q = threadIdx.x; q < 4 * kGtabPerDir; q += blockDim.x)
+                L.w[q] = A.gtab[((q / kGtabPerDir) * 2 + dir) * kGtabPerDir + q % kGtabPerDir];
+#pragma unroll
+            for (int k = 0; k < 2 * kNPos; ++k)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) wtop[k].x[c] = uniform(A.gtab[(3 * 2 + dir) * kGtabPerDir + k * 4 + c]);
+            // every face of the window at the top radius (or absent): no radius tests
+            top = __syncthreads_and(!notop) != 0;
+        } else {
+            __syncthreads();
+        }
+        if (r + 1 < 8) fetch_round(J, r + 1, i0, j0, pre);
+        if (own) {
+            // the cell's own image, then (edge cells of an outflow axis) its ghosts
+            real sum = real(0);
+            if (top) {
+                if (dir == 0) gather_sides<real, 0, false, true>(L, wtop, tx + 3, ty + 3, sum);
+                else gather_sides<real, 1, false, true>(L, wtop, tx + 3, ty + 3, sum);
+            } else {
+                if (dir == 0) gather_sides<real, 0, false, false>(L, wtop, tx + 3, ty + 3, sum);
+                else gather_sides<real, 1, false, false>(L, wtop, tx + 3, ty + 3, sum);
+            }
+            for (int qy = 0; qy < niy; ++qy)
+                for (int qx = (qy == 0 ? 1 : 0); qx < nix; ++qx) {
+                    const int bx = image(mi, nx, A.bcx, qx) - (i0 - 3), by = image(mj, ny, A.bcy, qy) - (j0 - 3);
+                    if (dir == 0) gather_sides<real, 0, true, false>(L, wtop, bx, by, sum);
+                    else gather_sides<real, 1, true, false>(L, wtop, bx, by, sum);
+                }
+            acc[v] += (double)sum;
+        }
+    }
+    if (!own) return;
+    const size_t k = (size_t)mj * nx + mi;
     const real alpha = A.s == 0 ? real(1) : (A.s == 1 ? real(0.25) : real(2) / real(3));
     const real beta = A.s == 0 ? real(0) : (A.s == 1 ? real(0.75) : real(1) / real(3));
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
-        const int mi = (int)(k % nx), mj = (int)(k / nx);
-        int ux[9], uy[9];
-        const int nix = axis_images(mi, nx, A.bcx, ux), niy = axis_images(mj, ny, A.bcy, uy);
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int qy = 0; qy < niy; ++qy)
-            for (int qx = 0; qx < nix; ++qx)
-                for (int slot = 0; slot < kAdjSlots; ++slot) {
-                    const int dir = slot / (2 * kAdjOffsets), side = (slot / kAdjOffsets) & 1, o = slot % kAdjOffsets;
-                    // the face side whose stencil centre is the image minus the offset
-                    const int ci = ux[qx] - kAdjDa[o], cj = uy[qy] - kAdjDb[o];
-                    bool ok;
-                    if (dir == 0) ok = cj >= 0 && cj < ny && (side == 0 ? (ci >= -1 && ci <= nx - 1) : (ci >= 0 && ci <= nx));
-                    else ok = ci >= 0 && ci < nx && (side == 0 ? (cj >= -1 && cj <= ny - 1) : (cj >= 0 && cj <= ny));
-                    if (!ok) continue;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[v] += (double)J.slots[slot_index(J, slot, v, ux[qx], uy[qy])];
-                }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const size_t q = v * n + k;
-            const real lo = J.lam_out[q];
-            const real ls = (real)((double)(alpha * lo) + acc[v]);
-            if (A.s > 0) {
-                J.lam_Us[q] = ls;
-                J.lam_Un[q] += beta * lo;
-            } else {
-                // U^n feeds both arguments of stage 0: fold in its other adjoint if given
-                J.lam_Us[q] = J.lam_Un ? ls + J.lam_Un[q] : ls;
-            }
+    for (int v = 0; v < 4; ++v) {
+        const size_t q = v * n + k;
+        const real lo = J.lam_out[q];
+        const real ls = (real)((double)(alpha * lo) + acc[v]);
+        if (A.s > 0) {
+            J.lam_Us[q] = ls;
+            J.lam_Un[q] += beta * lo;
+        } else {
+            // U^n feeds both arguments of stage 0: fold in its other adjoint if given
+            J.lam_Us[q] = J.lam_Un ? ls + J.lam_Un[q] : ls;
         }
     }
 }
@@ -510,9 +678,8 @@ hipError_t launch_stage_vjp(const AdjArgs<real> &J, int nblk_faces, double *dl_o
 {
     const size_t n = (size_t)J.A.nx * J.A.ny;
     hipLaunchKernelGGL(k_adj_faces<real>, dim3(nblk_faces), dim3(128), 0, st, J);
-    size_t nb = (n + 255) / 256;
-    if (nb > 4096) nb = 4096;
-    hipLaunchKernelGGL(k_adj_cells<real>, dim3((unsigned)nb), dim3(256), 0, st, J);
+    const dim3 tiles((unsigned)((J.A.nx + kTile - 1) / kTile), (unsigned)((J.A.ny + kTile - 1) / kTile));
+    hipLaunchKernelGGL(k_adj_cells<real>, tiles, dim3(kTile * kTile), 0, st, J);
     hipLaunchKernelGGL(k_adj_dl_final, dim3(1), dim3(256), 0, st, J.dl_partial, nblk_faces, dl_out);
     return hipGetLastError();
 }

@@ -72,7 +72,7 @@ struct gpm_ctx {
     int instrument = 0;           // bit 0: stage events and iteration counts, bit 1: level statistics
     long long acc_iters = 0, acc_stages = 0;
     long long cstat[3] = {0, 0, 0};  // last stage: multi-block passes, tail passes, hand-backs
-    // adjoint workspace (gpm_bind_adjoint): contribution slots, then the FP64
+    // adjoint workspace (gpm_bind_adjoint): per-face records, then the FP64
     // derivative of the compact weight table with respect to ell
     char *adj = nullptr;
     std::vector<hipEvent_t> evs;  // 3 per instrumented stage: first pass start/end, stage end
@@ -86,20 +86,20 @@ static inline gpm_status fail(gpm_ctx *c, gpm_status st, const std::string &msg)
     return st;
 }
 
-// Adjoint workspace: [kAdjSlots][4][ny+8][nx+8] values of the state precision,
-// then kGtabSize doubles (256-byte aligned parts).
-static inline size_t adj_slot_bytes(const gpm_ctx *c)
+// Adjoint workspace: the per-face records, [2][64][ny+1][nx+1] values of the
+// state precision, then kGtabSize doubles (256-byte aligned parts).
+static inline size_t adj_face_bytes(const gpm_ctx *c)
 {
     const size_t esz = c->prec == GPM_F64 ? 8 : 4;
-    return align_up((size_t)kAdjSlots * 4 * (size_t)(c->nx + 2 * kAdjGhost) * (size_t)(c->ny + 2 * kAdjGhost) * esz);
+    return align_up((size_t)2 * 64 * (size_t)(c->nx + 1) * (size_t)(c->ny + 1) * esz);
 }
-static inline size_t adj_bytes(const gpm_ctx *c) { return adj_slot_bytes(c) + align_up((size_t)kGtabSize * 8); }
+static inline size_t adj_bytes(const gpm_ctx *c) { return adj_face_bytes(c) + align_up((size_t)kGtabSize * 8); }
 
 // Copy the FP64 ell-derivative of the compact weights into the adjoint workspace.
 static inline gpm_status upload_adj_dl(gpm_ctx *c)
 {
     if (!c->adj || !c->have_scheme) return GPM_OK;
-    hipError_t e = hipMemcpyAsync(c->adj + adj_slot_bytes(c), c->gtab64.data() + kGtabSize,
+    hipError_t e = hipMemcpyAsync(c->adj + adj_face_bytes(c), c->gtab64.data() + kGtabSize,
                                   (size_t)kGtabSize * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("adjoint table upload: ") + hipGetErrorString(e));

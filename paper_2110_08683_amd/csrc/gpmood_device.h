@@ -580,22 +580,20 @@ struct BatchTabs {
 
 // Arguments of the stage adjoint: A carries U^n, U_s, the frozen final orders of
 // the forward stage (A.order), dt and the weights; lam_* are [4][ny][nx] in the
-// state precision.  slots: the per-face contributions to the stencil cells, one
-// slot per (face direction, side, stencil offset) on the grid with 4 ghost layers
-// ([kAdjSlots][4][ny+8][nx+8], state precision), each (slot, cell) written by
-// exactly one face; dl64: the FP64 derivative of the compact weight table with
-// respect to ell; dl_partial holds one dL/d(ell) partial per block of the face
-// kernel.
+// state precision.  gface: one record per face, the adjoints of both sides'
+// quarter accumulators (64 values, state precision) in planes
+// [direction][64][ny+1][nx+1], written by the face kernel and gathered by the
+// cells of the faces' stencils; dl64: the FP64 derivative of the compact weight
+// table with respect to ell; dl_partial holds one dL/d(ell) partial per block of
+// the face kernel.
 constexpr int kAdjOffsets = 25;  // offsets (da, db) with |da| + |db| <= 3
-constexpr int kAdjSlots = 4 * kAdjOffsets;
-constexpr int kAdjGhost = 4;
 template <typename real>
 struct AdjArgs {
     StageArgs<real> A;
     const real *lam_out;
     real *lam_Us;
     real *lam_Un;
-    real *slots;
+    real *gface;
     const double *dl64;
     double *dl_partial;
 };
