@@ -232,7 +232,9 @@ def run_batch(steps, warmup):
 def run_adjoint(steps, every):
     """Reverse-mode rollout: 512^2 vortex + Gaussian density bump on [0,10]^2,
     periodic, GP-MOOD7 FP32, loss = sum over the middle quarter of rho^2 dx dy,
-    gradient with respect to the initial state and ell, checkpoint every `every`."""
+    gradient with respect to the initial state and ell; timed with checkpoints
+    every `every` steps (the backward recomputes each segment) and with the whole
+    tape kept (no recomputation)."""
     import torch
 
     import gpmood_inputs as gi
@@ -243,27 +245,34 @@ def run_adjoint(steps, every):
     U0 = torch.tensor(gi.vortex_bump(n, n, seed=5), dtype=torch.float32, device="cuda:0").requires_grad_(True)
     ell = torch.tensor(g.ell, dtype=torch.float64, requires_grad=True)
     a, b = n // 4, 3 * n // 4
-    # warm-up (library and allocator) on a short rollout
-    UT = rollout(g, U0, 2, cfl=CFL, checkpoint_every=every, ell=ell)
-    ((UT[0, a:b, a:b].double() ** 2).sum() * (10.0 / n) ** 2).backward()
-    U0.grad = None
-    ell.grad = None
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    UT = rollout(g, U0, steps, cfl=CFL, checkpoint_every=every, ell=ell)
-    loss = (UT[0, a:b, a:b].double() ** 2).sum() * (10.0 / n) ** 2
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    loss.backward()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    gn = float(U0.grad[0].double().norm())
+    out = {"workload": "512^2 isentropic vortex + Gaussian density bump (seed 5) on [0,10]^2, periodic, "
+                       "GP-MOOD7 FP32, CFL 0.8, loss = sum_box rho^2 dx dy", "steps": steps}
+    grads = []
+    for mode, ev in (("checkpointed", every), ("taped", 0)):
+        # warm-up (library and allocator) on a short rollout
+        UT = rollout(g, U0, 2, cfl=CFL, checkpoint_every=ev, ell=ell)
+        ((UT[0, a:b, a:b].double() ** 2).sum() * (10.0 / n) ** 2).backward()
+        U0.grad = None
+        ell.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        UT = rollout(g, U0, steps, cfl=CFL, checkpoint_every=ev, ell=ell)
+        loss = (UT[0, a:b, a:b].double() ** 2).sum() * (10.0 / n) ** 2
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        grads.append(U0.grad.detach().clone())
+        out[mode] = {"checkpoint_every": ev, "forward_ms_per_step": 1e3 * (t1 - t0) / steps,
+                     "backward_ms_per_step": 1e3 * (t2 - t1) / steps, "backward_over_forward": (t2 - t1) / (t1 - t0),
+                     "loss": float(loss.detach()), "grad_rho0_norm": float(U0.grad[0].double().norm()),
+                     "dL_dell": float(ell.grad)}
+        U0.grad = None
+        ell.grad = None
+    out["taped_equals_checkpointed"] = bool(torch.equal(grads[0], grads[1]))
     g.close()
-    return {"workload": "512^2 isentropic vortex + Gaussian density bump (seed 5) on [0,10]^2, periodic, "
-                        "GP-MOOD7 FP32, CFL 0.8, loss = sum_box rho^2 dx dy", "steps": steps,
-            "checkpoint_every": every, "forward_ms_per_step": 1e3 * (t1 - t0) / steps,
-            "backward_ms_per_step": 1e3 * (t2 - t1) / steps, "backward_over_forward": (t2 - t1) / (t1 - t0),
-            "loss": float(loss), "grad_rho0_norm": gn, "dL_dell": float(ell.grad)}
+    return out
 
 
 def run_3d(steps, warmup, n=384):
@@ -634,7 +643,8 @@ def main():
     if a.adjoint_steps > 0:
         print(f"[bench] adjoint rollout {a.adjoint_steps} steps", file=sys.stderr, flush=True)
         line["adjoint"] = run_adjoint(a.adjoint_steps, 20)
-        print(f"[bench] adjoint done: backward/forward {line['adjoint']['backward_over_forward']:.2f}",
+        print(f"[bench] adjoint done: backward/forward {line['adjoint']['checkpointed']['backward_over_forward']:.2f} "
+              f"checkpointed, {line['adjoint']['taped']['backward_over_forward']:.2f} taped",
               file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)

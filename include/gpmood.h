@@ -299,6 +299,14 @@ gpm_status gpm_bind_adjoint(gpm_ctx *ctx, void *adj_work);
 gpm_status gpm_stage_vjp(gpm_ctx *ctx, int s, const void *Un, const void *Us, const void *order, double dt,
                          const void *lam_out, void *lam_Us, void *lam_Un, double *dL_dell);
 
+/* gpm_stage_vjp without a host round trip: the stage's dL/d(ell) contribution is
+   added, in stream order, to the FP64 value at device address dl_dev (8-byte
+   aligned, caller-owned, read back when the caller chooses), so that a backward
+   sweep of many stages never synchronises.  Same inputs, outputs and errors as
+   gpm_stage_vjp, plus GPM_EINVAL for a NULL or misaligned dl_dev. */
+gpm_status gpm_stage_vjp_acc(gpm_ctx *ctx, int s, const void *Un, const void *Us, const void *order, double dt,
+                             const void *lam_out, void *lam_Us, void *lam_Un, void *dl_dev);
+
 /* ---------------------------------------------------------------------------
    Batched ensemble: many independent problems of uneven size advanced
    together.  Each problem is a 2D grid of its own size and boundary conditions;

@@ -5,8 +5,11 @@ single-problem context `g` (GPMood): the forward advances U0 by nsteps SSP-RK3
 steps on the GPU and keeps the state every `checkpoint_every` steps; the backward
 recomputes each segment from its checkpoint (keeping that segment's stage inputs
 and final cell orders, with the dt recorded in the forward, which the
-recomputation must reproduce bit for bit) and runs gpm_stage_vjp stage by stage in
-reverse.  The cell orders and every dt are those of the forward, held fixed (the
+recomputation must reproduce bit for bit) and runs the stage adjoint stage by
+stage in reverse.  With checkpoint_every = 0 the forward keeps every stage's
+inputs and orders instead (three states and three order masks per step: 50 MB a
+step at 1024^2 in FP32) and the backward recomputes nothing.  The backward
+accumulates dL/d(ell) on the device (gpm_stage_vjp_acc) and reads it once.  The cell orders and every dt are those of the forward, held fixed (the
 detection and the CFL reduction are not differentiated).  The stage adjoint is
 deterministic, so a backward gives the same bits every time.  Besides dL/dU0 the backward returns
 dL/d(ell) through the GP weights (as the gradient of the `ell` input).
@@ -26,13 +29,19 @@ class _Rollout(torch.autograd.Function):
         U = U0.detach().to(device=g.device, dtype=g.dtype).contiguous().clone()
         checkpoints = []
         dts = []
+        tape = []
         with torch.cuda.stream(g.stream):
             for n in range(ctx.nsteps):
-                if n % ctx.every == 0:
-                    checkpoints.append(U.clone())
-                U, dt, _, _ = _step(g, U, ctx.cfl, keep=False)
+                if ctx.every == 0:
+                    U, dt, stages, orders = _step(g, U, ctx.cfl, keep=True)
+                    tape.append((dt, stages, orders))
+                else:
+                    if n % ctx.every == 0:
+                        checkpoints.append(U.clone())
+                    U, dt, _, _ = _step(g, U, ctx.cfl, keep=False)
                 dts.append(dt)
         ctx.checkpoints = checkpoints
+        ctx.tape = tape
         ctx.dts = dts
         return U
 
@@ -40,29 +49,41 @@ class _Rollout(torch.autograd.Function):
     def backward(ctx, lam_T):
         g = ctx.g
         lam = lam_T.detach().to(device=g.device, dtype=g.dtype).contiguous().clone()
-        dl_dell = 0.0
         with torch.cuda.stream(g.stream):
-            nseg = len(ctx.checkpoints)
-            for seg in reversed(range(nseg)):
-                n0 = seg * ctx.every
-                n1 = min(ctx.nsteps, n0 + ctx.every)
-                # recompute the segment, keeping every stage's inputs and orders
-                U = ctx.checkpoints[seg].clone()
-                tape = []
-                for n in range(n0, n1):
-                    U, dt, stages, orders = _step(g, U, ctx.cfl, keep=True, dt_forward=ctx.dts[n])
-                    tape.append((dt, stages, orders))
-                for dt, (Un, U1, U2), (o0, o1, o2) in reversed(tape):
-                    lam_n = torch.zeros_like(lam)
-                    l2 = torch.empty_like(lam)
-                    dl_dell += g.gpm_stage_vjp(2, Un, U2, o2, dt, lam, l2, lam_n)
-                    l1 = torch.empty_like(lam)
-                    dl_dell += g.gpm_stage_vjp(1, Un, U1, o1, dt, l2, l1, lam_n)
-                    l0 = torch.empty_like(lam)
-                    dl_dell += g.gpm_stage_vjp(0, Un, Un, o0, dt, l1, l0, lam_n)
-                    lam = l0
-        grad_ell = torch.tensor(dl_dell, dtype=torch.float64)
+            dl = torch.zeros(1, dtype=torch.float64, device=g.device)
+            if ctx.every == 0:
+                lam = _reverse(g, ctx.tape, lam, dl)
+            else:
+                for seg in reversed(range(len(ctx.checkpoints))):
+                    n0 = seg * ctx.every
+                    n1 = min(ctx.nsteps, n0 + ctx.every)
+                    # recompute the segment, keeping every stage's inputs and orders
+                    U = ctx.checkpoints[seg].clone()
+                    tape = []
+                    for n in range(n0, n1):
+                        U, dt, stages, orders = _step(g, U, ctx.cfl, keep=True, dt_forward=ctx.dts[n])
+                        tape.append((dt, stages, orders))
+                    lam = _reverse(g, tape, lam, dl)
+            grad_ell = dl.to("cpu").reshape(())
+        ctx.tape = None
         return lam, grad_ell, None, None, None, None
+
+
+def _reverse(g, tape, lam, dl):
+    """Stage adjoints of the taped steps in reverse order, from lam = dL/dU after the
+    last of them; dL/d(ell) is added to the device scalar dl.  Returns dL/dU before
+    the first."""
+    import torch
+    for dt, (Un, U1, U2), (o0, o1, o2) in reversed(tape):
+        lam_n = torch.zeros_like(lam)
+        l2 = torch.empty_like(lam)
+        g.gpm_stage_vjp_acc(2, Un, U2, o2, dt, lam, l2, lam_n, dl)
+        l1 = torch.empty_like(lam)
+        g.gpm_stage_vjp_acc(1, Un, U1, o1, dt, l2, l1, lam_n, dl)
+        l0 = torch.empty_like(lam)
+        g.gpm_stage_vjp_acc(0, Un, Un, o0, dt, l1, l0, lam_n, dl)
+        lam = l0
+    return lam
 
 
 def _step(g, Un, cfl, keep, dt_forward=None):
@@ -94,6 +115,7 @@ def _step(g, Un, cfl, keep, dt_forward=None):
 
 def rollout(g, U0, nsteps, cfl=0.8, checkpoint_every=20, ell=None):
     """Differentiable nsteps-step rollout of context g from U0 (torch (4, ny, nx)).
+    checkpoint_every = 0 keeps the whole tape (no recomputation in the backward).
 
     `ell` (a 0-dim tensor, default the context's length scale) receives dL/d(ell);
     its value must equal the context's ell (the weights are built by set_scheme).

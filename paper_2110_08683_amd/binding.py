@@ -28,7 +28,7 @@ EXPORTS = ("gpm_create", "gpm_set_scheme", "gpm_workspace_size", "gpm_bind", "gp
            "gpm_step", "gpm_troubled_counts", "gpm_get_order_mask", "gpm_totals", "gpm_totals_dev",
            "gpm_totals_static",
            "gpm_set_tuning", "gpm_instrument", "gpm_instrument_read", "gpm_cascade_stats", "gpm_order_ptr", "gpm_adjoint_workspace_size",
-           "gpm_bind_adjoint", "gpm_stage_vjp",
+           "gpm_bind_adjoint", "gpm_stage_vjp", "gpm_stage_vjp_acc",
            "gpm_batch_create",
            "gpm_batch_set_scheme", "gpm_batch_workspace_size", "gpm_batch_bind", "gpm_batch_set_tuning",
            "gpm_batch_set_tuning_per_problem", "gpm_batch_autotune",
@@ -105,6 +105,7 @@ def lib():
         "gpm_adjoint_workspace_size": ([ctxp, ctypes.POINTER(ctypes.c_size_t)], st),
         "gpm_bind_adjoint": ([ctxp, vp], st),
         "gpm_stage_vjp": ([ctxp, ctypes.c_int, vp, vp, vp, ctypes.c_double, vp, vp, vp, dp], st),
+        "gpm_stage_vjp_acc": ([ctxp, ctypes.c_int, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp], st),
         "gpm_batch_create": ([ctypes.c_int, ctypes.POINTER(gpm_grid), ctypes.c_int, vp, ctypes.POINTER(ctxp)], st),
         "gpm_batch_set_scheme": ([ctxp, ctypes.POINTER(gpm_scheme)], st),
         "gpm_batch_workspace_size": ([ctxp, ctypes.POINTER(ctypes.c_size_t)], st),
@@ -361,6 +362,21 @@ class GPMood:
                                         vp(lam_Un.data_ptr() if lam_Un is not None else 0),
                                         ctypes.byref(d) if want_dell else None))
         return d.value if want_dell else None
+
+    def gpm_stage_vjp_acc(self, s, Un, Us, order, dt, lam_out, lam_Us, lam_Un, dl_dev):
+        """Stage adjoint adding dL/d(ell) into the float64 device tensor dl_dev (one
+        element), in stream order, without synchronising."""
+        self.bind_adjoint()
+        for t in (Us, lam_out, lam_Us) + (() if s == 0 else (Un,)) + (() if lam_Un is None else (lam_Un,)):
+            assert t.dtype == self.dtype and t.is_contiguous() and t.numel() == 4 * self.nx * self.ny
+        assert order.dtype == self.torch.uint8 and order.numel() == self.nx * self.ny
+        assert dl_dev.dtype == self.torch.float64 and dl_dev.numel() >= 1 and dl_dev.is_cuda
+        vp = ctypes.c_void_p
+        self._check(lib().gpm_stage_vjp_acc(self.ctx, int(s), vp(Un.data_ptr() if Un is not None else 0),
+                                            vp(Us.data_ptr()), vp(order.data_ptr()), float(dt),
+                                            vp(lam_out.data_ptr()), vp(lam_Us.data_ptr()),
+                                            vp(lam_Un.data_ptr() if lam_Un is not None else 0),
+                                            vp(dl_dev.data_ptr())))
 
     def gpm_set_tuning(self, passes_per_check=4, rows_per_wave=12, tail_threshold=32):
         self._check(lib().gpm_set_tuning(self.ctx, int(passes_per_check), int(rows_per_wave), int(tail_threshold)))

@@ -554,7 +554,7 @@ gpm_status gpm_order_ptr(const gpm_ctx *c, void **order_dev)
 template <typename real>
 static gpm_status stage_vjp(gpm_ctx *c, const Weights<real> &W, int s, const void *Un, const void *Us,
                             const void *order, double dt, const void *lam_out, void *lam_Us, void *lam_Un,
-                            double *dL_dell)
+                            double *dL_dell, double *dl_dev)
 {
     AdjArgs<real> J;
     fill_args(c, W, J.A);
@@ -577,7 +577,7 @@ static gpm_status stage_vjp(gpm_ctx *c, const Weights<real> &W, int s, const voi
     const size_t nft = nfaces_x(c) + nfaces_y(c);
     int nblk = (int)((nft + 127) / 128);
     if (nblk > kTotBlocks * 8) nblk = kTotBlocks * 8;
-    e = launch_stage_vjp<real>(J, nblk, &c->ctl->totals[0], c->stream);
+    e = launch_stage_vjp<real>(J, nblk, dl_dev ? dl_dev : &c->ctl->totals[0], dl_dev != nullptr, c->stream);
     if (e != hipSuccess) return fail(c, GPM_EHIP, std::string("stage adjoint: ") + hipGetErrorString(e));
     if (dL_dell) {
         double d = 0.0;
@@ -590,8 +590,8 @@ static gpm_status stage_vjp(gpm_ctx *c, const Weights<real> &W, int s, const voi
 
 extern "C" {
 
-gpm_status gpm_stage_vjp(gpm_ctx *c, int s, const void *Un, const void *Us, const void *order, double dt,
-                         const void *lam_out, void *lam_Us, void *lam_Un, double *dL_dell)
+static gpm_status stage_vjp_checked(gpm_ctx *c, int s, const void *Un, const void *Us, const void *order, double dt,
+                                    const void *lam_out, void *lam_Us, void *lam_Un, double *dL_dell, double *dl_dev)
 {
     if (!c) return GPM_EINVAL;
     if (!c->have_scheme) return fail(c, GPM_ESTATE, "no scheme set");
@@ -606,8 +606,23 @@ gpm_status gpm_stage_vjp(gpm_ctx *c, int s, const void *Un, const void *Us, cons
         return fail(c, GPM_EUNSUPPORTED, "the stage adjoint differentiates the HLLC scheme only");
     if (c->grid.slit != 0) return fail(c, GPM_EUNSUPPORTED, "the stage adjoint has no inflow slit");
     if (!c->adj) return fail(c, GPM_ESTATE, "no adjoint workspace bound (gpm_bind_adjoint)");
-    return c->prec == GPM_F64 ? stage_vjp<double>(c, c->w64, s, Un, Us, order, dt, lam_out, lam_Us, lam_Un, dL_dell)
-                              : stage_vjp<float>(c, c->w32, s, Un, Us, order, dt, lam_out, lam_Us, lam_Un, dL_dell);
+    return c->prec == GPM_F64
+               ? stage_vjp<double>(c, c->w64, s, Un, Us, order, dt, lam_out, lam_Us, lam_Un, dL_dell, dl_dev)
+               : stage_vjp<float>(c, c->w32, s, Un, Us, order, dt, lam_out, lam_Us, lam_Un, dL_dell, dl_dev);
+}
+
+gpm_status gpm_stage_vjp(gpm_ctx *c, int s, const void *Un, const void *Us, const void *order, double dt,
+                         const void *lam_out, void *lam_Us, void *lam_Un, double *dL_dell)
+{
+    return stage_vjp_checked(c, s, Un, Us, order, dt, lam_out, lam_Us, lam_Un, dL_dell, nullptr);
+}
+
+gpm_status gpm_stage_vjp_acc(gpm_ctx *c, int s, const void *Un, const void *Us, const void *order, double dt,
+                             const void *lam_out, void *lam_Us, void *lam_Un, void *dl_dev)
+{
+    if (!c) return GPM_EINVAL;
+    if (!dl_dev || ((uintptr_t)dl_dev & 7u)) return fail(c, GPM_EINVAL, "dl_dev: NULL or not 8-byte aligned");
+    return stage_vjp_checked(c, s, Un, Us, order, dt, lam_out, lam_Us, lam_Un, nullptr, (double *)dl_dev);
 }
 
 gpm_status gpm_adjoint_workspace_size(const gpm_ctx *c, size_t *bytes)

@@ -653,10 +653,11 @@ __global__ __launch_bounds__(256, sizeof(real) == 4 ? 3 : 2) void k_adj_cells(co
     }
 }
 
-// Fixed-order sum of the per-block partials into *out (one block of 256 threads):
-// thread t sums the contiguous chunk t in order, then a pairwise tree in LDS.  The
-// order does not depend on timing, so the result is the same on every run.
-__global__ __launch_bounds__(256) void k_adj_dl_final(const double *partial, int n, double *out)
+// Fixed-order sum of the per-block partials into *out, or added to *out when
+// accumulate is set (one block of 256 threads): thread t sums the contiguous
+// chunk t in order, then a pairwise tree in LDS.  The order does not depend on
+// timing, so the result is the same on every run.
+__global__ __launch_bounds__(256) void k_adj_dl_final(const double *partial, int n, double *out, int accumulate)
 {
     __shared__ double red[256];
     const int t = threadIdx.x;
@@ -670,21 +671,21 @@ __global__ __launch_bounds__(256) void k_adj_dl_final(const double *partial, int
         if (t < h) red[t] += red[t + h];
         __syncthreads();
     }
-    if (t == 0) *out = red[0];
+    if (t == 0) *out = accumulate ? *out + red[0] : red[0];
 }
 
 template <typename real>
-hipError_t launch_stage_vjp(const AdjArgs<real> &J, int nblk_faces, double *dl_out, hipStream_t st)
+hipError_t launch_stage_vjp(const AdjArgs<real> &J, int nblk_faces, double *dl_out, bool accumulate, hipStream_t st)
 {
     const size_t n = (size_t)J.A.nx * J.A.ny;
     hipLaunchKernelGGL(k_adj_faces<real>, dim3(nblk_faces), dim3(128), 0, st, J);
     const dim3 tiles((unsigned)((J.A.nx + kTile - 1) / kTile), (unsigned)((J.A.ny + kTile - 1) / kTile));
     hipLaunchKernelGGL(k_adj_cells<real>, tiles, dim3(kTile * kTile), 0, st, J);
-    hipLaunchKernelGGL(k_adj_dl_final, dim3(1), dim3(256), 0, st, J.dl_partial, nblk_faces, dl_out);
+    hipLaunchKernelGGL(k_adj_dl_final, dim3(1), dim3(256), 0, st, J.dl_partial, nblk_faces, dl_out, (int)accumulate);
     return hipGetLastError();
 }
 
-template hipError_t launch_stage_vjp<float>(const AdjArgs<float> &, int, double *, hipStream_t);
-template hipError_t launch_stage_vjp<double>(const AdjArgs<double> &, int, double *, hipStream_t);
+template hipError_t launch_stage_vjp<float>(const AdjArgs<float> &, int, double *, bool, hipStream_t);
+template hipError_t launch_stage_vjp<double>(const AdjArgs<double> &, int, double *, bool, hipStream_t);
 
 }  // namespace gpm

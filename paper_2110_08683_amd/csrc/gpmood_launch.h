@@ -39,7 +39,7 @@ hipError_t launch_batch_dt(const BatchTabs<real> &B, int ndt_blocks, const Casca
 hipError_t launch_batch_status(const Cascade *casc, int nprob, int *iters, double *dts, hipStream_t st);
 hipError_t launch_batch_stamp_restart(const Cascade *casc, int nprob, hipStream_t st);
 template <typename real>
-hipError_t launch_stage_vjp(const AdjArgs<real> &J, int nblk_faces, double *dl_out, hipStream_t st);
+hipError_t launch_stage_vjp(const AdjArgs<real> &J, int nblk_faces, double *dl_out, bool accumulate, hipStream_t st);
 
 }  // namespace gpm
 

@@ -259,6 +259,61 @@ def test_adjoint_is_bitwise_deterministic(torch_cuda, prec):
     g.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_taped_rollout_equals_checkpointed(torch_cuda, prec):
+    """Keeping the whole tape (checkpoint_every = 0) and recomputing segments from
+    checkpoints run the same stage adjoints on the same inputs: the same bits for
+    dL/dU0 and dL/d(ell)."""
+    torch = torch_cuda
+    from paper_2110_08683_amd import GPMood
+    from paper_2110_08683_amd.adjoint import rollout
+    n, nsteps = 80, 7
+    _note(f"taped vs checkpointed rollout {prec} {n}^2 quadrants {nsteps} steps")
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    U0 = gi.quadrants(n, n, seed=13)
+    g = GPMood(n, n, bc=(1, 1), prec=prec, cascade=(3, 2, 1, 0), device="cuda:0")
+    grads = []
+    for every in (3, 0):
+        U0_d = _dev(torch, U0, dtype).requires_grad_(True)
+        ell = torch.tensor(g.ell, dtype=torch.float64, requires_grad=True)
+        UT = rollout(g, U0_d, nsteps, cfl=0.8, checkpoint_every=every, ell=ell)
+        ((UT[0].double() ** 2).sum() / n ** 2).backward()
+        grads.append((U0_d.grad.cpu().numpy().copy(), float(ell.grad)))
+    assert np.array_equal(grads[0][0], grads[1][0])
+    assert grads[0][1] == grads[1][1]
+    g.close()
+
+
+def test_stage_vjp_acc_adds_the_ell_term_on_the_device(torch_cuda):
+    """gpm_stage_vjp_acc gives gpm_stage_vjp's dL/dU_s bit for bit and adds its
+    dL/d(ell) to a device scalar (here starting at 1.5), in stream order."""
+    torch = torch_cuda
+    from paper_2110_08683_amd import GPMood
+    from paper_2110_08683_amd.binding import GpmError
+    n = 40
+    _note(f"stage vjp acc f64 {n}^2")
+    g = GPMood(n, n, bc=(1, 1), prec="f64", cascade=(3, 2, 1, 0), device="cuda:0")
+    rng = np.random.default_rng(3)
+    U = _dev(torch, gi.density_wave(n, n), torch.float64)  # smooth: every face keeps the top order
+    lam = _dev(torch, rng.standard_normal((4, n, n)), torch.float64)
+    order = torch.full((n, n), 3, dtype=torch.uint8, device="cuda:0")
+    dt = 2e-3
+    a = torch.empty_like(U)
+    la = torch.zeros_like(U)
+    dl_host = g.gpm_stage_vjp(1, U, U, order, dt, lam, a, la)
+    b = torch.empty_like(U)
+    lb = torch.zeros_like(U)
+    dl_dev = torch.full((1,), 1.5, dtype=torch.float64, device="cuda:0")
+    g.gpm_stage_vjp_acc(1, U, U, order, dt, lam, b, lb, dl_dev)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(a).all()) and np.isfinite(dl_host) and dl_host != 0.0
+    assert torch.equal(a, b) and torch.equal(la, lb)
+    assert float(dl_dev.cpu()[0]) == 1.5 + dl_host
+    with pytest.raises((GpmError, AssertionError)):
+        g.gpm_stage_vjp_acc(1, U, U, order, dt, lam, b, lb, torch.zeros(1, dtype=torch.float32, device="cuda:0"))
+    g.close()
+
+
 def test_rollout_gradient_with_lowered_cells_vs_oracle_fd(torch_cuda):
     """A quadrant rollout in which the forward lowers cells (48^2, 7 steps,
     checkpoints every 3, FP64): dL/d(rho^0) in random density directions against
