@@ -37,6 +37,7 @@ int dt_blocks(const gpm_ctx *c)
     return (int)(b < 1 ? 1 : b);
 }
 
+
 }  // namespace
 
 struct gpm_batch {
@@ -55,6 +56,7 @@ struct gpm_batch {
     Cascade *casc = nullptr;    // [nprob]
     int *blk = nullptr;         // [nprob + 1]
     int *dblk = nullptr;        // [nprob + 1]
+    int *plan = nullptr;        // [2][nprob + 1] (written on the device each cascade pass)
     int *st_iters = nullptr;    // [nprob]
     double *st_dt = nullptr;    // [nprob]
     int nfp = 0, ndt = 0;
@@ -85,7 +87,7 @@ static gpm_status bfail(gpm_batch *b, gpm_status st, const std::string &msg)
 // workspace, then the tables.
 struct BatchLayout {
     std::vector<size_t> state_off, work_off;
-    size_t args, pout, casc, blk, dblk, iters, dts, total;
+    size_t args, pout, casc, blk, dblk, plan, iters, dts, total;
 };
 
 static BatchLayout batch_layout(const gpm_batch *b)
@@ -110,6 +112,8 @@ static BatchLayout batch_layout(const gpm_batch *b)
     o = align_up(o + (size_t)(b->nprob + 1) * sizeof(int));
     L.dblk = o;
     o = align_up(o + (size_t)(b->nprob + 1) * sizeof(int));
+    L.plan = o;
+    o = align_up(o + 2 * (size_t)(b->nprob + 1) * sizeof(int));
     L.iters = o;
     o = align_up(o + (size_t)b->nprob * sizeof(int));
     L.dts = o;
@@ -169,8 +173,10 @@ static gpm_status build_tables(gpm_batch *b)
         C.clist[0] = c->clist[0];
         C.clist[1] = c->clist[1];
         C.ctl = c->ctl;
-        C.tail_thr = 0;
-        C.back_thr = 0x7fffffff;  // one workgroup per problem runs the whole cascade
+        // multi-block passes while the previous evaluation left more than
+        // tail_threshold troubled cells, then one workgroup per problem to the end
+        C.tail_thr = c->tail_threshold;
+        C.back_thr = 0x7fffffff;
         blk[p + 1] = blk[p] + fp_blocks(c, c->rows);
         dblk[p + 1] = dblk[p] + dt_blocks(c);
     }
@@ -212,6 +218,7 @@ static BatchTabs<real> tabs(const gpm_batch *b, int rot, int s)
     B.casc = b->casc;
     B.blk = b->blk;
     B.dblk = b->dblk;
+    B.plan = b->plan;
     B.nprob = b->nprob;
     B.iso = b->iso;
     B.walls = b->walls;
@@ -386,6 +393,7 @@ gpm_status gpm_batch_bind(gpm_batch *b, void *mem)
     b->casc = (Cascade *)(b->mem + L.casc);
     b->blk = (int *)(b->mem + L.blk);
     b->dblk = (int *)(b->mem + L.dblk);
+    b->plan = (int *)(b->mem + L.plan);
     b->st_iters = (int *)(b->mem + L.iters);
     b->st_dt = (double *)(b->mem + L.dts);
     b->cur = 0;

@@ -572,6 +572,7 @@ struct BatchTabs {
     const Cascade *casc;
     const int *blk;
     const int *dblk;
+    int *plan;  // [2][nprob + 1] work-block offsets of the batch's multi-block cascade passes
     int nprob;
     int iso;     // every problem's A.iso is 1
     int walls;   // some problem has a reflecting axis

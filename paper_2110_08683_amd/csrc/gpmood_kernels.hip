@@ -119,7 +119,7 @@ __device__ __forceinline__ void claim_after_lowering(const StageArgs<real> &A, c
 // One wavefront's strip (tile wid of the problem) of the first pass; ring is the
 // wavefront's LDS ring.  ISO: A.iso is 1 (the y states read the x weights).
 // A lowered cell is only appended to P.clist (count P.ccount); its claims are
-// made after the pass (k_claims_first, or k_tail_batch in a batch), which keeps
+// made after the pass (k_claims_first, or k_claims_first_batch in a batch), which keeps
 // the claim atomics, and the wait for their results, out of the march.
 template <typename real, int RT, bool ISO, bool HLL, bool BND>
 __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const PassOut &P, int wid,
@@ -1211,29 +1211,91 @@ __global__ __launch_bounds__(64 * WPB, sizeof(real) == 4 ? 2 : 1) void k_first_p
     const StageArgs<real> &A = table_entry(B.args, p);
     const Cascade &C = table_entry(B.casc, p);
     PassOut Q = table_entry(B.pout, p);
-    // lowered cells are listed in clist[0]; k_tail_batch makes their claims
+    // lowered cells are listed in clist[0]; k_claims_first_batch makes their claims
     Q.clist = C.clist[0];
     Q.ccount = &C.ctl->nlow;
     const int wv = threadIdx.x >> 6;
     first_pass_wave<real, RT, ISO, HLL, BND>(A, Q, (blockIdx.x - blk[p]) * WPB + wv, ring_all[wv]);
 }
 
-// Problem p = blockIdx.x makes the claims of the cells its first pass lowered,
-// then runs its whole cascade (no hand-back).
-template <typename real, bool WALLS, bool HLL>
-__global__ __launch_bounds__(kTailThreads) void k_tail_batch(const BatchTabs<real> B)
+// Multi-block cascade passes of a batch.  Before each pass, k_batch_plan sizes
+// every problem's share of the pass (0 when it has no work, or when its previous
+// evaluation left at most tail_thr troubled cells, which then leaves the rest of
+// its cascade to its tail workgroup) and lays the shares end to end: plan[p] is
+// the first work block of problem p, in units of 64 faces (256 threads) and,
+// at plan + nprob + 1, of 64 cells.  The pass kernels have a fixed grid whose
+// blocks stride over these work blocks, so the whole batch's faces and cells of a
+// pass are spread over the GPU however they fall among the problems.  Pass 0 is
+// the claims of the cells the first passes lowered (64 x 4 cells per block).
+constexpr int kBatchPasses = 12;
+constexpr int kBatchFaceGrid = 1024, kBatchCellGrid = 2048;
+
+template <typename real>
+__global__ __launch_bounds__(1024) void k_batch_plan(const BatchTabs<real> B, int k, int *plan)
 {
-    __shared__ TailShared<real> S;
-    const int p = blockIdx.x;
-    const StageArgs<real> &A = table_entry(B.args, p);
-    const Cascade &C = table_entry(B.casc, p);
-    PassOut P = table_entry(B.pout, p);
-    P.stamp = *A.stamp0;
-    const int n = C.ctl->nlow;
-    const int nround = (n + kTailThreads - 1) / kTailThreads;
-    for (int r = 0; r < nround; ++r) {
-        const int t = r * kTailThreads + (int)threadIdx.x;
-        const bool act = t < n;
+    __shared__ int sf[1024], sc[1024];
+    __shared__ int carry[2];
+    if (threadIdx.x == 0) carry[0] = carry[1] = 0;
+    for (int base = 0; base < B.nprob; base += blockDim.x) {
+        const int p = base + (int)threadIdx.x;
+        int df = 0, dc = 0;
+        if (p < B.nprob) {
+            const StageArgs<real> &A = table_entry(B.args, p);
+            const Cascade &C = table_entry(B.casc, p);
+            if (k == 0) {
+                df = (C.ctl->nlow + 255) / 256;
+            } else if (pass_runs(C, k)) {
+                const int capf = (A.nx + 1) * A.ny + A.nx * (A.ny + 1), capc = A.nx * A.ny;
+                const int nf = min(C.ctl->nface[k], capf), nc = min(C.ctl->ncell[k], capc);
+                df = (nf + 63) / 64;
+                dc = (nc + 63) / 64;
+            } else if (C.ctl->ncell[k] > 0) {
+                C.ctl->tail_k0 = k;  // the tail takes over from this pass
+            }
+        }
+        sf[threadIdx.x] = df;
+        sc[threadIdx.x] = dc;
+        __syncthreads();
+        // inclusive scan (Hillis-Steele) of both demands
+        for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+            const int tf = threadIdx.x >= (unsigned)off ? sf[threadIdx.x - off] : 0;
+            const int tc = threadIdx.x >= (unsigned)off ? sc[threadIdx.x - off] : 0;
+            __syncthreads();
+            sf[threadIdx.x] += tf;
+            sc[threadIdx.x] += tc;
+            __syncthreads();
+        }
+        if (p < B.nprob) {
+            plan[p] = carry[0] + sf[threadIdx.x] - df;
+            plan[B.nprob + 1 + p] = carry[1] + sc[threadIdx.x] - dc;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            carry[0] += sf[blockDim.x - 1];
+            carry[1] += sc[blockDim.x - 1];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        plan[B.nprob] = carry[0];
+        plan[2 * B.nprob + 1] = carry[1];
+    }
+}
+
+// The claims of the cells each problem's first pass lowered.
+template <typename real>
+__global__ __launch_bounds__(256) void k_claims_first_batch(const BatchTabs<real> B, const int *plan)
+{
+    cptr<int> pl = (cptr<int>)plan;
+    const int total = pl[B.nprob];
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        const int p = find_problem(pl, B.nprob, w);
+        const StageArgs<real> &A = table_entry(B.args, p);
+        const Cascade &C = table_entry(B.casc, p);
+        PassOut P = table_entry(B.pout, p);
+        P.stamp = *A.stamp0;
+        const int t = (w - pl[p]) * 256 + (int)threadIdx.x;
+        const bool act = t < C.ctl->nlow;
         int i = 0, j = 0;
         if (act) {
             const int c = C.clist[0][t];
@@ -1242,9 +1304,58 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_batch(const BatchTabs<rea
         }
         claim_after_lowering(A, P, i, j, act);
     }
-    __threadfence();  // the claims' counts and lists are read below from device memory
-    __syncthreads();
-    tail_body<WALLS, HLL>(A, C, 1, 1, kMaxPasses, S);
+}
+
+template <typename real, bool WALLS, bool HLL>
+__global__ __launch_bounds__(256) void k_faces_batch(const BatchTabs<real> B, int k, const int *plan)
+{
+    __shared__ real wl[kGtabSize];
+    __shared__ FaceXchg<real> xch[4];
+    cptr<int> pl = (cptr<int>)plan;
+    const int total = pl[B.nprob];
+    int loaded = -1;  // problem whose weights wl holds
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        const int p = find_problem(pl, B.nprob, w);
+        const StageArgs<real> &A = table_entry(B.args, p);
+        const Cascade &C = table_entry(B.casc, p);
+        if (p != loaded) {
+            __syncthreads();  // the previous work block's readers of wl are done
+            load_gtab<256>(A.gtab, wl);
+            __syncthreads();
+            loaded = p;
+        }
+        const int capf = (A.nx + 1) * A.ny + A.nx * (A.ny + 1);
+        const int n = min(C.ctl->nface[k], capf);
+        faces_phase<WALLS, HLL>(A, wl, xch[threadIdx.x >> 6], C.flist[k & 1], n, (w - pl[p]) * 256 + (int)threadIdx.x,
+                                4 * n);
+    }
+}
+
+template <typename real, bool WALLS>
+__global__ __launch_bounds__(64) void k_cells_batch(const BatchTabs<real> B, int k, const int *plan)
+{
+    cptr<int> pl = (cptr<int>)(plan + B.nprob + 1);
+    const int total = pl[B.nprob];
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        const int p = find_problem(pl, B.nprob, w);
+        const StageArgs<real> &A = table_entry(B.args, p);
+        const Cascade &C = table_entry(B.casc, p);
+        const int n = min(C.ctl->ncell[k], A.nx * A.ny);
+        cells_phase<WALLS>(A, C.clist[k & 1], n, (w - pl[p]) * 64 + (int)threadIdx.x, n,
+                           pass_out(C, k, C.ctl->stamp0));
+    }
+}
+
+// Problem p = blockIdx.x runs the rest of its cascade in one workgroup, from the
+// pass the multi-block passes left to it (no hand-back).
+template <typename real, bool WALLS, bool HLL>
+__global__ __launch_bounds__(kTailThreads) void k_tail_batch(const BatchTabs<real> B)
+{
+    __shared__ TailShared<real> S;
+    const int p = blockIdx.x;
+    const StageArgs<real> &A = table_entry(B.args, p);
+    const Cascade &C = table_entry(B.casc, p);
+    tail_body<WALLS, HLL>(A, C, 1, kBatchPasses + 1, kMaxPasses, S);
 }
 
 // Stage start of every problem: counts of evaluation 0 and pass 1, tail state,
@@ -1254,9 +1365,12 @@ __global__ void k_reset_batch(const Cascade *casc, int nprob)
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nprob) return;
     Ctl *ctl = casc[p].ctl;
-    ctl->nface[1] = 0;
-    ctl->ncell[1] = 0;
-    ctl->ntroub[0] = 0;
+    // the counts the first pass and the multi-block passes add to
+    for (int k = 0; k <= kBatchPasses + 1; ++k) {
+        ctl->nface[k] = 0;
+        ctl->ncell[k] = 0;
+        ctl->ntroub[k] = 0;
+    }
     ctl->tail_end = 0;
     ctl->tail_k0 = 0;
     ctl->tail_back = 0;
@@ -1312,6 +1426,24 @@ __global__ void k_batch_status(const Cascade *casc, int nprob, int *iters, doubl
     }
 }
 
+// The cascade of a batch stage after its first pass: the claims of the lowered
+// cells, kBatchPasses multi-block passes, then one workgroup per problem.
+template <typename real, bool WALLS, bool HLL>
+static hipError_t launch_batch_cascade(const BatchTabs<real> &B, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_batch_plan<real>, dim3(1), dim3(1024), 0, st, B, 0, B.plan);
+    hipLaunchKernelGGL(k_claims_first_batch<real>, dim3(kBatchFaceGrid), dim3(256), 0, st, B, (const int *)B.plan);
+    for (int k = 1; k <= kBatchPasses; ++k) {
+        hipLaunchKernelGGL(k_batch_plan<real>, dim3(1), dim3(1024), 0, st, B, k, B.plan);
+        hipLaunchKernelGGL((k_faces_batch<real, WALLS, HLL>), dim3(kBatchFaceGrid), dim3(256), 0, st, B, k,
+                           (const int *)B.plan);
+        hipLaunchKernelGGL((k_cells_batch<real, WALLS>), dim3(kBatchCellGrid), dim3(64), 0, st, B, k,
+                           (const int *)B.plan);
+    }
+    hipLaunchKernelGGL((k_tail_batch<real, WALLS, HLL>), dim3(B.nprob), dim3(kTailThreads), 0, st, B);
+    return hipGetLastError();
+}
+
 // BW: the first-pass build with the boundary handling (some problem has walls).
 template <typename real, bool BW>
 static hipError_t launch_batch_stage_bw(const BatchTabs<real> &B, int top, int nfp_blocks, const Cascade *casc,
@@ -1332,11 +1464,7 @@ static hipError_t launch_batch_stage_bw(const BatchTabs<real> &B, int top, int n
         default: return hipErrorInvalidValue;
         }
         if (!tail) return hipGetLastError();
-        if (B.walls)
-            hipLaunchKernelGGL((k_tail_batch<real, true, true>), dim3(B.nprob), dim3(kTailThreads), 0, st, B);
-        else
-            hipLaunchKernelGGL((k_tail_batch<real, false, true>), dim3(B.nprob), dim3(kTailThreads), 0, st, B);
-        return hipGetLastError();
+        return B.walls ? launch_batch_cascade<real, true, true>(B, st) : launch_batch_cascade<real, false, true>(B, st);
     }
     switch (top * 2 + (B.iso ? 1 : 0)) {
     case 7: hipLaunchKernelGGL((k_first_pass_batch<real, 3, WPB, true, false, BW>), g, t, 0, st, B); break;
@@ -1348,11 +1476,7 @@ static hipError_t launch_batch_stage_bw(const BatchTabs<real> &B, int top, int n
     default: return hipErrorInvalidValue;
     }
     if (!tail) return hipGetLastError();
-    if (B.walls)
-        hipLaunchKernelGGL((k_tail_batch<real, true, false>), dim3(B.nprob), dim3(kTailThreads), 0, st, B);
-    else
-        hipLaunchKernelGGL((k_tail_batch<real, false, false>), dim3(B.nprob), dim3(kTailThreads), 0, st, B);
-    return hipGetLastError();
+    return B.walls ? launch_batch_cascade<real, true, false>(B, st) : launch_batch_cascade<real, false, false>(B, st);
 }
 
 template <typename real>
