@@ -294,6 +294,7 @@ int gpw3_level(int R, double ax_d, double ay_d, double az_d, Gpw3Level *out)
         w[0] = w2[0]; w[1] = w2[1]; w[2] = w2[0];
     }
     out->nq = q * q;
+    std::vector<std::vector<qf>> zq(9);  // R = 2: a face's unnormalised prediction vectors
     for (int f = 0; f < 6; ++f) {
         const int ax = f / 2;
         const qf side = (f & 1) ? (qf)0.5 : (qf)-0.5;
@@ -320,7 +321,37 @@ int gpw3_level(int R, double ax_d, double ay_d, double az_d, Gpw3Level *out)
                 }
                 out->qw64[k] = (double)(w[i1] * w[i2]);
                 out->qw32[k] = (float)(w[i1] * w[i2]);
+                if (R == 2) zq[k] = z;
             }
+        if (R != 2) continue;
+        // parity-basis weights of the four node classes, from the normalised
+        // quad-precision prediction vectors
+        for (int cls = 0; cls < 4; ++cls) {
+            const int k = kPar3Canon[cls];
+            qf zs = 0;
+            for (int m = 0; m < n; ++m) zs += zq[k][m];
+            for (int e = 0; e < kNPar3; ++e) {
+                const Par3 &P = kPar3[e];
+                const bool use = cls == 3 || P.comp == 0 || (cls == 1 && P.comp == 1) || (cls == 2 && P.comp == 2);
+                qf acc = 0;
+                int cnt = 0;
+                for (int s1 = -1; s1 <= 1; s1 += 2)
+                    for (int s2 = -1; s2 <= 1; s2 += 2) {
+                        if ((P.a1 == 0 && s1 < 0) || (P.a2 == 0 && s2 < 0)) continue;
+                        int d[3];
+                        d[ax] = P.dn;
+                        d[t1] = s1 * P.a1;
+                        d[t2] = s2 * P.a2;
+                        const int m = ball_index(d[0], d[1], d[2]);
+                        const int chi = (P.comp == 1 || P.comp == 3 ? s1 : 1) * (P.comp == 2 || P.comp == 3 ? s2 : 1);
+                        acc += (qf)chi * zq[k][m];
+                        ++cnt;
+                    }
+                const qf v = use ? acc / zs / (qf)cnt : (qf)0;
+                out->pz64[f][cls][e] = (double)v;
+                out->pz32[f][cls][e] = (float)v;
+            }
+        }
     }
     return 0;
 }

@@ -36,6 +36,11 @@ struct Gpw3Level {
     float z32[6][9][25];
     double qw64[9];
     float qw32[9];
+    // R = 2: the parity-basis weights of each face's four node classes (kPar3
+    // entries; the orbit averages of the canonical node's prediction vector with
+    // the component's signs), zero where a class does not use the component
+    double pz64[6][4][25];
+    float pz32[6][4][25];
 };
 
 // 3D u2 curvature weights per direction d on the R = 1 ball: [0] centre, [1] the

@@ -34,6 +34,7 @@
 namespace gpm {
 
 constexpr int kZ3 = 6 * 9 * 25;  // weights per radius: [6 faces][9 nodes][25 cells]
+constexpr int kPZ3 = 6 * 4 * kNPar3;  // radius-2 parity weights: [6 faces][4 node classes][25 entries]
 
 template <typename real>
 struct Stage3 {
@@ -54,6 +55,7 @@ struct Stage3 {
     real d[3], gamma, sigma_v, sigma_p, plat_thr, delta;
     const real *z;       // [R - 1][6][9][25]
     const real *qw;      // [R - 1][9]
+    const real *pz;      // [6][4][25]: radius 2 in the parity basis (kPar3)
     real curv[3][4];
     const unsigned *stamp0;
 };
@@ -280,15 +282,177 @@ __global__ __launch_bounds__(128, 1) void k3_faces_top(const Stage3<real> S)
     S.Ff[A][loc] = (uint8_t)((bl ? 1 : 0) | (br ? 2 : 0));
 }
 
+// Radius 2 in the parity basis: one thread per face; per variable, each side's 25
+// ball values are folded into the 25 parity entries of the face axis (kPar3) and
+// the nine node states come from the four node classes' weights: 14 products for
+// the centre, 19 for each pair on a tangential axis, 25 for the four corners (77,
+// against 225 for nine 25-term dot products).  The weights are the orbit
+// averages of the quad-precision prediction vectors; the node states agree with
+// the plain dot products to rounding.
+template <int A>
+__device__ __forceinline__ constexpr int par_member(int e, int s1, int s2)
+{
+    const int t1 = A == 0 ? 1 : 0, t2 = A == 2 ? 1 : 2;
+    int d[3] = {0, 0, 0};
+    d[A] = kPar3[e].dn;
+    d[t1] = s1 * kPar3[e].a1;
+    d[t2] = s2 * kPar3[e].a2;
+    return ball_index(d[0], d[1], d[2]);
+}
+
+template <int A, typename real>
+__device__ __forceinline__ void par3_entries(const real (&q)[25], real (&P)[kNPar3])
+{
+#pragma unroll
+    for (int e = 0; e < kNPar3; ++e) {
+        const int a1 = kPar3[e].a1, a2 = kPar3[e].a2, c = kPar3[e].comp;
+        const real pp = q[par_member<A>(e, 1, 1)];
+        if (a1 == 0 && a2 == 0) {
+            P[e] = pp;
+        } else if (a2 == 0) {
+            const real mp = q[par_member<A>(e, -1, 1)];
+            P[e] = c == 0 ? pp + mp : pp - mp;
+        } else if (a1 == 0) {
+            const real pm = q[par_member<A>(e, 1, -1)];
+            P[e] = c == 0 ? pp + pm : pp - pm;
+        } else {
+            const real mp = q[par_member<A>(e, -1, 1)], pm = q[par_member<A>(e, 1, -1)];
+            const real mm = q[par_member<A>(e, -1, -1)];
+            P[e] = c == 0 ? (pp + mp) + (pm + mm)
+                 : c == 1 ? (pp - mp) + (pm - mm)
+                 : c == 2 ? (pp + mp) - (pm + mm)
+                          : (pp - mp) - (pm - mm);
+        }
+    }
+}
+
+// The nine node states (table order) of one face side from its parity entries.
+template <typename real>
+__device__ __forceinline__ void par3_states(const real (&P)[kNPar3], cptr<real> W, real (&s)[9])
+{
+    real c0 = real(0), a1 = real(0), a2 = real(0), a3 = real(0);
+#pragma unroll
+    for (int e = 0; e < kPar3EE; ++e) {
+        c0 = fma(W[e], P[e], c0);
+        a1 = fma(W[kNPar3 + e], P[e], a1);
+        a2 = fma(W[2 * kNPar3 + e], P[e], a2);
+        a3 = fma(W[3 * kNPar3 + e], P[e], a3);
+    }
+    real b1 = real(0), b3 = real(0);
+#pragma unroll
+    for (int e = kPar3EE; e < kPar3EE + kPar3OE; ++e) {
+        b1 = fma(W[kNPar3 + e], P[e], b1);
+        b3 = fma(W[3 * kNPar3 + e], P[e], b3);
+    }
+    real c2 = real(0), c3 = real(0);
+#pragma unroll
+    for (int e = kPar3EE + kPar3OE; e < kNPar3 - 1; ++e) {
+        c2 = fma(W[2 * kNPar3 + e], P[e], c2);
+        c3 = fma(W[3 * kNPar3 + e], P[e], c3);
+    }
+    const real d3 = W[3 * kNPar3 + kNPar3 - 1] * P[kNPar3 - 1];
+    s[4] = c0;
+    s[1] = a1 + b1;
+    s[7] = a1 - b1;
+    s[3] = a2 + c2;
+    s[5] = a2 - c2;
+    s[0] = (a3 + b3) + (c3 + d3);
+    s[2] = (a3 + b3) - (c3 + d3);
+    s[6] = (a3 - b3) + (c3 - d3);
+    s[8] = (a3 - b3) - (c3 - d3);
+}
+
+// Node states of both sides of face (i, j, k) of axis A (left cell (iL, jL, kL)).
+// IN: both balls lie inside the grid (offsets from the cell index, no mapping).
+template <int A, bool IN, typename real>
+__device__ __forceinline__ void top2_states(const Stage3<real> &S, int i, int j, int k, real (&sl)[9][5],
+                                            real (&sr)[9][5])
+{
+    const size_t plane = (size_t)S.n[0] * S.n[1] * S.n[2];
+    const int iL = i - (A == 0), jL = j - (A == 1), kL = k - (A == 2);
+    const int sy = S.n[0], sz = S.n[0] * S.n[1];
+    const cptr<real> WL = (cptr<real>)S.pz + (2 * A + 1) * 4 * kNPar3;  // + face of the left cell
+    const cptr<real> WR = (cptr<real>)S.pz + (2 * A) * 4 * kNPar3;      // - face of the right cell
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        // one variable's loads at a time: the node states of all five stay live
+        __builtin_amdgcn_sched_barrier(0);
+        const real *U = S.Us + v * plane;
+        // the weights are reloaded (scalar loads) for each variable rather than
+        // held in scalar registers across all five
+        cptr<real> WLv = WL, WRv = WR;
+        asm volatile("" : "+s"(WLv), "+s"(WRv));
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int ci = side == 0 ? iL : i, cj = side == 0 ? jL : j, ck = side == 0 ? kL : k;
+            real q[25], P[kNPar3], st[9];
+            if constexpr (IN) {
+                const real *c0 = U + ((size_t)ck * S.n[1] + cj) * S.n[0] + ci;
+#pragma unroll
+                for (int m = 0; m < 25; ++m) q[m] = c0[kBall[m][2] * sz + kBall[m][1] * sy + kBall[m][0]];
+            } else {
+#pragma unroll
+                for (int m = 0; m < 25; ++m) q[m] = U[cell3(S, ci + kBall[m][0], cj + kBall[m][1], ck + kBall[m][2])];
+            }
+            par3_entries<A>(q, P);
+            par3_states(P, side == 0 ? WLv : WRv, st);
+#pragma unroll
+            for (int n = 0; n < 9; ++n) {
+                if (side == 0) sl[n][v] = st[n];
+                else sr[n][v] = st[n];
+            }
+        }
+    }
+}
+
+template <typename real, int A>
+__global__ __launch_bounds__(128) void k3_faces_top2(const Stage3<real> S)
+{
+    const int m0 = S.n[0] + (A == 0), m1 = S.n[1] + (A == 1), m2 = S.n[2] + (A == 2);
+    const int nfa = m0 * m1 * m2;
+    const int loc = blockIdx.x * blockDim.x + threadIdx.x;
+    if (loc >= nfa) return;
+    const int i = loc % m0, rr = loc / m0, j = rr % m1, k = rr / m1;
+    const int lo[3] = {i - (A == 0), j - (A == 1), k - (A == 2)}, hi[3] = {i, j, k};
+    bool inside = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) inside = inside && lo[d] >= 2 && hi[d] + 2 < S.n[d];
+    real sl[9][5], sr[9][5];
+    if (inside) top2_states<A, true>(S, i, j, k, sl, sr);
+    else top2_states<A, false>(S, i, j, k, sl, sr);
+    const cptr<real> w = (cptr<real>)S.qw + 9;
+    real Fs[5] = {real(0), real(0), real(0), real(0), real(0)};
+    bool bl = false, br = false;
+#pragma unroll
+    for (int n = 0; n < 9; ++n) {
+        real fl[5];
+        bool b1, b2;
+        hllc3(S.gamma, A, sl[n], sr[n], fl, b1, b2);
+        bl = bl || b1;
+        br = br || b2;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Fs[v] = fma(w[n], fl[v], Fs[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) S.F[A][(size_t)v * nfa + loc] = Fs[v];
+    S.Ff[A][loc] = (uint8_t)((bl ? 1 : 0) | (br ? 2 : 0));
+}
+
 template <typename real, int R>
 static void launch_faces_top(const Stage3<real> &S, hipStream_t st)
 {
     for (int a = 0; a < 3; ++a) {
         const long long nfa = (long long)(S.n[0] + (a == 0)) * (S.n[1] + (a == 1)) * (S.n[2] + (a == 2));
         const dim3 g((unsigned)((nfa + 127) / 128)), t(128);
-        if (a == 0) hipLaunchKernelGGL((k3_faces_top<real, R, 0>), g, t, 0, st, S);
-        if (a == 1) hipLaunchKernelGGL((k3_faces_top<real, R, 1>), g, t, 0, st, S);
-        if (a == 2) hipLaunchKernelGGL((k3_faces_top<real, R, 2>), g, t, 0, st, S);
+        if constexpr (R == 2) {
+            if (a == 0) hipLaunchKernelGGL((k3_faces_top2<real, 0>), g, t, 0, st, S);
+            if (a == 1) hipLaunchKernelGGL((k3_faces_top2<real, 1>), g, t, 0, st, S);
+            if (a == 2) hipLaunchKernelGGL((k3_faces_top2<real, 2>), g, t, 0, st, S);
+        } else {
+            if (a == 0) hipLaunchKernelGGL((k3_faces_top<real, R, 0>), g, t, 0, st, S);
+            if (a == 1) hipLaunchKernelGGL((k3_faces_top<real, R, 1>), g, t, 0, st, S);
+            if (a == 2) hipLaunchKernelGGL((k3_faces_top<real, R, 2>), g, t, 0, st, S);
+        }
     }
 }
 
@@ -621,8 +785,8 @@ struct gpm3_ctx {
     bool have_scheme = false;
     gpm_scheme scheme;
     int top = 0, next[4] = {0, 0, 0, 0}, levidx[3] = {0, 0, 0};
-    std::vector<double> z64, qw64;
-    std::vector<float> z32, qw32;
+    std::vector<double> z64, qw64, pz64;
+    std::vector<float> z32, qw32, pz32;
     double curv64[3][4];
     float curv32[3][4];
     char *state = nullptr, *work = nullptr;
@@ -665,7 +829,7 @@ static size_t layout3(const gpm3_ctx *c, size_t off[X_N])
     const size_t sz[X_N] = {c->ncell, 4 * c->ncell, 4 * c->nfaces, 4 * c->nfaces, 4 * c->nfaces, 4 * c->ncell,
                             4 * c->ncell, 5 * e * c->nface[0], 5 * e * c->nface[1], 5 * e * c->nface[2],
                             c->nface[0], c->nface[1], c->nface[2], sizeof(Ctl),
-                            ((size_t)kTot3Blocks * 5 * 2 + 8) * sizeof(double), (size_t)(2 * kZ3 + 2 * 9) * e};
+                            ((size_t)kTot3Blocks * 5 * 2 + 8) * sizeof(double), (size_t)(2 * kZ3 + 2 * 9 + kPZ3) * e};
     size_t o = 0;
     for (int k = 0; k < X_N; ++k) {
         off[k] = o;
@@ -714,6 +878,7 @@ static Stage3<real> args3(gpm3_ctx *c, int s, const void *Un, const void *Us, vo
     S.delta = (real)dm;
     S.z = (const real *)c->wtab;
     S.qw = (const real *)c->wtab + 2 * kZ3;
+    S.pz = (const real *)c->wtab + 2 * kZ3 + 18;
     for (int d = 0; d < 3; ++d)
         for (int k = 0; k < 4; ++k) S.curv[d][k] = sizeof(real) == 8 ? (real)c->curv64[d][k] : (real)c->curv32[d][k];
     S.stamp0 = &c->ctl->stamp0;
@@ -850,13 +1015,15 @@ static gpm_status upload3(gpm3_ctx *c)
 {
     if (!c->wtab || !c->have_scheme) return GPM_OK;
     const size_t e = esz3(c);
-    std::vector<char> buf((2 * kZ3 + 18) * e);
+    std::vector<char> buf((2 * kZ3 + 18 + kPZ3) * e);
     if (e == 8) {
         std::memcpy(buf.data(), c->z64.data(), 2 * kZ3 * 8);
         std::memcpy(buf.data() + 2 * kZ3 * 8, c->qw64.data(), 18 * 8);
+        std::memcpy(buf.data() + (2 * kZ3 + 18) * 8, c->pz64.data(), kPZ3 * 8);
     } else {
         std::memcpy(buf.data(), c->z32.data(), 2 * kZ3 * 4);
         std::memcpy(buf.data() + 2 * kZ3 * 4, c->qw32.data(), 18 * 4);
+        std::memcpy(buf.data() + (2 * kZ3 + 18) * 4, c->pz32.data(), kPZ3 * 4);
     }
     H3(c, hipMemcpyAsync(c->wtab, buf.data(), buf.size(), hipMemcpyHostToDevice, c->stream));
     H3(c, hipStreamSynchronize(c->stream));
@@ -883,6 +1050,8 @@ gpm_status gpm3_set_scheme(gpm3_ctx *c, const gpm_scheme *s)
     c->z32.assign(2 * kZ3, 0.0f);
     c->qw64.assign(18, 0.0);
     c->qw32.assign(18, 0.0f);
+    c->pz64.assign(kPZ3, 0.0);
+    c->pz32.assign(kPZ3, 0.0f);
     for (int R = 1; R <= 2; ++R) {
         bool used = false;
         for (int l = 0; l < s->nlev; ++l) used = used || s->radius[l] == R;
@@ -901,6 +1070,13 @@ gpm_status gpm3_set_scheme(gpm3_ctx *c, const gpm_scheme *s)
             c->qw64[(R - 1) * 9 + k] = L.qw64[k];
             c->qw32[(R - 1) * 9 + k] = L.qw32[k];
         }
+        if (R == 2)
+            for (int f = 0; f < 6; ++f)
+                for (int cls = 0; cls < 4; ++cls)
+                    for (int e = 0; e < kNPar3; ++e) {
+                        c->pz64[((size_t)f * 4 + cls) * kNPar3 + e] = L.pz64[f][cls][e];
+                        c->pz32[((size_t)f * 4 + cls) * kNPar3 + e] = L.pz32[f][cls][e];
+                    }
     }
     Gpw3Curv K;
     if (gpw3_curvature(ell / c->d[0], ell / c->d[1], ell / c->d[2], ell, &K) != 0)

@@ -79,6 +79,41 @@ constexpr int kBall[25][3] = {
 };
 constexpr int kNBall[3] = {1, 7, 25};
 
+// Parity basis of the radius-2 ball seen from a face normal to axis A (normal
+// offset dn, tangential offsets d1, d2 along the face's first and second
+// tangential axes): the cells form orbits under d1 -> -d1 and d2 -> -d2, and entry
+// e is the sum over the orbit of (dn, +-a1, +-a2) with the signs of component c
+// (0: even-even, 1: odd in d1, 2: odd in d2, 3: odd in both).  A node at
+// tangential signs (s1, s2) takes sum_e chi_c(s) W[e] P[e], with W the
+// orbit-averaged weights of the class's canonical node: the 14 even entries come
+// first, then the 5 odd-in-d1, the 5 odd-in-d2 and the one odd-odd entry.
+struct Par3 {
+    int dn, a1, a2, comp;
+};
+constexpr int kNPar3 = 25, kPar3EE = 14, kPar3OE = 5, kPar3EO = 5;
+constexpr Par3 kPar3[kNPar3] = {
+    {-2, 0, 0, 0}, {-1, 0, 0, 0}, {0, 0, 0, 0}, {1, 0, 0, 0}, {2, 0, 0, 0},
+    {-1, 1, 0, 0}, {0, 1, 0, 0}, {1, 1, 0, 0}, {0, 2, 0, 0},
+    {-1, 0, 1, 0}, {0, 0, 1, 0}, {1, 0, 1, 0}, {0, 0, 2, 0},
+    {0, 1, 1, 0},
+    {-1, 1, 0, 1}, {0, 1, 0, 1}, {1, 1, 0, 1}, {0, 2, 0, 1}, {0, 1, 1, 1},
+    {-1, 0, 1, 2}, {0, 0, 1, 2}, {1, 0, 1, 2}, {0, 0, 2, 2}, {0, 1, 1, 2},
+    {0, 1, 1, 3},
+};
+// Node classes of the 3 x 3 tensor nodes (node k = i1 * 3 + i2, i = 0, 1, 2 at
+// tangential coordinate +g, 0, -g): 0 the centre (k = 4), 1 on the first
+// tangential axis (k = 1, 7), 2 on the second (k = 3, 5), 3 the corners (k = 0,
+// 2, 6, 8); canonical nodes 4, 1, 3, 0.
+constexpr int kPar3Canon[4] = {4, 1, 3, 0};
+
+// Ball index of the cell at offset (d[0], d[1], d[2]), -1 if outside the ball.
+constexpr int ball_index(int dx, int dy, int dz)
+{
+    for (int m = 0; m < 25; ++m)
+        if (kBall[m][0] == dx && kBall[m][1] == dy && kBall[m][2] == dz) return m;
+    return -1;
+}
+
 }  // namespace gpm
 
 #endif
