@@ -172,8 +172,9 @@ def batch_sizes():
 def run_batch(steps, warmup):
     """The batched ensemble: every problem a four-quadrant problem with its own seed
     (1000 + k), GP-MOOD7 FP32, one HIP-graph replay per SSP-RK3 step; timed with the
-    default first-pass march length and again, from the same initial states, with
-    the library's autotuned march lengths per size class."""
+    default first-pass march length and cascade threshold and again, from the same
+    initial states, with the library's autotuned march lengths per size class and
+    cascade threshold."""
     import torch
 
     import gpmood_inputs as gi
@@ -189,11 +190,13 @@ def run_batch(steps, warmup):
         if mode == "autotuned":
             t0 = time.perf_counter()
             rows, gain = b.gpm_batch_autotune(CFL, reps=3)
+            tail, tgain = b.gpm_batch_autotune_cascade(CFL, reps=2)
             by_side = {}
             for n, r in zip(sides, rows):
                 by_side[n] = r
             tune = {"seconds": time.perf_counter() - t0, "first_pass_gain": gain,
-                    "rows_per_wave_by_side": {str(n): by_side[n] for n in sorted(by_side)}}
+                    "rows_per_wave_by_side": {str(n): by_side[n] for n in sorted(by_side)},
+                    "cascade_threshold": tail, "stage_gain_of_threshold": tgain}
         b.gpm_batch_step(CFL, warmup, use_graph=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -356,6 +356,17 @@ gpm_status gpm_batch_set_tuning_per_problem(gpm_batch *b, const int *rows_per_wa
    GPM_EINVAL, GPM_ESTATE (not bound or no scheme), GPM_EHIP. */
 gpm_status gpm_batch_autotune(gpm_batch *b, double cfl, int reps, int *rows_out, double *gain);
 
+/* The batch's cascade threshold (the troubled-cell count at or below which a
+   problem's MOOD loop leaves the batch-wide multi-block passes for its own tail
+   workgroup; default 32), chosen on the device among 8, 16, 32, 64, 128 and 256
+   by timing whole stage-0 stages (first pass and cascade, reps timed launches
+   each after one untimed) at the current states' dt; the states are left as they
+   were, and the threshold changes the schedule only (every stage gives the same
+   bits).  tail_out: the choice (applied to the batch); gain: time at the
+   threshold in force before the call over time at the choice.  Errors as
+   gpm_batch_autotune. */
+gpm_status gpm_batch_autotune_cascade(gpm_batch *b, double cfl, int reps, int *tail_out, double *gain);
+
 /* Initial state / current state of problem p (host double SoA [4][ny_p][nx_p]).
    Synchronising. */
 gpm_status gpm_batch_init_state(gpm_batch *b, int p, const double *U_host);

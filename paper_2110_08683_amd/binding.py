@@ -31,7 +31,7 @@ EXPORTS = ("gpm_create", "gpm_set_scheme", "gpm_workspace_size", "gpm_bind", "gp
            "gpm_bind_adjoint", "gpm_stage_vjp", "gpm_stage_vjp_acc",
            "gpm_batch_create",
            "gpm_batch_set_scheme", "gpm_batch_workspace_size", "gpm_batch_bind", "gpm_batch_set_tuning",
-           "gpm_batch_set_tuning_per_problem", "gpm_batch_autotune",
+           "gpm_batch_set_tuning_per_problem", "gpm_batch_autotune", "gpm_batch_autotune_cascade",
            "gpm_batch_init_state", "gpm_batch_get_state", "gpm_batch_step", "gpm_batch_status",
            "gpm_batch_troubled_counts", "gpm_batch_get_order_mask", "gpm_batch_last_error",
            "gpm_batch_destroy", "gpm3_create", "gpm3_set_scheme", "gpm3_workspace_size", "gpm3_bind",
@@ -113,6 +113,7 @@ def lib():
         "gpm_batch_set_tuning": ([ctxp, ctypes.c_int], st),
         "gpm_batch_set_tuning_per_problem": ([ctxp, ctypes.POINTER(ctypes.c_int)], st),
         "gpm_batch_autotune": ([ctxp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp], st),
+        "gpm_batch_autotune_cascade": ([ctxp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp], st),
         "gpm_batch_init_state": ([ctxp, ctypes.c_int, dp], st),
         "gpm_batch_get_state": ([ctxp, ctypes.c_int, dp], st),
         "gpm_batch_step": ([ctxp, ctypes.c_double, ctypes.c_int, ctypes.c_int], st),
@@ -472,6 +473,13 @@ class GPMoodBatch:
         gain = ctypes.c_double()
         self._check(lib().gpm_batch_autotune(self.b, float(cfl), int(reps), arr, ctypes.byref(gain)))
         return [int(x) for x in arr], gain.value
+
+    def gpm_batch_autotune_cascade(self, cfl=0.8, reps=3):
+        """Choose the batch's cascade threshold on the device; returns (threshold, gain)."""
+        t = ctypes.c_int()
+        gain = ctypes.c_double()
+        self._check(lib().gpm_batch_autotune_cascade(self.b, float(cfl), int(reps), ctypes.byref(t), ctypes.byref(gain)))
+        return t.value, gain.value
 
     def autotune(self, cfl=0.8, reps=3, cache=None):
         """Autotuned march lengths with an on-disk cache (JSON file `cache`, keyed by

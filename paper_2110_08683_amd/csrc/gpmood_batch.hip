@@ -277,6 +277,34 @@ static gpm_status time_first_pass(gpm_batch *b, int reps, hipEvent_t e0, hipEven
     return GPM_OK;
 }
 
+// Candidate cascade thresholds (troubled cells at or below which a problem's
+// cascade leaves the batch-wide multi-block passes for its tail workgroup), and
+// the time of `reps` whole batch stage-0 stages (first pass and cascade, after
+// one untimed stage) between two HIP events.  Stage 0 reads the current slot and
+// writes another, so the states are left as they were.
+static const int kTuneTail[] = {8, 16, 32, 64, 128, 256};
+
+template <typename real>
+static gpm_status time_stage0(gpm_batch *b, int reps, hipEvent_t e0, hipEvent_t e1, float *ms)
+{
+    const int top = b->ctx[0]->top;
+    BHIPCHK(b, launch_batch_stage<real>(tabs<real>(b, b->cur, 0), top, b->nfp, b->casc, b->stream));
+    BHIPCHK(b, hipEventRecord(e0, b->stream));
+    for (int r = 0; r < reps; ++r)
+        BHIPCHK(b, launch_batch_stage<real>(tabs<real>(b, b->cur, 0), top, b->nfp, b->casc, b->stream));
+    BHIPCHK(b, hipEventRecord(e1, b->stream));
+    BHIPCHK(b, hipEventSynchronize(e1));
+    BHIPCHK(b, hipEventElapsedTime(ms, e0, e1));
+    b->stages_run += (unsigned long long)reps + 1;
+    return GPM_OK;
+}
+
+static gpm_status set_tail(gpm_batch *b, int tail)
+{
+    for (gpm_ctx *c : b->ctx) c->tail_threshold = tail;
+    return rebuild(b);
+}
+
 extern "C" {
 
 gpm_status gpm_batch_create(int nprob, const gpm_grid *grids, int prec, void *hip_stream, gpm_batch **out)
@@ -502,6 +530,48 @@ gpm_status gpm_batch_autotune(gpm_batch *b, double cfl, int reps, int *rows_out,
         for (int p = 0; p < P; ++p) rows_out[p] = rows[p];
     if (gain) *gain = ttun > 0.f ? (double)tdef / (double)ttun : 1.0;
     return st;
+}
+
+// Choose the cascade threshold of the whole batch (see kTuneTail) by timing whole
+// stage-0 stages at the current states' dt; the problems' states are left as they
+// were.  Like the march length, the threshold changes the schedule only.
+gpm_status gpm_batch_autotune_cascade(gpm_batch *b, double cfl, int reps, int *tail_out, double *gain)
+{
+    if (!b || reps < 1 || reps > 64 || !(cfl > 0.0)) return GPM_EINVAL;
+    if (!b->mem || !b->have_scheme) return bfail(b, GPM_ESTATE, "not bound or no scheme");
+    const int ncand = (int)(sizeof(kTuneTail) / sizeof(int));
+    gpm_status st = stamps_guard(b, (ncand + 2) * (reps + 1));
+    if (st != GPM_OK) return st;
+    const hipError_t de = b->prec == GPM_F64
+                              ? launch_batch_dt<double>(tabs<double>(b, b->cur, 0), b->ndt, b->casc, cfl, b->stream)
+                              : launch_batch_dt<float>(tabs<float>(b, b->cur, 0), b->ndt, b->casc, cfl, b->stream);
+    BHIPCHK(b, de);
+    const int tail0 = b->ctx[0]->tail_threshold;
+    hipEvent_t e0, e1;
+    BHIPCHK(b, hipEventCreate(&e0));
+    BHIPCHK(b, hipEventCreate(&e1));
+    int best = tail0;
+    float tbest = -1.f, tdef = 0.f;
+    for (int i = -1; i < ncand && st == GPM_OK; ++i) {
+        const int cand = i < 0 ? tail0 : kTuneTail[i];  // the current setting first, as the reference
+        st = set_tail(b, cand);
+        float ms = 0.f;
+        if (st == GPM_OK)
+            st = b->prec == GPM_F64 ? time_stage0<double>(b, reps, e0, e1, &ms) : time_stage0<float>(b, reps, e0, e1, &ms);
+        if (st != GPM_OK) break;
+        if (i < 0) tdef = ms;
+        if (tbest < 0.f || ms < tbest) {
+            best = cand;
+            tbest = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == GPM_OK) st = set_tail(b, best);
+    if (st != GPM_OK) return st;
+    if (tail_out) *tail_out = best;
+    if (gain) *gain = tbest > 0.f ? (double)tdef / (double)tbest : 1.0;
+    return GPM_OK;
 }
 
 gpm_status gpm_batch_init_state(gpm_batch *b, int p, const double *U)

@@ -160,3 +160,31 @@ def test_autotuned_batch_is_bitwise_equal(torch_cuda, tmp_path):
     rows2, gain2 = b.autotune(0.8, reps=2, cache=str(tmp_path / "tune.json"))
     assert gain2 is None and rows2 == rows
     b.close()
+
+
+def test_cascade_autotuned_batch_is_bitwise_equal(torch_cuda):
+    """The cascade threshold the autotuner picks changes the schedule only: the
+    tuned batch gives the same bits as the default one (FP64, uneven sizes, graph
+    replay), and its timing stages leave the states unchanged."""
+    from paper_2110_08683_amd import GPMoodBatch
+    sizes = [(64, 64), (96, 80), (128, 128), (200, 160)]
+    _note(f"batch cascade autotune f64 sizes={sizes}")
+    U0s = [gi.quadrants(nx, ny, seed=80 + k) for k, (nx, ny) in enumerate(sizes)]
+    states = []
+    for tuned in (False, True):
+        b = GPMoodBatch(sizes, bc=(1, 1), prec="f64", cascade=(3, 2, 1, 0), device="cuda:0")
+        for k, U0 in enumerate(U0s):
+            b.gpm_batch_init_state(k, U0)
+        b.gpm_batch_step(0.8, 2, use_graph=True)
+        if tuned:
+            before = [b.gpm_batch_get_state(k) for k in range(len(sizes))]
+            tail, gain = b.gpm_batch_autotune_cascade(0.8, reps=2)
+            _note(f"  chosen cascade threshold {tail}, gain over the default {gain:.3f}")
+            assert tail in (8, 16, 32, 64, 128, 256) and gain > 0
+            for k in range(len(sizes)):
+                assert np.array_equal(b.gpm_batch_get_state(k), before[k])
+        b.gpm_batch_step(0.8, 3, use_graph=True)
+        states.append([b.gpm_batch_get_state(k) for k in range(len(sizes))])
+        b.close()
+    for k in range(len(sizes)):
+        assert np.array_equal(states[0][k], states[1][k]), k
