@@ -566,11 +566,11 @@ static gpm_status stage_vjp(gpm_ctx *c, const Weights<real> &W, int s, const voi
     J.lam_out = (const real *)lam_out;
     J.lam_Us = (real *)lam_Us;
     J.lam_Un = (real *)lam_Un;
-    // the adjoint workspace holds the per-face records and the FP64 ell table;
-    // the reduction partials hold the ell terms
+    // the adjoint workspace holds the per-face records, the FP64 ell table and
+    // the per-tile dL/d(ell) partials
     J.gface = (real *)c->adj;
     J.dl64 = (const double *)(c->adj + adj_face_bytes(c));
-    J.dl_partial = c->partial;
+    J.dl_partial = (double *)(c->adj + adj_partial_offset(c));
     hipError_t e = launch_set_dt(c->ctl, dt, c->stream);
     if (e != hipSuccess) return fail(c, GPM_EHIP, hipGetErrorString(e));
     J.A.dt = &c->ctl->dt;

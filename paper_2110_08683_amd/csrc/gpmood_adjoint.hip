@@ -175,55 +175,27 @@ __host__ __device__ constexpr int pos_of(int a, int b)
 }
 __host__ __device__ constexpr int min_radius(int e) { return e == 0 ? 0 : (e <= 2 ? 1 : (e <= 5 ? 2 : 3)); }
 
-// The per-face record: the adjoints of both sides' quarter accumulators,
-// component side * 32 + v * 8 + p * 4 + c, in planes [dir][component][ny+1][nx+1].
-constexpr int kFaceComps = 64;
+// The per-face record: the adjoints of both sides' quarter accumulators, 64
+// values per face in blocks of 16 per (direction, variable): block (dir, v) of
+// face (i, j) holds side * 8 + p * 4 + c contiguously, at [dir][v][ny+1][nx+1][16],
+// so that a face writes, and a gather reads, whole 16-byte quads.
 template <typename real>
-__device__ __forceinline__ size_t gface_index(const AdjArgs<real> &J, int dir, int comp, int i, int j)
+__device__ __forceinline__ real *record_block(const AdjArgs<real> &J, int dir, int v, int i, int j)
 {
     const size_t FX = (size_t)J.A.nx + 1, FY = (size_t)J.A.ny + 1;
-    return (((size_t)dir * kFaceComps + comp) * FY + (size_t)j) * FX + (size_t)i;
+    return J.gface + ((((size_t)dir * 4 + v) * FY + (size_t)j) * FX + (size_t)i) * 16;
 }
 
-// dL/d(ell) of one face, in FP64: the sum over both sides' stencil positions of
-// d(weight)/d(ell) x accumulator adjoint x parity sum (positions within the
-// face's radius).
+// Four values moved together (one 16-byte access per four floats).
 template <typename real>
-__device__ __forceinline__ void face_dl(const AdjArgs<real> &J, int dir, int iL, int jL, int iR, int jR, int np, int R,
-                                        const real (&gL)[4][2][4], const real (&gR)[4][2][4], double &dl)
-{
-    const StageArgs<real> &A = J.A;
-    const int nx = A.nx, ny = A.ny;
-    const size_t plane = (size_t)nx * ny;
-    const double *dwt = J.dl64 + (R * 2 + dir) * kGtabPerDir;
-    for (int e = 0; e < np; ++e) {
-        const int a = (int)((kPosA >> (4 * e)) & 15u), b = (int)((kPosB >> (4 * e)) & 15u);
-        const int xLp = wrap(iL + a, nx, A.bcx), xLm = wrap(iL - a, nx, A.bcx);
-        const int xRp = wrap(iR + a, nx, A.bcx), xRm = wrap(iR - a, nx, A.bcx);
-        const size_t yLp = (size_t)wrap(jL + b, ny, A.bcy) * nx, yLm = (size_t)wrap(jL - b, ny, A.bcy) * nx;
-        const size_t yRp = (size_t)wrap(jR + b, ny, A.bcy) * nx, yRm = (size_t)wrap(jR - b, ny, A.bcy) * nx;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const real *U = A.Us + v * plane;
-            double ql[4], qr[4];
-            parity4((double)U[yLp + xLp], (double)U[yLp + xLm], (double)U[yLm + xLp], (double)U[yLm + xLm], ql);
-            parity4((double)U[yRp + xRp], (double)U[yRp + xRm], (double)U[yRm + xRp], (double)U[yRm + xRm], qr);
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-                for (int p = 0; p < 2; ++p) {
-                    const double dw = dwt[p * (kNPos * 4) + e * 4 + c];
-                    dl += dw * ((double)gL[v][p][c] * ql[c] + (double)gR[v][p][c] * qr[c]);
-                }
-        }
-    }
-}
+struct alignas(16) Quad {
+    real x[4];
+};
 
 // ------------------------------------------------------------ per-face adjoint
 template <typename real>
 __global__ __launch_bounds__(128) void k_adj_faces(const AdjArgs<real> J)
 {
-    __shared__ double red[128];
     const StageArgs<real> &A = J.A;
     const int nx = A.nx, ny = A.ny;
     const size_t plane = (size_t)nx * ny;
@@ -233,7 +205,6 @@ __global__ __launch_bounds__(128) void k_adj_faces(const AdjArgs<real> J)
     const int nfx = fxn * ny, nft = nfx + nx * fyn;
     const real alpha = A.s == 0 ? real(1) : (A.s == 1 ? real(0.25) : real(2) / real(3));
     const real dt = (real)(*A.dt);
-    double dl = 0.0;
     for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < nft; f += gridDim.x * blockDim.x) {
         int dir, iL, jL, i, j;
         bool hasL, hasR;
@@ -270,7 +241,12 @@ __global__ __launch_bounds__(128) void k_adj_faces(const AdjArgs<real> J)
         }
         if (!any) {
             // nothing flows through this face: its record holds zeros
-            for (int k = 0; k < kFaceComps; ++k) J.gface[gface_index(J, dir, k, i, j)] = real(0);
+            const Quad<real> z = {{real(0), real(0), real(0), real(0)}};
+            for (int v = 0; v < 4; ++v) {
+                Quad<real> *blk = reinterpret_cast<Quad<real> *>(record_block(J, dir, v, i, j));
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) blk[k4] = z;
+            }
             continue;
         }
         const int R = min((int)A.order[cL], (int)A.order[cR]);
@@ -291,19 +267,37 @@ __global__ __launch_bounds__(128) void k_adj_faces(const AdjArgs<real> J)
             const int xRp = wrap(iR + a, nx, A.bcx), xRm = wrap(iR - a, nx, A.bcx);
             const size_t yLp = (size_t)wrap(jL + b, ny, A.bcy) * nx, yLm = (size_t)wrap(jL - b, ny, A.bcy) * nx;
             const size_t yRp = (size_t)wrap(jR + b, ny, A.bcy) * nx, yRm = (size_t)wrap(jR - b, ny, A.bcy) * nx;
+            // the position's 32 values and 8 weights, all loads issued before the
+            // arithmetic that waits for them
+            real u[4][8], wq[2][4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const real *U = A.Us + v * plane;
+                u[v][0] = U[yLp + xLp];
+                u[v][1] = U[yLp + xLm];
+                u[v][2] = U[yLm + xLp];
+                u[v][3] = U[yLm + xLm];
+                u[v][4] = U[yRp + xRp];
+                u[v][5] = U[yRp + xRm];
+                u[v][6] = U[yRm + xRp];
+                u[v][7] = U[yRm + xRm];
+            }
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) wq[p][c] = wt[p * (kNPos * 4) + e * 4 + c];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
                 real ql[4], qr[4];
-                parity4(U[yLp + xLp], U[yLp + xLm], U[yLm + xLp], U[yLm + xLm], ql);
-                parity4(U[yRp + xRp], U[yRp + xRm], U[yRm + xRp], U[yRm + xRm], qr);
+                parity4(u[v][0], u[v][1], u[v][2], u[v][3], ql);
+                parity4(u[v][4], u[v][5], u[v][6], u[v][7], qr);
 #pragma unroll
                 for (int p = 0; p < 2; ++p)
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
-                        const real w = wt[p * (kNPos * 4) + e * 4 + c];
-                        PL[v][p][c] = fma(w, ql[c], PL[v][p][c]);
-                        PR[v][p][c] = fma(w, qr[c], PR[v][p][c]);
+                        PL[v][p][c] = fma(wq[p][c], ql[c], PL[v][p][c]);
+                        PR[v][p][c] = fma(wq[p][c], qr[c], PR[v][p][c]);
                     }
             }
         }
@@ -359,27 +353,24 @@ __global__ __launch_bounds__(128) void k_adj_faces(const AdjArgs<real> J)
                 }
             }
         }
-        // 4-5. the face's record (the transposed reconstruction is applied by the
-        // cells that gather it) and its ell term
+        // 4. the face's record (the transposed reconstruction, and the ell terms,
+        // are applied by the cells that gather it)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
+        for (int v = 0; v < 4; ++v) {
+            Quad<real> *blk = reinterpret_cast<Quad<real> *>(record_block(J, dir, v, i, j));
 #pragma unroll
-            for (int p = 0; p < 2; ++p)
+            for (int p = 0; p < 2; ++p) {
+                Quad<real> l, r;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    J.gface[gface_index(J, dir, v * 8 + p * 4 + c, i, j)] = gL[v][p][c];
-                    J.gface[gface_index(J, dir, 32 + v * 8 + p * 4 + c, i, j)] = gR[v][p][c];
+                    l.x[c] = gL[v][p][c];
+                    r.x[c] = gR[v][p][c];
                 }
-        face_dl(J, dir, iL, jL, iR, jR, np, R, gL, gR, dl);
+                blk[p] = l;
+                blk[2 + p] = r;
+            }
+        }
     }
-    // dL/d(ell) partial of this block, summed in a fixed order
-    red[threadIdx.x] = dl;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) J.dl_partial[blockIdx.x] = red[0];
 }
 
 // ------------------------------------------------------------ per-cell gather
@@ -393,7 +384,7 @@ __global__ __launch_bounds__(128) void k_adj_faces(const AdjArgs<real> J)
 // (h_c = sum_p w[p][e][c] g[p][c] at position e = (|da|, |db|)), combined with
 // the signs of the mirror image (+-a, +-b) that reads this cell, both mirrors
 // when a or b is 0.
-constexpr int kTile = 16;
+constexpr int kTile = kAdjTile;
 constexpr int kWin = kTile + 7;
 template <typename real>
 struct GatherLds {
@@ -401,12 +392,6 @@ struct GatherLds {
     alignas(16) real g[kWin * kWin * kStride];
     alignas(16) real w[4 * kGtabPerDir];
     signed char r[kWin * kWin];
-};
-
-// Four values read together (one 16-byte LDS access per four floats).
-template <typename real>
-struct alignas(16) Quad {
-    real x[4];
 };
 
 // Contribution of the face side whose LDS record is g (8 values: p, c) to the
@@ -546,13 +531,13 @@ __device__ __forceinline__ void fetch_round(const AdjArgs<real> &J, int r, int i
         const int q = threadIdx.x + t * 256;
         const WinFace w = win_face(q, dir, i0, j0, J.A.nx, J.A.ny, J.A.bcx, J.A.bcy);
         const bool ok = q < kWin * kWin && w.ok;
+        const Quad<real> *blk = reinterpret_cast<const Quad<real> *>(record_block(J, dir, v, ok ? w.fi : 0, ok ? w.fj : 0));
 #pragma unroll
-        for (int k4 = 0; k4 < 4; ++k4)
+        for (int k4 = 0; k4 < 4; ++k4) {  // side * 2 + p; an absent face (block of face 0) reads as zeros
+            const Quad<real> r = blk[k4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int comp = (k4 >> 1) * 32 + v * 8 + (k4 & 1) * 4 + c;  // side, v, p, c
-                pre[t][k4].x[c] = ok ? J.gface[gface_index(J, dir, comp, w.fi, w.fj)] : real(0);
-            }
+            for (int c = 0; c < 4; ++c) pre[t][k4].x[c] = ok ? r.x[c] : real(0);
+        }
     }
 }
 
@@ -563,7 +548,11 @@ __global__ __launch_bounds__(256, sizeof(real) == 4 ? 3 : 2) void k_adj_cells(co
     const StageArgs<real> &A = J.A;
     const int nx = A.nx, ny = A.ny;
     const size_t n = (size_t)nx * ny;
-    const int i0 = blockIdx.x * kTile, j0 = blockIdx.y * kTile;
+    // tiles in row-major order, dealt so that the workgroups of one XCD take a
+    // contiguous run of them: neighbouring tiles, whose windows overlap by seven
+    // faces on each side, share the records in that XCD's L2
+    const int ntx = (nx + kTile - 1) / kTile, t = xcd_tile(blockIdx.x, gridDim.x);
+    const int i0 = (t % ntx) * kTile, j0 = (t / ntx) * kTile;
     const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
     const int mi = i0 + tx, mj = j0 + ty;
     const bool own = mi < nx && mj < ny;
@@ -653,6 +642,156 @@ __global__ __launch_bounds__(256, sizeof(real) == 4 ? 3 : 2) void k_adj_cells(co
     }
 }
 
+// ------------------------------------------------------------ dL/d(ell)
+// The ell terms, in FP64, cell by cell.  Each face side is centred on a cell (or,
+// on an outflow axis, on the ghost cell beyond a boundary face); the term of a
+// side of radius R is the sum over its stencil positions e within R of
+// d(w[p][e][c])/d(ell) x record[p][c] x the parity sum q[e][c] of the state
+// around the centre (eq. (gp_reconstructor) differentiated in ell through the
+// weights).  A cell forms the parity sums of each variable once and uses them for
+// the four sides centred on it: in each direction the right side of its face
+// below and the left side of its face above, one sum over e when the two faces
+// have the same radius.  An edge cell of an outflow axis also takes the outer
+// side of its boundary face.  Each block sums its cells' terms in a fixed order.
+
+// Parity sums of variable plane U around (ci, cj) (unwrapped) at the kNPos
+// stencil positions, in FP64.
+template <typename real>
+__device__ __forceinline__ void parity_sums(const StageArgs<real> &A, const real *U, int ci, int cj,
+                                            double (&q)[kNPos][4])
+{
+    const int nx = A.nx, ny = A.ny;
+    // the seven columns and rows around the centre, then every load, then the sums
+    int xs[7];
+    size_t ys[7];
+#pragma unroll
+    for (int d = 0; d < 7; ++d) {
+        xs[d] = wrap(ci + d - 3, nx, A.bcx);
+        ys[d] = (size_t)wrap(cj + d - 3, ny, A.bcy) * nx;
+    }
+    real u[kNPos][4];
+#pragma unroll
+    for (int e = 0; e < kNPos; ++e) {
+        const int a = (int)((kPosA >> (4 * e)) & 15u), b = (int)((kPosB >> (4 * e)) & 15u);
+        u[e][0] = U[ys[3 + b] + xs[3 + a]];
+        u[e][1] = U[ys[3 + b] + xs[3 - a]];
+        u[e][2] = U[ys[3 - b] + xs[3 + a]];
+        u[e][3] = U[ys[3 - b] + xs[3 - a]];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int e = 0; e < kNPos; ++e)
+        parity4((double)u[e][0], (double)u[e][1], (double)u[e][2], (double)u[e][3], q[e]);
+}
+
+// Sum over the positions e within radius R of dw[p][e][c] q[e][c] g[p][c] (dw:
+// the ell derivatives of the weights of R and the face direction; g: the records
+// of the sides, summed).  TOP: R is the top radius 3.
+template <bool TOP>
+__device__ __forceinline__ double ell_term(const double *dw, const double (&q)[kNPos][4], const double (&g)[2][4],
+                                           int R)
+{
+    const int np = TOP ? kNPos : (R <= 0 ? 1 : (R == 1 ? 3 : (R == 2 ? 6 : 10)));
+    double t = 0.0;
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double sq = 0.0;
+#pragma unroll
+            for (int e = 0; e < kNPos; ++e)
+                if (e < np) sq = fma(dw[p * (kNPos * 4) + e * 4 + c], q[e][c], sq);
+            t = fma(g[p][c], sq, t);
+        }
+    return t;
+}
+
+// A side's record of variable v (8 values p, c) at face (fi, fj) of direction
+// dir, added in FP64 to g.
+template <typename real>
+__device__ __forceinline__ void add_record(const AdjArgs<real> &J, int dir, int side, int v, int fi, int fj,
+                                           double (&g)[2][4])
+{
+    const Quad<real> *blk = reinterpret_cast<const Quad<real> *>(record_block(J, dir, v, fi, fj)) + side * 2;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const Quad<real> r = blk[p];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) g[p][c] += (double)r.x[c];
+    }
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_adj_dl(const AdjArgs<real> J)
+{
+    __shared__ double red[256];
+    __shared__ double dwl[4 * 2 * kGtabPerDir];  // the ell derivatives of the weights, [R][dir][.]
+    for (int q = threadIdx.x; q < 4 * 2 * kGtabPerDir; q += blockDim.x) dwl[q] = J.dl64[q];
+    __syncthreads();
+    const StageArgs<real> &A = J.A;
+    const int nx = A.nx, ny = A.ny;
+    const size_t n = (size_t)nx * ny;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double dl = 0.0;
+    if (k < n) {
+        const int mj = (int)(k / nx), mi = (int)(k - (size_t)mj * nx);
+        // the radii of the cell's faces (EDP_1: the smaller order of the two cells)
+        const size_t row = (size_t)mj * nx;
+        const int o = A.order[k], oxm = A.order[row + wrap(mi - 1, nx, A.bcx)], oxp = A.order[row + wrap(mi + 1, nx, A.bcx)];
+        const int oym = A.order[(size_t)wrap(mj - 1, ny, A.bcy) * nx + mi], oyp = A.order[(size_t)wrap(mj + 1, ny, A.bcy) * nx + mi];
+        const int R[2][2] = {{min(oxm, o), min(o, oxp)}, {min(oym, o), min(o, oyp)}};
+        // face indices: below (fi, fj) = (mi, mj) in both directions; above, the
+        // next index (on a periodic axis the face at the wrap is face 0)
+        const int hx = A.bcx == 0 && mi + 1 == nx ? 0 : mi + 1, hy = A.bcy == 0 && mj + 1 == ny ? 0 : mj + 1;
+        const bool top = __all(R[0][0] == 3 && R[0][1] == 3 && R[1][0] == 3 && R[1][1] == 3) != 0;
+        for (int v = 0; v < 4; ++v) {
+            const real *U = A.Us + (size_t)v * n;
+            double q[kNPos][4];
+            parity_sums(A, U, mi, mj, q);
+#pragma unroll
+            for (int dir = 0; dir < 2; ++dir) {
+                double g[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+                add_record(J, dir, 1, v, mi, mj, g);  // right side of the face below
+                if (top) {
+                    add_record(J, dir, 0, v, dir == 0 ? hx : mi, dir == 0 ? mj : hy, g);
+                    dl += ell_term<true>(dwl + (3 * 2 + dir) * kGtabPerDir, q, g, 3);
+                } else {
+                    const int R0 = R[dir][0], R1 = R[dir][1];
+                    if (R0 == R1) add_record(J, dir, 0, v, dir == 0 ? hx : mi, dir == 0 ? mj : hy, g);
+                    dl += ell_term<false>(dwl + (R0 * 2 + dir) * kGtabPerDir, q, g, R0);
+                    if (R0 != R1) {
+                        double h[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+                        add_record(J, dir, 0, v, dir == 0 ? hx : mi, dir == 0 ? mj : hy, h);
+                        dl += ell_term<false>(dwl + (R1 * 2 + dir) * kGtabPerDir, q, h, R1);
+                    }
+                }
+            }
+            // outer sides of the boundary faces of an outflow axis, centred on ghosts
+#pragma unroll 1
+            for (int gk = 0; gk < 4; ++gk) {
+                const int dir = gk >> 1, hi = gk & 1;
+                const int m = dir == 0 ? mi : mj, nd = dir == 0 ? nx : ny;
+                if ((dir == 0 ? A.bcx : A.bcy) == 0 || m != (hi ? nd - 1 : 0)) continue;
+                const int ci = mi + (dir == 0 ? (hi ? 1 : -1) : 0), cj = mj + (dir == 1 ? (hi ? 1 : -1) : 0);
+                double qg[kNPos][4];
+                parity_sums(A, U, ci, cj, qg);
+                double g[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+                // the left side of face 0, or the right side of face nd
+                add_record(J, dir, hi ? 1 : 0, v, dir == 0 && hi ? nx : mi, dir == 1 && hi ? ny : mj, g);
+                const int Rg = R[dir][hi];
+                dl += ell_term<false>(dwl + (Rg * 2 + dir) * kGtabPerDir, qg, g, Rg);
+            }
+        }
+    }
+    red[threadIdx.x] = dl;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) J.dl_partial[blockIdx.x] = red[0];
+}
+
 // Fixed-order sum of the per-block partials into *out, or added to *out when
 // accumulate is set (one block of 256 threads): thread t sums the contiguous
 // chunk t in order, then a pairwise tree in LDS.  The order does not depend on
@@ -677,11 +816,13 @@ __global__ __launch_bounds__(256) void k_adj_dl_final(const double *partial, int
 template <typename real>
 hipError_t launch_stage_vjp(const AdjArgs<real> &J, int nblk_faces, double *dl_out, bool accumulate, hipStream_t st)
 {
-    const size_t n = (size_t)J.A.nx * J.A.ny;
     hipLaunchKernelGGL(k_adj_faces<real>, dim3(nblk_faces), dim3(128), 0, st, J);
-    const dim3 tiles((unsigned)((J.A.nx + kTile - 1) / kTile), (unsigned)((J.A.ny + kTile - 1) / kTile));
-    hipLaunchKernelGGL(k_adj_cells<real>, tiles, dim3(kTile * kTile), 0, st, J);
-    hipLaunchKernelGGL(k_adj_dl_final, dim3(1), dim3(256), 0, st, J.dl_partial, nblk_faces, dl_out, (int)accumulate);
+    const int tiles = ((J.A.nx + kTile - 1) / kTile) * ((J.A.ny + kTile - 1) / kTile);
+    hipLaunchKernelGGL(k_adj_cells<real>, dim3((unsigned)tiles), dim3(kTile * kTile), 0, st, J);
+    // one thread per cell: ceil(nx ny / 256) <= tiles blocks, one partial each
+    const int nblk_dl = (int)(((size_t)J.A.nx * J.A.ny + 255) / 256);
+    hipLaunchKernelGGL(k_adj_dl<real>, dim3((unsigned)nblk_dl), dim3(256), 0, st, J);
+    hipLaunchKernelGGL(k_adj_dl_final, dim3(1), dim3(256), 0, st, J.dl_partial, nblk_dl, dl_out, (int)accumulate);
     return hipGetLastError();
 }
 

@@ -86,14 +86,20 @@ static inline gpm_status fail(gpm_ctx *c, gpm_status st, const std::string &msg)
     return st;
 }
 
-// Adjoint workspace: the per-face records, [2][64][ny+1][nx+1] values of the
-// state precision, then kGtabSize doubles (256-byte aligned parts).
+// Adjoint workspace: the per-face records, [2][4][ny+1][nx+1][16] values of the
+// state precision, then kGtabSize doubles (the ell table), then one double per
+// kAdjTile x kAdjTile tile of cells (its dL/d(ell) partial); 256-byte aligned parts.
 static inline size_t adj_face_bytes(const gpm_ctx *c)
 {
     const size_t esz = c->prec == GPM_F64 ? 8 : 4;
     return align_up((size_t)2 * 64 * (size_t)(c->nx + 1) * (size_t)(c->ny + 1) * esz);
 }
-static inline size_t adj_bytes(const gpm_ctx *c) { return adj_face_bytes(c) + align_up((size_t)kGtabSize * 8); }
+static inline size_t adj_tiles(const gpm_ctx *c)
+{
+    return (size_t)((c->nx + kAdjTile - 1) / kAdjTile) * (size_t)((c->ny + kAdjTile - 1) / kAdjTile);
+}
+static inline size_t adj_partial_offset(const gpm_ctx *c) { return adj_face_bytes(c) + align_up((size_t)kGtabSize * 8); }
+static inline size_t adj_bytes(const gpm_ctx *c) { return adj_partial_offset(c) + align_up(adj_tiles(c) * 8); }
 
 // Copy the FP64 ell-derivative of the compact weights into the adjoint workspace.
 static inline gpm_status upload_adj_dl(gpm_ctx *c)

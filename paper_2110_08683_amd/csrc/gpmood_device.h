@@ -139,6 +139,15 @@ __device__ __forceinline__ int remap(int i, int n, int bc)
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
+// blockIdx -> tile: consecutive tiles go to the same XCD (blocks are dealt to the
+// 8 XCDs round robin), so neighbouring strips share halo rows in one L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int per = nb >> 3;
+    if (b >= (per << 3)) return b;
+    return (b & 7) * per + (b >> 3);
+}
+
 // remap() for an index at most one period outside the axis (-n <= i < 2n): the
 // cascade reaches at most 4 cells beyond the domain, and periodic and reflecting
 // axes have at least 4 cells.  WALLS = false: the build for grids without a
@@ -582,12 +591,13 @@ struct BatchTabs {
 // Arguments of the stage adjoint: A carries U^n, U_s, the frozen final orders of
 // the forward stage (A.order), dt and the weights; lam_* are [4][ny][nx] in the
 // state precision.  gface: one record per face, the adjoints of both sides'
-// quarter accumulators (64 values, state precision) in planes
-// [direction][64][ny+1][nx+1], written by the face kernel and gathered by the
-// cells of the faces' stencils; dl64: the FP64 derivative of the compact weight
-// table with respect to ell; dl_partial holds one dL/d(ell) partial per block of
-// the face kernel.
+// quarter accumulators (64 values, state precision) in blocks of 16 per
+// (direction, variable), [direction][variable][ny+1][nx+1][16], written by the
+// face kernel and gathered by the cells of the faces' stencils; dl64: the FP64 derivative of the compact weight
+// table with respect to ell; dl_partial holds one dL/d(ell) partial per tile of
+// the cell kernel.
 constexpr int kAdjOffsets = 25;  // offsets (da, db) with |da| + |db| <= 3
+constexpr int kAdjTile = 16;     // the cell kernel's tiles: kAdjTile x kAdjTile cells
 template <typename real>
 struct AdjArgs {
     StageArgs<real> A;

@@ -31,15 +31,6 @@ namespace gpm {
 
 constexpr int LW = 70;  // LDS columns per ring row: 64 lanes + 3 halo columns each side
 
-// blockIdx -> tile: consecutive tiles go to the same XCD (blocks are dealt to the
-// 8 XCDs round robin), so neighbouring strips share halo rows in one L2.
-__device__ __forceinline__ int xcd_tile(int b, int nb)
-{
-    const int per = nb >> 3;
-    if (b >= (per << 3)) return b;
-    return (b & 7) * per + (b >> 3);
-}
-
 // Claims after lowering cell (i, j) (act = this lane lowered it): its four faces
 // (and, on periodic axes, the duplicate copy of a boundary face) are listed for
 // recomputation in the next pass, and the cell with its four face neighbours for
