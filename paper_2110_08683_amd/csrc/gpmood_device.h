@@ -509,6 +509,13 @@ __device__ __forceinline__ bool troubled(const StageArgs<real> &A, int order, co
     return true;
 }
 
+// The cascade's next radius after radius o (next: the cascade table, held in
+// scalar registers; a select chain instead of an indexed load).
+__device__ __forceinline__ int next_radius(const int (&next)[4], int o)
+{
+    return o == 3 ? next[3] : (o == 2 ? next[2] : (o == 1 ? next[1] : next[0]));
+}
+
 // Order this wavefront's LDS writes before its later LDS reads of other lanes'
 // data.  The lanes of a wavefront execute in lockstep and LDS serves a wavefront's
 // requests in order, so this only keeps the compiler from moving the accesses.

@@ -462,6 +462,7 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
                 cR = wrap<WALLS>(j, ny, A.bcy) * nx + i;
             }
             const int iR = iL + (dir == 0), jR = jL + (dir == 1);
+            const int oL = A.order[cL], oR = A.order[cR];  // issued ahead of the stencil loads
             // an isotropic y face computes what an x face computes on the transposed
             // grid: position (a, b) is gathered at offset (b, a) and the x table used
             tr = dir == 1 && A.iso;
@@ -534,7 +535,7 @@ __device__ __forceinline__ void faces_phase(const StageArgs<real> &A, const real
                     QR[f][C_EO] = tr ? r0[C_OE] : r1[C_EO];
                 }
             }
-            R = min((int)A.order[cL], (int)A.order[cR]);
+            R = min(oL, oR);
             const real *wt = wl + (R * 2 + (tr ? 0 : dir)) * kGtabPerDir;
             const int np = R <= 0 ? 1 : (R == 1 ? 3 : (R == 2 ? 6 : 10));
 #pragma unroll
@@ -748,6 +749,13 @@ __device__ __forceinline__ void cell_fetch(const StageArgs<real> &A, const CellI
     F.fid[1] = (int)fxm + 1;
     F.fid[2] = (int)(nfx + gym);
     F.fid[3] = (int)(nfx + gym + nx);
+    // every flux and flag is consumed here: the flag loads are issued with the
+    // flux loads (not sunk into the branch of the detection that reads them), and
+    // the cell waits once for all of them
+    asm volatile("" ::"v"(F.fl[0]), "v"(F.fl[1]), "v"(F.fl[2]), "v"(F.fl[3]), "v"(F.f[0][0]), "v"(F.f[0][1]),
+                 "v"(F.f[0][2]), "v"(F.f[0][3]), "v"(F.f[1][0]), "v"(F.f[1][1]), "v"(F.f[1][2]), "v"(F.f[1][3]),
+                 "v"(F.f[2][0]), "v"(F.f[2][1]), "v"(F.f[2][2]), "v"(F.f[2][3]), "v"(F.f[3][0]), "v"(F.f[3][1]),
+                 "v"(F.f[3][2]), "v"(F.f[3][3]));
 }
 
 // Returns whether the cell is troubled (it has then been lowered).
@@ -775,7 +783,7 @@ __device__ __forceinline__ bool cell_finish_flux(const StageArgs<real> &A, const
     const bool tr = troubled(A, X.o, ust, rs, nb);
 #pragma unroll
     for (int w = 0; w < 4; ++w) A.Uout[w * plane + X.c] = combine(A.s, X.un[w], ust[w], A.ca, A.cb);
-    if (tr) A.order[X.c] = (uint8_t)A.next[X.o];
+    if (tr) A.order[X.c] = (uint8_t)next_radius(A.next, X.o);
     return tr;
 }
 
@@ -789,10 +797,9 @@ __device__ __forceinline__ bool cell_finish(const StageArgs<real> &A, const Cell
 
 template <bool WALLS, typename real>
 __device__ __forceinline__ void cells_phase(const StageArgs<real> &A, const int *clist, int n, int t0, int stride,
-                                            const PassOut &P, int pre = 0, bool use_pre = false)
+                                            const PassOut &P, real dt, int pre = 0, bool use_pre = false)
 {
     const int nround = (n + stride - 1) / stride;
-    const real dt = (real)(*A.dt * A.dtf);
     for (int r = 0; r < nround; ++r) {
         const int idx = r * stride + t0;
         const bool valid = idx < n;
@@ -860,11 +867,12 @@ __global__ __launch_bounds__(64) void k_cells(const StageArgs<real> A, const Cas
     const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
     // this thread's first list entry, issued before the counts are known (in bounds)
     const int pre = C.clist[k & 1][t0 < cap ? t0 : cap - 1];
+    const real dt = (real)(*A.dt * A.dtf);
     if (!pass_runs(C, k)) return;
     int n = C.ctl->ncell[k];
     n = n < cap ? n : cap;  // a list holds each cell at most once
     if (n <= (int)(blockIdx.x * blockDim.x)) return;
-    cells_phase<WALLS>(A, C.clist[k & 1], n, t0, gridDim.x * blockDim.x, pass_out(C, k, C.ctl->stamp0), pre, true);
+    cells_phase<WALLS>(A, C.clist[k & 1], n, t0, gridDim.x * blockDim.x, pass_out(C, k, C.ctl->stamp0), dt, pre, true);
 }
 
 // The tail of a long cascade (few troubled cells per pass) in one workgroup:
@@ -898,6 +906,7 @@ __device__ __forceinline__ void tail_body(const StageArgs<real> &A, const Cascad
     const int capf = (A.nx + 1) * A.ny + A.nx * (A.ny + 1), capc = A.nx * A.ny;
     Ctl *ctl = C.ctl;
     const unsigned stamp0 = ctl->stamp0;
+    const real dtr = (real)(*A.dt * A.dtf);  // read once, not after each pass's barrier
     load_gtab<tail_threads<real>()>(A.gtab, S.wl);
     int k0 = ctl->tail_k0 > 0 ? ctl->tail_k0 : kdef;
     if (ctl->tail_k0 <= 0 && kbeg < kdef) {
@@ -958,14 +967,14 @@ __device__ __forceinline__ void tail_body(const StageArgs<real> &A, const Cascad
             __syncthreads();
             if (cellwave) {
                 bool tr = false;
-                if (valid) tr = cell_finish(A, X, (real)(*A.dt * A.dtf));
+                if (valid) tr = cell_finish(A, X, dtr);
                 wave_count(tr, P.tcount);
                 claim_after_lowering(A, P, X.i, X.j, tr);
             }
         } else {
             faces_phase<WALLS, HLL>(A, S.wl, S.xch[wv], C.flist[k & 1], nf, threadIdx.x, blockDim.x);
             __syncthreads();
-            cells_phase<WALLS>(A, C.clist[k & 1], nc, threadIdx.x, blockDim.x, P);
+            cells_phase<WALLS>(A, C.clist[k & 1], nc, threadIdx.x, blockDim.x, P, dtr);
         }
     }
     if (k >= kend) {
@@ -1340,7 +1349,7 @@ __global__ __launch_bounds__(64) void k_cells_batch(const BatchTabs<real> B, int
         const Cascade &C = table_entry(B.casc, p);
         const int n = min(C.ctl->ncell[k], A.nx * A.ny);
         cells_phase<WALLS>(A, C.clist[k & 1], n, (w - pl[p]) * 64 + (int)threadIdx.x, n,
-                           pass_out(C, k, C.ctl->stamp0));
+                           pass_out(C, k, C.ctl->stamp0), (real)(*A.dt * A.dtf));
     }
 }
 
