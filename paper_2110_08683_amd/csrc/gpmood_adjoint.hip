@@ -721,8 +721,10 @@ __device__ __forceinline__ void add_record(const AdjArgs<real> &J, int dir, int 
     }
 }
 
+// dlw: J.dl64 again, as a restricted pointer the kernel never writes through, so
+// that the block-uniform reads of the top-radius path are scalar loads.
 template <typename real>
-__global__ __launch_bounds__(256) void k_adj_dl(const AdjArgs<real> J)
+__global__ __launch_bounds__(256) void k_adj_dl(const AdjArgs<real> J, const double *__restrict__ dlw)
 {
     __shared__ double red[256];
     __shared__ double dwl[4 * 2 * kGtabPerDir];  // the ell derivatives of the weights, [R][dir][.]
@@ -754,7 +756,7 @@ __global__ __launch_bounds__(256) void k_adj_dl(const AdjArgs<real> J)
                 add_record(J, dir, 1, v, mi, mj, g);  // right side of the face below
                 if (top) {
                     add_record(J, dir, 0, v, dir == 0 ? hx : mi, dir == 0 ? mj : hy, g);
-                    dl += ell_term<true>(dwl + (3 * 2 + dir) * kGtabPerDir, q, g, 3);
+                    dl += ell_term<true>(dlw + (3 * 2 + dir) * kGtabPerDir, q, g, 3);
                 } else {
                     const int R0 = R[dir][0], R1 = R[dir][1];
                     if (R0 == R1) add_record(J, dir, 0, v, dir == 0 ? hx : mi, dir == 0 ? mj : hy, g);
@@ -821,7 +823,7 @@ hipError_t launch_stage_vjp(const AdjArgs<real> &J, int nblk_faces, double *dl_o
     hipLaunchKernelGGL(k_adj_cells<real>, dim3((unsigned)tiles), dim3(kTile * kTile), 0, st, J);
     // one thread per cell: ceil(nx ny / 256) <= tiles blocks, one partial each
     const int nblk_dl = (int)(((size_t)J.A.nx * J.A.ny + 255) / 256);
-    hipLaunchKernelGGL(k_adj_dl<real>, dim3((unsigned)nblk_dl), dim3(256), 0, st, J);
+    hipLaunchKernelGGL(k_adj_dl<real>, dim3((unsigned)nblk_dl), dim3(256), 0, st, J, J.dl64);
     hipLaunchKernelGGL(k_adj_dl_final, dim3(1), dim3(256), 0, st, J.dl_partial, nblk_dl, dl_out, (int)accumulate);
     return hipGetLastError();
 }
