@@ -509,11 +509,12 @@ __device__ __forceinline__ bool troubled(const StageArgs<real> &A, int order, co
     return true;
 }
 
-// The cascade's next radius after radius o (next: the cascade table, held in
-// scalar registers; a select chain instead of an indexed load).
-__device__ __forceinline__ int next_radius(const int (&next)[4], int o)
+// The cascade's next radius after radius o (n0..n3: the cascade table, held in
+// scalar registers; a select chain instead of an indexed load, which would also
+// copy the kernel's argument block to the stack).
+__device__ __forceinline__ int next_radius(int n0, int n1, int n2, int n3, int o)
 {
-    return o == 3 ? next[3] : (o == 2 ? next[2] : (o == 1 ? next[1] : next[0]));
+    return o == 3 ? n3 : (o == 2 ? n2 : (o == 1 ? n1 : n0));
 }
 
 // Order this wavefront's LDS writes before its later LDS reads of other lanes'

@@ -783,7 +783,7 @@ __device__ __forceinline__ bool cell_finish_flux(const StageArgs<real> &A, const
     const bool tr = troubled(A, X.o, ust, rs, nb);
 #pragma unroll
     for (int w = 0; w < 4; ++w) A.Uout[w * plane + X.c] = combine(A.s, X.un[w], ust[w], A.ca, A.cb);
-    if (tr) A.order[X.c] = (uint8_t)next_radius(A.next, X.o);
+    if (tr) A.order[X.c] = (uint8_t)next_radius(A.next[0], A.next[1], A.next[2], A.next[3], X.o);
     return tr;
 }
 
