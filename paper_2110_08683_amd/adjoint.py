@@ -3,10 +3,12 @@
 `rollout(g, U0, nsteps, cfl, checkpoint_every)` is a torch.autograd.Function over a
 single-problem context `g` (GPMood): the forward advances U0 by nsteps SSP-RK3
 steps on the GPU and keeps the state every `checkpoint_every` steps; the backward
-recomputes each segment from its checkpoint (keeping that segment's stage inputs
-and final cell orders, with the dt recorded in the forward, which the
-recomputation must reproduce bit for bit) and runs the stage adjoint stage by
-stage in reverse.  With checkpoint_every = 0 the forward keeps every stage's
+recomputes each segment from its checkpoint with the dts recorded in the forward
+(keeping that segment's stage inputs and final cell orders) and runs the stage
+adjoint stage by stage in reverse.  The recomputation must reproduce the forward
+bit for bit: the state it reaches at the end of each segment is compared on the
+device with the forward's (the next checkpoint, or the rollout's output), and
+the backward raises if any differs.  With checkpoint_every = 0 the forward keeps every stage's
 inputs and orders instead (three states and three order masks per step: 50 MB a
 step at 1024^2 in FP32) and the backward recomputes nothing.  The backward
 accumulates dL/d(ell) on the device (gpm_stage_vjp_acc) and reads it once.  The cell orders and every dt are those of the forward, held fixed (the
@@ -43,6 +45,8 @@ class _Rollout(torch.autograd.Function):
         ctx.checkpoints = checkpoints
         ctx.tape = tape
         ctx.dts = dts
+        # the end of the last segment, for the check of its recomputation
+        ctx.U_T = U.clone() if ctx.every != 0 else None
         return U
 
     @staticmethod
@@ -54,18 +58,25 @@ class _Rollout(torch.autograd.Function):
             if ctx.every == 0:
                 lam = _reverse(g, ctx.tape, lam, dl)
             else:
+                differs = torch.zeros((), dtype=torch.bool, device=g.device)
                 for seg in reversed(range(len(ctx.checkpoints))):
                     n0 = seg * ctx.every
                     n1 = min(ctx.nsteps, n0 + ctx.every)
-                    # recompute the segment, keeping every stage's inputs and orders
+                    # recompute the segment with the recorded dts, keeping every
+                    # stage's inputs and orders
                     U = ctx.checkpoints[seg].clone()
                     tape = []
                     for n in range(n0, n1):
                         U, dt, stages, orders = _step(g, U, ctx.cfl, keep=True, dt_forward=ctx.dts[n])
                         tape.append((dt, stages, orders))
+                    end = ctx.checkpoints[seg + 1] if seg + 1 < len(ctx.checkpoints) else ctx.U_T
+                    differs |= (U != end).any()
                     lam = _reverse(g, tape, lam, dl)
+                if bool(differs):
+                    raise RuntimeError("the backward's recomputation did not reproduce the forward's states")
             grad_ell = dl.to("cpu").reshape(())
         ctx.tape = None
+        ctx.U_T = None
         return lam, grad_ell, None, None, None, None
 
 
@@ -88,13 +99,11 @@ def _reverse(g, tape, lam, dl):
 
 def _step(g, Un, cfl, keep, dt_forward=None):
     """One SSP-RK3 step of context g from the device tensor Un (4, ny, nx).  With
-    dt_forward (the recomputation of a recorded step), the step uses that dt; the
-    dt recomputed from Un must equal it bit for bit (the forward is deterministic),
-    else the recorded orders would not belong to this state."""
-    dt = g.gpm_compute_dt_dev(Un, cfl)
-    if dt_forward is not None:
-        if dt != dt_forward:
-            raise RuntimeError(f"recomputed dt {dt!r} differs from the forward's {dt_forward!r}")
+    dt_forward (the recomputation of a recorded step) the step takes that dt,
+    without a reduction or a host round trip."""
+    if dt_forward is None:
+        dt = g.gpm_compute_dt_dev(Un, cfl)
+    else:
         g.gpm_set_dt(dt_forward)
         dt = dt_forward
     U1 = torch.empty_like(Un)
