@@ -464,18 +464,6 @@ __device__ __forceinline__ void gather_sides(const GatherLds<real> &L, const Qua
     }
 }
 
-// A value the whole wavefront holds, made scalar.
-__device__ __forceinline__ float uniform(float x)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
-}
-__device__ __forceinline__ double uniform(double x)
-{
-    const long long b = __builtin_bit_cast(long long, x);
-    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll)), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
-    return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-
 __device__ __forceinline__ int mod_n(int i, int n)
 {
     const int r = i % n;

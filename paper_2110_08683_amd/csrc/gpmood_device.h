@@ -448,6 +448,27 @@ __device__ __forceinline__ real combine(int s, real un, real ust, real ca = real
     return dv(un + real(2) * ust, real(3));
 }
 
+// This lane's index within its wavefront, recomputed where it is used (two
+// instructions) rather than kept live, and spilled, across a long loop.
+__device__ __forceinline__ int lane_here()
+{
+    int l;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+    return l;
+}
+
+// A value the whole wavefront holds, made scalar.
+__device__ __forceinline__ float uniform(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
+__device__ __forceinline__ double uniform(double x)
+{
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll)), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // Detection of one cell (Steps 4-10).  nb(di, dj, v) returns the stage input at
 // an offset within radius 2.  Returns true if the candidate is troubled.
 template <typename real, typename Nb>
@@ -475,10 +496,12 @@ __device__ __forceinline__ bool troubled(const StageArgs<real> &A, int order, co
         const real pW = pressure(g, rW, nb(-1, 0, 1), nb(-1, 0, 2), nb(-1, 0, 3));
         const real pN = pressure(g, rN, nb(0, 1, 1), nb(0, 1, 2), nb(0, 1, 3));
         const real pS = pressure(g, rS, nb(0, -1, 1), nb(0, -1, 2), nb(0, -1, 3));
-        const real divV = dv(dv(nb(1, 0, 1), rE) - dv(nb(-1, 0, 1), rW), real(2) * A.dx) +
-                          dv(dv(nb(0, 1, 2), rN) - dv(nb(0, -1, 2), rS), real(2) * A.dy);
-        const real gradp = dv(fabs(pE - pW), real(2) * A.dx * vmin(pE, pW)) +
-                           dv(fabs(pN - pS), real(2) * A.dy * vmin(pN, pS));
+        // 2 dx, 2 dy: the same values in every lane, kept in scalar registers
+        const real tdx = uniform(real(2) * A.dx), tdy = uniform(real(2) * A.dy);
+        const real divV = dv(dv(nb(1, 0, 1), rE) - dv(nb(-1, 0, 1), rW), tdx) +
+                          dv(dv(nb(0, 1, 2), rN) - dv(nb(0, -1, 2), rS), tdy);
+        const real gradp = dv(fabs(pE - pW), tdx * vmin(pE, pW)) +
+                           dv(fabs(pN - pS), tdy * vmin(pN, pS));
         if (divV >= -A.sigma_v && gradp <= A.sigma_p) return false;
     }
     if (A.flags & 4u) {                                       // Step 9: u2

@@ -182,7 +182,7 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
     }
     wave_lds_sync();
 
-    const real dt = (real)(*A.dt * A.dtf);
+    const real dt = uniform((real)(*A.dt * A.dtf));  // in a scalar register
     const real g = A.gamma;
     real sypP[q][4];   // y+ states of row j-1
     real Gprev[4];     // flux through face j-3/2
@@ -192,6 +192,15 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
     for (int v = 0; v < 4; ++v) { Gprev[v] = real(0); dFxP[v] = real(0); }
 
     for (int j = y0 - 1; j <= yend; ++j) {
+        // U^n of the cell this row completes, (i, j-1), issued before the row
+        // prefetch: waiting for it later leaves the prefetch in flight
+        real unp[4] = {real(0), real(0), real(0), real(0)};
+        if (A.s != 0 && own && j - 1 >= y0) {
+            const unsigned c = (unsigned)(j - 1) * (unsigned)nx + (unsigned)(x0 - 1 + lane_here());
+#pragma unroll
+            for (int v = 0; v < 4; ++v) unp[v] = (A.Un + v * plane)[c];
+        }
+        __builtin_amdgcn_sched_barrier(0);
         real pf[4][2];
         load_row(j + 4, pf);  // in flight during this row's arithmetic
         const bool doX = j >= y0 && j < yend;
@@ -232,9 +241,10 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
             }
             // store face i+1/2: lanes of the strip's own cells, plus the domain's left face
             if ((own || (lane == 0 && x0 == 0)) && j < ny) {
-                const size_t fi = (size_t)j * (nx + 1) + (i + 1);
+                // 32-bit lane offsets from block-uniform bases (fewer live registers)
+                const unsigned fi = (unsigned)j * (unsigned)(nx + 1) + (unsigned)(x0 + lane_here());  // face i + 1/2
 #pragma unroll
-                for (int v = 0; v < 4; ++v) A.FX[v * nfx + fi] = F[v];
+                for (int v = 0; v < 4; ++v) (A.FX + v * nfx)[fi] = F[v];
                 A.FXf[fi] = (uint8_t)((rsx ? 1 : 0) | (badNb ? 2 : 0));
             }
             // an inadmissible state on either side of the face troubles both of its
@@ -280,9 +290,9 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
             // store face j-1/2 (y index j): the segment's faces above its first row,
             // plus the domain's bottom face
             if (own_col && (j > y0 || y0 == 0)) {
-                const size_t gi = (size_t)j * nx + i;
+                const unsigned gi = (unsigned)j * (unsigned)nx + (unsigned)(x0 - 1 + lane_here());
 #pragma unroll
-                for (int v = 0; v < 4; ++v) A.GY[v * nfy + gi] = G[v];
+                for (int v = 0; v < 4; ++v) (A.GY + v * nfy)[gi] = G[v];
                 A.GYf[gi] = (uint8_t)((badLy ? 1 : 0) | (badRy ? 2 : 0));
             }
             if (j - 1 >= y0) {
@@ -299,17 +309,14 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
                 auto nb = [&](int di, int dj, int v) { return ring[(jr + dj) & 7][v][lane + 3 + di]; };
                 const bool tr = own && troubled(A, RT, ust, rs, nb);
                 if (own) {
-                    const size_t c = (size_t)jr * nx + i;
+                    const unsigned c = (unsigned)jr * (unsigned)nx + (unsigned)(x0 - 1 + lane_here());
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const real un = A.s == 0 ? real(0) : A.Un[v * plane + c];
-                        A.Uout[v * plane + c] = combine(A.s, un, ust[v], A.ca, A.cb);
-                    }
+                    for (int v = 0; v < 4; ++v) (A.Uout + v * plane)[c] = combine(A.s, unp[v], ust[v], A.ca, A.cb);
                     A.order[c] = (uint8_t)(tr ? A.next[RT] : RT);
                 }
                 wave_count(tr, P.tcount);
                 const int b = wave_reserve(tr ? 1 : 0, P.ccount);
-                if (tr) P.clist[b] = jr * nx + i;
+                if (tr) P.clist[b] = jr * nx + (x0 - 1 + lane_here());
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) Gprev[v] = G[v];
