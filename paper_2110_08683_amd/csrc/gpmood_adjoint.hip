@@ -429,14 +429,14 @@ constexpr int kGatherDa[kAdjOffsets] = {0, 1, -1, 0, 0, 2, -2, 0, 0, 1, -1, 1, -
 constexpr int kGatherDb[kAdjOffsets] = {0, 0, 0, 1, -1, 0, 0, 2, -2, 1, 1, -1, -1, 0, 0, 3, -3, 1, 1, -1, -1, 2, 2, -2, -2};
 
 // The contributions to one cell image at window coordinates (bx, by) from the
-// faces of direction DIR, summed over (offset, side) in a fixed order.  TOP:
-// every face of the window has the top radius 3 or does not exist (then its
-// record is zero), so the weights are the block-uniform radius-3 weights wtop
-// and no radius test is needed: the sum has the same bits as the general path's.
-// CHECK: the image may reach outside the window (ghost images of edge cells).
+// faces of direction DIR, summed over (offset, side) in a fixed order, with the
+// weights of each face's radius from the LDS table (all lanes read the same
+// entries).  TOP: every face of the window has the top radius 3 or does not exist
+// (then its record is zero), so no radius test is needed: the sum has the same
+// bits as the general path's.  CHECK: the image may reach outside the window
+// (ghost images of edge cells).
 template <typename real, int DIR, bool CHECK, bool TOP, int O = 0>
-__device__ __forceinline__ void gather_sides(const GatherLds<real> &L, const Quad<real> (&wtop)[2 * kNPos], int bx,
-                                             int by, real &sum)
+__device__ __forceinline__ void gather_sides(const GatherLds<real> &L, int bx, int by, real &sum)
 {
     if constexpr (O < 2 * kAdjOffsets) {
         constexpr int o = O / 2, side = O % 2;
@@ -447,20 +447,20 @@ __device__ __forceinline__ void gather_sides(const GatherLds<real> &L, const Qua
         const int f = wy * kWin + wx;
         const real *g = L.g + f * GatherLds<real>::kStride + side * 8;
         if constexpr (TOP) {
-            sum += side_term<real, da, db>(wtop[e], wtop[kNPos + e], g);
+            const real *w = L.w + 3 * kGtabPerDir + e * 4;
+            sum += side_term<real, da, db>(*reinterpret_cast<const Quad<real> *>(w),
+                                           *reinterpret_cast<const Quad<real> *>(w + kNPos * 4), g);
         } else {
             if (!CHECK || (wx >= 0 && wx < kWin && wy >= 0 && wy < kWin)) {
                 const int R = L.r[f];
-                if (R == 3) {
-                    sum += side_term<real, da, db>(wtop[e], wtop[kNPos + e], g);
-                } else if (R >= min_radius(e)) {  // not: no face (-1), or beyond its radius
+                if (R >= min_radius(e)) {  // not: no face (-1), or beyond its radius
                     const real *w = L.w + R * kGtabPerDir + e * 4;
                     sum += side_term<real, da, db>(*reinterpret_cast<const Quad<real> *>(w),
                                                    *reinterpret_cast<const Quad<real> *>(w + kNPos * 4), g);
                 }
             }
         }
-        gather_sides<real, DIR, CHECK, TOP, O + 1>(L, wtop, bx, by, sum);
+        gather_sides<real, DIR, CHECK, TOP, O + 1>(L, bx, by, sum);
     }
 }
 
@@ -530,7 +530,7 @@ __device__ __forceinline__ void fetch_round(const AdjArgs<real> &J, int r, int i
 }
 
 template <typename real>
-__global__ __launch_bounds__(256, sizeof(real) == 4 ? 3 : 2) void k_adj_cells(const AdjArgs<real> J)
+__global__ __launch_bounds__(256, 2) void k_adj_cells(const AdjArgs<real> J)
 {
     __shared__ GatherLds<real> L;
     const StageArgs<real> &A = J.A;
@@ -552,7 +552,6 @@ __global__ __launch_bounds__(256, sizeof(real) == 4 ? 3 : 2) void k_adj_cells(co
     Quad<real> pre[kWinPerThread][4];
     fetch_round(J, 0, i0, j0, pre);
     bool top = false;
-    Quad<real> wtop[2 * kNPos];
     for (int r = 0; r < 8; ++r) {
         const int dir = r >> 2, v = r & 3;
         __syncthreads();  // the previous round's readers are done
@@ -580,12 +579,22 @@ __global__ __launch_bounds__(256, sizeof(real) == 4 ? 3 : 2) void k_adj_cells(co
                 L.r[q] = (signed char)R;
                 notop = notop || (R >= 0 && R != 3);
             }
-            for (int q = threadIdx.x; q < 4 * kGtabPerDir; q += blockDim.x)
-                L.w[q] = A.gtab[((q / kGtabPerDir) * 2 + dir) * kGtabPerDir + q % kGtabPerDir];
+            {
+                // every load issued before the first store
+                constexpr int per = (4 * kGtabPerDir + kTile * kTile - 1) / (kTile * kTile);
+                real wv[per];
 #pragma unroll
-            for (int k = 0; k < 2 * kNPos; ++k)
+                for (int m = 0; m < per; ++m) {
+                    const int q = (int)threadIdx.x + m * kTile * kTile;
+                    wv[m] = q < 4 * kGtabPerDir ? A.gtab[((q / kGtabPerDir) * 2 + dir) * kGtabPerDir + q % kGtabPerDir]
+                                                : real(0);
+                }
 #pragma unroll
-                for (int c = 0; c < 4; ++c) wtop[k].x[c] = uniform(A.gtab[(3 * 2 + dir) * kGtabPerDir + k * 4 + c]);
+                for (int m = 0; m < per; ++m) {
+                    const int q = (int)threadIdx.x + m * kTile * kTile;
+                    if (q < 4 * kGtabPerDir) L.w[q] = wv[m];
+                }
+            }
             // every face of the window at the top radius (or absent): no radius tests
             top = __syncthreads_and(!notop) != 0;
         } else {
@@ -596,17 +605,17 @@ __global__ __launch_bounds__(256, sizeof(real) == 4 ? 3 : 2) void k_adj_cells(co
             // the cell's own image, then (edge cells of an outflow axis) its ghosts
             real sum = real(0);
             if (top) {
-                if (dir == 0) gather_sides<real, 0, false, true>(L, wtop, tx + 3, ty + 3, sum);
-                else gather_sides<real, 1, false, true>(L, wtop, tx + 3, ty + 3, sum);
+                if (dir == 0) gather_sides<real, 0, false, true>(L, tx + 3, ty + 3, sum);
+                else gather_sides<real, 1, false, true>(L, tx + 3, ty + 3, sum);
             } else {
-                if (dir == 0) gather_sides<real, 0, false, false>(L, wtop, tx + 3, ty + 3, sum);
-                else gather_sides<real, 1, false, false>(L, wtop, tx + 3, ty + 3, sum);
+                if (dir == 0) gather_sides<real, 0, false, false>(L, tx + 3, ty + 3, sum);
+                else gather_sides<real, 1, false, false>(L, tx + 3, ty + 3, sum);
             }
             for (int qy = 0; qy < niy; ++qy)
                 for (int qx = (qy == 0 ? 1 : 0); qx < nix; ++qx) {
                     const int bx = image(mi, nx, A.bcx, qx) - (i0 - 3), by = image(mj, ny, A.bcy, qy) - (j0 - 3);
-                    if (dir == 0) gather_sides<real, 0, true, false>(L, wtop, bx, by, sum);
-                    else gather_sides<real, 1, true, false>(L, wtop, bx, by, sum);
+                    if (dir == 0) gather_sides<real, 0, true, false>(L, bx, by, sum);
+                    else gather_sides<real, 1, true, false>(L, bx, by, sum);
                 }
             acc[v] += (double)sum;
         }
