@@ -6,19 +6,22 @@
 // every face flux a Gauss sum of HLLC fluxes of GP-reconstructed states at the
 // face's EDP_1 radius (eq. (fvm_F), eq. (gp_reconstructor)).  Given lambda_out =
 // dL/dU_out this returns dL/dU_s, adds dL/dU^n, and sums dL/d(ell) through the
-// ell-dependence of the GP weights.  Per face:
+// ell-dependence of the GP weights.  Per face (k_adj_faces):
 //   1. lambda_F = (alpha lambda_out(R) - alpha lambda_out(L)) dt / Delta, from the
 //      cells whose update uses this copy of the face (alpha = 1, 1/4, 2/3);
 //   2. the node states are rebuilt in the quarter basis (as in the cascade);
 //   3. per Gauss node, J^T (w_g lambda_F) for both states, by reverse mode
 //      through the HLLC flux with the forward's branches;
-//   4. the transposed reconstruction: node adjoints -> accumulator adjoints ->
-//      parity-sum adjoints -> the four mirror cells, added with FP64 atomics into
-//      an accumulator (stencil cells remapped exactly as the forward gathers them);
-//   5. dL/d(ell) += sum of accumulator adjoints times d(accumulator)/d(ell).
-// A second kernel forms dL/dU_s = alpha lambda_out + accumulator and adds
-// beta lambda_out to dL/dU^n (beta = 3/4, 1/3); in stage 0, where U^n is also U_s,
-// a given dL/dU^n from the later stages is added to dL/dU_s instead.
+//   4. node adjoints -> the adjoints of both sides' quarter accumulators, stored
+//      as the face's record (no atomics).
+// Per cell (k_adj_cells): the transposed reconstruction, gathered in a fixed
+// order from the records of the faces whose stencils hold the cell (stencil cells
+// remapped exactly as the forward gathers them), gives dL/dU_s = alpha lambda_out
+// + that sum, and beta lambda_out is added to dL/dU^n (beta = 3/4, 1/3); in stage
+// 0, where U^n is also U_s, a given dL/dU^n from the later stages is added to
+// dL/dU_s instead.  Per cell again (k_adj_dl): dL/d(ell), the records times the
+// ell-derivatives of the weights times the parity sums of the state, for the face
+// sides centred on the cell, summed per block and then in a fixed order.
 #include "gpmood_device.h"
 #include "gpmood_launch.h"
 
