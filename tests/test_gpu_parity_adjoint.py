@@ -345,3 +345,33 @@ def test_rollout_gradient_with_lowered_cells_vs_oracle_fd(torch_cuda):
         _note(f"  rho direction {t}: fd {fd:.10e} adjoint {ad:.10e} rel {abs(fd - ad) / abs(fd):.2e}")
         assert abs(fd - ad) <= 1e-4 * abs(fd)
     g.close()
+
+
+def test_backward_raises_when_the_recomputation_differs(torch_cuda):
+    """The checkpointed backward recomputes each segment with the recorded dts and
+    compares its end with the forward's state: a scheme changed between the
+    forward and the backward (here radius 1 instead of the forward's GP-MOOD7)
+    makes them differ, and the backward raises instead of returning the gradient
+    of another trajectory."""
+    import ctypes
+
+    torch = torch_cuda
+    from paper_2110_08683_amd import GPMood
+    from paper_2110_08683_amd import binding as B
+    from paper_2110_08683_amd.adjoint import rollout
+    n = 32
+    _note(f"rollout backward with a changed scheme f64 {n}^2 4 steps")
+    g = GPMood(n, n, hi=(10.0, 10.0), bc=(0, 0), prec="f64", cascade=(3, 2, 1, 0), device="cuda:0")
+    U0_d = _dev(torch, gi.vortex_bump(n, n, seed=5), torch.float64).requires_grad_(True)
+    UT = rollout(g, U0_d, 4, cfl=0.8, checkpoint_every=2)
+    loss = (UT[0] ** 2).sum()
+    s = B.gpm_scheme()
+    s.nlev, s.radius[0], s.radius[1] = 2, 1, 0
+    s.sigma_v = s.sigma_p = 5.0
+    s.flags = B.GPM_FLAGS_ALL
+    s.solver = B.GPM_SOLVERS["hllc"]
+    s.stencil = B.GPM_STENCILS["diamond"]
+    assert B.lib().gpm_set_scheme(g.ctx, ctypes.byref(s)) == B.GPM_OK
+    with pytest.raises(RuntimeError, match="did not reproduce"):
+        loss.backward()
+    g.close()
