@@ -888,20 +888,22 @@ __global__ __launch_bounds__(64) void k_cells(const StageArgs<real> A, const Cas
 // kend is reached, or the previous evaluation left more than back_thr troubled
 // cells (hand back to the multi-block passes).  The counts of the running passes
 // stay in LDS and are copied to the control block as each pass completes.
-// Threads of the tail workgroup: 512 in FP32; 256 in FP64, whose cell and face
-// state needs more than the 256 registers a lane has when two wavefronts share
-// a SIMD (one wavefront per SIMD gives it 512, with no spill to scratch).
-template <typename real>
+// Threads of the tail workgroup: 512 (two wavefronts per SIMD, at most 256
+// registers a lane); 256 in the FP64 build for walls and slits, whose cell and
+// face state needs more than 256 registers (one wavefront per SIMD gives it 512,
+// with no spill to scratch).
+template <typename real, bool WALLS>
 constexpr int tail_threads()
 {
-    return sizeof(real) == 8 ? 256 : 512;
+    return sizeof(real) == 8 && WALLS ? 256 : 512;
 }
+constexpr int kTailMaxWaves = 8;
 
 // LDS of the single-workgroup cascade.
 template <typename real>
 struct TailShared {
     real wl[kGtabSize];
-    FaceXchg<real> xch[tail_threads<real>() / 64];
+    FaceXchg<real> xch[kTailMaxWaves];
     int cnt[2][3];  // [pass parity][faces, cells, troubled cells of the previous evaluation]
     int kfirst;
 };
@@ -914,7 +916,7 @@ __device__ __forceinline__ void tail_body(const StageArgs<real> &A, const Cascad
     Ctl *ctl = C.ctl;
     const unsigned stamp0 = ctl->stamp0;
     const real dtr = (real)(*A.dt * A.dtf);  // read once, not after each pass's barrier
-    load_gtab<tail_threads<real>()>(A.gtab, S.wl);
+    load_gtab<tail_threads<real, WALLS>()>(A.gtab, S.wl);
     int k0 = ctl->tail_k0 > 0 ? ctl->tail_k0 : kdef;
     if (ctl->tail_k0 <= 0 && kbeg < kdef) {
         // no hand-over: the cascade either ended inside the batch kbeg..kdef-1 (at
@@ -959,10 +961,10 @@ __device__ __forceinline__ void tail_body(const StageArgs<real> &A, const Cascad
         P.tcount = &S.cnt[(k + 1) & 1][2];
         const int fw = (4 * nf + 63) >> 6, cw = (nc + 63) >> 6;  // wavefronts of faces, of cells
         const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);  // uniform per wavefront
-        if (fw + cw <= tail_threads<real>() / 64) {
+        if (fw + cw <= tail_threads<real, WALLS>() / 64) {
             // one round each, on separate wavefronts: the cell wavefronts gather
             // their inputs while the face wavefronts recompute the fluxes
-            const int c0 = tail_threads<real>() / 64 - cw;  // first cell wavefront
+            const int c0 = tail_threads<real, WALLS>() / 64 - cw;  // first cell wavefront
             const bool cellwave = wv >= c0;
             const int idx = (int)threadIdx.x - 64 * c0;
             const bool valid = cellwave && idx < nc;
@@ -1001,7 +1003,7 @@ __device__ __forceinline__ void tail_body(const StageArgs<real> &A, const Cascad
 }
 
 template <typename real, bool WALLS, bool HLL>
-__global__ __launch_bounds__(tail_threads<real>()) void k_tail(const StageArgs<real> A, const Cascade C, int kbeg, int kdef,
+__global__ __launch_bounds__((tail_threads<real, WALLS>())) void k_tail(const StageArgs<real> A, const Cascade C, int kbeg, int kdef,
                                                        int kend)
 {
     __shared__ TailShared<real> S;
@@ -1363,7 +1365,7 @@ __global__ __launch_bounds__(64) void k_cells_batch(const BatchTabs<real> B, int
 // Problem p = blockIdx.x runs the rest of its cascade in one workgroup, from the
 // pass the multi-block passes left to it (no hand-back).
 template <typename real, bool WALLS, bool HLL>
-__global__ __launch_bounds__(tail_threads<real>()) void k_tail_batch(const BatchTabs<real> B)
+__global__ __launch_bounds__((tail_threads<real, WALLS>())) void k_tail_batch(const BatchTabs<real> B)
 {
     __shared__ TailShared<real> S;
     const int p = blockIdx.x;
@@ -1454,7 +1456,7 @@ static hipError_t launch_batch_cascade(const BatchTabs<real> &B, hipStream_t st)
         hipLaunchKernelGGL((k_cells_batch<real, WALLS>), dim3(kBatchCellGrid), dim3(64), 0, st, B, k,
                            (const int *)B.plan);
     }
-    hipLaunchKernelGGL((k_tail_batch<real, WALLS, HLL>), dim3(B.nprob), dim3(tail_threads<real>()), 0, st, B);
+    hipLaunchKernelGGL((k_tail_batch<real, WALLS, HLL>), dim3(B.nprob), dim3(tail_threads<real, WALLS>()), 0, st, B);
     return hipGetLastError();
 }
 
@@ -1612,13 +1614,13 @@ hipError_t launch_cascade_tail(const StageArgs<real> &A, const Cascade &C, int k
 {
     const bool walls = A.bcx == 2 || A.bcy == 2 || A.slit != 0;
     if (walls && A.solver == 1)
-        hipLaunchKernelGGL((k_tail<real, true, true>), dim3(1), dim3(tail_threads<real>()), 0, st, A, C, kbeg, kdef, kend);
+        hipLaunchKernelGGL((k_tail<real, true, true>), dim3(1), dim3(tail_threads<real, true>()), 0, st, A, C, kbeg, kdef, kend);
     else if (walls)
-        hipLaunchKernelGGL((k_tail<real, true, false>), dim3(1), dim3(tail_threads<real>()), 0, st, A, C, kbeg, kdef, kend);
+        hipLaunchKernelGGL((k_tail<real, true, false>), dim3(1), dim3(tail_threads<real, true>()), 0, st, A, C, kbeg, kdef, kend);
     else if (A.solver == 1)
-        hipLaunchKernelGGL((k_tail<real, false, true>), dim3(1), dim3(tail_threads<real>()), 0, st, A, C, kbeg, kdef, kend);
+        hipLaunchKernelGGL((k_tail<real, false, true>), dim3(1), dim3(tail_threads<real, false>()), 0, st, A, C, kbeg, kdef, kend);
     else
-        hipLaunchKernelGGL((k_tail<real, false, false>), dim3(1), dim3(tail_threads<real>()), 0, st, A, C, kbeg, kdef, kend);
+        hipLaunchKernelGGL((k_tail<real, false, false>), dim3(1), dim3(tail_threads<real, false>()), 0, st, A, C, kbeg, kdef, kend);
     return hipGetLastError();
 }
 
