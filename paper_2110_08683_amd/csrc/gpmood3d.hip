@@ -634,7 +634,10 @@ __global__ __launch_bounds__(128) void k3_cells(const Stage3<real> S, const int 
             k = c / (S.n[0] * S.n[1]);
             real ust[5];
             real div[5] = {real(0), real(0), real(0), real(0), real(0)};
-            bool rs = false;
+            // every flux, flag and state value of the cell loaded first, then one
+            // wait (the flag tests and the divisions had split the loads by axis)
+            real fpv[3][5], fmv[3][5], us[5];
+            int fl = 0;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int m0 = S.n[0] + (a == 0), m1 = S.n[1] + (a == 1), m2 = S.n[2] + (a == 2);
@@ -642,19 +645,30 @@ __global__ __launch_bounds__(128) void k3_cells(const Stage3<real> S, const int 
                 const int fm = (k * m1 + j) * m0 + i;
                 const int fp = ((k + (a == 2)) * m1 + j + (a == 1)) * m0 + i + (a == 0);
 #pragma unroll
-                for (int v = 0; v < 5; ++v) div[v] = div[v] + (S.F[a][v * nfa + fp] - S.F[a][v * nfa + fm]) / S.d[a];
-                rs = rs || (S.Ff[a][fm] | S.Ff[a][fp]) != 0;  // either side of either face
+                for (int v = 0; v < 5; ++v) {
+                    fpv[a][v] = S.F[a][v * nfa + fp];
+                    fmv[a][v] = S.F[a][v * nfa + fm];
+                }
+                fl |= S.Ff[a][fm] | S.Ff[a][fp];  // either side of either face
             }
 #pragma unroll
-            for (int v = 0; v < 5; ++v) ust[v] = S.Us[v * plane + c] - dt * div[v];
+            for (int v = 0; v < 5; ++v) us[v] = S.Us[v * plane + c];
             const int o = S.order[c];
+            __builtin_amdgcn_sched_barrier(0);
+            const bool rs = fl != 0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) div[v] = div[v] + (fpv[a][v] - fmv[a][v]) / S.d[a];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) ust[v] = us[v] - dt * div[v];
             tr = troubled3(S, o, ust, rs, i, j, k);
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
                 const real un = S.s == 0 ? real(0) : S.Un[v * plane + c];
                 S.Uout[v * plane + c] = combine(S.s, un, ust[v]);
             }
-            if (tr) S.order[c] = (uint8_t)S.next[o];
+            if (tr) S.order[c] = (uint8_t)next_radius(S.next[0], S.next[1], S.next[2], S.next[3], o);
         }
         wave_count(tr, P.tcount);
         claims3(S, P, i, j, k, tr);
