@@ -233,7 +233,8 @@ gpm_status gpm_totals_static(gpm_ctx *ctx, const void *U, double totals[4]);
    pass leaves more than 4 x tail_threshold), with one host check per batch.
    passes_per_check (1..128) is the smallest batch; the batch otherwise follows
    the previous stage's number of multi-block passes.  rows_per_wave (4..256):
-   rows per wavefront march in the first pass.  Defaults 4, 12 and 32. */
+   rows per wavefront march in the first pass.  Defaults 4, 12 (24 in FP64 when
+   the grid has at least 2048 marches of 24 rows) and 32. */
 gpm_status gpm_set_tuning(gpm_ctx *ctx, int passes_per_check, int rows_per_wave, int tail_threshold);
 
 /* Instrumentation for measurement (not part of the method).  mode bit 0: every

@@ -81,6 +81,11 @@ gpm_status gpm_create(const gpm_grid *grid, int prec, void *hip_stream, gpm_ctx 
     c->nx = grid->n[0];
     c->ny = grid->n[1];
     c->ncell = (size_t)c->nx * c->ny;
+    // first-pass march length: 12 rows; 24 in FP64 (one wavefront per SIMD) when
+    // the grid still gives at least two marches for each of the 1024 SIMDs, where
+    // the shorter halo re-read pays (2048^2 FP64: 0.846 -> 0.817 ms per launch)
+    const long long strips = (c->nx + 61) / 62;
+    c->rows = (prec == GPM_F64 && strips * ((c->ny + 23) / 24) >= 2048) ? 24 : 12;
     c->dx = (grid->hi[0] - grid->lo[0]) / c->nx;
     c->dy = (grid->hi[1] - grid->lo[1]) / c->ny;
     c->si0 = si0;
