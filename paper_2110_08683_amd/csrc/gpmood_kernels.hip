@@ -1087,15 +1087,30 @@ __device__ __forceinline__ void dt_reduce_body(const real *U, size_t ncell, doub
                                                double *red)
 {
     double lam = 0.0;
-    for (size_t k = first; k < ncell; k += stride) {
-        const double r = U[k], mx = U[ncell + k], my = U[2 * ncell + k], E = U[3 * ncell + k];
-        const double p = (gamma - 1.0) * (E - 0.5 * (mx * mx + my * my) / r);
-        if (!(r > 0.0 && p > 0.0 && __builtin_isfinite(r) && __builtin_isfinite(p))) continue;
-        const double cs = sqrt(gamma * p / r);
-        const double lx = (fabs(mx / r) + cs) / dx;
-        const double ly = (fabs(my / r) + cs) / dy;
-        const double l = lx > ly ? lx : ly;
-        lam = l > lam ? l : lam;
+    // four cells per round, their 16 loads issued before the arithmetic (the
+    // maximum does not depend on the order)
+    constexpr int kU = 4;
+    for (size_t k0 = first; k0 < ncell; k0 += kU * stride) {
+        double q[kU][4];
+#pragma unroll
+        for (int m = 0; m < kU; ++m) {
+            const size_t k = k0 + (size_t)m * stride;
+            const size_t kk = k < ncell ? k : first;  // in bounds; the cell is skipped below
+#pragma unroll
+            for (int v = 0; v < 4; ++v) q[m][v] = U[(size_t)v * ncell + kk];
+        }
+#pragma unroll
+        for (int m = 0; m < kU; ++m) {
+            if (k0 + (size_t)m * stride >= ncell) continue;
+            const double r = q[m][0], mx = q[m][1], my = q[m][2], E = q[m][3];
+            const double p = (gamma - 1.0) * (E - 0.5 * (mx * mx + my * my) / r);
+            if (!(r > 0.0 && p > 0.0 && __builtin_isfinite(r) && __builtin_isfinite(p))) continue;
+            const double cs = sqrt(gamma * p / r);
+            const double lx = (fabs(mx / r) + cs) / dx;
+            const double ly = (fabs(my / r) + cs) / dy;
+            const double l = lx > ly ? lx : ly;
+            lam = l > lam ? l : lam;
+        }
     }
     red[threadIdx.x] = lam;
     __syncthreads();
