@@ -269,8 +269,9 @@ gpm_status gpm_order_ptr(const gpm_ctx *ctx, void **order_dev);
 /* Bytes of the device workspace the stage adjoint needs (gpm_stage_vjp), bound
    separately so that a context used only forward does not carry it: one record
    per face, the adjoints of both sides' reconstruction accumulators, 2 x 64 x
-   (nx+1) x (ny+1) values of the context's precision, and the FP64 derivative of
-   the weight table with respect to ell. */
+   (nx+1) x (ny+1) values of the context's precision, the FP64 derivative of the
+   weight table with respect to ell, and one FP64 dL/d(ell) partial per 16 x 16
+   tile of cells. */
 gpm_status gpm_adjoint_workspace_size(const gpm_ctx *ctx, size_t *bytes);
 
 /* Bind caller-owned device memory (>= gpm_adjoint_workspace_size, 256-byte
