@@ -4,8 +4,8 @@ plain FP64 oracle run with the same frozen cell orders and time steps.
 The adjoint differentiates a stage with the forward's final orders and dt held
 fixed, so the reference is the oracle's forced-order stage (Sec. "Stepwise
 implementation" with the detection replaced by the recorded orders) at the GPU's
-dt: d/d(eps) <lambda, S(U + eps v)> by a central difference.  The bar is the
-spec 1e-4 relative; the differences seen are far smaller except where a
+dt: d/d(eps) <lambda, S(U + eps v)> by a central difference.  The bar is 1e-4
+relative, in FP32 as in FP64; the differences seen are far smaller except where a
 direction crosses an HLLC branch switch.
 """
 import sys
