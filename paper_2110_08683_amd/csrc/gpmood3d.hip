@@ -713,7 +713,11 @@ __global__ __launch_bounds__(256) void k3_dt(const real *U, size_t n, double gam
         if ((int)threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] > red[threadIdx.x + s] ? red[threadIdx.x] : red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && red[0] > 0.0) atomicMax(lam_bits, (unsigned long long)__double_as_longlong(red[0]));
+    if (threadIdx.x == 0 && red[0] > 0.0) {
+        // as in 2D: no atomic from a block whose value cannot raise the maximum
+        const unsigned long long b = (unsigned long long)__double_as_longlong(red[0]);
+        if (b > __hip_atomic_load(lam_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(lam_bits, b);
+    }
 }
 
 __global__ void k3_dt_begin(Ctl *ctl) { ctl->lam_bits = 0ull; }

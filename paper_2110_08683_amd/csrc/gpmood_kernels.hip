@@ -1118,7 +1118,13 @@ __device__ __forceinline__ void dt_reduce_body(const real *U, size_t ncell, doub
         if (threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] > red[threadIdx.x + s] ? red[threadIdx.x] : red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && red[0] > 0.0) atomicMax(lam_bits, (unsigned long long)__double_as_longlong(red[0]));
+    if (threadIdx.x == 0 && red[0] > 0.0) {
+        // the maximum only grows (the bit patterns of positive doubles order as
+        // the values): a block whose value does not exceed the one already stored
+        // skips its atomic, so the blocks do not queue on the one address
+        const unsigned long long b = (unsigned long long)__double_as_longlong(red[0]);
+        if (b > __hip_atomic_load(lam_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(lam_bits, b);
+    }
 }
 
 template <typename real>
