@@ -83,7 +83,7 @@ HBM_PEAK = 8.0e12
 # (mean over the launches of 3 steps, so 1/3 stage-0 launches that read no U^n),
 # scaled by the counters' reading of a 512 MiB device copy (FETCH x 2.0, WRITE x
 # 1.0).  Valid for the kernel sources with this hash only; see profiles/.
-TRAFFIC = {"src": "f9a2e1e751715a4d", "f32": 372.5e6, "f64": 688.8e6}
+TRAFFIC = {"src": "77d0b64a68d63acd", "f32": 371.6e6, "f64": 688.1e6}
 KERNEL_SOURCES = ["gpmood_kernels.hip", "gpmood_device.h", "gpmood_tables.h", "gpmood_abi.hip"]
 
 

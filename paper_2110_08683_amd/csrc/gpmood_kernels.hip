@@ -188,6 +188,7 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
     real Gprev[4];     // flux through face j-3/2
     real dFxP[4];      // x-flux difference of row j-1
     bool rsxP = false, rsymP = false;
+    unsigned long long tmask = 0ull;  // this lane's lowered cells, bit (row - y0) mod 64
 #pragma unroll
     for (int v = 0; v < 4; ++v) { Gprev[v] = real(0); dFxP[v] = real(0); }
 
@@ -314,9 +315,20 @@ __device__ __forceinline__ void first_pass_wave(const StageArgs<real> &A, const 
                     for (int v = 0; v < 4; ++v) (A.Uout + v * plane)[c] = combine(A.s, unp[v], ust[v], A.ca, A.cb);
                     A.order[c] = (uint8_t)(tr ? A.next[RT] : RT);
                 }
-                wave_count(tr, P.tcount);
-                const int b = wave_reserve(tr ? 1 : 0, P.ccount);
-                if (tr) P.clist[b] = jr * nx + (x0 - 1 + lane_here());
+                // lowered cells are listed once per 64 rows of the march (once per
+                // march at the default lengths), not row by row: the wait for the
+                // slot an atomic returns would stall the march
+                const int rb = (jr - y0) & 63;
+                if (tr) tmask |= 1ull << rb;
+                if (rb == 63 || jr == yend - 1) {  // the same in every lane
+                    const int nt = __popcll(tmask);  // at most 64
+                    int b, bt;
+                    wave_reserve2(nt | (nt << 16), P.ccount, P.tcount, b, bt);
+                    const int row0 = jr - rb;
+                    for (unsigned long long m = tmask; m != 0ull; m &= m - 1ull)
+                        P.clist[b++] = (row0 + __ffsll((long long)m) - 1) * nx + (x0 - 1 + lane_here());
+                    tmask = 0ull;
+                }
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) Gprev[v] = G[v];
