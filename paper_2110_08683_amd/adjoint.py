@@ -5,7 +5,8 @@ single-problem context `g` (GPMood): the forward advances U0 by nsteps SSP-RK3
 steps on the GPU and keeps the state every `checkpoint_every` steps; the backward
 recomputes each segment from its checkpoint with the dts recorded in the forward
 (keeping that segment's stage inputs and final cell orders) and runs the stage
-adjoint stage by stage in reverse.  The recomputation must reproduce the forward
+adjoint stage by stage in reverse, on a twin context's stream, so that the
+adjoint of one segment overlaps the recomputation of the one before it.  The recomputation must reproduce the forward
 bit for bit: the state it reaches at the end of each segment is compared on the
 device with the forward's (the next checkpoint, or the rollout's output), and
 the backward raises if any differs.  With checkpoint_every = 0 the forward keeps every stage's
@@ -58,7 +59,16 @@ class _Rollout(torch.autograd.Function):
             if ctx.every == 0:
                 lam = _reverse(g, ctx.tape, lam, dl)
             else:
+                # the stage adjoints of a segment run on the twin context's stream
+                # while this context recomputes the segment before it (the
+                # recomputation waits on the host once per stage, and the adjoint
+                # kernels fill those gaps); same kernels, same order, same bits
+                tw = g.vjp_twin()
+                sA, sB = g.stream, tw.stream
                 differs = torch.zeros((), dtype=torch.bool, device=g.device)
+                sB.wait_stream(sA)  # lam and dl are written
+                for t in (lam, dl):
+                    t.record_stream(sB)
                 for seg in reversed(range(len(ctx.checkpoints))):
                     n0 = seg * ctx.every
                     n1 = min(ctx.nsteps, n0 + ctx.every)
@@ -71,7 +81,14 @@ class _Rollout(torch.autograd.Function):
                         tape.append((dt, stages, orders))
                     end = ctx.checkpoints[seg + 1] if seg + 1 < len(ctx.checkpoints) else ctx.U_T
                     differs |= (U != end).any()
-                    lam = _reverse(g, tape, lam, dl)
+                    sB.wait_stream(sA)  # the segment's tape is written
+                    for _, stages, orders in tape:
+                        for t in (*stages, *orders):
+                            t.record_stream(sB)  # kept from reuse until sB has read it
+                    with torch.cuda.stream(sB):
+                        lam = _reverse(tw, tape, lam, dl)
+                sA.wait_stream(sB)
+                lam = lam.clone()  # on this context's stream, like the other results
                 if bool(differs):
                     raise RuntimeError("the backward's recomputation did not reproduce the forward's states")
             grad_ell = dl.to("cpu").reshape(())

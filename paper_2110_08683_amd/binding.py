@@ -170,6 +170,11 @@ class GPMood:
         self.torch = torch
         self.device = torch.device(device if device is not None else "cuda")
         self.nx, self.ny = int(nx), int(ny)
+        # everything but the stream, for a twin context (vjp_twin)
+        self._init_kw = dict(lo=lo, hi=hi, bc=bc, prec=prec, cascade=cascade, ell=ell, gamma=gamma,
+                             sigma_v=sigma_v, sigma_p=sigma_p, flags=flags, device=device, stencil=stencil,
+                             solver=solver, slit=slit)
+        self._twin = None
         self.prec = prec
         self.dtype = torch.float64 if prec == "f64" else torch.float32
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -221,9 +226,22 @@ class GPMood:
             raise GpmError(f"status {st}: {msg}")
 
     def close(self):
+        if getattr(self, "_twin", None) is not None:
+            self._twin.close()
+            self._twin = None
         if getattr(self, "ctx", None) is not None:
             lib().gpm_destroy(self.ctx)
             self.ctx = None
+
+    def vjp_twin(self):
+        """A second context with this one's grid and scheme (so the same weights, bit
+        for bit) on a stream of its own, made on the first call and kept: the
+        checkpointed backward runs the stage adjoints of one segment on it while
+        this context recomputes the previous segment."""
+        if self._twin is None:
+            st = self.torch.cuda.Stream(device=self.device)
+            self._twin = GPMood(self.nx, self.ny, stream=st, **self._init_kw)
+        return self._twin
 
     def __del__(self):
         try:
